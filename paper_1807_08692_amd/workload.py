@@ -1,0 +1,347 @@
+"""Seeded synthetic workloads: database descriptors, queries, the k-NN graph
+and its leading eigenpairs.
+
+This module only prepares inputs. It holds none of the query-time arithmetic
+(the observation vector, the spectral term, the conjugate-gradient solve and
+the ranking live in the HIP library, and separately in the FP64 oracle).
+What it builds is the off-line side of Section 3 and Section 6.1 of Iscen et
+al. (the database, its reciprocal k-NN graph with (v^T z)_+^3 weights, the
+symmetric normalisation, and the r leading eigenpairs that the hybrid method
+assumes were computed off-line), on synthetic data in place of the paper's
+image descriptors:
+
+* descriptors: a mixture of von Mises-Fisher distributions on the unit
+  sphere S^(d-1), cluster centres uniform on the sphere, each point drawn
+  from vMF(mu_c, kappa) by Wood's rejection sampler (Wood 1994,
+  "Simulation of the von Mises Fisher distribution");
+* queries: further draws from the same mixture with an independent stream;
+* graph: mutual ("reciprocal") k-NN over cosine similarity, self excluded,
+  weight max(0, cos)^3, zero diagonal, then D^-1/2 W D^-1/2;
+* eigenpairs: the r algebraically largest eigenpairs of the normalised
+  graph, from ARPACK (small graphs) or a Chebyshev-filtered subspace
+  iteration (large graphs, torch on the GPU when one is present).
+
+Everything is deterministic given the seed. Bulk similarity products and the
+large eigensolve use torch on the GPU when available: this is input
+preparation outside the library, and its results are handed to both the
+library and the oracle as plain arrays.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# Configurations (shapes of the paper's large-scale setting, Section 6.1:
+# alpha = 0.99, reciprocal k-NN, d = 2048 descriptors)
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class WorkloadConfig:
+    name: str
+    n: int
+    d: int
+    clusters: int
+    kappa: float
+    k: int                 # neighbours per item in the reciprocal k-NN graph
+    alpha: float
+    r: int                 # rank of the spectral term
+    batch: int             # queries per batch
+    k_y: int               # non-zeros of the observation vector
+    tol: float             # CG stopping rule on the relative residual
+    max_iter: int
+    seed_base: int
+
+    @property
+    def seeds(self):
+        """(centres, points, queries, eigensolver start) seeds."""
+        b = self.seed_base
+        return b + 1, b + 2, b + 3, b + 4
+
+
+CONFIGS = {
+    # 5,000 items, d=128, 50 vMF clusters (kappa 40), k=10, r in {0, 50}.
+    "n5k": WorkloadConfig("n5k", 5000, 128, 50, 40.0, 10, 0.99, 50, 1, 10, 1e-6, 20, 0),
+    # 100,000 items, d=2048, 1,000 clusters (kappa 60), k=50, r=400, 64 queries.
+    "n100k": WorkloadConfig("n100k", 100_000, 2048, 1000, 60.0, 50, 0.99, 400, 64, 50, 1e-5, 100, 1000),
+    # 1,000,000 items, d=2048, 10,000 clusters (kappa 60), k=50, r=1000, 256 queries.
+    "n1m": WorkloadConfig("n1m", 1_000_000, 2048, 10_000, 60.0, 50, 0.99, 1000, 256, 50, 1e-5, 100, 2000),
+    # 2,000,000 items, d=512, 20,000 clusters (kappa 60), k=30, r up to 4000, 1024 queries.
+    "n2m": WorkloadConfig("n2m", 2_000_000, 512, 20_000, 60.0, 30, 0.99, 400, 1024, 50, 1e-3, 100, 4000),
+}
+
+
+# --------------------------------------------------------------------------
+# von Mises-Fisher mixture (Wood 1994)
+# --------------------------------------------------------------------------
+
+def _wood_w(rng: np.random.Generator, d: int, kappa: float, m: int) -> np.ndarray:
+    """m samples of w = mu^T x for x ~ vMF(mu, kappa) on S^(d-1), by Wood's
+    rejection scheme (envelope from a Beta((d-1)/2, (d-1)/2) variate)."""
+    dm1 = d - 1.0
+    b = dm1 / (2.0 * kappa + math.sqrt(4.0 * kappa * kappa + dm1 * dm1))
+    x0 = (1.0 - b) / (1.0 + b)
+    c = kappa * x0 + dm1 * math.log(1.0 - x0 * x0)
+    out = np.empty(m)
+    filled = 0
+    while filled < m:
+        need = m - filled
+        draw = max(16, int(need * 1.3))
+        z = rng.beta(dm1 / 2.0, dm1 / 2.0, size=draw)
+        u = rng.uniform(size=draw)
+        w = (1.0 - (1.0 + b) * z) / (1.0 - (1.0 - b) * z)
+        ok = kappa * w + dm1 * np.log(1.0 - x0 * w) - c >= np.log(u)
+        acc = w[ok][:need]
+        out[filled:filled + acc.size] = acc
+        filled += acc.size
+    return out
+
+
+def vmf_draw(rng: np.random.Generator, mus: np.ndarray, kappa: float) -> np.ndarray:
+    """One vMF(mu_i, kappa) draw for each row mu_i of mus (unit rows)."""
+    m, d = mus.shape
+    w = _wood_w(rng, d, kappa, m)
+    v = rng.standard_normal((m, d))
+    v -= np.sum(v * mus, axis=1, keepdims=True) * mus      # tangent direction
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    x = w[:, None] * mus + np.sqrt(np.maximum(0.0, 1.0 - w * w))[:, None] * v
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    return x
+
+
+def vmf_mixture(n: int, d: int, clusters: int, kappa: float, seed_centres: int,
+                seed_points: int, chunk: int = 65536):
+    """n unit-norm float32 descriptors from an equal-weight vMF mixture.
+    Returns (V n x d float32, labels n int32, centres clusters x d float64)."""
+    rc = np.random.default_rng(seed_centres)
+    centres = rc.standard_normal((clusters, d))
+    centres /= np.linalg.norm(centres, axis=1, keepdims=True)
+    rp = np.random.default_rng(seed_points)
+    labels = rp.integers(0, clusters, size=n).astype(np.int32)
+    V = np.empty((n, d), np.float32)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        V[s:e] = vmf_draw(rp, centres[labels[s:e]], kappa).astype(np.float32)
+    # re-normalise in float32 so every stored row is unit norm to fp32 rounding
+    V /= np.linalg.norm(V, axis=1, keepdims=True).astype(np.float32)
+    return V, labels, centres
+
+
+def vmf_queries(m: int, centres: np.ndarray, kappa: float, seed: int) -> np.ndarray:
+    rq = np.random.default_rng(seed)
+    lab = rq.integers(0, centres.shape[0], size=m)
+    Q = vmf_draw(rq, centres[lab], kappa).astype(np.float32)
+    Q /= np.linalg.norm(Q, axis=1, keepdims=True).astype(np.float32)
+    return Q
+
+
+# --------------------------------------------------------------------------
+# Reciprocal k-NN graph
+# --------------------------------------------------------------------------
+
+def _torch_device(prefer_gpu: bool = True):
+    import torch
+    if prefer_gpu and torch.cuda.is_available():
+        return torch.device("cuda:0")
+    return torch.device("cpu")
+
+
+def knn_lists(V: np.ndarray, k: int, prefer_gpu: bool = True, block: int = 4096):
+    """Per item, its k most similar other items by cosine (self excluded),
+    with the float32 similarities. Returns (nbr n x k int64, sim n x k float32)."""
+    import torch
+    dev = _torch_device(prefer_gpu)
+    n = V.shape[0]
+    Vt = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
+    nbr = np.empty((n, k), np.int64)
+    sim = np.empty((n, k), np.float32)
+    if dev.type == "cuda":
+        block = max(256, min(block, int(2 ** 31 // max(n, 1))))
+    for s in range(0, n, block):
+        e = min(n, s + block)
+        S = Vt[s:e] @ Vt.T
+        S[torch.arange(e - s, device=dev), torch.arange(s, e, device=dev)] = -float("inf")
+        val, idx = torch.topk(S, k, dim=1, largest=True, sorted=True)
+        nbr[s:e] = idx.cpu().numpy()
+        sim[s:e] = val.cpu().numpy()
+        del S
+    return nbr, sim
+
+
+def mutual_knn_graph(nbr: np.ndarray, sim: np.ndarray, n: int):
+    """Reciprocal k-NN adjacency W (Section 6.1): edge i-j iff each is among
+    the other's k nearest neighbours; weight max(0, cos)^3, zero diagonal,
+    edges of weight 0 dropped. The cosine of an edge is taken from its
+    lower-id endpoint's list so W is exactly symmetric.
+    Returns CSR (rowptr int64[n+1], col int32[nnz], w float64[nnz])."""
+    k = nbr.shape[1]
+    rows = np.repeat(np.arange(n, dtype=np.int64), k)
+    cols = nbr.reshape(-1)
+    vals = sim.reshape(-1).astype(np.float64)
+    key = rows * n + cols
+    rkey = cols * n + rows
+    order = np.argsort(key, kind="stable")
+    skey = key[order]
+    pos = np.searchsorted(skey, rkey)
+    pos = np.minimum(pos, skey.size - 1)
+    mutual = skey[pos] == rkey
+    # canonical similarity: from the (min, max) orientation
+    other = vals[order[pos]]
+    canon = np.where(rows < cols, vals, other)
+    rows, cols, canon = rows[mutual], cols[mutual], canon[mutual]
+    w = np.maximum(canon, 0.0) ** 3
+    keep = w > 0.0
+    rows, cols, w = rows[keep], cols[keep], w[keep]
+    o = np.lexsort((cols, rows))
+    rows, cols, w = rows[o], cols[o], w[o]
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return rowptr, cols.astype(np.int32), w
+
+
+def symmetric_normalize(n, rowptr, col, w):
+    """Section 3: D^-1/2 W D^-1/2 on W's pattern (float64); zero-degree items
+    get a zero row."""
+    deg = np.zeros(n)
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    np.add.at(deg, rows, w)
+    dinv = np.where(deg > 0, 1.0 / np.sqrt(np.where(deg > 0, deg, 1.0)), 0.0)
+    return w * (dinv[rows] * dinv[col])
+
+
+# --------------------------------------------------------------------------
+# Leading eigenpairs (off-line input of the hybrid method)
+# --------------------------------------------------------------------------
+
+def top_eigs_arpack(n, rowptr, col, sval, r, seed):
+    """r algebraically largest eigenpairs (descending) with ARPACK."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    if r == 0:
+        return np.zeros((n, 0)), np.zeros(0), np.zeros(0)
+    A = sp.csr_matrix((np.asarray(sval, np.float64), col, rowptr), shape=(n, n))
+    v0 = np.random.default_rng(seed).standard_normal(n)
+    if r >= n - 1:
+        w, Uf = np.linalg.eigh(A.toarray())
+        o = np.argsort(-w, kind="stable")[:r]
+        w, Uf = w[o], Uf[:, o]
+    else:
+        w, Uf = sla.eigsh(A, k=r, which="LA", v0=v0, tol=1e-13, maxiter=100000)
+        o = np.argsort(-w, kind="stable")
+        w, Uf = w[o], Uf[:, o]
+    res = np.linalg.norm(A @ Uf - Uf * w, axis=0)
+    return Uf, w, res
+
+
+def top_eigs_chebyshev(n, rowptr, col, sval, r, seed, guard=None, degree=12,
+                       max_outer=60, tol=1e-9, time_budget=120.0, prefer_gpu=True):
+    """r algebraically largest eigenpairs by Chebyshev-filtered subspace
+    iteration with Rayleigh-Ritz, in float64 (torch; GPU if present).
+    The filter damps the interval [-1, b] with b the smallest Ritz value of
+    the block. Returns (U n x r, lambda r, residual norms r)."""
+    import torch
+    dev = _torch_device(prefer_gpu)
+    if r == 0:
+        return np.zeros((n, 0)), np.zeros(0), np.zeros(0)
+    m = r + (guard if guard is not None else max(20, r // 4))
+    m = min(m, n)
+    S = torch.sparse_csr_tensor(torch.from_numpy(np.asarray(rowptr, np.int64)),
+                                torch.from_numpy(np.asarray(col, np.int64)),
+                                torch.from_numpy(np.asarray(sval, np.float64)),
+                                size=(n, n)).to(dev)
+    g = torch.Generator(device="cpu").manual_seed(int(seed))
+    X = torch.randn(n, m, generator=g, dtype=torch.float64).to(dev)
+    X, _ = torch.linalg.qr(X)
+    t0 = time.time()
+    lam = None
+    res = None
+    for outer in range(max_outer):
+        SX = S @ X
+        H = X.T @ SX
+        H = 0.5 * (H + H.T)
+        w, Z = torch.linalg.eigh(H)
+        w, Z = w.flip(0), Z.flip(1)
+        X = X @ Z
+        SX = SX @ Z
+        lam = w
+        res = torch.linalg.vector_norm(SX - X * w, dim=0)
+        if float(res[:r].max()) < tol or time.time() - t0 > time_budget:
+            break
+        a, b = -1.0, float(w[-1])
+        c, e = 0.5 * (a + b), 0.5 * (b - a)
+        Y0 = X
+        Y1 = (S @ X - c * X) / e
+        for _ in range(2, degree + 1):
+            Y2 = 2.0 * (S @ Y1 - c * Y1) / e - Y0
+            Y0, Y1 = Y1, Y2
+        X, _ = torch.linalg.qr(Y1)
+    return (X[:, :r].cpu().numpy(), lam[:r].cpu().numpy(), res[:r].cpu().numpy())
+
+
+# --------------------------------------------------------------------------
+# Fixture bundle
+# --------------------------------------------------------------------------
+
+@dataclass
+class Fixture:
+    cfg: WorkloadConfig
+    V: np.ndarray            # n x d float32 database descriptors
+    Q: np.ndarray            # m x d float32 queries
+    rowptr: np.ndarray       # int64[n+1]
+    col: np.ndarray          # int32[nnz]
+    w: np.ndarray            # float64[nnz] raw weights
+    s: np.ndarray            # float32[nnz] normalised values (what the GPU stores)
+    U: np.ndarray            # n x r float32 eigenvectors (what the GPU stores)
+    lam: np.ndarray          # r float64 eigenvalues, descending
+    eig_res: np.ndarray      # r residual norms ||S u - lambda u||
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.cfg.n
+
+    @property
+    def nnz(self):
+        return int(self.col.size)
+
+
+def build_fixture(cfg: WorkloadConfig, n_queries: Optional[int] = None, r: Optional[int] = None,
+                  prefer_gpu: bool = True, eig_time_budget: float = 120.0,
+                  log=None) -> Fixture:
+    """Generate a whole workload for cfg (descriptors, queries, graph, eigenpairs)."""
+    t0 = time.time()
+    say = log or (lambda *a: None)
+    sc, spt, sq, se = cfg.seeds
+    V, labels, centres = vmf_mixture(cfg.n, cfg.d, cfg.clusters, cfg.kappa, sc, spt)
+    Q = vmf_queries(n_queries if n_queries is not None else cfg.batch, centres, cfg.kappa, sq)
+    say(f"descriptors {time.time() - t0:.1f}s")
+    nbr, sim = knn_lists(V, cfg.k, prefer_gpu=prefer_gpu)
+    rowptr, col, w = mutual_knn_graph(nbr, sim, cfg.n)
+    del nbr, sim
+    s64 = symmetric_normalize(cfg.n, rowptr, col, w)
+    s32 = s64.astype(np.float32)
+    say(f"graph nnz={col.size} {time.time() - t0:.1f}s")
+    rr = cfg.r if r is None else r
+    if rr == 0:
+        U = np.zeros((cfg.n, 0), np.float32)
+        lam = np.zeros(0)
+        res = np.zeros(0)
+    elif cfg.n <= 20000:
+        U64, lam, res = top_eigs_arpack(cfg.n, rowptr, col, s32.astype(np.float64), rr, se)
+        U = U64.astype(np.float32)
+    else:
+        U64, lam, res = top_eigs_chebyshev(cfg.n, rowptr, col, s32.astype(np.float64), rr, se,
+                                            time_budget=eig_time_budget, prefer_gpu=prefer_gpu)
+        U = U64.astype(np.float32)
+    say(f"eigs r={rr} max_res={float(res.max()) if res.size else 0:.2e} {time.time() - t0:.1f}s")
+    deg = np.diff(rowptr)
+    info = dict(nnz=int(col.size), mean_degree=float(deg.mean()), isolated=int((deg == 0).sum()),
+                eig_max_residual=float(res.max()) if res.size else 0.0,
+                build_seconds=time.time() - t0)
+    return Fixture(cfg, V, Q, rowptr, col, w, s32, U, np.asarray(lam, np.float64), res, info)

@@ -1,0 +1,406 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed
+form, a spectral identity, the paper's theorem at every rank, the CG error
+bound, a worked number printed in the paper, or brute force on inputs whose
+answer is known by construction. A plausible slip in the oracle (a dropped
+(1 - alpha), a wrong sign, g exchanged for h, a transposed U, a wrong index)
+fails at least one of them.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1807_08692_amd import workload as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ALPHA = 0.99
+
+
+def small_graph(n=150, d=16, clusters=6, kappa=12.0, k=8, seed=7):
+    """Reciprocal k-NN graph on a tiny vMF mixture, oracle-normalised."""
+    V, _, _ = W.vmf_mixture(n, d, clusters, kappa, seed, seed + 1)
+    nbr, sim = W.knn_lists(V, k, prefer_gpu=False)
+    rowptr, col, w = W.mutual_knn_graph(nbr, sim, n)
+    s = O.normalize(n, rowptr, col, w)
+    g = O.Graph64.from_csr(n, rowptr, col, s)
+    return V, g, w
+
+
+def csr_from_dense(A):
+    n = A.shape[0]
+    rowptr = [0]
+    col, val = [], []
+    for i in range(n):
+        nz = np.nonzero(A[i])[0]
+        col.extend(nz.tolist())
+        val.extend(A[i, nz].tolist())
+        rowptr.append(len(col))
+    return np.array(rowptr, np.int64), np.array(col, np.int32), np.array(val, np.float64)
+
+
+def normalised_graph_from_weights(Wd):
+    rp, cl, w = csr_from_dense(Wd)
+    s = O.normalize(Wd.shape[0], rp, cl, w)
+    return O.Graph64.from_csr(Wd.shape[0], rp, cl, s)
+
+
+def sparse_y(n, k, seed):
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)
+    vals = rng.uniform(0.05, 1.0, size=k)
+    return ids, vals
+
+
+# ---------------------------------------------------------------- P1 / P5
+
+
+def test_truth_dense_residual_and_plain_cg_agree():
+    """eqs. (temporal), (transfer): the Cholesky solution satisfies
+    (I - alpha S) x = (1 - alpha) y, and the r = 0 CG of the oracle (plain
+    temporal filtering) converges to it."""
+    _, g, _ = small_graph()
+    S = g.dense()
+    ids, vals = sparse_y(g.n, 5, 1)
+    y = O.dense_y(g.n, ids, vals)
+    xt = O.truth_dense(S, ALPHA, y)
+    res = (np.eye(g.n) - ALPHA * S) @ xt - (1 - ALPHA) * y
+    assert np.linalg.norm(res) <= 1e-13 * max(1.0, np.linalg.norm(y))
+    x, it, rr, st = O.cg(g, None, None, ALPHA, y, 5000, 1e-14)
+    assert st == O.CONVERGED and rr <= 1e-14
+    assert np.linalg.norm(x - xt) <= 1e-10 * np.linalg.norm(xt)
+
+
+# ---------------------------------------------------------------- P2
+
+
+def test_complete_graph_closed_form_and_finite_termination():
+    """K_n with equal weights: S = (J - I)/(n - 1), eigenvalues 1 and
+    -1/(n - 1) (attaining the bound lambda_n <= -1/(n-1) of Section 5), so
+    x* = P1 y + (1 - alpha)/(1 + alpha/(n - 1)) (I - P1) y with P1 = 11^T/n,
+    and CG terminates in two products (two distinct eigenvalues)."""
+    n = 40
+    g = normalised_graph_from_weights(np.ones((n, n)) - np.eye(n))
+    assert np.allclose(g.val, 1.0 / (n - 1), rtol=0, atol=1e-16)
+    rng = np.random.default_rng(3)
+    y = rng.uniform(size=n)
+    P1y = np.full(n, y.mean())
+    closed = P1y + (1 - ALPHA) / (1 + ALPHA / (n - 1)) * (y - P1y)
+    assert np.linalg.norm(O.truth_dense(g.dense(), ALPHA, y) - closed) <= 1e-13 * np.linalg.norm(closed)
+    x1, it1, _, _ = O.cg(g, None, None, ALPHA, y, 1, 0.0)
+    x2, it2, rr2, st2 = O.cg(g, None, None, ALPHA, y, 2, 0.0)
+    assert np.linalg.norm(x2 - closed) <= 1e-12 * np.linalg.norm(closed)
+    assert rr2 <= 1e-12
+    # after one product the iterate lies in span{y} (Krylov space K_1)
+    c = x1 @ y / (y @ y)
+    assert np.linalg.norm(x1 - c * y) <= 1e-13 * np.linalg.norm(x1)
+    assert np.linalg.norm(x1 - closed) > 1e-3 * np.linalg.norm(closed)
+
+
+def test_cycle_graph_by_fourier():
+    """Cycle C_n: S = (Z + Z^T)/2 with Z the cyclic shift, eigenvalues
+    cos(2 pi j / n) on the Fourier basis, so h(S) y is a circular filter
+    computed with the FFT (eq. (spectral) with U the Fourier basis)."""
+    n = 64
+    Wd = np.zeros((n, n))
+    for i in range(n):
+        Wd[i, (i + 1) % n] = Wd[(i + 1) % n, i] = 1.0
+    g = normalised_graph_from_weights(Wd)
+    rng = np.random.default_rng(5)
+    y = rng.uniform(size=n)
+    hj = (1 - ALPHA) / (1 - ALPHA * np.cos(2 * np.pi * np.arange(n) / n))
+    xf = np.real(np.fft.ifft(hj * np.fft.fft(y)))
+    assert np.linalg.norm(O.truth_dense(g.dense(), ALPHA, y) - xf) <= 1e-12 * np.linalg.norm(xf)
+    x, _, rr, st = O.cg(g, None, None, ALPHA, y, 2000, 1e-15)
+    assert np.linalg.norm(x - xf) <= 1e-10 * np.linalg.norm(xf)
+
+
+def test_star_graph_extreme_spectrum():
+    """Star K_{1,m} is bipartite: S has eigenvalues +1, -1 and 0, so the
+    spectrum touches both ends of [-1, 1] (Section 3) and
+    kappa(L(S)) = (1 + alpha)/(1 - alpha) by eq. (cond)."""
+    m = 9
+    n = m + 1
+    Wd = np.zeros((n, n))
+    Wd[0, 1:] = Wd[1:, 0] = np.arange(1, m + 1)   # unequal weights still give +-1
+    g = normalised_graph_from_weights(Wd)
+    ev = np.linalg.eigvalsh(g.dense())
+    assert abs(ev[-1] - 1) < 1e-14 and abs(ev[0] + 1) < 1e-14
+    assert np.allclose(ev[1:-1], 0, atol=1e-14)
+    L = (np.eye(n) - ALPHA * g.dense()) / (1 - ALPHA)
+    lv = np.linalg.eigvalsh(L)
+    assert abs(lv[-1] / lv[0] - (1 + ALPHA) / (1 - ALPHA)) < 1e-9 * (1 + ALPHA) / (1 - ALPHA)
+
+
+# ---------------------------------------------------------------- P3 / P4
+
+
+@pytest.mark.parametrize("r", [0, 1, 5, 20, 60])
+def test_theorem_hybrid_equals_truth_at_every_rank(r):
+    """Theorem, eq. (main) with eq. (aux): for the r leading eigenpairs,
+    U1 g(L1) U1^T y + h(S - U1 L1 U1^T) y = h(S) y exactly. Checked with a
+    dense temporal solve (method_dense) and with the oracle's own spectral
+    term plus converged CG (iterate)."""
+    _, g, _ = small_graph()
+    S = g.dense()
+    w, Uf = np.linalg.eigh(S)
+    o = np.argsort(-w)
+    U, lam = Uf[:, o[:r]], w[o[:r]]
+    ids, vals = sparse_y(g.n, 5, 11)
+    y = O.dense_y(g.n, ids, vals)
+    truth = O.truth_dense(S, ALPHA, y)
+    md = O.method_dense(S, U, lam, ALPHA, y)
+    assert np.linalg.norm(md - truth) <= 1e-11 * np.linalg.norm(truth)
+    x, xs, xt, it, rr, st = O.iterate(g, U if r else None, lam, ALPHA, ids, vals, 5000, 1e-14)
+    assert st == O.CONVERGED
+    assert np.linalg.norm(x - truth) <= 1e-9 * np.linalg.norm(truth)
+
+
+def test_theorem_any_orthogonal_split():
+    """The derivation only uses orthogonality of (U1 U2): any subset of
+    eigenpairs, not only the leading ones, gives the exact solution."""
+    _, g, _ = small_graph(seed=9)
+    S = g.dense()
+    w, Uf = np.linalg.eigh(S)
+    pick = np.random.default_rng(2).choice(g.n, size=17, replace=False)
+    ids, vals = sparse_y(g.n, 4, 12)
+    y = O.dense_y(g.n, ids, vals)
+    truth = O.truth_dense(S, ALPHA, y)
+    x, *_ = O.iterate(g, Uf[:, pick], w[pick], ALPHA, ids, vals, 5000, 1e-14)
+    assert np.linalg.norm(x - truth) <= 1e-9 * np.linalg.norm(truth)
+
+
+def test_full_rank_limit_is_spectral_filtering():
+    """r = n: S - U L U^T = 0, the temporal system of eq. (h-temporal) is
+    I/(1 - alpha) x^t = y, so CG returns (1 - alpha) y after one product, and
+    x = U h(L) U^T y, eq. (spectral)."""
+    _, g, _ = small_graph(n=80, seed=13)
+    S = g.dense()
+    w, U = np.linalg.eigh(S)
+    ids, vals = sparse_y(g.n, 5, 14)
+    y = O.dense_y(g.n, ids, vals)
+    x, xs, xt, it, rr, st = O.iterate(g, U, w, ALPHA, ids, vals, 10, 1e-12)
+    assert it == 1 and st == O.CONVERGED
+    assert np.linalg.norm(xt - (1 - ALPHA) * y) <= 1e-12 * np.linalg.norm(y)
+    hx = U @ ((1 - ALPHA) / (1 - ALPHA * w) * (U.T @ y))
+    assert np.linalg.norm(x - hx) <= 1e-12 * np.linalg.norm(hx)
+
+
+def test_spectral_term_uses_g_not_h():
+    """eq. (h-spectral) filters with g(x) = h(x) - h(0) = (1 - alpha) alpha x /
+    (1 - alpha x): for a single eigenvector u and y = u, x^s = g(lambda) u."""
+    _, g, _ = small_graph(n=60, seed=15)
+    w, U = np.linalg.eigh(g.dense())
+    u, lam = U[:, -1:], w[-1:]
+    ids = np.arange(g.n, dtype=np.int32)
+    xs = O.spectral(u, lam, ALPHA, ids, u[:, 0])
+    expect = (1 - ALPHA) * ALPHA * lam[0] / (1 - ALPHA * lam[0]) * u[:, 0]
+    assert np.linalg.norm(xs - expect) <= 1e-13
+
+
+# ---------------------------------------------------------------- P6 / P7
+
+
+def test_condition_number_formula_and_worked_ratio():
+    """eqs. (cond), (cond-r): kappa(L(S_r)) = (1 - alpha lambda_n)/(1 - alpha
+    lambda_{r+1}), checked against a dense eigen-decomposition of the deflated
+    Laplacian; and the worked ratio printed in Section 5."""
+    rows = [l for l in open(os.path.join(HERE, "golden", "cond_ratio.txt")) if not l.startswith("#")]
+    a, lr1, ratio, digits = rows[0].split()
+    a, lr1, ratio, digits = float(a), float(lr1), float(ratio), int(digits)
+    _, g, _ = small_graph()
+    S = g.dense()
+    w, Uf = np.linalg.eigh(S)
+    o = np.argsort(-w)
+    w, Uf = w[o], Uf[:, o]
+    for r in (0, 3, 10):
+        Sr = S - (Uf[:, :r] * w[:r]) @ Uf[:, :r].T
+        lv = np.linalg.eigvalsh((np.eye(g.n) - a * Sr) / (1 - a))
+        kappa = lv[-1] / lv[0]
+        assert abs(kappa - (1 - a * w[-1]) / (1 - a * w[r])) <= 1e-8 * kappa
+    # the ratio kappa(L(W_r))/kappa(L(W)) is (1 - alpha)/(1 - alpha lambda_{r+1})
+    got = (1 - a) / (1 - a * lr1)
+    assert round(got, digits) == ratio
+
+
+@pytest.mark.parametrize("r", [0, 10])
+def test_cg_iterates_obey_error_bound(r):
+    """eq. (bound): ||e_i||_A / ||e_0||_A <= 2 ((sqrt k - 1)/(sqrt k + 1))^i for
+    every iterate of the oracle's CG on L(S_r), with k from eq. (cond-r)."""
+    _, g, _ = small_graph(seed=21)
+    S = g.dense()
+    w, Uf = np.linalg.eigh(S)
+    o = np.argsort(-w)
+    w, Uf = w[o], Uf[:, o]
+    U, lam = Uf[:, :r], w[:r]
+    ids, vals = sparse_y(g.n, 5, 22)
+    y = O.dense_y(g.n, ids, vals)
+    A = (np.eye(g.n) - ALPHA * (S - (U * lam) @ U.T)) / (1 - ALPHA)
+    xstar = np.linalg.solve(A, y)
+    kappa = (1 - ALPHA * w[-1]) / (1 - ALPHA * w[r])
+    q = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    e0 = np.sqrt(xstar @ A @ xstar)
+    for i in range(1, 40):
+        xi, it, _, st = O.cg(g, U if r else None, lam, ALPHA, y, i, 0.0)
+        ei = xstar - xi
+        ratio = np.sqrt(max(ei @ A @ ei, 0.0)) / e0
+        assert ratio <= 2 * q ** i * (1 + 1e-9) + 1e-13, (i, ratio, 2 * q ** i)
+
+
+# ---------------------------------------------------------------- P8
+
+
+def test_graph_fixture_invariants():
+    """Section 3: W symmetric, non-negative, zero diagonal; S = D^-1/2 W
+    D^-1/2 has its spectrum in [-1, 1], top eigenvalue 1 with eigenvector
+    D^1/2 1 on a connected graph, and lambda_n <= -1/(n - 1) (Section 5).
+    The workload's own normalisation agrees with the oracle's."""
+    V, g, w = small_graph(n=200, k=10, seed=31)
+    S = g.dense()
+    assert np.array_equal(S, S.T)
+    assert np.all(np.diag(S) == 0) and np.all(g.val > 0)
+    ev = np.linalg.eigvalsh(S)
+    assert ev[0] >= -1 - 1e-12 and ev[-1] <= 1 + 1e-12
+    assert ev[0] <= -1.0 / (g.n - 1) + 1e-12
+    deg = np.zeros(g.n)
+    np.add.at(deg, np.repeat(np.arange(g.n), np.diff(g.rowptr)), w)
+    import scipy.sparse.csgraph as cg_
+    import scipy.sparse as sp
+    ncomp, lab = cg_.connected_components(sp.csr_matrix((g.val, g.col, g.rowptr), shape=(g.n, g.n)))
+    big = np.argmax(np.bincount(lab))
+    u = np.where(lab == big, np.sqrt(deg), 0.0)
+    u /= np.linalg.norm(u)
+    assert np.linalg.norm(S @ u - u) <= 1e-13
+    assert abs(ev[-1] - 1) <= 1e-13
+    s_w = W.symmetric_normalize(g.n, g.rowptr, g.col, w)
+    assert np.allclose(s_w, g.val, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------- P9
+
+
+def test_invariances_scale_permutation_sign():
+    """Linearity in y, equivariance under relabelling the items, and
+    invariance to the sign of each eigenvector (x depends on U1 only through
+    U1 g(L1) U1^T and U1 L1 U1^T)."""
+    _, g, _ = small_graph(seed=41)
+    S = g.dense()
+    w, Uf = np.linalg.eigh(S)
+    o = np.argsort(-w)[:7]
+    U, lam = Uf[:, o], w[o]
+    ids, vals = sparse_y(g.n, 5, 42)
+    base, *_ = O.iterate(g, U, lam, ALPHA, ids, vals, 12, 0.0)
+    sc, *_ = O.iterate(g, U, lam, ALPHA, ids, 3.5 * vals, 12, 0.0)
+    assert np.linalg.norm(sc - 3.5 * base) <= 1e-13 * np.linalg.norm(sc)
+    flip = U * np.array([1, -1, 1, -1, -1, 1, -1.0])
+    fl, *_ = O.iterate(g, flip, lam, ALPHA, ids, vals, 12, 0.0)
+    assert np.linalg.norm(fl - base) <= 1e-12 * np.linalg.norm(base)
+    perm = np.random.default_rng(43).permutation(g.n)
+    inv = np.argsort(perm)
+    Sp = S[np.ix_(perm, perm)]
+    rp, cl, vv = csr_from_dense(Sp)
+    gp = O.Graph64.from_csr(g.n, rp, cl, vv)
+    pid = inv[ids].astype(np.int32)
+    px, *_ = O.iterate(gp, U[perm], lam, ALPHA, pid, vals, 12, 0.0)
+    assert np.linalg.norm(px[inv] - base) <= 1e-12 * np.linalg.norm(base)
+
+
+def test_rotation_inside_degenerate_eigenspace():
+    """On the cycle graph each eigenvalue cos(2 pi j/n), 0 < j < n/2, has a
+    two-dimensional eigenspace; any orthonormal basis of it gives the same
+    hybrid result."""
+    n = 32
+    Wd = np.zeros((n, n))
+    for i in range(n):
+        Wd[i, (i + 1) % n] = Wd[(i + 1) % n, i] = 1.0
+    g = normalised_graph_from_weights(Wd)
+    t = 2 * np.pi * np.arange(n) / n
+    c1 = np.cos(t) / np.sqrt(n / 2)
+    s1 = np.sin(t) / np.sqrt(n / 2)
+    u0 = np.ones(n) / np.sqrt(n)
+    lam = np.array([1.0, np.cos(2 * np.pi / n), np.cos(2 * np.pi / n)])
+    U = np.stack([u0, c1, s1], 1)
+    th = 0.7
+    R = np.stack([u0, np.cos(th) * c1 + np.sin(th) * s1, -np.sin(th) * c1 + np.cos(th) * s1], 1)
+    ids, vals = np.array([0, 5], np.int32), np.array([1.0, 0.5])
+    a, *_ = O.iterate(g, U, lam, ALPHA, ids, vals, 9, 0.0)
+    b, *_ = O.iterate(g, R, lam, ALPHA, ids, vals, 9, 0.0)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+
+
+# ---------------------------------------------------------------- P10 / P11
+
+
+def test_observation_known_cosines_and_ties():
+    """Sections 3 and 6.1: y keeps the k largest cosines, value max(0, c)^3.
+    Database rows are built with known cosines to the query, including a tie
+    (lower id first) and negative cosines (clamped to 0)."""
+    cos = np.array([0.3, 0.9, -0.5, 0.6, 0.9, 0.1, -0.2, 0.75])
+    V = np.stack([cos, np.sqrt(1 - cos ** 2), np.zeros_like(cos)], 1)
+    q = np.array([1.0, 0.0, 0.0])
+    ids, vals = O.observation(V, q, 4)
+    assert ids.tolist() == [1, 4, 7, 3]
+    assert np.allclose(vals, [0.9 ** 3, 0.9 ** 3, 0.75 ** 3, 0.6 ** 3], rtol=1e-14)
+    ids, vals = O.observation(V, q, 8)
+    assert ids.tolist() == [1, 4, 7, 3, 0, 5, 6, 2]
+    assert vals[-1] == 0.0 and vals[-2] == 0.0
+    ids, vals = O.observation(V, q, 0)
+    assert ids.size == 0
+
+
+def test_observation_matches_exhaustive_sort():
+    """Brute force on a random tiny database: the selected set is the k
+    largest of all n FP64 cosines."""
+    rng = np.random.default_rng(51)
+    V = rng.standard_normal((300, 24))
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    q = V[17] + 0.1 * rng.standard_normal(24)
+    q /= np.linalg.norm(q)
+    s = V @ q
+    order = sorted(range(300), key=lambda j: (-s[j], j))
+    ids, vals = O.observation(V, q, 10)
+    assert ids.tolist() == order[:10]
+    assert np.allclose(vals, np.maximum(s[order[:10]], 0) ** 3, rtol=1e-13)
+
+
+def test_rank_order_and_ties():
+    """Section 3: decreasing x, equal values to the lower id."""
+    x = np.array([0.5, 2.0, -1.0, 2.0, 0.5, 3.0, 0.0])
+    ids, sc = O.rank(x, 7)
+    assert ids.tolist() == [5, 1, 3, 0, 4, 6, 2]
+    assert sc.tolist() == [3.0, 2.0, 2.0, 0.5, 0.5, 0.0, -1.0]
+    perm = np.random.default_rng(3).permutation(1000)
+    ids, _ = O.rank(perm.astype(np.float64), 10)
+    assert ids.tolist() == list(np.argsort(-perm)[:10])
+
+
+# ---------------------------------------------------------------- degenerate cases
+
+
+def test_zero_rhs_and_breakdown_statuses():
+    """y = 0 gives x = 0 and ZERO_RHS; an eigenvalue corrupted so that
+    L(S - U1 L1 U1^T) is indefinite along y gives BREAKDOWN at once."""
+    _, g, _ = small_graph(n=80, seed=61)
+    x, it, rr, st = O.cg(g, None, None, ALPHA, np.zeros(g.n), 10, 1e-6)
+    assert st == O.ZERO_RHS and it == 0 and not np.any(x)
+    w, Uf = np.linalg.eigh(g.dense())
+    u = Uf[:, -1:]
+    bad = np.array([w[-1] - 300.0])       # S_r has eigenvalue 301 along u
+    x, it, rr, st = O.cg(g, u, bad, ALPHA, u[:, 0], 10, 1e-6)
+    assert st == O.BREAKDOWN and it == 0
+
+
+def test_isolated_node_keeps_its_observation():
+    """A node of zero degree has a zero row in S, so x_i = (1 - alpha) y_i."""
+    Wd = np.zeros((5, 5))
+    Wd[0, 1] = Wd[1, 0] = 1.0
+    Wd[1, 2] = Wd[2, 1] = 0.5
+    Wd[2, 3] = Wd[3, 2] = 2.0
+    g = normalised_graph_from_weights(Wd)     # node 4 isolated
+    y = np.array([0.1, 0.0, 0.3, 0.0, 0.7])
+    x = O.truth_dense(g.dense(), ALPHA, y)
+    assert abs(x[4] - (1 - ALPHA) * 0.7) < 1e-15
+    xc, *_ = O.cg(g, None, None, ALPHA, y, 200, 1e-15)
+    assert abs(xc[4] - (1 - ALPHA) * 0.7) < 1e-14
