@@ -1,0 +1,182 @@
+/*
+ * hd.h - C ABI of the MI355X (gfx950) query path of hybrid spectral-temporal
+ * diffusion (Iscen, Avrithis, Tolias, Furon, Chum, "Hybrid Diffusion:
+ * Spectral-Temporal Graph Filtering for Manifold Ranking").
+ *
+ * The library answers batches of queries against a resident database:
+ *   1. the observation vector y of each query: its k_y most similar database
+ *      items, with entries max(0, cos)^3 (Section 3; Section 6.1);
+ *   2. the spectral term x^s = U1 g(L1) U1^T y (Section 4.2, eq. (h-spectral));
+ *   3. the temporal term x^t, conjugate gradient from x0 = 0 on
+ *      L(S - U1 L1 U1^T) x^t = y through the product of eq. (box)
+ *      (Section 4.2, eq. (h-temporal); Section 5);
+ *   4. the ranking of x = x^s + x^t by decreasing value (Section 3,
+ *      eq. (hybrid)).
+ *
+ * Conventions for every entry point:
+ *   - The return value is an hd_status: HD_OK (0) on success, a negative
+ *     code on failure. No entry point aborts or throws; hd_last_error()
+ *     returns a message for the last failure on the calling thread.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are GPU
+ *     memory on the context's device (for instance a torch tensor's
+ *     data_ptr()). Each argument says which it takes.
+ *   - Loaders copy their inputs: the caller may free them on return. The
+ *     library owns every device buffer it allocates and frees them in
+ *     hd_destroy(). It never frees caller memory.
+ *   - A context is used by one host thread at a time.
+ *   - Queries run on the HIP stream passed in (NULL = the default stream).
+ */
+#ifndef HD_H
+#define HD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hd_ctx hd_ctx;
+
+typedef enum {
+    HD_OK = 0,
+    HD_EINVAL = -1,   /* an argument or an input array is invalid          */
+    HD_ENOMEM = -2,   /* a device or host allocation failed                */
+    HD_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed        */
+    HD_ESTATE = -4    /* call out of order (e.g. query before load_graph)  */
+} hd_status;
+
+/* Outcome of one query column of the conjugate-gradient solve. */
+typedef enum {
+    HD_COL_CONVERGED = 0,  /* relative residual reached the tolerance        */
+    HD_COL_MAXITER = 1,    /* stopped at the iteration cap                   */
+    HD_COL_ZERO_RHS = 2,   /* y = 0: x = 0, no iteration                     */
+    HD_COL_BREAKDOWN = 3   /* p^T A p not positive and finite: stopped, last x kept */
+} hd_col_status;
+
+/* Storage precision of the eigenvectors U1 and of the database descriptors. */
+typedef enum {
+    HD_F32 = 0,
+    HD_BF16 = 1,          /* bfloat16, rounded to nearest even from the fp32 input */
+    HD_FP8_E4M3 = 2       /* OCP e4m3 with one fp32 scale per column (U1) or row (V) */
+} hd_dtype;
+
+/* hd_load_graph flags. */
+#define HD_GRAPH_NORMALIZE 1u   /* val holds W; store D^-1/2 W D^-1/2 (Section 3) */
+#define HD_GRAPH_CHECK_SYMMETRY 2u  /* verify W = W^T (costs one pass over the edges) */
+
+/*
+ * Create a context on HIP device `device` (index as seen by this process).
+ * *out receives the context. Errors: HD_EINVAL (bad device or NULL out),
+ * HD_EDEVICE.
+ */
+int hd_create(int device, hd_ctx **out);
+
+/* Release every device buffer of the context and the context itself.
+ * NULL is accepted. Waits for work queued by the context to finish. */
+void hd_destroy(hd_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). The string
+ * stays valid until the next call on this thread. */
+const char *hd_last_error(void);
+
+/*
+ * Load the graph (Section 3): n items, a sparse symmetric non-negative
+ * zero-diagonal matrix in CSR form with int64 row pointers (host, n+1),
+ * int32 column ids (host, nnz) sorted within each row, and fp32 values
+ * (host, nnz). Without HD_GRAPH_NORMALIZE the values are taken as the
+ * normalised S = D^-1/2 W D^-1/2; with it they are W and the library
+ * normalises (in double precision, exactly symmetric; an item of zero
+ * degree gets a zero row). Replaces any previous graph and drops any loaded
+ * eigenpairs and descriptors of another size.
+ * Errors (HD_EINVAL): n <= 0 or n >= 2^31, rowptr not starting at 0,
+ * decreasing or not ending at nnz, a column out of range, unsorted or
+ * repeated within its row, a diagonal entry, a negative or non-finite
+ * value, or (with HD_GRAPH_CHECK_SYMMETRY) an asymmetric matrix.
+ */
+int hd_load_graph(hd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr,
+                  const int32_t *col, const float *val, uint32_t flags);
+
+/*
+ * Load r eigenpairs of S (Section 4.1: U1 is n x r with orthonormal
+ * columns, L1 = diag(lambda)), the input of eqs. (h-spectral) and (box).
+ * U (host, fp32, n x r row-major: row i holds item i's r components),
+ * lambda (host, double, r values, each in [-1, 1] up to 1e-6 of rounding). `dtype` selects the
+ * storage precision on the device (HD_F32, HD_BF16, HD_FP8_E4M3 with a
+ * per-column scale max_i |U_ic| / 448). r = 0 unloads. Queries may use any
+ * prefix of the loaded columns (hd_query_opts.rank_r).
+ * Errors: HD_ESTATE (no graph), HD_EINVAL (r < 0, r > n, lambda outside
+ * [-1, 1] or non-finite, non-finite U, unknown dtype).
+ */
+int hd_load_eigs(hd_ctx *ctx, int32_t r, const float *U, const double *lambda,
+                 int32_t dtype);
+
+/*
+ * Load the database descriptors used to build y from query descriptors
+ * (Section 3: nearest neighbours of the query in the dataset). V (host,
+ * fp32, n x d row-major, unit-norm rows so that the dot product is the
+ * cosine). `dtype` selects the device storage (HD_F32 or HD_BF16).
+ * Errors: HD_ESTATE (no graph), HD_EINVAL (d <= 0, non-finite V, dtype).
+ */
+int hd_load_descriptors(hd_ctx *ctx, int32_t d, const float *V, int32_t dtype);
+
+/* Options of one query batch. */
+typedef struct {
+    double alpha;      /* Section 3: alpha in [0, 1); the paper uses 0.99      */
+    int32_t max_iter;  /* CG iteration cap (number of operator products), >= 0 */
+    double tol;        /* stop a column when sqrt(r^T r / y^T y) <= tol (after
+                          the x and r updates); tol <= 0 runs max_iter products */
+    int32_t rank_r;    /* use the first rank_r loaded eigenpairs (0 = plain CG,
+                          the temporal filtering of eq. (temporal)); -1 = all  */
+    int32_t k_y;       /* non-zeros of y per query, 1..min(n, 1024)             */
+    int32_t top_k;     /* K of the ranking, 0 (none) .. min(n, 1024)           */
+} hd_query_opts;
+
+/*
+ * Answer B queries, 1 <= B <= 1024 (the whole path above, steps 1-4).
+ * Query input, one of:
+ *   q_desc (device, fp32, B x d row-major) with descriptors loaded: y is
+ *     built on the GPU (step 1); or
+ *   q_desc = NULL and y_ids / y_val (device, int32 / fp32, B x k_y
+ *     row-major): a precomputed sparse y per query. Ids must lie in
+ *     [0, n); a repeated id adds its values.
+ * Outputs (each may be NULL when not wanted):
+ *   rank_ids, rank_scores (device, int32 / fp32, B x top_k): the top_k items
+ *     of x per query, best first, equal scores to the lower id;
+ *   x_out (device, fp32, B x n row-major): x = x^s + x^t;
+ *   y_ids_out, y_val_out (device, B x k_y): the y that was used;
+ *   iters, status (host, int32, B) and relres (host, double, B): per-query
+ *     CG iteration count, hd_col_status, and final sqrt(r^T r / y^T y).
+ * The call returns when the batch is complete (the stream is synchronised:
+ * the CG stopping test reads per-column residuals back to the host).
+ * Scalars of CG (dot products, step sizes, residual norms) are double
+ * precision on the GPU; vectors are fp32.
+ * Errors: HD_ESTATE (no graph, no descriptors for q_desc, rank_r above the
+ * loaded r), HD_EINVAL (B < 1, bad options, an id out of range),
+ * HD_ENOMEM, HD_EDEVICE.
+ */
+int hd_query_batch(hd_ctx *ctx, int32_t B, const float *q_desc,
+                   const int32_t *y_ids, const float *y_val,
+                   const hd_query_opts *opts,
+                   int32_t *rank_ids, float *rank_scores, float *x_out,
+                   int32_t *y_ids_out, float *y_val_out,
+                   int32_t *iters, double *relres, int32_t *status,
+                   void *stream);
+
+/*
+ * Rank B score vectors (Section 3: decreasing x, equal values to the lower
+ * id). x (device, fp32, B x n row-major with row stride ldx >= n elements);
+ * ids_out / scores_out (device, B x K). 1 <= K <= min(n, 1024).
+ * Runs asynchronously on `stream`. Errors: HD_EINVAL, HD_ENOMEM, HD_EDEVICE.
+ */
+int hd_rank(hd_ctx *ctx, int32_t B, int64_t n, const float *x, int64_t ldx,
+            int32_t K, int32_t *ids_out, float *scores_out, void *stream);
+
+/* Device bytes currently held by the context (graph, eigenpairs,
+ * descriptors, solver workspace). Returns 0 for NULL. */
+int64_t hd_device_bytes(const hd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HD_H */

@@ -1,0 +1,452 @@
+// C ABI of the library (declared in include/hd.h): argument checking, device
+// memory of the context, and the host-side schedule of one query batch.
+//
+// Schedule of hd_query_batch (one HIP stream):
+//   1. y         : similarity product + top-k_y + cube    (k_sim, k_topk)
+//   2. spectral  : c = U1^T y by gather; Cs = g(L1) c     (k_gather_proj)
+//   3. temporal  : per iteration  [U1^T P -> reduce]      (k_ut_p, k_reduce_c)
+//                                 [Z = P + a U1 L1 U1^T P] (k_u_c)
+//                                 Q = (Z - a S P)/(1 - a)  (k_spmm)
+//                                 scalars, R, X, P updates (k_cg_*)
+//                  stopping test read back once per iteration
+//   4. x = U1 Cs + X, transposed to query-major; top-K     (k_combine, k_topk)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hd.h"
+#include "hd_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? HD_ENOMEM : HD_EDEVICE, "%s: %s",   \
+                        #call, hipGetErrorString(e_));                                  \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Grow-only: keeps the allocation when it is already large enough.
+    hipError_t ensure(size_t want) {
+        if (want <= bytes && p) return hipSuccess;
+        release();
+        if (want == 0) want = 256;
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+int pow2_at_least(int v) {
+    int p = 64;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct hd_ctx {
+    int device = 0;
+    // graph
+    int64_t n = 0, nnz = 0;
+    DevBuf rowptr, col, val;
+    // eigenpairs
+    int r = 0, rp = 0, u_dtype = HD_F32;
+    DevBuf U, lam;
+    // descriptors
+    int d = 0, ldv = 0;
+    DevBuf V;
+    // solver workspace
+    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, part, scal, xbuf, sim, ybuf, topk, err;
+    int32_t *h_pinned = nullptr;  // nact counts + error flag
+    hd::CgState st{};
+};
+
+static int64_t ctx_bytes(const hd_ctx *c) {
+    const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->lam, &c->V, &c->X, &c->R,
+                           &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs, &c->part, &c->scal,
+                           &c->xbuf, &c->sim, &c->ybuf, &c->topk, &c->err};
+    int64_t s = 0;
+    for (const DevBuf *b : all) s += (int64_t)b->bytes;
+    return s;
+}
+
+extern "C" {
+
+const char *hd_last_error(void) { return g_err.c_str(); }
+
+int hd_create(int device, hd_ctx **out) {
+    g_err.clear();
+    if (!out) return fail(HD_EINVAL, "hd_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(HD_EINVAL, "hd_create: device %d not in [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    hd_ctx *c = new (std::nothrow) hd_ctx();
+    if (!c) return fail(HD_ENOMEM, "hd_create: out of host memory");
+    c->device = device;
+    void *hp = nullptr;
+    hipError_t e = hipHostMalloc(&hp, 64 * sizeof(int32_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(HD_ENOMEM, "hd_create: hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    c->h_pinned = reinterpret_cast<int32_t *>(hp);
+    *out = c;
+    return HD_OK;
+}
+
+void hd_destroy(hd_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->lam, &c->V, &c->X, &c->R, &c->P,
+                     &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs, &c->part, &c->scal, &c->xbuf,
+                     &c->sim, &c->ybuf, &c->topk, &c->err};
+    for (DevBuf *b : all) b->release();
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    delete c;
+}
+
+int64_t hd_device_bytes(const hd_ctx *c) { return c ? ctx_bytes(c) : 0; }
+
+int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                  const float *val, uint32_t flags) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_load_graph: NULL context");
+    if (n <= 0 || n >= (int64_t)1 << 31) return fail(HD_EINVAL, "hd_load_graph: n=%lld out of range", (long long)n);
+    if (nnz < 0) return fail(HD_EINVAL, "hd_load_graph: nnz < 0");
+    if (!rowptr || (nnz > 0 && (!col || !val))) return fail(HD_EINVAL, "hd_load_graph: NULL array");
+    if (flags & ~(HD_GRAPH_NORMALIZE | HD_GRAPH_CHECK_SYMMETRY))
+        return fail(HD_EINVAL, "hd_load_graph: unknown flags 0x%x", flags);
+    if (rowptr[0] != 0 || rowptr[n] != nnz)
+        return fail(HD_EINVAL, "hd_load_graph: rowptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t s = rowptr[i], e = rowptr[i + 1];
+        if (e < s) return fail(HD_EINVAL, "hd_load_graph: rowptr decreases at row %lld", (long long)i);
+        for (int64_t k = s; k < e; ++k) {
+            const int32_t j = col[k];
+            if (j < 0 || j >= n) return fail(HD_EINVAL, "hd_load_graph: column %d out of range in row %lld", j, (long long)i);
+            if (j == i) return fail(HD_EINVAL, "hd_load_graph: diagonal entry in row %lld", (long long)i);
+            if (k > s && col[k - 1] >= j)
+                return fail(HD_EINVAL, "hd_load_graph: columns not strictly increasing in row %lld", (long long)i);
+            if (!(val[k] >= 0.f) || !std::isfinite(val[k]))
+                return fail(HD_EINVAL, "hd_load_graph: negative or non-finite value in row %lld", (long long)i);
+        }
+    }
+    if (flags & HD_GRAPH_CHECK_SYMMETRY) {
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int32_t j = col[k];
+                // binary search for i in row j
+                int64_t lo = rowptr[j], hi = rowptr[j + 1];
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) / 2;
+                    if (col[mid] < i) lo = mid + 1; else hi = mid;
+                }
+                if (lo >= rowptr[j + 1] || col[lo] != i || val[lo] != val[k])
+                    return fail(HD_EINVAL, "hd_load_graph: matrix not symmetric at (%lld, %d)", (long long)i, j);
+            }
+        }
+    }
+    std::vector<float> sv;
+    const float *vals = val;
+    if (flags & HD_GRAPH_NORMALIZE) {
+        // Section 3: S = D^-1/2 W D^-1/2, D = diag(W 1), in double precision;
+        // the two scales are multiplied first so S stays exactly symmetric.
+        std::vector<double> dinv((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            double deg = 0.0;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) deg += val[k];
+            dinv[(size_t)i] = deg > 0.0 ? 1.0 / std::sqrt(deg) : 0.0;
+        }
+        sv.resize((size_t)nnz);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                sv[(size_t)k] = (float)((double)val[k] * (dinv[(size_t)i] * dinv[(size_t)col[k]]));
+        vals = sv.data();
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    if (c->n != n) {
+        c->U.release();
+        c->lam.release();
+        c->r = c->rp = 0;
+        c->V.release();
+        c->d = c->ldv = 0;
+    }
+    HIP_TRY(c->rowptr.ensure((size_t)(n + 1) * sizeof(int64_t)));
+    HIP_TRY(c->col.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
+    HIP_TRY(c->val.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(float)));
+    HIP_TRY(hipMemcpy(c->rowptr.p, rowptr, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (nnz > 0) {
+        HIP_TRY(hipMemcpy(c->col.p, col, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->val.p, vals, (size_t)nnz * sizeof(float), hipMemcpyHostToDevice));
+    }
+    c->n = n;
+    c->nnz = nnz;
+    return HD_OK;
+}
+
+int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int32_t dtype) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_load_eigs: NULL context");
+    if (c->n == 0) return fail(HD_ESTATE, "hd_load_eigs: no graph loaded");
+    if (r < 0 || r > c->n) return fail(HD_EINVAL, "hd_load_eigs: r=%d not in [0, n]", r);
+    if (dtype != HD_F32) return fail(HD_EINVAL, "hd_load_eigs: dtype %d not supported", dtype);
+    if (r == 0) {
+        c->U.release();
+        c->lam.release();
+        c->r = c->rp = 0;
+        return HD_OK;
+    }
+    if (!U || !lambda) return fail(HD_EINVAL, "hd_load_eigs: NULL array");
+    for (int k = 0; k < r; ++k)
+        // the spectrum of S lies in [-1, 1]; allow eigensolver rounding
+        if (!(std::fabs(lambda[k]) <= 1.0 + 1e-6))
+            return fail(HD_EINVAL, "hd_load_eigs: lambda[%d]=%g outside [-1, 1]", k, lambda[k]);
+    const int rp = (r + 31) / 32 * 32;
+    const int64_t n = c->n;
+    std::vector<float> host((size_t)n * rp, 0.f);
+    for (int64_t i = 0; i < n; ++i) {
+        const float *src = U + (size_t)i * r;
+        float *dst = host.data() + (size_t)i * rp;
+        for (int k = 0; k < r; ++k) {
+            if (!std::isfinite(src[k])) return fail(HD_EINVAL, "hd_load_eigs: non-finite U at row %lld", (long long)i);
+            dst[k] = src[k];
+        }
+    }
+    std::vector<double> lam((size_t)rp, 0.0);
+    for (int k = 0; k < r; ++k) lam[(size_t)k] = lambda[k];
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(c->U.ensure(host.size() * sizeof(float)));
+    HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
+    HIP_TRY(hipMemcpy(c->U.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->r = r;
+    c->rp = rp;
+    c->u_dtype = dtype;
+    return HD_OK;
+}
+
+int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_load_descriptors: NULL context");
+    if (c->n == 0) return fail(HD_ESTATE, "hd_load_descriptors: no graph loaded");
+    if (d <= 0 || !V) return fail(HD_EINVAL, "hd_load_descriptors: bad d or NULL V");
+    if (dtype != HD_F32) return fail(HD_EINVAL, "hd_load_descriptors: dtype %d not supported", dtype);
+    const int ldv = (d + 31) / 32 * 32;
+    const int64_t n = c->n;
+    std::vector<float> host((size_t)n * ldv, 0.f);
+    for (int64_t i = 0; i < n; ++i) {
+        const float *src = V + (size_t)i * d;
+        float *dst = host.data() + (size_t)i * ldv;
+        for (int t = 0; t < d; ++t) {
+            if (!std::isfinite(src[t])) return fail(HD_EINVAL, "hd_load_descriptors: non-finite V at row %lld", (long long)i);
+            dst[t] = src[t];
+        }
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(c->V.ensure(host.size() * sizeof(float)));
+    HIP_TRY(hipMemcpy(c->V.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->d = d;
+    c->ldv = ldv;
+    return HD_OK;
+}
+
+int hd_rank(hd_ctx *c, int32_t B, int64_t n, const float *x, int64_t ldx, int32_t K,
+            int32_t *ids_out, float *scores_out, void *stream) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_rank: NULL context");
+    if (B < 1 || n < 1 || ldx < n || !x) return fail(HD_EINVAL, "hd_rank: bad B, n, ldx or x");
+    if (K < 1 || K > n || K > hd::kTopkMax)
+        return fail(HD_EINVAL, "hd_rank: K=%d not in [1, min(n, %d)]", K, hd::kTopkMax);
+    if (!ids_out && !scores_out) return HD_OK;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, K)));
+    HIP_TRY(hd::launch_topk(B, n, x, ldx, K, c->topk.p, ids_out, scores_out, 0, (hipStream_t)stream));
+    return HD_OK;
+}
+
+int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
+                   const float *y_val, const hd_query_opts *o, int32_t *rank_ids,
+                   float *rank_scores, float *x_out, int32_t *y_ids_out, float *y_val_out,
+                   int32_t *iters, double *relres, int32_t *status, void *stream) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_query_batch: NULL context");
+    if (c->n == 0) return fail(HD_ESTATE, "hd_query_batch: no graph loaded");
+    if (!o) return fail(HD_EINVAL, "hd_query_batch: NULL options");
+    if (B < 1 || B > 1024) return fail(HD_EINVAL, "hd_query_batch: B=%d not in [1, 1024]", B);
+    if (!(o->alpha >= 0.0 && o->alpha < 1.0)) return fail(HD_EINVAL, "hd_query_batch: alpha=%g not in [0, 1)", o->alpha);
+    if (o->max_iter < 0) return fail(HD_EINVAL, "hd_query_batch: max_iter < 0");
+    if (std::isnan(o->tol)) return fail(HD_EINVAL, "hd_query_batch: tol is NaN");
+    const int64_t n = c->n;
+    const int ky = o->k_y;
+    if (ky < 1 || ky > n || ky > hd::kTopkMax) return fail(HD_EINVAL, "hd_query_batch: k_y=%d out of range", ky);
+    if (o->top_k < 0 || o->top_k > n || o->top_k > hd::kTopkMax)
+        return fail(HD_EINVAL, "hd_query_batch: top_k=%d out of range", o->top_k);
+    const int r_use = o->rank_r < 0 ? c->r : o->rank_r;
+    if (r_use > c->r) return fail(HD_ESTATE, "hd_query_batch: rank_r=%d above the %d loaded eigenpairs", r_use, c->r);
+    if (q_desc) {
+        if (c->d == 0) return fail(HD_ESTATE, "hd_query_batch: descriptors not loaded");
+    } else if (!y_ids || !y_val) {
+        return fail(HD_EINVAL, "hd_query_batch: give q_desc or both y_ids and y_val");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(c->device));
+
+    const int ldb = pow2_at_least(B);
+    const size_t vec = (size_t)n * ldb * sizeof(float);
+    const int rk = (r_use + 31) / 32 * 32;
+    const hd::RowPart rp = hd::make_row_part(n);
+    int64_t rc;
+    const int nchunk = hd::ut_p_chunks(n, &rc);
+    HIP_TRY(c->X.ensure(vec));
+    HIP_TRY(c->R.ensure(vec));
+    HIP_TRY(c->P.ensure(vec));
+    HIP_TRY(c->Q.ensure(vec));
+    if (rk > 0) {
+        HIP_TRY(c->Z.ensure(vec));
+        HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
+        HIP_TRY(c->Cl.ensure((size_t)rk * ldb * sizeof(float)));
+        HIP_TRY(c->Cs.ensure((size_t)rk * ldb * sizeof(float)));
+    }
+    HIP_TRY(c->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
+    HIP_TRY(c->scal.ensure((size_t)ldb * (5 * sizeof(double) + 3 * sizeof(int32_t)) + 64 * sizeof(int32_t)));
+    HIP_TRY(c->err.ensure(sizeof(int32_t) * 4));
+    {
+        char *b = c->scal.as<char>();
+        hd::CgState &st = c->st;
+        st.rho0 = reinterpret_cast<double *>(b); b += ldb * sizeof(double);
+        st.rho = reinterpret_cast<double *>(b); b += ldb * sizeof(double);
+        st.a = reinterpret_cast<double *>(b); b += ldb * sizeof(double);
+        st.beta = reinterpret_cast<double *>(b); b += ldb * sizeof(double);
+        st.relres = reinterpret_cast<double *>(b); b += ldb * sizeof(double);
+        st.active = reinterpret_cast<int32_t *>(b); b += ldb * sizeof(int32_t);
+        st.iters = reinterpret_cast<int32_t *>(b); b += ldb * sizeof(int32_t);
+        st.status = reinterpret_cast<int32_t *>(b); b += ldb * sizeof(int32_t);
+        st.nact_part = reinterpret_cast<int32_t *>(b);
+    }
+    const hd::CgState st = c->st;
+
+    // ---- step 1: observation vectors ----
+    const int32_t *yi = y_ids;
+    const float *yv = y_val;
+    if (q_desc) {
+        const int64_t lds = (n + 63) / 64 * 64;
+        HIP_TRY(c->sim.ensure((size_t)B * lds * sizeof(float)));
+        HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, ky)));
+        int32_t *oi = y_ids_out;
+        float *ov = y_val_out;
+        if (!oi || !ov) {
+            HIP_TRY(c->ybuf.ensure((size_t)B * ky * (sizeof(int32_t) + sizeof(float))));
+            oi = c->ybuf.as<int32_t>();
+            ov = reinterpret_cast<float *>(oi + (size_t)B * ky);
+        }
+        HIP_TRY(hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
+        HIP_TRY(hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
+        yi = oi;
+        yv = ov;
+    } else {
+        if (y_ids_out) HIP_TRY(hipMemcpyAsync(y_ids_out, y_ids, (size_t)B * ky * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        if (y_val_out) HIP_TRY(hipMemcpyAsync(y_val_out, y_val, (size_t)B * ky * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+
+    // ---- CG set-up: X = 0, R = P = y, rho0 = y^T y ----
+    float *X = c->X.as<float>(), *R = c->R.as<float>(), *P = c->P.as<float>(), *Q = c->Q.as<float>();
+    const size_t nv = (size_t)n * ldb;
+    HIP_TRY(hd::launch_fill_zero(X, nv, s));
+    HIP_TRY(hd::launch_fill_zero(R, nv, s));
+    HIP_TRY(hd::launch_fill_zero(P, nv, s));
+    HIP_TRY(hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 1, s));
+    HIP_TRY(hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s));
+    HIP_TRY(hd::launch_colsq_part(n, ldb, R, rp, c->part.as<double>(), s));
+    HIP_TRY(hd::launch_cg_init(B, ldb, c->part.as<double>(), rp.nblk, st, s));
+    HIP_TRY(hipMemcpyAsync(c->h_pinned + 32, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->h_pinned[32] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
+
+    // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
+    const float *U = c->U.as<float>();
+    if (rk > 0)
+        HIP_TRY(hd::launch_gather_proj(B, ky, yi, yv, n, U, c->rp, rk, r_use, c->lam.as<double>(), o->alpha, ldb,
+                                       c->Cs.as<float>(), c->Cl.as<float>(), s));
+
+    // ---- step 3: CG on the deflated system ----
+    const int ntile = ldb / 64;
+    for (int it = 1; it <= o->max_iter; ++it) {
+        const float *Zs = P;
+        if (rk > 0) {
+            if (it > 1) {
+                HIP_TRY(hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), s));
+                HIP_TRY(hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), r_use,
+                                            c->Cl.as<float>(), s));
+            }
+            HIP_TRY(hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), s));
+            Zs = c->Z.as<float>();
+        }
+        HIP_TRY(hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
+                                ldb, o->alpha, rp, c->part.as<double>(), s));
+        HIP_TRY(hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, s));
+        HIP_TRY(hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), s));
+        HIP_TRY(hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, s));
+        HIP_TRY(hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, s));
+        HIP_TRY(hipMemcpyAsync(c->h_pinned, st.nact_part, ntile * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int nact = 0;
+        for (int t = 0; t < ntile; ++t) nact += c->h_pinned[t];
+        if (nact == 0) break;
+    }
+    HIP_TRY(hd::launch_cg_final(ldb, st, s));
+
+    // ---- step 4: x = x^s + x^t (query-major), ranking ----
+    float *xq = x_out;
+    if (!xq) {
+        HIP_TRY(c->xbuf.ensure((size_t)B * n * sizeof(float)));
+        xq = c->xbuf.as<float>();
+    }
+    if (x_out || o->top_k > 0)
+        HIP_TRY(hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, X, xq, n, s));
+    if (o->top_k > 0 && (rank_ids || rank_scores)) {
+        HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, o->top_k)));
+        HIP_TRY(hd::launch_topk(B, n, xq, n, o->top_k, c->topk.p, rank_ids, rank_scores, 0, s));
+    }
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, st.iters, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (status) HIP_TRY(hipMemcpyAsync(status, st.status, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (relres) HIP_TRY(hipMemcpyAsync(relres, st.relres, B * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Device-side helpers shared by the gfx950 kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kBlock = 256;      // threads per block in every kernel (4 waves)
+
+// Broadcast lane `lane` (wave-uniform) of v to the whole wavefront.
+__device__ __forceinline__ int bcast_i(int v, int lane) {
+    return __builtin_amdgcn_readlane(v, lane);
+}
+__device__ __forceinline__ float bcast_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Monotone map float -> uint32: a > b (as floats, no NaN) iff key(a) > key(b).
+__device__ __forceinline__ uint32_t float_order_key(float x) {
+    uint32_t u = __float_as_uint(x);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float float_from_order_key(uint32_t k) {
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+// 64-bit ranking key: larger score first, and for equal scores the lower id
+// first (the id is stored complemented in the low word).
+__device__ __forceinline__ uint64_t rank_key(float score, uint32_t id) {
+    return ((uint64_t)float_order_key(score) << 32) | (uint64_t)(0xffffffffu - id);
+}
+__device__ __forceinline__ uint32_t rank_key_id(uint64_t k) {
+    return 0xffffffffu - (uint32_t)(k & 0xffffffffu);
+}
+__device__ __forceinline__ float rank_key_score(uint64_t k) {
+    return float_from_order_key((uint32_t)(k >> 32));
+}
+
+// Sum of a double over the 64 lanes of a wavefront (fixed butterfly order).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+}  // namespace hd

@@ -1,0 +1,91 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+//
+// Layouts used throughout:
+//   - graph: CSR with int64 row pointers, int32 columns, fp32 values;
+//   - solver vectors (X, R, P, Q, Z): node-major N x ldb fp32, row i holds
+//     the ldb query columns of item i; ldb is a power of two >= 64 and the
+//     columns B..ldb-1 are padding that stays zero;
+//   - eigenvectors U: node-major N x rp (rp = r rounded up to 32, zero
+//     padded); coefficient matrices (C, Cl, Cs): rk x ldb;
+//   - scores for ranking and similarities: query-major B x ld rows.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hd {
+
+// Per-column CG state on the device (all arrays hold ldb entries).
+struct CgState {
+    double *rho0, *rho, *a, *beta, *relres;
+    int32_t *active, *iters, *status;
+    int32_t *nact_part;  // one active-column count per 64-column tile
+};
+
+// Row partition shared by every kernel that writes per-block partial sums:
+// block g covers rows [g*rb, min(N, (g+1)*rb)).
+struct RowPart {
+    int64_t rb;
+    int nblk;
+};
+RowPart make_row_part(int64_t N);
+
+// ---- CG vector kernels (k_cg.hip) ----
+hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s);
+hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
+                            int ldb, float *R, float *P, int32_t *err, hipStream_t s);
+hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
+                             hipStream_t s);
+hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s);
+hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, hipStream_t s);
+hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
+                           const double *a, double *part, hipStream_t s);
+hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
+                            hipStream_t s);
+hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
+                            const double *a, const double *beta, const int32_t *active,
+                            hipStream_t s);
+hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
+hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
+                              const float *U, int rp, int rk, int r_use, const double *lam,
+                              double alpha, int ldb, float *Cs, float *Cl, hipStream_t s);
+
+// ---- sparse product (k_spmm.hip) ----
+// Q = (Zs - alpha * S P) / (1 - alpha); gpart[g][c] = sum over the rows of
+// block g of P[i][c] * Q[i][c] (double).
+hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
+                       const float *P, const float *Zs, float *Q, int ldb, double alpha,
+                       RowPart rp, double *gpart, hipStream_t s);
+
+// ---- eigenvector products on MFMA (k_ugemm.hip) ----
+// Number of row chunks of the split-K product U^T P.
+int ut_p_chunks(int64_t N, int64_t *rows_per_chunk);
+// Cpart[c] = U[chunk c]^T P[chunk c]  (rk x ldb per chunk)
+hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P, int ldb,
+                       float *Cpart, hipStream_t s);
+// Cl = lambda .* sum_c Cpart[c]   (rows k >= r_use zeroed)
+hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
+                           int r_use, float *Cl, hipStream_t s);
+// Z = P + alpha * U Cl
+hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl, int ldb,
+                      const float *P, double alpha, float *Z, hipStream_t s);
+// x[b][i] = (U Cs)[i][b] + X[i][b] for b < B, i < N   (x row stride ldx)
+hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
+                          int ldb, const float *X, float *x, int64_t ldx, hipStream_t s);
+
+// ---- similarity product for the observation vector (k_sim.hip) ----
+// sim[b][j] = sum_t q[b][t] V[j][t]  (q: B x d, row stride d; V: N x ldv)
+hipError_t launch_sim(int64_t N, int B, int d, const float *q, const float *V, int ldv,
+                      float *sim, int64_t lds, hipStream_t s);
+
+// ---- top-K selection (k_topk.hip) ----
+constexpr int kTopkChunk = 2048;
+constexpr int kTopkMax = 1024;
+// Bytes of scratch for selecting K of n in B rows.
+size_t topk_scratch_bytes(int B, int64_t n, int K);
+// ids/scores (B x K): the K largest x per row, best first, equal values to
+// the lower id. transform = 1 writes max(0, s)^3 in place of the score.
+hipError_t launch_topk(int B, int64_t n, const float *x, int64_t ldx, int K, void *scratch,
+                       int32_t *ids, float *scores, int transform, hipStream_t s);
+
+}  // namespace hd

@@ -1,0 +1,376 @@
+// Conjugate-gradient vector and scalar kernels for the temporal term
+// (Section 4.2, eq. (h-temporal); Section 5: CG from x0 = 0).
+//
+// B query columns are solved side by side as independent CG recurrences
+// (not block CG): every dot product, step size and stopping test is per
+// column and in double precision, the vectors are fp32. Per-block partial
+// sums are reduced in a fixed order, so a column's result does not depend on
+// which other columns share the batch.
+//
+// One iteration, for each active column c:
+//   Q = A P                                   (k_spmm.hip, k_ugemm.hip)
+//   gamma = P^T Q ; a = rho / gamma           (cg_step_a)
+//   R -= a Q ; rho' = R^T R                   (update_r)
+//   stop if sqrt(rho'/rho0) <= tol ; beta = rho'/rho   (cg_step_b)
+//   X += a P ; P = R + beta P                 (update_xp)
+#include "hd_device.h"
+#include "hd_kernels.h"
+
+namespace hd {
+
+enum { COL_CONVERGED = 0, COL_MAXITER = 1, COL_ZERO_RHS = 2, COL_BREAKDOWN = 3 };
+
+RowPart make_row_part(int64_t N) {
+    // at most ~2048 blocks so that the scalar kernels reduce few partials
+    int64_t rb = (N + 2047) / 2048;
+    rb = ((rb + 63) / 64) * 64;
+    if (rb < 64) rb = 64;
+    RowPart p;
+    p.rb = rb;
+    p.nblk = (int)((N + rb - 1) / rb);
+    if (p.nblk < 1) p.nblk = 1;
+    return p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(float4 *p, size_t n4, float *tail, int ntail) {
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * kBlock;
+    for (; i < n4; i += stride) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0.f;
+}
+
+hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t n4 = n / 4;
+    int ntail = (int)(n - n4 * 4);
+    size_t want = (n4 + kBlock - 1) / kBlock;
+    int grid = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    k_fill_zero<<<grid, kBlock, 0, s>>>(reinterpret_cast<float4 *>(p), n4, p + n4 * 4, ntail);
+    return hipGetLastError();
+}
+
+// R, P = y (dense, node-major) from the sparse y of each column. Ids outside
+// [0, N) are skipped and flagged in *err.
+__global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32_t *ids,
+                                                      const float *vals, int64_t N, int ldb,
+                                                      float *R, float *P, int32_t *err) {
+    int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= B * ky) return;
+    int b = idx / ky;
+    int id = ids[idx];
+    if (id < 0 || (int64_t)id >= N) {
+        atomicOr(err, 1);
+        return;
+    }
+    float v = vals[idx];
+    atomicAdd(&R[(size_t)id * ldb + b], v);
+    atomicAdd(&P[(size_t)id * ldb + b], v);
+}
+
+hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
+                            int ldb, float *R, float *P, int32_t *err, hipStream_t s) {
+    int tot = B * ky;
+    if (tot == 0) return hipSuccess;
+    k_scatter_y<<<(tot + kBlock - 1) / kBlock, kBlock, 0, s>>>(B, ky, ids, vals, N, ldb, R, P, err);
+    return hipGetLastError();
+}
+
+// Each thread owns 4 consecutive columns (one float4) of one row; the
+// kBlock/G threads of a block that own the same columns step over the
+// block's rows together, then combine in LDS in a fixed order.
+__device__ __forceinline__ void block_colsum4(double s0, double s1, double s2, double s3, int G,
+                                              double *out /* ldb-strided row of partials */) {
+    __shared__ double sh[kBlock * 4];
+    int t = threadIdx.x;
+    sh[t * 4 + 0] = s0;
+    sh[t * 4 + 1] = s1;
+    sh[t * 4 + 2] = s2;
+    sh[t * 4 + 3] = s3;
+    __syncthreads();
+    int rows = kBlock / G;
+    if (t < G) {
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int rr = 0; rr < rows; ++rr) {
+            const double *q = sh + (rr * G + t) * 4;
+            a0 += q[0];
+            a1 += q[1];
+            a2 += q[2];
+            a3 += q[3];
+        }
+        out[t * 4 + 0] = a0;
+        out[t * 4 + 1] = a1;
+        out[t * 4 + 2] = a2;
+        out[t * 4 + 3] = a3;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_colsq_part(int64_t N, int ldb, const float *R,
+                                                       int64_t rb, double *part) {
+    const int G = ldb / 4;
+    const int rows = kBlock / G;
+    int cg = threadIdx.x % G;
+    int r0 = threadIdx.x / G;
+    int64_t rs = (int64_t)blockIdx.x * rb;
+    int64_t re = rs + rb < N ? rs + rb : N;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int64_t i = rs + r0; i < re; i += rows) {
+        float4 v = reinterpret_cast<const float4 *>(R + (size_t)i * ldb)[cg];
+        s0 += (double)v.x * v.x;
+        s1 += (double)v.y * v.y;
+        s2 += (double)v.z * v.z;
+        s3 += (double)v.w * v.w;
+    }
+    block_colsum4(s0, s1, s2, s3, G, part + (size_t)blockIdx.x * ldb);
+}
+
+hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
+                             hipStream_t s) {
+    k_colsq_part<<<rp.nblk, kBlock, 0, s>>>(N, ldb, R, rp.rb, part);
+    return hipGetLastError();
+}
+
+// Fixed-order reduction of nblk partials for the 64 columns of this block's
+// tile: wave w sums a contiguous quarter, the quarters are then added in
+// order. Returns the total for column (tile*64 + lane) on wave 0.
+__device__ __forceinline__ double tile_reduce(const double *part, int nblk, int ldb, int col) {
+    __shared__ double sh[4][kWave];
+    int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int q = (nblk + 3) / 4;
+    int g0 = w * q, g1 = g0 + q < nblk ? g0 + q : nblk;
+    double acc = 0;
+    for (int g = g0; g < g1; ++g) acc += part[(size_t)g * ldb + col];
+    sh[w][lane] = acc;
+    __syncthreads();
+    return ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_init(int B, int ldb, const double *part, int nblk,
+                                                    CgState st) {
+    int lane = threadIdx.x % kWave;
+    int c = blockIdx.x * kWave + lane;
+    double rho0 = tile_reduce(part, nblk, ldb, c);
+    __shared__ int cnt[kWave];
+    if (threadIdx.x < kWave) {
+        int act = 0, stat;
+        if (c >= B || rho0 == 0.0) {
+            stat = COL_ZERO_RHS;
+            rho0 = 0.0;
+        } else if (!(rho0 > 0.0) || !isfinite(rho0)) {
+            stat = COL_BREAKDOWN;
+        } else {
+            stat = COL_MAXITER;
+            act = 1;
+        }
+        st.rho0[c] = rho0;
+        st.rho[c] = rho0;
+        st.a[c] = 0.0;
+        st.beta[c] = 0.0;
+        st.relres[c] = 0.0;
+        st.active[c] = act;
+        st.iters[c] = 0;
+        st.status[c] = stat;
+        cnt[lane] = act;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int l = 0; l < kWave; ++l) n += cnt[l];
+        st.nact_part[blockIdx.x] = n;
+    }
+}
+
+hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s) {
+    k_cg_init<<<ldb / kWave, kBlock, 0, s>>>(B, ldb, part, nblk, st);
+    return hipGetLastError();
+}
+
+// gamma = P^T Q per column; a = rho / gamma, or stop the column (breakdown)
+// when gamma is not positive and finite.
+__global__ __launch_bounds__(kBlock) void k_cg_step_a(int ldb, const double *gpart, int nblk,
+                                                      CgState st) {
+    int lane = threadIdx.x % kWave;
+    int c = blockIdx.x * kWave + lane;
+    double gamma = tile_reduce(gpart, nblk, ldb, c);
+    if (threadIdx.x < kWave) {
+        double a = 0.0;
+        if (st.active[c]) {
+            if (!(gamma > 0.0) || !isfinite(gamma)) {
+                st.status[c] = COL_BREAKDOWN;
+                st.active[c] = 0;
+            } else {
+                a = st.rho[c] / gamma;
+            }
+        }
+        st.a[c] = a;
+    }
+}
+
+hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, hipStream_t s) {
+    k_cg_step_a<<<ldb / kWave, kBlock, 0, s>>>(ldb, gpart, nblk, st);
+    return hipGetLastError();
+}
+
+// R -= a Q, and per-block partials of the new R^T R.
+__global__ __launch_bounds__(kBlock) void k_update_r(int64_t N, int ldb, const float *Q, float *R,
+                                                     int64_t rb, const double *a, double *part) {
+    const int G = ldb / 4;
+    const int rows = kBlock / G;
+    int cg = threadIdx.x % G;
+    int r0 = threadIdx.x / G;
+    double a0 = a[cg * 4 + 0], a1 = a[cg * 4 + 1], a2 = a[cg * 4 + 2], a3 = a[cg * 4 + 3];
+    int64_t rs = (int64_t)blockIdx.x * rb;
+    int64_t re = rs + rb < N ? rs + rb : N;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int64_t i = rs + r0; i < re; i += rows) {
+        float4 *rp = reinterpret_cast<float4 *>(R + (size_t)i * ldb) + cg;
+        float4 q = reinterpret_cast<const float4 *>(Q + (size_t)i * ldb)[cg];
+        float4 r = *rp;
+        // a = 0 leaves a stopped column untouched even if its Q is not finite
+        if (a0 != 0.0) r.x = (float)((double)r.x - a0 * (double)q.x);
+        if (a1 != 0.0) r.y = (float)((double)r.y - a1 * (double)q.y);
+        if (a2 != 0.0) r.z = (float)((double)r.z - a2 * (double)q.z);
+        if (a3 != 0.0) r.w = (float)((double)r.w - a3 * (double)q.w);
+        *rp = r;
+        s0 += (double)r.x * r.x;
+        s1 += (double)r.y * r.y;
+        s2 += (double)r.z * r.z;
+        s3 += (double)r.w * r.w;
+    }
+    block_colsum4(s0, s1, s2, s3, G, part + (size_t)blockIdx.x * ldb);
+}
+
+hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
+                           const double *a, double *part, hipStream_t s) {
+    k_update_r<<<rp.nblk, kBlock, 0, s>>>(N, ldb, Q, R, rp.rb, a, part);
+    return hipGetLastError();
+}
+
+// rho' = R^T R per column; stopping test sqrt(rho'/rho0) <= tol after the
+// update; beta = rho'/rho for the columns that go on.
+__global__ __launch_bounds__(kBlock) void k_cg_step_b(int ldb, const double *part, int nblk,
+                                                      double tol, CgState st) {
+    int lane = threadIdx.x % kWave;
+    int c = blockIdx.x * kWave + lane;
+    double rho_new = tile_reduce(part, nblk, ldb, c);
+    __shared__ int cnt[kWave];
+    if (threadIdx.x < kWave) {
+        int act = st.active[c];
+        if (act) {
+            st.iters[c] += 1;
+            double rel = sqrt(rho_new / st.rho0[c]);
+            if (rel <= tol) {
+                st.status[c] = COL_CONVERGED;
+                st.active[c] = 0;
+                act = 0;
+            } else {
+                st.beta[c] = rho_new / st.rho[c];
+            }
+            st.rho[c] = rho_new;
+        }
+        cnt[lane] = act;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int l = 0; l < kWave; ++l) n += cnt[l];
+        st.nact_part[blockIdx.x] = n;
+    }
+}
+
+hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
+                            hipStream_t s) {
+    k_cg_step_b<<<ldb / kWave, kBlock, 0, s>>>(ldb, part, nblk, tol, st);
+    return hipGetLastError();
+}
+
+// X += a P (the step of this iteration); P = R + beta P for columns still
+// active after the stopping test.
+__global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, float *X, float *P,
+                                                      const float *R, const double *a,
+                                                      const double *beta, const int32_t *active) {
+    const int G = ldb / 4;
+    const int rows = kBlock / G;
+    int cg = threadIdx.x % G;
+    int r0 = threadIdx.x / G;
+    double a0 = a[cg * 4 + 0], a1 = a[cg * 4 + 1], a2 = a[cg * 4 + 2], a3 = a[cg * 4 + 3];
+    double b0 = beta[cg * 4 + 0], b1 = beta[cg * 4 + 1], b2 = beta[cg * 4 + 2], b3 = beta[cg * 4 + 3];
+    int k0 = active[cg * 4 + 0], k1 = active[cg * 4 + 1], k2 = active[cg * 4 + 2], k3 = active[cg * 4 + 3];
+    size_t total = (size_t)N;
+    for (size_t i = (size_t)blockIdx.x * rows + r0; i < total; i += (size_t)gridDim.x * rows) {
+        float4 *xp = reinterpret_cast<float4 *>(X + i * ldb) + cg;
+        float4 *pp = reinterpret_cast<float4 *>(P + i * ldb) + cg;
+        float4 r = reinterpret_cast<const float4 *>(R + i * ldb)[cg];
+        float4 x = *xp, p = *pp;
+        if (a0 != 0.0) x.x = (float)((double)x.x + a0 * (double)p.x);
+        if (a1 != 0.0) x.y = (float)((double)x.y + a1 * (double)p.y);
+        if (a2 != 0.0) x.z = (float)((double)x.z + a2 * (double)p.z);
+        if (a3 != 0.0) x.w = (float)((double)x.w + a3 * (double)p.w);
+        if (k0) p.x = (float)((double)r.x + b0 * (double)p.x);
+        if (k1) p.y = (float)((double)r.y + b1 * (double)p.y);
+        if (k2) p.z = (float)((double)r.z + b2 * (double)p.z);
+        if (k3) p.w = (float)((double)r.w + b3 * (double)p.w);
+        *xp = x;
+        *pp = p;
+    }
+}
+
+hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
+                            const double *a, const double *beta, const int32_t *active,
+                            hipStream_t s) {
+    int rows = kBlock / (ldb / 4);
+    int64_t want = (N + rows - 1) / rows;
+    int grid = (int)(want < 16384 ? want : 16384);
+    if (grid < 1) grid = 1;
+    k_update_xp<<<grid, kBlock, 0, s>>>(N, ldb, X, P, R, a, beta, active);
+    return hipGetLastError();
+}
+
+__global__ void k_cg_final(int ldb, CgState st) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ldb) return;
+    double r0 = st.rho0[c];
+    st.relres[c] = r0 > 0.0 ? sqrt(st.rho[c] / r0) : 0.0;
+}
+
+hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s) {
+    k_cg_final<<<(ldb + 63) / 64, 64, 0, s>>>(ldb, st);
+    return hipGetLastError();
+}
+
+// Section 4.2, eq. (h-spectral): c = U1^T y is a gather of the k_y rows of U1
+// that y touches. Writes Cs = g(lambda) .* c (the spectral coefficients,
+// g(x) = h(x) - h(0), eq. (aux)) and Cl = lambda .* c, which is L1 U1^T P for
+// the first CG product since P0 = y.
+__global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int32_t *ids,
+                                                        const float *vals, int64_t N,
+                                                        const float *U, int rp, int rk, int r_use,
+                                                        const double *lam, double alpha, int ldb,
+                                                        float *Cs, float *Cl) {
+    int k = blockIdx.x * kBlock + threadIdx.x;
+    int b = blockIdx.y;
+    if (k >= rk) return;
+    double acc = 0.0;
+    if (k < r_use && b < B) {
+        for (int t = 0; t < ky; ++t) {
+            int id = ids[b * ky + t];
+            if (id >= 0 && (int64_t)id < N) acc += (double)U[(size_t)id * rp + k] * (double)vals[b * ky + t];
+        }
+    }
+    double lk = k < r_use ? lam[k] : 0.0;
+    double h = (1.0 - alpha) / (1.0 - alpha * lk);
+    double g = h - (1.0 - alpha);
+    Cs[(size_t)k * ldb + b] = (float)(g * acc);
+    Cl[(size_t)k * ldb + b] = (float)(lk * acc);
+}
+
+hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
+                              const float *U, int rp, int rk, int r_use, const double *lam,
+                              double alpha, int ldb, float *Cs, float *Cl, hipStream_t s) {
+    if (rk == 0) return hipSuccess;
+    dim3 grid((rk + kBlock - 1) / kBlock, ldb);
+    k_gather_proj<<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N, U, rp, rk, r_use, lam, alpha, ldb,
+                                          Cs, Cl);
+    return hipGetLastError();
+}
+
+}  // namespace hd

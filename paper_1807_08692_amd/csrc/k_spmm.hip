@@ -1,0 +1,169 @@
+// Sparse product with the normalised graph over many right-hand sides, the
+// S z part of the operator of Section 4.2, eq. (box):
+//     Q = (Zs - alpha * S P) / (1 - alpha),
+// where Zs = P + alpha U1 L1 U1^T P (from k_ugemm.hip) or Zs = P when r = 0
+// (plain temporal filtering, eq. (temporal)). It also returns per-block
+// partials of gamma = P^T Q in double precision.
+//
+// gfx950 mapping: one wavefront per graph row; the 64 lanes (x CPL columns
+// per lane) cover a tile of query columns, so the gathered row P[j, :] of
+// each neighbour is one contiguous, fully coalesced load. The wave fetches
+// 64 (column id, value) pairs of its row at a time and broadcasts each pair
+// with readlane, keeping up to 16 gathers in flight. The kernel is bound by
+// HBM (or Infinity Cache) bandwidth: it reads the CSR once, gathers P, and
+// streams Zs in and Q out.
+#include "hd_device.h"
+#include "hd_kernels.h"
+
+namespace hd {
+
+template <int CPL>
+struct VecF;
+template <>
+struct VecF<1> {
+    float v[1];
+    __device__ __forceinline__ void load(const float *p) { v[0] = *p; }
+    __device__ __forceinline__ void store(float *p) const { *p = v[0]; }
+};
+template <>
+struct VecF<2> {
+    float v[2];
+    __device__ __forceinline__ void load(const float *p) {
+        float2 t = *reinterpret_cast<const float2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    }
+    __device__ __forceinline__ void store(float *p) const {
+        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+    }
+};
+template <>
+struct VecF<4> {
+    float v[4];
+    __device__ __forceinline__ void load(const float *p) {
+        float4 t = *reinterpret_cast<const float4 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
+    __device__ __forceinline__ void store(float *p) const {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+
+template <int CPL>
+__global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const float *__restrict__ val,
+                                                 const float *__restrict__ P,
+                                                 const float *__restrict__ Zs,
+                                                 float *__restrict__ Q, int ldb, float alpha,
+                                                 float one_minus_alpha, int64_t rb,
+                                                 double *__restrict__ gpart) {
+    const int lane = threadIdx.x % kWave;
+    const int w = threadIdx.x / kWave;
+    const int c0 = blockIdx.y * (kWave * CPL) + lane * CPL;
+    const int64_t rs = (int64_t)blockIdx.x * rb;
+    const int64_t re = rs + rb < N ? rs + rb : N;
+    double g[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) g[c] = 0.0;
+
+    for (int64_t i = rs + w; i < re; i += 4) {
+        const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+        float acc[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] = 0.f;
+        for (int64_t eb = e0; eb < e1; eb += kWave) {
+            const int64_t me = eb + lane;
+            int cidx = 0;
+            float cv = 0.f;
+            if (me < e1) {
+                cidx = col[me];
+                cv = val[me];
+            }
+            const int cnt = (int)(e1 - eb < kWave ? e1 - eb : kWave);
+            int t = 0;
+            for (; t + 16 <= cnt; t += 16) {
+                VecF<CPL> pv[16];
+                float vv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int j = bcast_i(cidx, t + u);
+                    vv[u] = bcast_f(cv, t + u);
+                    pv[u].load(P + (size_t)j * ldb + c0);
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) acc[c] += vv[u] * pv[u].v[c];
+            }
+            for (; t + 4 <= cnt; t += 4) {
+                VecF<CPL> pv[4];
+                float vv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = bcast_i(cidx, t + u);
+                    vv[u] = bcast_f(cv, t + u);
+                    pv[u].load(P + (size_t)j * ldb + c0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) acc[c] += vv[u] * pv[u].v[c];
+            }
+            for (; t < cnt; ++t) {
+                const int j = bcast_i(cidx, t);
+                const float v = bcast_f(cv, t);
+                VecF<CPL> pv;
+                pv.load(P + (size_t)j * ldb + c0);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) acc[c] += v * pv.v[c];
+            }
+        }
+        VecF<CPL> z, p, q;
+        z.load(Zs + (size_t)i * ldb + c0);
+        if (Zs == P) {
+            p = z;
+        } else {
+            p.load(P + (size_t)i * ldb + c0);
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            q.v[c] = (z.v[c] - alpha * acc[c]) / one_minus_alpha;
+            g[c] += (double)p.v[c] * (double)q.v[c];
+        }
+        q.store(Q + (size_t)i * ldb + c0);
+    }
+
+    __shared__ double sh[4][kWave * CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) sh[w][lane * CPL + c] = g[c];
+    __syncthreads();
+    for (int t = threadIdx.x; t < kWave * CPL; t += kBlock) {
+        double s = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+        gpart[(size_t)blockIdx.x * ldb + blockIdx.y * (kWave * CPL) + t] = s;
+    }
+}
+
+hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
+                       const float *P, const float *Zs, float *Q, int ldb, double alpha,
+                       RowPart rp, double *gpart, hipStream_t s) {
+    const float a = (float)alpha, oma = (float)(1.0 - alpha);
+    if (ldb == 64) {
+        k_spmm<1><<<dim3(rp.nblk, 1), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma,
+                                                       rp.rb, gpart);
+    } else if (ldb == 128) {
+        k_spmm<2><<<dim3(rp.nblk, 1), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma,
+                                                       rp.rb, gpart);
+    } else if (ldb >= 256 && ldb % 256 == 0) {
+        k_spmm<4><<<dim3(rp.nblk, ldb / 256), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb,
+                                                               a, oma, rp.rb, gpart);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hd

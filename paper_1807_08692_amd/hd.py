@@ -1,0 +1,199 @@
+"""Python binding of the C ABI in include/hd.h (ctypes, argument marshalling
+only). Every step of the query path runs in the library's HIP kernels;
+torch supplies device buffers and streams. There is no fallback: without the
+built library (``libhd.so``, see ``build.py``) every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhd.so")
+
+HD_OK, HD_EINVAL, HD_ENOMEM, HD_EDEVICE, HD_ESTATE = 0, -1, -2, -3, -4
+COL_CONVERGED, COL_MAXITER, COL_ZERO_RHS, COL_BREAKDOWN = 0, 1, 2, 3
+HD_F32, HD_BF16, HD_FP8_E4M3 = 0, 1, 2
+HD_GRAPH_NORMALIZE, HD_GRAPH_CHECK_SYMMETRY = 1, 2
+TOPK_MAX = 1024
+
+_DTYPES = {"f32": HD_F32, "bf16": HD_BF16, "fp8": HD_FP8_E4M3}
+
+# Exported entry points and their ctypes signatures (same names as hd.h).
+_P = ctypes.c_void_p
+_SIGS = {
+    "hd_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "hd_destroy": (None, [_P]),
+    "hd_last_error": (ctypes.c_char_p, []),
+    "hd_load_graph": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P, ctypes.c_uint32]),
+    "hd_load_eigs": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
+    "hd_load_descriptors": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32]),
+    "hd_query_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                      _P, _P, _P, _P]),
+    "hd_rank": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
+                               ctypes.c_int32, _P, _P, _P]),
+    "hd_device_bytes": (ctypes.c_int64, [_P]),
+}
+
+
+class hd_query_opts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("rank_r", ctypes.c_int32), ("k_y", ctypes.c_int32), ("top_k", ctypes.c_int32)]
+
+
+class HDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_1807_08692_amd.build.build() (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().hd_last_error().decode()
+
+
+def _check(code: int):
+    if code != HD_OK:
+        raise HDError(code, last_error())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream) if stream.cuda_stream else None
+
+
+class Context:
+    """One hd_ctx on a GPU (hd_create / hd_destroy)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().hd_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.n = 0
+        self.r = 0
+        self.d = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- loaders (host arrays, copied) ----
+    def load_graph(self, n, rowptr, col, val, normalize=False, check_symmetry=False):
+        rp, rpp = _host(rowptr, np.int64)
+        cl, clp = _host(col, np.int32)
+        vl, vlp = _host(val, np.float32)
+        flags = (HD_GRAPH_NORMALIZE if normalize else 0) | (HD_GRAPH_CHECK_SYMMETRY if check_symmetry else 0)
+        _check(lib().hd_load_graph(self._h, int(n), int(cl.size), rpp, clp, vlp, flags))
+        self.n = int(n)
+
+    def load_eigs(self, U, lam, dtype="f32"):
+        U = np.asarray(U)
+        r = 0 if U.size == 0 else U.shape[1]
+        Ua, Up = _host(U.reshape(self.n, r) if r else np.zeros(1, np.float32), np.float32)
+        la, lp = _host(lam if r else np.zeros(1), np.float64)
+        _check(lib().hd_load_eigs(self._h, r, Up, lp, _DTYPES[dtype]))
+        self.r = r
+
+    def load_descriptors(self, V, dtype="f32"):
+        Va, Vp = _host(V, np.float32)
+        _check(lib().hd_load_descriptors(self._h, int(Va.shape[1]), Vp, _DTYPES[dtype]))
+        self.d = int(Va.shape[1])
+
+    def device_bytes(self) -> int:
+        return int(lib().hd_device_bytes(self._h))
+
+    # ---- query path ----
+    def query_batch(self, q_desc=None, y_ids=None, y_val=None, *, alpha=0.99, max_iter=20,
+                    tol=1e-6, rank_r=-1, k_y=10, top_k=100, want_x=False, want_y=False,
+                    stream=None, out=None):
+        """Run the whole query path on B queries. q_desc: torch (B x d fp32,
+        device) or None with y_ids / y_val (B x k_y int32 / fp32, device).
+        Returns a dict of device tensors (rank_ids, rank_scores, x, y_ids,
+        y_val) and host arrays (iters, relres, status)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if q_desc is not None:
+            B = int(q_desc.shape[0])
+        else:
+            B = int(y_ids.shape[0])
+            k_y = int(y_ids.shape[1])
+        o = hd_query_opts(float(alpha), int(max_iter), float(tol), int(rank_r), int(k_y), int(top_k))
+        res = out if out is not None else {}
+        if top_k > 0:
+            res.setdefault("rank_ids", torch.empty((B, top_k), dtype=torch.int32, device=dev))
+            res.setdefault("rank_scores", torch.empty((B, top_k), dtype=torch.float32, device=dev))
+        if want_x:
+            res.setdefault("x", torch.empty((B, self.n), dtype=torch.float32, device=dev))
+        if want_y:
+            res.setdefault("y_ids", torch.empty((B, k_y), dtype=torch.int32, device=dev))
+            res.setdefault("y_val", torch.empty((B, k_y), dtype=torch.float32, device=dev))
+        it = res.setdefault("iters", np.zeros(B, np.int32))
+        rr = res.setdefault("relres", np.zeros(B, np.float64))
+        st = res.setdefault("status", np.zeros(B, np.int32))
+        code = lib().hd_query_batch(
+            self._h, B, _dptr(q_desc), _dptr(y_ids), _dptr(y_val), ctypes.byref(o),
+            _dptr(res.get("rank_ids")), _dptr(res.get("rank_scores")), _dptr(res.get("x")),
+            _dptr(res.get("y_ids")), _dptr(res.get("y_val")),
+            it.ctypes.data_as(_P), rr.ctypes.data_as(_P), st.ctypes.data_as(_P),
+            _stream_ptr(stream))
+        _check(code)
+        return res
+
+    def rank(self, x, K, stream=None, ids=None, scores=None):
+        """Top-K of each row of x (torch, B x n fp32, device)."""
+        import torch
+        B, n = int(x.shape[0]), int(x.shape[1])
+        ldx = int(x.stride(0))
+        if ids is None:
+            ids = torch.empty((B, K), dtype=torch.int32, device=x.device)
+        if scores is None:
+            scores = torch.empty((B, K), dtype=torch.float32, device=x.device)
+        _check(lib().hd_rank(self._h, B, n, _dptr(x), ldx, int(K), _dptr(ids), _dptr(scores),
+                             _stream_ptr(stream)))
+        return ids, scores

@@ -1,0 +1,49 @@
+"""Host-only checks of the C ABI: the built library loads and exports every
+entry point that include/hd.h declares, and calls that need no device fail
+cleanly with a status code (no GPU is touched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1807_08692_amd import hd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hd.lib()
+    names = declared_symbols()
+    assert "hd_query_batch" in names and "hd_load_graph" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(hd._SIGS), "binding and header disagree"
+
+
+def test_null_context_errors_without_device():
+    L = hd.lib()
+    assert L.hd_load_graph(None, 1, 0, None, None, None, 0) == hd.HD_EINVAL
+    assert b"NULL context" in L.hd_last_error()
+    assert L.hd_load_eigs(None, 0, None, None, 0) == hd.HD_EINVAL
+    assert L.hd_load_descriptors(None, 4, None, 0) == hd.HD_EINVAL
+    opts = hd.hd_query_opts(0.99, 10, 1e-6, 0, 5, 10)
+    assert L.hd_query_batch(None, 1, None, None, None, ctypes.byref(opts), None, None, None,
+                            None, None, None, None, None, None) == hd.HD_EINVAL
+    assert L.hd_rank(None, 1, 10, None, 10, 5, None, None, None) == hd.HD_EINVAL
+    assert L.hd_device_bytes(None) == 0
+    L.hd_destroy(None)
+    out = ctypes.c_void_p()
+    assert L.hd_create(-1, ctypes.byref(out)) != hd.HD_OK
+    assert L.hd_create(0, None) == hd.HD_EINVAL
+
+
+def test_binding_raises_on_error():
+    with pytest.raises(hd.HDError):
+        hd._check(hd.lib().hd_load_graph(None, 1, 0, None, None, None, 0))

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Workload: 5,000 items, d = 128, 50 vMF clusters (kappa 40), reciprocal
+k-NN with k = 10, alpha = 0.99, r in {0, 50}, k_y = 10 (the small
+configuration). Sizes span several tiles of every kernel and leave ragged
+tails (n = 5000 is not a multiple of 64, r = 50 not a multiple of 32).
+
+Bars:
+  * x against oracle.iterate run for the same per-column iteration count:
+    relative L2 error <= 1e-4 (fp32 vectors, double CG scalars);
+  * ranking and neighbour ids: exact where unique (the GPU's ranking equals
+    the oracle's sort of the GPU's own x, bit for bit); the y set is
+    checked against FP64 similarities with a near-tie margin.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1807_08692_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def fx():
+    return W.build_fixture(W.CONFIGS["n5k"], n_queries=16, prefer_gpu=False)
+
+
+@pytest.fixture(scope="module")
+def g64(fx):
+    return O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
+
+
+@pytest.fixture(scope="module")
+def ctx(fx, torch_dev):
+    from paper_1807_08692_amd import hd
+    c = hd.Context(0)
+    c.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    c.load_eigs(fx.U, fx.lam)
+    c.load_descriptors(fx.V)
+    yield c
+    c.close()
+
+
+def oracle_y(fx, qs):
+    ids, vals = [], []
+    for q in qs:
+        i, v = O.observation(fx.V, q, fx.cfg.k_y)
+        ids.append(i)
+        vals.append(v)
+    return np.stack(ids).astype(np.int32), np.stack(vals)
+
+
+def run_sparse(ctx, torch_dev, ids, vals, **kw):
+    import torch
+    yi = torch.from_numpy(np.ascontiguousarray(ids, np.int32)).to(torch_dev)
+    yv = torch.from_numpy(np.ascontiguousarray(vals, np.float32)).to(torch_dev)
+    out = ctx.query_batch(None, yi, yv, want_x=True, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.mark.parametrize("r", [0, 50])
+@pytest.mark.parametrize("B", [1, 3])
+def test_sparse_y_parity(fx, g64, ctx, torch_dev, r, B):
+    ids, vals = oracle_y(fx, fx.Q[:B])
+    out = run_sparse(ctx, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=20,
+                     tol=1e-6, rank_r=r, k_y=fx.cfg.k_y, top_k=100)
+    x = out["x"].cpu().numpy()
+    U = fx.U[:, :r] if r else None
+    for b in range(B):
+        it = int(out["iters"][b])
+        assert 1 <= it <= 20
+        xo, xs, xt, it_o, rr_o, st_o = O.iterate(g64, U, fx.lam[:r], 0.99, ids[b],
+                                                 vals[b].astype(np.float32), it, 0.0)
+        assert rel(x[b], xo) <= REL_TOL, (b, rel(x[b], xo))
+        # the stopping test agrees with the oracle's residual recurrence
+        assert abs(out["relres"][b] - rr_o) <= 1e-3 * rr_o + 1e-9
+    # ranking: exactly the oracle's sort of the GPU's own x (ties to lower id)
+    rid = out["rank_ids"].cpu().numpy()
+    rsc = out["rank_scores"].cpu().numpy()
+    for b in range(B):
+        oid, osc = O.rank(x[b].astype(np.float64), 100)
+        assert np.array_equal(rid[b], oid)
+        assert np.array_equal(rsc[b], x[b][oid])
+
+
+def test_convergence_status_matches_oracle(fx, g64, ctx, torch_dev):
+    """With the same tolerance the GPU stops each column where the oracle
+    does (or one product away when the residual sits on the threshold)."""
+    ids, vals = oracle_y(fx, fx.Q[:4])
+    out = run_sparse(ctx, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=200,
+                     tol=1e-6, rank_r=0, k_y=fx.cfg.k_y, top_k=0)
+    for b in range(4):
+        _, _, _, it_o, rr_o, st_o = O.iterate(g64, None, None, 0.99, ids[b], vals[b].astype(np.float32),
+                                              200, 1e-6)
+        assert st_o == O.CONVERGED and out["status"][b] == O.CONVERGED
+        assert abs(int(out["iters"][b]) - it_o) <= 1
+
+
+def test_descriptor_path_builds_valid_y(fx, ctx, torch_dev):
+    """Step 1 on the GPU: the k_y selected items are the k_y largest FP64
+    cosines up to a near-tie margin, their values are max(0, cos)^3."""
+    import torch
+    q = torch.from_numpy(fx.Q[:8]).to(torch_dev)
+    out = ctx.query_batch(q, alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y,
+                          top_k=50, want_x=True, want_y=True)
+    torch.cuda.synchronize()
+    gi = out["y_ids"].cpu().numpy()
+    gv = out["y_val"].cpu().numpy()
+    eps = 1e-5
+    for b in range(8):
+        s = O.similarities(fx.V, fx.Q[b])
+        kth = np.sort(s)[::-1][fx.cfg.k_y - 1]
+        assert len(set(gi[b].tolist())) == fx.cfg.k_y
+        assert np.all(s[gi[b]] >= kth - eps)
+        must = np.nonzero(s > kth + eps)[0]
+        assert set(must.tolist()) <= set(gi[b].tolist())
+        assert np.allclose(gv[b], np.maximum(s[gi[b]], 0) ** 3, rtol=1e-4, atol=1e-7)
+        # best first, ties to lower id, in the GPU's own similarity order
+        assert np.all(np.diff(gv[b]) <= 0)
+
+
+def test_descriptor_path_end_to_end(fx, g64, ctx, torch_dev):
+    """The whole path from query descriptors: x against the oracle run on the
+    y the GPU selected (ties in y are judged by the previous test)."""
+    import torch
+    q = torch.from_numpy(fx.Q[:4]).to(torch_dev)
+    out = ctx.query_batch(q, alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y,
+                          top_k=100, want_x=True, want_y=True)
+    torch.cuda.synchronize()
+    x = out["x"].cpu().numpy()
+    yi, yv = out["y_ids"].cpu().numpy(), out["y_val"].cpu().numpy()
+    for b in range(4):
+        xo, *_ = O.iterate(g64, fx.U, fx.lam, 0.99, yi[b], yv[b], int(out["iters"][b]), 0.0)
+        assert rel(x[b], xo) <= REL_TOL
+
+
+def test_r0_is_plain_temporal_bitwise(fx, ctx, torch_dev):
+    """r = 0 runs exactly the plain-CG kernel sequence: the same bits as a
+    context that never loaded eigenpairs (temporal filtering)."""
+    from paper_1807_08692_amd import hd
+    ids, vals = oracle_y(fx, fx.Q[:2])
+    a = run_sparse(ctx, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=15, tol=0.0,
+                   rank_r=0, k_y=fx.cfg.k_y, top_k=10)
+    with hd.Context(0) as c2:
+        c2.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+        b = run_sparse(c2, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=15,
+                       tol=0.0, rank_r=0, k_y=fx.cfg.k_y, top_k=10)
+    assert np.array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
+
+
+def test_column_alone_equals_in_mix(fx, ctx, torch_dev):
+    """Columns are independent recurrences with a fixed reduction order: a
+    query alone gives the same bits as inside a batch of the same width."""
+    ids, vals = oracle_y(fx, fx.Q[:7])
+    mix = run_sparse(ctx, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=20,
+                     tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=10)
+    for b in (0, 4, 6):
+        one = run_sparse(ctx, torch_dev, ids[b:b + 1], vals[b:b + 1].astype(np.float32), alpha=0.99,
+                         max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=10)
+        assert np.array_equal(one["x"].cpu().numpy()[0], mix["x"].cpu().numpy()[b])
+        assert one["iters"][0] == mix["iters"][b]
+
+
+@pytest.mark.parametrize("B", [65, 200])
+def test_wide_batches(fx, g64, ctx, torch_dev, B):
+    """Batch widths that need 128 and 256 padded columns (other kernel
+    variants); sampled columns against the oracle."""
+    rng = np.random.default_rng(B)
+    qi = rng.integers(0, fx.Q.shape[0], size=B)
+    ids, vals = oracle_y(fx, fx.Q[qi])
+    out = run_sparse(ctx, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=20,
+                     tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=10)
+    x = out["x"].cpu().numpy()
+    for b in (0, 63, 64, B - 1):
+        xo, *_ = O.iterate(g64, fx.U, fx.lam, 0.99, ids[b], vals[b].astype(np.float32),
+                           int(out["iters"][b]), 0.0)
+        assert rel(x[b], xo) <= REL_TOL
+
+
+def test_degenerate_columns(fx, g64, ctx, torch_dev):
+    """y = 0 gives ZERO_RHS and x = 0; a non-finite y gives BREAKDOWN; the
+    other columns of the batch are unaffected."""
+    ids, vals = oracle_y(fx, fx.Q[:3])
+    vals = vals.astype(np.float32)
+    vals[1] = 0.0
+    vals[2, 0] = np.nan
+    out = run_sparse(ctx, torch_dev, ids, vals, alpha=0.99, max_iter=20, tol=1e-6, rank_r=50,
+                     k_y=fx.cfg.k_y, top_k=5)
+    assert out["status"][1] == O.ZERO_RHS and out["iters"][1] == 0
+    assert not np.any(out["x"].cpu().numpy()[1])
+    assert out["status"][2] == O.BREAKDOWN
+    xo, *_ = O.iterate(g64, fx.U, fx.lam, 0.99, ids[0], vals[0], int(out["iters"][0]), 0.0)
+    assert rel(out["x"].cpu().numpy()[0], xo) <= REL_TOL
+
+
+def test_zero_iterations_is_spectral_term(fx, ctx, torch_dev):
+    """max_iter = 0: x = x^s, the spectral term of eq. (h-spectral)."""
+    ids, vals = oracle_y(fx, fx.Q[:2])
+    out = run_sparse(ctx, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=0,
+                     tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=5)
+    x = out["x"].cpu().numpy()
+    for b in range(2):
+        xs = O.spectral(fx.U, fx.lam, 0.99, ids[b], vals[b].astype(np.float32))
+        assert rel(x[b], xs) <= REL_TOL
+        assert out["iters"][b] == 0 and out["status"][b] == O.MAXITER
+
+
+def test_bad_ids_rejected(fx, ctx, torch_dev):
+    from paper_1807_08692_amd import hd
+    ids, vals = oracle_y(fx, fx.Q[:1])
+    ids[0, 3] = fx.n + 5
+    with pytest.raises(hd.HDError):
+        run_sparse(ctx, torch_dev, ids, vals.astype(np.float32), alpha=0.99, max_iter=5, tol=0.0,
+                   rank_r=0, k_y=fx.cfg.k_y, top_k=5)
+
+
+@pytest.mark.parametrize("n,K,B", [(1000, 1000, 2), (2049, 100, 3), (4097, 1024, 1), (100003, 100, 5), (7, 1, 1)])
+def test_rank_entry_exact(ctx, torch_dev, n, K, B):
+    """hd_rank: exact agreement with the oracle's sort, with many ties, ragged
+    lengths and a row stride larger than n."""
+    import torch
+    rng = np.random.default_rng(n + K)
+    x = rng.integers(0, 50, size=(B, n)).astype(np.float32) * 0.25 - 3.0
+    xt = torch.zeros((B, n + 13), dtype=torch.float32, device=torch_dev)
+    xt[:, :n] = torch.from_numpy(x).to(torch_dev)
+    ids, sc = ctx.rank(xt[:, :n], K)
+    torch.cuda.synchronize()
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    for b in range(B):
+        oid, osc = O.rank(x[b].astype(np.float64), K)
+        assert np.array_equal(ids[b], oid)
+        assert np.array_equal(sc[b], osc.astype(np.float32))
