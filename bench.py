@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Throughput of the hybrid diffusion query path on one MI355X.
+
+One step = one batch of B queries through the whole path, from query
+descriptors already resident in HBM to the top-100 ranking: the observation
+vectors y (similarity product + top-k_y), the spectral term, conjugate
+gradient on the deflated system until every column reaches the relative
+residual tolerance, and the ranking of x = x^s + x^t.
+
+Default workload: 100,000 database items, d = 2048, a mixture of 1,000 von
+Mises-Fisher clusters (kappa 60), reciprocal k-NN graph with k = 50 and
+weights max(0, cos)^3, alpha = 0.99, r = 400 eigenvectors (FP32), batches of
+64 queries with k_y = 50, CG to relative residual 1e-5. All inputs are
+seeded and synthetic.
+
+Prints one JSON line (rank 0, N = 1). Per-kernel HIP-event times over the
+timed region give the roofline figures of the dominant kernel; the FP64
+oracle, timed on a bounded sample on the host, gives the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "queries/s at N=1M, hybrid vs plain CG at equal rel-err; p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense fp32 matrix
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="n100k")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="approximate CPU time budget of the oracle baseline sample")
+    p.add_argument("--eig-seconds", type=float, default=120.0)
+    p.add_argument("--fixture-cache", default=None,
+                   help="directory to keep the generated workload between runs")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain device copy of known size (for counter scaling)")
+    return p.parse_args()
+
+
+def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk):
+    """(bytes, flops) one launch of kernel `kind` must move / compute."""
+    v = 4.0 * n * ldb
+    if kind == "spmm":
+        return 8.0 * (n + 1) + 8.0 * nnz + v * (3 if rk > 0 else 2), 2.0 * nnz * ldb
+    if kind == "u_c":
+        return 4.0 * n * rk + 4.0 * rk * ldb + 2 * v, 2.0 * n * rk * ldb
+    if kind == "ut_p":
+        return 4.0 * n * rk + v + 4.0 * nchunk * rk * ldb, 2.0 * n * rk * ldb
+    if kind == "update_r":
+        return 3 * v, 2.0 * n * ldb
+    if kind == "update_xp":
+        return 5 * v, 4.0 * n * ldb
+    if kind == "sim":
+        return 4.0 * n * d + 4.0 * B * d + 4.0 * B * n, 2.0 * B * n * d
+    if kind == "combine":
+        return 4.0 * n * rk + v + 4.0 * B * n, 2.0 * n * rk * B
+    return None
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "bench.py measures one GPU only: the query path runs on a "
+                                   "single MI355X in this build (multi-GPU sharding is a design "
+                                   "note, not implemented); run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1807_08692_amd import hd
+    from paper_1807_08692_amd import workload as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    cfg = W.CONFIGS[args.workload]
+    B = cfg.batch
+    nbatch = 4
+    t0 = time.time()
+    fx = W.build_fixture(cfg, n_queries=B * nbatch, prefer_gpu=True,
+                         eig_time_budget=args.eig_seconds, log=lambda m: log("[fixture]", m),
+                         cache_dir=args.fixture_cache)
+    log(f"[fixture] done in {time.time() - t0:.1f}s: nnz={fx.nnz} eig max residual "
+        f"{fx.info['eig_max_residual']:.2e}")
+    dev = torch.device("cuda:0")
+    ctx = hd.Context(0)
+    ctx.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    ctx.load_eigs(fx.U, fx.lam)
+    ctx.load_descriptors(fx.V)
+    Qd = torch.from_numpy(fx.Q.reshape(nbatch, B, cfg.d)).to(dev)
+    torch.cuda.synchronize()
+    log(f"[setup] library holds {ctx.device_bytes() / 2**20:.0f} MiB on the device")
+
+    K_RANK = 100
+
+    def step(i, r, out=None):
+        return ctx.query_batch(Qd[i % nbatch], alpha=cfg.alpha, max_iter=cfg.max_iter, tol=cfg.tol,
+                               rank_r=r, k_y=cfg.k_y, top_k=K_RANK, out=out)
+
+    def timed(r, steps, with_events):
+        outs = []
+        lat = []
+        if with_events:
+            ctx.timing_enable(True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(steps):
+            ts = time.perf_counter()
+            o = step(k, r)
+            lat.append(time.perf_counter() - ts)
+            outs.append((o["iters"].copy(), o["status"].copy()))
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+        tm = ctx.timing() if with_events else None
+        if with_events:
+            ctx.timing_enable(False)
+        return total, lat, outs, tm
+
+    for w in range(args.warmup):
+        step(w, -1)
+        step(w, 0)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+
+    total_h, lat_h, outs_h, tm = timed(-1, args.steps, True)
+    log(f"[bench] hybrid r={cfg.r}: {args.steps} batches in {total_h:.3f}s")
+    total_p, lat_p, outs_p, _ = timed(0, args.steps, False)
+    log(f"[bench] plain CG: {args.steps} batches in {total_p:.3f}s")
+
+    q_h = B * args.steps / total_h
+    q_p = B * args.steps / total_p
+    it_h = np.concatenate([o[0] for o in outs_h])
+    it_p = np.concatenate([o[0] for o in outs_p])
+    st_h = np.concatenate([o[1] for o in outs_h])
+
+    # roofline of the dominant kernel (largest share of the event time)
+    ldb = 64
+    while ldb < B:
+        ldb *= 2
+    rk = (cfg.r + 31) // 32 * 32
+    nchunk = -(-fx.n // max(256, ((-(-fx.n // 256)) + 63) // 64 * 64))
+    kernels = {}
+    for kind, (ms, cnt) in tm.items():
+        if cnt == 0:
+            continue
+        cost = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk)
+        kernels[kind] = {"ms_total": round(ms, 4), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 3)}
+        if cost:
+            by, fl = cost
+            kernels[kind]["GB_s"] = round(by / (ms / cnt * 1e-3) / 1e9, 1)
+            kernels[kind]["TFLOP_s"] = round(fl / (ms / cnt * 1e-3) / 1e12, 2)
+    dom = max((k for k in kernels if algorithmic_cost(k, 1, 1, 64, 32, 1, 1, 1)),
+              key=lambda k: kernels[k]["ms_total"])
+    by, fl = algorithmic_cost(dom, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk)
+    avg_s = kernels[dom]["ms_total"] / kernels[dom]["launches"] * 1e-3
+    ai = fl / by
+    if dom in ("u_c", "ut_p", "sim", "combine") and ai > FP32_MFMA_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS:
+        roof = {"bound": "mfma", "achieved": round(fl / avg_s / 1e12, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(by / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_us"] = round(avg_s * 1e6, 2)
+    roof["algorithmic_bytes_per_launch"] = by
+    roof["flops_per_launch"] = fl
+
+    result = {
+        "metric": METRIC,
+        "value": round(q_h, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total_h / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"vMF mixture N={cfg.n} d={cfg.d} clusters={cfg.clusters} kappa={cfg.kappa:g}, "
+                        f"reciprocal kNN k={cfg.k} (nnz={fx.nnz}), alpha={cfg.alpha}, hybrid r={cfg.r} "
+                        f"FP32, batch {B} queries, k_y={cfg.k_y}, CG rel-res {cfg.tol:g}, top-{K_RANK}",
+            "global_batch": B,
+            "parallelism": "single GPU",
+        },
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat_h, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(lat_h, 99)), 3),
+                       "note": "per query = its batch's wall time (closed loop)"},
+        "hybrid": {"r": cfg.r, "queries_per_s": round(q_h, 2), "iters_mean": float(it_h.mean()),
+                   "iters_max": int(it_h.max()), "converged_frac": float(np.mean(st_h == 0))},
+        "plain_cg": {"r": 0, "queries_per_s": round(q_p, 2), "iters_mean": float(it_p.mean()),
+                     "iters_max": int(it_p.max()),
+                     "p50_ms": round(1e3 * float(np.percentile(lat_p, 50)), 3),
+                     "p99_ms": round(1e3 * float(np.percentile(lat_p, 99)), 3)},
+        "roofline": roof,
+        "kernels": kernels,
+        "fixture": {"eig_max_residual": fx.info["eig_max_residual"], "mean_degree": fx.info["mean_degree"],
+                    "isolated": fx.info["isolated"], "lambda_1": float(fx.lam[0]) if fx.lam.size else None,
+                    "lambda_r": float(fx.lam[-1]) if fx.lam.size else None},
+    }
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = nbytes
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args, cfg, fx, ctx, Qd, B, torch, np)
+
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(args, cfg, fx, ctx, Qd, B, torch, np):
+    """The FP64 oracle on a bounded sample of the same workload (whole query
+    path per query, single thread), plus the accuracy of the GPU results on
+    that sample: against the oracle at the same iteration count, and against
+    the exact solution (tight FP64 CG on the unmodified system)."""
+    from oracle import oracle as O
+    g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
+    U64 = fx.U.astype(np.float64)
+    # GPU results for the first batch, hybrid and plain
+    oh = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=cfg.max_iter, tol=cfg.tol, rank_r=-1,
+                         k_y=cfg.k_y, top_k=100, want_x=True, want_y=True)
+    op = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=cfg.max_iter, tol=cfg.tol, rank_r=0,
+                         k_y=cfg.k_y, top_k=100, want_x=True)
+    torch.cuda.synchronize()
+    xh, xp = oh["x"].cpu().numpy(), op["x"].cpu().numpy()
+    yi = oh["y_ids"].cpu().numpy()
+    Qh = Qd[0].cpu().numpy()
+    t_cpu = 0.0
+    done = 0
+    errs, yset_eq = [], []
+    t_begin = time.time()
+    while done < B and (t_cpu < args.cpu_seconds or done == 0):
+        b = done
+        ts = time.process_time()
+        res = O.query(g, U64, fx.lam, cfg.alpha, fx.V, Qh[b], cfg.k_y, int(oh["iters"][b]), 0.0, 100)
+        t_cpu += time.process_time() - ts
+        same = set(res["y_ids"].tolist()) == set(yi[b].tolist())
+        yset_eq.append(same)
+        if same:
+            errs.append(float(np.linalg.norm(xh[b] - res["x"]) / np.linalg.norm(res["x"])))
+        done += 1
+        log(f"[cpu] oracle query {b}: {time.time() - t_begin:.1f}s")
+    # exact solution for the first sampled query (not part of the timing)
+    y_o = O.observation(fx.V, Qh[0], cfg.k_y)
+    truth, it_t, rr_t, st_t = O.cg(g, None, None, cfg.alpha, O.dense_y(fx.n, *y_o), 2000, 1e-10)
+    truth *= 1.0
+    nt = np.linalg.norm(truth)
+    return {
+        "value": round(done / t_cpu, 4),
+        "unit": "queries/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{done} queries of the first batch, whole path (y by brute force over all {fx.n} "
+                  f"items, spectral term, CG at the GPU's per-query iteration count, full sort), "
+                  f"single-threaded FP64, {t_cpu:.1f}s CPU",
+        "gpu_vs_oracle_max_rel_err": max(errs) if errs else None,
+        "y_sets_identical": int(sum(yset_eq)),
+        "rel_err_vs_exact": {"hybrid": float(np.linalg.norm(xh[0] - truth) / nt),
+                             "plain_cg": float(np.linalg.norm(xp[0] - truth) / nt),
+                             "exact_solve_iters": int(it_t)},
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -175,6 +175,21 @@ int hd_rank(hd_ctx *ctx, int32_t B, int64_t n, const float *x, int64_t ldx,
  * descriptors, solver workspace). Returns 0 for NULL. */
 int64_t hd_device_bytes(const hd_ctx *ctx);
 
+/*
+ * Per-kernel timing (a profiling aid). While enabled, every kernel launch of
+ * the context is bracketed by a pair of HIP events recorded on the launch
+ * stream, and the elapsed times are accumulated per kernel kind at the
+ * synchronisation points of hd_query_batch. hd_timing_enable(ctx, 1) turns
+ * it on and clears the counters; 0 turns it off. hd_timing_get returns the
+ * total milliseconds and the launch count of kernel kind `kind` (0 <=
+ * kind < hd_timing_kinds()); hd_timing_name gives its name (NULL if out of
+ * range). hd_rank launches are not timed. Errors: HD_EINVAL.
+ */
+int hd_timing_enable(hd_ctx *ctx, int enable);
+int hd_timing_kinds(void);
+const char *hd_timing_name(int kind);
+int hd_timing_get(const hd_ctx *ctx, int kind, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,67 @@ int pow2_at_least(int v) {
     return p;
 }
 
+// Kernel kinds for the optional per-launch event timing.
+enum Kind {
+    K_SIM, K_TOPK_Y, K_FILL, K_SCATTER, K_COLSQ, K_SCALAR, K_GATHER, K_UT_P, K_REDUCE_C,
+    K_U_C, K_SPMM, K_UPDATE_R, K_UPDATE_XP, K_COMBINE, K_TOPK_RANK, K_NKINDS
+};
+const char *const kKindNames[K_NKINDS] = {
+    "sim", "topk_y", "fill_zero", "scatter_y", "colsq", "cg_scalar", "gather_proj", "ut_p",
+    "reduce_c", "u_c", "spmm", "update_r", "update_xp", "combine", "topk_rank"};
+
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> pending;  // (kind, index of start event)
+    double total_ms[K_NKINDS] = {};
+    int64_t count[K_NKINDS] = {};
+
+    void reset() {
+        for (int k = 0; k < K_NKINDS; ++k) {
+            total_ms[k] = 0.0;
+            count[k] = 0;
+        }
+        pending.clear();
+        used = 0;
+    }
+    hipError_t begin(hipStream_t s, size_t *idx) {
+        if (used + 2 > pool.size()) {
+            for (int t = 0; t < 64; ++t) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                pool.push_back(e);
+            }
+        }
+        *idx = used;
+        used += 2;
+        return hipEventRecord(pool[*idx], s);
+    }
+    hipError_t end(int kind, size_t idx, hipStream_t s) {
+        pending.emplace_back(kind, idx);
+        return hipEventRecord(pool[idx + 1], s);
+    }
+    // Call after the stream has been synchronised.
+    hipError_t harvest() {
+        for (auto &pk : pending) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, pool[pk.second], pool[pk.second + 1]);
+            if (e != hipSuccess) return e;
+            total_ms[pk.first] += ms;
+            count[pk.first] += 1;
+        }
+        pending.clear();
+        used = 0;
+        return hipSuccess;
+    }
+    void destroy() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
 }  // namespace
 
 struct hd_ctx {
@@ -90,7 +151,18 @@ struct hd_ctx {
     DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, part, scal, xbuf, sim, ybuf, topk, err;
     int32_t *h_pinned = nullptr;  // nact counts + error flag
     hd::CgState st{};
+    Timing timing;
 };
+
+// Launch `call` (a launcher returning hipError_t) as kernel kind `kind`,
+// bracketed by timing events when timing is on.
+#define LAUNCH(kind, call)                                                        \
+    do {                                                                          \
+        size_t ev_ = 0;                                                           \
+        if (c->timing.on) HIP_TRY(c->timing.begin(s, &ev_));                      \
+        HIP_TRY(call);                                                            \
+        if (c->timing.on) HIP_TRY(c->timing.end(kind, ev_, s));                   \
+    } while (0)
 
 static int64_t ctx_bytes(const hd_ctx *c) {
     const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->lam, &c->V, &c->X, &c->R,
@@ -137,10 +209,34 @@ void hd_destroy(hd_ctx *c) {
                      &c->sim, &c->ybuf, &c->topk, &c->err};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    c->timing.destroy();
     delete c;
 }
 
 int64_t hd_device_bytes(const hd_ctx *c) { return c ? ctx_bytes(c) : 0; }
+
+int hd_timing_enable(hd_ctx *c, int enable) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_timing_enable: NULL context");
+    c->timing.reset();
+    c->timing.on = enable != 0;
+    return HD_OK;
+}
+
+int hd_timing_kinds(void) { return K_NKINDS; }
+
+const char *hd_timing_name(int kind) {
+    return kind >= 0 && kind < K_NKINDS ? kKindNames[kind] : nullptr;
+}
+
+int hd_timing_get(const hd_ctx *c, int kind, double *total_ms, int64_t *launches) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_timing_get: NULL context");
+    if (kind < 0 || kind >= K_NKINDS) return fail(HD_EINVAL, "hd_timing_get: kind %d out of range", kind);
+    if (total_ms) *total_ms = c->timing.total_ms[kind];
+    if (launches) *launches = c->timing.count[kind];
+    return HD_OK;
+}
 
 int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
                   const float *val, uint32_t flags) {
@@ -374,8 +470,8 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
             oi = c->ybuf.as<int32_t>();
             ov = reinterpret_cast<float *>(oi + (size_t)B * ky);
         }
-        HIP_TRY(hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
-        HIP_TRY(hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
+        LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
+        LAUNCH(K_TOPK_Y, hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
         yi = oi;
         yv = ov;
     } else {
@@ -386,21 +482,22 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     // ---- CG set-up: X = 0, R = P = y, rho0 = y^T y ----
     float *X = c->X.as<float>(), *R = c->R.as<float>(), *P = c->P.as<float>(), *Q = c->Q.as<float>();
     const size_t nv = (size_t)n * ldb;
-    HIP_TRY(hd::launch_fill_zero(X, nv, s));
-    HIP_TRY(hd::launch_fill_zero(R, nv, s));
-    HIP_TRY(hd::launch_fill_zero(P, nv, s));
-    HIP_TRY(hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 1, s));
-    HIP_TRY(hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s));
-    HIP_TRY(hd::launch_colsq_part(n, ldb, R, rp, c->part.as<double>(), s));
-    HIP_TRY(hd::launch_cg_init(B, ldb, c->part.as<double>(), rp.nblk, st, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(X, nv, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(R, nv, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(P, nv, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 1, s));
+    LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s));
+    LAUNCH(K_COLSQ, hd::launch_colsq_part(n, ldb, R, rp, c->part.as<double>(), s));
+    LAUNCH(K_SCALAR, hd::launch_cg_init(B, ldb, c->part.as<double>(), rp.nblk, st, s));
     HIP_TRY(hipMemcpyAsync(c->h_pinned + 32, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (c->timing.on) HIP_TRY(c->timing.harvest());
     if (c->h_pinned[32] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
 
     // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
     const float *U = c->U.as<float>();
     if (rk > 0)
-        HIP_TRY(hd::launch_gather_proj(B, ky, yi, yv, n, U, c->rp, rk, r_use, c->lam.as<double>(), o->alpha, ldb,
+        LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, U, c->rp, rk, r_use, c->lam.as<double>(), o->alpha, ldb,
                                        c->Cs.as<float>(), c->Cl.as<float>(), s));
 
     // ---- step 3: CG on the deflated system ----
@@ -409,26 +506,27 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         const float *Zs = P;
         if (rk > 0) {
             if (it > 1) {
-                HIP_TRY(hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), s));
-                HIP_TRY(hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), r_use,
+                LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), s));
+                LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), r_use,
                                             c->Cl.as<float>(), s));
             }
-            HIP_TRY(hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), s));
+            LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), s));
             Zs = c->Z.as<float>();
         }
-        HIP_TRY(hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
+        LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
                                 ldb, o->alpha, rp, c->part.as<double>(), s));
-        HIP_TRY(hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, s));
-        HIP_TRY(hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), s));
-        HIP_TRY(hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, s));
-        HIP_TRY(hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, s));
+        LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, s));
+        LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), s));
+        LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, s));
+        LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, s));
         HIP_TRY(hipMemcpyAsync(c->h_pinned, st.nact_part, ntile * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (c->timing.on) HIP_TRY(c->timing.harvest());
         int nact = 0;
         for (int t = 0; t < ntile; ++t) nact += c->h_pinned[t];
         if (nact == 0) break;
     }
-    HIP_TRY(hd::launch_cg_final(ldb, st, s));
+    LAUNCH(K_SCALAR, hd::launch_cg_final(ldb, st, s));
 
     // ---- step 4: x = x^s + x^t (query-major), ranking ----
     float *xq = x_out;
@@ -437,15 +535,16 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         xq = c->xbuf.as<float>();
     }
     if (x_out || o->top_k > 0)
-        HIP_TRY(hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, X, xq, n, s));
+        LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, X, xq, n, s));
     if (o->top_k > 0 && (rank_ids || rank_scores)) {
         HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, o->top_k)));
-        HIP_TRY(hd::launch_topk(B, n, xq, n, o->top_k, c->topk.p, rank_ids, rank_scores, 0, s));
+        LAUNCH(K_TOPK_RANK, hd::launch_topk(B, n, xq, n, o->top_k, c->topk.p, rank_ids, rank_scores, 0, s));
     }
     if (iters) HIP_TRY(hipMemcpyAsync(iters, st.iters, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (status) HIP_TRY(hipMemcpyAsync(status, st.status, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (relres) HIP_TRY(hipMemcpyAsync(relres, st.relres, B * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (c->timing.on) HIP_TRY(c->timing.harvest());
     return HD_OK;
 }
 

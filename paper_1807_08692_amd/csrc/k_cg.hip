@@ -129,22 +129,34 @@ hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, dou
     return hipGetLastError();
 }
 
-// Fixed-order reduction of nblk partials for the 64 columns of this block's
-// tile: wave w sums a contiguous quarter, the quarters are then added in
-// order. Returns the total for column (tile*64 + lane) on wave 0.
+// Fixed-order reduction of nblk per-block partials for the 64 columns of this
+// block's tile. The scalar kernels run 1024 threads (16 waves) per tile:
+// wave w sums partial rows w, w+16, w+32, ... with four independent
+// accumulators (so many loads are in flight), then the 16 wave sums are added
+// in order. The order depends on nblk only, never on timing.
+constexpr int kScalarThreads = 1024;
+constexpr int kScalarWaves = kScalarThreads / kWave;
+
 __device__ __forceinline__ double tile_reduce(const double *part, int nblk, int ldb, int col) {
-    __shared__ double sh[4][kWave];
-    int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    int q = (nblk + 3) / 4;
-    int g0 = w * q, g1 = g0 + q < nblk ? g0 + q : nblk;
-    double acc = 0;
-    for (int g = g0; g < g1; ++g) acc += part[(size_t)g * ldb + col];
-    sh[w][lane] = acc;
+    __shared__ double sh[kScalarWaves][kWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int g = w;
+    for (; g + 3 * kScalarWaves < nblk; g += 4 * kScalarWaves) {
+        a0 += part[(size_t)g * ldb + col];
+        a1 += part[(size_t)(g + kScalarWaves) * ldb + col];
+        a2 += part[(size_t)(g + 2 * kScalarWaves) * ldb + col];
+        a3 += part[(size_t)(g + 3 * kScalarWaves) * ldb + col];
+    }
+    for (; g < nblk; g += kScalarWaves) a0 += part[(size_t)g * ldb + col];
+    sh[w][lane] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    return ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+    double t = 0.0;
+    for (int v = 0; v < kScalarWaves; ++v) t += sh[v][lane];
+    return t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_init(int B, int ldb, const double *part, int nblk,
+__global__ __launch_bounds__(kScalarThreads) void k_cg_init(int B, int ldb, const double *part, int nblk,
                                                     CgState st) {
     int lane = threadIdx.x % kWave;
     int c = blockIdx.x * kWave + lane;
@@ -180,13 +192,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int B, int ldb, const double
 }
 
 hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s) {
-    k_cg_init<<<ldb / kWave, kBlock, 0, s>>>(B, ldb, part, nblk, st);
+    k_cg_init<<<ldb / kWave, kScalarThreads, 0, s>>>(B, ldb, part, nblk, st);
     return hipGetLastError();
 }
 
 // gamma = P^T Q per column; a = rho / gamma, or stop the column (breakdown)
 // when gamma is not positive and finite.
-__global__ __launch_bounds__(kBlock) void k_cg_step_a(int ldb, const double *gpart, int nblk,
+__global__ __launch_bounds__(kScalarThreads) void k_cg_step_a(int ldb, const double *gpart, int nblk,
                                                       CgState st) {
     int lane = threadIdx.x % kWave;
     int c = blockIdx.x * kWave + lane;
@@ -206,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_a(int ldb, const double *gpa
 }
 
 hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, hipStream_t s) {
-    k_cg_step_a<<<ldb / kWave, kBlock, 0, s>>>(ldb, gpart, nblk, st);
+    k_cg_step_a<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, gpart, nblk, st);
     return hipGetLastError();
 }
 
@@ -247,7 +259,7 @@ hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart
 
 // rho' = R^T R per column; stopping test sqrt(rho'/rho0) <= tol after the
 // update; beta = rho'/rho for the columns that go on.
-__global__ __launch_bounds__(kBlock) void k_cg_step_b(int ldb, const double *part, int nblk,
+__global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const double *part, int nblk,
                                                       double tol, CgState st) {
     int lane = threadIdx.x % kWave;
     int c = blockIdx.x * kWave + lane;
@@ -279,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_b(int ldb, const double *par
 
 hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
                             hipStream_t s) {
-    k_cg_step_b<<<ldb / kWave, kBlock, 0, s>>>(ldb, part, nblk, tol, st);
+    k_cg_step_b<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, part, nblk, tol, st);
     return hipGetLastError();
 }
 

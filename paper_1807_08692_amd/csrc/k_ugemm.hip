@@ -104,23 +104,36 @@ hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P
     return hipGetLastError();
 }
 
+// Cl = L1 .* sum over chunks of Cpart. A block reduces 64 consecutive
+// entries of the rk x ldb matrix: its four waves take the chunks c = w mod 4
+// with two accumulators each, then the four wave sums are added in order.
 __global__ __launch_bounds__(kBlock) void k_reduce_c(int nchunk, const float *__restrict__ Cpart,
                                                      int rk, int ldb, const double *lam, int r_use,
                                                      float *__restrict__ Cl) {
-    const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ double sh[4][kWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const size_t tot = (size_t)rk * ldb;
-    if (idx >= tot) return;
-    const int k = (int)(idx / ldb);
-    double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += (double)Cpart[(size_t)c * tot + idx];
-    Cl[idx] = k < r_use ? (float)(lam[k] * s) : 0.f;
+    const size_t idx = (size_t)blockIdx.x * kWave + lane;   // tot is a multiple of 64
+    double s0 = 0.0, s1 = 0.0;
+    int c = w;
+    for (; c + 4 < nchunk; c += 8) {
+        s0 += (double)Cpart[(size_t)c * tot + idx];
+        s1 += (double)Cpart[(size_t)(c + 4) * tot + idx];
+    }
+    for (; c < nchunk; c += 4) s0 += (double)Cpart[(size_t)c * tot + idx];
+    sh[w][lane] = s0 + s1;
+    __syncthreads();
+    if (w == 0) {
+        const double sum = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+        const int k = (int)(idx / ldb);
+        Cl[idx] = k < r_use ? (float)(lam[k] * sum) : 0.f;
+    }
 }
 
 hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
                            int r_use, float *Cl, hipStream_t s) {
     size_t tot = (size_t)rk * ldb;
-    k_reduce_c<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb,
-                                                                          lam, r_use, Cl);
+    k_reduce_c<<<(unsigned)(tot / kWave), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb, lam, r_use, Cl);
     return hipGetLastError();
 }
 

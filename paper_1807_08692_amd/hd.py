@@ -36,6 +36,10 @@ _SIGS = {
     "hd_rank": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
                                ctypes.c_int32, _P, _P, _P]),
     "hd_device_bytes": (ctypes.c_int64, [_P]),
+    "hd_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "hd_timing_kinds": (ctypes.c_int, []),
+    "hd_timing_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "hd_timing_get": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
 }
 
 
@@ -147,6 +151,20 @@ class Context:
 
     def device_bytes(self) -> int:
         return int(lib().hd_device_bytes(self._h))
+
+    def timing_enable(self, on: bool = True):
+        _check(lib().hd_timing_enable(self._h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        """{kernel kind: (total_ms, launches)} accumulated since timing_enable."""
+        L = lib()
+        out = {}
+        for k in range(L.hd_timing_kinds()):
+            ms = ctypes.c_double()
+            cnt = ctypes.c_int64()
+            _check(L.hd_timing_get(self._h, k, ctypes.byref(ms), ctypes.byref(cnt)))
+            out[L.hd_timing_name(k).decode()] = (ms.value, cnt.value)
+        return out
 
     # ---- query path ----
     def query_batch(self, q_desc=None, y_ids=None, y_val=None, *, alpha=0.99, max_iter=20,

@@ -311,15 +311,58 @@ class Fixture:
         return int(self.col.size)
 
 
+_FIELDS = ("V", "Q", "rowptr", "col", "w", "s", "U", "lam", "eig_res")
+
+
+def save_fixture(fx: Fixture, path: str) -> None:
+    """Write the arrays of a fixture to a directory (one .npy per array)."""
+    import json
+    import os
+    os.makedirs(path, exist_ok=True)
+    for f in _FIELDS:
+        np.save(os.path.join(path, f + ".npy"), getattr(fx, f), allow_pickle=False)
+    with open(os.path.join(path, "meta.json"), "w") as fh:
+        json.dump({"cfg": fx.cfg.name, "n_queries": int(fx.Q.shape[0]), "r": int(fx.U.shape[1]),
+                   "info": fx.info}, fh)
+
+
+def load_fixture(cfg: WorkloadConfig, path: str, n_queries: int, r: int) -> Optional[Fixture]:
+    """Read a fixture written by save_fixture if it matches (cfg, n_queries, r)."""
+    import json
+    import os
+    meta_p = os.path.join(path, "meta.json")
+    if not os.path.exists(meta_p):
+        return None
+    meta = json.load(open(meta_p))
+    if meta["cfg"] != cfg.name or meta["n_queries"] != n_queries or meta["r"] != r:
+        return None
+    arrs = {f: np.load(os.path.join(path, f + ".npy"), allow_pickle=False) for f in _FIELDS}
+    return Fixture(cfg, info=meta["info"], **arrs)
+
+
 def build_fixture(cfg: WorkloadConfig, n_queries: Optional[int] = None, r: Optional[int] = None,
                   prefer_gpu: bool = True, eig_time_budget: float = 120.0,
-                  log=None) -> Fixture:
-    """Generate a whole workload for cfg (descriptors, queries, graph, eigenpairs)."""
+                  log=None, cache_dir: Optional[str] = None) -> Fixture:
+    """Generate a whole workload for cfg (descriptors, queries, graph,
+    eigenpairs), or read it from cache_dir when a matching copy is there."""
+    nq = n_queries if n_queries is not None else cfg.batch
+    rr_ = cfg.r if r is None else r
+    if cache_dir:
+        fx = load_fixture(cfg, cache_dir, nq, rr_)
+        if fx is not None:
+            return fx
+    fx = _build_fixture(cfg, nq, rr_, prefer_gpu, eig_time_budget, log)
+    if cache_dir:
+        save_fixture(fx, cache_dir)
+    return fx
+
+
+def _build_fixture(cfg, n_queries, r, prefer_gpu, eig_time_budget, log) -> Fixture:
     t0 = time.time()
     say = log or (lambda *a: None)
     sc, spt, sq, se = cfg.seeds
     V, labels, centres = vmf_mixture(cfg.n, cfg.d, cfg.clusters, cfg.kappa, sc, spt)
-    Q = vmf_queries(n_queries if n_queries is not None else cfg.batch, centres, cfg.kappa, sq)
+    Q = vmf_queries(n_queries, centres, cfg.kappa, sq)
     say(f"descriptors {time.time() - t0:.1f}s")
     nbr, sim = knn_lists(V, cfg.k, prefer_gpu=prefer_gpu)
     rowptr, col, w = mutual_knn_graph(nbr, sim, cfg.n)
@@ -327,7 +370,7 @@ def build_fixture(cfg: WorkloadConfig, n_queries: Optional[int] = None, r: Optio
     s64 = symmetric_normalize(cfg.n, rowptr, col, w)
     s32 = s64.astype(np.float32)
     say(f"graph nnz={col.size} {time.time() - t0:.1f}s")
-    rr = cfg.r if r is None else r
+    rr = r
     if rr == 0:
         U = np.zeros((cfg.n, 0), np.float32)
         lam = np.zeros(0)
