@@ -186,6 +186,10 @@ int64_t hd_device_bytes(const hd_ctx *ctx);
  * range). hd_rank launches are not timed. Errors: HD_EINVAL.
  */
 int hd_timing_enable(hd_ctx *ctx, int enable);
+/* Like hd_timing_enable(ctx, 1), but only the kernel kinds whose bit
+ * (1u << kind) is set in kind_mask are bracketed by events, so the others
+ * run without the extra queue packets. */
+int hd_timing_enable_kinds(hd_ctx *ctx, uint32_t kind_mask);
 int hd_timing_kinds(void);
 const char *hd_timing_name(int kind);
 int hd_timing_get(const hd_ctx *ctx, int kind, double *total_ms, int64_t *launches);

@@ -84,9 +84,16 @@ const char *const kKindNames[K_NKINDS] = {
 
 struct Timing {
     bool on = false;
+    uint32_t mask = ~0u;  // kinds that get events while on
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    std::vector<std::pair<int, size_t>> pending;  // (kind, index of start event)
+    struct Pending {
+        int kind;
+        size_t ev;
+        int iter;  // CG iteration the launch belongs to (0 = none)
+    };
+    std::vector<Pending> pending;
+    int tag = 0;  // iteration of the launches being queued
     double total_ms[K_NKINDS] = {};
     int64_t count[K_NKINDS] = {};
 
@@ -112,17 +119,20 @@ struct Timing {
         return hipEventRecord(pool[*idx], s);
     }
     hipError_t end(int kind, size_t idx, hipStream_t s) {
-        pending.emplace_back(kind, idx);
+        pending.push_back({kind, idx, tag});
         return hipEventRecord(pool[idx + 1], s);
     }
-    // Call after the stream has been synchronised.
-    hipError_t harvest() {
+    // Call after the stream has been synchronised. Launches of iterations
+    // after last_iter were queued ahead and returned at once; they are not
+    // counted.
+    hipError_t harvest(int last_iter) {
         for (auto &pk : pending) {
+            if (pk.iter > last_iter) continue;
             float ms = 0.f;
-            hipError_t e = hipEventElapsedTime(&ms, pool[pk.second], pool[pk.second + 1]);
+            hipError_t e = hipEventElapsedTime(&ms, pool[pk.ev], pool[pk.ev + 1]);
             if (e != hipSuccess) return e;
-            total_ms[pk.first] += ms;
-            count[pk.first] += 1;
+            total_ms[pk.kind] += ms;
+            count[pk.kind] += 1;
         }
         pending.clear();
         used = 0;
@@ -149,7 +159,8 @@ struct hd_ctx {
     DevBuf V;
     // solver workspace
     DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, part, scal, xbuf, sim, ybuf, topk, err;
-    int32_t *h_pinned = nullptr;  // nact counts + error flag
+    int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
+    hipEvent_t iter_ev[2] = {nullptr, nullptr};
     hd::CgState st{};
     Timing timing;
 };
@@ -159,9 +170,10 @@ struct hd_ctx {
 #define LAUNCH(kind, call)                                                        \
     do {                                                                          \
         size_t ev_ = 0;                                                           \
-        if (c->timing.on) HIP_TRY(c->timing.begin(s, &ev_));                      \
+        const bool tm_ = c->timing.on && ((c->timing.mask >> (kind)) & 1u);       \
+        if (tm_) HIP_TRY(c->timing.begin(s, &ev_));                               \
         HIP_TRY(call);                                                            \
-        if (c->timing.on) HIP_TRY(c->timing.end(kind, ev_, s));                   \
+        if (tm_) HIP_TRY(c->timing.end(kind, ev_, s));                            \
     } while (0)
 
 static int64_t ctx_bytes(const hd_ctx *c) {
@@ -190,12 +202,19 @@ int hd_create(int device, hd_ctx **out) {
     if (!c) return fail(HD_ENOMEM, "hd_create: out of host memory");
     c->device = device;
     void *hp = nullptr;
-    hipError_t e = hipHostMalloc(&hp, 64 * sizeof(int32_t), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&hp, 256 * sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
         return fail(HD_ENOMEM, "hd_create: hipHostMalloc: %s", hipGetErrorString(e));
     }
     c->h_pinned = reinterpret_cast<int32_t *>(hp);
+    for (int k = 0; k < 2; ++k) {
+        e = hipEventCreateWithFlags(&c->iter_ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            hd_destroy(c);
+            return fail(HD_EDEVICE, "hd_create: hipEventCreate: %s", hipGetErrorString(e));
+        }
+    }
     *out = c;
     return HD_OK;
 }
@@ -209,6 +228,8 @@ void hd_destroy(hd_ctx *c) {
                      &c->sim, &c->ybuf, &c->topk, &c->err};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    for (hipEvent_t e : c->iter_ev)
+        if (e) (void)hipEventDestroy(e);
     c->timing.destroy();
     delete c;
 }
@@ -220,6 +241,16 @@ int hd_timing_enable(hd_ctx *c, int enable) {
     if (!c) return fail(HD_EINVAL, "hd_timing_enable: NULL context");
     c->timing.reset();
     c->timing.on = enable != 0;
+    c->timing.mask = ~0u;
+    return HD_OK;
+}
+
+int hd_timing_enable_kinds(hd_ctx *c, uint32_t kind_mask) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_timing_enable_kinds: NULL context");
+    c->timing.reset();
+    c->timing.on = kind_mask != 0;
+    c->timing.mask = kind_mask;
     return HD_OK;
 }
 
@@ -439,7 +470,7 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         HIP_TRY(c->Cs.ensure((size_t)rk * ldb * sizeof(float)));
     }
     HIP_TRY(c->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
-    HIP_TRY(c->scal.ensure((size_t)ldb * (5 * sizeof(double) + 3 * sizeof(int32_t)) + 64 * sizeof(int32_t)));
+    HIP_TRY(c->scal.ensure((size_t)ldb * (5 * sizeof(double) + 3 * sizeof(int32_t)) + 128 * sizeof(int32_t)));
     HIP_TRY(c->err.ensure(sizeof(int32_t) * 4));
     {
         char *b = c->scal.as<char>();
@@ -489,10 +520,10 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s));
     LAUNCH(K_COLSQ, hd::launch_colsq_part(n, ldb, R, rp, c->part.as<double>(), s));
     LAUNCH(K_SCALAR, hd::launch_cg_init(B, ldb, c->part.as<double>(), rp.nblk, st, s));
-    HIP_TRY(hipMemcpyAsync(c->h_pinned + 32, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c->h_pinned + 200, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (c->timing.on) HIP_TRY(c->timing.harvest());
-    if (c->h_pinned[32] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
+    if (c->timing.on) HIP_TRY(c->timing.harvest(0));
+    if (c->h_pinned[200] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
 
     // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
     const float *U = c->U.as<float>();
@@ -501,29 +532,52 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
                                        c->Cs.as<float>(), c->Cl.as<float>(), s));
 
     // ---- step 3: CG on the deflated system ----
+    // Iteration it checks the active counts left by iteration it-1 (parity
+    // (it-1)&1) and its stopping test writes parity it&1, which is copied to
+    // pinned memory behind an event. The host queues iteration it+1 before
+    // waiting for iteration it's counts, so the GPU never idles on the host;
+    // an iteration queued after the last one returns at once from every kernel.
     const int ntile = ldb / 64;
-    for (int it = 1; it <= o->max_iter; ++it) {
+    int32_t *nact_dev[2] = {st.nact_part, st.nact_part + 64};
+    auto enqueue_iter = [&](int it) -> int {
+        c->timing.tag = it;
+        const hd::IterGuard g{nact_dev[(it - 1) & 1], ntile};
         const float *Zs = P;
         if (rk > 0) {
             if (it > 1) {
-                LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), s));
-                LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), r_use,
-                                            c->Cl.as<float>(), s));
+                LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), g, s));
+                LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(),
+                                                       r_use, c->Cl.as<float>(), g, s));
             }
-            LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), s));
+            LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), g, s));
             Zs = c->Z.as<float>();
         }
         LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
-                                ldb, o->alpha, rp, c->part.as<double>(), s));
-        LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, s));
-        LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), s));
-        LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, s));
-        LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, s));
-        HIP_TRY(hipMemcpyAsync(c->h_pinned, st.nact_part, ntile * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (c->timing.on) HIP_TRY(c->timing.harvest());
+                                       ldb, o->alpha, rp, c->part.as<double>(), g, s));
+        LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s));
+        LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), g, s));
+        LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, g, nact_dev[it & 1], s));
+        LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s));
+        HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(c->iter_ev[it & 1], s));
+        c->timing.tag = 0;
+        return HD_OK;
+    };
+    int last_iter = 0;
+    if (o->max_iter >= 1) {
+        const int e = enqueue_iter(1);
+        if (e != HD_OK) return e;
+    }
+    for (int it = 1; it <= o->max_iter; ++it) {
+        if (it + 1 <= o->max_iter) {
+            const int e = enqueue_iter(it + 1);
+            if (e != HD_OK) return e;
+        }
+        HIP_TRY(hipEventSynchronize(c->iter_ev[it & 1]));
+        last_iter = it;
         int nact = 0;
-        for (int t = 0; t < ntile; ++t) nact += c->h_pinned[t];
+        for (int t = 0; t < ntile; ++t) nact += c->h_pinned[64 * (it & 1) + t];
         if (nact == 0) break;
     }
     LAUNCH(K_SCALAR, hd::launch_cg_final(ldb, st, s));
@@ -544,7 +598,7 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     if (status) HIP_TRY(hipMemcpyAsync(status, st.status, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (relres) HIP_TRY(hipMemcpyAsync(relres, st.relres, B * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (c->timing.on) HIP_TRY(c->timing.harvest());
+    if (c->timing.on) HIP_TRY(c->timing.harvest(last_iter));
     return HD_OK;
 }
 

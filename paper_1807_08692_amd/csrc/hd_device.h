@@ -12,6 +12,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kBlock = 256;      // threads per block in every kernel (4 waves)
 
+// Solver vectors (N x ldb) are node-major: element (i, b) at i * ldb + b, so
+// the ldb query columns of one item are one contiguous row (a neighbour
+// gather in the SpMM is one coalesced 4*ldb-byte load).
+__host__ __device__ __forceinline__ size_t vec_index(int64_t N, int ldb, int64_t i, int b) {
+    (void)N;
+    return (size_t)i * (size_t)ldb + (size_t)b;
+}
+
 // Broadcast lane `lane` (wave-uniform) of v to the whole wavefront.
 __device__ __forceinline__ int bcast_i(int v, int lane) {
     return __builtin_amdgcn_readlane(v, lane);
@@ -40,6 +48,16 @@ __device__ __forceinline__ uint32_t rank_key_id(uint64_t k) {
 }
 __device__ __forceinline__ float rank_key_score(uint64_t k) {
     return float_from_order_key((uint32_t)(k >> 32));
+}
+
+// Iteration guard of the CG kernels: true when the previous stopping test
+// left no active column (ntile per-tile counts, all zero). Every kernel of an
+// iteration returns at once then, so the host can queue an iteration before
+// it knows whether it is needed.
+__device__ __forceinline__ bool all_stopped(const int32_t *nact, int ntile) {
+    int s = 0;
+    for (int t = 0; t < ntile; ++t) s += nact[t];
+    return s == 0;
 }
 
 // Sum of a double over the 64 lanes of a wavefront (fixed butterfly order).

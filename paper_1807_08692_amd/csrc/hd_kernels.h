@@ -19,7 +19,15 @@ namespace hd {
 struct CgState {
     double *rho0, *rho, *a, *beta, *relres;
     int32_t *active, *iters, *status;
-    int32_t *nact_part;  // one active-column count per 64-column tile
+    int32_t *nact_part;  // [2][64]: active-column count per 64-column tile,
+                         // double buffered by iteration parity
+};
+
+// The guard every per-iteration kernel checks: the counts written by the
+// previous stopping test (nact) for ntile column tiles.
+struct IterGuard {
+    const int32_t *nact;
+    int ntile;
 };
 
 // Row partition shared by every kernel that writes per-block partial sums:
@@ -37,14 +45,16 @@ hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals
 hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
                              hipStream_t s);
 hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s);
-hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, hipStream_t s);
-hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
-                           const double *a, double *part, hipStream_t s);
-hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
+hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, IterGuard g,
                             hipStream_t s);
+hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
+                           const double *a, double *part, IterGuard g, hipStream_t s);
+// writes the new per-tile active counts to nact_out
+hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
+                            IterGuard g, int32_t *nact_out, hipStream_t s);
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
-                            hipStream_t s);
+                            IterGuard g, hipStream_t s);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const float *U, int rp, int rk, int r_use, const double *lam,
@@ -55,20 +65,20 @@ hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *va
 // block g of P[i][c] * Q[i][c] (double).
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
-                       RowPart rp, double *gpart, hipStream_t s);
+                       RowPart rp, double *gpart, IterGuard g, hipStream_t s);
 
 // ---- eigenvector products on MFMA (k_ugemm.hip) ----
 // Number of row chunks of the split-K product U^T P.
 int ut_p_chunks(int64_t N, int64_t *rows_per_chunk);
 // Cpart[c] = U[chunk c]^T P[chunk c]  (rk x ldb per chunk)
 hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P, int ldb,
-                       float *Cpart, hipStream_t s);
+                       float *Cpart, IterGuard g, hipStream_t s);
 // Cl = lambda .* sum_c Cpart[c]   (rows k >= r_use zeroed)
 hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
-                           int r_use, float *Cl, hipStream_t s);
+                           int r_use, float *Cl, IterGuard g, hipStream_t s);
 // Z = P + alpha * U Cl
 hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl, int ldb,
-                      const float *P, double alpha, float *Z, hipStream_t s);
+                      const float *P, double alpha, float *Z, IterGuard g, hipStream_t s);
 // x[b][i] = (U Cs)[i][b] + X[i][b] for b < B, i < N   (x row stride ldx)
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
                           int ldb, const float *X, float *x, int64_t ldx, hipStream_t s);
@@ -79,7 +89,6 @@ hipError_t launch_sim(int64_t N, int B, int d, const float *q, const float *V, i
                       float *sim, int64_t lds, hipStream_t s);
 
 // ---- top-K selection (k_topk.hip) ----
-constexpr int kTopkChunk = 2048;
 constexpr int kTopkMax = 1024;
 // Bytes of scratch for selecting K of n in B rows.
 size_t topk_scratch_bytes(int B, int64_t n, int K);

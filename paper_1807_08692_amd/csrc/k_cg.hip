@@ -63,8 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32
         return;
     }
     float v = vals[idx];
-    atomicAdd(&R[(size_t)id * ldb + b], v);
-    atomicAdd(&P[(size_t)id * ldb + b], v);
+    const size_t o = vec_index(N, ldb, id, b);
+    atomicAdd(&R[o], v);
+    atomicAdd(&P[o], v);
 }
 
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_colsq_part(int64_t N, int ldb, const
     int64_t re = rs + rb < N ? rs + rb : N;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int64_t i = rs + r0; i < re; i += rows) {
-        float4 v = reinterpret_cast<const float4 *>(R + (size_t)i * ldb)[cg];
+        float4 v = *reinterpret_cast<const float4 *>(R + vec_index(N, ldb, i, cg * 4));
         s0 += (double)v.x * v.x;
         s1 += (double)v.y * v.y;
         s2 += (double)v.z * v.z;
@@ -199,7 +200,8 @@ hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState 
 // gamma = P^T Q per column; a = rho / gamma, or stop the column (breakdown)
 // when gamma is not positive and finite.
 __global__ __launch_bounds__(kScalarThreads) void k_cg_step_a(int ldb, const double *gpart, int nblk,
-                                                      CgState st) {
+                                                      CgState st, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
     int lane = threadIdx.x % kWave;
     int c = blockIdx.x * kWave + lane;
     double gamma = tile_reduce(gpart, nblk, ldb, c);
@@ -217,14 +219,17 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_a(int ldb, const dou
     }
 }
 
-hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, hipStream_t s) {
-    k_cg_step_a<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, gpart, nblk, st);
+hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, IterGuard g,
+                            hipStream_t s) {
+    k_cg_step_a<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, gpart, nblk, st, g);
     return hipGetLastError();
 }
 
 // R -= a Q, and per-block partials of the new R^T R.
 __global__ __launch_bounds__(kBlock) void k_update_r(int64_t N, int ldb, const float *Q, float *R,
-                                                     int64_t rb, const double *a, double *part) {
+                                                     int64_t rb, const double *a, double *part,
+                                                     IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
     const int G = ldb / 4;
     const int rows = kBlock / G;
     int cg = threadIdx.x % G;
@@ -234,8 +239,9 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t N, int ldb, const f
     int64_t re = rs + rb < N ? rs + rb : N;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int64_t i = rs + r0; i < re; i += rows) {
-        float4 *rp = reinterpret_cast<float4 *>(R + (size_t)i * ldb) + cg;
-        float4 q = reinterpret_cast<const float4 *>(Q + (size_t)i * ldb)[cg];
+        const size_t o = vec_index(N, ldb, i, cg * 4);
+        float4 *rp = reinterpret_cast<float4 *>(R + o);
+        float4 q = *reinterpret_cast<const float4 *>(Q + o);
         float4 r = *rp;
         // a = 0 leaves a stopped column untouched even if its Q is not finite
         if (a0 != 0.0) r.x = (float)((double)r.x - a0 * (double)q.x);
@@ -252,15 +258,21 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t N, int ldb, const f
 }
 
 hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
-                           const double *a, double *part, hipStream_t s) {
-    k_update_r<<<rp.nblk, kBlock, 0, s>>>(N, ldb, Q, R, rp.rb, a, part);
+                           const double *a, double *part, IterGuard g, hipStream_t s) {
+    k_update_r<<<rp.nblk, kBlock, 0, s>>>(N, ldb, Q, R, rp.rb, a, part, g);
     return hipGetLastError();
 }
 
 // rho' = R^T R per column; stopping test sqrt(rho'/rho0) <= tol after the
 // update; beta = rho'/rho for the columns that go on.
 __global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const double *part, int nblk,
-                                                      double tol, CgState st) {
+                                                      double tol, CgState st, IterGuard ig,
+                                                      int32_t *nact_out) {
+    if (all_stopped(ig.nact, ig.ntile)) {
+        // nothing ran: carry the (zero) counts over to the other parity
+        if (threadIdx.x == 0) nact_out[blockIdx.x] = 0;
+        return;
+    }
     int lane = threadIdx.x % kWave;
     int c = blockIdx.x * kWave + lane;
     double rho_new = tile_reduce(part, nblk, ldb, c);
@@ -285,13 +297,13 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const dou
     if (threadIdx.x == 0) {
         int n = 0;
         for (int l = 0; l < kWave; ++l) n += cnt[l];
-        st.nact_part[blockIdx.x] = n;
+        nact_out[blockIdx.x] = n;
     }
 }
 
 hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
-                            hipStream_t s) {
-    k_cg_step_b<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, part, nblk, tol, st);
+                            IterGuard g, int32_t *nact_out, hipStream_t s) {
+    k_cg_step_b<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, part, nblk, tol, st, g, nact_out);
     return hipGetLastError();
 }
 
@@ -299,7 +311,9 @@ hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, C
 // active after the stopping test.
 __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, float *X, float *P,
                                                       const float *R, const double *a,
-                                                      const double *beta, const int32_t *active) {
+                                                      const double *beta, const int32_t *active,
+                                                      IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
     const int G = ldb / 4;
     const int rows = kBlock / G;
     int cg = threadIdx.x % G;
@@ -309,9 +323,10 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, float 
     int k0 = active[cg * 4 + 0], k1 = active[cg * 4 + 1], k2 = active[cg * 4 + 2], k3 = active[cg * 4 + 3];
     size_t total = (size_t)N;
     for (size_t i = (size_t)blockIdx.x * rows + r0; i < total; i += (size_t)gridDim.x * rows) {
-        float4 *xp = reinterpret_cast<float4 *>(X + i * ldb) + cg;
-        float4 *pp = reinterpret_cast<float4 *>(P + i * ldb) + cg;
-        float4 r = reinterpret_cast<const float4 *>(R + i * ldb)[cg];
+        const size_t o = vec_index(N, ldb, (int64_t)i, cg * 4);
+        float4 *xp = reinterpret_cast<float4 *>(X + o);
+        float4 *pp = reinterpret_cast<float4 *>(P + o);
+        float4 r = *reinterpret_cast<const float4 *>(R + o);
         float4 x = *xp, p = *pp;
         if (a0 != 0.0) x.x = (float)((double)x.x + a0 * (double)p.x);
         if (a1 != 0.0) x.y = (float)((double)x.y + a1 * (double)p.y);
@@ -328,12 +343,12 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, float 
 
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
-                            hipStream_t s) {
+                            IterGuard g, hipStream_t s) {
     int rows = kBlock / (ldb / 4);
     int64_t want = (N + rows - 1) / rows;
     int grid = (int)(want < 16384 ? want : 16384);
     if (grid < 1) grid = 1;
-    k_update_xp<<<grid, kBlock, 0, s>>>(N, ldb, X, P, R, a, beta, active);
+    k_update_xp<<<grid, kBlock, 0, s>>>(N, ldb, X, P, R, a, beta, active, g);
     return hipGetLastError();
 }
 

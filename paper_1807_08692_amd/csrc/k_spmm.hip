@@ -60,7 +60,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__res
                                                  const float *__restrict__ Zs,
                                                  float *__restrict__ Q, int ldb, float alpha,
                                                  float one_minus_alpha, int64_t rb,
-                                                 double *__restrict__ gpart) {
+                                                 double *__restrict__ gpart, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
     const int lane = threadIdx.x % kWave;
     const int w = threadIdx.x / kWave;
     const int c0 = blockIdx.y * (kWave * CPL) + lane * CPL;
@@ -149,17 +150,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__res
 
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
-                       RowPart rp, double *gpart, hipStream_t s) {
+                       RowPart rp, double *gpart, IterGuard g, hipStream_t s) {
     const float a = (float)alpha, oma = (float)(1.0 - alpha);
     if (ldb == 64) {
         k_spmm<1><<<dim3(rp.nblk, 1), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma,
-                                                       rp.rb, gpart);
+                                                       rp.rb, gpart, g);
     } else if (ldb == 128) {
         k_spmm<2><<<dim3(rp.nblk, 1), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma,
-                                                       rp.rb, gpart);
+                                                       rp.rb, gpart, g);
     } else if (ldb >= 256 && ldb % 256 == 0) {
         k_spmm<4><<<dim3(rp.nblk, ldb / 256), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb,
-                                                               a, oma, rp.rb, gpart);
+                                                               a, oma, rp.rb, gpart, g);
     } else {
         return hipErrorInvalidValue;
     }

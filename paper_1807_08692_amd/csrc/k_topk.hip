@@ -3,26 +3,75 @@
 //
 // Each element becomes a 64-bit key (order-preserving score bits, then the
 // complemented id), so one unsigned comparison orders by score and breaks
-// ties toward the lower id, and the result is unique. Rows are cut into
-// chunks of 2048 keys; a block sorts a chunk in LDS with a bitonic network
-// and keeps its best min(K, 2048). The surviving candidates are chunked and
-// sorted again until one chunk per row remains, whose first K keys are the
-// answer. Each round shrinks the candidate set by 2048/K.
+// ties toward the lower id: the selected set and its order are unique.
+//
+// Three kernels per call:
+//   thresh : (one block per row) radix-select on a strided sample of
+//            m <= 4096 elements: the threshold t is the sample's j-th largest, j a few
+//            standard deviations above the number of true top-K elements
+//            expected in the sample (K m / n), so that t lies below the K-th
+//            best with high probability;
+//   filter : one coalesced pass over the rows, 8192 elements per block; each
+//            element with score >= t is appended to its block's own list
+//            (LDS counter, no global atomics);
+//   select : (one block per row) if the lists hold K <= count <= 4096
+//            candidates and none overflowed, they contain the top K (at least
+//            K elements are >= t, so the K-th best is >= t): gather, sort in
+//            LDS, write the first K. Otherwise the block selects exactly on
+//            its own: an MSB-first radix select over the row finds the K-th
+//            key, then a pass in index order collects the keys above it and
+//            the lowest-id ties.
+// Candidate order within a list depends on timing; the result does not.
 #include "hd_device.h"
 #include "hd_kernels.h"
 
 namespace hd {
 
-constexpr int CH = kTopkChunk;
+constexpr int kCap = 4096;        // candidates per row for the final sort
+constexpr int kSample = 4096;     // sampled elements per row
+constexpr int kChunk = 8192;      // row elements per filter block
+constexpr int kChunkCap = 256;    // candidates kept per filter block
+constexpr int kWide = 1024;       // threads of the thresh / select blocks
 
-// Sort CH keys in LDS into descending order (256 threads).
-__device__ __forceinline__ void bitonic_desc(uint64_t *s) {
-    for (int k = 2; k <= CH; k <<= 1) {
+struct TopkScratch {
+    uint64_t *cand;   // [B][nchunk][kChunkCap]
+    int32_t *cnt;     // [B][nchunk]
+    uint32_t *thr;    // [B]
+    int32_t *all;     // [B] 1 = threshold admits every element
+    int nchunk;
+};
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static TopkScratch carve(void *scratch, int B, int64_t n) {
+    TopkScratch t;
+    t.nchunk = (int)ceil_div(n, kChunk);
+    char *p = reinterpret_cast<char *>(scratch);
+    t.cand = reinterpret_cast<uint64_t *>(p);
+    p += (size_t)B * t.nchunk * kChunkCap * sizeof(uint64_t);
+    t.cnt = reinterpret_cast<int32_t *>(p);
+    p += (size_t)B * t.nchunk * sizeof(int32_t);
+    t.thr = reinterpret_cast<uint32_t *>(p);
+    p += (size_t)B * sizeof(uint32_t);
+    t.all = reinterpret_cast<int32_t *>(p);
+    return t;
+}
+
+size_t topk_scratch_bytes(int B, int64_t n, int K) {
+    (void)K;
+    const int64_t nchunk = ceil_div(n, kChunk);
+    return (size_t)B * (nchunk * (kChunkCap * sizeof(uint64_t) + sizeof(int32_t)) +
+                        sizeof(uint32_t) + sizeof(int32_t)) + 256;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void bitonic_desc(T *s, int size) {
+    for (int k = 2; k <= size; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < CH / 2; t += kBlock) {
+            for (int t = threadIdx.x; t < size / 2; t += NT) {
                 const int i = 2 * t - (t & (j - 1));
                 const int p = i + j;
-                const uint64_t a = s[i], c = s[p];
+                const T a = s[i], c = s[p];
                 const bool desc = (i & k) == 0;
                 if (desc ? (a < c) : (a > c)) {
                     s[i] = c;
@@ -34,90 +83,274 @@ __device__ __forceinline__ void bitonic_desc(uint64_t *s) {
     }
 }
 
-// Level 0: scores -> keys. Block (c, b) sorts x[b][c*CH .. c*CH+CH) and
-// writes its best kc keys to out[b][c][0..kc).
-__global__ __launch_bounds__(kBlock) void k_topk_f32(int64_t n, const float *__restrict__ x,
-                                                     int64_t ldx, int kc, int nchunk,
-                                                     uint64_t *__restrict__ out) {
-    __shared__ uint64_t s[CH];
-    const int b = blockIdx.y;
-    const int64_t base = (int64_t)blockIdx.x * CH;
-    for (int t = threadIdx.x; t < CH; t += kBlock) {
-        const int64_t i = base + t;
-        s[t] = i < n ? rank_key(x[(size_t)b * ldx + i], (uint32_t)i) : 0ull;
-    }
-    __syncthreads();
-    bitonic_desc(s);
-    uint64_t *o = out + ((size_t)b * nchunk + blockIdx.x) * kc;
-    for (int t = threadIdx.x; t < kc; t += kBlock) o[t] = s[t];
+__device__ __forceinline__ int pow2_ceil(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
 }
 
-// Level >= 1: keys -> keys (m keys per row).
-__global__ __launch_bounds__(kBlock) void k_topk_u64(int64_t m, const uint64_t *__restrict__ in,
-                                                     int kc, int nchunk,
-                                                     uint64_t *__restrict__ out) {
-    __shared__ uint64_t s[CH];
-    const int b = blockIdx.y;
-    const int64_t base = (int64_t)blockIdx.x * CH;
-    for (int t = threadIdx.x; t < CH; t += kBlock) {
-        const int64_t i = base + t;
-        s[t] = i < m ? in[(size_t)b * m + i] : 0ull;
-    }
-    __syncthreads();
-    bitonic_desc(s);
-    uint64_t *o = out + ((size_t)b * nchunk + blockIdx.x) * kc;
-    for (int t = threadIdx.x; t < kc; t += kBlock) o[t] = s[t];
-}
-
-__global__ void k_topk_decode(int B, int K, const uint64_t *__restrict__ keys,
-                              int32_t *__restrict__ ids, float *__restrict__ scores,
-                              int transform) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= B * K) return;
-    const uint64_t k = keys[idx];
-    if (ids) ids[idx] = (int32_t)rank_key_id(k);
-    if (scores) {
-        float s = rank_key_score(k);
-        if (transform == 1) {
-            const float c = s > 0.f ? s : 0.f;
-            s = c * c * c;
+// MSB-first radix select of the need-th largest key (1-based) among the keys
+// each thread holds in registers (up to 4 per thread). Per 8-bit digit: an LDS
+// histogram of the keys that still match the prefix, then wave 0 scans the 256
+// bins from the top (4 bins per lane, shuffle scan) to find the digit.
+__device__ __forceinline__ uint32_t block_select_key(const uint32_t *key, int nkey, int need) {
+    __shared__ int hist[256];
+    __shared__ int sel[2];
+    uint32_t prefix = 0, pmask = 0;
+    const int lane = threadIdx.x % kWave;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int t = threadIdx.x; t < 256; t += blockDim.x) hist[t] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < nkey && (key[u] & pmask) == prefix) atomicAdd(&hist[(key[u] >> shift) & 255], 1);
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            int c[4], loc = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c[q] = hist[255 - 4 * lane - q];
+                loc += c[q];
+            }
+            int inc = loc;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int v = __shfl_up(inc, off, kWave);
+                if (lane >= off) inc += v;
+            }
+            const uint64_t hit = __ballot(inc >= need);
+            const int first = __ffsll((long long)hit) - 1;
+            if (lane == first) {
+                int above = inc - loc;
+                int q = 0;
+                while (q < 3 && above + c[q] < need) {
+                    above += c[q];
+                    ++q;
+                }
+                sel[0] = 255 - 4 * lane - q;
+                sel[1] = need - above;
+            }
         }
-        scores[idx] = s;
+        __syncthreads();
+        prefix |= (uint32_t)sel[0] << shift;
+        pmask |= 255u << shift;
+        need = sel[1];
+        __syncthreads();
+    }
+    return prefix;
+}
+
+__global__ __launch_bounds__(kWide) void k_topk_thresh(int64_t n, const float *__restrict__ x,
+                                                       int64_t ldx, int K, int64_t stride,
+                                                       TopkScratch ts) {
+    const int b = blockIdx.x;
+    const int64_t m = (n + stride - 1) / stride;  // sample size, <= kSample = 4 * kWide
+    uint32_t key[4];
+    int nkey = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t t = threadIdx.x + (int64_t)u * kWide;
+        key[u] = 0u;
+        if (t < m) {
+            key[u] = float_order_key(x[(size_t)b * ldx + (size_t)t * stride]);
+            nkey = u + 1;
+        }
+    }
+    // threshold: the sample's (j+1)-th largest, j a few standard deviations
+    // above the number e = K m / n of true top-K elements expected in it
+    const double e = (double)K * (double)m / (double)n;
+    const int64_t j = (int64_t)ceil(e + 4.0 * sqrt(e) + 4.0);
+    const bool all = j >= m;
+    uint32_t thr = 0u;
+    if (!all) thr = block_select_key(key, nkey, (int)j + 1);
+    if (threadIdx.x == 0) {
+        ts.thr[b] = thr;
+        ts.all[b] = all ? 1 : 0;
     }
 }
 
-static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__global__ __launch_bounds__(kBlock) void k_topk_filter(int64_t n, const float *__restrict__ x,
+                                                        int64_t ldx, TopkScratch ts) {
+    __shared__ int lcount;
+    const int b = blockIdx.y;
+    const int c = blockIdx.x;
+    if (ts.all[b]) return;  // the select kernel reads such rows directly
+    const uint32_t thr = ts.thr[b];
+    if (threadIdx.x == 0) lcount = 0;
+    __syncthreads();
+    uint64_t *cand = ts.cand + ((size_t)b * ts.nchunk + c) * kChunkCap;
+    const int64_t base = (int64_t)c * kChunk;
+    const float *row = x + (size_t)b * ldx;
+#pragma unroll 4
+    for (int u = 0; u < kChunk / kBlock; ++u) {
+        const int64_t i = base + u * kBlock + threadIdx.x;
+        if (i < n) {
+            const float v = row[i];
+            if (float_order_key(v) >= thr) {
+                const int slot = atomicAdd(&lcount, 1);
+                if (slot < kChunkCap) cand[slot] = rank_key(v, (uint32_t)i);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) ts.cnt[(size_t)b * ts.nchunk + c] = lcount;
+}
 
-size_t topk_scratch_bytes(int B, int64_t n, int K) {
-    const int kc = K < CH ? K : CH;
-    const int64_t n0 = ceil_div(n, CH) * kc;  // keys per row after level 0
-    return 2 * (size_t)B * (size_t)n0 * sizeof(uint64_t) + 256;
+__device__ __forceinline__ void write_out(const uint64_t *s, int K, int b, int32_t *ids,
+                                          float *scores, int transform) {
+    for (int t = threadIdx.x; t < K; t += kWide) {
+        const uint64_t k = s[t];
+        if (ids) ids[(size_t)b * K + t] = (int32_t)rank_key_id(k);
+        if (scores) {
+            float v = rank_key_score(k);
+            if (transform == 1) {
+                const float c = v > 0.f ? v : 0.f;
+                v = c * c * c;
+            }
+            scores[(size_t)b * K + t] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *__restrict__ x,
+                                                       int64_t ldx, int K, TopkScratch ts,
+                                                       int32_t *__restrict__ ids,
+                                                       float *__restrict__ scores, int transform) {
+    __shared__ uint64_t s[kCap];
+    __shared__ int offs[kCap / 16 + 1];
+    __shared__ int hist[256];
+    __shared__ int sh_int[8];
+    __shared__ int wcount[kWide / kWave];
+    const int b = blockIdx.x;
+    const float *row = x + (size_t)b * ldx;
+    const int nchunk = ts.nchunk;
+
+    // ---- fast paths ----
+    int total = -1;
+    if (ts.all[b]) {
+        if (n <= kCap) total = (int)n;
+    } else if (nchunk <= kCap / 16) {
+        if (threadIdx.x == 0) {
+            int acc = 0, bad = 0;
+            for (int c = 0; c < nchunk; ++c) {
+                const int k = ts.cnt[(size_t)b * nchunk + c];
+                offs[c] = acc;
+                bad |= k > kChunkCap;
+                acc += k;
+            }
+            offs[nchunk] = acc;
+            sh_int[0] = (bad || acc < K || acc > kCap) ? -1 : acc;
+        }
+        __syncthreads();
+        total = sh_int[0];
+        __syncthreads();
+    }
+    if (total >= 0) {
+        const int size = pow2_ceil(total);
+        if (ts.all[b]) {
+            for (int t = threadIdx.x; t < size; t += kWide)
+                s[t] = t < total ? rank_key(row[t], (uint32_t)t) : 0ull;
+        } else {
+            for (int c = 0; c < nchunk; ++c) {
+                const int o = offs[c], k = offs[c + 1] - o;
+                const uint64_t *src = ts.cand + ((size_t)b * nchunk + c) * kChunkCap;
+                for (int t = threadIdx.x; t < k; t += kWide) s[o + t] = src[t];
+            }
+            for (int t = total + threadIdx.x; t < size; t += kWide) s[t] = 0ull;
+        }
+        __syncthreads();
+        bitonic_desc<uint64_t, kWide>(s, size);
+        write_out(s, K, b, ids, scores, transform);
+        return;
+    }
+
+    // ---- exact selection within the block ----
+    uint32_t prefix = 0, pmask = 0;
+    int need = K;  // rank (1-based) of the wanted key among those matching the prefix
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int t = threadIdx.x; t < 256; t += kWide) hist[t] = 0;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < n; i += kWide) {
+            const uint32_t key = float_order_key(row[i]);
+            if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int above = 0, dsel = 0;
+            for (int dgt = 255; dgt >= 0; --dgt) {
+                if (above + hist[dgt] >= need) {
+                    dsel = dgt;
+                    break;
+                }
+                above += hist[dgt];
+            }
+            sh_int[0] = dsel;
+            sh_int[1] = need - above;
+        }
+        __syncthreads();
+        prefix |= (uint32_t)sh_int[0] << shift;
+        pmask |= 255u << shift;
+        need = sh_int[1];
+        __syncthreads();
+    }
+    // prefix is the K-th largest key; `need` of its equals are taken (lowest
+    // ids first) and K - need keys lie strictly above it.
+    const int n_above = K - need;
+    if (threadIdx.x == 0) {
+        sh_int[2] = 0;  // slots used by keys above
+        sh_int[3] = 0;  // equal keys taken so far
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += kWide) {
+        const float v = row[i];
+        if (float_order_key(v) > prefix) {
+            const int slot = atomicAdd(&sh_int[2], 1);
+            s[slot] = rank_key(v, (uint32_t)i);
+        }
+    }
+    __syncthreads();
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t base = 0; base < n; base += kWide) {
+        if (sh_int[3] >= need) break;  // uniform: written before the last barrier
+        const int64_t i = base + threadIdx.x;
+        const float v = i < n ? row[i] : 0.f;
+        const bool eq = i < n && float_order_key(v) == prefix;
+        const uint64_t mask = __ballot(eq);
+        if (lane == 0) wcount[w] = __popcll(mask);
+        __syncthreads();
+        int before = sh_int[3];
+        for (int q = 0; q < w; ++q) before += wcount[q];
+        const int slot = before + __popcll(mask & below);
+        if (eq && slot < need) s[n_above + slot] = rank_key(v, (uint32_t)i);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int q = 0; q < kWide / kWave; ++q) tot += wcount[q];
+            sh_int[3] += tot;
+        }
+        __syncthreads();
+    }
+    const int size = pow2_ceil(K);
+    for (int t = K + threadIdx.x; t < size; t += kWide) s[t] = 0ull;
+    __syncthreads();
+    bitonic_desc<uint64_t, kWide>(s, size);
+    write_out(s, K, b, ids, scores, transform);
 }
 
 hipError_t launch_topk(int B, int64_t n, const float *x, int64_t ldx, int K, void *scratch,
                        int32_t *ids, float *scores, int transform, hipStream_t s) {
     if (K < 1 || K > kTopkMax || K > n || B < 1) return hipErrorInvalidValue;
-    const int kc = K;
-    const int64_t n0 = ceil_div(n, CH) * kc;
-    uint64_t *buf[2];
-    buf[0] = reinterpret_cast<uint64_t *>(scratch);
-    buf[1] = buf[0] + (size_t)B * n0;
-    int nchunk = (int)ceil_div(n, CH);
-    k_topk_f32<<<dim3(nchunk, B), kBlock, 0, s>>>(n, x, ldx, kc, nchunk, buf[0]);
+    TopkScratch ts = carve(scratch, B, n);
+    const int64_t stride = ceil_div(n, kSample);
+    k_topk_thresh<<<B, kWide, 0, s>>>(n, x, ldx, K, stride, ts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int64_t m = (int64_t)nchunk * kc;
-    int cur = 0;
-    while (nchunk > 1) {
-        nchunk = (int)ceil_div(m, CH);
-        k_topk_u64<<<dim3(nchunk, B), kBlock, 0, s>>>(m, buf[cur], kc, nchunk, buf[cur ^ 1]);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        cur ^= 1;
-        m = (int64_t)nchunk * kc;
-    }
-    const int tot = B * K;
-    k_topk_decode<<<(tot + 255) / 256, 256, 0, s>>>(B, K, buf[cur], ids, scores, transform);
+    k_topk_filter<<<dim3((unsigned)ts.nchunk, B), kBlock, 0, s>>>(n, x, ldx, ts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_topk_select<<<B, kWide, 0, s>>>(n, x, ldx, K, ts, ids, scores, transform);
     return hipGetLastError();
 }
 

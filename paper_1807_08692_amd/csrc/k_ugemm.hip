@@ -36,11 +36,16 @@ int ut_p_chunks(int64_t N, int64_t *rows_per_chunk) {
 
 // A = U^T (k x rows): lane reads U[row0 + l/32][k0 + l%32] - 128 contiguous
 // bytes per row, coalesced. B = P (rows x b): P[row0 + l/32][b0 + l%32].
-// Each wave owns one 32-wide k tile and NT 32-wide column tiles.
+// Each wave owns one 32-wide k tile and NT 32-wide column tiles. The row loop
+// is software pipelined: the operands of the next 16 rows are loaded while
+// the MFMAs of the current 16 rows run, so ~24 loads per wave are in flight.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_ut_p(int64_t N, const float *__restrict__ U, int rp,
                                                  int rk, const float *__restrict__ P, int ldb,
-                                                 int64_t rc, float *__restrict__ Cpart) {
+                                                 int64_t rc, float *__restrict__ Cpart,
+                                                 IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
+    constexpr int G = 8;  // MFMA k-steps (2 rows each) per pipeline stage
     const int lane = threadIdx.x % kWave;
     const int w = threadIdx.x / kWave;
     const int k0 = (blockIdx.y * 4 + w) * 32;
@@ -54,33 +59,55 @@ __global__ __launch_bounds__(kBlock) void k_ut_p(int64_t N, const float *__restr
     for (int t = 0; t < NT; ++t)
         for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
 
+    const int64_t full_end = rs + ((re - rs) / (2 * G)) * (2 * G);
+    float a[G], b[G][NT];
     int64_t i = rs;
-    for (; i + 8 <= re; i += 8) {
-        float a[4], b[4][NT];
+    if (i < full_end) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < G; ++u) {
             const int64_t row = i + 2 * u + hi;
             a[u] = U[(size_t)row * rp + k0 + lo];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) b[u][t] = P[(size_t)row * ldb + b0 + t * 32 + lo];
+            for (int t = 0; t < NT; ++t) b[u][t] = P[vec_index(N, ldb, row, b0 + t * 32 + lo)];
+        }
+    }
+    for (; i < full_end; i += 2 * G) {
+        float an[G], bn[G][NT];
+        const bool more = i + 2 * G < full_end;
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int64_t row = i + 2 * G + 2 * u + hi;
+                an[u] = U[(size_t)row * rp + k0 + lo];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) bn[u][t] = P[vec_index(N, ldb, row, b0 + t * 32 + lo)];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < G; ++u)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = mfma32(a[u], b[u][t], acc[t]);
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                a[u] = an[u];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) b[u][t] = bn[u][t];
+            }
+        }
     }
     for (; i < re; i += 2) {
         const int64_t row = i + hi;
-        float a = 0.f, b[NT];
+        float a1 = 0.f, b1[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) b[t] = 0.f;
+        for (int t = 0; t < NT; ++t) b1[t] = 0.f;
         if (row < re) {
-            a = U[(size_t)row * rp + k0 + lo];
+            a1 = U[(size_t)row * rp + k0 + lo];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = P[(size_t)row * ldb + b0 + t * 32 + lo];
+            for (int t = 0; t < NT; ++t) b1[t] = P[vec_index(N, ldb, row, b0 + t * 32 + lo)];
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = mfma32(a, b[t], acc[t]);
+        for (int t = 0; t < NT; ++t) acc[t] = mfma32(a1, b1[t], acc[t]);
     }
     float *out = Cpart + (size_t)blockIdx.x * rk * ldb;
 #pragma unroll
@@ -91,15 +118,15 @@ __global__ __launch_bounds__(kBlock) void k_ut_p(int64_t N, const float *__restr
 }
 
 hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P, int ldb,
-                       float *Cpart, hipStream_t s) {
+                       float *Cpart, IterGuard g, hipStream_t s) {
     int64_t rc;
     int nchunk = ut_p_chunks(N, &rc);
     int kgroups = (rk / 32 + 3) / 4;
     if (ldb == 64) {
-        k_ut_p<2><<<dim3(nchunk, kgroups, 1), kBlock, 0, s>>>(N, U, rp, rk, P, ldb, rc, Cpart);
+        k_ut_p<2><<<dim3(nchunk, kgroups, 1), kBlock, 0, s>>>(N, U, rp, rk, P, ldb, rc, Cpart, g);
     } else {
         k_ut_p<4><<<dim3(nchunk, kgroups, ldb / 128), kBlock, 0, s>>>(N, U, rp, rk, P, ldb, rc,
-                                                                       Cpart);
+                                                                       Cpart, g);
     }
     return hipGetLastError();
 }
@@ -109,7 +136,8 @@ hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P
 // with two accumulators each, then the four wave sums are added in order.
 __global__ __launch_bounds__(kBlock) void k_reduce_c(int nchunk, const float *__restrict__ Cpart,
                                                      int rk, int ldb, const double *lam, int r_use,
-                                                     float *__restrict__ Cl) {
+                                                     float *__restrict__ Cl, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
     __shared__ double sh[4][kWave];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const size_t tot = (size_t)rk * ldb;
@@ -131,147 +159,182 @@ __global__ __launch_bounds__(kBlock) void k_reduce_c(int nchunk, const float *__
 }
 
 hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
-                           int r_use, float *Cl, hipStream_t s) {
+                           int r_use, float *Cl, IterGuard g, hipStream_t s) {
     size_t tot = (size_t)rk * ldb;
-    k_reduce_c<<<(unsigned)(tot / kWave), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb, lam, r_use, Cl);
+    k_reduce_c<<<(unsigned)(tot / kWave), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb, lam, r_use, Cl, g);
     return hipGetLastError();
 }
 
-// Stage U[i0 .. i0+64)[k0 .. k0+32) into LDS (row pitch 33 floats, so the
-// column-wise MFMA reads below hit distinct banks). 256 threads, 8 floats each.
-__device__ __forceinline__ void stage_u_tile(float (*Us)[33], const float *__restrict__ U, int rp,
-                                             int64_t N, int64_t i0, int k0) {
-    const int t = threadIdx.x;
-    const int row = t / 4, kk = (t % 4) * 8;
-    const int64_t gi = i0 + row;
-    float4 x = make_float4(0.f, 0.f, 0.f, 0.f), y = x;
-    if (gi < N) {
-        const float4 *src = reinterpret_cast<const float4 *>(U + (size_t)gi * rp + k0 + kk);
-        x = src[0];
-        y = src[1];
+// Operand staging shared by u_c and combine. A block covers 128 rows; per
+// 32-wide k chunk it holds U[128 rows][32 k] and C[32 k][64*NT columns] in
+// LDS. The next chunk is fetched into registers (float4) while the MFMAs of
+// the current chunk run, then written to LDS between two barriers.
+template <int NT>
+struct UcStage {
+    static constexpr int ROWS = 128;
+    static constexpr int COLS = 64 * NT;
+    float4 u[4];       // U: thread t -> row t/2, k (t%2)*16 .. +16
+    float4 c[2 * NT];  // C: float4 index t + 256 m of the 32 x COLS chunk
+
+    __device__ __forceinline__ void fetch(const float *__restrict__ U, int rp, int64_t N,
+                                          int64_t i0, int k0, const float *__restrict__ C,
+                                          int ldb, int c0) {
+        const int t = threadIdx.x;
+        const int64_t gi = i0 + t / 2;
+        const int kk = (t % 2) * 16;
+        if (gi < N) {
+            const float4 *src = reinterpret_cast<const float4 *>(U + (size_t)gi * rp + k0 + kk);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) u[m] = src[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) u[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int m = 0; m < 2 * NT; ++m) {
+            const int f = t + kBlock * m;
+            const int kr = f / (COLS / 4), c4 = (f % (COLS / 4)) * 4;
+            c[m] = *reinterpret_cast<const float4 *>(C + (size_t)(k0 + kr) * ldb + c0 + c4);
+        }
     }
-    Us[row][kk + 0] = x.x;
-    Us[row][kk + 1] = x.y;
-    Us[row][kk + 2] = x.z;
-    Us[row][kk + 3] = x.w;
-    Us[row][kk + 4] = y.x;
-    Us[row][kk + 5] = y.y;
-    Us[row][kk + 6] = y.z;
-    Us[row][kk + 7] = y.w;
+    __device__ __forceinline__ void store(float (*Us)[33], float (*Cs)[COLS + 4]) const {
+        const int t = threadIdx.x;
+        const int row = t / 2, kk = (t % 2) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            Us[row][kk + 4 * m + 0] = u[m].x;
+            Us[row][kk + 4 * m + 1] = u[m].y;
+            Us[row][kk + 4 * m + 2] = u[m].z;
+            Us[row][kk + 4 * m + 3] = u[m].w;
+        }
+#pragma unroll
+        for (int m = 0; m < 2 * NT; ++m) {
+            const int f = t + kBlock * m;
+            const int kr = f / (COLS / 4), c4 = (f % (COLS / 4)) * 4;
+            *reinterpret_cast<float4 *>(&Cs[kr][c4]) = c[m];
+        }
+    }
+};
+
+// acc[t] (t < 2*NT) += U[rows 32w..32w+31] x C[:, 32t..32t+31] over one chunk.
+template <int NT>
+__device__ __forceinline__ void uc_chunk(const float (*Us)[33], const float (*Cs)[64 * NT + 4],
+                                         f32x16 *acc) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int hi = lane / 32, lo = lane % 32;
+#pragma unroll 4
+    for (int kk = 0; kk < 32; kk += 2) {
+        const float a = Us[32 * w + lo][kk + hi];
+#pragma unroll
+        for (int t = 0; t < 2 * NT; ++t) acc[t] = mfma32(a, Cs[kk + hi][32 * t + lo], acc[t]);
+    }
 }
 
-// Z = P + alpha U Cl over a 64-row x (64*NT)-column tile; the four waves
-// split it 2 (rows) x 2 (columns). A = U (rows x k) from LDS, B = Cl (k x b)
-// straight from global memory (small, cache resident).
+// Z = P + alpha U Cl for 128 rows x 64*NT columns; wave w owns rows
+// 32w..32w+31 and all the block's columns.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_u_c(int64_t N, const float *__restrict__ U, int rp,
                                                 int rk, const float *__restrict__ Cl, int ldb,
                                                 const float *__restrict__ P, float alpha,
-                                                float *__restrict__ Z) {
-    __shared__ float Us[64][33];
-    const int lane = threadIdx.x % kWave;
-    const int w = threadIdx.x / kWave;
-    const int hi = lane / 32, lo = lane % 32;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int wr = (w & 1) * 32;
-    const int wc = blockIdx.y * 64 * NT + (w >> 1) * 32 * NT;
-    f32x16 acc[NT];
+                                                float *__restrict__ Z, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
+    constexpr int COLS = 64 * NT;
+    __shared__ float Us[128][33];
+    __shared__ __attribute__((aligned(16))) float Cs[32][COLS + 4];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int lo = lane % 32;
+    const int64_t i0 = (int64_t)blockIdx.x * 128;
+    const int c0 = blockIdx.y * COLS;
+    f32x16 acc[2 * NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < 2 * NT; ++t)
         for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+    UcStage<NT> st;
+    if (rk > 0) st.fetch(U, rp, N, i0, 0, Cl, ldb, c0);
     for (int k0 = 0; k0 < rk; k0 += 32) {
-        stage_u_tile(Us, U, rp, N, i0, k0);
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < 32; kk += 2) {
-            const float a = Us[wr + lo][kk + hi];
-            const float *crow = Cl + (size_t)(k0 + kk + hi) * ldb + wc + lo;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma32(a, crow[t * 32], acc[t]);
-        }
+        st.store(Us, Cs);
         __syncthreads();
+        if (k0 + 32 < rk) st.fetch(U, rp, N, i0, k0 + 32, Cl, ldb, c0);
+        uc_chunk<NT>(Us, Cs, acc);
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < 2 * NT; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int64_t i = i0 + wr + acc_row(v, lane);
+            const int64_t i = i0 + 32 * w + acc_row(v, lane);
             if (i < N) {
-                const size_t o = (size_t)i * ldb + wc + t * 32 + lo;
+                const size_t o = vec_index(N, ldb, i, c0 + 32 * t + lo);
                 Z[o] = P[o] + alpha * acc[t][v];
             }
         }
 }
 
 hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl, int ldb,
-                      const float *P, double alpha, float *Z, hipStream_t s) {
-    const unsigned gx = (unsigned)((N + 63) / 64);
+                      const float *P, double alpha, float *Z, IterGuard g, hipStream_t s) {
+    const unsigned gx = (unsigned)((N + 127) / 128);
     if (ldb == 64) {
-        k_u_c<1><<<dim3(gx, 1), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z);
+        k_u_c<1><<<dim3(gx, 1), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
     } else if (ldb == 128) {
-        k_u_c<2><<<dim3(gx, 1), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z);
+        k_u_c<2><<<dim3(gx, 1), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
     } else {
-        k_u_c<4><<<dim3(gx, ldb / 256), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z);
+        k_u_c<4><<<dim3(gx, ldb / 256), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
     }
     return hipGetLastError();
 }
 
-// x^T tile: rows of the product are queries b, columns are items i, so each
-// store writes 32 consecutive items of one query. A = Cs^T (b x k) from
-// global memory; B = U^T (k x i) from the staged U tile. X (node-major) is
-// staged through LDS to add the temporal term in the transposed layout.
+// x[b][i] = (U Cs)[i][b] + X[i][b] for 128 items x 64 queries per block: the
+// product is formed as in u_c, the temporal term added in the accumulator
+// layout, and the tile transposed through LDS so that each query's 128 items
+// are written as one contiguous run.
 __global__ __launch_bounds__(kBlock) void k_combine(int64_t N, int B, const float *__restrict__ U,
-                                                    int rp, int rk, const float *__restrict__ Cs,
+                                                    int rp, int rk, const float *__restrict__ Csp,
                                                     int ldb, const float *__restrict__ X,
                                                     float *__restrict__ x, int64_t ldx) {
-    __shared__ float Us[64][33];
-    __shared__ float Xs[64][65];
-    const int lane = threadIdx.x % kWave;
-    const int w = threadIdx.x / kWave;
-    const int hi = lane / 32, lo = lane % 32;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int bt = blockIdx.y * 64;
-    const int wb = (w & 1) * 32;   // query offset of this wave
-    const int wi = (w >> 1) * 32;  // item offset of this wave
-    // stage X[i0..i0+64)[bt..bt+64)
-    for (int t = threadIdx.x; t < 64 * 16; t += kBlock) {
-        const int row = t / 16, c4 = (t % 16) * 4;
-        const int64_t gi = i0 + row;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gi < N) v = *reinterpret_cast<const float4 *>(X + (size_t)gi * ldb + bt + c4);
-        Xs[row][c4 + 0] = v.x;
-        Xs[row][c4 + 1] = v.y;
-        Xs[row][c4 + 2] = v.z;
-        Xs[row][c4 + 3] = v.w;
+    __shared__ float Us[128][33];
+    __shared__ __attribute__((aligned(16))) float Cs[32][64 + 4];
+    __shared__ float T[64][129];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int lo = lane % 32;
+    const int64_t i0 = (int64_t)blockIdx.x * 128;
+    const int c0 = blockIdx.y * 64;
+    f32x16 acc[2];
+    for (int v = 0; v < 16; ++v) {
+        acc[0][v] = 0.f;
+        acc[1][v] = 0.f;
     }
-    f32x16 acc;
-    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    UcStage<1> st;
+    if (rk > 0) st.fetch(U, rp, N, i0, 0, Csp, ldb, c0);
     for (int k0 = 0; k0 < rk; k0 += 32) {
         __syncthreads();
-        stage_u_tile(Us, U, rp, N, i0, k0);
+        st.store(Us, Cs);
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < 32; kk += 2) {
-            const float a = Cs[(size_t)(k0 + kk + hi) * ldb + bt + wb + lo];
-            const float b = Us[wi + lo][kk + hi];
-            acc = mfma32(a, b, acc);
-        }
+        if (k0 + 32 < rk) st.fetch(U, rp, N, i0, k0 + 32, Csp, ldb, c0);
+        uc_chunk<1>(Us, Cs, acc);
     }
-    __syncthreads();
-    const int64_t i = i0 + wi + lo;
-    if (i < N) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int bl = wb + acc_row(v, lane);
-            const int b = bt + bl;
-            if (b < B) x[(size_t)b * ldx + i] = acc[v] + Xs[wi + lo][bl];
+            const int rl = 32 * w + acc_row(v, lane);
+            const int64_t i = i0 + rl;
+            const int bl = 32 * t + lo;
+            float val = acc[t][v];
+            if (i < N) val += X[vec_index(N, ldb, i, c0 + bl)];
+            T[bl][rl] = val;
         }
+    __syncthreads();
+    for (int f = threadIdx.x; f < 64 * 128; f += kBlock) {
+        const int bl = f / 128, rl = f % 128;
+        const int b = c0 + bl;
+        const int64_t i = i0 + rl;
+        if (b < B && i < N) x[(size_t)b * ldx + i] = T[bl][rl];
     }
 }
 
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
                           int ldb, const float *X, float *x, int64_t ldx, hipStream_t s) {
-    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((B + 63) / 64));
+    dim3 grid((unsigned)((N + 127) / 128), (unsigned)((B + 63) / 64));
     k_combine<<<grid, kBlock, 0, s>>>(N, B, U, rp, rk, Cs, ldb, X, x, ldx);
     return hipGetLastError();
 }

@@ -37,6 +37,7 @@ _SIGS = {
                                ctypes.c_int32, _P, _P, _P]),
     "hd_device_bytes": (ctypes.c_int64, [_P]),
     "hd_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "hd_timing_enable_kinds": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "hd_timing_kinds": (ctypes.c_int, []),
     "hd_timing_name": (ctypes.c_char_p, [ctypes.c_int]),
     "hd_timing_get": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
@@ -152,8 +153,17 @@ class Context:
     def device_bytes(self) -> int:
         return int(lib().hd_device_bytes(self._h))
 
-    def timing_enable(self, on: bool = True):
-        _check(lib().hd_timing_enable(self._h, 1 if on else 0))
+    def timing_enable(self, on: bool = True, kinds=None):
+        """Per-kernel event timing: all kinds, or only the named ones."""
+        if kinds is None or not on:
+            _check(lib().hd_timing_enable(self._h, 1 if on else 0))
+            return
+        L = lib()
+        names = {L.hd_timing_name(k).decode(): k for k in range(L.hd_timing_kinds())}
+        mask = 0
+        for name in kinds:
+            mask |= 1 << names[name]
+        _check(L.hd_timing_enable_kinds(self._h, mask))
 
     def timing(self) -> dict:
         """{kernel kind: (total_ms, launches)} accumulated since timing_enable."""

@@ -247,3 +247,34 @@ def test_rank_entry_exact(ctx, torch_dev, n, K, B):
         oid, osc = O.rank(x[b].astype(np.float64), K)
         assert np.array_equal(ids[b], oid)
         assert np.array_equal(sc[b], osc.astype(np.float32))
+
+
+def _rank_check(ctx, torch_dev, x, K):
+    import torch
+    xt = torch.from_numpy(x).to(torch_dev)
+    ids, sc = ctx.rank(xt, K)
+    torch.cuda.synchronize()
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    for b in range(x.shape[0]):
+        oid, osc = O.rank(x[b].astype(np.float64), K)
+        assert np.array_equal(ids[b], oid)
+        assert np.array_equal(sc[b], osc.astype(np.float32))
+
+
+def test_rank_exact_selection_paths(ctx, torch_dev):
+    """Rows on which the sampled threshold cannot be used (too many
+    candidates: all values equal, or spikes the strided sample misses; too
+    few: the sample holds all of the large values) go through the exact
+    in-block radix selection; the result must not change."""
+    n = 100000
+    flat = np.full((1, 20000), 0.5, np.float32)
+    _rank_check(ctx, torch_dev, flat, 100)
+    spikes = np.zeros((1, n), np.float32)
+    pos = np.arange(1, n, 25)[:60]
+    spikes[0, pos] = 1.0 + pos * 1e-3
+    _rank_check(ctx, torch_dev, spikes, 100)
+    few = np.full((1, n), -1.0, np.float32)
+    few[0, ::25] = np.arange(0, n, 25, dtype=np.float32)
+    _rank_check(ctx, torch_dev, few, 1024)
+    mix = np.concatenate([flat[:, :1000].repeat(2, 0), np.random.default_rng(1).standard_normal((2, 1000)).astype(np.float32)])
+    _rank_check(ctx, torch_dev, mix, 1000)
