@@ -101,9 +101,11 @@ int hd_load_graph(hd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr,
  * columns, L1 = diag(lambda)), the input of eqs. (h-spectral) and (box).
  * U (host, fp32, n x r row-major: row i holds item i's r components),
  * lambda (host, double, r values, each in [-1, 1] up to 1e-6 of rounding). `dtype` selects the
- * storage precision on the device (HD_F32, HD_BF16, HD_FP8_E4M3 with a
- * per-column scale max_i |U_ic| / 448). r = 0 unloads. Queries may use any
- * prefix of the loaded columns (hd_query_opts.rank_r).
+ * storage precision on the device: HD_F32, or HD_BF16 (U rounded to
+ * nearest-even bfloat16 and kept twice, item-major and component-major; the
+ * products multiply it with the fp32 operand split into two bfloat16 parts
+ * and accumulate in fp32). r = 0 unloads. Queries may use any prefix of the
+ * loaded columns (hd_query_opts.rank_r).
  * Errors: HD_ESTATE (no graph), HD_EINVAL (r < 0, r > n, lambda outside
  * [-1, 1] or non-finite, non-finite U, unknown dtype).
  */
@@ -114,7 +116,9 @@ int hd_load_eigs(hd_ctx *ctx, int32_t r, const float *U, const double *lambda,
  * Load the database descriptors used to build y from query descriptors
  * (Section 3: nearest neighbours of the query in the dataset). V (host,
  * fp32, n x d row-major, unit-norm rows so that the dot product is the
- * cosine). `dtype` selects the device storage (HD_F32 or HD_BF16).
+ * cosine). `dtype` selects the device storage: HD_F32, or HD_BF16 (rounded to
+ * nearest even; the query descriptors stay fp32 and are split into two
+ * bfloat16 parts for the product).
  * Errors: HD_ESTATE (no graph), HD_EINVAL (d <= 0, non-finite V, dtype).
  */
 int hd_load_descriptors(hd_ctx *ctx, int32_t d, const float *V, int32_t dtype);

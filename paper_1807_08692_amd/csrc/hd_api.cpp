@@ -67,6 +67,14 @@ struct DevBuf {
     T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// fp32 -> bfloat16 bit pattern, round to nearest even (inputs are finite).
+uint16_t bf16_rne_host(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 int pow2_at_least(int v) {
     int p = 64;
     while (p < v) p <<= 1;
@@ -151,14 +159,15 @@ struct hd_ctx {
     // graph
     int64_t n = 0, nnz = 0;
     DevBuf rowptr, col, val;
-    // eigenpairs
+    // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp) + UbT (bf16, rp x ldut)
     int r = 0, rp = 0, u_dtype = HD_F32;
-    DevBuf U, lam;
-    // descriptors
-    int d = 0, ldv = 0;
-    DevBuf V;
+    int64_t ldut = 0;
+    DevBuf U, Ub, UbT, lam;
+    // descriptors: V (fp32) or Vb (bf16), N x ldv
+    int d = 0, ldv = 0, v_dtype = HD_F32;
+    DevBuf V, Vb;
     // solver workspace
-    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, part, scal, xbuf, sim, ybuf, topk, err;
+    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, part, scal, xbuf, sim, ybuf, topk, err, qsplit;
     int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
     hipEvent_t iter_ev[2] = {nullptr, nullptr};
     hd::CgState st{};
@@ -177,9 +186,10 @@ struct hd_ctx {
     } while (0)
 
 static int64_t ctx_bytes(const hd_ctx *c) {
-    const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->lam, &c->V, &c->X, &c->R,
-                           &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs, &c->part, &c->scal,
-                           &c->xbuf, &c->sim, &c->ybuf, &c->topk, &c->err};
+    const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->V,
+                           &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
+                           &c->ClT, &c->CsT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
+                           &c->topk, &c->err, &c->qsplit};
     int64_t s = 0;
     for (const DevBuf *b : all) s += (int64_t)b->bytes;
     return s;
@@ -223,9 +233,10 @@ void hd_destroy(hd_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->lam, &c->V, &c->X, &c->R, &c->P,
-                     &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs, &c->part, &c->scal, &c->xbuf,
-                     &c->sim, &c->ybuf, &c->topk, &c->err};
+    DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->V,
+                     &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
+                     &c->ClT, &c->CsT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
+                     &c->topk, &c->err, &c->qsplit};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (hipEvent_t e : c->iter_ev)
@@ -328,9 +339,12 @@ int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, cons
     HIP_TRY(hipSetDevice(c->device));
     if (c->n != n) {
         c->U.release();
+        c->Ub.release();
+        c->UbT.release();
         c->lam.release();
         c->r = c->rp = 0;
         c->V.release();
+        c->Vb.release();
         c->d = c->ldv = 0;
     }
     HIP_TRY(c->rowptr.ensure((size_t)(n + 1) * sizeof(int64_t)));
@@ -351,9 +365,13 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
     if (!c) return fail(HD_EINVAL, "hd_load_eigs: NULL context");
     if (c->n == 0) return fail(HD_ESTATE, "hd_load_eigs: no graph loaded");
     if (r < 0 || r > c->n) return fail(HD_EINVAL, "hd_load_eigs: r=%d not in [0, n]", r);
-    if (dtype != HD_F32) return fail(HD_EINVAL, "hd_load_eigs: dtype %d not supported", dtype);
+    if (dtype != HD_F32 && dtype != HD_BF16)
+        return fail(HD_EINVAL, "hd_load_eigs: dtype %d not supported", dtype);
+    HIP_TRY(hipSetDevice(c->device));
+    c->U.release();
+    c->Ub.release();
+    c->UbT.release();
     if (r == 0) {
-        c->U.release();
         c->lam.release();
         c->r = c->rp = 0;
         return HD_OK;
@@ -365,21 +383,34 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
             return fail(HD_EINVAL, "hd_load_eigs: lambda[%d]=%g outside [-1, 1]", k, lambda[k]);
     const int rp = (r + 31) / 32 * 32;
     const int64_t n = c->n;
-    std::vector<float> host((size_t)n * rp, 0.f);
-    for (int64_t i = 0; i < n; ++i) {
-        const float *src = U + (size_t)i * r;
-        float *dst = host.data() + (size_t)i * rp;
-        for (int k = 0; k < r; ++k) {
-            if (!std::isfinite(src[k])) return fail(HD_EINVAL, "hd_load_eigs: non-finite U at row %lld", (long long)i);
-            dst[k] = src[k];
-        }
-    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < r; ++k)
+            if (!std::isfinite(U[(size_t)i * r + k]))
+                return fail(HD_EINVAL, "hd_load_eigs: non-finite U at row %lld", (long long)i);
     std::vector<double> lam((size_t)rp, 0.0);
     for (int k = 0; k < r; ++k) lam[(size_t)k] = lambda[k];
-    HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(c->U.ensure(host.size() * sizeof(float)));
+    if (dtype == HD_F32) {
+        std::vector<float> host((size_t)n * rp, 0.f);
+        for (int64_t i = 0; i < n; ++i)
+            std::memcpy(host.data() + (size_t)i * rp, U + (size_t)i * r, (size_t)r * sizeof(float));
+        HIP_TRY(c->U.ensure(host.size() * sizeof(float)));
+        HIP_TRY(hipMemcpy(c->U.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        const int64_t ldut = (n + 63) / 64 * 64;
+        std::vector<uint16_t> im((size_t)n * rp, 0), cm((size_t)rp * ldut, 0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < r; ++k) {
+                const uint16_t h = bf16_rne_host(U[(size_t)i * r + k]);
+                im[(size_t)i * rp + k] = h;
+                cm[(size_t)k * ldut + i] = h;
+            }
+        HIP_TRY(c->Ub.ensure(im.size() * sizeof(uint16_t)));
+        HIP_TRY(c->UbT.ensure(cm.size() * sizeof(uint16_t)));
+        HIP_TRY(hipMemcpy(c->Ub.p, im.data(), im.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->UbT.p, cm.data(), cm.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        c->ldut = ldut;
+    }
     HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
-    HIP_TRY(hipMemcpy(c->U.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
     c->r = r;
     c->rp = rp;
@@ -392,23 +423,33 @@ int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
     if (!c) return fail(HD_EINVAL, "hd_load_descriptors: NULL context");
     if (c->n == 0) return fail(HD_ESTATE, "hd_load_descriptors: no graph loaded");
     if (d <= 0 || !V) return fail(HD_EINVAL, "hd_load_descriptors: bad d or NULL V");
-    if (dtype != HD_F32) return fail(HD_EINVAL, "hd_load_descriptors: dtype %d not supported", dtype);
+    if (dtype != HD_F32 && dtype != HD_BF16)
+        return fail(HD_EINVAL, "hd_load_descriptors: dtype %d not supported", dtype);
     const int ldv = (d + 31) / 32 * 32;
     const int64_t n = c->n;
-    std::vector<float> host((size_t)n * ldv, 0.f);
-    for (int64_t i = 0; i < n; ++i) {
-        const float *src = V + (size_t)i * d;
-        float *dst = host.data() + (size_t)i * ldv;
-        for (int t = 0; t < d; ++t) {
-            if (!std::isfinite(src[t])) return fail(HD_EINVAL, "hd_load_descriptors: non-finite V at row %lld", (long long)i);
-            dst[t] = src[t];
-        }
-    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int t = 0; t < d; ++t)
+            if (!std::isfinite(V[(size_t)i * d + t]))
+                return fail(HD_EINVAL, "hd_load_descriptors: non-finite V at row %lld", (long long)i);
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(c->V.ensure(host.size() * sizeof(float)));
-    HIP_TRY(hipMemcpy(c->V.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->V.release();
+    c->Vb.release();
+    if (dtype == HD_F32) {
+        std::vector<float> host((size_t)n * ldv, 0.f);
+        for (int64_t i = 0; i < n; ++i)
+            std::memcpy(host.data() + (size_t)i * ldv, V + (size_t)i * d, (size_t)d * sizeof(float));
+        HIP_TRY(c->V.ensure(host.size() * sizeof(float)));
+        HIP_TRY(hipMemcpy(c->V.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        std::vector<uint16_t> host((size_t)n * ldv, 0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int t = 0; t < d; ++t) host[(size_t)i * ldv + t] = bf16_rne_host(V[(size_t)i * d + t]);
+        HIP_TRY(c->Vb.ensure(host.size() * sizeof(uint16_t)));
+        HIP_TRY(hipMemcpy(c->Vb.p, host.data(), host.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
     c->d = d;
     c->ldv = ldv;
+    c->v_dtype = dtype;
     return HD_OK;
 }
 
@@ -468,6 +509,10 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
         HIP_TRY(c->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         HIP_TRY(c->Cs.ensure((size_t)rk * ldb * sizeof(float)));
+        if (c->u_dtype == HD_BF16) {
+            HIP_TRY(c->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
+            HIP_TRY(c->CsT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
+        }
     }
     HIP_TRY(c->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
     HIP_TRY(c->scal.ensure((size_t)ldb * (5 * sizeof(double) + 3 * sizeof(int32_t)) + 128 * sizeof(int32_t)));
@@ -501,7 +546,13 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
             oi = c->ybuf.as<int32_t>();
             ov = reinterpret_cast<float *>(oi + (size_t)B * ky);
         }
-        LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
+        if (c->v_dtype == HD_BF16) {
+            HIP_TRY(c->qsplit.ensure((size_t)2 * B * c->ldv * sizeof(uint16_t)));
+            LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.as<uint16_t>(), c->ldv,
+                                              c->qsplit.as<uint16_t>(), c->sim.as<float>(), lds, s));
+        } else {
+            LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
+        }
         LAUNCH(K_TOPK_Y, hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
         yi = oi;
         yv = ov;
@@ -526,10 +577,21 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     if (c->h_pinned[200] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
 
     // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
+    const bool ubf = c->u_dtype == HD_BF16;
     const float *U = c->U.as<float>();
-    if (rk > 0)
-        LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, U, c->rp, rk, r_use, c->lam.as<double>(), o->alpha, ldb,
-                                       c->Cs.as<float>(), c->Cl.as<float>(), s));
+    const uint16_t *Ub = c->Ub.as<uint16_t>(), *UbT = c->UbT.as<uint16_t>();
+    uint16_t *ClT_hi = c->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
+    uint16_t *CsT_hi = c->CsT.as<uint16_t>(), *CsT_lo = CsT_hi ? CsT_hi + (size_t)rk * ldb : nullptr;
+    if (rk > 0) {
+        LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, ubf ? (const void *)Ub : (const void *)U,
+                                                ubf ? 1 : 0, c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
+                                                ldb, c->Cs.as<float>(), c->Cl.as<float>(), s));
+        if (ubf) {
+            const hd::IterGuard none{nullptr, 0};
+            LAUNCH(K_GATHER, hd::launch_split_t(c->Cs.as<float>(), rk, ldb, CsT_hi, CsT_lo, none, s));
+            LAUNCH(K_GATHER, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, none, s));
+        }
+    }
 
     // ---- step 3: CG on the deflated system ----
     // Iteration it checks the active counts left by iteration it-1 (parity
@@ -545,11 +607,21 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         const float *Zs = P;
         if (rk > 0) {
             if (it > 1) {
-                LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), g, s));
+                if (ubf) {
+                    LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, c->ldut, rk, P, ldb, c->Cpart.as<float>(), g, s));
+                } else {
+                    LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), g, s));
+                }
                 LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(),
                                                        r_use, c->Cl.as<float>(), g, s));
+                if (ubf) LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
             }
-            LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), g, s));
+            if (ubf) {
+                LAUNCH(K_U_C, hd::launch_u_c_bf16(n, Ub, c->rp, rk, ClT_hi, ClT_lo, ldb, P, o->alpha,
+                                                  c->Z.as<float>(), g, s));
+            } else {
+                LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), g, s));
+            }
             Zs = c->Z.as<float>();
         }
         LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
@@ -588,8 +660,13 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         HIP_TRY(c->xbuf.ensure((size_t)B * n * sizeof(float)));
         xq = c->xbuf.as<float>();
     }
-    if (x_out || o->top_k > 0)
-        LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, X, xq, n, s));
+    if (x_out || o->top_k > 0) {
+        if (ubf && rk > 0) {
+            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, Ub, c->rp, rk, CsT_hi, CsT_lo, ldb, X, xq, n, s));
+        } else {
+            LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, X, xq, n, s));
+        }
+    }
     if (o->top_k > 0 && (rank_ids || rank_scores)) {
         HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, o->top_k)));
         LAUNCH(K_TOPK_RANK, hd::launch_topk(B, n, xq, n, o->top_k, c->topk.p, rank_ids, rank_scores, 0, s));

@@ -56,9 +56,11 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
                             const double *a, const double *beta, const int32_t *active,
                             IterGuard g, hipStream_t s);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
+// U is fp32 (u_bf16 = 0) or bf16 bit patterns (u_bf16 = 1), item-major N x rp.
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                              const float *U, int rp, int rk, int r_use, const double *lam,
-                              double alpha, int ldb, float *Cs, float *Cl, hipStream_t s);
+                              const void *U, int u_bf16, int rp, int rk, int r_use,
+                              const double *lam, double alpha, int ldb, float *Cs, float *Cl,
+                              hipStream_t s);
 
 // ---- sparse product (k_spmm.hip) ----
 // Q = (Zs - alpha * S P) / (1 - alpha); gpart[g][c] = sum over the rows of
@@ -82,6 +84,28 @@ hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl
 // x[b][i] = (U Cs)[i][b] + X[i][b] for b < B, i < N   (x row stride ldx)
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
                           int ldb, const float *X, float *x, int64_t ldx, hipStream_t s);
+
+// ---- bfloat16 storage form of the eigenvector and descriptor products
+//      (k_ugemm_bf16.hip); bf16 values are passed as their 16-bit patterns ----
+// CT_hi / CT_lo (ldb x rk, bf16) = hi / lo split of C^T (C: rk x ldb fp32).
+// A null g.nact disables the iteration guard.
+hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi,
+                          unsigned short *CT_lo, IterGuard g, hipStream_t s);
+// Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT, rp x ldut)
+hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, int64_t ldut, int rk, const float *P,
+                            int ldb, float *Cpart, IterGuard g, hipStream_t s);
+// Z = P + alpha U Cl, U item-major (N x rp), Cl given as split transpose
+hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, int rp, int rk,
+                           const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
+                           const float *P, double alpha, float *Z, IterGuard g, hipStream_t s);
+// x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
+hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, int rp, int rk,
+                               const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
+                               const float *X, float *x, int64_t ldx, hipStream_t s);
+// sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv); qsplit: scratch for
+// 2 x B x ldv bf16 (the hi / lo parts of q)
+hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsigned short *V,
+                           int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s);
 
 // ---- similarity product for the observation vector (k_sim.hip) ----
 // sim[b][j] = sum_t q[b][t] V[j][t]  (q: B x d, row stride d; V: N x ldv)

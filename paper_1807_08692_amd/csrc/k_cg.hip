@@ -368,9 +368,19 @@ hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s) {
 // that y touches. Writes Cs = g(lambda) .* c (the spectral coefficients,
 // g(x) = h(x) - h(0), eq. (aux)) and Cl = lambda .* c, which is L1 U1^T P for
 // the first CG product since P0 = y.
+template <typename UT>
+__device__ __forceinline__ double u_elem(const UT *U, size_t o);
+template <>
+__device__ __forceinline__ double u_elem<float>(const float *U, size_t o) { return (double)U[o]; }
+template <>
+__device__ __forceinline__ double u_elem<unsigned short>(const unsigned short *U, size_t o) {
+    return (double)__uint_as_float((uint32_t)U[o] << 16);
+}
+
+template <typename UT>
 __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int32_t *ids,
                                                         const float *vals, int64_t N,
-                                                        const float *U, int rp, int rk, int r_use,
+                                                        const UT *U, int rp, int rk, int r_use,
                                                         const double *lam, double alpha, int ldb,
                                                         float *Cs, float *Cl) {
     int k = blockIdx.x * kBlock + threadIdx.x;
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
     if (k < r_use && b < B) {
         for (int t = 0; t < ky; ++t) {
             int id = ids[b * ky + t];
-            if (id >= 0 && (int64_t)id < N) acc += (double)U[(size_t)id * rp + k] * (double)vals[b * ky + t];
+            if (id >= 0 && (int64_t)id < N) acc += u_elem<UT>(U, (size_t)id * rp + k) * (double)vals[b * ky + t];
         }
     }
     double lk = k < r_use ? lam[k] : 0.0;
@@ -391,12 +401,20 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
 }
 
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                              const float *U, int rp, int rk, int r_use, const double *lam,
-                              double alpha, int ldb, float *Cs, float *Cl, hipStream_t s) {
+                              const void *U, int u_bf16, int rp, int rk, int r_use,
+                              const double *lam, double alpha, int ldb, float *Cs, float *Cl,
+                              hipStream_t s) {
     if (rk == 0) return hipSuccess;
     dim3 grid((rk + kBlock - 1) / kBlock, ldb);
-    k_gather_proj<<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N, U, rp, rk, r_use, lam, alpha, ldb,
-                                          Cs, Cl);
+    if (u_bf16) {
+        k_gather_proj<unsigned short><<<grid, kBlock, 0, s>>>(
+            B, ky, ids, vals, N, reinterpret_cast<const unsigned short *>(U), rp, rk, r_use, lam,
+            alpha, ldb, Cs, Cl);
+    } else {
+        k_gather_proj<float><<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N,
+                                                     reinterpret_cast<const float *>(U), rp, rk,
+                                                     r_use, lam, alpha, ldb, Cs, Cl);
+    }
     return hipGetLastError();
 }
 
