@@ -7,11 +7,13 @@ vectors y (similarity product + top-k_y), the spectral term, conjugate
 gradient on the deflated system until every column reaches the relative
 residual tolerance, and the ranking of x = x^s + x^t.
 
-Default workload: 100,000 database items, d = 2048, a mixture of 1,000 von
-Mises-Fisher clusters (kappa 60), reciprocal k-NN graph with k = 50 and
-weights max(0, cos)^3, alpha = 0.99, r = 400 eigenvectors (FP32), batches of
-64 queries with k_y = 50, CG to relative residual 1e-5. All inputs are
-seeded and synthetic.
+Default workload (n1m): 1,000,000 database items, d = 2048, a mixture of
+10,000 von Mises-Fisher clusters (kappa 60), reciprocal k-NN graph with
+k = 50 and weights max(0, cos)^3, alpha = 0.99, r = 1000 eigenvectors and
+the descriptors stored in bfloat16 (the precision form; CG vectors fp32,
+CG scalars fp64), batches of 256 queries with k_y = 50, CG to relative
+residual 1e-5. --workload n100k --precision f32 runs the 100,000-item,
+r = 400, 64-query fp32 configuration. All inputs are seeded and synthetic.
 
 Prints one JSON line (rank 0, N = 1). Per-kernel HIP-event times over the
 timed region give the roofline figures of the dominant kernel; the FP64
@@ -32,6 +34,7 @@ if ROOT not in sys.path:
 METRIC = "queries/s at N=1M, hybrid vs plain CG at equal rel-err; p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense fp32 matrix
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix
 
 
 def log(*a):
@@ -43,11 +46,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="n100k")
+    p.add_argument("--workload", default="n1m")
+    p.add_argument("--precision", choices=["f32", "bf16"], default=None,
+                   help="storage of U1 and the descriptors (default: bf16 for n1m, f32 otherwise)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU time budget of the oracle baseline sample")
-    p.add_argument("--eig-seconds", type=float, default=120.0)
+    p.add_argument("--eig-seconds", type=float, default=90.0)
     p.add_argument("--fixture-cache", default=None,
                    help="directory to keep the generated workload between runs")
     p.add_argument("--copy-calibration", action="store_true",
@@ -55,23 +60,24 @@ def parse():
     return p.parse_args()
 
 
-def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk):
-    """(bytes, flops) one launch of kernel `kind` must move / compute."""
+def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4):
+    """(bytes, flops) one launch of kernel `kind` must move / compute;
+    su = bytes per stored U1 / descriptor element (4 fp32, 2 bf16)."""
     v = 4.0 * n * ldb
     if kind == "spmm":
         return 8.0 * (n + 1) + 8.0 * nnz + v * (3 if rk > 0 else 2), 2.0 * nnz * ldb
     if kind == "u_c":
-        return 4.0 * n * rk + 4.0 * rk * ldb + 2 * v, 2.0 * n * rk * ldb
+        return su * n * rk + 4.0 * rk * ldb + 2 * v, 2.0 * n * rk * ldb
     if kind == "ut_p":
-        return 4.0 * n * rk + v + 4.0 * nchunk * rk * ldb, 2.0 * n * rk * ldb
+        return su * n * rk + v + 4.0 * nchunk * rk * ldb, 2.0 * n * rk * ldb
     if kind == "update_r":
         return 3 * v, 2.0 * n * ldb
     if kind == "update_xp":
         return 5 * v, 4.0 * n * ldb
     if kind == "sim":
-        return 4.0 * n * d + 4.0 * B * d + 4.0 * B * n, 2.0 * B * n * d
+        return su * n * d + 4.0 * B * d + 4.0 * B * n, 2.0 * B * n * d
     if kind == "combine":
-        return 4.0 * n * rk + v + 4.0 * B * n, 2.0 * n * rk * B
+        return su * n * rk + v + 4.0 * B * n, 2.0 * n * rk * B
     return None
 
 
@@ -92,6 +98,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     cfg = W.CONFIGS[args.workload]
+    prec = args.precision or ("bf16" if args.workload in ("n1m", "n2m") else "f32")
     B = cfg.batch
     nbatch = 4
     t0 = time.time()
@@ -103,8 +110,10 @@ def main():
     dev = torch.device("cuda:0")
     ctx = hd.Context(0)
     ctx.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
-    ctx.load_eigs(fx.U, fx.lam)
-    ctx.load_descriptors(fx.V)
+    t1 = time.time()
+    ctx.load_eigs(fx.U, fx.lam, dtype=prec)
+    ctx.load_descriptors(fx.V, dtype=prec)
+    log(f"[setup] loaded graph, eigenpairs, descriptors ({prec}) in {time.time() - t1:.1f}s")
     Qd = torch.from_numpy(fx.Q.reshape(nbatch, B, cfg.d)).to(dev)
     torch.cuda.synchronize()
     log(f"[setup] library holds {ctx.device_bytes() / 2**20:.0f} MiB on the device")
@@ -148,6 +157,7 @@ def main():
         ldb *= 2
     rk = (cfg.r + 31) // 32 * 32
     nchunk = -(-fx.n // max(256, ((-(-fx.n // 256)) + 63) // 64 * 64))
+    su = 2 if prec == "bf16" else 4
     costed = [k for k, (ms, cnt) in tm_all.items()
               if cnt and algorithmic_cost(k, 1, 1, 64, 32, 1, 1, 1)]
     dom = max(costed, key=lambda k: tm_all[k][0])
@@ -169,18 +179,19 @@ def main():
     for kind, (ms, cnt) in tm_all.items():
         if cnt == 0:
             continue
-        cost = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk)
+        cost = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, su)
         kernels[kind] = {"ms_total": round(ms, 4), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 3)}
         if cost:
             by, fl = cost
             kernels[kind]["GB_s"] = round(by / (ms / cnt * 1e-3) / 1e9, 1)
             kernels[kind]["TFLOP_s"] = round(fl / (ms / cnt * 1e-3) / 1e12, 2)
     # roofline of the dominant kernel, from its events inside the timed region
-    by, fl = algorithmic_cost(dom, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk)
+    by, fl = algorithmic_cost(dom, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, su)
     avg_s = tm[dom][0] / tm[dom][1] * 1e-3
     ai = fl / by
-    if dom in ("u_c", "ut_p", "sim", "combine") and ai > FP32_MFMA_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS:
-        roof = {"bound": "mfma", "achieved": round(fl / avg_s / 1e12, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+    mfma_peak = BF16_MFMA_PEAK_TFLOPS if prec == "bf16" else FP32_MFMA_PEAK_TFLOPS
+    if dom in ("u_c", "ut_p", "sim", "combine") and ai > mfma_peak * 1e3 / HBM_PEAK_GBS:
+        roof = {"bound": "mfma", "achieved": round(fl / avg_s / 1e12, 2), "peak": mfma_peak,
                 "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": round(by / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
@@ -202,12 +213,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == "f32" else "bf16+f32",
         "data": "synthetic",
         "config": {
             "workload": f"vMF mixture N={cfg.n} d={cfg.d} clusters={cfg.clusters} kappa={cfg.kappa:g}, "
-                        f"reciprocal kNN k={cfg.k} (nnz={fx.nnz}), alpha={cfg.alpha}, hybrid r={cfg.r} "
-                        f"FP32, batch {B} queries, k_y={cfg.k_y}, CG rel-res {cfg.tol:g}, top-{K_RANK}",
+                        f"reciprocal kNN k={cfg.k} (nnz={fx.nnz}), alpha={cfg.alpha}, hybrid r={cfg.r}, "
+                        f"U1 and descriptors {prec.upper()}, batch {B} queries, k_y={cfg.k_y}, CG rel-res {cfg.tol:g}, top-{K_RANK}",
             "global_batch": B,
             "parallelism": "single GPU",
         },

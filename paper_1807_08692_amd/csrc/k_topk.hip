@@ -230,10 +230,12 @@ __global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *_
     if (ts.all[b]) {
         if (n <= kCap) total = (int)n;
     } else if (nchunk <= kCap / 16) {
+        for (int c = threadIdx.x; c < nchunk; c += kWide) offs[c + 1] = ts.cnt[(size_t)b * nchunk + c];
+        __syncthreads();
         if (threadIdx.x == 0) {
             int acc = 0, bad = 0;
             for (int c = 0; c < nchunk; ++c) {
-                const int k = ts.cnt[(size_t)b * nchunk + c];
+                const int k = offs[c + 1];
                 offs[c] = acc;
                 bad |= k > kChunkCap;
                 acc += k;

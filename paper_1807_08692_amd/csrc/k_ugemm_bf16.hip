@@ -93,10 +93,12 @@ __global__ __launch_bounds__(kBlock) void k_ut_p_bf16(int64_t N, const unsigned 
     __shared__ __attribute__((aligned(16))) unsigned short Ph[64][40];
     __shared__ __attribute__((aligned(16))) unsigned short Pl[64][40];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    // grid: x = 64-column group (fastest, so the groups of one row chunk run
+    // side by side and read U once from memory), y = k group, z = row chunk
     const int k0 = blockIdx.y * 128 + 32 * w;
     const bool kact = k0 < rk;  // waves past rk still help stage P
-    const int b0 = blockIdx.z * 64;
-    const int64_t rs = (int64_t)blockIdx.x * rc;
+    const int b0 = blockIdx.x * 64;
+    const int64_t rs = (int64_t)blockIdx.z * rc;
     const int64_t re = rs + rc < N ? rs + rc : N;
     const int g = lane / 16, c16 = lane % 16;
     // P staging: thread t -> row t/8 of the tile, columns 8*(t%8) .. +7
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_ut_p_bf16(int64_t N, const unsigned 
         }
     }
     if (!kact) return;
-    float *out = Cpart + (size_t)blockIdx.x * rk * ldb;
+    float *out = Cpart + (size_t)blockIdx.z * rk * ldb;
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -179,7 +181,7 @@ hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, int64_t ldut, i
     int64_t rc;
     const int nchunk = ut_p_chunks(N, &rc);
     const int kgroups = (rk + 127) / 128;
-    k_ut_p_bf16<<<dim3(nchunk, kgroups, ldb / 64), kBlock, 0, s>>>(N, UT, ldut, rk, P, ldb, rc, Cpart, g);
+    k_ut_p_bf16<<<dim3(ldb / 64, kgroups, nchunk), kBlock, 0, s>>>(N, UT, ldut, rk, P, ldb, rc, Cpart, g);
     return hipGetLastError();
 }
 
@@ -248,8 +250,10 @@ __global__ __launch_bounds__(kBlock) void k_u_c_bf16(int64_t N, const unsigned s
     if (all_stopped(ig.nact, ig.ntile)) return;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
-    const int64_t i0 = (int64_t)blockIdx.x * 128;
-    const int c0 = blockIdx.y * 64;
+    // grid: x = 64-column group (fastest: the groups of one row block share
+    // their U rows through the caches), y = 128-row block
+    const int64_t i0 = (int64_t)blockIdx.y * 128;
+    const int c0 = blockIdx.x * 64;
     f32x4 acc[2][4];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_u_c_bf16(int64_t N, const unsigned s
 hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, int rp, int rk,
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                            const float *P, double alpha, float *Z, IterGuard g, hipStream_t s) {
-    dim3 grid((unsigned)((N + 127) / 128), (unsigned)(ldb / 64));
+    dim3 grid((unsigned)(ldb / 64), (unsigned)((N + 127) / 128));
     k_u_c_bf16<<<grid, kBlock, 0, s>>>(N, U, rp, rk, CT_hi, CT_lo, ldb, P, (float)alpha, Z, g);
     return hipGetLastError();
 }
@@ -289,8 +293,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_bf16(int64_t N, int B,
     __shared__ float T[64][129];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
-    const int64_t i0 = (int64_t)blockIdx.x * 128;
-    const int c0 = blockIdx.y * 64;
+    const int64_t i0 = (int64_t)blockIdx.y * 128;  // x: query group (fastest), y: row block
+    const int c0 = blockIdx.x * 64;
     f32x4 acc[2][4];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_combine_bf16(int64_t N, int B,
 hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, int rp, int rk,
                                const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                const float *X, float *x, int64_t ldx, hipStream_t s) {
-    dim3 grid((unsigned)((N + 127) / 128), (unsigned)((B + 63) / 64));
+    dim3 grid((unsigned)((B + 63) / 64), (unsigned)((N + 127) / 128));
     k_combine_bf16<<<grid, kBlock, 0, s>>>(N, B, U, rp, rk, CT_hi, CT_lo, ldb, X, x, ldx);
     return hipGetLastError();
 }

@@ -114,19 +114,43 @@ def vmf_draw(rng: np.random.Generator, mus: np.ndarray, kappa: float) -> np.ndar
     return x
 
 
+def vmf_draw_torch(rng: np.random.Generator, gen, mus, kappa: float):
+    """vmf_draw with the tangent Gaussians drawn by torch on mus's device
+    (gen: a seeded torch.Generator on that device)."""
+    import torch
+    m, d = mus.shape
+    w = torch.from_numpy(_wood_w(rng, d, kappa, m)).to(mus.device)
+    v = torch.randn((m, d), generator=gen, device=mus.device, dtype=torch.float64)
+    v -= (v * mus).sum(1, keepdim=True) * mus
+    v /= torch.linalg.vector_norm(v, dim=1, keepdim=True)
+    x = w[:, None] * mus + torch.sqrt(torch.clamp(1.0 - w * w, min=0.0))[:, None] * v
+    return x / torch.linalg.vector_norm(x, dim=1, keepdim=True)
+
+
 def vmf_mixture(n: int, d: int, clusters: int, kappa: float, seed_centres: int,
-                seed_points: int, chunk: int = 65536):
+                seed_points: int, chunk: int = 65536, device=None):
     """n unit-norm float32 descriptors from an equal-weight vMF mixture.
-    Returns (V n x d float32, labels n int32, centres clusters x d float64)."""
+    Returns (V n x d float32, labels n int32, centres clusters x d float64).
+    With a torch GPU device the tangent Gaussians come from torch's seeded
+    generator there (a different, equally deterministic stream)."""
     rc = np.random.default_rng(seed_centres)
     centres = rc.standard_normal((clusters, d))
     centres /= np.linalg.norm(centres, axis=1, keepdims=True)
     rp = np.random.default_rng(seed_points)
     labels = rp.integers(0, clusters, size=n).astype(np.int32)
     V = np.empty((n, d), np.float32)
-    for s in range(0, n, chunk):
-        e = min(n, s + chunk)
-        V[s:e] = vmf_draw(rp, centres[labels[s:e]], kappa).astype(np.float32)
+    if device is not None:
+        import torch
+        gen = torch.Generator(device=device).manual_seed(int(seed_points))
+        ct = torch.from_numpy(centres).to(device)
+        lt = torch.from_numpy(labels.astype(np.int64)).to(device)
+        for s in range(0, n, chunk):
+            e = min(n, s + chunk)
+            V[s:e] = vmf_draw_torch(rp, gen, ct[lt[s:e]], kappa).float().cpu().numpy()
+    else:
+        for s in range(0, n, chunk):
+            e = min(n, s + chunk)
+            V[s:e] = vmf_draw(rp, centres[labels[s:e]], kappa).astype(np.float32)
     # re-normalise in float32 so every stored row is unit norm to fp32 rounding
     V /= np.linalg.norm(V, axis=1, keepdims=True).astype(np.float32)
     return V, labels, centres
@@ -151,20 +175,33 @@ def _torch_device(prefer_gpu: bool = True):
     return torch.device("cpu")
 
 
-def knn_lists(V: np.ndarray, k: int, prefer_gpu: bool = True, block: int = 4096):
+def knn_lists(V: np.ndarray, k: int, prefer_gpu: bool = True, block: int = 4096,
+              bf16_inputs: bool = False):
     """Per item, its k most similar other items by cosine (self excluded),
-    with the float32 similarities. Returns (nbr n x k int64, sim n x k float32)."""
+    with the float32 similarities. Returns (nbr n x k int64, sim n x k float32).
+    bf16_inputs: form the products from bfloat16-rounded descriptors with
+    fp32 accumulation and fp32 results (for very large n on the GPU)."""
     import torch
     dev = _torch_device(prefer_gpu)
     n = V.shape[0]
     Vt = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
+    Vb = Vt.to(torch.bfloat16) if (bf16_inputs and dev.type == "cuda") else None
     nbr = np.empty((n, k), np.int64)
     sim = np.empty((n, k), np.float32)
     if dev.type == "cuda":
         block = max(256, min(block, int(2 ** 31 // max(n, 1))))
+
+    def products(s, e):
+        if Vb is not None:
+            try:
+                return torch.mm(Vb[s:e], Vb.T, out_dtype=torch.float32)
+            except (TypeError, RuntimeError, NotImplementedError):
+                pass
+        return Vt[s:e] @ Vt.T
+
     for s in range(0, n, block):
         e = min(n, s + block)
-        S = Vt[s:e] @ Vt.T
+        S = products(s, e)
         S[torch.arange(e - s, device=dev), torch.arange(s, e, device=dev)] = -float("inf")
         val, idx = torch.topk(S, k, dim=1, largest=True, sorted=True)
         nbr[s:e] = idx.cpu().numpy()
@@ -203,6 +240,29 @@ def mutual_knn_graph(nbr: np.ndarray, sim: np.ndarray, n: int):
     np.add.at(rowptr, rows + 1, 1)
     rowptr = np.cumsum(rowptr)
     return rowptr, cols.astype(np.int32), w
+
+
+def mutual_knn_graph_torch(nbr, sim, n: int, device):
+    """mutual_knn_graph on a torch device (same result, sorted keys on the GPU)."""
+    import torch
+    k = nbr.shape[1]
+    nb = torch.from_numpy(np.ascontiguousarray(nbr)).to(device).reshape(-1)
+    sv = torch.from_numpy(np.ascontiguousarray(sim)).to(device).reshape(-1).double()
+    rows = torch.arange(n, device=device, dtype=torch.int64).repeat_interleave(k)
+    key = rows * n + nb
+    skey, order = torch.sort(key)
+    vals = sv[order]
+    rs, cs = skey // n, skey % n
+    rkey = cs * n + rs
+    pos = torch.searchsorted(skey, rkey).clamp(max=skey.numel() - 1)
+    mutual = skey[pos] == rkey
+    canon = torch.where(rs < cs, vals, vals[pos])
+    w = torch.clamp(canon, min=0.0) ** 3
+    keep = mutual & (w > 0.0)
+    rs, cs, w = rs[keep], cs[keep], w[keep]
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(torch.bincount(rs, minlength=n), 0)
+    return rowptr.cpu().numpy(), cs.to(torch.int32).cpu().numpy(), w.cpu().numpy()
 
 
 def symmetric_normalize(n, rowptr, col, w):
@@ -361,11 +421,18 @@ def _build_fixture(cfg, n_queries, r, prefer_gpu, eig_time_budget, log) -> Fixtu
     t0 = time.time()
     say = log or (lambda *a: None)
     sc, spt, sq, se = cfg.seeds
-    V, labels, centres = vmf_mixture(cfg.n, cfg.d, cfg.clusters, cfg.kappa, sc, spt)
+    dev = _torch_device(prefer_gpu)
+    big = dev.type == "cuda" and cfg.n >= 200_000   # generate on the GPU
+    V, labels, centres = vmf_mixture(cfg.n, cfg.d, cfg.clusters, cfg.kappa, sc, spt,
+                                     device=dev if big else None)
     Q = vmf_queries(n_queries, centres, cfg.kappa, sq)
     say(f"descriptors {time.time() - t0:.1f}s")
-    nbr, sim = knn_lists(V, cfg.k, prefer_gpu=prefer_gpu)
-    rowptr, col, w = mutual_knn_graph(nbr, sim, cfg.n)
+    nbr, sim = knn_lists(V, cfg.k, prefer_gpu=prefer_gpu, bf16_inputs=big)
+    say(f"knn {time.time() - t0:.1f}s")
+    if big:
+        rowptr, col, w = mutual_knn_graph_torch(nbr, sim, cfg.n, dev)
+    else:
+        rowptr, col, w = mutual_knn_graph(nbr, sim, cfg.n)
     del nbr, sim
     s64 = symmetric_normalize(cfg.n, rowptr, col, w)
     s32 = s64.astype(np.float32)
