@@ -198,6 +198,70 @@ int hd_timing_kinds(void);
 const char *hd_timing_name(int kind);
 int hd_timing_get(const hd_ctx *ctx, int kind, double *total_ms, int64_t *launches);
 
+/*
+ * Continuous-batching server. One server keeps a conjugate-gradient solve
+ * running over a fixed set of query columns (slots) of the context's graph,
+ * eigenpairs and descriptors, which must stay loaded and unchanged while it
+ * is open. Requests join free columns between iterations, while other
+ * columns are in the middle of their solves, and leave when their column
+ * stops: converged (opts.tol), their own iteration cap, y = 0, or breakdown.
+ * Each column is an independent recurrence with fixed-order reductions, so a
+ * request gets the same result alone or in a full server. The server runs on
+ * its own HIP stream. A server is
+ * used by one host thread at a time; several servers (e.g. one per
+ * database) may run side by side. Calls return when their work is done,
+ * except hd_serve_step, which only queues it.
+ */
+typedef struct hd_server hd_server;
+
+/*
+ * Open a server with up to `slots` columns (1..1024) and the options of
+ * hd_query_batch (alpha, tol, rank_r, k_y, top_k >= 1; max_iter is the
+ * default per-request cap). hbm_budget_bytes > 0 caps the device memory of
+ * the server: the column count is the largest power of two >= 64 that fits,
+ * and slots is lowered to it (hd_serve_slots reports the result).
+ * Errors: HD_EINVAL, HD_ESTATE (no graph, rank_r above the loaded r),
+ * HD_ENOMEM (budget below 64 columns, or allocation failure), HD_EDEVICE.
+ */
+int hd_serve_open(hd_ctx *ctx, int32_t slots, int64_t hbm_budget_bytes,
+                  const hd_query_opts *opts, hd_server **out);
+
+/* Device bytes one server column takes on this context with these options
+ * (0 for NULL arguments): the unit of hd_serve_open's budget. */
+int64_t hd_serve_column_bytes(const hd_ctx *ctx, const hd_query_opts *opts);
+
+/* Column capacity and columns now holding a request (admitted, not polled). */
+int hd_serve_slots(const hd_server *srv);
+int hd_serve_in_use(const hd_server *srv);
+
+/*
+ * Admit up to n requests, in order, into free columns. Input as in
+ * hd_query_batch but in HOST memory: q_desc (n x d fp32) or y_ids / y_val
+ * (n x k_y). max_iter (host, n entries, >= 0) or NULL for the server default.
+ * tickets (host, n) receives an id for each admitted request. Returns the
+ * number admitted (0 when no column is free), or a negative hd_status.
+ */
+int hd_serve_submit(hd_server *srv, int32_t n, const float *q_desc, const int32_t *y_ids,
+                    const float *y_val, const int32_t *max_iter, int64_t *tickets);
+
+/* Queue `iters` CG iterations over all columns on the server's stream and
+ * return at once (HD_OK or a negative hd_status); the next submit or poll
+ * waits for them. Steps of different servers therefore overlap on the GPU. */
+int hd_serve_step(hd_server *srv, int32_t iters);
+
+/*
+ * Collect up to max_out finished requests and free their columns. Per
+ * request (host arrays): tickets, the top_k ranking (ids and scores,
+ * max_out x top_k, best first, equal scores to the lower id; each may be
+ * NULL), CG iterations, final relative residual and hd_col_status. Returns
+ * the number collected, or a negative hd_status.
+ */
+int hd_serve_poll(hd_server *srv, int32_t max_out, int64_t *tickets, int32_t *ids, float *scores,
+                  int32_t *iters, double *relres, int32_t *status);
+
+/* Release the server's device memory and stream. NULL is accepted. */
+void hd_serve_close(hd_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

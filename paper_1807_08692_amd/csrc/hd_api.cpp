@@ -10,180 +10,11 @@
 //                                 scalars, R, X, P updates (k_cg_*)
 //                  stopping test read back once per iteration
 //   4. x = U1 Cs + X, transposed to query-major; top-K     (k_combine, k_topk)
-#include <hip/hip_runtime.h>
+#include "hd_internal.h"
 
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "../../include/hd.h"
-#include "hd_kernels.h"
-
-namespace {
-
+namespace hdi {
 thread_local std::string g_err;
-
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
-#define HIP_TRY(call)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (call);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(e_ == hipErrorOutOfMemory ? HD_ENOMEM : HD_EDEVICE, "%s: %s",   \
-                        #call, hipGetErrorString(e_));                                  \
-    } while (0)
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    // Grow-only: keeps the allocation when it is already large enough.
-    hipError_t ensure(size_t want) {
-        if (want <= bytes && p) return hipSuccess;
-        release();
-        if (want == 0) want = 256;
-        hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) bytes = want;
-        return e;
-    }
-    template <class T>
-    T *as() const { return reinterpret_cast<T *>(p); }
-};
-
-// fp32 -> bfloat16 bit pattern, round to nearest even (inputs are finite).
-uint16_t bf16_rne_host(float f) {
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-int pow2_at_least(int v) {
-    int p = 64;
-    while (p < v) p <<= 1;
-    return p;
-}
-
-// Kernel kinds for the optional per-launch event timing.
-enum Kind {
-    K_SIM, K_TOPK_Y, K_FILL, K_SCATTER, K_COLSQ, K_SCALAR, K_GATHER, K_UT_P, K_REDUCE_C,
-    K_U_C, K_SPMM, K_UPDATE_R, K_UPDATE_XP, K_COMBINE, K_TOPK_RANK, K_NKINDS
-};
-const char *const kKindNames[K_NKINDS] = {
-    "sim", "topk_y", "fill_zero", "scatter_y", "colsq", "cg_scalar", "gather_proj", "ut_p",
-    "reduce_c", "u_c", "spmm", "update_r", "update_xp", "combine", "topk_rank"};
-
-struct Timing {
-    bool on = false;
-    uint32_t mask = ~0u;  // kinds that get events while on
-    std::vector<hipEvent_t> pool;
-    size_t used = 0;
-    struct Pending {
-        int kind;
-        size_t ev;
-        int iter;  // CG iteration the launch belongs to (0 = none)
-    };
-    std::vector<Pending> pending;
-    int tag = 0;  // iteration of the launches being queued
-    double total_ms[K_NKINDS] = {};
-    int64_t count[K_NKINDS] = {};
-
-    void reset() {
-        for (int k = 0; k < K_NKINDS; ++k) {
-            total_ms[k] = 0.0;
-            count[k] = 0;
-        }
-        pending.clear();
-        used = 0;
-    }
-    hipError_t begin(hipStream_t s, size_t *idx) {
-        if (used + 2 > pool.size()) {
-            for (int t = 0; t < 64; ++t) {
-                hipEvent_t e;
-                hipError_t err = hipEventCreate(&e);
-                if (err != hipSuccess) return err;
-                pool.push_back(e);
-            }
-        }
-        *idx = used;
-        used += 2;
-        return hipEventRecord(pool[*idx], s);
-    }
-    hipError_t end(int kind, size_t idx, hipStream_t s) {
-        pending.push_back({kind, idx, tag});
-        return hipEventRecord(pool[idx + 1], s);
-    }
-    // Call after the stream has been synchronised. Launches of iterations
-    // after last_iter were queued ahead and returned at once; they are not
-    // counted.
-    hipError_t harvest(int last_iter) {
-        for (auto &pk : pending) {
-            if (pk.iter > last_iter) continue;
-            float ms = 0.f;
-            hipError_t e = hipEventElapsedTime(&ms, pool[pk.ev], pool[pk.ev + 1]);
-            if (e != hipSuccess) return e;
-            total_ms[pk.kind] += ms;
-            count[pk.kind] += 1;
-        }
-        pending.clear();
-        used = 0;
-        return hipSuccess;
-    }
-    void destroy() {
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-        pool.clear();
-    }
-};
-
-}  // namespace
-
-struct hd_ctx {
-    int device = 0;
-    // graph
-    int64_t n = 0, nnz = 0;
-    DevBuf rowptr, col, val;
-    // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp) + UbT (bf16, rp x ldut)
-    int r = 0, rp = 0, u_dtype = HD_F32;
-    int64_t ldut = 0;
-    DevBuf U, Ub, UbT, lam;
-    // descriptors: V (fp32) or Vb (bf16), N x ldv
-    int d = 0, ldv = 0, v_dtype = HD_F32;
-    DevBuf V, Vb;
-    // solver workspace
-    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, part, scal, xbuf, sim, ybuf, topk, err, qsplit;
-    int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
-    hipEvent_t iter_ev[2] = {nullptr, nullptr};
-    hd::CgState st{};
-    Timing timing;
-};
-
-// Launch `call` (a launcher returning hipError_t) as kernel kind `kind`,
-// bracketed by timing events when timing is on.
-#define LAUNCH(kind, call)                                                        \
-    do {                                                                          \
-        size_t ev_ = 0;                                                           \
-        const bool tm_ = c->timing.on && ((c->timing.mask >> (kind)) & 1u);       \
-        if (tm_) HIP_TRY(c->timing.begin(s, &ev_));                               \
-        HIP_TRY(call);                                                            \
-        if (tm_) HIP_TRY(c->timing.end(kind, ev_, s));                            \
-    } while (0)
+}  // namespace hdi
 
 static int64_t ctx_bytes(const hd_ctx *c) {
     const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->V,
@@ -529,6 +360,7 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         st.iters = reinterpret_cast<int32_t *>(b); b += ldb * sizeof(int32_t);
         st.status = reinterpret_cast<int32_t *>(b); b += ldb * sizeof(int32_t);
         st.nact_part = reinterpret_cast<int32_t *>(b);
+        st.maxit = nullptr;  // the host loop applies max_iter to every column
     }
     const hd::CgState st = c->st;
 

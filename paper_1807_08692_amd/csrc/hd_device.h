@@ -55,6 +55,7 @@ __device__ __forceinline__ float rank_key_score(uint64_t k) {
 // iteration returns at once then, so the host can queue an iteration before
 // it knows whether it is needed.
 __device__ __forceinline__ bool all_stopped(const int32_t *nact, int ntile) {
+    if (nact == nullptr) return false;
     int s = 0;
     for (int t = 0; t < ntile; ++t) s += nact[t];
     return s == 0;

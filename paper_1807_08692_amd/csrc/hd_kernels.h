@@ -19,6 +19,7 @@ namespace hd {
 struct CgState {
     double *rho0, *rho, *a, *beta, *relres;
     int32_t *active, *iters, *status;
+    int32_t *maxit;      // per-column iteration cap (nullptr: none, the host stops)
     int32_t *nact_part;  // [2][64]: active-column count per 64-column tile,
                          // double buffered by iteration parity
 };
@@ -40,8 +41,10 @@ RowPart make_row_part(int64_t N);
 
 // ---- CG vector kernels (k_cg.hip) ----
 hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s);
+// colmap (nullptr = identity): y row t goes to solver column colmap[t]
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                            int ldb, float *R, float *P, int32_t *err, hipStream_t s);
+                            int ldb, float *R, float *P, int32_t *err, hipStream_t s,
+                            const int32_t *colmap = nullptr);
 hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
                              hipStream_t s);
 hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s);
@@ -57,9 +60,23 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
                             IterGuard g, hipStream_t s);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 // U is fp32 (u_bf16 = 0) or bf16 bit patterns (u_bf16 = 1), item-major N x rp.
+// colmap (nullptr = identity, B columns of ldb): y row t -> column colmap[t]
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const void *U, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
+                              hipStream_t s, const int32_t *colmap = nullptr);
+
+// ---- continuous batching (columns joining and leaving a running solve) ----
+// zero columns cols[0..ncols) of X, R and P
+hipError_t launch_zero_cols(int64_t N, int ldb, float *X, float *R, float *P, const int32_t *cols,
+                            int ncols, hipStream_t s);
+// start the CG recurrence of columns cols[0..ncols) from the R^T R partials:
+// rho0 = rho = y^T y, iteration 0, cap maxit[t] (written to st.maxit)
+hipError_t launch_init_cols(int ldb, const double *part, int nblk, CgState st, const int32_t *cols,
+                            const int32_t *maxit, int ncols, hipStream_t s);
+// Xc (N x ldc node-major) and Csc (rk x ldc) = the columns cols[0..ncols) of X and Cs
+hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *Cs, int rk,
+                              const int32_t *cols, int ncols, int ldc, float *Xc, float *Csc,
                               hipStream_t s);
 
 // ---- sparse product (k_spmm.hip) ----

@@ -53,10 +53,11 @@ hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s) {
 // [0, N) are skipped and flagged in *err.
 __global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32_t *ids,
                                                       const float *vals, int64_t N, int ldb,
-                                                      float *R, float *P, int32_t *err) {
+                                                      float *R, float *P, int32_t *err,
+                                                      const int32_t *colmap) {
     int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= B * ky) return;
-    int b = idx / ky;
+    int b = colmap ? colmap[idx / ky] : idx / ky;
     int id = ids[idx];
     if (id < 0 || (int64_t)id >= N) {
         atomicOr(err, 1);
@@ -69,10 +70,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32
 }
 
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                            int ldb, float *R, float *P, int32_t *err, hipStream_t s) {
+                            int ldb, float *R, float *P, int32_t *err, hipStream_t s,
+                            const int32_t *colmap) {
     int tot = B * ky;
     if (tot == 0) return hipSuccess;
-    k_scatter_y<<<(tot + kBlock - 1) / kBlock, kBlock, 0, s>>>(B, ky, ids, vals, N, ldb, R, P, err);
+    k_scatter_y<<<(tot + kBlock - 1) / kBlock, kBlock, 0, s>>>(B, ky, ids, vals, N, ldb, R, P, err,
+                                                                colmap);
     return hipGetLastError();
 }
 
@@ -280,7 +283,8 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const dou
     if (threadIdx.x < kWave) {
         int act = st.active[c];
         if (act) {
-            st.iters[c] += 1;
+            const int it = st.iters[c] + 1;
+            st.iters[c] = it;
             double rel = sqrt(rho_new / st.rho0[c]);
             if (rel <= tol) {
                 st.status[c] = COL_CONVERGED;
@@ -288,6 +292,10 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const dou
                 act = 0;
             } else {
                 st.beta[c] = rho_new / st.rho[c];
+                if (st.maxit && it >= st.maxit[c]) {  // per-column cap: status stays MAXITER
+                    st.active[c] = 0;
+                    act = 0;
+                }
             }
             st.rho[c] = rho_new;
         }
@@ -382,10 +390,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
                                                         const float *vals, int64_t N,
                                                         const UT *U, int rp, int rk, int r_use,
                                                         const double *lam, double alpha, int ldb,
-                                                        float *Cs, float *Cl) {
+                                                        float *Cs, float *Cl,
+                                                        const int32_t *colmap) {
     int k = blockIdx.x * kBlock + threadIdx.x;
-    int b = blockIdx.y;
+    int b = blockIdx.y;  // y row; its solver column is colmap[b] (or b)
     if (k >= rk) return;
+    if (colmap && b >= B) return;
+    const int col = colmap ? colmap[b] : b;
     double acc = 0.0;
     if (k < r_use && b < B) {
         for (int t = 0; t < ky; ++t) {
@@ -396,25 +407,112 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
     double lk = k < r_use ? lam[k] : 0.0;
     double h = (1.0 - alpha) / (1.0 - alpha * lk);
     double g = h - (1.0 - alpha);
-    Cs[(size_t)k * ldb + b] = (float)(g * acc);
-    Cl[(size_t)k * ldb + b] = (float)(lk * acc);
+    Cs[(size_t)k * ldb + col] = (float)(g * acc);
+    if (Cl) Cl[(size_t)k * ldb + col] = (float)(lk * acc);
 }
 
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const void *U, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                              hipStream_t s) {
+                              hipStream_t s, const int32_t *colmap) {
     if (rk == 0) return hipSuccess;
-    dim3 grid((rk + kBlock - 1) / kBlock, ldb);
+    dim3 grid((rk + kBlock - 1) / kBlock, colmap ? B : ldb);
     if (u_bf16) {
         k_gather_proj<unsigned short><<<grid, kBlock, 0, s>>>(
             B, ky, ids, vals, N, reinterpret_cast<const unsigned short *>(U), rp, rk, r_use, lam,
-            alpha, ldb, Cs, Cl);
+            alpha, ldb, Cs, Cl, colmap);
     } else {
         k_gather_proj<float><<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N,
                                                      reinterpret_cast<const float *>(U), rp, rk,
-                                                     r_use, lam, alpha, ldb, Cs, Cl);
+                                                     r_use, lam, alpha, ldb, Cs, Cl, colmap);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Continuous batching: a server keeps one solve running over ldb columns and
+// lets requests join (admission) and leave (retirement) between iterations.
+// Each column is its own CG recurrence, so a request's arithmetic is the same
+// whatever else shares the batch.
+
+__global__ __launch_bounds__(kBlock) void k_zero_cols(int64_t N, int ldb, float *X, float *R,
+                                                      float *P, const int32_t *cols, int ncols) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    for (int t = 0; t < ncols; ++t) {
+        const size_t o = (size_t)i * ldb + cols[t];
+        X[o] = 0.f;
+        R[o] = 0.f;
+        P[o] = 0.f;
+    }
+}
+
+hipError_t launch_zero_cols(int64_t N, int ldb, float *X, float *R, float *P, const int32_t *cols,
+                            int ncols, hipStream_t s) {
+    if (ncols == 0) return hipSuccess;
+    k_zero_cols<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, s>>>(N, ldb, X, R, P, cols, ncols);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kScalarThreads) void k_init_cols(int ldb, const double *part, int nblk,
+                                                              CgState st, const int32_t *cols,
+                                                              const int32_t *maxit, int ncols) {
+    const int lane = threadIdx.x % kWave;
+    const int c = blockIdx.x * kWave + lane;
+    const double rho0 = tile_reduce(part, nblk, ldb, c);
+    if (threadIdx.x < kWave) {
+        int t = -1;
+        for (int q = 0; q < ncols; ++q)
+            if (cols[q] == c) t = q;
+        if (t >= 0) {
+            int act = 0, stat;
+            if (rho0 == 0.0) {
+                stat = COL_ZERO_RHS;
+            } else if (!(rho0 > 0.0) || !isfinite(rho0)) {
+                stat = COL_BREAKDOWN;
+            } else {
+                stat = COL_MAXITER;
+                act = maxit[t] > 0 ? 1 : 0;
+            }
+            st.rho0[c] = rho0 == 0.0 ? 0.0 : rho0;
+            st.rho[c] = rho0;
+            st.a[c] = 0.0;
+            st.beta[c] = 0.0;
+            st.relres[c] = rho0 > 0.0 ? 1.0 : 0.0;
+            st.active[c] = act;
+            st.iters[c] = 0;
+            st.status[c] = stat;
+            st.maxit[c] = maxit[t];
+        }
+    }
+}
+
+hipError_t launch_init_cols(int ldb, const double *part, int nblk, CgState st, const int32_t *cols,
+                            const int32_t *maxit, int ncols, hipStream_t s) {
+    if (ncols == 0) return hipSuccess;
+    k_init_cols<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, part, nblk, st, cols, maxit, ncols);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_cols(int64_t N, int ldb, const float *X,
+                                                        const float *Cs, int rk,
+                                                        const int32_t *cols, int ncols, int ldc,
+                                                        float *Xc, float *Csc) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < N)
+        for (int t = 0; t < ldc; ++t)
+            Xc[(size_t)i * ldc + t] = t < ncols ? X[(size_t)i * ldb + cols[t]] : 0.f;
+    if (i < rk)
+        for (int t = 0; t < ldc; ++t)
+            Csc[(size_t)i * ldc + t] = t < ncols ? Cs[(size_t)i * ldb + cols[t]] : 0.f;
+}
+
+hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *Cs, int rk,
+                              const int32_t *cols, int ncols, int ldc, float *Xc, float *Csc,
+                              hipStream_t s) {
+    const int64_t rows = N > rk ? N : rk;
+    k_gather_cols<<<(unsigned)((rows + kBlock - 1) / kBlock), kBlock, 0, s>>>(N, ldb, X, Cs, rk, cols,
+                                                                            ncols, ldc, Xc, Csc);
     return hipGetLastError();
 }
 

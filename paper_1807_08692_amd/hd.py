@@ -41,6 +41,14 @@ _SIGS = {
     "hd_timing_kinds": (ctypes.c_int, []),
     "hd_timing_name": (ctypes.c_char_p, [ctypes.c_int]),
     "hd_timing_get": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "hd_serve_open": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_void_p)]),
+    "hd_serve_column_bytes": (ctypes.c_int64, [_P, _P]),
+    "hd_serve_slots": (ctypes.c_int, [_P]),
+    "hd_serve_in_use": (ctypes.c_int, [_P]),
+    "hd_serve_submit": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "hd_serve_step": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "hd_serve_poll": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
+    "hd_serve_close": (None, [_P]),
 }
 
 
@@ -225,3 +233,84 @@ class Context:
         _check(lib().hd_rank(self._h, B, n, _dptr(x), ldx, int(K), _dptr(ids), _dptr(scores),
                              _stream_ptr(stream)))
         return ids, scores
+
+
+class Server:
+    """Continuous-batching server on a context (hd_serve_*). Requests are
+    host arrays; results come back as host arrays."""
+
+    def __init__(self, ctx: Context, slots: int, *, hbm_budget_bytes: int = 0, alpha=0.99,
+                 max_iter=20, tol=1e-6, rank_r=-1, k_y=10, top_k=100):
+        o = hd_query_opts(float(alpha), int(max_iter), float(tol), int(rank_r), int(k_y), int(top_k))
+        h = ctypes.c_void_p()
+        _check(lib().hd_serve_open(ctx._h, int(slots), int(hbm_budget_bytes), ctypes.byref(o),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx  # keeps the context alive
+        self.k_y = int(k_y)
+        self.top_k = int(top_k)
+
+    @staticmethod
+    def column_bytes(ctx: Context, *, alpha=0.99, max_iter=20, tol=1e-6, rank_r=-1, k_y=10, top_k=100) -> int:
+        o = hd_query_opts(float(alpha), int(max_iter), float(tol), int(rank_r), int(k_y), int(top_k))
+        return int(lib().hd_serve_column_bytes(ctx._h, ctypes.byref(o)))
+
+    @property
+    def slots(self) -> int:
+        return int(lib().hd_serve_slots(self._h))
+
+    @property
+    def in_use(self) -> int:
+        return int(lib().hd_serve_in_use(self._h))
+
+    def submit(self, y_ids=None, y_val=None, q_desc=None, max_iter=None):
+        """Admit requests into free columns; returns the tickets of the
+        admitted prefix (length = number admitted)."""
+        if q_desc is not None:
+            q, qp = _host(q_desc, np.float32)
+            n = q.shape[0]
+            ip = vp = None
+        else:
+            yi, ip = _host(y_ids, np.int32)
+            yv, vp = _host(y_val, np.float32)
+            n = yi.shape[0]
+            qp = None
+        mp = None
+        if max_iter is not None:
+            mi, mp = _host(np.broadcast_to(np.asarray(max_iter, np.int32), (n,)), np.int32)
+        tickets = np.zeros(max(n, 1), np.int64)
+        got = lib().hd_serve_submit(self._h, n, qp, ip, vp, mp, tickets.ctypes.data_as(_P))
+        if got < 0:
+            _check(got)
+        return tickets[:got]
+
+    def step(self, iters: int = 1):
+        _check(lib().hd_serve_step(self._h, int(iters)))
+
+    def poll(self, max_out: int = 1024):
+        """Finished requests: dict of arrays keyed tickets, ids, scores,
+        iters, relres, status (ids / scores: n x top_k)."""
+        t = np.zeros(max_out, np.int64)
+        ids = np.zeros((max_out, self.top_k), np.int32)
+        sc = np.zeros((max_out, self.top_k), np.float32)
+        it = np.zeros(max_out, np.int32)
+        rr = np.zeros(max_out, np.float64)
+        st = np.zeros(max_out, np.int32)
+        got = lib().hd_serve_poll(self._h, int(max_out), t.ctypes.data_as(_P), ids.ctypes.data_as(_P),
+                                  sc.ctypes.data_as(_P), it.ctypes.data_as(_P), rr.ctypes.data_as(_P),
+                                  st.ctypes.data_as(_P))
+        if got < 0:
+            _check(got)
+        return dict(tickets=t[:got], ids=ids[:got], scores=sc[:got], iters=it[:got], relres=rr[:got],
+                    status=st[:got])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hd_serve_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

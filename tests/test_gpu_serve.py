@@ -1,0 +1,156 @@
+"""GPU tests of the continuous-batching server: a request gives the same
+result alone and in a busy server (joining while other columns are mid-way
+through their solves), matches the batch path and the oracle, honours its own
+iteration cap, and the HBM budget sets the column count."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1807_08692_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def fx():
+    return W.build_fixture(W.CONFIGS["n5k"], n_queries=40, prefer_gpu=False)
+
+
+@pytest.fixture(scope="module")
+def ctx(fx, torch_dev):
+    from paper_1807_08692_amd import hd
+    c = hd.Context(0)
+    c.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    c.load_eigs(fx.U, fx.lam)
+    c.load_descriptors(fx.V)
+    yield c
+    c.close()
+
+
+def ys(fx, idx):
+    ids, vals = [], []
+    for q in fx.Q[idx]:
+        i, v = O.observation(fx.V, q, fx.cfg.k_y)
+        ids.append(i)
+        vals.append(v)
+    return np.stack(ids).astype(np.int32), np.stack(vals).astype(np.float32)
+
+
+def drain(srv, want, results, max_steps=200):
+    for _ in range(max_steps):
+        if len(results) >= want:
+            return
+        srv.step(1)
+        res = srv.poll()
+        for k, t in enumerate(res["tickets"]):
+            results[int(t)] = {key: res[key][k] for key in ("ids", "scores", "iters", "relres", "status")}
+    raise AssertionError("server did not finish")
+
+
+def test_alone_equals_in_mix(fx, ctx):
+    from paper_1807_08692_amd import hd
+    ids, vals = ys(fx, np.arange(30))
+    kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+    with_alone = {}
+    srv = hd.Server(ctx, 32, **kw)
+    t = srv.submit(ids[7:8], vals[7:8])
+    drain(srv, 1, with_alone)
+    alone = with_alone[int(t[0])]
+    srv.close()
+    # busy server: 12 requests start, two steps later 18 more join (incl. #7)
+    srv = hd.Server(ctx, 32, **kw)
+    res = {}
+    t_first = srv.submit(ids[:7], vals[:7])
+    srv.submit(ids[8:13], vals[8:13])
+    srv.step(2)
+    t_join = srv.submit(ids[7:8], vals[7:8])
+    srv.submit(ids[13:30], vals[13:30])
+    assert srv.in_use == 30
+    drain(srv, 30, res)
+    mixed = res[int(t_join[0])]
+    assert np.array_equal(mixed["ids"], alone["ids"])
+    assert np.array_equal(mixed["scores"], alone["scores"])
+    assert mixed["iters"] == alone["iters"]
+    assert srv.in_use == 0
+    srv.close()
+
+
+def test_server_matches_batch_and_oracle(fx, ctx, torch_dev):
+    import torch
+    from paper_1807_08692_amd import hd
+    ids, vals = ys(fx, np.arange(5))
+    kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+    srv = hd.Server(ctx, 8, **kw)
+    tk = srv.submit(ids, vals)
+    res = {}
+    drain(srv, 5, res)
+    srv.close()
+    out = ctx.query_batch(None, torch.from_numpy(ids).to(torch_dev), torch.from_numpy(vals).to(torch_dev),
+                          want_x=True, **kw)
+    torch.cuda.synchronize()
+    g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
+    for b in range(5):
+        r = res[int(tk[b])]
+        assert r["iters"] == out["iters"][b] and r["status"] == O.CONVERGED
+        xo, *_ = O.iterate(g, fx.U, fx.lam, 0.99, ids[b], vals[b], int(r["iters"]), 0.0)
+        # scores of the ranked items agree with the oracle's x
+        assert np.allclose(r["scores"], xo[r["ids"]], rtol=2e-4, atol=1e-9 * np.abs(xo).max())
+        # and with the batch path (same rounding up to the first product's coefficients)
+        assert np.allclose(r["scores"], out["rank_scores"].cpu().numpy()[b], rtol=1e-5, atol=1e-12)
+
+
+def test_per_request_cap_and_descriptors(fx, ctx):
+    from paper_1807_08692_amd import hd
+    srv = hd.Server(ctx, 16, alpha=0.99, max_iter=20, tol=1e-6, rank_r=-1, k_y=fx.cfg.k_y, top_k=20)
+    tk = srv.submit(q_desc=fx.Q[:6], max_iter=[2, 0, 20, 5, 20, 1])
+    res = {}
+    drain(srv, 6, res)
+    got = [res[int(t)] for t in tk]
+    assert [r["iters"] for r in got[:2]] == [2, 0]
+    assert got[0]["status"] == O.MAXITER and got[1]["status"] == O.MAXITER
+    assert got[2]["status"] == O.CONVERGED
+    assert got[3]["iters"] == 5 and got[5]["iters"] == 1
+    srv.close()
+
+
+def test_hbm_budget_sets_columns(fx, ctx):
+    from paper_1807_08692_amd import hd
+    with pytest.raises(hd.HDError):
+        hd.Server(ctx, 64, hbm_budget_bytes=1 << 20, k_y=fx.cfg.k_y, top_k=10)
+    big = hd.Server(ctx, 512, k_y=fx.cfg.k_y, top_k=10)
+    assert big.slots == 512
+    big.close()
+    col = hd.Server.column_bytes(ctx, k_y=fx.cfg.k_y, top_k=10)
+    assert col > 20 * fx.n  # at least the five solver vectors
+    for budget_cols, want in ((100, 64), (300, 256), (5000, 512)):
+        s = hd.Server(ctx, 512, hbm_budget_bytes=budget_cols * col, k_y=fx.cfg.k_y, top_k=10)
+        assert s.slots == want
+        s.close()
+    with pytest.raises(hd.HDError):
+        hd.Server(ctx, 512, hbm_budget_bytes=63 * col, k_y=fx.cfg.k_y, top_k=10)
+
+
+def test_request_loop_poisson(fx, ctx):
+    """The serving loop over two servers (plain CG and hybrid on the same
+    graph): every request finishes, with latencies measured."""
+    from paper_1807_08692_amd import hd, serve
+    ids, vals = ys(fx, np.arange(40))
+    arr = serve.poisson_arrivals(2000.0, 40, seed=3)
+    reqs = [serve.Request(i, float(arr[i]), "plain" if i % 2 else "hybrid", ids[i], vals[i], max_iter=100)
+            for i in range(40)]
+    servers = {"plain": hd.Server(ctx, 16, rank_r=0, k_y=fx.cfg.k_y, top_k=10, tol=1e-6),
+               "hybrid": hd.Server(ctx, 16, rank_r=50, k_y=fx.cfg.k_y, top_k=10, tol=1e-6)}
+    reqs, wall = serve.run(servers, reqs)
+    st = serve.latency_stats(reqs)
+    assert st["count"] == 40 and all(r.finished >= r.arrival for r in reqs)
+    assert all(r.result["status"] == O.CONVERGED for r in reqs)
+    for s in servers.values():
+        s.close()
