@@ -57,7 +57,9 @@ typedef enum {
 typedef enum {
     HD_F32 = 0,
     HD_BF16 = 1,          /* bfloat16, rounded to nearest even from the fp32 input */
-    HD_FP8_E4M3 = 2       /* OCP e4m3 with one fp32 scale per column (U1) or row (V) */
+    HD_FP8_E4M3 = 2,      /* OCP e4m3 with one fp32 scale per column (U1) or row (V) */
+    HD_BF16X2 = 3         /* U1 only: two bfloat16 terms hi + lo, hi = RNE(u),
+                             lo = RNE(u - hi) (about 16 significant bits) */
 } hd_dtype;
 
 /* hd_load_graph flags. */
@@ -104,7 +106,9 @@ int hd_load_graph(hd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr,
  * storage precision on the device: HD_F32, or HD_BF16 (U rounded to
  * nearest-even bfloat16 and kept twice, item-major and component-major; the
  * products multiply it with the fp32 operand split into two bfloat16 parts
- * and accumulate in fp32). r = 0 unloads. Queries may use any prefix of the
+ * and accumulate in fp32), or HD_BF16X2 (U kept as two bfloat16 terms in
+ * both layouts, products over three bfloat16 terms, accuracy close to fp32
+ * at twice the bytes of HD_BF16). r = 0 unloads. Queries may use any prefix of the
  * loaded columns (hd_query_opts.rank_r).
  * Errors: HD_ESTATE (no graph), HD_EINVAL (r < 0, r > n, lambda outside
  * [-1, 1] or non-finite, non-finite U, unknown dtype).
@@ -113,12 +117,43 @@ int hd_load_eigs(hd_ctx *ctx, int32_t r, const float *U, const double *lambda,
                  int32_t dtype);
 
 /*
+ * Launch parameters of the hot kernels: the search space of hd_autotune.
+ * Value 0 selects the built-in default; a value that does not fit the
+ * solver width of a call (1, 2 or 4, dividing the width in 64-column units)
+ * falls back to the default for that call.
+ */
+typedef enum {
+    HD_TUNE_SPMM_CPL = 0,  /* sparse product: query columns per lane (1, 2, 4) */
+    HD_TUNE_UTP_NT = 1,    /* U1^T P, bfloat16 forms: 16-column tiles per wave */
+    HD_TUNE_UC_NT = 2,     /* U1 C and the final combine, bfloat16 forms: same */
+    HD_TUNE_NKEYS = 3
+} hd_tune_key;
+
+/* Set / read one launch parameter. Errors: HD_EINVAL (key, value not in
+ * {0, 1, 2, 4}, NULL). */
+int hd_set_tuning(hd_ctx *ctx, int32_t key, int32_t value);
+int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
+
+/*
+ * Autotuner (batching form): for batches of `batch` queries, time every
+ * valid value of each launch parameter on the loaded graph and eigenvectors
+ * (one warm-up and `reps` timed launches each, on device scratch vectors of
+ * the solver width, on the null stream) and keep the fastest in the
+ * context. times_ms (host, may be NULL) receives HD_TUNE_NKEYS x 3 mean
+ * launch times in ms for the values 1, 2, 4 (-1 where a value does not fit
+ * or the kernel is not used: no eigenvectors, or fp32 storage).
+ * Synchronous. Errors: HD_ESTATE (no graph), HD_EINVAL (batch not in
+ * [1, 1024], reps not in [1, 1000]).
+ */
+int hd_autotune(hd_ctx *ctx, int32_t batch, int32_t reps, double *times_ms);
+
+/*
  * Load the database descriptors used to build y from query descriptors
  * (Section 3: nearest neighbours of the query in the dataset). V (host,
  * fp32, n x d row-major, unit-norm rows so that the dot product is the
  * cosine). `dtype` selects the device storage: HD_F32, or HD_BF16 (rounded to
  * nearest even; the query descriptors stay fp32 and are split into two
- * bfloat16 parts for the product).
+ * bfloat16 parts for the product). HD_BF16X2 is not accepted here.
  * Errors: HD_ESTATE (no graph), HD_EINVAL (d <= 0, non-finite V, dtype).
  */
 int hd_load_descriptors(hd_ctx *ctx, int32_t d, const float *V, int32_t dtype);

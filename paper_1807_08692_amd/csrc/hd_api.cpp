@@ -19,7 +19,7 @@ thread_local std::string g_err;
 static int64_t ctx_bytes(const hd_ctx *c) {
     const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
-                           &c->ClT, &c->CsT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
+                           &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
                            &c->topk, &c->err, &c->qsplit};
     int64_t s = 0;
     for (const DevBuf *b : all) s += (int64_t)b->bytes;
@@ -66,7 +66,7 @@ void hd_destroy(hd_ctx *c) {
     (void)hipDeviceSynchronize();
     DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
-                     &c->ClT, &c->CsT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
+                     &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
                      &c->topk, &c->err, &c->qsplit};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
@@ -196,7 +196,7 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
     if (!c) return fail(HD_EINVAL, "hd_load_eigs: NULL context");
     if (c->n == 0) return fail(HD_ESTATE, "hd_load_eigs: no graph loaded");
     if (r < 0 || r > c->n) return fail(HD_EINVAL, "hd_load_eigs: r=%d not in [0, n]", r);
-    if (dtype != HD_F32 && dtype != HD_BF16)
+    if (dtype != HD_F32 && dtype != HD_BF16 && dtype != HD_BF16X2)
         return fail(HD_EINVAL, "hd_load_eigs: dtype %d not supported", dtype);
     HIP_TRY(hipSetDevice(c->device));
     c->U.release();
@@ -227,13 +227,25 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
         HIP_TRY(c->U.ensure(host.size() * sizeof(float)));
         HIP_TRY(hipMemcpy(c->U.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
     } else {
+        // hi terms first; the two-term form appends the lo terms (same layout)
         const int64_t ldut = (n + 63) / 64 * 64;
-        std::vector<uint16_t> im((size_t)n * rp, 0), cm((size_t)rp * ldut, 0);
+        const int terms = dtype == HD_BF16X2 ? 2 : 1;
+        const size_t imn = (size_t)n * rp, cmn = (size_t)rp * ldut;
+        std::vector<uint16_t> im(imn * terms, 0), cm(cmn * terms, 0);
         for (int64_t i = 0; i < n; ++i)
             for (int k = 0; k < r; ++k) {
-                const uint16_t h = bf16_rne_host(U[(size_t)i * r + k]);
+                const float u = U[(size_t)i * r + k];
+                const uint16_t h = bf16_rne_host(u);
                 im[(size_t)i * rp + k] = h;
                 cm[(size_t)k * ldut + i] = h;
+                if (terms == 2) {
+                    float hf;
+                    const uint32_t hb = (uint32_t)h << 16;
+                    std::memcpy(&hf, &hb, sizeof(hf));
+                    const uint16_t l = bf16_rne_host(u - hf);
+                    im[imn + (size_t)i * rp + k] = l;
+                    cm[cmn + (size_t)k * ldut + i] = l;
+                }
             }
         HIP_TRY(c->Ub.ensure(im.size() * sizeof(uint16_t)));
         HIP_TRY(c->UbT.ensure(cm.size() * sizeof(uint16_t)));
@@ -340,9 +352,10 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
         HIP_TRY(c->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         HIP_TRY(c->Cs.ensure((size_t)rk * ldb * sizeof(float)));
-        if (c->u_dtype == HD_BF16) {
+        if (c->u_dtype != HD_F32) {
             HIP_TRY(c->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
             HIP_TRY(c->CsT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
+            HIP_TRY(c->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
         }
     }
     HIP_TRY(c->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
@@ -409,14 +422,17 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     if (c->h_pinned[200] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
 
     // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
-    const bool ubf = c->u_dtype == HD_BF16;
+    const bool ubf = c->u_dtype != HD_F32;
+    const bool two = c->u_dtype == HD_BF16X2;
     const float *U = c->U.as<float>();
     const uint16_t *Ub = c->Ub.as<uint16_t>(), *UbT = c->UbT.as<uint16_t>();
+    const uint16_t *Ubl = two ? Ub + (size_t)n * c->rp : nullptr;
+    const uint16_t *UbTl = two ? UbT + (size_t)c->rp * c->ldut : nullptr;
     uint16_t *ClT_hi = c->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
     uint16_t *CsT_hi = c->CsT.as<uint16_t>(), *CsT_lo = CsT_hi ? CsT_hi + (size_t)rk * ldb : nullptr;
     if (rk > 0) {
         LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, ubf ? (const void *)Ub : (const void *)U,
-                                                ubf ? 1 : 0, c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
+                                                Ubl, ubf ? 1 : 0, c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
                                                 ldb, c->Cs.as<float>(), c->Cl.as<float>(), s));
         if (ubf) {
             const hd::IterGuard none{nullptr, 0};
@@ -440,7 +456,10 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         if (rk > 0) {
             if (it > 1) {
                 if (ubf) {
-                    LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, c->ldut, rk, P, ldb, c->Cpart.as<float>(), g, s));
+                    // PT was written by the previous iteration's update_xp
+                    uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
+                    LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb,
+                                                        c->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
                 } else {
                     LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), g, s));
                 }
@@ -449,19 +468,25 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
                 if (ubf) LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
             }
             if (ubf) {
-                LAUNCH(K_U_C, hd::launch_u_c_bf16(n, Ub, c->rp, rk, ClT_hi, ClT_lo, ldb, P, o->alpha,
-                                                  c->Z.as<float>(), g, s));
+                LAUNCH(K_U_C, hd::launch_u_c_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, P, o->alpha,
+                                                  c->Z.as<float>(), g, s, c->tv(HD_TUNE_UC_NT, ldb)));
             } else {
                 LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), g, s));
             }
             Zs = c->Z.as<float>();
         }
         LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
-                                       ldb, o->alpha, rp, c->part.as<double>(), g, s));
+                                       ldb, o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb)));
         LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s));
         LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), g, s));
         LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, g, nact_dev[it & 1], s));
-        LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s));
+        if (ubf && rk > 0) {
+            uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
+            LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut,
+                                                        PTh, PTl, g, s));
+        } else {
+            LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s));
+        }
         HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(c->iter_ev[it & 1], s));
@@ -494,7 +519,8 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     }
     if (x_out || o->top_k > 0) {
         if (ubf && rk > 0) {
-            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, Ub, c->rp, rk, CsT_hi, CsT_lo, ldb, X, xq, n, s));
+            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, Ub, Ubl, c->rp, rk, CsT_hi, CsT_lo, ldb, X, xq, n, s,
+                                                        c->tv(HD_TUNE_UC_NT, ldb)));
         } else {
             LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, X, xq, n, s));
         }

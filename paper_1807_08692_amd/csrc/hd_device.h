@@ -20,6 +20,20 @@ __host__ __device__ __forceinline__ size_t vec_index(int64_t N, int ldb, int64_t
     return (size_t)i * (size_t)ldb + (size_t)b;
 }
 
+// Workgroups of a launch are dealt round-robin to the eight XCDs of the chip
+// (block b to XCD b % 8), and each XCD has its own L2. xcd_tile() turns the
+// hardware block id of a 1-D launch into a logical tile id such that every
+// XCD works through one contiguous range of logical ids. Kernels number
+// their tiles so that tiles sharing an operand are neighbours; those then run
+// on one XCD and share the operand through its L2 instead of each XCD
+// fetching it from memory.
+constexpr unsigned kXcd = 8;
+__device__ __forceinline__ unsigned xcd_tile() {
+    const unsigned h = blockIdx.x, n = gridDim.x;
+    const unsigned x = h % kXcd, slot = h / kXcd, q = n / kXcd, rem = n % kXcd;
+    return x * q + (x < rem ? x : rem) + slot;
+}
+
 // Broadcast lane `lane` (wave-uniform) of v to the whole wavefront.
 __device__ __forceinline__ int bcast_i(int v, int lane) {
     return __builtin_amdgcn_readlane(v, lane);

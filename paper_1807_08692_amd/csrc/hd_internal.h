@@ -155,7 +155,8 @@ struct hd_ctx {
     // graph
     int64_t n = 0, nnz = 0;
     DevBuf rowptr, col, val;
-    // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp) + UbT (bf16, rp x ldut)
+    // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp) + UbT (bf16, rp x ldut);
+    // the two-term form stores the lo terms after the hi terms of each
     int r = 0, rp = 0, u_dtype = HD_F32;
     int64_t ldut = 0;
     DevBuf U, Ub, UbT, lam;
@@ -163,11 +164,23 @@ struct hd_ctx {
     int d = 0, ldv = 0, v_dtype = HD_F32;
     DevBuf V, Vb;
     // solver workspace
-    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, part, scal, xbuf, sim, ybuf, topk, err, qsplit;
+    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, PT, part, scal, xbuf, sim, ybuf, topk, err, qsplit;
     int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
     hipEvent_t iter_ev[2] = {nullptr, nullptr};
     hd::CgState st{};
     Timing timing;
+    int tune[HD_TUNE_NKEYS] = {0, 0, 0};  // launch parameters (0 = default)
+
+    // second bfloat16 terms of the two-term U1 form (null otherwise)
+    const uint16_t *ub_lo() const {
+        return u_dtype == HD_BF16X2 ? Ub.as<uint16_t>() + (size_t)n * rp : nullptr;
+    }
+    const uint16_t *ubt_lo() const {
+        return u_dtype == HD_BF16X2 ? UbT.as<uint16_t>() + (size_t)rp * ldut : nullptr;
+    }
+    // launch parameter `key` for solver width ldb (0 = default when unset or
+    // not fitting the width)
+    int tv(int key, int ldb) const { return hd::tile_param_ok(tune[key], ldb) ? tune[key] : 0; }
 };
 
 // Launch `call` (a launcher returning hipError_t) as kernel kind `kind`,

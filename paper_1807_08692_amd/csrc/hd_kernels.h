@@ -58,11 +58,19 @@ hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, C
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
                             IterGuard g, hipStream_t s);
+// update_xp that also writes the new P as its split transpose (bfloat16
+// forms; PT_hi / PT_lo ldb x ldpt, ldpt a multiple of 64 >= N)
+hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
+                               const double *a, const double *beta, const int32_t *active,
+                               int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
+                               hipStream_t s);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 // U is fp32 (u_bf16 = 0) or bf16 bit patterns (u_bf16 = 1), item-major N x rp.
 // colmap (nullptr = identity, B columns of ldb): y row t -> column colmap[t]
+// U: fp32 (u_bf16 = 0) or bfloat16 (u_bf16 = 1, value U + U_lo when U_lo is
+// not null: the two-term storage form)
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                              const void *U, int u_bf16, int rp, int rk, int r_use,
+                              const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
                               hipStream_t s, const int32_t *colmap = nullptr);
 
@@ -84,7 +92,7 @@ hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *C
 // block g of P[i][c] * Q[i][c] (double).
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
-                       RowPart rp, double *gpart, IterGuard g, hipStream_t s);
+                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl = 0);
 
 // ---- eigenvector products on MFMA (k_ugemm.hip) ----
 // Number of row chunks of the split-K product U^T P.
@@ -103,22 +111,35 @@ hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, cons
                           int ldb, const float *X, float *x, int64_t ldx, hipStream_t s);
 
 // ---- bfloat16 storage form of the eigenvector and descriptor products
-//      (k_ugemm_bf16.hip); bf16 values are passed as their 16-bit patterns ----
+//      (k_ugemm_bf16.hip); bf16 values are passed as their 16-bit patterns.
+//      U_lo / UT_lo, when not null, hold the second bfloat16 term of the
+//      two-term form (U = U_hi + U_lo) in the same layout ----
 // CT_hi / CT_lo (ldb x rk, bf16) = hi / lo split of C^T (C: rk x ldb fp32).
 // A null g.nact disables the iteration guard.
 hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi,
                           unsigned short *CT_lo, IterGuard g, hipStream_t s);
-// Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT, rp x ldut)
-hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, int64_t ldut, int rk, const float *P,
-                            int ldb, float *Cpart, IterGuard g, hipStream_t s);
+// PT_hi / PT_lo (ldb x ldpt, bf16, item index contiguous, zero past N) =
+// hi / lo split of P^T (P: N x ldb fp32 node-major); ldpt a multiple of 64.
+hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
+                           unsigned short *PTl, IterGuard g, hipStream_t s);
+// Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT, rp x ldut,
+// zero past N) and P as its split transpose (PT_hi / PT_lo, pitch ldut)
+hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned short *UT_lo,
+                            int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
+                            int ldb, float *Cpart, IterGuard g, hipStream_t s, int nt = 0);
 // Z = P + alpha U Cl, U item-major (N x rp), Cl given as split transpose
-hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, int rp, int rk,
+hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp, int rk,
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
-                           const float *P, double alpha, float *Z, IterGuard g, hipStream_t s);
+                           const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
+                           int nt = 0);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
-hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, int rp, int rk,
+hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const unsigned short *U_lo,
+                               int rp, int rk,
                                const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
-                               const float *X, float *x, int64_t ldx, hipStream_t s);
+                               const float *X, float *x, int64_t ldx, hipStream_t s, int nt = 0);
+// Tile parameters: a requested value (0 = default) is valid for width ldb
+// when it is one of 1, 2, 4 and divides the width in 64-column units.
+bool tile_param_ok(int v, int ldb);
 // sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv); qsplit: scratch for
 // 2 x B x ldv bf16 (the hi / lo parts of q)
 hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsigned short *V,

@@ -20,7 +20,7 @@ struct Srv {
     hipStream_t s = nullptr;
     hd::RowPart rp{};
     int nchunk = 0;
-    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, part, scal, err, cols, maxit, xc, csc, cst, xq,
+    DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, PT, part, scal, err, cols, maxit, xc, csc, cst, xq,
         topk, rids, rsc, ybuf, qbuf, sim, qsplit;
     hd::CgState st{};
     int32_t *h = nullptr;  // pinned: [0,ldb) active, [ldb,2ldb) iters, [2ldb,3ldb) status, err
@@ -29,7 +29,7 @@ struct Srv {
     int64_t next_ticket = 1;
 
     void release() {
-        DevBuf *all[] = {&X, &R, &P, &Q, &Z, &Cpart, &Cl, &Cs, &ClT, &CsT, &part, &scal, &err, &cols,
+        DevBuf *all[] = {&X, &R, &P, &Q, &Z, &Cpart, &Cl, &Cs, &ClT, &CsT, &PT, &part, &scal, &err, &cols,
                          &maxit, &xc, &csc, &cst, &xq, &topk, &rids, &rsc, &ybuf, &qbuf, &sim,
                          &qsplit};
         for (DevBuf *b : all) b->release();
@@ -45,8 +45,10 @@ struct Srv {
 // Device bytes one solver column needs at n items (vectors X R P Q Z, the
 // coefficient columns, the partial sums and the ranking buffers).
 int64_t bytes_per_column(const hd_ctx *c, int rk, int nchunk, int nblk, int top_k, int ky) {
+    // X R P Q Z, the partial and full coefficient columns, reduction
+    // partials, the gathered x columns, the split P^T of the bfloat16 forms
     return 5 * 4 * c->n + (int64_t)4 * rk * (nchunk + 4) + 8 * nblk + 4 * c->n * 2 +
-           (int64_t)top_k * 8 + (int64_t)ky * 8 + 64;
+           (c->u_dtype != HD_F32 && rk > 0 ? 4 * c->ldut : 0) + (int64_t)top_k * 8 + (int64_t)ky * 8 + 64;
 }
 
 }  // namespace
@@ -121,6 +123,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
         SRV_TRY(v->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->Cs.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
+        if (c->u_dtype != HD_F32) SRV_TRY(v->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
         SRV_TRY(v->csc.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->cst.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
     }
@@ -247,9 +250,9 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     HIP_TRY(hd::launch_colsq_part(N, ldb, v->R.as<float>(), v->rp, v->part.as<double>(), s));
     HIP_TRY(hd::launch_init_cols(ldb, v->part.as<double>(), v->rp.nblk, v->st, cols, v->maxit.as<int32_t>(), m, s));
     if (v->rk > 0) {
-        const bool ubf = c->u_dtype == HD_BF16;
+        const bool ubf = c->u_dtype != HD_F32;
         HIP_TRY(hd::launch_gather_proj(m, ky, yi, yv, N, ubf ? (const void *)c->Ub.p : (const void *)c->U.p,
-                                       ubf ? 1 : 0, c->rp, v->rk, v->r_use, c->lam.as<double>(), v->o.alpha,
+                                       c->ub_lo(), ubf ? 1 : 0, c->rp, v->rk, v->r_use, c->lam.as<double>(), v->o.alpha,
                                        ldb, v->Cs.as<float>(), nullptr, s, cols));
     }
     HIP_TRY(hipMemcpyAsync(v->h + 3 * ldb, v->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -274,7 +277,7 @@ int hd_serve_step(hd_server *v, int32_t iters) {
     hipStream_t s = v->s;
     const int64_t N = c->n;
     const int ldb = v->ldb, rk = v->rk;
-    const bool ubf = c->u_dtype == HD_BF16;
+    const bool ubf = c->u_dtype != HD_F32;
     const hd::IterGuard g{nullptr, 0};
     float *X = v->X.as<float>(), *R = v->R.as<float>(), *P = v->P.as<float>(), *Q = v->Q.as<float>();
     uint16_t *ClT_hi = v->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
@@ -283,7 +286,10 @@ int hd_serve_step(hd_server *v, int32_t iters) {
         if (rk > 0) {
             // L1 U1^T P for every column (a newly admitted column has P = y)
             if (ubf) {
-                HIP_TRY(hd::launch_ut_p_bf16(N, c->UbT.as<uint16_t>(), c->ldut, rk, P, ldb, v->Cpart.as<float>(), g, s));
+                uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
+                HIP_TRY(hd::launch_split_pt(N, ldb, P, c->ldut, PTh, PTl, g, s));
+                HIP_TRY(hd::launch_ut_p_bf16(N, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
+                                             v->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
             } else {
                 HIP_TRY(hd::launch_ut_p(N, c->U.as<float>(), c->rp, rk, P, ldb, v->Cpart.as<float>(), g, s));
             }
@@ -291,8 +297,8 @@ int hd_serve_step(hd_server *v, int32_t iters) {
                                         v->Cl.as<float>(), g, s));
             if (ubf) {
                 HIP_TRY(hd::launch_split_t(v->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
-                HIP_TRY(hd::launch_u_c_bf16(N, c->Ub.as<uint16_t>(), c->rp, rk, ClT_hi, ClT_lo, ldb, P, v->o.alpha,
-                                            v->Z.as<float>(), g, s));
+                HIP_TRY(hd::launch_u_c_bf16(N, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, ClT_hi, ClT_lo, ldb, P, v->o.alpha,
+                                            v->Z.as<float>(), g, s, c->tv(HD_TUNE_UC_NT, ldb)));
             } else {
                 HIP_TRY(hd::launch_u_c(N, c->U.as<float>(), c->rp, rk, v->Cl.as<float>(), ldb, P, v->o.alpha,
                                        v->Z.as<float>(), g, s));
@@ -300,7 +306,7 @@ int hd_serve_step(hd_server *v, int32_t iters) {
             Zs = v->Z.as<float>();
         }
         HIP_TRY(hd::launch_spmm(N, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
-                                ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s));
+                                ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb)));
         HIP_TRY(hd::launch_cg_step_a(ldb, v->part.as<double>(), v->rp.nblk, v->st, g, s));
         HIP_TRY(hd::launch_update_r(N, ldb, Q, R, v->rp, v->st.a, v->part.as<double>(), g, s));
         HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->rp.nblk, v->o.tol, v->st, g,
@@ -336,11 +342,11 @@ int hd_serve_poll(hd_server *v, int32_t max_out, int64_t *tickets, int32_t *ids,
     HIP_TRY(hd::launch_gather_cols(N, ldb, v->X.as<float>(), v->Cs.as<float>(), rk, v->cols.as<int32_t>(), m,
                                    ldc, v->xc.as<float>(), v->csc.as<float>(), s));
     float *xq = v->xq.as<float>();
-    if (rk > 0 && c->u_dtype == HD_BF16) {
+    if (rk > 0 && c->u_dtype != HD_F32) {
         uint16_t *hi = v->cst.as<uint16_t>(), *lo = hi + (size_t)rk * ldc;
         HIP_TRY(hd::launch_split_t(v->csc.as<float>(), rk, ldc, hi, lo, hd::IterGuard{nullptr, 0}, s));
-        HIP_TRY(hd::launch_combine_bf16(N, m, c->Ub.as<uint16_t>(), c->rp, rk, hi, lo, ldc, v->xc.as<float>(), xq,
-                                        N, s));
+        HIP_TRY(hd::launch_combine_bf16(N, m, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, hi, lo, ldc, v->xc.as<float>(), xq,
+                                        N, s, c->tv(HD_TUNE_UC_NT, ldc)));
     } else {
         HIP_TRY(hd::launch_combine(N, m, c->U.as<float>(), c->rp, rk, v->csc.as<float>(), ldc, v->xc.as<float>(),
                                    xq, N, s));

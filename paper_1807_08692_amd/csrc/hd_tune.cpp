@@ -1,0 +1,118 @@
+// Launch parameters of the hot kernels and the autotuner that picks them.
+//
+// The search space is small and discrete (columns per lane of the sparse
+// product; 16-column tiles per wave of the bfloat16 eigenvector products),
+// so the tuner times every candidate on the context's own graph and
+// eigenvectors at the solver width of the batch size it is asked for, on
+// scratch vectors, and keeps the fastest. Timing uses HIP events on the
+// null stream around `reps` back-to-back launches after one warm-up launch.
+#include "hd_internal.h"
+
+extern "C" {
+
+int hd_set_tuning(hd_ctx *c, int32_t key, int32_t value) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_set_tuning: NULL context");
+    if (key < 0 || key >= HD_TUNE_NKEYS) return fail(HD_EINVAL, "hd_set_tuning: key %d unknown", key);
+    if (value != 0 && value != 1 && value != 2 && value != 4)
+        return fail(HD_EINVAL, "hd_set_tuning: value %d not in {0, 1, 2, 4}", value);
+    c->tune[key] = value;
+    return HD_OK;
+}
+
+int hd_get_tuning(const hd_ctx *c, int32_t key, int32_t *value) {
+    g_err.clear();
+    if (!c || !value) return fail(HD_EINVAL, "hd_get_tuning: NULL argument");
+    if (key < 0 || key >= HD_TUNE_NKEYS) return fail(HD_EINVAL, "hd_get_tuning: key %d unknown", key);
+    *value = c->tune[key];
+    return HD_OK;
+}
+
+int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_autotune: NULL context");
+    if (c->n == 0) return fail(HD_ESTATE, "hd_autotune: no graph loaded");
+    if (batch < 1 || batch > 1024) return fail(HD_EINVAL, "hd_autotune: batch=%d not in [1, 1024]", batch);
+    if (reps < 1 || reps > 1000) return fail(HD_EINVAL, "hd_autotune: reps=%d not in [1, 1000]", reps);
+    HIP_TRY(hipSetDevice(c->device));
+    const int64_t n = c->n;
+    const int ldb = pow2_at_least(batch);
+    const int rk = c->rp;
+    const bool ubf = c->u_dtype != HD_F32 && rk > 0;
+    const size_t vec = (size_t)n * ldb * sizeof(float);
+    const hd::RowPart rp = hd::make_row_part(n);
+    int64_t rc;
+    const int nchunk = hd::ut_p_chunks(n, &rc);
+    HIP_TRY(c->P.ensure(vec));
+    HIP_TRY(c->Q.ensure(vec));
+    HIP_TRY(c->Z.ensure(vec));
+    HIP_TRY(c->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
+    hipStream_t s = nullptr;
+    HIP_TRY(hd::launch_fill_zero(c->P.as<float>(), (size_t)n * ldb, s));
+    HIP_TRY(hd::launch_fill_zero(c->Z.as<float>(), (size_t)n * ldb, s));
+    uint16_t *PTh = nullptr, *PTl = nullptr, *CTh = nullptr, *CTl = nullptr;
+    if (ubf) {
+        HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
+        HIP_TRY(c->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
+        HIP_TRY(c->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
+        PTh = c->PT.as<uint16_t>();
+        PTl = PTh + (size_t)ldb * c->ldut;
+        CTh = c->ClT.as<uint16_t>();
+        CTl = CTh + (size_t)rk * ldb;
+        HIP_TRY(hd::launch_fill_zero(reinterpret_cast<float *>(CTh), (size_t)rk * ldb, s));
+        HIP_TRY(hd::launch_split_pt(n, ldb, c->P.as<float>(), c->ldut, PTh, PTl, hd::IterGuard{nullptr, 0}, s));
+    }
+    const hd::IterGuard none{nullptr, 0};
+    auto launch = [&](int key, int v) -> hipError_t {
+        switch (key) {
+        case HD_TUNE_SPMM_CPL:
+            return hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(),
+                                   c->P.as<float>(), c->Z.as<float>(), c->Q.as<float>(), ldb, 0.99, rp,
+                                   c->part.as<double>(), none, s, v);
+        case HD_TUNE_UTP_NT:
+            return hd::launch_ut_p_bf16(n, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
+                                        c->Cpart.as<float>(), none, s, v);
+        default:
+            return hd::launch_u_c_bf16(n, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, CTh, CTl, ldb,
+                                       c->P.as<float>(), 0.99, c->Z.as<float>(), none, s, v);
+        }
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int cand[3] = {1, 2, 4};
+    int err = HD_OK;
+    for (int key = 0; key < HD_TUNE_NKEYS && err == HD_OK; ++key) {
+        const bool used = key == HD_TUNE_SPMM_CPL || ubf;
+        double best = -1.0;
+        int best_v = 0;
+        for (int j = 0; j < 3; ++j) {
+            double ms = -1.0;
+            if (used && hd::tile_param_ok(cand[j], ldb)) {
+                hipError_t e = launch(key, cand[j]);
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                for (int t = 0; t < reps && e == hipSuccess; ++t) e = launch(key, cand[j]);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float el = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+                if (e != hipSuccess) {
+                    err = fail(HD_EDEVICE, "hd_autotune: %s", hipGetErrorString(e));
+                    break;
+                }
+                ms = (double)el / reps;
+                if (best < 0.0 || ms < best) {
+                    best = ms;
+                    best_v = cand[j];
+                }
+            }
+            if (times_ms) times_ms[key * 3 + j] = ms;
+        }
+        if (used && best_v != 0) c->tune[key] = best_v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return err;
+}
+
+}  // extern "C"

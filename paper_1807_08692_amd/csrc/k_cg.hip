@@ -360,6 +360,87 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
     return hipGetLastError();
 }
 
+// update_xp for the bfloat16 forms of U1: the same X and P updates, and the
+// new P also written as its split transpose PT_hi / PT_lo (ldb x ldpt
+// bfloat16, item index contiguous, zero past N), the operand of the next
+// iteration's U1^T P. A block covers 64 items x 64 columns: thread t updates
+// the float4 at column 4(t%16) of rows t/16 + 16j, then the 64 x 64 tile of
+// new P is transposed through LDS and thread t writes column t/4, items
+// 16(t%4) .. +15 of PT as 16-byte stores.
+__global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, float *X, float *P,
+                                                         const float *R, const double *a,
+                                                         const double *beta, const int32_t *active,
+                                                         int64_t ldpt, unsigned short *PTh,
+                                                         unsigned short *PTl, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
+    __shared__ float T[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int b0 = blockIdx.y * 64;
+    const int c4 = 4 * (threadIdx.x % 16);
+    double av[4], bv[4];
+    int kv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        av[q] = a[b0 + c4 + q];
+        bv[q] = beta[b0 + c4 + q];
+        kv[q] = active[b0 + c4 + q];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = threadIdx.x / 16 + 16 * j;
+        const int64_t i = i0 + r;
+        float pn[4] = {0.f, 0.f, 0.f, 0.f};
+        if (i < N) {
+            const size_t o = vec_index(N, ldb, i, b0 + c4);
+            float4 *xp = reinterpret_cast<float4 *>(X + o);
+            float4 *pp = reinterpret_cast<float4 *>(P + o);
+            const float4 rv = *reinterpret_cast<const float4 *>(R + o);
+            float4 x = *xp, p = *pp;
+            float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w};
+            const float rs[4] = {rv.x, rv.y, rv.z, rv.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (av[q] != 0.0) xs[q] = (float)((double)xs[q] + av[q] * (double)ps[q]);
+                if (kv[q]) ps[q] = (float)((double)rs[q] + bv[q] * (double)ps[q]);
+                pn[q] = ps[q];
+            }
+            *xp = make_float4(xs[0], xs[1], xs[2], xs[3]);
+            *pp = make_float4(ps[0], ps[1], ps[2], ps[3]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) T[c4 + q][r] = pn[q];
+    }
+    __syncthreads();
+    typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+    const int b = threadIdx.x / 4, seg = 16 * (threadIdx.x % 4);
+    bf16x8_t h[2], l[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float v = T[b][seg + 8 * u + q];
+            const __bf16 hb = (__bf16)v;
+            h[u][q] = hb;
+            l[u][q] = (__bf16)(v - (float)hb);
+        }
+    const size_t o = (size_t)(b0 + b) * ldpt + i0 + seg;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        *reinterpret_cast<bf16x8_t *>(PTh + o + 8 * u) = h[u];
+        *reinterpret_cast<bf16x8_t *>(PTl + o + 8 * u) = l[u];
+    }
+}
+
+hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
+                               const double *a, const double *beta, const int32_t *active,
+                               int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
+                               hipStream_t s) {
+    if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0) return hipErrorInvalidValue;
+    k_update_xp_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(ldb / 64)), kBlock, 0, s>>>(
+        N, ldb, X, P, R, a, beta, active, ldpt, PTh, PTl, g);
+    return hipGetLastError();
+}
+
 __global__ void k_cg_final(int ldb, CgState st) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ldb) return;
@@ -377,20 +458,25 @@ hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s) {
 // g(x) = h(x) - h(0), eq. (aux)) and Cl = lambda .* c, which is L1 U1^T P for
 // the first CG product since P0 = y.
 template <typename UT>
-__device__ __forceinline__ double u_elem(const UT *U, size_t o);
+__device__ __forceinline__ double u_elem(const UT *U, const UT *U_lo, size_t o);
 template <>
-__device__ __forceinline__ double u_elem<float>(const float *U, size_t o) { return (double)U[o]; }
+__device__ __forceinline__ double u_elem<float>(const float *U, const float *, size_t o) {
+    return (double)U[o];
+}
 template <>
-__device__ __forceinline__ double u_elem<unsigned short>(const unsigned short *U, size_t o) {
-    return (double)__uint_as_float((uint32_t)U[o] << 16);
+__device__ __forceinline__ double u_elem<unsigned short>(const unsigned short *U,
+                                                         const unsigned short *U_lo, size_t o) {
+    double v = (double)__uint_as_float((uint32_t)U[o] << 16);
+    if (U_lo) v += (double)__uint_as_float((uint32_t)U_lo[o] << 16);
+    return v;
 }
 
 template <typename UT>
 __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int32_t *ids,
                                                         const float *vals, int64_t N,
-                                                        const UT *U, int rp, int rk, int r_use,
-                                                        const double *lam, double alpha, int ldb,
-                                                        float *Cs, float *Cl,
+                                                        const UT *U, const UT *U_lo, int rp, int rk,
+                                                        int r_use, const double *lam, double alpha,
+                                                        int ldb, float *Cs, float *Cl,
                                                         const int32_t *colmap) {
     int k = blockIdx.x * kBlock + threadIdx.x;
     int b = blockIdx.y;  // y row; its solver column is colmap[b] (or b)
@@ -401,7 +487,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
     if (k < r_use && b < B) {
         for (int t = 0; t < ky; ++t) {
             int id = ids[b * ky + t];
-            if (id >= 0 && (int64_t)id < N) acc += u_elem<UT>(U, (size_t)id * rp + k) * (double)vals[b * ky + t];
+            if (id >= 0 && (int64_t)id < N)
+                acc += u_elem<UT>(U, U_lo, (size_t)id * rp + k) * (double)vals[b * ky + t];
         }
     }
     double lk = k < r_use ? lam[k] : 0.0;
@@ -412,19 +499,20 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
 }
 
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                              const void *U, int u_bf16, int rp, int rk, int r_use,
+                              const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
                               hipStream_t s, const int32_t *colmap) {
     if (rk == 0) return hipSuccess;
     dim3 grid((rk + kBlock - 1) / kBlock, colmap ? B : ldb);
     if (u_bf16) {
         k_gather_proj<unsigned short><<<grid, kBlock, 0, s>>>(
-            B, ky, ids, vals, N, reinterpret_cast<const unsigned short *>(U), rp, rk, r_use, lam,
-            alpha, ldb, Cs, Cl, colmap);
+            B, ky, ids, vals, N, reinterpret_cast<const unsigned short *>(U),
+            reinterpret_cast<const unsigned short *>(U_lo), rp, rk, r_use, lam, alpha, ldb, Cs, Cl,
+            colmap);
     } else {
         k_gather_proj<float><<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N,
-                                                     reinterpret_cast<const float *>(U), rp, rk,
-                                                     r_use, lam, alpha, ldb, Cs, Cl, colmap);
+                                                     reinterpret_cast<const float *>(U), nullptr, rp,
+                                                     rk, r_use, lam, alpha, ldb, Cs, Cl, colmap);
     }
     return hipGetLastError();
 }

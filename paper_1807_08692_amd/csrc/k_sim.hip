@@ -28,8 +28,11 @@ __global__ __launch_bounds__(kBlock) void k_sim(int64_t N, int B, int d,
     const int t = threadIdx.x;
     const int lane = t % kWave, w = t / kWave;
     const int hi = lane / 32, lo = lane % 32;
-    const int64_t j0 = (int64_t)blockIdx.x * 256;
-    const int b0 = blockIdx.y * 64;
+    // logical tiles: 64-query tile fastest (the tiles of one item range share
+    // V through one XCD's L2), then 256-item range
+    const unsigned L = xcd_tile(), nqt = (unsigned)(B + 63) / 64;
+    const int64_t j0 = (int64_t)(L / nqt) * 256;
+    const int b0 = (int)(L % nqt) * 64;
     f32x16 acc[2][2];
     for (int m = 0; m < 2; ++m)
         for (int n = 0; n < 2; ++n)
@@ -96,8 +99,8 @@ __global__ __launch_bounds__(kBlock) void k_sim(int64_t N, int B, int d,
 
 hipError_t launch_sim(int64_t N, int B, int d, const float *q, const float *V, int ldv, float *sim,
                       int64_t lds, hipStream_t s) {
-    dim3 grid((unsigned)((N + 255) / 256), (unsigned)((B + 63) / 64));
-    k_sim<<<grid, kBlock, 0, s>>>(N, B, d, q, V, ldv, sim, lds);
+    const unsigned nblk = (unsigned)((N + 255) / 256) * (unsigned)((B + 63) / 64);
+    k_sim<<<nblk, kBlock, 0, s>>>(N, B, d, q, V, ldv, sim, lds);
     return hipGetLastError();
 }
 

@@ -148,21 +148,24 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__res
     }
 }
 
+bool tile_param_ok(int v, int ldb) { return (v == 1 || v == 2 || v == 4) && ldb % (64 * v) == 0; }
+
+// cpl: query columns per lane (a wave covers 64 cpl columns of a row); the
+// default is 2 when it divides ldb (measured fastest at 256 columns on a
+// million-row graph), else 1.
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
-                       RowPart rp, double *gpart, IterGuard g, hipStream_t s) {
+                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl) {
     const float a = (float)alpha, oma = (float)(1.0 - alpha);
-    if (ldb == 64) {
-        k_spmm<1><<<dim3(rp.nblk, 1), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma,
-                                                       rp.rb, gpart, g);
-    } else if (ldb == 128) {
-        k_spmm<2><<<dim3(rp.nblk, 1), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma,
-                                                       rp.rb, gpart, g);
-    } else if (ldb >= 256 && ldb % 256 == 0) {
-        k_spmm<4><<<dim3(rp.nblk, ldb / 256), kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb,
-                                                               a, oma, rp.rb, gpart, g);
+    if (cpl == 0) cpl = ldb % 128 == 0 ? 2 : 1;
+    if (!tile_param_ok(cpl, ldb)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)rp.nblk, (unsigned)(ldb / (64 * cpl)));
+    if (cpl == 1) {
+        k_spmm<1><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g);
+    } else if (cpl == 2) {
+        k_spmm<2><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g);
     } else {
-        return hipErrorInvalidValue;
+        k_spmm<4><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g);
     }
     return hipGetLastError();
 }

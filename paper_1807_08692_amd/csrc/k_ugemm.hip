@@ -48,10 +48,15 @@ __global__ __launch_bounds__(kBlock) void k_ut_p(int64_t N, const float *__restr
     constexpr int G = 8;  // MFMA k-steps (2 rows each) per pipeline stage
     const int lane = threadIdx.x % kWave;
     const int w = threadIdx.x / kWave;
-    const int k0 = (blockIdx.y * 4 + w) * 32;
+    // logical tiles: column group fastest, then k group, then row chunk, so
+    // the tiles of one row chunk run on one XCD and share its rows in L2
+    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (32 * NT),
+                   nkg = (unsigned)(rk / 32 + 3) / 4;
+    const unsigned chunk = L / (ncg * nkg);
+    const int k0 = ((int)((L / ncg) % nkg) * 4 + w) * 32;
     if (k0 >= rk) return;  // no block-level synchronisation below
-    const int b0 = blockIdx.z * 32 * NT;
-    const int64_t rs = (int64_t)blockIdx.x * rc;
+    const int b0 = (int)(L % ncg) * 32 * NT;
+    const int64_t rs = (int64_t)chunk * rc;
     const int64_t re = rs + rc < N ? rs + rc : N;
     const int hi = lane / 32, lo = lane % 32;
     f32x16 acc[NT];
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_ut_p(int64_t N, const float *__restr
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = mfma32(a1, b1[t], acc[t]);
     }
-    float *out = Cpart + (size_t)blockIdx.x * rk * ldb;
+    float *out = Cpart + (size_t)chunk * rk * ldb;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -123,10 +128,10 @@ hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P
     int nchunk = ut_p_chunks(N, &rc);
     int kgroups = (rk / 32 + 3) / 4;
     if (ldb == 64) {
-        k_ut_p<2><<<dim3(nchunk, kgroups, 1), kBlock, 0, s>>>(N, U, rp, rk, P, ldb, rc, Cpart, g);
+        k_ut_p<2><<<(unsigned)(nchunk * kgroups), kBlock, 0, s>>>(N, U, rp, rk, P, ldb, rc, Cpart, g);
     } else {
-        k_ut_p<4><<<dim3(nchunk, kgroups, ldb / 128), kBlock, 0, s>>>(N, U, rp, rk, P, ldb, rc,
-                                                                       Cpart, g);
+        k_ut_p<4><<<(unsigned)(nchunk * kgroups * (ldb / 128)), kBlock, 0, s>>>(N, U, rp, rk, P, ldb,
+                                                                                rc, Cpart, g);
     }
     return hipGetLastError();
 }
@@ -243,8 +248,10 @@ __global__ __launch_bounds__(kBlock) void k_u_c(int64_t N, const float *__restri
     __shared__ __attribute__((aligned(16))) float Cs[32][COLS + 4];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int lo = lane % 32;
-    const int64_t i0 = (int64_t)blockIdx.x * 128;
-    const int c0 = blockIdx.y * COLS;
+    // logical tiles: column group fastest, then 128-row block
+    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / COLS;
+    const int64_t i0 = (int64_t)(L / ncg) * 128;
+    const int c0 = (int)(L % ncg) * COLS;
     f32x16 acc[2 * NT];
 #pragma unroll
     for (int t = 0; t < 2 * NT; ++t)
@@ -274,11 +281,12 @@ hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl
                       const float *P, double alpha, float *Z, IterGuard g, hipStream_t s) {
     const unsigned gx = (unsigned)((N + 127) / 128);
     if (ldb == 64) {
-        k_u_c<1><<<dim3(gx, 1), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
+        k_u_c<1><<<gx, kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
     } else if (ldb == 128) {
-        k_u_c<2><<<dim3(gx, 1), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
+        k_u_c<2><<<gx, kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
     } else {
-        k_u_c<4><<<dim3(gx, ldb / 256), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha, Z, g);
+        k_u_c<4><<<gx * (unsigned)(ldb / 256), kBlock, 0, s>>>(N, U, rp, rk, Cl, ldb, P, (float)alpha,
+                                                                 Z, g);
     }
     return hipGetLastError();
 }
@@ -296,8 +304,10 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t N, int B, const floa
     __shared__ float T[64][129];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int lo = lane % 32;
-    const int64_t i0 = (int64_t)blockIdx.x * 128;
-    const int c0 = blockIdx.y * 64;
+    // logical tiles: 64-query group fastest, then 128-row block
+    const unsigned L = xcd_tile(), nqg = (unsigned)(B + 63) / 64;
+    const int64_t i0 = (int64_t)(L / nqg) * 128;
+    const int c0 = (int)(L % nqg) * 64;
     f32x16 acc[2];
     for (int v = 0; v < 16; ++v) {
         acc[0][v] = 0.f;
@@ -334,8 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t N, int B, const floa
 
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
                           int ldb, const float *X, float *x, int64_t ldx, hipStream_t s) {
-    dim3 grid((unsigned)((N + 127) / 128), (unsigned)((B + 63) / 64));
-    k_combine<<<grid, kBlock, 0, s>>>(N, B, U, rp, rk, Cs, ldb, X, x, ldx);
+    const unsigned nblk = (unsigned)((N + 127) / 128) * (unsigned)((B + 63) / 64);
+    k_combine<<<nblk, kBlock, 0, s>>>(N, B, U, rp, rk, Cs, ldb, X, x, ldx);
     return hipGetLastError();
 }
 

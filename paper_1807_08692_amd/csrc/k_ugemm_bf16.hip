@@ -9,6 +9,11 @@
 // product is done twice (hi and lo) into fp32 accumulators, so the only
 // approximation beyond fp32 is the bfloat16 storage of U1 itself.
 //
+// Two-term form (LO = true): U1 is also stored as U_hi + U_lo, two bfloat16
+// arrays of the same layout (about 16 significant bits), and each product
+// takes the three terms U_hi P_hi + U_hi P_lo + U_lo P_hi (the U_lo P_lo term
+// is below fp32 rounding of the sum and is dropped).
+//
 // MFMA v_mfma_f32_16x16x32_bf16 operand layout (lane l of 64):
 //   A (16 x 32): row l % 16, k = 8*(l/16) .. +7;  B (32 x 16): col l % 16,
 //   k = 8*(l/16) .. +7;  C (16 x 16, 4 values): row 4*(l/16) + v, col l % 16.
@@ -24,25 +29,13 @@ __device__ __forceinline__ f32x4 mfma16bf(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// fp32 -> bf16 bits, round to nearest even (finite inputs).
+// fp32 -> bf16 bits, round to nearest even (the gfx950 conversion
+// instruction v_cvt_pk_bf16_f32).
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
-    const uint32_t u = __float_as_uint(x);
-    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)x);
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) {
     return __uint_as_float((uint32_t)h << 16);
-}
-// Split eight fp32 values into hi and lo bfloat16 vectors.
-__device__ __forceinline__ void split8(const float *v, bf16x8 &hi, bf16x8 &lo) {
-    u16x8 h, l;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const unsigned short hb = bf16_rne(v[q]);
-        h[q] = hb;
-        l[q] = bf16_rne(v[q] - bf16_to_f(hb));
-    }
-    hi = __builtin_bit_cast(bf16x8, h);
-    lo = __builtin_bit_cast(bf16x8, l);
 }
 __device__ __forceinline__ bf16x8 load8(const unsigned short *p) {
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(p));
@@ -74,261 +67,311 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 }
 
 // ---------------------------------------------------------------------------
-// Cpart[c] = U[chunk c]^T P[chunk c] with U component-major bf16 (UT, rp rows
-// of stride ldut >= N, a multiple of 64 so that every 8-row run is 16-byte
-// aligned).
-// M = k (16 per tile), N = b (16), K = rows (32 per MFMA). Wave w owns k
-// rows [32w, 32w+32) of the block's 128 (two m-tiles) and the block's 64
-// columns (four n-tiles). Per 32-row step the block loads the P tile
-// (32 rows x 64 columns, fp32, coalesced), splits it into hi/lo bfloat16 and
-// stores it transposed in LDS, so each wave reads its B fragments as 16-byte
-// LDS loads; the A fragments come straight from UT. The next step's P tile
-// and A fragments are fetched into registers while the current step runs.
-__global__ __launch_bounds__(kBlock) void k_ut_p_bf16(int64_t N, const unsigned short *__restrict__ UT,
-                                                      int64_t ldut, int rk,
-                                                      const float *__restrict__ P, int ldb,
-                                                      int64_t rc, float *__restrict__ Cpart,
-                                                      IterGuard ig) {
-    if (all_stopped(ig.nact, ig.ntile)) return;
-    __shared__ __attribute__((aligned(16))) unsigned short Ph[64][40];
-    __shared__ __attribute__((aligned(16))) unsigned short Pl[64][40];
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    // grid: x = 64-column group (fastest, so the groups of one row chunk run
-    // side by side and read U once from memory), y = k group, z = row chunk
-    const int k0 = blockIdx.y * 128 + 32 * w;
-    const bool kact = k0 < rk;  // waves past rk still help stage P
-    const int b0 = blockIdx.x * 64;
-    const int64_t rs = (int64_t)blockIdx.z * rc;
-    const int64_t re = rs + rc < N ? rs + rc : N;
+// Block GEMM shared by the three eigenvector products:
+//   acc[m][n] = sum_k A[m][k] B[n][k]
+// with both operands K-contiguous bfloat16: A (M x K, row stride lda, one or
+// two terms A + Al) and B (N x K, row stride ldbk, split hi + lo). A block
+// covers 128 rows of M and 64*NT columns of N; wave w owns the columns
+// n0 + 16 NT w .. +16 NT (NT n-tiles) for all 128 rows (eight m-tiles), so it
+// holds 32 NT accumulators per lane. Per 32-wide K step the 128 x 32 A tile
+// is loaded once per block (thread t: row t/2, 16 values from k 16(t%2)) and
+// staged in LDS, where every wave reads its A fragments; each wave loads its
+// own B fragments straight from memory (they are small and shared by all
+// blocks, so they come from L2). The next step's A tile and B fragments are
+// fetched into registers while the current step's MFMAs run.
+//   products per (A term, B term): A_hi B_hi + A_hi B_lo (+ A_lo B_hi)
+// MFMA v_mfma_f32_16x16x32_bf16: A fragment = A[m0 + l%16][k + 8(l/16) ..+7],
+// B fragment = B[n + l%16][k + 8(l/16) ..+7], C[m = 4(l/16) + v][n = l%16].
+template <bool LO, int NT>
+__device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
+                                         const unsigned short *__restrict__ Al, int64_t lda,
+                                         int64_t m0, int64_t mend,
+                                         const unsigned short *__restrict__ Bh,
+                                         const unsigned short *__restrict__ Bl, int64_t ldbk,
+                                         int64_t nw0, int64_t k0, int64_t k1, f32x4 (&acc)[8][NT]) {
+    __shared__ __attribute__((aligned(16))) unsigned short As[128][40];
+    __shared__ __attribute__((aligned(16))) unsigned short Asl[LO ? 128 : 1][40];
+    const int lane = threadIdx.x % kWave;
     const int g = lane / 16, c16 = lane % 16;
-    // P staging: thread t -> row t/8 of the tile, columns 8*(t%8) .. +7
-    const int prow = threadIdx.x / 8, pcol = 8 * (threadIdx.x % 8);
-    f32x4 acc[2][4];
+    const int sm = threadIdx.x / 2, sk = 16 * (threadIdx.x % 2);
+    const bool sok = m0 + sm < mend;
+    const unsigned short *sa = A + (size_t)(m0 + (sok ? sm : 0)) * lda + sk;
+    const unsigned short *sal = LO ? Al + (size_t)(m0 + (sok ? sm : 0)) * lda + sk : nullptr;
+    const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+    bf16x8 ra[2], ral[2], bh[NT], bl[NT];
+    auto fetch = [&](int64_t k) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    float4 pv[2];
-    bf16x8 a[2];
-    auto fetch = [&](int64_t i) {
-        const int64_t r = i + prow;
-        if (r < re) {
-            const float4 *src = reinterpret_cast<const float4 *>(P + vec_index(N, ldb, r, b0 + pcol));
-            pv[0] = src[0];
-            pv[1] = src[1];
-        } else {
-            pv[0] = pv[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int u = 0; u < 2; ++u) {
+            ra[u] = sok ? load8(sa + k + 8 * u) : zero;
+            if (LO) ral[u] = sok ? load8(sal + k + 8 * u) : zero;
         }
-        const int64_t r8 = i + 8 * g;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (!kact) {
-                a[m] = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-                continue;
-            }
-            const unsigned short *src = UT + (size_t)(k0 + 16 * m + c16) * ldut + r8;
-            if (r8 + 8 <= re) {
-                a[m] = load8(src);
-            } else {
-                u16x8 t;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) t[q] = (r8 + q < re) ? src[q] : (unsigned short)0;
-                a[m] = __builtin_bit_cast(bf16x8, t);
-            }
+        for (int n = 0; n < NT; ++n) {
+            const size_t o = (size_t)(nw0 + 16 * n + c16) * ldbk + k + 8 * g;
+            bh[n] = load8(Bh + o);
+            bl[n] = load8(Bl + o);
         }
     };
-    fetch(rs);
-    for (int64_t i = rs; i < re; i += 32) {
-        __syncthreads();  // previous step's LDS reads are done
-        {
-            const float v[8] = {pv[0].x, pv[0].y, pv[0].z, pv[0].w, pv[1].x, pv[1].y, pv[1].z, pv[1].w};
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const unsigned short h = bf16_rne(v[q]);
-                Ph[pcol + q][prow] = h;
-                Pl[pcol + q][prow] = bf16_rne(v[q] - bf16_to_f(h));
-            }
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (k0 < k1) fetch(k0);
+    for (int64_t k = k0; k < k1; k += 32) {
+        __syncthreads();  // the previous step's LDS reads are done
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            *reinterpret_cast<bf16x8 *>(&As[sm][sk + 8 * u]) = ra[u];
+            if (LO) *reinterpret_cast<bf16x8 *>(&Asl[sm][sk + 8 * u]) = ral[u];
         }
-        const bf16x8 a0 = a[0], a1 = a[1];
-        __syncthreads();
-        if (i + 32 < re) fetch(i + 32);
-        if (kact) {
+        bf16x8 ch[NT], cl[NT];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const bf16x8 hi = load8(&Ph[16 * n + c16][8 * g]);
-                const bf16x8 lo = load8(&Pl[16 * n + c16][8 * g]);
-                acc[0][n] = mfma16bf(a0, hi, acc[0][n]);
-                acc[0][n] = mfma16bf(a0, lo, acc[0][n]);
-                acc[1][n] = mfma16bf(a1, hi, acc[1][n]);
-                acc[1][n] = mfma16bf(a1, lo, acc[1][n]);
+        for (int n = 0; n < NT; ++n) {
+            ch[n] = bh[n];
+            cl[n] = bl[n];
+        }
+        __syncthreads();
+        if (k + 32 < k1) fetch(k + 32);
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            const bf16x8 a = load8(&As[16 * mt + c16][8 * g]);
+            bf16x8 al = zero;
+            if (LO) al = load8(&Asl[16 * mt + c16][8 * g]);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                acc[mt][n] = mfma16bf(a, ch[n], acc[mt][n]);
+                acc[mt][n] = mfma16bf(a, cl[n], acc[mt][n]);
+                if (LO) acc[mt][n] = mfma16bf(al, ch[n], acc[mt][n]);
             }
         }
     }
-    if (!kact) return;
-    float *out = Cpart + (size_t)blockIdx.z * rk * ldb;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                out[(size_t)(k0 + 16 * m + 4 * g + v) * ldb + b0 + 16 * n + c16] = acc[m][n][v];
 }
 
-hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, int64_t ldut, int rk, const float *P,
-                            int ldb, float *Cpart, IterGuard g, hipStream_t s) {
-    int64_t rc;
-    const int nchunk = ut_p_chunks(N, &rc);
-    const int kgroups = (rk + 127) / 128;
-    k_ut_p_bf16<<<dim3(ldb / 64, kgroups, nchunk), kBlock, 0, s>>>(N, UT, ldut, rk, P, ldb, rc, Cpart, g);
+// Number of n-tiles per wave (columns per block: 64 NT): the requested
+// value, or by default the widest of 1, 2, 4 up to `cap` that divides ldb
+// (measured defaults: 4 for U^T P, 2 for U C, whose four-tile form holds one
+// wave per SIMD).
+static inline int tn_nt(int ldb, int req, int cap) {
+    if (req != 0) return tile_param_ok(req, ldb) ? req : 0;
+    for (int v = cap; v > 1; v /= 2)
+        if (ldb % (64 * v) == 0) return v;
+    return 1;
+}
+
+// ---------------------------------------------------------------------------
+// P^T split: from P (N x ldb fp32, node-major) write PT_hi, PT_lo (ldb x ldpt
+// bfloat16, item index contiguous; items N .. ldpt-1 zero), the B operand of
+// U^T P. A block transposes a 64-item x 64-column tile through LDS.
+__global__ __launch_bounds__(kBlock) void k_split_pt(int64_t N, int ldb, const float *__restrict__ P,
+                                                     int64_t ldpt, unsigned short *__restrict__ PTh,
+                                                     unsigned short *__restrict__ PTl, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
+    __shared__ float T[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int b0 = blockIdx.y * 64;
+    const int c = threadIdx.x % 64;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int r = threadIdx.x / 64 + 4 * j;
+        T[c][r] = i0 + r < N ? P[vec_index(N, ldb, i0 + r, b0 + c)] : 0.f;
+    }
+    __syncthreads();
+    const int b = threadIdx.x / 4, seg = 16 * (threadIdx.x % 4);
+    bf16x8 h[2], l[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float v = T[b][seg + 8 * u + q];
+            const __bf16 hb = (__bf16)v;
+            h[u][q] = hb;
+            l[u][q] = (__bf16)(v - (float)hb);
+        }
+    const size_t o = (size_t)(b0 + b) * ldpt + i0 + seg;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        *reinterpret_cast<bf16x8 *>(PTh + o + 8 * u) = h[u];
+        *reinterpret_cast<bf16x8 *>(PTl + o + 8 * u) = l[u];
+    }
+}
+
+hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
+                           unsigned short *PTl, IterGuard g, hipStream_t s) {
+    if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0) return hipErrorInvalidValue;
+    k_split_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(ldb / 64)), kBlock, 0, s>>>(N, ldb, P, ldpt, PTh,
+                                                                                    PTl, g);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// acc += U[rows i0+32w .. +32] x C[:, c0 .. c0+64) over all rk, with U
-// item-major bf16 (N x rp) and C given as split transposed CT_hi/lo (ldb x rk).
-// The block's 64 columns of CT (hi and lo) for one 32-wide k chunk are
-// staged in LDS and shared by the four waves; the A fragments (U rows) come
-// straight from memory. The next chunk is fetched into registers while the
-// current one is multiplied.
-__device__ __forceinline__ void uc_bf16_tile(int64_t N, const unsigned short *__restrict__ U,
-                                             int rp, int rk,
-                                             const unsigned short *__restrict__ CT_hi,
-                                             const unsigned short *__restrict__ CT_lo,
-                                             int64_t i0, int c0, f32x4 (*acc)[4]) {
-    __shared__ __attribute__((aligned(16))) unsigned short Ch[64][40];
-    __shared__ __attribute__((aligned(16))) unsigned short Cl[64][40];
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    const int g = lane / 16, c16 = lane % 16;
-    // CT staging: thread t -> column t/4, k 8*(t%4) .. +7 of the chunk
-    const int scol = threadIdx.x / 4, sk = 8 * (threadIdx.x % 4);
-    int64_t row[2];
-    bool ok[2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        row[m] = i0 + 32 * w + 16 * m + c16;
-        ok[m] = row[m] < N;
-    }
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-    bf16x8 a[2], sh, sl;
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int m = 0; m < 2; ++m) a[m] = ok[m] ? load8(U + (size_t)row[m] * rp + k0 + 8 * g) : zero;
-        const size_t o = (size_t)(c0 + scol) * rk + k0 + sk;
-        sh = load8(CT_hi + o);
-        sl = load8(CT_lo + o);
-    };
-    if (rk > 0) fetch(0);
-    for (int k0 = 0; k0 < rk; k0 += 32) {
-        __syncthreads();
-        *reinterpret_cast<bf16x8 *>(&Ch[scol][sk]) = sh;
-        *reinterpret_cast<bf16x8 *>(&Cl[scol][sk]) = sl;
-        const bf16x8 a0 = a[0], a1 = a[1];
-        __syncthreads();
-        if (k0 + 32 < rk) fetch(k0 + 32);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const bf16x8 h = load8(&Ch[16 * n + c16][8 * g]);
-            const bf16x8 l = load8(&Cl[16 * n + c16][8 * g]);
-            acc[0][n] = mfma16bf(a0, h, acc[0][n]);
-            acc[0][n] = mfma16bf(a0, l, acc[0][n]);
-            acc[1][n] = mfma16bf(a1, h, acc[1][n]);
-            acc[1][n] = mfma16bf(a1, l, acc[1][n]);
-        }
-    }
-}
-
-// Z = P + alpha U Cl: a block covers 128 rows x 64 columns (wave w: 32 rows).
-__global__ __launch_bounds__(kBlock) void k_u_c_bf16(int64_t N, const unsigned short *__restrict__ U,
-                                                     int rp, int rk,
-                                                     const unsigned short *__restrict__ CT_hi,
-                                                     const unsigned short *__restrict__ CT_lo,
-                                                     int ldb, const float *__restrict__ P,
-                                                     float alpha, float *__restrict__ Z,
-                                                     IterGuard ig) {
+// Cpart[c] = U[chunk c]^T P[chunk c]: M = k (UT rows, component-major U,
+// row stride ldut, items past N zero), N = b (PT rows), K = the chunk's
+// items. Logical tiles: column group fastest, then k group, then row chunk,
+// so the tiles of one chunk run on one XCD and share PT and UT in its L2.
+template <bool LO, int NT>
+__global__ __launch_bounds__(kBlock) void k_ut_p_tn(const unsigned short *__restrict__ UT,
+                                                    const unsigned short *__restrict__ UTl,
+                                                    int64_t ldut, int rk,
+                                                    const unsigned short *__restrict__ PTh,
+                                                    const unsigned short *__restrict__ PTl, int ldb,
+                                                    int64_t rc, int64_t kend_all,
+                                                    float *__restrict__ Cpart, IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT), nkg = (unsigned)(rk + 127) / 128;
+    const unsigned chunk = L / (ncg * nkg);
+    const int64_t m0 = (int64_t)((L / ncg) % nkg) * 128;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t nw0 = (int64_t)(L % ncg) * 64 * NT + 16 * NT * w;
+    const int64_t ks = (int64_t)chunk * rc;
+    const int64_t ke = ks + rc < kend_all ? ks + rc : kend_all;
+    f32x4 acc[8][NT];
+    tn_block<LO, NT>(UT, UTl, ldut, m0, rk, PTh, PTl, ldut, nw0, ks, ke, acc);
+    float *out = Cpart + (size_t)chunk * rk * ldb;
     const int g = lane / 16, c16 = lane % 16;
-    // grid: x = 64-column group (fastest: the groups of one row block share
-    // their U rows through the caches), y = 128-row block
-    const int64_t i0 = (int64_t)blockIdx.y * 128;
-    const int c0 = blockIdx.x * 64;
-    f32x4 acc[2][4];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    uc_bf16_tile(N, U, rp, rk, CT_hi, CT_lo, i0, c0, acc);
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t i = i0 + 32 * w + 16 * m + 4 * g + v;
-            if (i >= N) continue;
+            const int64_t k = m0 + 16 * mt + 4 * g + v;
+            if (k >= rk) continue;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const size_t o = vec_index(N, ldb, i, c0 + 16 * n + c16);
-                Z[o] = P[o] + alpha * acc[m][n][v];
-            }
+            for (int n = 0; n < NT; ++n) out[(size_t)k * ldb + nw0 + 16 * n + c16] = acc[mt][n][v];
         }
 }
 
-hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, int rp, int rk,
-                           const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
-                           const float *P, double alpha, float *Z, IterGuard g, hipStream_t s) {
-    dim3 grid((unsigned)(ldb / 64), (unsigned)((N + 127) / 128));
-    k_u_c_bf16<<<grid, kBlock, 0, s>>>(N, U, rp, rk, CT_hi, CT_lo, ldb, P, (float)alpha, Z, g);
+hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned short *UT_lo,
+                            int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
+                            int ldb, float *Cpart, IterGuard g, hipStream_t s, int ntr) {
+    int64_t rc;
+    const int nchunk = ut_p_chunks(N, &rc);
+    // rows run to N rounded up to 32 (UT and PT are zero past N)
+    const int64_t kend = (N + 31) / 32 * 32;
+    if (kend > ldut || rc % 32 != 0) return hipErrorInvalidValue;
+    const int nt = tn_nt(ldb, ntr, 4);
+    if (nt == 0) return hipErrorInvalidValue;
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((rk + 127) / 128) * (unsigned)nchunk;
+#define HD_UTP(LOV, NTV) \
+    k_ut_p_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(UT, UT_lo ? UT_lo : UT, ldut, rk, PTh, PTl, ldb, rc, kend, Cpart, g)
+    if (UT_lo) {
+        if (nt == 4) HD_UTP(true, 4); else if (nt == 2) HD_UTP(true, 2); else HD_UTP(true, 1);
+    } else {
+        if (nt == 4) HD_UTP(false, 4); else if (nt == 2) HD_UTP(false, 2); else HD_UTP(false, 1);
+    }
+#undef HD_UTP
     return hipGetLastError();
 }
 
-// x[b][i] = (U Cs)[i][b] + X[i][b], transposed through LDS (see k_combine).
-__global__ __launch_bounds__(kBlock) void k_combine_bf16(int64_t N, int B,
-                                                         const unsigned short *__restrict__ U,
-                                                         int rp, int rk,
-                                                         const unsigned short *__restrict__ CT_hi,
-                                                         const unsigned short *__restrict__ CT_lo,
-                                                         int ldb, const float *__restrict__ X,
-                                                         float *__restrict__ x, int64_t ldx) {
-    __shared__ float T[64][129];
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+// ---------------------------------------------------------------------------
+// Z = P + alpha U Cl: M = items (128 per block), N = solver columns, K = rk;
+// A = U item-major (row stride rp), B = ClT split (ldb x rk). Logical tiles:
+// column group fastest, then 128-row block.
+template <bool LO, int NT>
+__global__ __launch_bounds__(kBlock) void k_u_c_tn(int64_t N, const unsigned short *__restrict__ U,
+                                                   const unsigned short *__restrict__ Ul, int rp, int rk,
+                                                   const unsigned short *__restrict__ CT_hi,
+                                                   const unsigned short *__restrict__ CT_lo, int ldb,
+                                                   const float *__restrict__ P, float alpha,
+                                                   float *__restrict__ Z, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
+    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
+    const int64_t i0 = (int64_t)(L / ncg) * 128;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t nw0 = (int64_t)(L % ncg) * 64 * NT + 16 * NT * w;
+    f32x4 acc[8][NT];
+    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nw0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
-    const int64_t i0 = (int64_t)blockIdx.y * 128;  // x: query group (fastest), y: row block
-    const int c0 = blockIdx.x * 64;
-    f32x4 acc[2][4];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    uc_bf16_tile(N, U, rp, rk, CT_hi, CT_lo, i0, c0, acc);
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int rl = 32 * w + 16 * m + 4 * g + v;
-            const int64_t i = i0 + rl;
+            const int64_t i = i0 + 16 * mt + 4 * g + v;
+            if (i >= N) continue;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const int bl = 16 * n + c16;
-                float val = acc[m][n][v];
-                if (i < N) val += X[vec_index(N, ldb, i, c0 + bl)];
-                T[bl][rl] = val;
+            for (int n = 0; n < NT; ++n) {
+                const size_t o = vec_index(N, ldb, i, (int)(nw0 + 16 * n + c16));
+                Z[o] = P[o] + alpha * acc[mt][n][v];
             }
         }
-    __syncthreads();
-    for (int f = threadIdx.x; f < 64 * 128; f += kBlock) {
-        const int bl = f / 128, rl = f % 128;
-        const int b = c0 + bl;
-        const int64_t i = i0 + rl;
-        if (b < B && i < N) x[(size_t)b * ldx + i] = T[bl][rl];
+}
+
+hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp, int rk,
+                           const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
+                           const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
+                           int ntr) {
+    const int nt = tn_nt(ldb, ntr, 2);
+    if (nt == 0) return hipErrorInvalidValue;
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + 127) / 128);
+    const float a = (float)alpha;
+#define HD_UC(LOV, NTV) \
+    k_u_c_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, P, a, Z, g)
+    if (U_lo) {
+        if (nt == 4) HD_UC(true, 4); else if (nt == 2) HD_UC(true, 2); else HD_UC(true, 1);
+    } else {
+        if (nt == 4) HD_UC(false, 4); else if (nt == 2) HD_UC(false, 2); else HD_UC(false, 1);
+    }
+#undef HD_UC
+    return hipGetLastError();
+}
+
+// x[b][i] = (U Cs)[i][b] + X[i][b] (b < B): the product as in u_c over the
+// ldc >= B columns of CsT; each wave then writes its tile query-major, one
+// 16-item m-tile at a time through LDS, so that every query's 16 items go
+// out as one 64-byte run.
+template <bool LO, int NT>
+__global__ __launch_bounds__(kBlock) void k_combine_tn(int64_t N, int B, const unsigned short *__restrict__ U,
+                                                       const unsigned short *__restrict__ Ul, int rp,
+                                                       int rk, const unsigned short *__restrict__ CT_hi,
+                                                       const unsigned short *__restrict__ CT_lo, int ldc,
+                                                       const float *__restrict__ X, float *__restrict__ x,
+                                                       int64_t ldx) {
+    __shared__ float T[4][16 * NT][17];
+    const unsigned L = xcd_tile(), ncg = (unsigned)ldc / (64 * NT);
+    const int64_t i0 = (int64_t)(L / ncg) * 128;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t nw0 = (int64_t)(L % ncg) * 64 * NT + 16 * NT * w;
+    f32x4 acc[8][NT];
+    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nw0, 0, rk, acc);
+    const int g = lane / 16, c16 = lane % 16;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rl = 4 * g + v;
+            const int64_t i = i0 + 16 * mt + rl;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int bl = 16 * n + c16;
+                float val = acc[mt][n][v];
+                if (i < N) val += X[vec_index(N, ldc, i, (int)(nw0 + bl))];
+                T[w][bl][rl] = val;
+            }
+        }
+        __syncthreads();
+        // lane -> (query bl = f / 16, item f % 16) over the wave's 16 NT queries
+        for (int f = lane; f < 16 * NT * 16; f += kWave) {
+            const int bl = f / 16, rl = f % 16;
+            const int64_t b = nw0 + bl, i = i0 + 16 * mt + rl;
+            if (b < B && i < N) x[(size_t)b * ldx + i] = T[w][bl][rl];
+        }
     }
 }
 
-hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, int rp, int rk,
-                               const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
-                               const float *X, float *x, int64_t ldx, hipStream_t s) {
-    dim3 grid((unsigned)((B + 63) / 64), (unsigned)((N + 127) / 128));
-    k_combine_bf16<<<grid, kBlock, 0, s>>>(N, B, U, rp, rk, CT_hi, CT_lo, ldb, X, x, ldx);
+hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const unsigned short *U_lo,
+                               int rp, int rk, const unsigned short *CT_hi,
+                               const unsigned short *CT_lo, int ldb, const float *X, float *x,
+                               int64_t ldx, hipStream_t s, int ntr) {
+    const int nt = tn_nt(ldb, ntr, 2);
+    if (nt == 0) return hipErrorInvalidValue;
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + 127) / 128);
+#define HD_CB(LOV, NTV) \
+    k_combine_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, B, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, X, x, ldx)
+    if (U_lo) {
+        if (nt == 4) HD_CB(true, 4); else if (nt == 2) HD_CB(true, 2); else HD_CB(true, 1);
+    } else {
+        if (nt == 4) HD_CB(false, 4); else if (nt == 2) HD_CB(false, 2); else HD_CB(false, 1);
+    }
+#undef HD_CB
     return hipGetLastError();
 }
 
@@ -352,9 +395,9 @@ __global__ __launch_bounds__(kBlock) void k_split_q(int B, int d, int ldv, const
 // items [64w, 64w+64) (four n-tiles) for all 64 queries (four m-tiles, hi
 // and lo), so each LDS fragment feeds four or eight MFMAs. Per 32-wide k
 // chunk the V tile (256 x 32) and the Q tiles (64 x 32, hi and lo) are staged
-// in LDS; the next chunk is fetched into registers meanwhile. blockIdx.x runs
-// over the query tiles so that the tiles of one item range run together and
-// share V through the caches.
+// in LDS; the next chunk is fetched into registers meanwhile. The logical
+// tiles run over the query tiles fastest, so the tiles of one item range run
+// on one XCD and share V through its L2.
 __global__ __launch_bounds__(kBlock) void k_sim_bf16(int64_t N, int B, int ldv,
                                                      const unsigned short *__restrict__ Qh,
                                                      const unsigned short *__restrict__ Ql,
@@ -364,8 +407,9 @@ __global__ __launch_bounds__(kBlock) void k_sim_bf16(int64_t N, int B, int ldv,
     __shared__ __attribute__((aligned(16))) unsigned short Qs[2][64][40];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
-    const int b0 = blockIdx.x * 64;
-    const int64_t jb = (int64_t)blockIdx.y * 256;
+    const unsigned L = xcd_tile(), nqt = (unsigned)(B + 63) / 64;
+    const int b0 = (int)(L % nqt) * 64;
+    const int64_t jb = (int64_t)(L / nqt) * 256;
     f32x4 acc[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -429,8 +473,8 @@ hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsign
     k_split_q<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(B, d, ldv, q, Qh, Ql);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)((B + 63) / 64), (unsigned)((N + 255) / 256));
-    k_sim_bf16<<<grid, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, sim, lds);
+    const unsigned nblk = (unsigned)((B + 63) / 64) * (unsigned)((N + 255) / 256);
+    k_sim_bf16<<<nblk, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, sim, lds);
     return hipGetLastError();
 }
 

@@ -16,11 +16,11 @@ LIB_PATH = os.path.join(_HERE, "libhd.so")
 
 HD_OK, HD_EINVAL, HD_ENOMEM, HD_EDEVICE, HD_ESTATE = 0, -1, -2, -3, -4
 COL_CONVERGED, COL_MAXITER, COL_ZERO_RHS, COL_BREAKDOWN = 0, 1, 2, 3
-HD_F32, HD_BF16, HD_FP8_E4M3 = 0, 1, 2
+HD_F32, HD_BF16, HD_FP8_E4M3, HD_BF16X2 = 0, 1, 2, 3
 HD_GRAPH_NORMALIZE, HD_GRAPH_CHECK_SYMMETRY = 1, 2
 TOPK_MAX = 1024
 
-_DTYPES = {"f32": HD_F32, "bf16": HD_BF16, "fp8": HD_FP8_E4M3}
+_DTYPES = {"f32": HD_F32, "bf16": HD_BF16, "fp8": HD_FP8_E4M3, "bf16x2": HD_BF16X2}
 
 # Exported entry points and their ctypes signatures (same names as hd.h).
 _P = ctypes.c_void_p
@@ -49,7 +49,13 @@ _SIGS = {
     "hd_serve_step": (ctypes.c_int, [_P, ctypes.c_int32]),
     "hd_serve_poll": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
     "hd_serve_close": (None, [_P]),
+    "hd_set_tuning": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "hd_get_tuning": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "hd_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
 }
+
+# Launch parameters (hd_tune_key)
+TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2}
 
 
 class hd_query_opts(ctypes.Structure):
@@ -160,6 +166,25 @@ class Context:
 
     def device_bytes(self) -> int:
         return int(lib().hd_device_bytes(self._h))
+
+    def set_tuning(self, key: str, value: int):
+        _check(lib().hd_set_tuning(self._h, TUNE_KEYS[key], int(value)))
+
+    def get_tuning(self, key: str) -> int:
+        v = ctypes.c_int32()
+        _check(lib().hd_get_tuning(self._h, TUNE_KEYS[key], ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, batch: int, reps: int = 5) -> dict:
+        """Time every candidate launch parameter at this batch size and keep
+        the fastest; returns {key: {value: mean ms}} and the chosen values."""
+        t = (ctypes.c_double * (3 * len(TUNE_KEYS)))()
+        _check(lib().hd_autotune(self._h, int(batch), int(reps), t))
+        out = {}
+        for name, k in TUNE_KEYS.items():
+            out[name] = {"times_ms": {v: t[3 * k + j] for j, v in enumerate((1, 2, 4)) if t[3 * k + j] >= 0},
+                         "chosen": self.get_tuning(name)}
+        return out
 
     def timing_enable(self, on: bool = True, kinds=None):
         """Per-kernel event timing: all kinds, or only the named ones."""

@@ -116,3 +116,55 @@ def test_bf16_descriptors_y(fx, ctx, torch_dev):
         assert np.all(s[gi[b]] >= kth - eps)
         assert set(np.nonzero(s > kth + eps)[0].tolist()) <= set(gi[b].tolist())
         assert np.allclose(gv[b], np.maximum(s[gi[b]], 0) ** 3, rtol=1e-4, atol=1e-7)
+
+
+def bf16x2_split(a):
+    """The two-term bfloat16 form: hi = RNE(a), lo = RNE(a - hi); returns the
+    represented value hi + lo in double."""
+    a = np.ascontiguousarray(a, np.float32)
+    hi = bf16_round(a)
+    lo = bf16_round((a - hi).astype(np.float32))
+    return hi.astype(np.float64) + lo.astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def ctx2(fx, torch_dev):
+    from paper_1807_08692_amd import hd
+    c = hd.Context(0)
+    c.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    c.load_eigs(fx.U, fx.lam, dtype="bf16x2")
+    c.load_descriptors(fx.V, dtype="f32")
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("B,r", [(1, 50), (70, 50), (130, 17)])
+def test_bf16x2_eigs_parity(fx, g64, ctx2, torch_dev, B, r):
+    """Two-term bfloat16 U1 (three-term products): parity with the oracle
+    given the represented U1 to the fp32 bar, and with the fp32 U1 oracle to
+    the same bar (the two terms carry about 16 significant bits)."""
+    import torch
+    rng = np.random.default_rng(100 + B)
+    qi = rng.integers(0, fx.Q.shape[0], size=B)
+    ids, vals = oracle_y(fx, fx.Q[qi])
+    yi = torch.from_numpy(ids).to(torch_dev)
+    yv = torch.from_numpy(vals).to(torch_dev)
+    out = ctx2.query_batch(None, yi, yv, alpha=0.99, max_iter=20, tol=1e-6, rank_r=r, k_y=fx.cfg.k_y,
+                           top_k=100, want_x=True)
+    torch.cuda.synchronize()
+    x = out["x"].cpu().numpy()
+    U2 = bf16x2_split(fx.U)
+    for b in sorted({0, B // 2, B - 1}):
+        it = int(out["iters"][b])
+        xq, *_ = O.iterate(g64, U2[:, :r], fx.lam[:r], 0.99, ids[b], vals[b], it, 0.0)
+        assert rel(x[b], xq) <= 1e-4, (b, rel(x[b], xq))
+        xf, *_ = O.iterate(g64, fx.U[:, :r], fx.lam[:r], 0.99, ids[b], vals[b], it, 0.0)
+        assert rel(x[b], xf) <= 1e-4, (b, rel(x[b], xf))
+        oid, _ = O.rank(x[b].astype(np.float64), 100)
+        assert np.array_equal(out["rank_ids"].cpu().numpy()[b], oid)
+
+
+def test_bf16x2_rejected_for_descriptors(fx, ctx2):
+    from paper_1807_08692_amd import hd
+    with pytest.raises(hd.HDError):
+        ctx2.load_descriptors(fx.V, dtype="bf16x2")

@@ -107,6 +107,34 @@ def test_server_matches_batch_and_oracle(fx, ctx, torch_dev):
         assert np.allclose(r["scores"], out["rank_scores"].cpu().numpy()[b], rtol=1e-5, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "bf16x2"])
+def test_server_bf16_forms_match_batch(fx, torch_dev, dtype):
+    """The server with bfloat16 (one- and two-term) U1: same ranking as the
+    batch path with the same storage, scores within fp32 rounding."""
+    import torch
+    from paper_1807_08692_amd import hd
+    c = hd.Context(0)
+    try:
+        c.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+        c.load_eigs(fx.U, fx.lam, dtype=dtype)
+        ids, vals = ys(fx, np.arange(6))
+        kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+        srv = hd.Server(c, 8, **kw)
+        tk = srv.submit(ids, vals)
+        res = {}
+        drain(srv, 6, res)
+        srv.close()
+        out = c.query_batch(None, torch.from_numpy(ids).to(torch_dev),
+                            torch.from_numpy(vals).to(torch_dev), **kw)
+        torch.cuda.synchronize()
+        for b in range(6):
+            r = res[int(tk[b])]
+            assert r["iters"] == out["iters"][b]
+            assert np.allclose(r["scores"], out["rank_scores"].cpu().numpy()[b], rtol=1e-5, atol=1e-12)
+    finally:
+        c.close()
+
+
 def test_per_request_cap_and_descriptors(fx, ctx):
     from paper_1807_08692_amd import hd
     srv = hd.Server(ctx, 16, alpha=0.99, max_iter=20, tol=1e-6, rank_r=-1, k_y=fx.cfg.k_y, top_k=20)
