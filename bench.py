@@ -75,6 +75,9 @@ def parse():
     p.add_argument("--calib-queries", type=int, default=4,
                    help="queries of the first batch whose exact solution fixes the iteration counts")
     p.add_argument("--calib-max-iter", type=int, default=40)
+    p.add_argument("--no-graph", action="store_true",
+                   help="time only eager launches (no HIP-graph query plans)")
+    p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--tol-mode", action="store_true",
                    help="time both methods with the workload's residual tolerance instead")
     return p.parse_args()
@@ -148,7 +151,7 @@ def main():
         return ctx.query_batch(Qd[i % nbatch], alpha=cfg.alpha, max_iter=iters, tol=tol,
                                rank_r=r, k_y=cfg.k_y, top_k=K_RANK)
 
-    def timed(r, iters, tol, steps, with_events, kinds=None):
+    def timed(r, iters, tol, steps, with_events, kinds=None, plan=None):
         outs = []
         lat = []
         if with_events:
@@ -157,7 +160,7 @@ def main():
         t_start = time.perf_counter()
         for k in range(steps):
             ts = time.perf_counter()
-            o = step(k, r, iters, tol)
+            o = plan.run(Qd[k % nbatch]) if plan is not None else step(k, r, iters, tol)
             lat.append(time.perf_counter() - ts)
             outs.append((o["iters"].copy(), o["status"].copy()))
         torch.cuda.synchronize()
@@ -175,7 +178,9 @@ def main():
                 "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
                 "iters_mean": float(its.mean()), "iters_max": int(its.max()),
-                "converged_frac": float(np.mean(sts == 0))}
+                "status": {name: int(np.sum(sts == code)) for code, name in
+                           ((0, "converged"), (1, "iteration_cap"), (2, "zero_rhs"), (3, "breakdown"))
+                           if np.any(sts == code)}}
 
     def run_form(form):
         """Calibrate and time one storage form of U1; returns its record."""
@@ -184,6 +189,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[setup] U1 {form}, descriptors {vprec}: loaded in {time.time() - t1:.1f}s, "
             f"library holds {ctx.device_bytes() / 2**20:.0f} MiB on the device")
+        tune = ctx.autotune(B, 3) if not args.no_autotune else None
+        if tune:
+            log(f"[setup] autotune: " + ", ".join(f"{k}={v['chosen']}" for k, v in tune.items()))
         for w in range(args.warmup):
             step(w, -1, cfg.max_iter, cfg.tol)
             step(w, 0, cfg.max_iter, cfg.tol)
@@ -226,9 +234,26 @@ def main():
             total_p, lat_p, outs_p, _ = timed(0, ip, tp, args.steps, False)
             log(f"[bench] U1 {form} {label}: plain CG ({ip} it) {args.steps} batches in {total_p:.3f}s")
             sh, sp = summary(total_h, lat_h, outs_h, cfg.r), summary(total_p, lat_p, outs_p, 0)
-            targets[label] = {"eps": e, "hybrid": sh, "plain_cg": sp,
-                              "hybrid_over_plain": round(sh["queries_per_s"] / sp["queries_per_s"], 3)}
-        return {"form": form, "su": su, "calibration": cal, "targets": targets,
+            rec = {"eps": e, "hybrid_eager": sh, "plain_cg_eager": sp}
+            if not args.no_graph:
+                # the same work replayed from HIP graphs (hd_plan_*)
+                for name, r_use, (it_, tl_) in (("hybrid_graph", -1, (ih, th)), ("plain_cg_graph", 0, (ip, tp))):
+                    pl = hd.Plan(ctx, B, "descriptors", alpha=cfg.alpha, max_iter=it_, tol=tl_, rank_r=r_use,
+                                 k_y=cfg.k_y, top_k=K_RANK)
+                    for w in range(max(1, args.warmup)):
+                        pl.run(Qd[w % nbatch])
+                    tot, lat, outs, _ = timed(r_use, it_, tl_, args.steps, False, plan=pl)
+                    pl.close()
+                    rec[name] = summary(tot, lat, outs, cfg.r if r_use else 0)
+                    log(f"[bench] U1 {form} {label}: {name} {args.steps} batches in {tot:.3f}s")
+            # headline per target: the faster of the eager and graph forms
+            for m in ("hybrid", "plain_cg"):
+                cand = [rec[k] for k in (m + "_graph", m + "_eager") if k in rec]
+                rec[m] = max(cand, key=lambda v: v["queries_per_s"])
+                rec[m]["launch"] = "graph" if rec[m] is rec.get(m + "_graph") else "eager"
+            rec["hybrid_over_plain"] = round(rec["hybrid"]["queries_per_s"] / rec["plain_cg"]["queries_per_s"], 3)
+            targets[label] = rec
+        return {"form": form, "su": su, "calibration": cal, "targets": targets, "autotune": tune,
                 "dominant": dom, "dom_tm": dom_tm, "kernels": kernels, "hybrid_plan": plans[0][2]}
 
     recs = [run_form(f) for f in forms]
@@ -295,7 +320,8 @@ def main():
         "hybrid": tgt["hybrid"],
         "plain_cg": tgt["plain_cg"],
         "hybrid_over_plain": tgt["hybrid_over_plain"],
-        "forms": {rec["form"]: {"targets": rec["targets"], "calibration": rec["calibration"]} for rec in recs},
+        "forms": {rec["form"]: {"targets": rec["targets"], "calibration": rec["calibration"],
+                                "autotune": rec["autotune"]} for rec in recs},
         "roofline": roof,
         "kernels": chosen["kernels"],
         "fixture": {"eig_max_residual": fx.info["eig_max_residual"], "mean_degree": fx.info["mean_degree"],

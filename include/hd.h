@@ -202,6 +202,46 @@ int hd_query_batch(hd_ctx *ctx, int32_t B, const float *q_desc,
                    void *stream);
 
 /*
+ * Query plans (batching form): the whole query path of hd_query_batch for a
+ * fixed batch size B, input kind and options, captured once into a HIP
+ * graph and replayed for each batch, so a batch costs one graph launch
+ * instead of some ten kernel launches per CG iteration. All max_iter CG
+ * iterations are in the graph; once every column has stopped, the later
+ * iterations' kernels return at once, so results equal hd_query_batch's
+ * (iteration counts, statuses and residuals included). The plan holds its
+ * own input and ranking buffers and runs in the context's workspace: it is
+ * captured again by itself when that workspace, the loaded data or the
+ * launch parameters have changed since. Calls on one context, plans
+ * included, must not overlap.
+ * input: HD_PLAN_DESCRIPTORS (queries given as B x d fp32 descriptors) or
+ * HD_PLAN_Y (B x k_y ids and values of y). The options are those of
+ * hd_query_batch; top_k must be >= 1.
+ * Errors: as hd_query_batch, HD_EINVAL (input kind, top_k), HD_EDEVICE
+ * (capture or instantiation failed).
+ */
+typedef struct hd_plan hd_plan;
+#define HD_PLAN_DESCRIPTORS 0
+#define HD_PLAN_Y 1
+int hd_plan_create(hd_ctx *ctx, int32_t B, int32_t input, const hd_query_opts *opts, hd_plan **out);
+
+/*
+ * Run a plan on stream `stream`: q_desc (device, B x d) for descriptor
+ * plans, or y_ids / y_val (device, B x k_y) for y plans, are copied into the
+ * plan's buffers, the graph is launched, and the results are written like
+ * hd_query_batch's: rank_ids / rank_scores (device, B x top_k, may be NULL),
+ * iters / relres / status (host, B, may be NULL). Returns after the stream
+ * has finished. Errors: HD_EINVAL (NULL plan or input, a y id outside
+ * [0, n) for y plans), HD_EDEVICE.
+ */
+int hd_plan_run(hd_plan *plan, const float *q_desc, const int32_t *y_ids, const float *y_val,
+                int32_t *rank_ids, float *rank_scores, int32_t *iters, double *relres,
+                int32_t *status, void *stream);
+
+/* Release a plan (NULL accepted). The context must outlive its plans. */
+void hd_plan_destroy(hd_plan *plan);
+
+
+/*
  * Rank B score vectors (Section 3: decreasing x, equal values to the lower
  * id). x (device, fp32, B x n row-major with row stride ldx >= n elements);
  * ids_out / scores_out (device, B x K). 1 <= K <= min(n, 1024).

@@ -310,11 +310,12 @@ int hd_rank(hd_ctx *c, int32_t B, int64_t n, const float *x, int64_t ldx, int32_
     return HD_OK;
 }
 
-int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
-                   const float *y_val, const hd_query_opts *o, int32_t *rank_ids,
-                   float *rank_scores, float *x_out, int32_t *y_ids_out, float *y_val_out,
-                   int32_t *iters, double *relres, int32_t *status, void *stream) {
-    g_err.clear();
+}  // extern "C"
+
+int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
+                     const float *y_val, const hd_query_opts *o, int32_t *rank_ids,
+                     float *rank_scores, float *x_out, int32_t *y_ids_out, float *y_val_out,
+                     hipStream_t s, bool graph, int *last_iter_out) {
     if (!c) return fail(HD_EINVAL, "hd_query_batch: NULL context");
     if (c->n == 0) return fail(HD_ESTATE, "hd_query_batch: no graph loaded");
     if (!o) return fail(HD_EINVAL, "hd_query_batch: NULL options");
@@ -334,7 +335,6 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     } else if (!y_ids || !y_val) {
         return fail(HD_EINVAL, "hd_query_batch: give q_desc or both y_ids and y_val");
     }
-    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(c->device));
 
     const int ldb = pow2_at_least(B);
@@ -416,10 +416,12 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s));
     LAUNCH(K_COLSQ, hd::launch_colsq_part(n, ldb, R, rp, c->part.as<double>(), s));
     LAUNCH(K_SCALAR, hd::launch_cg_init(B, ldb, c->part.as<double>(), rp.nblk, st, s));
-    HIP_TRY(hipMemcpyAsync(c->h_pinned + 200, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (c->timing.on) HIP_TRY(c->timing.harvest(0));
-    if (c->h_pinned[200] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
+    if (!graph) {
+        HIP_TRY(hipMemcpyAsync(c->h_pinned + 200, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c->timing.on) HIP_TRY(c->timing.harvest(0));
+        if (c->h_pinned[200] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
+    }
 
     // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
     const bool ubf = c->u_dtype != HD_F32;
@@ -447,6 +449,9 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
     // pinned memory behind an event. The host queues iteration it+1 before
     // waiting for iteration it's counts, so the GPU never idles on the host;
     // an iteration queued after the last one returns at once from every kernel.
+    // In graph form all max_iter iterations are queued with no host
+    // synchronisation: the same guards turn the iterations after the last
+    // active one into empty kernels.
     const int ntile = ldb / 64;
     int32_t *nact_dev[2] = {st.nact_part, st.nact_part + 64};
     auto enqueue_iter = [&](int it) -> int {
@@ -487,18 +492,26 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         } else {
             LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s));
         }
-        HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(c->iter_ev[it & 1], s));
+        if (!graph) {
+            HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipEventRecord(c->iter_ev[it & 1], s));
+        }
         c->timing.tag = 0;
         return HD_OK;
     };
     int last_iter = 0;
-    if (o->max_iter >= 1) {
+    if (graph) {
+        for (int it = 1; it <= o->max_iter; ++it) {
+            const int e = enqueue_iter(it);
+            if (e != HD_OK) return e;
+        }
+        last_iter = o->max_iter;
+    } else if (o->max_iter >= 1) {
         const int e = enqueue_iter(1);
         if (e != HD_OK) return e;
     }
-    for (int it = 1; it <= o->max_iter; ++it) {
+    for (int it = 1; !graph && it <= o->max_iter; ++it) {
         if (it + 1 <= o->max_iter) {
             const int e = enqueue_iter(it + 1);
             if (e != HD_OK) return e;
@@ -529,6 +542,23 @@ int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, o->top_k)));
         LAUNCH(K_TOPK_RANK, hd::launch_topk(B, n, xq, n, o->top_k, c->topk.p, rank_ids, rank_scores, 0, s));
     }
+    if (last_iter_out) *last_iter_out = last_iter;
+    return HD_OK;
+}
+
+extern "C" {
+
+int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
+                   const float *y_val, const hd_query_opts *o, int32_t *rank_ids,
+                   float *rank_scores, float *x_out, int32_t *y_ids_out, float *y_val_out,
+                   int32_t *iters, double *relres, int32_t *status, void *stream) {
+    g_err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    int last_iter = 0;
+    const int e = queue_query(c, B, q_desc, y_ids, y_val, o, rank_ids, rank_scores, x_out, y_ids_out,
+                              y_val_out, s, false, &last_iter);
+    if (e != HD_OK) return e;
+    const hd::CgState &st = c->st;
     if (iters) HIP_TRY(hipMemcpyAsync(iters, st.iters, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (status) HIP_TRY(hipMemcpyAsync(status, st.status, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (relres) HIP_TRY(hipMemcpyAsync(relres, st.relres, B * sizeof(double), hipMemcpyDeviceToHost, s));

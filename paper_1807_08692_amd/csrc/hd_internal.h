@@ -183,6 +183,18 @@ struct hd_ctx {
     int tv(int key, int ldb) const { return hd::tile_param_ok(tune[key], ldb) ? tune[key] : 0; }
 };
 
+namespace hdi {
+// Validate and queue the whole query path of hd_query_batch on stream s.
+// graph = false: the host watches the stopping test (one iteration of
+// lookahead) and returns after queueing the final steps. graph = true: all
+// max_iter iterations are queued with no host synchronisation and no event
+// or host copy, so the sequence can be captured into a HIP graph; the y-id
+// error flag is left in c->err and the per-column results in c->st.
+int queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids, const float *y_val,
+                const hd_query_opts *o, int32_t *rank_ids, float *rank_scores, float *x_out,
+                int32_t *y_ids_out, float *y_val_out, hipStream_t s, bool graph, int *last_iter);
+}  // namespace hdi
+
 // Launch `call` (a launcher returning hipError_t) as kernel kind `kind`,
 // bracketed by timing events when timing is on.
 #define LAUNCH(kind, call)                                                        \

@@ -71,45 +71,55 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 //   acc[m][n] = sum_k A[m][k] B[n][k]
 // with both operands K-contiguous bfloat16: A (M x K, row stride lda, one or
 // two terms A + Al) and B (N x K, row stride ldbk, split hi + lo). A block
-// covers 128 rows of M and 64*NT columns of N; wave w owns the columns
-// n0 + 16 NT w .. +16 NT (NT n-tiles) for all 128 rows (eight m-tiles), so it
-// holds 32 NT accumulators per lane. Per 32-wide K step the 128 x 32 A tile
-// is loaded once per block (thread t: row t/2, 16 values from k 16(t%2)) and
-// staged in LDS, where every wave reads its A fragments; each wave loads its
-// own B fragments straight from memory (they are small and shared by all
-// blocks, so they come from L2). The next step's A tile and B fragments are
-// fetched into registers while the current step's MFMAs run.
+// covers 128 rows of M and 64*NT columns of N (from nb0); wave w owns the
+// columns nb0 + 16 NT w .. +16 NT (NT n-tiles) for all 128 rows (eight
+// m-tiles), so it holds 32 NT accumulators per lane. Per 32-wide K step the
+// block loads the 128 x 32 A tile (thread t: row t/2, 16 values from k
+// 16(t%2)) and the 64 NT x 32 B tile (hi and lo; NT 16-byte pieces per
+// thread) once, stages both in LDS, and every wave reads its A and B
+// fragments there; the next step's tiles are fetched into registers while
+// the current step's MFMAs run. Holding no operand fragments across steps
+// keeps the four-tile form at two waves per SIMD.
 //   products per (A term, B term): A_hi B_hi + A_hi B_lo (+ A_lo B_hi)
 // MFMA v_mfma_f32_16x16x32_bf16: A fragment = A[m0 + l%16][k + 8(l/16) ..+7],
 // B fragment = B[n + l%16][k + 8(l/16) ..+7], C[m = 4(l/16) + v][n = l%16].
+// LDS rows are padded to 40 halves (80 bytes) so the 16-byte fragment reads
+// of 16 consecutive rows fall in distinct banks.
 template <bool LO, int NT>
 __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
                                          const unsigned short *__restrict__ Al, int64_t lda,
                                          int64_t m0, int64_t mend,
                                          const unsigned short *__restrict__ Bh,
                                          const unsigned short *__restrict__ Bl, int64_t ldbk,
-                                         int64_t nw0, int64_t k0, int64_t k1, f32x4 (&acc)[8][NT]) {
+                                         int64_t nb0, int64_t k0, int64_t k1, f32x4 (&acc)[8][NT]) {
     __shared__ __attribute__((aligned(16))) unsigned short As[128][40];
     __shared__ __attribute__((aligned(16))) unsigned short Asl[LO ? 128 : 1][40];
-    const int lane = threadIdx.x % kWave;
+    __shared__ __attribute__((aligned(16))) unsigned short Bsh[64 * NT][40];
+    __shared__ __attribute__((aligned(16))) unsigned short Bsl[64 * NT][40];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
+    // A staging: row sm, k sk .. sk+15
     const int sm = threadIdx.x / 2, sk = 16 * (threadIdx.x % 2);
     const bool sok = m0 + sm < mend;
     const unsigned short *sa = A + (size_t)(m0 + (sok ? sm : 0)) * lda + sk;
     const unsigned short *sal = LO ? Al + (size_t)(m0 + (sok ? sm : 0)) * lda + sk : nullptr;
+    // B staging: pieces p = NT t + j -> row p / 4, k 8 (p % 4)
+    const int brow0 = (NT * threadIdx.x) / 4, bk0 = 8 * ((NT * threadIdx.x) % 4);
+    const unsigned short *sbh = Bh + (size_t)(nb0 + brow0) * ldbk + bk0;
+    const unsigned short *sbl = Bl + (size_t)(nb0 + brow0) * ldbk + bk0;
     const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-    bf16x8 ra[2], ral[2], bh[NT], bl[NT];
+    bf16x8 ra[2], ral[2], rbh[NT], rbl[NT];
     auto fetch = [&](int64_t k) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             ra[u] = sok ? load8(sa + k + 8 * u) : zero;
             if (LO) ral[u] = sok ? load8(sal + k + 8 * u) : zero;
         }
+        // NT pieces run along one row (NT <= 4 pieces = the row's 32 k)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const size_t o = (size_t)(nw0 + 16 * n + c16) * ldbk + k + 8 * g;
-            bh[n] = load8(Bh + o);
-            bl[n] = load8(Bl + o);
+        for (int j = 0; j < NT; ++j) {
+            rbh[j] = load8(sbh + k + 8 * j);
+            rbl[j] = load8(sbl + k + 8 * j);
         }
     };
 #pragma unroll
@@ -117,6 +127,7 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (k0 < k1) fetch(k0);
+    const int wn = 16 * NT * w;
     for (int64_t k = k0; k < k1; k += 32) {
         __syncthreads();  // the previous step's LDS reads are done
 #pragma unroll
@@ -124,14 +135,19 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
             *reinterpret_cast<bf16x8 *>(&As[sm][sk + 8 * u]) = ra[u];
             if (LO) *reinterpret_cast<bf16x8 *>(&Asl[sm][sk + 8 * u]) = ral[u];
         }
-        bf16x8 ch[NT], cl[NT];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            ch[n] = bh[n];
-            cl[n] = bl[n];
+        for (int j = 0; j < NT; ++j) {
+            *reinterpret_cast<bf16x8 *>(&Bsh[brow0][bk0 + 8 * j]) = rbh[j];
+            *reinterpret_cast<bf16x8 *>(&Bsl[brow0][bk0 + 8 * j]) = rbl[j];
         }
         __syncthreads();
         if (k + 32 < k1) fetch(k + 32);
+        bf16x8 bh[NT], bl[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            bh[n] = load8(&Bsh[wn + 16 * n + c16][8 * g]);
+            bl[n] = load8(&Bsl[wn + 16 * n + c16][8 * g]);
+        }
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             const bf16x8 a = load8(&As[16 * mt + c16][8 * g]);
@@ -139,9 +155,9 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
             if (LO) al = load8(&Asl[16 * mt + c16][8 * g]);
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
-                acc[mt][n] = mfma16bf(a, ch[n], acc[mt][n]);
-                acc[mt][n] = mfma16bf(a, cl[n], acc[mt][n]);
-                if (LO) acc[mt][n] = mfma16bf(al, ch[n], acc[mt][n]);
+                acc[mt][n] = mfma16bf(a, bh[n], acc[mt][n]);
+                acc[mt][n] = mfma16bf(a, bl[n], acc[mt][n]);
+                if (LO) acc[mt][n] = mfma16bf(al, bh[n], acc[mt][n]);
             }
         }
     }
@@ -209,7 +225,7 @@ hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, uns
 // items. Logical tiles: column group fastest, then k group, then row chunk,
 // so the tiles of one chunk run on one XCD and share PT and UT in its L2.
 template <bool LO, int NT>
-__global__ __launch_bounds__(kBlock) void k_ut_p_tn(const unsigned short *__restrict__ UT,
+__global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__restrict__ UT,
                                                     const unsigned short *__restrict__ UTl,
                                                     int64_t ldut, int rk,
                                                     const unsigned short *__restrict__ PTh,
@@ -221,11 +237,11 @@ __global__ __launch_bounds__(kBlock) void k_ut_p_tn(const unsigned short *__rest
     const unsigned chunk = L / (ncg * nkg);
     const int64_t m0 = (int64_t)((L / ncg) % nkg) * 128;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t nw0 = (int64_t)(L % ncg) * 64 * NT + 16 * NT * w;
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
     const int64_t ks = (int64_t)chunk * rc;
     const int64_t ke = ks + rc < kend_all ? ks + rc : kend_all;
     f32x4 acc[8][NT];
-    tn_block<LO, NT>(UT, UTl, ldut, m0, rk, PTh, PTl, ldut, nw0, ks, ke, acc);
+    tn_block<LO, NT>(UT, UTl, ldut, m0, rk, PTh, PTl, ldut, nb0, ks, ke, acc);
     float *out = Cpart + (size_t)chunk * rk * ldb;
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
@@ -266,7 +282,7 @@ hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned 
 // A = U item-major (row stride rp), B = ClT split (ldb x rk). Logical tiles:
 // column group fastest, then 128-row block.
 template <bool LO, int NT>
-__global__ __launch_bounds__(kBlock) void k_u_c_tn(int64_t N, const unsigned short *__restrict__ U,
+__global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned short *__restrict__ U,
                                                    const unsigned short *__restrict__ Ul, int rp, int rk,
                                                    const unsigned short *__restrict__ CT_hi,
                                                    const unsigned short *__restrict__ CT_lo, int ldb,
@@ -276,9 +292,9 @@ __global__ __launch_bounds__(kBlock) void k_u_c_tn(int64_t N, const unsigned sho
     const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
     const int64_t i0 = (int64_t)(L / ncg) * 128;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t nw0 = (int64_t)(L % ncg) * 64 * NT + 16 * NT * w;
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
     f32x4 acc[8][NT];
-    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nw0, 0, rk, acc);
+    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt)
@@ -318,7 +334,7 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
 // 16-item m-tile at a time through LDS, so that every query's 16 items go
 // out as one 64-byte run.
 template <bool LO, int NT>
-__global__ __launch_bounds__(kBlock) void k_combine_tn(int64_t N, int B, const unsigned short *__restrict__ U,
+__global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, const unsigned short *__restrict__ U,
                                                        const unsigned short *__restrict__ Ul, int rp,
                                                        int rk, const unsigned short *__restrict__ CT_hi,
                                                        const unsigned short *__restrict__ CT_lo, int ldc,
@@ -328,9 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_combine_tn(int64_t N, int B, const u
     const unsigned L = xcd_tile(), ncg = (unsigned)ldc / (64 * NT);
     const int64_t i0 = (int64_t)(L / ncg) * 128;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t nw0 = (int64_t)(L % ncg) * 64 * NT + 16 * NT * w;
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
     f32x4 acc[8][NT];
-    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nw0, 0, rk, acc);
+    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {

@@ -52,6 +52,9 @@ _SIGS = {
     "hd_set_tuning": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "hd_get_tuning": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "hd_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+    "hd_plan_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)]),
+    "hd_plan_run": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "hd_plan_destroy": (None, [_P]),
 }
 
 # Launch parameters (hd_tune_key)
@@ -258,6 +261,48 @@ class Context:
         _check(lib().hd_rank(self._h, B, n, _dptr(x), ldx, int(K), _dptr(ids), _dptr(scores),
                              _stream_ptr(stream)))
         return ids, scores
+
+
+class Plan:
+    """A query plan: the whole query path for B queries captured into a HIP
+    graph (hd_plan_*). input: "descriptors" or "y"."""
+
+    def __init__(self, ctx: "Context", B: int, input: str = "descriptors", *, alpha=0.99, max_iter=20,
+                 tol=1e-6, rank_r=-1, k_y=10, top_k=100):
+        self.ctx, self.B, self.top_k, self.k_y = ctx, int(B), int(top_k), int(k_y)
+        self.input = {"descriptors": 0, "y": 1}[input]
+        o = hd_query_opts(float(alpha), int(max_iter), float(tol), int(rank_r), int(k_y), int(top_k))
+        h = ctypes.c_void_p()
+        _check(lib().hd_plan_create(ctx._h, self.B, self.input, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, q_desc=None, y_ids=None, y_val=None, stream=None, out=None) -> dict:
+        """Run on device tensors (q_desc B x d, or y_ids / y_val B x k_y);
+        returns rank_ids / rank_scores (device) and iters / relres / status."""
+        import torch
+        dev = torch.device("cuda", self.ctx.device)
+        res = out if out is not None else {}
+        res.setdefault("rank_ids", torch.empty((self.B, self.top_k), dtype=torch.int32, device=dev))
+        res.setdefault("rank_scores", torch.empty((self.B, self.top_k), dtype=torch.float32, device=dev))
+        it = res.setdefault("iters", np.zeros(self.B, np.int32))
+        rr = res.setdefault("relres", np.zeros(self.B, np.float64))
+        st = res.setdefault("status", np.zeros(self.B, np.int32))
+        _check(lib().hd_plan_run(self._h, _dptr(q_desc), _dptr(y_ids), _dptr(y_val),
+                                 _dptr(res["rank_ids"]), _dptr(res["rank_scores"]),
+                                 it.ctypes.data_as(_P), rr.ctypes.data_as(_P), st.ctypes.data_as(_P),
+                                 _stream_ptr(stream)))
+        return res
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:
