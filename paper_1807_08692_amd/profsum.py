@@ -1,0 +1,125 @@
+"""Summaries of rocprofv3 output for the query path (a developer utility).
+
+    python -m paper_1807_08692_amd.profsum trace TRACE_CSV > summary.md
+    python -m paper_1807_08692_amd.profsum traffic FETCH_CSV WRITE_CSV OUT_JSON > table.md
+
+`trace` reads a --kernel-trace CSV (one row per dispatch) and prints, per
+kernel, the dispatch count and mean duration over all dispatches and over the
+working dispatches only: the solver queues iterations ahead of its stopping
+test, and an iteration queued after every column stopped returns at once
+(a few microseconds), which would otherwise pull the mean down.
+
+`traffic` reads the FETCH_SIZE and WRITE_SIZE counter CSVs of two --pmc runs
+that include a 1 GiB device copy (grid 131072 of __amd_rocclr_copyBuffer),
+scales each counter by what it reads for that copy (1 GiB read and written),
+and writes per-kernel HBM-side bytes per dispatch to OUT_JSON together with a
+SHA-256 of each kernel's source file, so that a later run can tell whether the
+kernel has changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+# kernel name prefix -> (kind used by bench.py, source file)
+KINDS = {
+    "hd::k_spmm": ("spmm", "k_spmm.hip"),
+    "hd::k_ut_p_tn": ("ut_p", "k_ugemm_bf16.hip"),
+    "hd::k_ut_p": ("ut_p", "k_ugemm.hip"),
+    "hd::k_u_c_tn": ("u_c", "k_ugemm_bf16.hip"),
+    "hd::k_u_c": ("u_c", "k_ugemm.hip"),
+    "hd::k_update_xp_pt": ("update_xp", "k_cg.hip"),
+    "hd::k_update_xp": ("update_xp", "k_cg.hip"),
+    "hd::k_update_r": ("update_r", "k_cg.hip"),
+    "hd::k_combine_tn": ("combine", "k_ugemm_bf16.hip"),
+    "hd::k_combine": ("combine", "k_ugemm.hip"),
+    "hd::k_sim_bf16": ("sim", "k_ugemm_bf16.hip"),
+    "hd::k_sim": ("sim", "k_sim.hip"),
+}
+
+
+def short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def kind_of(name: str):
+    n = short(name)
+    for pre in sorted(KINDS, key=len, reverse=True):
+        if n == pre or n.startswith(pre + "<"):
+            return KINDS[pre]
+    return None
+
+
+def sha(fname: str) -> str:
+    with open(os.path.join(CSRC, fname), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def trace(path: str, work_frac: float = 0.05) -> str:
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        per[short(r["Kernel_Name"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in per.values())
+    out = ["| kernel | dispatches | mean us (all) | working dispatches | mean us (working) | % of GPU time |",
+           "|---|---|---|---|---|---|"]
+    for k in sorted(per, key=lambda k: -sum(per[k])):
+        v = per[k]
+        if not k.startswith("hd::") or sum(v) < 1e-4 * total:
+            continue
+        mx = max(v)
+        work = [t for t in v if t >= work_frac * mx]
+        out.append(f"| {k} | {len(v)} | {sum(v) / len(v):.1f} | {len(work)} | {sum(work) / len(work):.1f} "
+                   f"| {100 * sum(v) / total:.2f} |")
+    return "\n".join(out)
+
+
+def traffic(fetch_csv: str, write_csv: str, out_json: str) -> str:
+    def agg(fn):
+        a = collections.defaultdict(list)
+        copy = []
+        for r in csv.DictReader(open(fn)):
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in r["Kernel_Name"] and r["Grid_Size"] == "131072":
+                copy.append(v)
+            a[short(r["Kernel_Name"])].append(v)
+        return a, copy
+    fs, cf = agg(fetch_csv)
+    ws, cw = agg(write_csv)
+    if not cf or not cw:
+        raise SystemExit("no 1 GiB copy dispatch in the counter runs (bench.py --copy-calibration)")
+    kf = 1048576.0 / (sum(cf) / len(cf))
+    kw = 1048576.0 / (sum(cw) / len(cw))
+    rows = ["| kernel | dispatches | FETCH_SIZE KiB (mean) | fetched GB | WRITE_SIZE KiB (mean) | written GB |",
+            "|---|---|---|---|---|---|"]
+    res = {"scale_fetch": kf, "scale_write": kw, "kernels": {}}
+    for k in sorted(fs, key=lambda k: -sum(fs[k])):
+        kd = kind_of(k)
+        if not k.startswith("hd::"):
+            continue
+        # working dispatches only (a skipped iteration fetches a few bytes)
+        mx = max(fs[k])
+        f = [v for v in fs[k] if v >= 0.05 * mx]
+        wv = [v for v in ws.get(k, []) if v >= 0.05 * max(ws.get(k, [0.0]) or [0.0])] or [0.0]
+        fb, wb = sum(f) / len(f) * kf * 1024, sum(wv) / len(wv) * kw * 1024
+        rows.append(f"| {k} | {len(f)} | {sum(f) / len(f):.0f} | {fb / 1e9:.3f} | {sum(wv) / len(wv):.0f} | {wb / 1e9:.3f} |")
+        if kd:
+            res["kernels"][k] = {"kind": kd[0], "fetch_bytes": fb, "write_bytes": wb,
+                                 "source": kd[1], "sha256": sha(kd[1])}
+    with open(out_json, "w") as fh:
+        json.dump(res, fh, indent=1)
+    head = (f"Counter scaling from the 1 GiB copy: FETCH_SIZE x {kf:.3f}, WRITE_SIZE x {kw:.3f}.\n\n")
+    return head + "\n".join(rows)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        print(trace(sys.argv[2]))
+    elif sys.argv[1] == "traffic":
+        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4]))
+    else:
+        raise SystemExit(__doc__)
