@@ -305,6 +305,8 @@ def main():
     tr = measured_traffic(args.workload, dom, chosen)
     if tr:
         roof["traffic"] = tr["bytes"]
+        tr["rate_GBs"] = round(tr["bytes"] / avg_s / 1e9, 1)
+        tr["rate_frac_of_hbm_peak"] = round(tr["bytes"] / avg_s / 1e9 / HBM_PEAK_GBS, 4)
         roof["traffic_detail"] = tr
     roof["kernel"] = dom
     roof["avg_us"] = round(avg_s * 1e6, 2)
