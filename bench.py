@@ -81,6 +81,7 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=2000.0,
                    help="offered load (queries/s) of the open-loop serving run; 0 skips it")
     p.add_argument("--serve-requests", type=int, default=3000)
+    p.add_argument("--no-planner", action="store_true", help="skip the (r, i) planner leg")
     p.add_argument("--tune", default=None,
                    help="fixed launch parameters instead of the autotuner, e.g. spmm_cpl=1,utp_nt=2,uc_nt=4")
     p.add_argument("--iters", default=None,
@@ -354,9 +355,20 @@ def main():
                     "lambda_r": float(fx.lam[-1]) if fx.lam.size else None},
     }
 
+    loaded = [recs[-1]["form"]]
+
+    def use_form(f):
+        if loaded[0] != f:
+            ctx.load_eigs(fx.U, fx.lam, dtype=f)
+            loaded[0] = f
+
+    if not args.no_planner and not args.iters:
+        use_form(form0)
+        result["planner"] = planner_leg(args, cfg, fx, ctx, Qd, B, e0 if e0 is not None else eps_list[0],
+                                        hd, torch, np)
+
     if args.serve_rate > 0:
-        if recs[-1]["form"] != form0:
-            ctx.load_eigs(fx.U, fx.lam, dtype=form0)
+        use_form(form0)
         ih_s = chosen["hybrid_plan"][0]
         ip_s = tgt["plain_cg"]["iters_max"]
         result["serving"] = serving(args, cfg, fx, ctx, B, K_RANK, ih_s, ip_s, hd, np)
@@ -372,8 +384,7 @@ def main():
         result["copy_calibration_bytes"] = nbytes
 
     if not args.no_cpu_baseline:
-        if recs[-1]["form"] != form0:
-            ctx.load_eigs(fx.U, fx.lam, dtype=form0)
+        use_form(form0)
         ih0, th0 = chosen["hybrid_plan"]
         result["cpu_baseline"] = cpu_baseline(args, cfg, fx, ctx, Qd, B, ih0, th0, torch, np)
 
@@ -381,18 +392,19 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
-    """Fewest CG iterations at which each method is within relative error eps
-    of the exact solution on every sampled query. The exact solution of each
-    sampled query is the FP64 oracle's tight CG solve of (I - alpha S) x =
-    (1 - alpha) y with the y the GPU path itself formed (so both methods are
-    measured on the diffusion alone); the GPU results come from runs with a
-    fixed iteration count and no tolerance."""
+_TRUTH = {}
+
+
+def exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np):
+    """x* for the sampled queries of the first batch: the FP64 oracle's tight
+    CG solve of (I - alpha S) x = (1 - alpha) y, with the y the GPU path itself
+    formed (so every method is measured on the diffusion alone). Cached: the
+    descriptors, hence y, are the same for every U1 form."""
+    if "truths" in _TRUTH:
+        return _TRUTH["truths"], _TRUTH["iters"]
     from oracle import oracle as O
     ns = max(1, min(args.calib_queries, B))
     g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
-    dev = Qd.device
-    buf = {"x": torch.empty((B, fx.n), dtype=torch.float32, device=dev)}
     o = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=0, tol=0.0, rank_r=0, k_y=cfg.k_y,
                         top_k=0, want_y=True)
     torch.cuda.synchronize()
@@ -406,22 +418,41 @@ def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
         truths.append(t)
         exact_iters.append(int(it_t))
     log(f"[calib] exact solutions of {ns} queries in {time.time() - t0:.1f}s (iters {exact_iters})")
+    _TRUTH.update(truths=truths, iters=exact_iters)
+    return truths, exact_iters
+
+
+def error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np):
+    """Relative L2 error against x* of the GPU path at 0, 1, 2, ...
+    iterations (no tolerance), until eps_min is reached or the error stops
+    falling (no 2% gain over four iterations)."""
+    ns = len(truths)
     norms = [np.linalg.norm(t) for t in truths]
+    errs = []
+    for it in range(0, args.calib_max_iter + 1):
+        ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use, k_y=cfg.k_y,
+                        top_k=0, want_x=True, out=buf)
+        X = buf["x"][:ns].double().cpu().numpy()
+        err = max(float(np.linalg.norm(X[b] - truths[b]) / norms[b]) for b in range(ns))
+        errs.append(err)
+        if err <= eps_min:
+            break
+        if it >= 6 and err > 0.98 * min(errs[:-4]):
+            break
+    return errs
+
+
+def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
+    """Fewest CG iterations at which each method is within relative error eps
+    of the exact solution on every sampled query; the GPU results come from
+    runs with a fixed iteration count and no tolerance."""
+    truths, exact_iters = exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np)
+    ns = len(truths)
+    buf = {"x": torch.empty((B, fx.n), dtype=torch.float32, device=Qd.device)}
     eps_min = min(eps_list)
     curves, iters, floors, overlap = {}, {}, {}, {}
     for name, r_use in (("hybrid", -1), ("plain", 0)):
-        errs = []
-        for it in range(0, args.calib_max_iter + 1):
-            ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use, k_y=cfg.k_y,
-                            top_k=0, want_x=True, out=buf)
-            X = buf["x"][:ns].double().cpu().numpy()
-            err = max(float(np.linalg.norm(X[b] - truths[b]) / norms[b]) for b in range(ns))
-            errs.append(err)
-            if err <= eps_min:
-                break
-            # error floor: no 2% gain over the last four iterations
-            if it >= 6 and err > 0.98 * min(errs[:-4]):
-                break
+        errs = error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np)
         curves[name] = [float(f"{e:.4g}") for e in errs]
         floors[name] = min(errs)
         for e in eps_list:
@@ -445,6 +476,55 @@ def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
             "exact_solve_iters": exact_iters, "rel_err_by_iter": curves,
             "error_floor": {k: float(f"{v:.4g}") for k, v in floors.items()},
             "iters": iters, "top100_overlap_min": overlap}
+
+
+def planner_leg(args, cfg, fx, ctx, Qd, B, eps, hd, torch, np):
+    """The (r, i) planner on the loaded eigenpairs: per candidate rank, the
+    iterations the CG bound guarantees (hd_rank_plan), the measured cost of
+    the fixed steps and of one iteration (runs at 1 and 3 iterations), the
+    predicted time, and beside them the iterations actually needed to reach
+    eps against x* and the time they take."""
+    cands = sorted({0, cfg.r} | {r for r in (32, 100, 400, 1000, 4000) if r < cfg.r})
+    K = 100
+
+    def wall(r, it, reps=9):
+        # median batch time of graph replays (least host noise)
+        pl = hd.Plan(ctx, B, "descriptors", alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r,
+                     k_y=cfg.k_y, top_k=K)
+        pl.run(Qd[0])
+        ts = []
+        for k in range(reps):
+            t0 = time.perf_counter()
+            pl.run(Qd[k % Qd.shape[0]])
+            ts.append(time.perf_counter() - t0)
+        pl.close()
+        return 1e3 * float(np.median(ts))
+
+    fixed, per_it = [], []
+    for r in cands:
+        t1, t3 = wall(r, 1), wall(r, 3)
+        per_it.append(max(0.0, (t3 - t1) / 2))
+        fixed.append(max(0.0, t1 - per_it[-1]))
+    plan = hd.rank_plan(fx.lam, cands, alpha=cfg.alpha, eps=eps, lambda_min=-1.0,
+                        fixed_ms=fixed, iter_ms=per_it)
+    truths, _ = exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np)
+    buf = {"x": torch.empty((B, fx.n), dtype=torch.float32, device=Qd.device)}
+    rows = []
+    for c, r in enumerate(cands):
+        errs = error_curve(args, cfg, ctx, Qd, truths, r, eps, buf, np)
+        hit = [i for i, v in enumerate(errs) if v <= eps]
+        mi = hit[0] if hit else None
+        rows.append({"r": r, "fixed_ms": round(fixed[c], 3), "iter_ms": round(per_it[c], 3),
+                     "bound_iters": int(plan["iters"][c]), "predicted_ms": round(float(plan["pred_ms"][c]), 3),
+                     "measured_iters": mi, "measured_ms": round(fixed[c] + mi * per_it[c], 3) if mi is not None else None,
+                     "error_floor": float(f"{min(errs):.4g}")})
+        log(f"[planner] r={r}: bound {plan['iters'][c]} it, {plan['pred_ms'][c]:.1f} ms; measured {mi} it")
+    del buf
+    reach = [x for x in rows if x["measured_ms"] is not None]
+    best_meas = min(reach, key=lambda x: x["measured_ms"])["r"] if reach else None
+    return {"eps": eps, "norm": "bound on the relative A-norm error; measured: relative L2 error against x*",
+            "lambda_min": -1.0, "candidates": rows, "chosen_r": cands[plan["best"]],
+            "best_r_by_measured_iterations": best_meas}
 
 
 def measured_traffic(workload, dom, rec):

@@ -148,6 +148,25 @@ int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
 int hd_autotune(hd_ctx *ctx, int32_t batch, int32_t reps, double *times_ms);
 
 /*
+ * (r, i) planner (Section 5, eqs. (bound) and (cond-r)): for each candidate
+ * number of deflated eigenpairs cand_r[c] (0 <= r <= nlam), the number of CG
+ * iterations that the error bound guarantees to bring the relative A-norm
+ * error below eps, refined for up to 64 outlying eigenvalues above the rest;
+ * with per-candidate costs (fixed_ms: y, spectral term, combine and ranking;
+ * iter_ms: one CG iteration; both may be NULL) also the predicted time and
+ * the fastest candidate. lambda (host, nlam values): the leading eigenvalues
+ * of S, descending (the loaded Lambda1); lambda_min: a lower value for the
+ * smallest eigenvalue of S (-1 is always valid); eigenvalues past nlam are
+ * taken as lambda[nlam-1]. Host only; no device work.
+ * Outputs (host): iters_out[ncand], pred_ms_out[ncand] (may be NULL), *best
+ * (index of the fastest candidate, -1 without costs; may be NULL).
+ * Errors: HD_EINVAL (arguments).
+ */
+int hd_rank_plan(int32_t nlam, const double *lambda, double lambda_min, double alpha, double eps,
+                 int32_t ncand, const int32_t *cand_r, const double *fixed_ms, const double *iter_ms,
+                 int32_t *iters_out, double *pred_ms_out, int32_t *best);
+
+/*
  * Load the database descriptors used to build y from query descriptors
  * (Section 3: nearest neighbours of the query in the dataset). V (host,
  * fp32, n x d row-major, unit-norm rows so that the dot product is the

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhd.so")
 SOURCES = ["k_cg.hip", "k_spmm.hip", "k_ugemm.hip", "k_ugemm_bf16.hip", "k_sim.hip", "k_topk.hip",
-           "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp"]
+           "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp"]
 ARCH = "gfx950"
 
 

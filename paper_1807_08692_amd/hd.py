@@ -55,7 +55,27 @@ _SIGS = {
     "hd_plan_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)]),
     "hd_plan_run": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "hd_plan_destroy": (None, [_P]),
+    "hd_rank_plan": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
 }
+
+
+def rank_plan(lam, cand_r, *, alpha=0.99, eps=1e-3, lambda_min=-1.0, fixed_ms=None, iter_ms=None):
+    """(r, i) planner (hd_rank_plan): iterations the CG bound guarantees for
+    each candidate rank, and with costs the predicted times and the best."""
+    lam = np.ascontiguousarray(lam, np.float64)
+    cr = np.ascontiguousarray(cand_r, np.int32)
+    it = np.zeros(cr.size, np.int32)
+    pm = np.zeros(cr.size, np.float64)
+    best = ctypes.c_int32(-1)
+    fx = np.ascontiguousarray(fixed_ms, np.float64) if fixed_ms is not None else None
+    im = np.ascontiguousarray(iter_ms, np.float64) if iter_ms is not None else None
+    _check(lib().hd_rank_plan(int(lam.size), lam.ctypes.data_as(_P), float(lambda_min), float(alpha),
+                              float(eps), int(cr.size), cr.ctypes.data_as(_P),
+                              None if fx is None else fx.ctypes.data_as(_P),
+                              None if im is None else im.ctypes.data_as(_P),
+                              it.ctypes.data_as(_P), pm.ctypes.data_as(_P), ctypes.byref(best)))
+    return {"iters": it, "pred_ms": pm if fx is not None else None, "best": best.value}
 
 # Launch parameters (hd_tune_key)
 TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2}
