@@ -58,8 +58,10 @@ typedef enum {
     HD_F32 = 0,
     HD_BF16 = 1,          /* bfloat16, rounded to nearest even from the fp32 input */
     HD_FP8_E4M3 = 2,      /* OCP e4m3 with one fp32 scale per column (U1) or row (V) */
-    HD_BF16X2 = 3         /* U1 only: two bfloat16 terms hi + lo, hi = RNE(u),
+    HD_BF16X2 = 3,        /* U1 only: two bfloat16 terms hi + lo, hi = RNE(u),
                              lo = RNE(u - hi) (about 16 significant bits) */
+    HD_SPARSE_F32 = 4     /* U1 only, set by hd_load_eigs_sparse: sparsified
+                             fp32 U1 (SHybrid) */
 } hd_dtype;
 
 /* hd_load_graph flags. */
@@ -165,6 +167,22 @@ int hd_autotune(hd_ctx *ctx, int32_t batch, int32_t reps, double *times_ms);
 int hd_rank_plan(int32_t nlam, const double *lambda, double lambda_min, double alpha, double eps,
                  int32_t ncand, const int32_t *cand_r, const double *fixed_ms, const double *iter_ms,
                  int32_t *iters_out, double *pred_ms_out, int32_t *best);
+
+/*
+ * SHybrid (Section 6.2): load a sparsified U1 (most entries set to zero,
+ * not renormalised) and its eigenvalues; the hybrid method then runs with
+ * sparse eigenvector products (one wave per item or component, gathering
+ * rows of the small dense operand). U~ is given by item in CSR form (host):
+ * rowptr[n+1] (int64, from 0, non-decreasing, ending at nnz), col[nnz]
+ * (component ids in [0, r), strictly increasing within a row), val[nnz]
+ * (fp32, finite); lambda as for hd_load_eigs. The library keeps the CSR and
+ * builds the by-component (CSC) copy. Replaces any loaded eigenpairs; queries
+ * may use a prefix rank_r as with dense U1. The continuous-batching server
+ * does not take sparse U1 (HD_ESTATE from hd_serve_open).
+ * Errors: HD_ESTATE (no graph), HD_EINVAL (r, arrays, lambda).
+ */
+int hd_load_eigs_sparse(hd_ctx *ctx, int32_t r, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                        const float *val, const double *lambda);
 
 /*
  * Load the database descriptors used to build y from query descriptors

@@ -17,7 +17,8 @@ thread_local std::string g_err;
 }  // namespace hdi
 
 static int64_t ctx_bytes(const hd_ctx *c) {
-    const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->V,
+    const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->Usr, &c->Usc,
+                           &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                            &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
                            &c->topk, &c->err, &c->qsplit};
@@ -64,7 +65,8 @@ void hd_destroy(hd_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->V,
+    DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->Usr, &c->Usc,
+                           &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                      &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
                      &c->topk, &c->err, &c->qsplit};
@@ -172,6 +174,8 @@ int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, cons
         c->U.release();
         c->Ub.release();
         c->UbT.release();
+        for (DevBuf *b : {&c->Usr, &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv}) b->release();
+        c->u_dtype = HD_F32;
         c->lam.release();
         c->r = c->rp = 0;
         c->V.release();
@@ -202,6 +206,8 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
     c->U.release();
     c->Ub.release();
     c->UbT.release();
+    for (DevBuf *b : {&c->Usr, &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv}) b->release();
+    c->u_dtype = HD_F32;
     if (r == 0) {
         c->lam.release();
         c->r = c->rp = 0;
@@ -258,6 +264,73 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
     c->r = r;
     c->rp = rp;
     c->u_dtype = dtype;
+    return HD_OK;
+}
+
+int hd_load_eigs_sparse(hd_ctx *c, int32_t r, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                        const float *val, const double *lambda) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_load_eigs_sparse: NULL context");
+    if (c->n == 0) return fail(HD_ESTATE, "hd_load_eigs_sparse: no graph loaded");
+    const int64_t n = c->n;
+    if (r < 1 || r > n) return fail(HD_EINVAL, "hd_load_eigs_sparse: r=%d not in [1, n]", r);
+    if (nnz < 0 || !rowptr || !lambda || (nnz > 0 && (!col || !val)))
+        return fail(HD_EINVAL, "hd_load_eigs_sparse: NULL array or nnz < 0");
+    if (rowptr[0] != 0 || rowptr[n] != nnz) return fail(HD_EINVAL, "hd_load_eigs_sparse: rowptr must run from 0 to nnz");
+    for (int64_t i = 0; i < n; ++i) {
+        if (rowptr[i + 1] < rowptr[i]) return fail(HD_EINVAL, "hd_load_eigs_sparse: rowptr decreases at row %lld", (long long)i);
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= r || (e > rowptr[i] && col[e] <= col[e - 1]))
+                return fail(HD_EINVAL, "hd_load_eigs_sparse: row %lld: component ids out of range or not increasing", (long long)i);
+            if (!std::isfinite(val[e])) return fail(HD_EINVAL, "hd_load_eigs_sparse: non-finite value in row %lld", (long long)i);
+        }
+    }
+    for (int k = 0; k < r; ++k)
+        if (!(std::fabs(lambda[k]) <= 1.0 + 1e-6))
+            return fail(HD_EINVAL, "hd_load_eigs_sparse: lambda[%d]=%g outside [-1, 1]", k, lambda[k]);
+    HIP_TRY(hipSetDevice(c->device));
+    c->U.release();
+    c->Ub.release();
+    c->UbT.release();
+    const int rp = (r + 31) / 32 * 32;
+    // by-component copy: counting sort of the entries by component
+    std::vector<int64_t> cptr((size_t)rp + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) ++cptr[(size_t)col[e] + 1];
+    for (int k = 0; k < rp; ++k) cptr[(size_t)k + 1] += cptr[(size_t)k];
+    std::vector<int32_t> crow((size_t)(nnz > 0 ? nnz : 1));
+    std::vector<float> cval((size_t)(nnz > 0 ? nnz : 1));
+    {
+        std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                const int64_t p = fill[(size_t)col[e]]++;
+                crow[(size_t)p] = (int32_t)i;
+                cval[(size_t)p] = val[e];
+            }
+    }
+    const size_t nz = (size_t)(nnz > 0 ? nnz : 1);
+    HIP_TRY(c->Usr.ensure((size_t)(n + 1) * sizeof(int64_t)));
+    HIP_TRY(c->Usc.ensure(nz * sizeof(int32_t)));
+    HIP_TRY(c->Usv.ensure(nz * sizeof(float)));
+    HIP_TRY(c->Ustp.ensure(cptr.size() * sizeof(int64_t)));
+    HIP_TRY(c->Ustr.ensure(nz * sizeof(int32_t)));
+    HIP_TRY(c->Ustv.ensure(nz * sizeof(float)));
+    HIP_TRY(hipMemcpy(c->Usr.p, rowptr, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->Ustp.p, cptr.data(), cptr.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (nnz > 0) {
+        HIP_TRY(hipMemcpy(c->Usc.p, col, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->Usv.p, val, (size_t)nnz * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->Ustr.p, crow.data(), (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->Ustv.p, cval.data(), (size_t)nnz * sizeof(float), hipMemcpyHostToDevice));
+    }
+    std::vector<double> lam((size_t)rp, 0.0);
+    for (int k = 0; k < r; ++k) lam[(size_t)k] = lambda[k];
+    HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
+    HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->r = r;
+    c->rp = rp;
+    c->us_nnz = nnz;
+    c->u_dtype = HD_SPARSE_F32;
     return HD_OK;
 }
 
@@ -339,7 +412,10 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
 
     const int ldb = pow2_at_least(B);
     const size_t vec = (size_t)n * ldb * sizeof(float);
-    const int rk = (r_use + 31) / 32 * 32;
+    // the sparsified form keeps every loaded component's coefficient row (its
+    // item rows may name any of them; rows past r_use stay zero)
+    const bool sparse = c->u_sparse();
+    const int rk = sparse ? (r_use > 0 ? c->rp : 0) : (r_use + 31) / 32 * 32;
     const hd::RowPart rp = hd::make_row_part(n);
     int64_t rc;
     const int nchunk = hd::ut_p_chunks(n, &rc);
@@ -349,10 +425,10 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     HIP_TRY(c->Q.ensure(vec));
     if (rk > 0) {
         HIP_TRY(c->Z.ensure(vec));
-        HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
+        if (!sparse) HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
         HIP_TRY(c->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         HIP_TRY(c->Cs.ensure((size_t)rk * ldb * sizeof(float)));
-        if (c->u_dtype != HD_F32) {
+        if (c->u_bf16()) {
             HIP_TRY(c->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
             HIP_TRY(c->CsT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
             HIP_TRY(c->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
@@ -424,15 +500,21 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     }
 
     // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
-    const bool ubf = c->u_dtype != HD_F32;
+    const bool ubf = c->u_bf16();
     const bool two = c->u_dtype == HD_BF16X2;
+    const int64_t *Usr = c->Usr.as<int64_t>(), *Ustp = c->Ustp.as<int64_t>();
+    const int32_t *Usc = c->Usc.as<int32_t>(), *Ustr = c->Ustr.as<int32_t>();
+    const float *Usv = c->Usv.as<float>(), *Ustv = c->Ustv.as<float>();
     const float *U = c->U.as<float>();
     const uint16_t *Ub = c->Ub.as<uint16_t>(), *UbT = c->UbT.as<uint16_t>();
     const uint16_t *Ubl = two ? Ub + (size_t)n * c->rp : nullptr;
     const uint16_t *UbTl = two ? UbT + (size_t)c->rp * c->ldut : nullptr;
     uint16_t *ClT_hi = c->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
     uint16_t *CsT_hi = c->CsT.as<uint16_t>(), *CsT_lo = CsT_hi ? CsT_hi + (size_t)rk * ldb : nullptr;
-    if (rk > 0) {
+    if (rk > 0 && sparse) {
+        LAUNCH(K_GATHER, hd::launch_sp_gather_proj(B, ky, yi, yv, n, Usr, Usc, Usv, rk, r_use, c->lam.as<double>(),
+                                                   o->alpha, ldb, c->Cs.as<float>(), c->Cl.as<float>(), s));
+    } else if (rk > 0) {
         LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, ubf ? (const void *)Ub : (const void *)U,
                                                 Ubl, ubf ? 1 : 0, c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
                                                 ldb, c->Cs.as<float>(), c->Cl.as<float>(), s));
@@ -458,7 +540,14 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         c->timing.tag = it;
         const hd::IterGuard g{nact_dev[(it - 1) & 1], ntile};
         const float *Zs = P;
-        if (rk > 0) {
+        if (rk > 0 && sparse) {
+            if (it > 1)
+                LAUNCH(K_UT_P, hd::launch_sp_utp(rk, r_use, Ustp, Ustr, Ustv, P, ldb, c->lam.as<double>(),
+                                                 c->Cl.as<float>(), g, s));
+            LAUNCH(K_U_C, hd::launch_sp_uc(n, Usr, Usc, Usv, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(),
+                                           g, s));
+            Zs = c->Z.as<float>();
+        } else if (rk > 0) {
             if (it > 1) {
                 if (ubf) {
                     // PT was written by the previous iteration's update_xp
@@ -531,7 +620,9 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         xq = c->xbuf.as<float>();
     }
     if (x_out || o->top_k > 0) {
-        if (ubf && rk > 0) {
+        if (sparse && rk > 0) {
+            LAUNCH(K_COMBINE, hd::launch_sp_combine(n, B, Usr, Usc, Usv, c->Cs.as<float>(), ldb, X, xq, n, s));
+        } else if (ubf && rk > 0) {
             LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, Ub, Ubl, c->rp, rk, CsT_hi, CsT_lo, ldb, X, xq, n, s,
                                                         c->tv(HD_TUNE_UC_NT, ldb)));
         } else {

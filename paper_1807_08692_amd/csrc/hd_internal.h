@@ -160,6 +160,9 @@ struct hd_ctx {
     int r = 0, rp = 0, u_dtype = HD_F32;
     int64_t ldut = 0;
     DevBuf U, Ub, UbT, lam;
+    // sparsified U1 (SHybrid): by item (CSR) and by component (CSC, rp + 1 pointers)
+    DevBuf Usr, Usc, Usv, Ustp, Ustr, Ustv;
+    int64_t us_nnz = 0;
     // descriptors: V (fp32) or Vb (bf16), N x ldv
     int d = 0, ldv = 0, v_dtype = HD_F32;
     DevBuf V, Vb;
@@ -171,6 +174,8 @@ struct hd_ctx {
     Timing timing;
     int tune[HD_TUNE_NKEYS] = {0, 0, 0};  // launch parameters (0 = default)
 
+    bool u_bf16() const { return u_dtype == HD_BF16 || u_dtype == HD_BF16X2; }
+    bool u_sparse() const { return u_dtype == HD_SPARSE_F32; }
     // second bfloat16 terms of the two-term U1 form (null otherwise)
     const uint16_t *ub_lo() const {
         return u_dtype == HD_BF16X2 ? Ub.as<uint16_t>() + (size_t)n * rp : nullptr;

@@ -159,4 +159,18 @@ size_t topk_scratch_bytes(int B, int64_t n, int K);
 hipError_t launch_topk(int B, int64_t n, const float *x, int64_t ldx, int K, void *scratch,
                        int32_t *ids, float *scores, int transform, hipStream_t s);
 
+// ---- SHybrid: sparsified U1 (k_sparse_u.hip). U~ by item (CSR rptr / rcol /
+//      rval, N rows) and by component (CSC cptr / crow / cval, rk columns) ----
+hipError_t launch_sp_utp(int rk, int r_use, const int64_t *cptr, const int32_t *crow, const float *cval,
+                         const float *P, int ldb, const double *lam, float *Cl, IterGuard g, hipStream_t s);
+hipError_t launch_sp_uc(int64_t N, const int64_t *rptr, const int32_t *rcol, const float *rval,
+                        const float *Cl, int ldb, const float *P, double alpha, float *Z, IterGuard g,
+                        hipStream_t s);
+hipError_t launch_sp_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
+                                 const int64_t *rptr, const int32_t *rcol, const float *rval, int rk,
+                                 int r_use, const double *lam, double alpha, int ldb, float *Cs, float *Cl,
+                                 hipStream_t s, const int32_t *colmap = nullptr);
+hipError_t launch_sp_combine(int64_t N, int B, const int64_t *rptr, const int32_t *rcol, const float *rval,
+                             const float *Cs, int ldc, const float *X, float *x, int64_t ldx, hipStream_t s);
+
 }  // namespace hd

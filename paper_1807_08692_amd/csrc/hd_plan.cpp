@@ -36,7 +36,8 @@ std::vector<intptr_t> snapshot(const hd_ctx *c) {
     const DevBuf *bufs[] = {&c->rowptr, &c->col, &c->val, &c->U,    &c->Ub,   &c->UbT,  &c->lam,
                             &c->V,      &c->Vb,  &c->X,   &c->R,    &c->P,    &c->Q,    &c->Z,
                             &c->Cpart,  &c->Cl,  &c->Cs,  &c->ClT,  &c->CsT,  &c->PT,   &c->part,
-                            &c->scal,   &c->xbuf, &c->sim, &c->ybuf, &c->topk, &c->err, &c->qsplit};
+                            &c->scal,   &c->xbuf, &c->sim, &c->ybuf, &c->topk, &c->err, &c->qsplit,
+                            &c->Usr,    &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv};
     std::vector<intptr_t> v;
     for (const DevBuf *b : bufs) v.push_back((intptr_t)b->p);
     const int64_t meta[] = {c->n, c->nnz, c->r, c->rp, c->u_dtype, c->ldut, c->d, c->ldv, c->v_dtype};

@@ -11,11 +11,14 @@
 // solve. The number of columns is chosen against an HBM budget at open time.
 #include "hd_internal.h"
 
+#include <vector>
+
 namespace {
 
 struct Srv {
     hd_ctx *c = nullptr;
     hd_query_opts o{};
+    std::vector<intptr_t> data;  // the context's data the server was opened on
     int slots = 0, ldb = 0, rk = 0, r_use = 0;
     hipStream_t s = nullptr;
     hd::RowPart rp{};
@@ -48,7 +51,16 @@ int64_t bytes_per_column(const hd_ctx *c, int rk, int nchunk, int nblk, int top_
     // X R P Q Z, the partial and full coefficient columns, reduction
     // partials, the gathered x columns, the split P^T of the bfloat16 forms
     return 5 * 4 * c->n + (int64_t)4 * rk * (nchunk + 4) + 8 * nblk + 4 * c->n * 2 +
-           (c->u_dtype != HD_F32 && rk > 0 ? 4 * c->ldut : 0) + (int64_t)top_k * 8 + (int64_t)ky * 8 + 64;
+           (c->u_bf16() && rk > 0 ? 4 * c->ldut : 0) + (int64_t)top_k * 8 + (int64_t)ky * 8 + 64;
+}
+
+// The context's loaded data and layouts; a server refuses to run once they
+// have changed (its buffers are sized for what it was opened on).
+std::vector<intptr_t> data_of(const hd_ctx *c) {
+    return {(intptr_t)c->n, (intptr_t)c->nnz, (intptr_t)c->r, (intptr_t)c->rp, (intptr_t)c->u_dtype,
+            (intptr_t)c->ldut, (intptr_t)c->d, (intptr_t)c->ldv, (intptr_t)c->v_dtype,
+            (intptr_t)c->rowptr.p, (intptr_t)c->U.p, (intptr_t)c->Ub.p, (intptr_t)c->UbT.p,
+            (intptr_t)c->lam.p, (intptr_t)c->V.p, (intptr_t)c->Vb.p};
 }
 
 }  // namespace
@@ -72,6 +84,8 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
         return fail(HD_EINVAL, "hd_serve_open: top_k must be in [1, min(n, 1024)]");
     const int r_use = o->rank_r < 0 ? c->r : o->rank_r;
     if (r_use > c->r) return fail(HD_ESTATE, "hd_serve_open: rank_r=%d above the %d loaded eigenpairs", r_use, c->r);
+    if (r_use > 0 && c->u_sparse())
+        return fail(HD_ESTATE, "hd_serve_open: the server does not take sparsified eigenvectors");
     HIP_TRY(hipSetDevice(c->device));
     const int rk = (r_use + 31) / 32 * 32;
     const hd::RowPart rp = hd::make_row_part(c->n);
@@ -92,6 +106,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
     hd_server *sv = static_cast<hd_server *>(v);
     v->c = c;
     v->o = *o;
+    v->data = data_of(c);
     v->slots = slots;
     v->ldb = ldb;
     v->rk = rk;
@@ -123,7 +138,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
         SRV_TRY(v->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->Cs.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
-        if (c->u_dtype != HD_F32) SRV_TRY(v->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
+        if (c->u_bf16()) SRV_TRY(v->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
         SRV_TRY(v->csc.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->cst.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
     }
@@ -200,6 +215,8 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     if (!v) return fail(HD_EINVAL, "hd_serve_submit: NULL server");
     if (n < 0 || (n > 0 && !tickets)) return fail(HD_EINVAL, "hd_serve_submit: bad n or NULL tickets");
     hd_ctx *c = v->c;
+    if (data_of(c) != v->data)
+        return fail(HD_ESTATE, "%s: the context's data changed since the server was opened", "hd_serve_submit");
     const int ky = v->o.k_y, ldb = v->ldb;
     if (q_desc) {
         if (c->d == 0) return fail(HD_ESTATE, "hd_serve_submit: descriptors not loaded");
@@ -250,7 +267,7 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     HIP_TRY(hd::launch_colsq_part(N, ldb, v->R.as<float>(), v->rp, v->part.as<double>(), s));
     HIP_TRY(hd::launch_init_cols(ldb, v->part.as<double>(), v->rp.nblk, v->st, cols, v->maxit.as<int32_t>(), m, s));
     if (v->rk > 0) {
-        const bool ubf = c->u_dtype != HD_F32;
+        const bool ubf = c->u_bf16();
         HIP_TRY(hd::launch_gather_proj(m, ky, yi, yv, N, ubf ? (const void *)c->Ub.p : (const void *)c->U.p,
                                        c->ub_lo(), ubf ? 1 : 0, c->rp, v->rk, v->r_use, c->lam.as<double>(), v->o.alpha,
                                        ldb, v->Cs.as<float>(), nullptr, s, cols));
@@ -273,11 +290,13 @@ int hd_serve_step(hd_server *v, int32_t iters) {
     if (!v) return fail(HD_EINVAL, "hd_serve_step: NULL server");
     if (iters < 0) return fail(HD_EINVAL, "hd_serve_step: iters < 0");
     hd_ctx *c = v->c;
+    if (data_of(c) != v->data)
+        return fail(HD_ESTATE, "%s: the context's data changed since the server was opened", "hd_serve_step");
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = v->s;
     const int64_t N = c->n;
     const int ldb = v->ldb, rk = v->rk;
-    const bool ubf = c->u_dtype != HD_F32;
+    const bool ubf = c->u_bf16();
     const hd::IterGuard g{nullptr, 0};
     float *X = v->X.as<float>(), *R = v->R.as<float>(), *P = v->P.as<float>(), *Q = v->Q.as<float>();
     uint16_t *ClT_hi = v->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
@@ -322,6 +341,8 @@ int hd_serve_poll(hd_server *v, int32_t max_out, int64_t *tickets, int32_t *ids,
     if (!v) return fail(HD_EINVAL, "hd_serve_poll: NULL server");
     if (max_out < 0 || (max_out > 0 && !tickets)) return fail(HD_EINVAL, "hd_serve_poll: bad max_out or NULL tickets");
     hd_ctx *c = v->c;
+    if (data_of(c) != v->data)
+        return fail(HD_ESTATE, "%s: the context's data changed since the server was opened", "hd_serve_poll");
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = v->s;
     const int64_t N = c->n;
@@ -342,7 +363,7 @@ int hd_serve_poll(hd_server *v, int32_t max_out, int64_t *tickets, int32_t *ids,
     HIP_TRY(hd::launch_gather_cols(N, ldb, v->X.as<float>(), v->Cs.as<float>(), rk, v->cols.as<int32_t>(), m,
                                    ldc, v->xc.as<float>(), v->csc.as<float>(), s));
     float *xq = v->xq.as<float>();
-    if (rk > 0 && c->u_dtype != HD_F32) {
+    if (rk > 0 && c->u_bf16()) {
         uint16_t *hi = v->cst.as<uint16_t>(), *lo = hi + (size_t)rk * ldc;
         HIP_TRY(hd::launch_split_t(v->csc.as<float>(), rk, ldc, hi, lo, hd::IterGuard{nullptr, 0}, s));
         HIP_TRY(hd::launch_combine_bf16(N, m, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, hi, lo, ldc, v->xc.as<float>(), xq,

@@ -38,7 +38,7 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
     const int64_t n = c->n;
     const int ldb = pow2_at_least(batch);
     const int rk = c->rp;
-    const bool ubf = c->u_dtype != HD_F32 && rk > 0;
+    const bool ubf = c->u_bf16() && rk > 0;
     const size_t vec = (size_t)n * ldb * sizeof(float);
     const hd::RowPart rp = hd::make_row_part(n);
     int64_t rc;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhd.so")
 
 HD_OK, HD_EINVAL, HD_ENOMEM, HD_EDEVICE, HD_ESTATE = 0, -1, -2, -3, -4
 COL_CONVERGED, COL_MAXITER, COL_ZERO_RHS, COL_BREAKDOWN = 0, 1, 2, 3
-HD_F32, HD_BF16, HD_FP8_E4M3, HD_BF16X2 = 0, 1, 2, 3
+HD_F32, HD_BF16, HD_FP8_E4M3, HD_BF16X2, HD_SPARSE_F32 = 0, 1, 2, 3, 4
 HD_GRAPH_NORMALIZE, HD_GRAPH_CHECK_SYMMETRY = 1, 2
 TOPK_MAX = 1024
 
@@ -31,6 +31,7 @@ _SIGS = {
     "hd_load_graph": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P, ctypes.c_uint32]),
     "hd_load_eigs": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "hd_load_descriptors": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32]),
+    "hd_load_eigs_sparse": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
     "hd_query_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       _P, _P, _P, _P]),
     "hd_rank": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
@@ -181,6 +182,15 @@ class Context:
         la, lp = _host(lam if r else np.zeros(1), np.float64)
         _check(lib().hd_load_eigs(self._h, r, Up, lp, _DTYPES[dtype]))
         self.r = r
+
+    def load_eigs_sparse(self, r, rowptr, col, val, lam):
+        """Sparsified U1 (SHybrid) by item in CSR form: rowptr (n+1), col
+        (component ids, increasing within a row), val (fp32); lam (r)."""
+        rp_, rpp = _host(rowptr, np.int64)
+        cl, clp = _host(col, np.int32)
+        vl, vlp = _host(val, np.float32)
+        lm, lmp = _host(lam, np.float64)
+        _check(lib().hd_load_eigs_sparse(self._h, int(r), int(cl.size), rpp, clp, vlp, lmp))
 
     def load_descriptors(self, V, dtype="f32"):
         Va, Vp = _host(V, np.float32)

@@ -344,6 +344,38 @@ def top_eigs_chebyshev(n, rowptr, col, sval, r, seed, guard=None, degree=12,
     return (X[:, :r].cpu().numpy(), lam[:r].cpu().numpy(), res[:r].cpu().numpy())
 
 
+def sparsify_eigvecs(U: np.ndarray, sparsity: float):
+    """SHybrid's sparsified embeddings (Section 6.2): the smallest entries of
+    U1 in magnitude are set to zero, one global threshold over the whole
+    matrix, until the fraction `sparsity` of entries is zero; the kept values
+    are not renormalised. Returns U1 by item in CSR form (rowptr int64[n+1],
+    col int32 component ids increasing within each row, val float32)."""
+    n, r = U.shape
+    keep = int(round((1.0 - sparsity) * n * r))
+    flat = np.abs(np.asarray(U, np.float32)).ravel()
+    if keep <= 0:
+        mask = np.zeros(n * r, bool)
+    elif keep >= flat.size:
+        mask = np.ones(n * r, bool)
+    else:
+        part = np.argpartition(-flat, keep - 1)[:keep]   # the keep largest magnitudes
+        mask = np.zeros(n * r, bool)
+        mask[part] = True
+    mask = mask.reshape(n, r)
+    rowptr = np.zeros(n + 1, np.int64)
+    rowptr[1:] = np.cumsum(mask.sum(1))
+    rows, cols = np.nonzero(mask)                       # row-major order, cols increasing
+    return rowptr, cols.astype(np.int32), np.asarray(U, np.float32)[rows, cols]
+
+
+def sparse_to_dense(n, r, rowptr, col, val) -> np.ndarray:
+    """Dense n x r float64 copy of a CSR matrix (for the oracle)."""
+    D = np.zeros((n, r))
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    D[rows, col] = val
+    return D
+
+
 # --------------------------------------------------------------------------
 # Fixture bundle
 # --------------------------------------------------------------------------

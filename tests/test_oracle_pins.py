@@ -404,3 +404,21 @@ def test_isolated_node_keeps_its_observation():
     assert abs(x[4] - (1 - ALPHA) * 0.7) < 1e-15
     xc, *_ = O.cg(g, None, None, ALPHA, y, 200, 1e-15)
     assert abs(xc[4] - (1 - ALPHA) * 0.7) < 1e-14
+
+
+def test_sparsify_keeps_the_largest_entries():
+    """SHybrid input (Section 6.2): a global magnitude threshold; the kept
+    count matches the sparsity and every kept entry is at least as large as
+    every dropped one."""
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((300, 40)).astype(np.float32)
+    for sp in (0.5, 0.9, 0.99):
+        rp, col, val = W.sparsify_eigvecs(U, sp)
+        keep = int(round((1 - sp) * U.size))
+        assert rp[-1] == keep == col.size
+        D = W.sparse_to_dense(300, 40, rp, col, val)
+        kept = np.abs(U[D != 0])
+        dropped = np.abs(U[D == 0])
+        assert kept.min() >= dropped.max()
+        assert np.array_equal(D[D != 0], U[D != 0].astype(np.float64))
+        assert all(np.all(np.diff(col[rp[i]:rp[i + 1]]) > 0) for i in range(300))
