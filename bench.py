@@ -58,8 +58,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="n1m")
     p.add_argument("--forms", default=None,
-                   help="comma list of U1 storage forms to measure, from f32, bf16, bf16x2 "
-                        "(default: bf16x2,bf16 for n1m and n2m, f32 otherwise)")
+                   help="comma list of U1 storage forms to measure, from f32, bf16, bf16x2 and "
+                        "sparseXX (SHybrid, XX%% of U1 zeroed) (default: bf16x2,bf16,sparse99 for "
+                        "n1m and n2m, f32 otherwise)")
     p.add_argument("--descriptors", choices=["f32", "bf16"], default=None,
                    help="descriptor storage (default: bf16 for n1m and n2m, f32 otherwise)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,7 +132,7 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     cfg = W.CONFIGS[args.workload]
     big = args.workload in ("n1m", "n2m")
-    forms = [f for f in (args.forms or ("bf16x2,bf16" if big else "f32")).split(",") if f]
+    forms = [f for f in (args.forms or ("bf16x2,bf16,sparse99" if big else "f32")).split(",") if f]
     vprec = args.descriptors or ("bf16" if big else "f32")
     B = cfg.batch
     nbatch = 4
@@ -192,9 +193,16 @@ def main():
                            if np.any(sts == code)}}
 
     def run_form(form):
-        """Calibrate and time one storage form of U1; returns its record."""
+        """Calibrate and time one storage form of U1; returns its record.
+        "sparseXX": SHybrid with XX% of U1's entries zeroed (fp32 values)."""
         t1 = time.time()
-        ctx.load_eigs(fx.U, fx.lam, dtype=form)
+        if form.startswith("sparse"):
+            sp = float(form[6:]) / 100.0
+            rp_, col_, val_ = W.sparsify_eigvecs(fx.U, sp)
+            ctx.load_eigs_sparse(fx.U.shape[1], rp_, col_, val_, fx.lam)
+            del rp_, col_, val_
+        else:
+            ctx.load_eigs(fx.U, fx.lam, dtype=form)
         torch.cuda.synchronize()
         log(f"[setup] U1 {form}, descriptors {vprec}: loaded in {time.time() - t1:.1f}s, "
             f"library holds {ctx.device_bytes() / 2**20:.0f} MiB on the device")
@@ -223,6 +231,14 @@ def main():
                 ih, ip = cal["iters"][str(e)]["hybrid"], cal["iters"][str(e)]["plain"]
                 if ih is not None and ip is not None:
                     plans.append((f"rel-err {e:g}", e, (ih, 0.0), (ip, 0.0)))
+        if not plans and cal is not None:
+            # the hybrid never reaches any target (its error floor lies above):
+            # time it at the iteration of its smallest error, plain CG at the
+            # loosest target
+            curve = cal["rel_err_by_iter"]["hybrid"]
+            i_floor = int(np.argmin(curve))
+            ip_ = cal["iters"][str(max(eps_list))]["plain"] or args.calib_max_iter
+            plans.append((f"hybrid at its error floor {min(curve):.3g}", None, (i_floor, 0.0), (ip_, 0.0)))
         if not plans:
             plans.append((f"rel-res {cfg.tol:g}", None, (cfg.max_iter, cfg.tol), (cfg.max_iter, cfg.tol)))
         # breakdown pass at the first target: every kernel bracketed by events
@@ -231,7 +247,7 @@ def main():
         _, _, _, tm_all = timed(-1, ih0, th0, max(3, args.steps // 4), True)
         costed = [k for k, (ms, cnt) in tm_all.items() if cnt and algorithmic_cost(k, 1, 1, 64, 32, 1, 1, 1)]
         dom = max(costed, key=lambda k: tm_all[k][0])
-        su = {"f32": 4, "bf16": 2, "bf16x2": 4}[form]
+        su = {"f32": 4, "bf16": 2, "bf16x2": 4}.get(form, 4)
         sv = 4 if vprec == "f32" else 2
         kernels = {}
         for kind, (ms, cnt) in tm_all.items():
@@ -319,7 +335,8 @@ def main():
               f"{tgt['hybrid']['iters_max']} CG iterations, plain CG {tgt['plain_cg']['iters_max']})"
               if e0 is not None else (f"fixed iteration counts {args.iters} (hybrid, plain CG)" if args.iters
                                       else f"CG to relative residual {cfg.tol:g}"))
-    form_txt = {"f32": "FP32", "bf16": "BF16", "bf16x2": "two-term BF16 (hi+lo)"}[form0]
+    form_txt = {"f32": "FP32", "bf16": "BF16", "bf16x2": "two-term BF16 (hi+lo)"}.get(
+        form0, f"sparsified FP32 (SHybrid, {form0[6:]}% zeros)")
     result = {
         "metric": METRIC,
         "value": q_h,
@@ -359,7 +376,11 @@ def main():
 
     def use_form(f):
         if loaded[0] != f:
-            ctx.load_eigs(fx.U, fx.lam, dtype=f)
+            if f.startswith("sparse"):
+                rp_, col_, val_ = W.sparsify_eigvecs(fx.U, float(f[6:]) / 100.0)
+                ctx.load_eigs_sparse(fx.U.shape[1], rp_, col_, val_, fx.lam)
+            else:
+                ctx.load_eigs(fx.U, fx.lam, dtype=f)
             loaded[0] = f
 
     if not args.no_planner and not args.iters:
@@ -487,18 +508,18 @@ def planner_leg(args, cfg, fx, ctx, Qd, B, eps, hd, torch, np):
     cands = sorted({0, cfg.r} | {r for r in (32, 100, 400, 1000, 4000) if r < cfg.r})
     K = 100
 
-    def wall(r, it, reps=9):
-        # median batch time of graph replays (least host noise)
-        pl = hd.Plan(ctx, B, "descriptors", alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r,
-                     k_y=cfg.k_y, top_k=K)
-        pl.run(Qd[0])
-        ts = []
+    def wall(r, it, reps=5):
+        # device time of the whole path (sum of the per-kernel event times)
+        ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r, k_y=cfg.k_y, top_k=K)
+        torch.cuda.synchronize()
+        ctx.timing_enable(True)
         for k in range(reps):
-            t0 = time.perf_counter()
-            pl.run(Qd[k % Qd.shape[0]])
-            ts.append(time.perf_counter() - t0)
-        pl.close()
-        return 1e3 * float(np.median(ts))
+            ctx.query_batch(Qd[k % Qd.shape[0]], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r,
+                            k_y=cfg.k_y, top_k=K)
+        torch.cuda.synchronize()
+        tm = ctx.timing()
+        ctx.timing_enable(False)
+        return sum(v[0] for v in tm.values()) / reps
 
     fixed, per_it = [], []
     for r in cands:

@@ -239,6 +239,23 @@ int hd_query_batch(hd_ctx *ctx, int32_t B, const float *q_desc,
                    void *stream);
 
 /*
+ * General filters (Appendix A, eq. (2-main)): ranks by x = h(S) y for a
+ * polynomial h(x) = sum_{i=0}^{degree} coeffs[i] x^i (for instance a
+ * truncated heat kernel or any other series), computed as the spectral term
+ * U1 g(L1) U1^T y with g = h - h(0) (eq. (2-aux)) plus the temporal term
+ * h(S_r) y, S_r = S - U1 L1 U1^T, by Horner's rule on the deflated operator
+ * (degree sparse products, each with the U1 products of the loaded form);
+ * rank_r = 0 gives the plain polynomial filter h(S) y. Inputs and outputs as
+ * hd_query_batch (q_desc, or y_ids / y_val; rank_ids / rank_scores / x_out
+ * device, may be NULL); coeffs: host, degree + 1 values.
+ * Errors: as hd_query_batch, HD_EINVAL (degree not in [0, 4096], NULL or
+ * non-finite coefficients).
+ */
+int hd_query_filter(hd_ctx *ctx, int32_t B, const float *q_desc, const int32_t *y_ids, const float *y_val,
+                    int32_t degree, const double *coeffs, int32_t rank_r, int32_t k_y, int32_t top_k,
+                    int32_t *rank_ids, float *rank_scores, float *x_out, void *stream);
+
+/*
  * Query plans (batching form): the whole query path of hd_query_batch for a
  * fixed batch size B, input kind and options, captured once into a HIP
  * graph and replayed for each batch, so a batch costs one graph launch

@@ -195,6 +195,31 @@ def iterate(g: Graph64, U, lam, alpha, y_ids, y_val, max_iter, tol):
     return xs + xt, xs, xt, it, rr, st
 
 
+def filter_poly(g: Graph64, U, lam, coeffs, y_ids, y_val) -> np.ndarray:
+    """Appendix A, eqs. (series), (2-main), (2-aux): for a polynomial
+    h(x) = sum_i c_i x^i, x = h(S) y = U1 g(L1) U1^T y + h(S_r) y with
+    g(x) = h(x) - h(0) and S_r = S - U1 L1 U1^T. The temporal term is the sum
+    of c_i S_r^i y written out term by term (powers of S_r applied in turn);
+    double precision throughout."""
+    c = _c(coeffs, np.float64)
+    y = dense_y(g.n, y_ids, y_val)
+    r = 0 if U is None else np.asarray(U).shape[1]
+    x = np.zeros(g.n)
+    if r:
+        U = _c(U, np.float64)
+        lam = _c(lam, np.float64)
+        gl = np.zeros(r)
+        for i in range(1, c.size):
+            gl += c[i] * lam ** i
+        x += U @ (gl * (U.T @ y))
+    v = y.copy()
+    x += c[0] * v
+    for i in range(1, c.size):
+        v = csr_matvec(g, v) - (U @ (lam * (U.T @ v)) if r else 0.0)
+        x += c[i] * v
+    return x
+
+
 def truth_dense(S_dense: np.ndarray, alpha, y) -> np.ndarray:
     """Section 3, eqs. (temporal), (transfer): x* = (1 - alpha)(I - alpha S)^-1 y.
     I - alpha S is symmetric positive definite (spectrum of S in [-1, 1] and

@@ -18,7 +18,7 @@ thread_local std::string g_err;
 
 static int64_t ctx_bytes(const hd_ctx *c) {
     const DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->Usr, &c->Usc,
-                           &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->V,
+                           &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                            &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
                            &c->topk, &c->err, &c->qsplit};
@@ -66,7 +66,7 @@ void hd_destroy(hd_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     DevBuf *all[] = {&c->rowptr, &c->col, &c->val, &c->U, &c->Ub, &c->UbT, &c->lam, &c->Usr, &c->Usc,
-                           &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->V,
+                           &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                      &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
                      &c->topk, &c->err, &c->qsplit};
@@ -261,6 +261,7 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
     }
     HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
     HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->lam_host = lam;
     c->r = r;
     c->rp = rp;
     c->u_dtype = dtype;
@@ -327,6 +328,7 @@ int hd_load_eigs_sparse(hd_ctx *c, int32_t r, int64_t nnz, const int64_t *rowptr
     for (int k = 0; k < r; ++k) lam[(size_t)k] = lambda[k];
     HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
     HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->lam_host = lam;
     c->r = r;
     c->rp = rp;
     c->us_nnz = nnz;
@@ -388,7 +390,7 @@ int hd_rank(hd_ctx *c, int32_t B, int64_t n, const float *x, int64_t ldx, int32_
 int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
                      const float *y_val, const hd_query_opts *o, int32_t *rank_ids,
                      float *rank_scores, float *x_out, int32_t *y_ids_out, float *y_val_out,
-                     hipStream_t s, bool graph, int *last_iter_out) {
+                     hipStream_t s, bool graph, int *last_iter_out, const Filter *flt) {
     if (!c) return fail(HD_EINVAL, "hd_query_batch: NULL context");
     if (c->n == 0) return fail(HD_ESTATE, "hd_query_batch: no graph loaded");
     if (!o) return fail(HD_EINVAL, "hd_query_batch: NULL options");
@@ -511,18 +513,81 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     const uint16_t *UbTl = two ? UbT + (size_t)c->rp * c->ldut : nullptr;
     uint16_t *ClT_hi = c->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
     uint16_t *CsT_hi = c->CsT.as<uint16_t>(), *CsT_lo = CsT_hi ? CsT_hi + (size_t)rk * ldb : nullptr;
+    // a general filter's g(lambda_k) = h(lambda_k) - h(0) (Appendix A, eq. (2-aux))
+    const double *gv = nullptr;
+    if (flt && rk > 0) {
+        std::vector<double> g((size_t)rk, 0.0);
+        for (int k = 0; k < r_use; ++k) {
+            double acc = 0.0, pw = 1.0;
+            for (int i = 1; i <= flt->degree; ++i) {
+                pw *= c->lam_host[(size_t)k];
+                acc += flt->coeffs[i] * pw;
+            }
+            g[(size_t)k] = acc;
+        }
+        HIP_TRY(c->gfil.ensure(g.size() * sizeof(double)));
+        HIP_TRY(hipMemcpy(c->gfil.p, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
+        gv = c->gfil.as<double>();
+    }
     if (rk > 0 && sparse) {
         LAUNCH(K_GATHER, hd::launch_sp_gather_proj(B, ky, yi, yv, n, Usr, Usc, Usv, rk, r_use, c->lam.as<double>(),
-                                                   o->alpha, ldb, c->Cs.as<float>(), c->Cl.as<float>(), s));
+                                                   o->alpha, ldb, c->Cs.as<float>(), c->Cl.as<float>(), s,
+                                                   nullptr, gv));
     } else if (rk > 0) {
         LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, ubf ? (const void *)Ub : (const void *)U,
                                                 Ubl, ubf ? 1 : 0, c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
-                                                ldb, c->Cs.as<float>(), c->Cl.as<float>(), s));
+                                                ldb, c->Cs.as<float>(), c->Cl.as<float>(), s, nullptr, gv));
         if (ubf) {
             const hd::IterGuard none{nullptr, 0};
             LAUNCH(K_GATHER, hd::launch_split_t(c->Cs.as<float>(), rk, ldb, CsT_hi, CsT_lo, none, s));
             LAUNCH(K_GATHER, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, none, s));
         }
+    }
+
+    // ---- step 3 (general filter, Appendix A, eq. (2-main)): the temporal
+    // term h(S_r) y = sum_i c_i S_r^i y by Horner's rule, v = c_K y,
+    // v = c_i y + S_r v. S_r v comes from the operator kernels with alpha = -1
+    // and a zero P term: Z = -U1 L1 U1^T v, Q = (Z + S v) / 2 = S_r v / 2.
+    const float *temporal = X;
+    if (flt) {
+        const hd::IterGuard none{nullptr, 0};
+        const size_t nv2 = (size_t)n * ldb;
+        float *Zb = rk > 0 ? c->Z.as<float>() : nullptr;
+        LAUNCH(K_UPDATE_XP, hd::launch_filter_axpy(P, R, Q, nv2, flt->coeffs[flt->degree], 0.0, s));
+        for (int i = flt->degree - 1; i >= 0; --i) {
+            const float *Zs = X;  // zeros
+            if (rk > 0) {
+                if (sparse) {
+                    LAUNCH(K_UT_P, hd::launch_sp_utp(rk, r_use, Ustp, Ustr, Ustv, P, ldb, c->lam.as<double>(),
+                                                     c->Cl.as<float>(), none, s));
+                    LAUNCH(K_U_C, hd::launch_sp_uc(n, Usr, Usc, Usv, c->Cl.as<float>(), ldb, X, -1.0, Zb, none, s));
+                } else {
+                    if (ubf) {
+                        uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
+                        LAUNCH(K_UT_P, hd::launch_split_pt(n, ldb, P, c->ldut, PTh, PTl, none, s));
+                        LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb,
+                                                            c->Cpart.as<float>(), none, s, c->tv(HD_TUNE_UTP_NT, ldb)));
+                    } else {
+                        LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), none, s));
+                    }
+                    LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(),
+                                                           r_use, c->Cl.as<float>(), none, s));
+                    if (ubf) {
+                        LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, none, s));
+                        LAUNCH(K_U_C, hd::launch_u_c_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, X, -1.0, Zb,
+                                                          none, s, c->tv(HD_TUNE_UC_NT, ldb)));
+                    } else {
+                        LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, X, -1.0, Zb, none, s));
+                    }
+                }
+                Zs = Zb;
+            }
+            LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs,
+                                           Q, ldb, -1.0, rp, c->part.as<double>(), none, s,
+                                           c->tv(HD_TUNE_SPMM_CPL, ldb)));
+            LAUNCH(K_UPDATE_XP, hd::launch_filter_axpy(P, R, Q, nv2, flt->coeffs[i], 2.0, s));
+        }
+        temporal = P;
     }
 
     // ---- step 3: CG on the deflated system ----
@@ -590,7 +655,9 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         return HD_OK;
     };
     int last_iter = 0;
-    if (graph) {
+    if (flt) {
+        // no CG: the temporal term is already in P
+    } else if (graph) {
         for (int it = 1; it <= o->max_iter; ++it) {
             const int e = enqueue_iter(it);
             if (e != HD_OK) return e;
@@ -600,7 +667,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         const int e = enqueue_iter(1);
         if (e != HD_OK) return e;
     }
-    for (int it = 1; !graph && it <= o->max_iter; ++it) {
+    for (int it = 1; !flt && !graph && it <= o->max_iter; ++it) {
         if (it + 1 <= o->max_iter) {
             const int e = enqueue_iter(it + 1);
             if (e != HD_OK) return e;
@@ -621,12 +688,12 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     }
     if (x_out || o->top_k > 0) {
         if (sparse && rk > 0) {
-            LAUNCH(K_COMBINE, hd::launch_sp_combine(n, B, Usr, Usc, Usv, c->Cs.as<float>(), ldb, X, xq, n, s));
+            LAUNCH(K_COMBINE, hd::launch_sp_combine(n, B, Usr, Usc, Usv, c->Cs.as<float>(), ldb, temporal, xq, n, s));
         } else if (ubf && rk > 0) {
-            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, Ub, Ubl, c->rp, rk, CsT_hi, CsT_lo, ldb, X, xq, n, s,
-                                                        c->tv(HD_TUNE_UC_NT, ldb)));
+            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, Ub, Ubl, c->rp, rk, CsT_hi, CsT_lo, ldb, temporal, xq, n,
+                                                        s, c->tv(HD_TUNE_UC_NT, ldb)));
         } else {
-            LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, X, xq, n, s));
+            LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, temporal, xq, n, s));
         }
     }
     if (o->top_k > 0 && (rank_ids || rank_scores)) {
@@ -638,6 +705,25 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
 }
 
 extern "C" {
+
+int hd_query_filter(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids, const float *y_val,
+                    int32_t degree, const double *coeffs, int32_t rank_r, int32_t k_y, int32_t top_k,
+                    int32_t *rank_ids, float *rank_scores, float *x_out, void *stream) {
+    g_err.clear();
+    if (degree < 0 || degree > 4096) return fail(HD_EINVAL, "hd_query_filter: degree=%d not in [0, 4096]", degree);
+    if (!coeffs) return fail(HD_EINVAL, "hd_query_filter: NULL coefficients");
+    for (int i = 0; i <= degree; ++i)
+        if (!std::isfinite(coeffs[i])) return fail(HD_EINVAL, "hd_query_filter: coefficient %d not finite", i);
+    hd_query_opts o{0.5, 0, 0.0, rank_r, k_y, top_k};
+    const Filter f{degree, coeffs};
+    hipStream_t s = (hipStream_t)stream;
+    const int e = queue_query(c, B, q_desc, y_ids, y_val, &o, rank_ids, rank_scores, x_out, nullptr, nullptr, s,
+                              false, nullptr, &f);
+    if (e != HD_OK) return e;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->timing.on) HIP_TRY(c->timing.harvest(0));
+    return HD_OK;
+}
 
 int hd_query_batch(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
                    const float *y_val, const hd_query_opts *o, int32_t *rank_ids,

@@ -163,6 +163,8 @@ struct hd_ctx {
     // sparsified U1 (SHybrid): by item (CSR) and by component (CSC, rp + 1 pointers)
     DevBuf Usr, Usc, Usv, Ustp, Ustr, Ustv;
     int64_t us_nnz = 0;
+    std::vector<double> lam_host;  // the loaded eigenvalues, padded with zeros to rp
+    DevBuf gfil;                   // g(lambda) of a general filter
     // descriptors: V (fp32) or Vb (bf16), N x ldv
     int d = 0, ldv = 0, v_dtype = HD_F32;
     DevBuf V, Vb;
@@ -189,6 +191,11 @@ struct hd_ctx {
 };
 
 namespace hdi {
+// A polynomial filter h(x) = sum_{i <= degree} coeffs[i] x^i (Appendix A).
+struct Filter {
+    int degree;
+    const double *coeffs;
+};
 // Validate and queue the whole query path of hd_query_batch on stream s.
 // graph = false: the host watches the stopping test (one iteration of
 // lookahead) and returns after queueing the final steps. graph = true: all
@@ -197,7 +204,8 @@ namespace hdi {
 // error flag is left in c->err and the per-column results in c->st.
 int queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids, const float *y_val,
                 const hd_query_opts *o, int32_t *rank_ids, float *rank_scores, float *x_out,
-                int32_t *y_ids_out, float *y_val_out, hipStream_t s, bool graph, int *last_iter);
+                int32_t *y_ids_out, float *y_val_out, hipStream_t s, bool graph, int *last_iter,
+                const Filter *flt = nullptr);
 }  // namespace hdi
 
 // Launch `call` (a launcher returning hipError_t) as kernel kind `kind`,

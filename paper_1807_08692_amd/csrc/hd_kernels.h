@@ -72,7 +72,10 @@ hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                              hipStream_t s, const int32_t *colmap = nullptr);
+                              hipStream_t s, const int32_t *colmap = nullptr, const double *gv = nullptr);
+// P = c R + qs Q over n floats (polynomial filter step); qs = 0 does not read Q
+hipError_t launch_filter_axpy(float *P, const float *R, const float *Q, size_t n, double c, double qs,
+                              hipStream_t s);
 
 // ---- continuous batching (columns joining and leaving a running solve) ----
 // zero columns cols[0..ncols) of X, R and P
@@ -169,7 +172,7 @@ hipError_t launch_sp_uc(int64_t N, const int64_t *rptr, const int32_t *rcol, con
 hipError_t launch_sp_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                                  const int64_t *rptr, const int32_t *rcol, const float *rval, int rk,
                                  int r_use, const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                                 hipStream_t s, const int32_t *colmap = nullptr);
+                                 hipStream_t s, const int32_t *colmap = nullptr, const double *gv = nullptr);
 hipError_t launch_sp_combine(int64_t N, int B, const int64_t *rptr, const int32_t *rcol, const float *rval,
                              const float *Cs, int ldc, const float *X, float *x, int64_t ldx, hipStream_t s);
 

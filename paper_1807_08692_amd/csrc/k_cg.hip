@@ -441,6 +441,33 @@ hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const flo
     return hipGetLastError();
 }
 
+// One step of the polynomial filter's Horner recurrence (Appendix A):
+// P = c R + qs Q, with R holding y and Q = S_r P_old / 2 (qs = 2), or
+// P = c R when qs = 0 (Q not read).
+__global__ __launch_bounds__(kBlock) void k_filter_axpy(size_t n4, float4 *P, const float4 *R,
+                                                        const float4 *Q, float c, float qs) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n4) return;
+    const float4 r = R[i];
+    float4 p = make_float4(c * r.x, c * r.y, c * r.z, c * r.w);
+    if (qs != 0.f) {
+        const float4 q = Q[i];
+        p = make_float4(p.x + qs * q.x, p.y + qs * q.y, p.z + qs * q.z, p.w + qs * q.w);
+    }
+    P[i] = p;
+}
+
+hipError_t launch_filter_axpy(float *P, const float *R, const float *Q, size_t n, double c, double qs,
+                              hipStream_t s) {
+    if (n % 4 != 0) return hipErrorInvalidValue;  // solver widths are multiples of 64
+    const size_t n4 = n / 4;
+    if (n4 == 0) return hipSuccess;
+    k_filter_axpy<<<(unsigned)((n4 + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        n4, reinterpret_cast<float4 *>(P), reinterpret_cast<const float4 *>(R),
+        reinterpret_cast<const float4 *>(Q), (float)c, (float)qs);
+    return hipGetLastError();
+}
+
 __global__ void k_cg_final(int ldb, CgState st) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ldb) return;
@@ -477,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
                                                         const UT *U, const UT *U_lo, int rp, int rk,
                                                         int r_use, const double *lam, double alpha,
                                                         int ldb, float *Cs, float *Cl,
-                                                        const int32_t *colmap) {
+                                                        const int32_t *colmap, const double *gv) {
     int k = blockIdx.x * kBlock + threadIdx.x;
     int b = blockIdx.y;  // y row; its solver column is colmap[b] (or b)
     if (k >= rk) return;
@@ -493,7 +520,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
     }
     double lk = k < r_use ? lam[k] : 0.0;
     double h = (1.0 - alpha) / (1.0 - alpha * lk);
-    double g = h - (1.0 - alpha);
+    // g of a general filter (Appendix A, eq. (2-aux)) when given, else g_alpha
+    double g = gv ? (k < r_use ? gv[k] : 0.0) : h - (1.0 - alpha);
     Cs[(size_t)k * ldb + col] = (float)(g * acc);
     if (Cl) Cl[(size_t)k * ldb + col] = (float)(lk * acc);
 }
@@ -501,18 +529,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                              hipStream_t s, const int32_t *colmap) {
+                              hipStream_t s, const int32_t *colmap, const double *gv) {
     if (rk == 0) return hipSuccess;
     dim3 grid((rk + kBlock - 1) / kBlock, colmap ? B : ldb);
     if (u_bf16) {
         k_gather_proj<unsigned short><<<grid, kBlock, 0, s>>>(
             B, ky, ids, vals, N, reinterpret_cast<const unsigned short *>(U),
             reinterpret_cast<const unsigned short *>(U_lo), rp, rk, r_use, lam, alpha, ldb, Cs, Cl,
-            colmap);
+            colmap, gv);
     } else {
         k_gather_proj<float><<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N,
                                                      reinterpret_cast<const float *>(U), nullptr, rp,
-                                                     rk, r_use, lam, alpha, ldb, Cs, Cl, colmap);
+                                                     rk, r_use, lam, alpha, ldb, Cs, Cl, colmap, gv);
     }
     return hipGetLastError();
 }

@@ -108,7 +108,8 @@ __global__ __launch_bounds__(kBlock) void k_sp_gather_proj(int B, int ky, const 
                                                            int r_use, const double *__restrict__ lam,
                                                            double alpha, int ldb, float *__restrict__ Cs,
                                                            float *__restrict__ Cl,
-                                                           const int32_t *__restrict__ colmap) {
+                                                           const int32_t *__restrict__ colmap,
+                                                           const double *__restrict__ gv) {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     const int b = blockIdx.y;
     if (k >= rk) return;
@@ -130,18 +131,19 @@ __global__ __launch_bounds__(kBlock) void k_sp_gather_proj(int B, int ky, const 
     }
     const double lk = k < r_use ? lam[k] : 0.0;
     const double h = (1.0 - alpha) / (1.0 - alpha * lk);
-    Cs[(size_t)k * ldb + col] = (float)((h - (1.0 - alpha)) * acc);
+    const double g = gv ? (k < r_use ? gv[k] : 0.0) : h - (1.0 - alpha);
+    Cs[(size_t)k * ldb + col] = (float)(g * acc);
     if (Cl) Cl[(size_t)k * ldb + col] = (float)(lk * acc);
 }
 
 hipError_t launch_sp_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                                  const int64_t *rptr, const int32_t *rcol, const float *rval, int rk,
                                  int r_use, const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                                 hipStream_t s, const int32_t *colmap) {
+                                 hipStream_t s, const int32_t *colmap, const double *gv) {
     if (rk == 0) return hipSuccess;
     dim3 grid((unsigned)((rk + kBlock - 1) / kBlock), (unsigned)(colmap ? B : ldb));
     k_sp_gather_proj<<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N, rptr, rcol, rval, rk, r_use, lam, alpha, ldb,
-                                             Cs, Cl, colmap);
+                                             Cs, Cl, colmap, gv);
     return hipGetLastError();
 }
 

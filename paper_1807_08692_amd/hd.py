@@ -32,6 +32,8 @@ _SIGS = {
     "hd_load_eigs": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "hd_load_descriptors": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32]),
     "hd_load_eigs_sparse": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
+    "hd_query_filter": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "hd_query_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       _P, _P, _P, _P]),
     "hd_rank": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
@@ -277,6 +279,28 @@ class Context:
             it.ctypes.data_as(_P), rr.ctypes.data_as(_P), st.ctypes.data_as(_P),
             _stream_ptr(stream))
         _check(code)
+        return res
+
+    def query_filter(self, coeffs, q_desc=None, y_ids=None, y_val=None, *, rank_r=-1, k_y=10, top_k=100,
+                     want_x=False, stream=None):
+        """Polynomial filter h(S) y, h(x) = sum_i coeffs[i] x^i (hd_query_filter)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if q_desc is not None:
+            B = int(q_desc.shape[0])
+        else:
+            B = int(y_ids.shape[0])
+            k_y = int(y_ids.shape[1])
+        c, cp = _host(coeffs, np.float64)
+        res = {}
+        if top_k > 0:
+            res["rank_ids"] = torch.empty((B, top_k), dtype=torch.int32, device=dev)
+            res["rank_scores"] = torch.empty((B, top_k), dtype=torch.float32, device=dev)
+        if want_x:
+            res["x"] = torch.empty((B, self.n), dtype=torch.float32, device=dev)
+        _check(lib().hd_query_filter(self._h, B, _dptr(q_desc), _dptr(y_ids), _dptr(y_val), int(c.size) - 1, cp,
+                                     int(rank_r), int(k_y), int(top_k), _dptr(res.get("rank_ids")),
+                                     _dptr(res.get("rank_scores")), _dptr(res.get("x")), _stream_ptr(stream)))
         return res
 
     def rank(self, x, K, stream=None, ids=None, scores=None):

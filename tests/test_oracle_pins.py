@@ -422,3 +422,48 @@ def test_sparsify_keeps_the_largest_entries():
         assert kept.min() >= dropped.max()
         assert np.array_equal(D[D != 0], U[D != 0].astype(np.float64))
         assert all(np.all(np.diff(col[rp[i]:rp[i + 1]]) > 0) for i in range(300))
+
+
+@pytest.mark.parametrize("r", [0, 3, 20, 150])
+def test_general_filter_theorem_for_polynomials(r):
+    """Appendix A, eq. (2-main): for a polynomial h the decomposition is exact,
+    so U1 g(L1) U1^T y + h(S_r) y equals sum_i c_i S^i y formed with dense
+    matrix powers, at every rank r (r = n included)."""
+    _, g, _ = small_graph(seed=41)
+    S = g.dense()
+    w, Uf = np.linalg.eigh(S)
+    o = np.argsort(-w)
+    w, Uf = w[o], Uf[:, o]
+    rng = np.random.default_rng(r)
+    coeffs = rng.uniform(-1, 1, size=7)
+    ids, vals = sparse_y(g.n, 5, 42)
+    y = O.dense_y(g.n, ids, vals)
+    direct = np.zeros(g.n)
+    v = y.copy()
+    for i, c in enumerate(coeffs):
+        if i:
+            v = S @ v
+        direct += c * v
+    x = O.filter_poly(g, Uf[:, :r] if r else None, w[:r], coeffs, ids, vals)
+    assert np.linalg.norm(x - direct) <= 1e-12 * np.linalg.norm(direct)
+
+
+@pytest.mark.parametrize("r", [0, 10])
+def test_general_filter_heat_kernel(r):
+    """A truncated Taylor series of the heat kernel h(x) = exp(t (x - 1))
+    agrees with the matrix exponential of t (S - I) applied to y, to the
+    truncation error (spectrum of S in [-1, 1])."""
+    from math import exp, factorial
+    from scipy.linalg import expm
+    _, g, _ = small_graph(seed=43)
+    S = g.dense()
+    w, Uf = np.linalg.eigh(S)
+    o = np.argsort(-w)
+    w, Uf = w[o], Uf[:, o]
+    t = 3.0
+    coeffs = [exp(-t) * t ** i / factorial(i) for i in range(40)]
+    ids, vals = sparse_y(g.n, 5, 44)
+    y = O.dense_y(g.n, ids, vals)
+    ref = expm(t * (S - np.eye(g.n))) @ y
+    x = O.filter_poly(g, Uf[:, :r] if r else None, w[:r], coeffs, ids, vals)
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
