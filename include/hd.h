@@ -169,6 +169,32 @@ int hd_rank_plan(int32_t nlam, const double *lambda, double lambda_min, double a
                  int32_t *iters_out, double *pred_ms_out, int32_t *best);
 
 /*
+ * On-device top-r eigensolver (the off-line input of Section 4.1): computes
+ * the r algebraically largest eigenpairs of the loaded S by Chebyshev-filtered
+ * subspace iteration in double precision on a block of r + guard vectors
+ * (rounded up to a multiple of 64), then loads them as hd_load_eigs does with
+ * `dtype` (HD_F32, HD_BF16, HD_BF16X2). Stops when the r leading residual
+ * norms ||S u_j - lambda_j u_j|| are <= tol, after max_outer Rayleigh-Ritz
+ * steps, or past time_budget_s (0: no limit). lambda_min: a lower value for
+ * the smallest eigenvalue of S (-1 is always valid). Device memory: about
+ * 4 N (r + guard) doubles while it runs. Outputs (host, may be NULL):
+ * lambda_out[r] (descending), resid_out[r], U_out[n x r] (fp32, item-major).
+ * Errors: HD_ESTATE (no graph), HD_EINVAL (options), HD_ENOMEM, HD_EDEVICE
+ * (a library call or factorisation failed).
+ */
+typedef struct {
+    int32_t guard;         /* extra block vectors beyond r (>= 1)            */
+    int32_t degree;        /* Chebyshev filter degree per step, [1, 64]      */
+    int32_t max_outer;     /* Rayleigh-Ritz steps at most                    */
+    double tol;            /* residual norm target                           */
+    double time_budget_s;  /* wall-clock limit, 0 = none                     */
+    uint64_t seed;         /* start block (counter-based normal draws)       */
+    double lambda_min;     /* lower end of the damped interval               */
+} hd_eig_opts;
+int hd_compute_eigs(hd_ctx *ctx, int32_t r, int32_t dtype, const hd_eig_opts *opts, double *lambda_out,
+                    double *resid_out, float *U_out);
+
+/*
  * SHybrid (Section 6.2): load a sparsified U1 (most entries set to zero,
  * not renormalised) and its eigenvalues; the hybrid method then runs with
  * sparse eigenvector products (one wave per item or component, gathering

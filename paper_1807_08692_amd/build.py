@@ -17,7 +17,10 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhd.so")
 SOURCES = ["k_cg.hip", "k_spmm.hip", "k_ugemm.hip", "k_ugemm_bf16.hip", "k_sparse_u.hip", "k_sim.hip", "k_topk.hip",
-           "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp"]
+           "k_eig.hip", "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp", "hd_eig.cpp"]
+# ROCm libraries for the eigensolver's dense steps (rocBLAS: Gram matrix,
+# rotations, triangular solve; rocSOLVER: Cholesky, small eigenproblem)
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = "gfx950"
 
 
@@ -53,7 +56,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"link failed:\n{p.stderr}")

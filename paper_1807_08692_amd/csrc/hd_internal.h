@@ -165,6 +165,7 @@ struct hd_ctx {
     int64_t us_nnz = 0;
     std::vector<double> lam_host;  // the loaded eigenvalues, padded with zeros to rp
     DevBuf gfil;                   // g(lambda) of a general filter
+    int eig_outer = 0;             // Rayleigh-Ritz steps of the last hd_compute_eigs
     // descriptors: V (fp32) or Vb (bf16), N x ldv
     int d = 0, ldv = 0, v_dtype = HD_F32;
     DevBuf V, Vb;

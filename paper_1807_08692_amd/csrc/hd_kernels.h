@@ -176,4 +176,14 @@ hipError_t launch_sp_gather_proj(int B, int ky, const int32_t *ids, const float 
 hipError_t launch_sp_combine(int64_t N, int B, const int64_t *rptr, const int32_t *rcol, const float *rval,
                              const float *Cs, int ldc, const float *X, float *x, int64_t ldx, hipStream_t s);
 
+// ---- top-r eigensolver blocks (k_eig.hip): N x m item-major, double ----
+hipError_t launch_eig_rand(int64_t N, int m, uint64_t seed, double *X, hipStream_t s);
+// Out = a S Y1 + b Y1 + c Y0 (Y0 may be null); m a multiple of 64
+hipError_t launch_eig_cheb(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val, int m,
+                           const double *Y1, const double *Y0, double *Out, double a, double b, double c,
+                           hipStream_t s);
+hipError_t launch_eig_resid(int64_t N, int m, const double *SX, const double *X, const double *w, int64_t rb,
+                            int nblk, double *part, hipStream_t s);
+hipError_t launch_eig_extract(int64_t N, int m, int r, const double *X, float *U, hipStream_t s);
+
 }  // namespace hd

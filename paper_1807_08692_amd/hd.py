@@ -32,6 +32,7 @@ _SIGS = {
     "hd_load_eigs": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "hd_load_descriptors": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32]),
     "hd_load_eigs_sparse": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
+    "hd_compute_eigs": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "hd_query_filter": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "hd_query_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -82,6 +83,12 @@ def rank_plan(lam, cand_r, *, alpha=0.99, eps=1e-3, lambda_min=-1.0, fixed_ms=No
 
 # Launch parameters (hd_tune_key)
 TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2}
+
+
+class hd_eig_opts(ctypes.Structure):
+    _fields_ = [("guard", ctypes.c_int32), ("degree", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("time_budget_s", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("lambda_min", ctypes.c_double)]
 
 
 class hd_query_opts(ctypes.Structure):
@@ -184,6 +191,19 @@ class Context:
         la, lp = _host(lam if r else np.zeros(1), np.float64)
         _check(lib().hd_load_eigs(self._h, r, Up, lp, _DTYPES[dtype]))
         self.r = r
+
+    def compute_eigs(self, r, dtype="f32", *, guard=None, degree=12, max_outer=60, tol=1e-9,
+                     time_budget_s=0.0, seed=1, lambda_min=-1.0, want_U=False):
+        """Top-r eigenpairs of the loaded S on the device (hd_compute_eigs),
+        loaded into the context; returns lambda, residuals (and U if asked)."""
+        o = hd_eig_opts(int(guard if guard is not None else max(20, r // 4)), int(degree), int(max_outer),
+                        float(tol), float(time_budget_s), int(seed), float(lambda_min))
+        lam = np.zeros(r, np.float64)
+        res = np.zeros(r, np.float64)
+        U = np.zeros((self.n, r), np.float32) if want_U else None
+        _check(lib().hd_compute_eigs(self._h, int(r), _DTYPES[dtype], ctypes.byref(o), lam.ctypes.data_as(_P),
+                                     res.ctypes.data_as(_P), None if U is None else U.ctypes.data_as(_P)))
+        return {"lam": lam, "resid": res, "U": U}
 
     def load_eigs_sparse(self, r, rowptr, col, val, lam):
         """Sparsified U1 (SHybrid) by item in CSR form: rowptr (n+1), col
