@@ -141,7 +141,8 @@ int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
  * valid value of each launch parameter on the loaded graph and eigenvectors
  * (one warm-up and `reps` timed launches each, on device scratch vectors of
  * the solver width, on the null stream) and keep the fastest in the
- * context. times_ms (host, may be NULL) receives HD_TUNE_NKEYS x 3 mean
+ * context; the built-in default is kept unless a candidate beats it by more
+ * than 2%. times_ms (host, may be NULL) receives HD_TUNE_NKEYS x 3 mean
  * launch times in ms for the values 1, 2, 4 (-1 where a value does not fit
  * or the kernel is not used: no eigenvectors, or fp32 storage).
  * Synchronous. Errors: HD_ESTATE (no graph), HD_EINVAL (batch not in

@@ -6,7 +6,24 @@
 // eigenvectors at the solver width of the batch size it is asked for, on
 // scratch vectors, and keeps the fastest. Timing uses HIP events on the
 // null stream around `reps` back-to-back launches after one warm-up launch.
+// A candidate replaces the built-in default only when it is more than 2%
+// faster: near-equal candidates would otherwise flip between runs on timing
+// noise, and the chosen launch variant decides which kernel a profile counts.
 #include "hd_internal.h"
+
+namespace {
+
+// the value each launcher picks for tuning value 0 at solver width ldb
+int default_value(int key, int ldb) {
+    const int cap = key == HD_TUNE_SPMM_CPL ? 2 : key == HD_TUNE_UTP_NT ? 4 : 2;
+    for (int v = cap; v > 1; v /= 2)
+        if (ldb % (64 * v) == 0) return v;
+    return 1;
+}
+
+constexpr double kKeepDefault = 0.98;
+
+}  // namespace
 
 extern "C" {
 
@@ -84,8 +101,9 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
     int err = HD_OK;
     for (int key = 0; key < HD_TUNE_NKEYS && err == HD_OK; ++key) {
         const bool used = key == HD_TUNE_SPMM_CPL || ubf;
-        double best = -1.0;
+        double best = -1.0, def_ms = -1.0;
         int best_v = 0;
+        const int def_v = default_value(key, ldb);
         for (int j = 0; j < 3; ++j) {
             double ms = -1.0;
             if (used && hd::tile_param_ok(cand[j], ldb)) {
@@ -101,6 +119,7 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
                     break;
                 }
                 ms = (double)el / reps;
+                if (cand[j] == def_v) def_ms = ms;
                 if (best < 0.0 || ms < best) {
                     best = ms;
                     best_v = cand[j];
@@ -108,7 +127,7 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
             }
             if (times_ms) times_ms[key * 3 + j] = ms;
         }
-        if (used && best_v != 0) c->tune[key] = best_v;
+        if (used && best_v != 0) c->tune[key] = (def_ms >= 0.0 && best >= kKeepDefault * def_ms) ? def_v : best_v;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

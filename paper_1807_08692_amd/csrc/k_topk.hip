@@ -14,20 +14,27 @@
 //   filter : one coalesced pass over the rows, 8192 elements per block; each
 //            element with score >= t is appended to its block's own list
 //            (LDS counter, no global atomics);
-//   select : (one block per row) if the lists hold K <= count <= 4096
+//   select : (one block per row) if the lists hold K <= count <= 8192
 //            candidates and none overflowed, they contain the top K (at least
 //            K elements are >= t, so the K-th best is >= t): gather, sort in
 //            LDS, write the first K. Otherwise the block selects exactly on
 //            its own: an MSB-first radix select over the row finds the K-th
 //            key, then a pass in index order collects the keys above it and
 //            the lowest-id ties.
+//
+// The number of row elements at or above t is about n Beta(j+1, m-j), mean
+// (j+1) n / m (about 2000 at K <= 100, n = 1M): a cap of 4096 was exceeded by
+// about one row in a hundred, and one such row holds a whole batch for the
+// full-row selection; at 8192 it is about one in 10^7. The kernel time of a
+// batch is that of its slowest row, so the cap matters more than the mean.
 // Candidate order within a list depends on timing; the result does not.
 #include "hd_device.h"
 #include "hd_kernels.h"
 
 namespace hd {
 
-constexpr int kCap = 4096;        // candidates per row for the final sort
+constexpr int kCap = 8192;        // candidates per row for the final sort (64 KB of LDS)
+constexpr int kMaxChunk = 4096;   // filter blocks per row the fast path accepts (n <= 32M)
 constexpr int kSample = 4096;     // sampled elements per row
 constexpr int kChunk = 8192;      // row elements per filter block
 constexpr int kChunkCap = 256;    // candidates kept per filter block
@@ -169,6 +176,16 @@ __global__ __launch_bounds__(kWide) void k_topk_thresh(int64_t n, const float *_
     }
 }
 
+__device__ __forceinline__ void filter_one(float v, int64_t i, uint32_t thr, int *lcount,
+                                           uint64_t *cand) {
+    if (float_order_key(v) >= thr) {
+        const int slot = atomicAdd(lcount, 1);
+        if (slot < kChunkCap) cand[slot] = rank_key(v, (uint32_t)i);
+    }
+}
+
+// V = 4: 16-byte loads (rows 16-byte aligned: x aligned and ldx % 4 == 0).
+template <int V>
 __global__ __launch_bounds__(kBlock) void k_topk_filter(int64_t n, const float *__restrict__ x,
                                                         int64_t ldx, TopkScratch ts) {
     __shared__ int lcount;
@@ -181,19 +198,60 @@ __global__ __launch_bounds__(kBlock) void k_topk_filter(int64_t n, const float *
     uint64_t *cand = ts.cand + ((size_t)b * ts.nchunk + c) * kChunkCap;
     const int64_t base = (int64_t)c * kChunk;
     const float *row = x + (size_t)b * ldx;
-#pragma unroll 4
-    for (int u = 0; u < kChunk / kBlock; ++u) {
-        const int64_t i = base + u * kBlock + threadIdx.x;
-        if (i < n) {
-            const float v = row[i];
-            if (float_order_key(v) >= thr) {
-                const int slot = atomicAdd(&lcount, 1);
-                if (slot < kChunkCap) cand[slot] = rank_key(v, (uint32_t)i);
+    if (V == 4) {
+        float4 v[kChunk / (4 * kBlock)];
+#pragma unroll
+        for (int u = 0; u < kChunk / (4 * kBlock); ++u) {
+            const int64_t i = base + (int64_t)(u * kBlock + threadIdx.x) * 4;
+            v[u] = i + 3 < n ? *reinterpret_cast<const float4 *>(row + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk / (4 * kBlock); ++u) {
+            const int64_t i = base + (int64_t)(u * kBlock + threadIdx.x) * 4;
+            if (i + 3 < n) {
+                filter_one(v[u].x, i, thr, &lcount, cand);
+                filter_one(v[u].y, i + 1, thr, &lcount, cand);
+                filter_one(v[u].z, i + 2, thr, &lcount, cand);
+                filter_one(v[u].w, i + 3, thr, &lcount, cand);
+            } else {
+                for (int64_t e = i; e < n && e < i + 4; ++e) filter_one(row[e], e, thr, &lcount, cand);
             }
+        }
+    } else {
+#pragma unroll 4
+        for (int u = 0; u < kChunk / kBlock; ++u) {
+            const int64_t i = base + u * kBlock + threadIdx.x;
+            if (i < n) filter_one(row[i], i, thr, &lcount, cand);
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) ts.cnt[(size_t)b * ts.nchunk + c] = lcount;
+}
+
+// Exclusive prefix sum over the kWide threads of the block; *total gets the
+// sum. wsum: kWide / kWave ints of LDS.
+__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int *total) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int inc = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += t;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        int t = lane < kWide / kWave ? wsum[lane] : 0;
+        for (int off = 1; off < kWide / kWave; off <<= 1) {
+            const int u = __shfl_up(t, off, kWave);
+            if (lane >= off) t += u;
+        }
+        if (lane < kWide / kWave) wsum[lane] = t;  // inclusive per-wave totals
+    }
+    __syncthreads();
+    const int base = w ? wsum[w - 1] : 0;
+    *total = wsum[kWide / kWave - 1];
+    __syncthreads();
+    return base + inc - v;
 }
 
 __device__ __forceinline__ void write_out(const uint64_t *s, int K, int b, int32_t *ids,
@@ -217,7 +275,7 @@ __global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *_
                                                        int32_t *__restrict__ ids,
                                                        float *__restrict__ scores, int transform) {
     __shared__ uint64_t s[kCap];
-    __shared__ int offs[kCap / 16 + 1];
+    __shared__ int offs[kMaxChunk + 1];
     __shared__ int hist[256];
     __shared__ int sh_int[8];
     __shared__ int wcount[kWide / kWave];
@@ -229,23 +287,29 @@ __global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *_
     int total = -1;
     if (ts.all[b]) {
         if (n <= kCap) total = (int)n;
-    } else if (nchunk <= kCap / 16) {
-        for (int c = threadIdx.x; c < nchunk; c += kWide) offs[c + 1] = ts.cnt[(size_t)b * nchunk + c];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int acc = 0, bad = 0;
-            for (int c = 0; c < nchunk; ++c) {
-                const int k = offs[c + 1];
-                offs[c] = acc;
-                bad |= k > kChunkCap;
-                acc += k;
-            }
-            offs[nchunk] = acc;
-            sh_int[0] = (bad || acc < K || acc > kCap) ? -1 : acc;
+    } else if (nchunk <= kMaxChunk) {
+        // offsets of the per-chunk lists: 4 consecutive chunks per thread
+        constexpr int kPer = kMaxChunk / kWide;
+        int v[kPer], loc = 0;
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int c = threadIdx.x * kPer + q;
+            v[q] = c < nchunk ? ts.cnt[(size_t)b * nchunk + c] : 0;
+            bad |= v[q] > kChunkCap;
+            loc += v[q];
         }
-        __syncthreads();
-        total = sh_int[0];
-        __syncthreads();
+        int acc;
+        int o = block_excl_scan(loc, wcount, &acc);
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int c = threadIdx.x * kPer + q;
+            if (c < nchunk) offs[c] = o;
+            o += v[q];
+        }
+        if (threadIdx.x == 0) offs[nchunk] = acc;
+        const int anybad = __syncthreads_or(bad ? 1 : 0);
+        total = (anybad || acc < K || acc > kCap) ? -1 : acc;
     }
     if (total >= 0) {
         const int size = pow2_ceil(total);
@@ -253,12 +317,22 @@ __global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *_
             for (int t = threadIdx.x; t < size; t += kWide)
                 s[t] = t < total ? rank_key(row[t], (uint32_t)t) : 0ull;
         } else {
-            for (int c = 0; c < nchunk; ++c) {
-                const int o = offs[c], k = offs[c + 1] - o;
-                const uint64_t *src = ts.cand + ((size_t)b * nchunk + c) * kChunkCap;
-                for (int t = threadIdx.x; t < k; t += kWide) s[o + t] = src[t];
+            // candidate t lives in the list of the chunk c with
+            // offs[c] <= t < offs[c + 1] (binary search; empty lists repeat
+            // an offset, so take the last such c)
+            const uint64_t *src = ts.cand + (size_t)b * nchunk * kChunkCap;
+            for (int t = threadIdx.x; t < size; t += kWide) {
+                uint64_t key = 0ull;
+                if (t < total) {
+                    int lo = 0, hi = nchunk;  // offs[lo] <= t < offs[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (offs[mid] <= t) lo = mid; else hi = mid;
+                    }
+                    key = src[(size_t)lo * kChunkCap + (t - offs[lo])];
+                }
+                s[t] = key;
             }
-            for (int t = total + threadIdx.x; t < size; t += kWide) s[t] = 0ull;
         }
         __syncthreads();
         bitonic_desc<uint64_t, kWide>(s, size);
@@ -349,7 +423,12 @@ hipError_t launch_topk(int B, int64_t n, const float *x, int64_t ldx, int K, voi
     k_topk_thresh<<<B, kWide, 0, s>>>(n, x, ldx, K, stride, ts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_topk_filter<<<dim3((unsigned)ts.nchunk, B), kBlock, 0, s>>>(n, x, ldx, ts);
+    const dim3 fg((unsigned)ts.nchunk, B);
+    if (ldx % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) {
+        k_topk_filter<4><<<fg, kBlock, 0, s>>>(n, x, ldx, ts);
+    } else {
+        k_topk_filter<1><<<fg, kBlock, 0, s>>>(n, x, ldx, ts);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_topk_select<<<B, kWide, 0, s>>>(n, x, ldx, K, ts, ids, scores, transform);

@@ -261,6 +261,33 @@ def _rank_check(ctx, torch_dev, x, K):
         assert np.array_equal(sc[b], osc.astype(np.float32))
 
 
+def test_rank_many_candidates(ctx, torch_dev):
+    """Rows whose sampled threshold admits between 4096 and 8192 elements
+    (6000 large values off the strided sample positions, the rest small or
+    tied at zero) and a row longer than 4M elements (more than 512 filter
+    blocks); ragged lengths, 16-byte and unaligned row strides."""
+    import torch
+    rng = np.random.default_rng(7)
+    n = 1000000
+    x = np.zeros((2, n), np.float32)
+    stride = -(-n // 4096)
+    x[:, ::stride] = rng.random((2, x[:, ::stride].shape[1]), dtype=np.float32)
+    off = np.setdiff1d(np.arange(n), np.arange(0, n, stride))
+    for b in range(2):
+        pos = rng.choice(off, 6000, replace=False)
+        x[b, pos] = 2.0 + rng.random(6000, dtype=np.float32)
+    _rank_check(ctx, torch_dev, x, 100)
+    big = rng.standard_normal((1, 4500003)).astype(np.float32)
+    _rank_check(ctx, torch_dev, big, 1024)
+    xt = torch.zeros((1, 4500003 + 1), dtype=torch.float32, device=torch_dev)
+    xt[:, :4500003] = torch.from_numpy(big).to(torch_dev)
+    ids, sc = ctx.rank(xt[:, :4500003], 64)
+    torch.cuda.synchronize()
+    oid, osc = O.rank(big[0].astype(np.float64), 64)
+    assert np.array_equal(ids.cpu().numpy()[0], oid)
+    assert np.array_equal(sc.cpu().numpy()[0], osc.astype(np.float32))
+
+
 def test_rank_exact_selection_paths(ctx, torch_dev):
     """Rows on which the sampled threshold cannot be used (too many
     candidates: all values equal, or spikes the strided sample misses; too
