@@ -97,14 +97,22 @@ def parse():
     return p.parse_args()
 
 
-def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4):
+# U1 storage forms whose CG iteration applies the eigenvector correction after
+# the sparse product, inside the residual update
+FUSED_FORMS = ("bf16", "bf16x2")
+
+
+def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False):
     """(bytes, flops) one launch of kernel `kind` must move / compute;
-    su = bytes per stored U1 / descriptor element (4 fp32, 2 bf16)."""
+    su = bytes per stored U1 / descriptor element (4 fp32, 2 bf16).
+    fused: the dense bfloat16 forms, where the sparse product reads P only
+    (Zs = P) and u_c is fused with the residual update (reads Qs and r,
+    writes r)."""
     v = 4.0 * n * ldb
     if kind == "spmm":
-        return 8.0 * (n + 1) + 8.0 * nnz + v * (3 if rk > 0 else 2), 2.0 * nnz * ldb
+        return 8.0 * (n + 1) + 8.0 * nnz + v * (3 if rk > 0 and not fused else 2), 2.0 * nnz * ldb
     if kind == "u_c":
-        return su * n * rk + 4.0 * rk * ldb + 2 * v, 2.0 * n * rk * ldb
+        return su * n * rk + 4.0 * rk * ldb + (3 if fused else 2) * v, 2.0 * n * rk * ldb
     if kind == "ut_p":
         return su * n * rk + v + 4.0 * nchunk * rk * ldb, 2.0 * n * rk * ldb
     if kind == "update_r":
@@ -257,7 +265,8 @@ def main():
         for kind, (ms, cnt) in tm_all.items():
             if cnt == 0:
                 continue
-            cost = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, sv if kind == "sim" else su)
+            cost = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, sv if kind == "sim" else su,
+                                    form in FUSED_FORMS)
             kernels[kind] = {"ms_total": round(ms, 4), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 3)}
             if cost:
                 by, fl = cost
@@ -312,7 +321,7 @@ def main():
     tm = chosen["dom_tm"]
     su = chosen["su"]
     # roofline of the dominant kernel, from its events inside the timed region
-    by, fl = algorithmic_cost(dom, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, su)
+    by, fl = algorithmic_cost(dom, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, su, form0 in FUSED_FORMS)
     avg_s = tm[dom][0] / tm[dom][1] * 1e-3
     ai = fl / by
     mfma_peak = FP32_MFMA_PEAK_TFLOPS if form0 == "f32" else BF16_MFMA_PEAK_TFLOPS

@@ -57,6 +57,13 @@ int hd_create(int device, hd_ctx **out) {
             return fail(HD_EDEVICE, "hd_create: hipEventCreate: %s", hipGetErrorString(e));
         }
     }
+    e = hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        hd_destroy(c);
+        return fail(HD_EDEVICE, "hd_create: stream / event: %s", hipGetErrorString(e));
+    }
     *out = c;
     return HD_OK;
 }
@@ -69,11 +76,14 @@ void hd_destroy(hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                      &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                     &c->topk, &c->err, &c->qsplit};
+                     &c->topk, &c->err, &c->qsplit, &c->Dg};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (hipEvent_t e : c->iter_ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->s_aux) (void)hipStreamDestroy(c->s_aux);
     c->timing.destroy();
     delete c;
 }
@@ -421,12 +431,20 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     const hd::RowPart rp = hd::make_row_part(n);
     int64_t rc;
     const int nchunk = hd::ut_p_chunks(n, &rc);
+    // Dense bfloat16 U1 in CG: the eigenvector correction follows the sparse
+    // product (Q = Qs + alpha / (1 - alpha) U1 L1 U1^T P, Qs = (P - alpha S P) /
+    // (1 - alpha)), U1^T P runs on the second stream beside the sparse
+    // product, and U1 C is applied inside the residual update, so Q is never
+    // stored; gamma = P^T Qs + alpha / (1 - alpha) (U1^T P)^T L1 (U1^T P).
+    const bool fused = rk > 0 && !sparse && c->u_bf16() && !flt;
+    const int nrb = hd::uc_update_r_blocks(n);
     HIP_TRY(c->X.ensure(vec));
     HIP_TRY(c->R.ensure(vec));
     HIP_TRY(c->P.ensure(vec));
     HIP_TRY(c->Q.ensure(vec));
+    if (fused) HIP_TRY(c->Dg.ensure((size_t)rk * ldb * sizeof(double)));
     if (rk > 0) {
-        HIP_TRY(c->Z.ensure(vec));
+        if (!fused) HIP_TRY(c->Z.ensure(vec));
         if (!sparse) HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
         HIP_TRY(c->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         HIP_TRY(c->Cs.ensure((size_t)rk * ldb * sizeof(float)));
@@ -436,7 +454,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             HIP_TRY(c->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
         }
     }
-    HIP_TRY(c->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
+    HIP_TRY(c->part.ensure((size_t)(fused && nrb > rp.nblk ? nrb : rp.nblk) * ldb * sizeof(double)));
     HIP_TRY(c->scal.ensure((size_t)ldb * (5 * sizeof(double) + 3 * sizeof(int32_t)) + 128 * sizeof(int32_t)));
     HIP_TRY(c->err.ensure(sizeof(int32_t) * 4));
     {
@@ -536,7 +554,8 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     } else if (rk > 0) {
         LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, ubf ? (const void *)Ub : (const void *)U,
                                                 Ubl, ubf ? 1 : 0, c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
-                                                ldb, c->Cs.as<float>(), c->Cl.as<float>(), s, nullptr, gv));
+                                                ldb, c->Cs.as<float>(), c->Cl.as<float>(), s, nullptr, gv,
+                                                fused ? c->Dg.as<double>() : nullptr));
         if (ubf) {
             const hd::IterGuard none{nullptr, 0};
             LAUNCH(K_GATHER, hd::launch_split_t(c->Cs.as<float>(), rk, ldb, CsT_hi, CsT_lo, none, s));
@@ -604,6 +623,44 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     auto enqueue_iter = [&](int it) -> int {
         c->timing.tag = it;
         const hd::IterGuard g{nact_dev[(it - 1) & 1], ntile};
+        if (fused) {
+            uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
+            if (it > 1) {
+                // U1^T P (P^T split written by the previous iteration's
+                // update) and its reduction beside the sparse product
+                HIP_TRY(hipEventRecord(c->ev_fork, s));
+                HIP_TRY(hipStreamWaitEvent(c->s_aux, c->ev_fork, 0));
+                LAUNCH_ON(c->s_aux, K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb,
+                                                                 c->Cpart.as<float>(), g, c->s_aux,
+                                                                 c->tv(HD_TUNE_UTP_NT, ldb)));
+                LAUNCH_ON(c->s_aux, K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb,
+                                                                    c->lam.as<double>(), r_use, c->Cl.as<float>(),
+                                                                    g, c->s_aux, c->Dg.as<double>(), o->alpha));
+                LAUNCH_ON(c->s_aux, K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g,
+                                                                   c->s_aux));
+                HIP_TRY(hipEventRecord(c->ev_join, c->s_aux));
+            }
+            LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P,
+                                           P, Q, ldb, o->alpha, rp, c->part.as<double>(), g, s,
+                                           c->tv(HD_TUNE_SPMM_CPL, ldb)));
+            if (it > 1) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+            LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, c->Dg.as<double>(),
+                                                  rk));
+            LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,
+                                                      st.a, c->part.as<double>(), g, s,
+                                                      c->tv(HD_TUNE_UC_NT, ldb)));
+            LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), nrb, o->tol, st, g, nact_dev[it & 1],
+                                                  s));
+            LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut, PTh,
+                                                        PTl, g, s));
+            if (!graph) {
+                HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipEventRecord(c->iter_ev[it & 1], s));
+            }
+            c->timing.tag = 0;
+            return HD_OK;
+        }
         const float *Zs = P;
         if (rk > 0 && sparse) {
             if (it > 1)

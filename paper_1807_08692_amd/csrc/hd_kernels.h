@@ -48,8 +48,10 @@ hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals
 hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
                              hipStream_t s);
 hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s);
+// gamma = the column sums of gpart (nblk rows), plus those of gpart2 (nblk2
+// rows) when given
 hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, IterGuard g,
-                            hipStream_t s);
+                            hipStream_t s, const double *gpart2 = nullptr, int nblk2 = 0);
 hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
                            const double *a, double *part, IterGuard g, hipStream_t s);
 // writes the new per-tile active counts to nact_out
@@ -72,7 +74,8 @@ hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                              hipStream_t s, const int32_t *colmap = nullptr, const double *gv = nullptr);
+                              hipStream_t s, const int32_t *colmap = nullptr, const double *gv = nullptr,
+                              double *Dg = nullptr);
 // P = c R + qs Q over n floats (polynomial filter step); qs = 0 does not read Q
 hipError_t launch_filter_axpy(float *P, const float *R, const float *Q, size_t n, double c, double qs,
                               hipStream_t s);
@@ -103,9 +106,12 @@ int ut_p_chunks(int64_t N, int64_t *rows_per_chunk);
 // Cpart[c] = U[chunk c]^T P[chunk c]  (rk x ldb per chunk)
 hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P, int ldb,
                        float *Cpart, IterGuard g, hipStream_t s);
-// Cl = lambda .* sum_c Cpart[c]   (rows k >= r_use zeroed)
+// Cl = lambda .* sum_c Cpart[c]   (rows k >= r_use zeroed); with Dg also
+// Dg = alpha / (1 - alpha) lambda .* (sum_c Cpart[c])^2 (double, rk x ldb):
+// the eigenvector part of P^T Q when the correction follows the sparse product
 hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
-                           int r_use, float *Cl, IterGuard g, hipStream_t s);
+                           int r_use, float *Cl, IterGuard g, hipStream_t s, double *Dg = nullptr,
+                           double alpha = 0.0);
 // Z = P + alpha * U Cl
 hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl, int ldb,
                       const float *P, double alpha, float *Z, IterGuard g, hipStream_t s);
@@ -135,6 +141,15 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                            const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
                            int nt = 0);
+// With Qs = (P - alpha S P) / (1 - alpha) (launch_spmm with Zs = P): the
+// residual update r -= a (Qs + alpha / (1 - alpha) U Cl) (Cl as split
+// transpose), and part[g][c] = sum over the rows of 128-row block g of the
+// new r^2 (uc_update_r_blocks(N) rows of ldb doubles)
+int uc_update_r_blocks(int64_t N);
+hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp,
+                                   int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
+                                   const float *Qs, double alpha, float *R, const double *a, double *part,
+                                   IterGuard g, hipStream_t s, int nt = 0);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
 hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const unsigned short *U_lo,
                                int rp, int rk,

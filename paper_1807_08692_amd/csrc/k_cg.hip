@@ -203,11 +203,16 @@ hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState 
 // gamma = P^T Q per column; a = rho / gamma, or stop the column (breakdown)
 // when gamma is not positive and finite.
 __global__ __launch_bounds__(kScalarThreads) void k_cg_step_a(int ldb, const double *gpart, int nblk,
-                                                      CgState st, IterGuard ig) {
+                                                      CgState st, IterGuard ig, const double *gpart2,
+                                                      int nblk2) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     int lane = threadIdx.x % kWave;
     int c = blockIdx.x * kWave + lane;
     double gamma = tile_reduce(gpart, nblk, ldb, c);
+    if (gpart2) {
+        __syncthreads();  // tile_reduce's LDS is reused
+        gamma += tile_reduce(gpart2, nblk2, ldb, c);
+    }
     if (threadIdx.x < kWave) {
         double a = 0.0;
         if (st.active[c]) {
@@ -223,8 +228,8 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_a(int ldb, const dou
 }
 
 hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, IterGuard g,
-                            hipStream_t s) {
-    k_cg_step_a<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, gpart, nblk, st, g);
+                            hipStream_t s, const double *gpart2, int nblk2) {
+    k_cg_step_a<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, gpart, nblk, st, g, gpart2, nblk2);
     return hipGetLastError();
 }
 
@@ -504,7 +509,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
                                                         const UT *U, const UT *U_lo, int rp, int rk,
                                                         int r_use, const double *lam, double alpha,
                                                         int ldb, float *Cs, float *Cl,
-                                                        const int32_t *colmap, const double *gv) {
+                                                        const int32_t *colmap, const double *gv,
+                                                        double *Dg) {
     int k = blockIdx.x * kBlock + threadIdx.x;
     int b = blockIdx.y;  // y row; its solver column is colmap[b] (or b)
     if (k >= rk) return;
@@ -524,23 +530,25 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
     double g = gv ? (k < r_use ? gv[k] : 0.0) : h - (1.0 - alpha);
     Cs[(size_t)k * ldb + col] = (float)(g * acc);
     if (Cl) Cl[(size_t)k * ldb + col] = (float)(lk * acc);
+    // eigenvector part of y^T Q when the correction follows the sparse product
+    if (Dg) Dg[(size_t)k * ldb + col] = alpha / (1.0 - alpha) * lk * acc * acc;
 }
 
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                              hipStream_t s, const int32_t *colmap, const double *gv) {
+                              hipStream_t s, const int32_t *colmap, const double *gv, double *Dg) {
     if (rk == 0) return hipSuccess;
     dim3 grid((rk + kBlock - 1) / kBlock, colmap ? B : ldb);
     if (u_bf16) {
         k_gather_proj<unsigned short><<<grid, kBlock, 0, s>>>(
             B, ky, ids, vals, N, reinterpret_cast<const unsigned short *>(U),
             reinterpret_cast<const unsigned short *>(U_lo), rp, rk, r_use, lam, alpha, ldb, Cs, Cl,
-            colmap, gv);
+            colmap, gv, Dg);
     } else {
         k_gather_proj<float><<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N,
                                                      reinterpret_cast<const float *>(U), nullptr, rp,
-                                                     rk, r_use, lam, alpha, ldb, Cs, Cl, colmap, gv);
+                                                     rk, r_use, lam, alpha, ldb, Cs, Cl, colmap, gv, Dg);
     }
     return hipGetLastError();
 }

@@ -141,7 +141,8 @@ hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P
 // with two accumulators each, then the four wave sums are added in order.
 __global__ __launch_bounds__(kBlock) void k_reduce_c(int nchunk, const float *__restrict__ Cpart,
                                                      int rk, int ldb, const double *lam, int r_use,
-                                                     float *__restrict__ Cl, IterGuard ig) {
+                                                     float *__restrict__ Cl, IterGuard ig,
+                                                     double *__restrict__ Dg, double cc) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     __shared__ double sh[4][kWave];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -160,13 +161,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce_c(int nchunk, const float *__
         const double sum = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
         const int k = (int)(idx / ldb);
         Cl[idx] = k < r_use ? (float)(lam[k] * sum) : 0.f;
+        if (Dg) Dg[idx] = k < r_use ? cc * lam[k] * sum * sum : 0.0;
     }
 }
 
 hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
-                           int r_use, float *Cl, IterGuard g, hipStream_t s) {
+                           int r_use, float *Cl, IterGuard g, hipStream_t s, double *Dg, double alpha) {
     size_t tot = (size_t)rk * ldb;
-    k_reduce_c<<<(unsigned)(tot / kWave), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb, lam, r_use, Cl, g);
+    const double cc = Dg ? alpha / (1.0 - alpha) : 0.0;
+    k_reduce_c<<<(unsigned)(tot / kWave), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb, lam, r_use, Cl, g, Dg, cc);
     return hipGetLastError();
 }
 

@@ -329,6 +329,83 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
     return hipGetLastError();
 }
 
+// The eigenvector correction applied after the sparse product, fused with the
+// CG residual update. With Qs = (P - alpha S P) / (1 - alpha) from the sparse
+// product, the deflated operator gives Q = Qs + c U Cl, c = alpha / (1 - alpha)
+// (Section 4.2, eq. (box)); Q is used once, in r -= a Q, so it is never
+// stored: each element of the U Cl tile goes straight into the update of r,
+// which follows update_r (double arithmetic, a = 0 leaves a stopped column
+// untouched), and the block's column sums of r^2 go to part, one row of ldb
+// doubles per 128-row block.
+template <bool LO, int NT>
+__global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const unsigned short *__restrict__ U,
+                                                           const unsigned short *__restrict__ Ul, int rp, int rk,
+                                                           const unsigned short *__restrict__ CT_hi,
+                                                           const unsigned short *__restrict__ CT_lo, int ldb,
+                                                           const float *__restrict__ Qs, float cc,
+                                                           float *__restrict__ R, const double *__restrict__ a,
+                                                           double *__restrict__ part, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
+    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
+    const int64_t rb = (int64_t)(L / ncg);
+    const int64_t i0 = rb * 128;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
+    f32x4 acc[8][NT];
+    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    const int g = lane / 16, c16 = lane % 16;
+    double av[NT], ss[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        av[n] = a[nw0 + 16 * n + c16];
+        ss[n] = 0.0;
+    }
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t i = i0 + 16 * mt + 4 * g + v;
+            if (i >= N) continue;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const size_t o = vec_index(N, ldb, i, (int)(nw0 + 16 * n + c16));
+                const float q = Qs[o] + cc * acc[mt][n][v];
+                float r = R[o];
+                if (av[n] != 0.0) r = (float)((double)r - av[n] * (double)q);
+                R[o] = r;
+                ss[n] += (double)r * (double)r;
+            }
+        }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        ss[n] += __shfl_xor(ss[n], 16, kWave);
+        ss[n] += __shfl_xor(ss[n], 32, kWave);
+        if (g == 0) part[(size_t)rb * ldb + nw0 + 16 * n + c16] = ss[n];
+    }
+}
+
+int uc_update_r_blocks(int64_t N) { return (int)((N + 127) / 128); }
+
+hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp,
+                                   int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
+                                   const float *Qs, double alpha, float *R, const double *a, double *part,
+                                   IterGuard g, hipStream_t s, int ntr) {
+    const int nt = tn_nt(ldb, ntr, 2);
+    if (nt == 0) return hipErrorInvalidValue;
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)uc_update_r_blocks(N);
+    const float cc = (float)(alpha / (1.0 - alpha));
+#define HD_UR(LOV, NTV)                                                                                   \
+    k_uc_update_r_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, Qs, \
+                                                       cc, R, a, part, g)
+    if (U_lo) {
+        if (nt == 4) HD_UR(true, 4); else if (nt == 2) HD_UR(true, 2); else HD_UR(true, 1);
+    } else {
+        if (nt == 4) HD_UR(false, 4); else if (nt == 2) HD_UR(false, 2); else HD_UR(false, 1);
+    }
+#undef HD_UR
+    return hipGetLastError();
+}
+
 // x[b][i] = (U Cs)[i][b] + X[i][b] (b < B): the product as in u_c over the
 // ldc >= B columns of CsT; each wave then writes its tile query-major, one
 // 16-item m-tile at a time through LDS, so that every query's 16 items go
