@@ -57,13 +57,6 @@ int hd_create(int device, hd_ctx **out) {
             return fail(HD_EDEVICE, "hd_create: hipEventCreate: %s", hipGetErrorString(e));
         }
     }
-    e = hipStreamCreateWithFlags(&c->s_aux, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        hd_destroy(c);
-        return fail(HD_EDEVICE, "hd_create: stream / event: %s", hipGetErrorString(e));
-    }
     *out = c;
     return HD_OK;
 }
@@ -81,9 +74,6 @@ void hd_destroy(hd_ctx *c) {
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (hipEvent_t e : c->iter_ev)
         if (e) (void)hipEventDestroy(e);
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
-    if (c->s_aux) (void)hipStreamDestroy(c->s_aux);
     c->timing.destroy();
     delete c;
 }
@@ -433,9 +423,8 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     const int nchunk = hd::ut_p_chunks(n, &rc);
     // Dense bfloat16 U1 in CG: the eigenvector correction follows the sparse
     // product (Q = Qs + alpha / (1 - alpha) U1 L1 U1^T P, Qs = (P - alpha S P) /
-    // (1 - alpha)), U1^T P runs on the second stream beside the sparse
-    // product, and U1 C is applied inside the residual update, so Q is never
-    // stored; gamma = P^T Qs + alpha / (1 - alpha) (U1^T P)^T L1 (U1^T P).
+    // (1 - alpha)) and U1 C is applied inside the residual update, so Q is
+    // never stored; gamma = P^T Qs + alpha / (1 - alpha) (U1^T P)^T L1 (U1^T P).
     const bool fused = rk > 0 && !sparse && c->u_bf16() && !flt;
     const int nrb = hd::uc_update_r_blocks(n);
     HIP_TRY(c->X.ensure(vec));
@@ -626,24 +615,18 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         if (fused) {
             uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
             if (it > 1) {
-                // U1^T P (P^T split written by the previous iteration's
-                // update) and its reduction beside the sparse product
-                HIP_TRY(hipEventRecord(c->ev_fork, s));
-                HIP_TRY(hipStreamWaitEvent(c->s_aux, c->ev_fork, 0));
-                LAUNCH_ON(c->s_aux, K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb,
-                                                                 c->Cpart.as<float>(), g, c->s_aux,
-                                                                 c->tv(HD_TUNE_UTP_NT, ldb)));
-                LAUNCH_ON(c->s_aux, K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb,
-                                                                    c->lam.as<double>(), r_use, c->Cl.as<float>(),
-                                                                    g, c->s_aux, c->Dg.as<double>(), o->alpha));
-                LAUNCH_ON(c->s_aux, K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g,
-                                                                   c->s_aux));
-                HIP_TRY(hipEventRecord(c->ev_join, c->s_aux));
+                // L1 U1^T P (P^T split written by the previous iteration's
+                // update) and the eigenvector part of gamma
+                LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb, c->Cpart.as<float>(),
+                                                    g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
+                LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(),
+                                                       r_use, c->Cl.as<float>(), g, s, c->Dg.as<double>(),
+                                                       o->alpha));
+                LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
             }
             LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P,
                                            P, Q, ldb, o->alpha, rp, c->part.as<double>(), g, s,
                                            c->tv(HD_TUNE_SPMM_CPL, ldb)));
-            if (it > 1) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
             LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, c->Dg.as<double>(),
                                                   rk));
             LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,

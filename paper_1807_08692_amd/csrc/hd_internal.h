@@ -173,10 +173,6 @@ struct hd_ctx {
     DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, PT, part, scal, xbuf, sim, ybuf, topk, err, qsplit;
     int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
     hipEvent_t iter_ev[2] = {nullptr, nullptr};
-    // second stream of the query path (U1^T P beside the sparse product),
-    // non-blocking, default priority; fork / join events
-    hipStream_t s_aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DevBuf Dg;  // alpha / (1 - alpha) lambda (U1^T P)^2 per component and column
     hd::CgState st{};
     Timing timing;
@@ -216,13 +212,12 @@ int queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
 
 // Launch `call` (a launcher returning hipError_t) as kernel kind `kind`,
 // bracketed by timing events when timing is on.
-#define LAUNCH_ON(strm, kind, call)                                               \
+#define LAUNCH(kind, call)                                                        \
     do {                                                                          \
         size_t ev_ = 0;                                                           \
         const bool tm_ = c->timing.on && ((c->timing.mask >> (kind)) & 1u);       \
-        if (tm_) HIP_TRY(c->timing.begin((strm), &ev_));                          \
+        if (tm_) HIP_TRY(c->timing.begin(s, &ev_));                               \
         HIP_TRY(call);                                                            \
-        if (tm_) HIP_TRY(c->timing.end(kind, ev_, (strm)));                       \
+        if (tm_) HIP_TRY(c->timing.end(kind, ev_, s));                            \
     } while (0)
-#define LAUNCH(kind, call) LAUNCH_ON(s, kind, call)
 

@@ -21,10 +21,13 @@ struct Srv {
     std::vector<intptr_t> data;  // the context's data the server was opened on
     int slots = 0, ldb = 0, rk = 0, r_use = 0;
     hipStream_t s = nullptr;
+    // bfloat16 U1: the eigenvector correction follows the sparse product and
+    // goes into the residual update, as in the batch path
+    bool fused = false;
     hd::RowPart rp{};
-    int nchunk = 0;
+    int nchunk = 0, nrb = 0;
     DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, PT, part, scal, err, cols, maxit, xc, csc, cst, xq,
-        topk, rids, rsc, ybuf, qbuf, sim, qsplit;
+        topk, rids, rsc, ybuf, qbuf, sim, qsplit, Dg;
     hd::CgState st{};
     int32_t *h = nullptr;  // pinned: [0,ldb) active, [ldb,2ldb) iters, [2ldb,3ldb) status, err
     double *hr = nullptr;  // pinned: relres
@@ -34,7 +37,7 @@ struct Srv {
     void release() {
         DevBuf *all[] = {&X, &R, &P, &Q, &Z, &Cpart, &Cl, &Cs, &ClT, &CsT, &PT, &part, &scal, &err, &cols,
                          &maxit, &xc, &csc, &cst, &xq, &topk, &rids, &rsc, &ybuf, &qbuf, &sim,
-                         &qsplit};
+                         &qsplit, &Dg};
         for (DevBuf *b : all) b->release();
         if (h) (void)hipHostFree(h);
         if (hr) (void)hipHostFree(hr);
@@ -45,13 +48,18 @@ struct Srv {
     }
 };
 
-// Device bytes one solver column needs at n items (vectors X R P Q Z, the
-// coefficient columns, the partial sums and the ranking buffers).
+// Device bytes one solver column needs at n items (vectors X R P Q, and Z
+// for fp32 U1, the coefficient columns, the partial sums and the ranking
+// buffers).
 int64_t bytes_per_column(const hd_ctx *c, int rk, int nchunk, int nblk, int top_k, int ky) {
-    // X R P Q Z, the partial and full coefficient columns, reduction
-    // partials, the gathered x columns, the split P^T of the bfloat16 forms
-    return 5 * 4 * c->n + (int64_t)4 * rk * (nchunk + 4) + 8 * nblk + 4 * c->n * 2 +
-           (c->u_bf16() && rk > 0 ? 4 * c->ldut : 0) + (int64_t)top_k * 8 + (int64_t)ky * 8 + 64;
+    // the vectors, the partial and full coefficient columns, reduction
+    // partials (and the eigenvector part of gamma), the gathered x columns,
+    // the split P^T of the bfloat16 forms
+    const bool fused = c->u_bf16() && rk > 0;
+    const int64_t nrb = hd::uc_update_r_blocks(c->n);
+    const int64_t prow = fused && nrb > nblk ? nrb : nblk;
+    return (fused ? 4 : 5) * 4 * c->n + (int64_t)4 * rk * (nchunk + 4) + 8 * prow + (fused ? 8 * rk : 0) +
+           4 * c->n * 2 + (fused ? 4 * c->ldut : 0) + (int64_t)top_k * 8 + (int64_t)ky * 8 + 64;
 }
 
 // The context's loaded data and layouts; a server refuses to run once they
@@ -127,13 +135,16 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
                              hipGetErrorString(e_)));                                          \
     } while (0)
     SRV_TRY(hipStreamCreate(&v->s));
+    v->fused = c->u_bf16() && rk > 0;
+    v->nrb = hd::uc_update_r_blocks(c->n);
+    if (v->fused) SRV_TRY(v->Dg.ensure((size_t)rk * ldb * sizeof(double)));
     const size_t vec = (size_t)c->n * ldb * sizeof(float);
     SRV_TRY(v->X.ensure(vec));
     SRV_TRY(v->R.ensure(vec));
     SRV_TRY(v->P.ensure(vec));
     SRV_TRY(v->Q.ensure(vec));
     if (rk > 0) {
-        SRV_TRY(v->Z.ensure(vec));
+        if (!v->fused) SRV_TRY(v->Z.ensure(vec));
         SRV_TRY(v->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
         SRV_TRY(v->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->Cs.ensure((size_t)rk * ldb * sizeof(float)));
@@ -142,7 +153,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
         SRV_TRY(v->csc.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->cst.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
     }
-    SRV_TRY(v->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
+    SRV_TRY(v->part.ensure((size_t)(v->fused && v->nrb > rp.nblk ? v->nrb : rp.nblk) * ldb * sizeof(double)));
     SRV_TRY(v->scal.ensure((size_t)ldb * (5 * sizeof(double) + 4 * sizeof(int32_t)) + 128 * sizeof(int32_t)));
     SRV_TRY(v->err.ensure(16));
     SRV_TRY(v->cols.ensure((size_t)ldb * sizeof(int32_t)));
@@ -300,7 +311,26 @@ int hd_serve_step(hd_server *v, int32_t iters) {
     const hd::IterGuard g{nullptr, 0};
     float *X = v->X.as<float>(), *R = v->R.as<float>(), *P = v->P.as<float>(), *Q = v->Q.as<float>();
     uint16_t *ClT_hi = v->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
-    for (int it = 0; it < iters; ++it) {
+    for (int it = 0; it < iters && v->fused; ++it) {
+        // L1 U1^T P for every column (a newly admitted column has P = y);
+        // the correction goes into the residual update
+        uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
+        HIP_TRY(hd::launch_split_pt(N, ldb, P, c->ldut, PTh, PTl, g, s));
+        HIP_TRY(hd::launch_ut_p_bf16(N, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
+                                     v->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
+        HIP_TRY(hd::launch_reduce_c(v->nchunk, v->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), v->r_use,
+                                    v->Cl.as<float>(), g, s, v->Dg.as<double>(), v->o.alpha));
+        HIP_TRY(hd::launch_split_t(v->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
+        HIP_TRY(hd::launch_spmm(N, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, P, Q,
+                                ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb)));
+        HIP_TRY(hd::launch_cg_step_a(ldb, v->part.as<double>(), v->rp.nblk, v->st, g, s, v->Dg.as<double>(), rk));
+        HIP_TRY(hd::launch_uc_update_r_bf16(N, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q,
+                                            v->o.alpha, R, v->st.a, v->part.as<double>(), g, s,
+                                            c->tv(HD_TUNE_UC_NT, ldb)));
+        HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->nrb, v->o.tol, v->st, g, v->st.nact_part, s));
+        HIP_TRY(hd::launch_update_xp(N, ldb, X, P, R, v->st.a, v->st.beta, v->st.active, g, s));
+    }
+    for (int it = 0; it < iters && !v->fused; ++it) {
         const float *Zs = P;
         if (rk > 0) {
             // L1 U1^T P for every column (a newly admitted column has P = y)

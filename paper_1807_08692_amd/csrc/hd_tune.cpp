@@ -63,9 +63,11 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
     HIP_TRY(c->P.ensure(vec));
     HIP_TRY(c->Q.ensure(vec));
     HIP_TRY(c->Z.ensure(vec));
-    HIP_TRY(c->part.ensure((size_t)rp.nblk * ldb * sizeof(double)));
+    const int nrb = hd::uc_update_r_blocks(n);
+    HIP_TRY(c->part.ensure((size_t)(nrb > rp.nblk ? nrb : rp.nblk) * ldb * sizeof(double)));
     hipStream_t s = nullptr;
     HIP_TRY(hd::launch_fill_zero(c->P.as<float>(), (size_t)n * ldb, s));
+    HIP_TRY(hd::launch_fill_zero(c->Q.as<float>(), (size_t)n * ldb, s));
     HIP_TRY(hd::launch_fill_zero(c->Z.as<float>(), (size_t)n * ldb, s));
     uint16_t *PTh = nullptr, *PTl = nullptr, *CTh = nullptr, *CTl = nullptr;
     if (ubf) {
@@ -77,6 +79,9 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
         CTh = c->ClT.as<uint16_t>();
         CTl = CTh + (size_t)rk * ldb;
         HIP_TRY(hd::launch_fill_zero(reinterpret_cast<float *>(CTh), (size_t)rk * ldb, s));
+        // per-column CG step sizes of the timed residual updates (zero)
+        HIP_TRY(c->Dg.ensure((size_t)rk * ldb * sizeof(double)));
+        HIP_TRY(hd::launch_fill_zero(c->Dg.as<float>(), (size_t)rk * ldb * 2, s));
         HIP_TRY(hd::launch_split_pt(n, ldb, c->P.as<float>(), c->ldut, PTh, PTl, hd::IterGuard{nullptr, 0}, s));
     }
     const hd::IterGuard none{nullptr, 0};
@@ -90,8 +95,10 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
             return hd::launch_ut_p_bf16(n, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
                                         c->Cpart.as<float>(), none, s, v);
         default:
-            return hd::launch_u_c_bf16(n, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, CTh, CTl, ldb,
-                                       c->P.as<float>(), 0.99, c->Z.as<float>(), none, s, v);
+            // U C as it runs in CG: fused with the residual update
+            return hd::launch_uc_update_r_bf16(n, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, CTh, CTl, ldb,
+                                               c->Q.as<float>(), 0.99, c->Z.as<float>(), c->Dg.as<double>(),
+                                               c->part.as<double>(), none, s, v);
         }
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -71,16 +71,19 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 //   acc[m][n] = sum_k A[m][k] B[n][k]
 // with both operands K-contiguous bfloat16: A (M x K, row stride lda, one or
 // two terms A + Al) and B (N x K, row stride ldbk, split hi + lo). A block
-// covers 128 rows of M and 64*NT columns of N (from nb0); wave w owns the
-// columns nb0 + 16 NT w .. +16 NT (NT n-tiles) for all 128 rows (eight
-// m-tiles), so it holds 32 NT accumulators per lane. Per 32-wide K step the
-// block loads the 128 x 32 A tile (thread t: row t/2, 16 values from k
-// 16(t%2)) and the 64 NT x 32 B tile (hi and lo; NT 16-byte pieces per
-// thread) once, stages both in LDS, and every wave reads its A and B
-// fragments there; the next step's tiles are fetched into registers while
-// the current step's MFMAs run. Holding no operand fragments across steps
-// keeps the four-tile form at two waves per SIMD.
+// covers 128 rows of M and 64*NT columns of N (from nb0); wave w owns rows
+// m0 + 32 w .. +31 (two m-tiles) for all 64 NT columns (4 NT n-tiles), so it
+// holds 8 NT accumulators per lane. A is the large streamed operand (U1): each
+// wave loads its own A fragments straight from global memory into registers,
+// one 32-wide K step ahead, with no LDS staging and no barrier between the
+// load and its use. B (the coefficients, or the split P^T) is shared by the
+// four waves: per K step the block loads the 64 NT x 32 B tile (hi and lo; NT
+// 16-byte pieces per thread) once, stages it in LDS and every wave reads its
+// B fragments there; the next step's B pieces are fetched into registers while
+// the current step's MFMAs run.
 //   products per (A term, B term): A_hi B_hi + A_hi B_lo (+ A_lo B_hi)
+// The accumulation order over K (and of the terms) is fixed: results do not
+// depend on NT.
 // MFMA v_mfma_f32_16x16x32_bf16: A fragment = A[m0 + l%16][k + 8(l/16) ..+7],
 // B fragment = B[n + l%16][k + 8(l/16) ..+7], C[m = 4(l/16) + v][n = l%16].
 // LDS rows are padded to 40 halves (80 bytes) so the 16-byte fragment reads
@@ -91,30 +94,36 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
                                          int64_t m0, int64_t mend,
                                          const unsigned short *__restrict__ Bh,
                                          const unsigned short *__restrict__ Bl, int64_t ldbk,
-                                         int64_t nb0, int64_t k0, int64_t k1, f32x4 (&acc)[8][NT]) {
-    __shared__ __attribute__((aligned(16))) unsigned short As[128][40];
-    __shared__ __attribute__((aligned(16))) unsigned short Asl[LO ? 128 : 1][40];
+                                         int64_t nb0, int64_t k0, int64_t k1, f32x4 (&acc)[2][4 * NT]) {
     __shared__ __attribute__((aligned(16))) unsigned short Bsh[64 * NT][40];
     __shared__ __attribute__((aligned(16))) unsigned short Bsl[64 * NT][40];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
-    // A staging: row sm, k sk .. sk+15
-    const int sm = threadIdx.x / 2, sk = 16 * (threadIdx.x % 2);
-    const bool sok = m0 + sm < mend;
-    const unsigned short *sa = A + (size_t)(m0 + (sok ? sm : 0)) * lda + sk;
-    const unsigned short *sal = LO ? Al + (size_t)(m0 + (sok ? sm : 0)) * lda + sk : nullptr;
+    const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
+    // this lane's A rows (one per m-tile) and k offset
+    const unsigned short *pa[2];
+    const unsigned short *pal[2];
+    bool aok[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        const int64_t row = m0 + 32 * w + 16 * mt + c16;
+        aok[mt] = row < mend;
+        pa[mt] = A + (size_t)(aok[mt] ? row : 0) * lda + 8 * g;
+        pal[mt] = LO ? Al + (size_t)(aok[mt] ? row : 0) * lda + 8 * g : nullptr;
+    }
     // B staging: pieces p = NT t + j -> row p / 4, k 8 (p % 4)
     const int brow0 = (NT * threadIdx.x) / 4, bk0 = 8 * ((NT * threadIdx.x) % 4);
     const unsigned short *sbh = Bh + (size_t)(nb0 + brow0) * ldbk + bk0;
     const unsigned short *sbl = Bl + (size_t)(nb0 + brow0) * ldbk + bk0;
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-    bf16x8 ra[2], ral[2], rbh[NT], rbl[NT];
-    auto fetch = [&](int64_t k) {
+    bf16x8 af[2][2], afl[2][2], rbh[NT], rbl[NT];
+    auto fetch_a = [&](int slot, int64_t k) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            ra[u] = sok ? load8(sa + k + 8 * u) : zero;
-            if (LO) ral[u] = sok ? load8(sal + k + 8 * u) : zero;
+        for (int mt = 0; mt < 2; ++mt) {
+            af[slot][mt] = (aok[mt] && k < k1) ? load8(pa[mt] + k) : zero;
+            if (LO) afl[slot][mt] = (aok[mt] && k < k1) ? load8(pal[mt] + k) : zero;
         }
+    };
+    auto fetch_b = [&](int64_t k) {
         // NT pieces run along one row (NT <= 4 pieces = the row's 32 k)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
@@ -123,41 +132,37 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
         }
     };
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (k0 < k1) fetch(k0);
-    const int wn = 16 * NT * w;
-    for (int64_t k = k0; k < k1; k += 32) {
-        __syncthreads();  // the previous step's LDS reads are done
+        for (int n = 0; n < 4 * NT; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    fetch_a(0, k0);
+    if (k0 < k1) fetch_b(k0);
+    // two K steps per trip so that the A register slots have fixed names
+    for (int64_t k = k0; k < k1; k += 64) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            *reinterpret_cast<bf16x8 *>(&As[sm][sk + 8 * u]) = ra[u];
-            if (LO) *reinterpret_cast<bf16x8 *>(&Asl[sm][sk + 8 * u]) = ral[u];
-        }
+        for (int st = 0; st < 2; ++st) {
+            const int64_t kk = k + 32 * st;
+            if (kk < k1) {
+                __syncthreads();  // the previous step's LDS reads are done
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            *reinterpret_cast<bf16x8 *>(&Bsh[brow0][bk0 + 8 * j]) = rbh[j];
-            *reinterpret_cast<bf16x8 *>(&Bsl[brow0][bk0 + 8 * j]) = rbl[j];
-        }
-        __syncthreads();
-        if (k + 32 < k1) fetch(k + 32);
-        bf16x8 bh[NT], bl[NT];
+                for (int j = 0; j < NT; ++j) {
+                    *reinterpret_cast<bf16x8 *>(&Bsh[brow0][bk0 + 8 * j]) = rbh[j];
+                    *reinterpret_cast<bf16x8 *>(&Bsl[brow0][bk0 + 8 * j]) = rbl[j];
+                }
+                __syncthreads();
+                if (kk + 32 < k1) fetch_b(kk + 32);
+                fetch_a(st ^ 1, kk + 32);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            bh[n] = load8(&Bsh[wn + 16 * n + c16][8 * g]);
-            bl[n] = load8(&Bsl[wn + 16 * n + c16][8 * g]);
-        }
+                for (int n = 0; n < 4 * NT; ++n) {
+                    const bf16x8 bh = load8(&Bsh[16 * n + c16][8 * g]);
+                    const bf16x8 bl = load8(&Bsl[16 * n + c16][8 * g]);
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
-            const bf16x8 a = load8(&As[16 * mt + c16][8 * g]);
-            bf16x8 al = zero;
-            if (LO) al = load8(&Asl[16 * mt + c16][8 * g]);
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                acc[mt][n] = mfma16bf(a, bh[n], acc[mt][n]);
-                acc[mt][n] = mfma16bf(a, bl[n], acc[mt][n]);
-                if (LO) acc[mt][n] = mfma16bf(al, bh[n], acc[mt][n]);
+                    for (int mt = 0; mt < 2; ++mt) {
+                        acc[mt][n] = mfma16bf(af[st][mt], bh, acc[mt][n]);
+                        acc[mt][n] = mfma16bf(af[st][mt], bl, acc[mt][n]);
+                        if (LO) acc[mt][n] = mfma16bf(afl[st][mt], bh, acc[mt][n]);
+                    }
+                }
             }
         }
     }
@@ -237,21 +242,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
     const unsigned chunk = L / (ncg * nkg);
     const int64_t m0 = (int64_t)((L / ncg) % nkg) * 128;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     const int64_t ks = (int64_t)chunk * rc;
     const int64_t ke = ks + rc < kend_all ? ks + rc : kend_all;
-    f32x4 acc[8][NT];
+    f32x4 acc[2][4 * NT];
     tn_block<LO, NT>(UT, UTl, ldut, m0, rk, PTh, PTl, ldut, nb0, ks, ke, acc);
     float *out = Cpart + (size_t)chunk * rk * ldb;
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t k = m0 + 16 * mt + 4 * g + v;
+            const int64_t k = m0 + 32 * w + 16 * mt + 4 * g + v;
             if (k >= rk) continue;
 #pragma unroll
-            for (int n = 0; n < NT; ++n) out[(size_t)k * ldb + nw0 + 16 * n + c16] = acc[mt][n][v];
+            for (int n = 0; n < 4 * NT; ++n) out[(size_t)k * ldb + nb0 + 16 * n + c16] = acc[mt][n][v];
         }
 }
 
@@ -292,19 +297,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned 
     const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
     const int64_t i0 = (int64_t)(L / ncg) * 128;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
-    f32x4 acc[8][NT];
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
+    f32x4 acc[2][4 * NT];
     tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t i = i0 + 16 * mt + 4 * g + v;
+            const int64_t i = i0 + 32 * w + 16 * mt + 4 * g + v;
             if (i >= N) continue;
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const size_t o = vec_index(N, ldb, i, (int)(nw0 + 16 * n + c16));
+            for (int n = 0; n < 4 * NT; ++n) {
+                const size_t o = vec_index(N, ldb, i, (int)(nb0 + 16 * n + c16));
                 Z[o] = P[o] + alpha * acc[mt][n][v];
             }
         }
@@ -350,38 +355,37 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
     const int64_t rb = (int64_t)(L / ncg);
     const int64_t i0 = rb * 128;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
-    f32x4 acc[8][NT];
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
+    f32x4 acc[2][4 * NT];
     tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
-    double av[NT], ss[NT];
+    __shared__ double sh[4][64 * NT];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        av[n] = a[nw0 + 16 * n + c16];
-        ss[n] = 0.0;
-    }
+    for (int n = 0; n < 4 * NT; ++n) {
+        const int col = (int)(nb0 + 16 * n + c16);
+        const double av = a[col];
+        double ss = 0.0;
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t i = i0 + 16 * mt + 4 * g + v;
-            if (i >= N) continue;
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const size_t o = vec_index(N, ldb, i, (int)(nw0 + 16 * n + c16));
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + 32 * w + 16 * mt + 4 * g + v;
+                if (i >= N) continue;
+                const size_t o = vec_index(N, ldb, i, col);
                 const float q = Qs[o] + cc * acc[mt][n][v];
                 float r = R[o];
-                if (av[n] != 0.0) r = (float)((double)r - av[n] * (double)q);
+                if (av != 0.0) r = (float)((double)r - av * (double)q);
                 R[o] = r;
-                ss[n] += (double)r * (double)r;
+                ss += (double)r * (double)r;
             }
-        }
-#pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        ss[n] += __shfl_xor(ss[n], 16, kWave);
-        ss[n] += __shfl_xor(ss[n], 32, kWave);
-        if (g == 0) part[(size_t)rb * ldb + nw0 + 16 * n + c16] = ss[n];
+        ss += __shfl_xor(ss, 16, kWave);
+        ss += __shfl_xor(ss, 32, kWave);
+        if (g == 0) sh[w][16 * n + c16] = ss;
     }
+    __syncthreads();
+    // the block's 128 rows: the four waves' sums in a fixed order
+    for (int t = threadIdx.x; t < 64 * NT; t += kBlock)
+        part[(size_t)rb * ldb + nb0 + t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
 }
 
 int uc_update_r_blocks(int64_t N) { return (int)((N + 127) / 128); }
@@ -417,35 +421,40 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
                                                        const unsigned short *__restrict__ CT_lo, int ldc,
                                                        const float *__restrict__ X, float *__restrict__ x,
                                                        int64_t ldx) {
-    __shared__ float T[4][16 * NT][17];
+    __shared__ float T[4][64][17];
     const unsigned L = xcd_tile(), ncg = (unsigned)ldc / (64 * NT);
     const int64_t i0 = (int64_t)(L / ncg) * 128;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT, nw0 = nb0 + 16 * NT * w;
-    f32x4 acc[8][NT];
+    const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
+    f32x4 acc[2][4 * NT];
     tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
+    // per m-tile (16 items) and group of four n-tiles (64 queries)
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
-        __syncthreads();
+    for (int mt = 0; mt < 2; ++mt) {
+        const int64_t ib = i0 + 32 * w + 16 * mt;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int rl = 4 * g + v;
-            const int64_t i = i0 + 16 * mt + rl;
+        for (int ng = 0; ng < NT; ++ng) {
+            __syncthreads();
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const int bl = 16 * n + c16;
-                float val = acc[mt][n][v];
-                if (i < N) val += X[vec_index(N, ldc, i, (int)(nw0 + bl))];
-                T[w][bl][rl] = val;
+            for (int v = 0; v < 4; ++v) {
+                const int rl = 4 * g + v;
+                const int64_t i = ib + rl;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int bl = 16 * q + c16;
+                    float val = acc[mt][4 * ng + q][v];
+                    if (i < N) val += X[vec_index(N, ldc, i, (int)(nb0 + 64 * ng + bl))];
+                    T[w][bl][rl] = val;
+                }
             }
-        }
-        __syncthreads();
-        // lane -> (query bl = f / 16, item f % 16) over the wave's 16 NT queries
-        for (int f = lane; f < 16 * NT * 16; f += kWave) {
-            const int bl = f / 16, rl = f % 16;
-            const int64_t b = nw0 + bl, i = i0 + 16 * mt + rl;
-            if (b < B && i < N) x[(size_t)b * ldx + i] = T[w][bl][rl];
+            __syncthreads();
+            // lane -> (query bl = f / 16, item f % 16)
+            for (int f = lane; f < 64 * 16; f += kWave) {
+                const int bl = f / 16, rl = f % 16;
+                const int64_t b = nb0 + 64 * ng + bl, i = ib + rl;
+                if (b < B && i < N) x[(size_t)b * ldx + i] = T[w][bl][rl];
+            }
         }
     }
 }
@@ -486,17 +495,17 @@ __global__ __launch_bounds__(kBlock) void k_split_q(int B, int d, int ldv, const
 // sim[b][j] = q[b] . V[j] with V stored bfloat16 (N x ldv) and q split hi/lo.
 // M = b, N = j, K = t. A block covers 64 queries x 256 items; wave w owns
 // items [64w, 64w+64) (four n-tiles) for all 64 queries (four m-tiles, hi
-// and lo), so each LDS fragment feeds four or eight MFMAs. Per 32-wide k
-// chunk the V tile (256 x 32) and the Q tiles (64 x 32, hi and lo) are staged
-// in LDS; the next chunk is fetched into registers meanwhile. The logical
-// tiles run over the query tiles fastest, so the tiles of one item range run
-// on one XCD and share V through its L2.
-__global__ __launch_bounds__(kBlock) void k_sim_bf16(int64_t N, int B, int ldv,
+// and lo), so each V fragment feeds eight MFMAs. V rows are read by one wave
+// only: each wave loads its V fragments straight from global memory into
+// registers, one 32-wide k chunk ahead. The Q tiles (64 x 32, hi and lo) are
+// shared by the four waves and staged in LDS per chunk. The logical tiles run
+// over the query tiles fastest, so the tiles of one item range run on one
+// XCD and share V through its L2.
+__global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ldv,
                                                      const unsigned short *__restrict__ Qh,
                                                      const unsigned short *__restrict__ Ql,
                                                      const unsigned short *__restrict__ V,
                                                      float *__restrict__ sim, int64_t lds) {
-    __shared__ __attribute__((aligned(16))) unsigned short Vs[256][40];
     __shared__ __attribute__((aligned(16))) unsigned short Qs[2][64][40];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
@@ -509,39 +518,52 @@ __global__ __launch_bounds__(kBlock) void k_sim_bf16(int64_t N, int B, int ldv,
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-    // staging: V row jb + t (32 values = 4 x 16 B); Q: thread t -> array t/128,
-    // row (t%128)/2, k 16*(t%2) .. +15
-    const int64_t jv = jb + threadIdx.x;
+    // this lane's V rows (one per n-tile) at k offset 8 (l / 16)
+    const unsigned short *pv[4];
+    bool vok[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const int64_t j = jb + 64 * w + 16 * n + c16;
+        vok[n] = j < N;
+        pv[n] = V + (size_t)(vok[n] ? j : 0) * ldv + 8 * g;
+    }
+    // Q staging: thread t -> array t/128, row (t%128)/2, k 16*(t%2) .. +15
     const int qa = threadIdx.x / 128, qr = (threadIdx.x % 128) / 2, qk = 16 * (threadIdx.x % 2);
     const unsigned short *qsrc = (qa == 0 ? Qh : Ql) + (size_t)(b0 + qr) * ldv;
     const bool qok = b0 + qr < B;
-    bf16x8 vr[4], qv[2];
-    auto fetch = [&](int t0) {
+    bf16x8 vf[2][4], qv[2];
+    auto fetch_v = [&](int slot, int t0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) vr[u] = jv < N ? load8(V + (size_t)jv * ldv + t0 + 8 * u) : zero;
+        for (int n = 0; n < 4; ++n) vf[slot][n] = (vok[n] && t0 < ldv) ? load8(pv[n] + t0) : zero;
+    };
+    auto fetch_q = [&](int t0) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) qv[u] = qok ? load8(qsrc + t0 + qk + 8 * u) : zero;
     };
-    fetch(0);
-    for (int t0 = 0; t0 < ldv; t0 += 32) {
-        __syncthreads();
+    fetch_v(0, 0);
+    fetch_q(0);
+    // two k chunks per trip so that the V register slots have fixed names
+    for (int t0 = 0; t0 < ldv; t0 += 64) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) *reinterpret_cast<bf16x8 *>(&Vs[threadIdx.x][8 * u]) = vr[u];
+        for (int st = 0; st < 2; ++st) {
+            const int tt = t0 + 32 * st;
+            if (tt < ldv) {
+                __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 2; ++u) *reinterpret_cast<bf16x8 *>(&Qs[qa][qr][qk + 8 * u]) = qv[u];
-        __syncthreads();
-        if (t0 + 32 < ldv) fetch(t0 + 32);
-        bf16x8 bv[4];
+                for (int u = 0; u < 2; ++u) *reinterpret_cast<bf16x8 *>(&Qs[qa][qr][qk + 8 * u]) = qv[u];
+                __syncthreads();
+                if (tt + 32 < ldv) fetch_q(tt + 32);
+                fetch_v(st ^ 1, tt + 32);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) bv[n] = load8(&Vs[64 * w + 16 * n + c16][8 * g]);
+                for (int m = 0; m < 4; ++m) {
+                    const bf16x8 h = load8(&Qs[0][16 * m + c16][8 * g]);
+                    const bf16x8 l = load8(&Qs[1][16 * m + c16][8 * g]);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const bf16x8 h = load8(&Qs[0][16 * m + c16][8 * g]);
-            const bf16x8 l = load8(&Qs[1][16 * m + c16][8 * g]);
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                acc[m][n] = mfma16bf(h, bv[n], acc[m][n]);
-                acc[m][n] = mfma16bf(l, bv[n], acc[m][n]);
+                    for (int n = 0; n < 4; ++n) {
+                        acc[m][n] = mfma16bf(h, vf[st][n], acc[m][n]);
+                        acc[m][n] = mfma16bf(l, vf[st][n], acc[m][n]);
+                    }
+                }
             }
         }
     }
