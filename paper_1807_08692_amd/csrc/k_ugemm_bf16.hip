@@ -66,14 +66,22 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
     return hipGetLastError();
 }
 
+// m-tiles per wave of the block GEMM for NT n-tiles per wave
+constexpr int tn_mt(int nt) { return nt == 4 ? 2 : 4; }
+// rows of M per block
+constexpr int tn_rows(int nt) { return 64 * tn_mt(nt); }
+static inline int tn_rows_rt(int nt) { return nt == 4 ? tn_rows(4) : tn_rows(1); }
+
 // ---------------------------------------------------------------------------
 // Block GEMM shared by the three eigenvector products:
 //   acc[m][n] = sum_k A[m][k] B[n][k]
 // with both operands K-contiguous bfloat16: A (M x K, row stride lda, one or
 // two terms A + Al) and B (N x K, row stride ldbk, split hi + lo). A block
-// covers 128 rows of M and 64*NT columns of N (from nb0); wave w owns rows
-// m0 + 32 w .. +31 (two m-tiles) for all 64 NT columns (4 NT n-tiles), so it
-// holds 8 NT accumulators per lane. A is the large streamed operand (U1): each
+// covers 64 MT rows of M and 64*NT columns of N (from nb0); wave w owns rows
+// m0 + 16 MT w .. +16 MT - 1 (MT m-tiles) for all 64 NT columns (4 NT
+// n-tiles), so it holds 4 MT NT accumulators per lane. MT = 4 (NT <= 2) or 2
+// (NT = 4, to stay within the registers of two waves per SIMD): each B
+// fragment read from LDS feeds 3 MT MFMAs. A is the large streamed operand (U1): each
 // wave loads its own A fragments straight from global memory into registers,
 // one 32-wide K step ahead, with no LDS staging and no barrier between the
 // load and its use. B (the coefficients, or the split P^T) is shared by the
@@ -88,25 +96,25 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 // B fragment = B[n + l%16][k + 8(l/16) ..+7], C[m = 4(l/16) + v][n = l%16].
 // LDS rows are padded to 40 halves (80 bytes) so the 16-byte fragment reads
 // of 16 consecutive rows fall in distinct banks.
-template <bool LO, int NT>
+template <bool LO, int NT, int MT = tn_mt(NT)>
 __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
                                          const unsigned short *__restrict__ Al, int64_t lda,
                                          int64_t m0, int64_t mend,
                                          const unsigned short *__restrict__ Bh,
                                          const unsigned short *__restrict__ Bl, int64_t ldbk,
-                                         int64_t nb0, int64_t k0, int64_t k1, f32x4 (&acc)[2][4 * NT]) {
+                                         int64_t nb0, int64_t k0, int64_t k1, f32x4 (&acc)[MT][4 * NT]) {
     __shared__ __attribute__((aligned(16))) unsigned short Bsh[64 * NT][40];
     __shared__ __attribute__((aligned(16))) unsigned short Bsl[64 * NT][40];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
     const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
     // this lane's A rows (one per m-tile) and k offset
-    const unsigned short *pa[2];
-    const unsigned short *pal[2];
-    bool aok[2];
+    const unsigned short *pa[MT];
+    const unsigned short *pal[MT];
+    bool aok[MT];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        const int64_t row = m0 + 32 * w + 16 * mt + c16;
+    for (int mt = 0; mt < MT; ++mt) {
+        const int64_t row = m0 + 16 * MT * w + 16 * mt + c16;
         aok[mt] = row < mend;
         pa[mt] = A + (size_t)(aok[mt] ? row : 0) * lda + 8 * g;
         pal[mt] = LO ? Al + (size_t)(aok[mt] ? row : 0) * lda + 8 * g : nullptr;
@@ -115,10 +123,10 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
     const int brow0 = (NT * threadIdx.x) / 4, bk0 = 8 * ((NT * threadIdx.x) % 4);
     const unsigned short *sbh = Bh + (size_t)(nb0 + brow0) * ldbk + bk0;
     const unsigned short *sbl = Bl + (size_t)(nb0 + brow0) * ldbk + bk0;
-    bf16x8 af[2][2], afl[2][2], rbh[NT], rbl[NT];
+    bf16x8 af[2][MT], afl[2][MT], rbh[NT], rbl[NT];
     auto fetch_a = [&](int slot, int64_t k) {
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
+        for (int mt = 0; mt < MT; ++mt) {
             af[slot][mt] = (aok[mt] && k < k1) ? load8(pa[mt] + k) : zero;
             if (LO) afl[slot][mt] = (aok[mt] && k < k1) ? load8(pal[mt] + k) : zero;
         }
@@ -132,7 +140,7 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
         }
     };
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int n = 0; n < 4 * NT; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     fetch_a(0, k0);
@@ -157,7 +165,7 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
                     const bf16x8 bh = load8(&Bsh[16 * n + c16][8 * g]);
                     const bf16x8 bl = load8(&Bsl[16 * n + c16][8 * g]);
 #pragma unroll
-                    for (int mt = 0; mt < 2; ++mt) {
+                    for (int mt = 0; mt < MT; ++mt) {
                         acc[mt][n] = mfma16bf(af[st][mt], bh, acc[mt][n]);
                         acc[mt][n] = mfma16bf(af[st][mt], bl, acc[mt][n]);
                         if (LO) acc[mt][n] = mfma16bf(afl[st][mt], bh, acc[mt][n]);
@@ -238,22 +246,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
                                                     int64_t rc, int64_t kend_all,
                                                     float *__restrict__ Cpart, IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
-    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT), nkg = (unsigned)(rk + 127) / 128;
+    constexpr int MT = tn_mt(NT), RB = tn_rows(NT);
+    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT), nkg = (unsigned)(rk + RB - 1) / RB;
     const unsigned chunk = L / (ncg * nkg);
-    const int64_t m0 = (int64_t)((L / ncg) % nkg) * 128;
+    const int64_t m0 = (int64_t)((L / ncg) % nkg) * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     const int64_t ks = (int64_t)chunk * rc;
     const int64_t ke = ks + rc < kend_all ? ks + rc : kend_all;
-    f32x4 acc[2][4 * NT];
+    f32x4 acc[MT][4 * NT];
     tn_block<LO, NT>(UT, UTl, ldut, m0, rk, PTh, PTl, ldut, nb0, ks, ke, acc);
     float *out = Cpart + (size_t)chunk * rk * ldb;
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t k = m0 + 32 * w + 16 * mt + 4 * g + v;
+            const int64_t k = m0 + 16 * MT * w + 16 * mt + 4 * g + v;
             if (k >= rk) continue;
 #pragma unroll
             for (int n = 0; n < 4 * NT; ++n) out[(size_t)k * ldb + nb0 + 16 * n + c16] = acc[mt][n][v];
@@ -270,7 +279,8 @@ hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned 
     if (kend > ldut || rc % 32 != 0) return hipErrorInvalidValue;
     const int nt = tn_nt(ldb, ntr, 4);
     if (nt == 0) return hipErrorInvalidValue;
-    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((rk + 127) / 128) * (unsigned)nchunk;
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((rk + tn_rows_rt(nt) - 1) / tn_rows_rt(nt)) *
+                          (unsigned)nchunk;
 #define HD_UTP(LOV, NTV) \
     k_ut_p_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(UT, UT_lo ? UT_lo : UT, ldut, rk, PTh, PTl, ldb, rc, kend, Cpart, g)
     if (UT_lo) {
@@ -295,17 +305,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned 
                                                    float *__restrict__ Z, IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
-    const int64_t i0 = (int64_t)(L / ncg) * 128;
+    constexpr int MT = tn_mt(NT), RB = tn_rows(NT);
+    const int64_t i0 = (int64_t)(L / ncg) * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
-    f32x4 acc[2][4 * NT];
+    f32x4 acc[MT][4 * NT];
     tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t i = i0 + 32 * w + 16 * mt + 4 * g + v;
+            const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
             if (i >= N) continue;
 #pragma unroll
             for (int n = 0; n < 4 * NT; ++n) {
@@ -321,7 +332,7 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
                            int ntr) {
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
-    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + 127) / 128);
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
     const float a = (float)alpha;
 #define HD_UC(LOV, NTV) \
     k_u_c_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, P, a, Z, g)
@@ -334,14 +345,16 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
     return hipGetLastError();
 }
 
+constexpr int kUcrMt = 2;  // m-tiles per wave of the fused residual update
+
 // The eigenvector correction applied after the sparse product, fused with the
 // CG residual update. With Qs = (P - alpha S P) / (1 - alpha) from the sparse
 // product, the deflated operator gives Q = Qs + c U Cl, c = alpha / (1 - alpha)
 // (Section 4.2, eq. (box)); Q is used once, in r -= a Q, so it is never
 // stored: each element of the U Cl tile goes straight into the update of r,
 // which follows update_r (double arithmetic, a = 0 leaves a stopped column
-// untouched), and the block's column sums of r^2 go to part, one row of ldb
-// doubles per 128-row block.
+// untouched), and the column sums of r^2 go to part, one row of ldb doubles
+// per 128-row group (a block covers one or two groups).
 template <bool LO, int NT>
 __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const unsigned short *__restrict__ U,
                                                            const unsigned short *__restrict__ Ul, int rp, int rk,
@@ -351,25 +364,32 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
                                                            float *__restrict__ R, const double *__restrict__ a,
                                                            double *__restrict__ part, IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
+    // two m-tiles per wave (three waves per SIMD): with four, the main loop
+    // is shorter but the epilogue's loads of Qs and r overlap less, and the
+    // kernel measured no faster
+    constexpr int MT = kUcrMt, RB = 64 * kUcrMt;
     const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
     const int64_t rb = (int64_t)(L / ncg);
-    const int64_t i0 = rb * 128;
+    const int64_t i0 = rb * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
-    f32x4 acc[2][4 * NT];
-    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    f32x4 acc[MT][4 * NT];
+    tn_block<LO, NT, MT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
-    __shared__ double sh[4][64 * NT];
+    // r^2 of each 16-row m-tile and column (4 rows per lane, then across the
+    // lane groups), summed below over the m-tiles of each 128-row group in
+    // order: the same sums whatever the block shape
+    __shared__ double sh[4 * MT][64 * NT];
 #pragma unroll
     for (int n = 0; n < 4 * NT; ++n) {
         const int col = (int)(nb0 + 16 * n + c16);
         const double av = a[col];
-        double ss = 0.0;
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < MT; ++mt) {
+            double ss = 0.0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t i = i0 + 32 * w + 16 * mt + 4 * g + v;
+                const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
                 if (i >= N) continue;
                 const size_t o = vec_index(N, ldb, i, col);
                 const float q = Qs[o] + cc * acc[mt][n][v];
@@ -378,14 +398,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
                 R[o] = r;
                 ss += (double)r * (double)r;
             }
-        ss += __shfl_xor(ss, 16, kWave);
-        ss += __shfl_xor(ss, 32, kWave);
-        if (g == 0) sh[w][16 * n + c16] = ss;
+            ss += __shfl_xor(ss, 16, kWave);
+            ss += __shfl_xor(ss, 32, kWave);
+            if (g == 0) sh[MT * w + mt][16 * n + c16] = ss;
+        }
     }
     __syncthreads();
-    // the block's 128 rows: the four waves' sums in a fixed order
-    for (int t = threadIdx.x; t < 64 * NT; t += kBlock)
-        part[(size_t)rb * ldb + nb0 + t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+    for (int t = threadIdx.x; t < (MT / 2) * 64 * NT; t += kBlock) {
+        const int q = t / (64 * NT), c = t % (64 * NT);
+        const int64_t grp = rb * (MT / 2) + q;  // 128-row group; ceil(N / 128) of them
+        if (grp * 128 >= N) continue;
+        double sum = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sum += sh[8 * q + j][c];
+        part[(size_t)grp * ldb + nb0 + c] = sum;
+    }
 }
 
 int uc_update_r_blocks(int64_t N) { return (int)((N + 127) / 128); }
@@ -396,7 +423,7 @@ hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const uns
                                    IterGuard g, hipStream_t s, int ntr) {
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
-    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)uc_update_r_blocks(N);
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + 64 * kUcrMt - 1) / (64 * kUcrMt));
     const float cc = (float)(alpha / (1.0 - alpha));
 #define HD_UR(LOV, NTV)                                                                                   \
     k_uc_update_r_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, Qs, \
@@ -422,17 +449,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
                                                        const float *__restrict__ X, float *__restrict__ x,
                                                        int64_t ldx) {
     __shared__ float T[4][64][17];
+    constexpr int MT = tn_mt(NT), RB = tn_rows(NT);
     const unsigned L = xcd_tile(), ncg = (unsigned)ldc / (64 * NT);
-    const int64_t i0 = (int64_t)(L / ncg) * 128;
+    const int64_t i0 = (int64_t)(L / ncg) * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
-    f32x4 acc[2][4 * NT];
+    f32x4 acc[MT][4 * NT];
     tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // per m-tile (16 items) and group of four n-tiles (64 queries)
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        const int64_t ib = i0 + 32 * w + 16 * mt;
+    for (int mt = 0; mt < MT; ++mt) {
+        const int64_t ib = i0 + 16 * MT * w + 16 * mt;
 #pragma unroll
         for (int ng = 0; ng < NT; ++ng) {
             __syncthreads();
@@ -465,7 +493,7 @@ hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const 
                                int64_t ldx, hipStream_t s, int ntr) {
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
-    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + 127) / 128);
+    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
 #define HD_CB(LOV, NTV) \
     k_combine_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, B, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, X, x, ldx)
     if (U_lo) {

@@ -2,6 +2,7 @@
 
     python -m paper_1807_08692_amd.profsum trace TRACE_CSV > summary.md
     python -m paper_1807_08692_amd.profsum traffic FETCH_CSV WRITE_CSV OUT_JSON > table.md
+    python -m paper_1807_08692_amd.profsum mfma COUNTER_CSV > mfma.md
 
 `trace` reads a --kernel-trace CSV (one row per dispatch) and prints, per
 kernel, the dispatch count and mean duration over all dispatches and over the
@@ -32,6 +33,7 @@ KINDS = {
     "hd::k_ut_p_tn": ("ut_p", "k_ugemm_bf16.hip"),
     "hd::k_ut_p": ("ut_p", "k_ugemm.hip"),
     "hd::k_u_c_tn": ("u_c", "k_ugemm_bf16.hip"),
+    "hd::k_uc_update_r_tn": ("u_c", "k_ugemm_bf16.hip"),
     "hd::k_u_c": ("u_c", "k_ugemm.hip"),
     "hd::k_update_xp_pt": ("update_xp", "k_cg.hip"),
     "hd::k_update_xp": ("update_xp", "k_cg.hip"),
@@ -116,10 +118,44 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str) -> str:
     return head + "\n".join(rows)
 
 
+def mfma(path: str) -> str:
+    """Matrix-core use per kernel from a --pmc pass with SQ_VALU_MFMA_BUSY_CYCLES,
+    SQ_BUSY_CU_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_BF16, SQ_LDS_BANK_CONFLICT and
+    GRBM_GUI_ACTIVE: per dispatch, each counter summed over its instances;
+    means over the working dispatches (CU-busy cycles >= 5% of the kernel's
+    largest). MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x
+    SQ_BUSY_CU_CYCLES); LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_BUSY_CU_CYCLES."""
+    per = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(float)))
+    for r in csv.DictReader(open(path)):
+        per[short(r["Kernel_Name"])][r["Dispatch_Id"]][r["Counter_Name"]] += float(r["Counter_Value"])
+    out = ["| kernel | dispatches | MFMA busy | bf16 MFMA ops (x512 flop) per dispatch | LDS bank-conflict cycles / CU-busy cycles |",
+           "|---|---|---|---|---|"]
+    rows = []
+    for k, disp in per.items():
+        if not k.startswith("hd::"):
+            continue
+        busy = [d.get("SQ_BUSY_CU_CYCLES", 0.0) for d in disp.values()]
+        mx = max(busy) if busy else 0.0
+        work = [d for d in disp.values() if mx > 0 and d.get("SQ_BUSY_CU_CYCLES", 0.0) >= 0.05 * mx]
+        if not work:
+            continue
+        mean = {c: sum(d.get(c, 0.0) for d in work) / len(work) for c in work[0]}
+        if mean.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) <= 0.0:
+            continue
+        cu = mean.get("SQ_BUSY_CU_CYCLES", 0.0)
+        rows.append((mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * len(work),
+                     f"| {k} | {len(work)} | {mean.get('SQ_VALU_MFMA_BUSY_CYCLES', 0.0) / (4 * cu):.3f} "
+                     f"| {mean['SQ_INSTS_VALU_MFMA_MOPS_BF16']:.4g} | {mean.get('SQ_LDS_BANK_CONFLICT', 0.0) / cu:.3f} |"))
+    out += [r for _, r in sorted(rows, reverse=True)]
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         print(trace(sys.argv[2]))
     elif sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "mfma":
+        print(mfma(sys.argv[2]))
     else:
         raise SystemExit(__doc__)
