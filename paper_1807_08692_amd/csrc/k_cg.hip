@@ -390,30 +390,36 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
         bv[q] = beta[b0 + c4 + q];
         kv[q] = active[b0 + c4 + q];
     }
+    // the four rows' loads first, unconditionally (a row past N reads row
+    // N - 1 and stores nothing), so all twelve are in flight together
+    float4 xv[4], pv[4], rv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = i0 + threadIdx.x / 16 + 16 * j;
+        const size_t o = vec_index(N, ldb, i < N ? i : N - 1, b0 + c4);
+        xv[j] = *reinterpret_cast<const float4 *>(X + o);
+        pv[j] = *reinterpret_cast<const float4 *>(P + o);
+        rv[j] = *reinterpret_cast<const float4 *>(R + o);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int r = threadIdx.x / 16 + 16 * j;
         const int64_t i = i0 + r;
-        float pn[4] = {0.f, 0.f, 0.f, 0.f};
+        float xs[4] = {xv[j].x, xv[j].y, xv[j].z, xv[j].w}, ps[4] = {pv[j].x, pv[j].y, pv[j].z, pv[j].w};
+        const float rs[4] = {rv[j].x, rv[j].y, rv[j].z, rv[j].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (av[q] != 0.0) xs[q] = (float)((double)xs[q] + av[q] * (double)ps[q]);
+            if (kv[q]) ps[q] = (float)((double)rs[q] + bv[q] * (double)ps[q]);
+        }
         if (i < N) {
             const size_t o = vec_index(N, ldb, i, b0 + c4);
-            float4 *xp = reinterpret_cast<float4 *>(X + o);
-            float4 *pp = reinterpret_cast<float4 *>(P + o);
-            const float4 rv = *reinterpret_cast<const float4 *>(R + o);
-            float4 x = *xp, p = *pp;
-            float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w};
-            const float rs[4] = {rv.x, rv.y, rv.z, rv.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (av[q] != 0.0) xs[q] = (float)((double)xs[q] + av[q] * (double)ps[q]);
-                if (kv[q]) ps[q] = (float)((double)rs[q] + bv[q] * (double)ps[q]);
-                pn[q] = ps[q];
-            }
-            *xp = make_float4(xs[0], xs[1], xs[2], xs[3]);
-            *pp = make_float4(ps[0], ps[1], ps[2], ps[3]);
+            *reinterpret_cast<float4 *>(X + o) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+            *reinterpret_cast<float4 *>(P + o) = make_float4(ps[0], ps[1], ps[2], ps[3]);
         }
+        // items past N stay zero in the transpose
 #pragma unroll
-        for (int q = 0; q < 4; ++q) T[c4 + q][r] = pn[q];
+        for (int q = 0; q < 4; ++q) T[c4 + q][r] = i < N ? ps[q] : 0.f;
     }
     __syncthreads();
     typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));

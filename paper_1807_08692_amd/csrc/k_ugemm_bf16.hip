@@ -107,44 +107,51 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
     __shared__ __attribute__((aligned(16))) unsigned short Bsl[64 * NT][40];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-    // this lane's A rows (one per m-tile) and k offset
+    // this lane's A rows (one per m-tile) and k offset. Every load is
+    // unconditional and in bounds: a row past mend reads row m0 instead
+    // (its accumulator rows are never stored), and a K step past k1 reloads
+    // the last step (never used). Loads without branches keep the compiler's
+    // wait counts exact, so waiting for the staged B pieces does not also
+    // wait for the A prefetch issued after them.
     const unsigned short *pa[MT];
     const unsigned short *pal[MT];
-    bool aok[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int64_t row = m0 + 16 * MT * w + 16 * mt + c16;
-        aok[mt] = row < mend;
-        pa[mt] = A + (size_t)(aok[mt] ? row : 0) * lda + 8 * g;
-        pal[mt] = LO ? Al + (size_t)(aok[mt] ? row : 0) * lda + 8 * g : nullptr;
+        const int64_t rr = row < mend ? row : m0;
+        pa[mt] = A + (size_t)rr * lda + 8 * g;
+        pal[mt] = LO ? Al + (size_t)rr * lda + 8 * g : nullptr;
     }
+    const int64_t klast = k1 - 32;  // the last K step (K ranges are multiples of 32)
     // B staging: pieces p = NT t + j -> row p / 4, k 8 (p % 4)
     const int brow0 = (NT * threadIdx.x) / 4, bk0 = 8 * ((NT * threadIdx.x) % 4);
     const unsigned short *sbh = Bh + (size_t)(nb0 + brow0) * ldbk + bk0;
     const unsigned short *sbl = Bl + (size_t)(nb0 + brow0) * ldbk + bk0;
     bf16x8 af[2][MT], afl[2][MT], rbh[NT], rbl[NT];
     auto fetch_a = [&](int slot, int64_t k) {
+        const int64_t kc = k < k1 ? k : klast;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            af[slot][mt] = (aok[mt] && k < k1) ? load8(pa[mt] + k) : zero;
-            if (LO) afl[slot][mt] = (aok[mt] && k < k1) ? load8(pal[mt] + k) : zero;
+            af[slot][mt] = load8(pa[mt] + kc);
+            if (LO) afl[slot][mt] = load8(pal[mt] + kc);
         }
     };
     auto fetch_b = [&](int64_t k) {
+        const int64_t kc = k < k1 ? k : klast;
         // NT pieces run along one row (NT <= 4 pieces = the row's 32 k)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            rbh[j] = load8(sbh + k + 8 * j);
-            rbl[j] = load8(sbl + k + 8 * j);
+            rbh[j] = load8(sbh + kc + 8 * j);
+            rbl[j] = load8(sbl + kc + 8 * j);
         }
     };
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int n = 0; n < 4 * NT; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (k0 >= k1) return;
     fetch_a(0, k0);
-    if (k0 < k1) fetch_b(k0);
+    fetch_b(k0);
     // two K steps per trip so that the A register slots have fixed names
     for (int64_t k = k0; k < k1; k += 64) {
 #pragma unroll
@@ -158,7 +165,7 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
                     *reinterpret_cast<bf16x8 *>(&Bsl[brow0][bk0 + 8 * j]) = rbl[j];
                 }
                 __syncthreads();
-                if (kk + 32 < k1) fetch_b(kk + 32);
+                fetch_b(kk + 32);
                 fetch_a(st ^ 1, kk + 32);
 #pragma unroll
                 for (int n = 0; n < 4 * NT; ++n) {
@@ -312,16 +319,20 @@ __global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned 
     f32x4 acc[MT][4 * NT];
     tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
+    // branch-free loads (rows past N read row N - 1 and store nothing)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
-            if (i >= N) continue;
+            const int64_t ic = i < N ? i : N - 1;
+            float pv[4 * NT];
 #pragma unroll
-            for (int n = 0; n < 4 * NT; ++n) {
-                const size_t o = vec_index(N, ldb, i, (int)(nb0 + 16 * n + c16));
-                Z[o] = P[o] + alpha * acc[mt][n][v];
+            for (int n = 0; n < 4 * NT; ++n) pv[n] = P[vec_index(N, ldb, ic, (int)(nb0 + 16 * n + c16))];
+            if (i < N) {
+#pragma unroll
+                for (int n = 0; n < 4 * NT; ++n)
+                    Z[vec_index(N, ldb, i, (int)(nb0 + 16 * n + c16))] = pv[n] + alpha * acc[mt][n][v];
             }
         }
 }
@@ -355,7 +366,7 @@ constexpr int kUcrMt = 2;  // m-tiles per wave of the fused residual update
 // which follows update_r (double arithmetic, a = 0 leaves a stopped column
 // untouched), and the column sums of r^2 go to part, one row of ldb doubles
 // per 128-row group (a block covers one or two groups).
-template <bool LO, int NT>
+template <bool LO, int NT, int MT = kUcrMt>
 __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const unsigned short *__restrict__ U,
                                                            const unsigned short *__restrict__ Ul, int rp, int rk,
                                                            const unsigned short *__restrict__ CT_hi,
@@ -367,7 +378,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
     // two m-tiles per wave (three waves per SIMD): with four, the main loop
     // is shorter but the epilogue's loads of Qs and r overlap less, and the
     // kernel measured no faster
-    constexpr int MT = kUcrMt, RB = 64 * kUcrMt;
+    constexpr int RB = 64 * MT;
     const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
     const int64_t rb = (int64_t)(L / ncg);
     const int64_t i0 = rb * RB;
@@ -380,23 +391,31 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
     // lane groups), summed below over the m-tiles of each 128-row group in
     // order: the same sums whatever the block shape
     __shared__ double sh[4 * MT][64 * NT];
+    // Branch-free: rows past N load row N - 1 and store nothing, so the
+    // loads of a tile are issued together rather than one at a time.
 #pragma unroll
     for (int n = 0; n < 4 * NT; ++n) {
         const int col = (int)(nb0 + 16 * n + c16);
         const double av = a[col];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
+            float qv[4], rv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
+                const size_t o = vec_index(N, ldb, i < N ? i : N - 1, col);
+                qv[v] = Qs[o];
+                rv[v] = R[o];
+            }
             double ss = 0.0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
-                if (i >= N) continue;
-                const size_t o = vec_index(N, ldb, i, col);
-                const float q = Qs[o] + cc * acc[mt][n][v];
-                float r = R[o];
-                if (av != 0.0) r = (float)((double)r - av * (double)q);
-                R[o] = r;
-                ss += (double)r * (double)r;
+                const float q = qv[v] + cc * acc[mt][n][v];
+                const float rn = (float)((double)rv[v] - av * (double)q);
+                const float r = av != 0.0 ? rn : rv[v];
+                if (i < N) R[vec_index(N, ldb, i, col)] = r;
+                ss += i < N ? (double)r * (double)r : 0.0;
             }
             ss += __shfl_xor(ss, 16, kWave);
             ss += __shfl_xor(ss, 32, kWave);
@@ -468,12 +487,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
             for (int v = 0; v < 4; ++v) {
                 const int rl = 4 * g + v;
                 const int64_t i = ib + rl;
+                const int64_t ic = i < N ? i : N - 1;  // branch-free loads
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int bl = 16 * q + c16;
-                    float val = acc[mt][4 * ng + q][v];
-                    if (i < N) val += X[vec_index(N, ldc, i, (int)(nb0 + 64 * ng + bl))];
-                    T[w][bl][rl] = val;
+                    T[w][bl][rl] = acc[mt][4 * ng + q][v] + X[vec_index(N, ldc, ic, (int)(nb0 + 64 * ng + bl))];
                 }
             }
             __syncthreads();
@@ -545,28 +563,29 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-    // this lane's V rows (one per n-tile) at k offset 8 (l / 16)
+    // this lane's V rows (one per n-tile) at k offset 8 (l / 16). Loads are
+    // unconditional and in bounds (rows past N read row jb, queries past B
+    // read row b0, a chunk past ldv reloads the last; none of those results
+    // is stored), so the compiler's wait counts stay exact.
     const unsigned short *pv[4];
-    bool vok[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int64_t j = jb + 64 * w + 16 * n + c16;
-        vok[n] = j < N;
-        pv[n] = V + (size_t)(vok[n] ? j : 0) * ldv + 8 * g;
+        pv[n] = V + (size_t)(j < N ? j : jb) * ldv + 8 * g;
     }
     // Q staging: thread t -> array t/128, row (t%128)/2, k 16*(t%2) .. +15
     const int qa = threadIdx.x / 128, qr = (threadIdx.x % 128) / 2, qk = 16 * (threadIdx.x % 2);
-    const unsigned short *qsrc = (qa == 0 ? Qh : Ql) + (size_t)(b0 + qr) * ldv;
-    const bool qok = b0 + qr < B;
+    const unsigned short *qsrc = (qa == 0 ? Qh : Ql) + (size_t)(b0 + qr < B ? b0 + qr : b0) * ldv;
     bf16x8 vf[2][4], qv[2];
     auto fetch_v = [&](int slot, int t0) {
+        const int tc = t0 < ldv ? t0 : ldv - 32;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) vf[slot][n] = (vok[n] && t0 < ldv) ? load8(pv[n] + t0) : zero;
+        for (int n = 0; n < 4; ++n) vf[slot][n] = load8(pv[n] + tc);
     };
     auto fetch_q = [&](int t0) {
+        const int tc = t0 < ldv ? t0 : ldv - 32;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) qv[u] = qok ? load8(qsrc + t0 + qk + 8 * u) : zero;
+        for (int u = 0; u < 2; ++u) qv[u] = load8(qsrc + tc + qk + 8 * u);
     };
     fetch_v(0, 0);
     fetch_q(0);
@@ -580,7 +599,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
 #pragma unroll
                 for (int u = 0; u < 2; ++u) *reinterpret_cast<bf16x8 *>(&Qs[qa][qr][qk + 8 * u]) = qv[u];
                 __syncthreads();
-                if (tt + 32 < ldv) fetch_q(tt + 32);
+                fetch_q(tt + 32);
                 fetch_v(st ^ 1, tt + 32);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
