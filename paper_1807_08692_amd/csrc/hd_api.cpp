@@ -21,7 +21,7 @@ static int64_t ctx_bytes(const hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                            &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                           &c->topk, &c->err, &c->qsplit};
+                           &c->topk, &c->err, &c->qsplit, &c->Dg};
     int64_t s = 0;
     for (const DevBuf *b : all) s += (int64_t)b->bytes;
     return s;
