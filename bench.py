@@ -396,6 +396,12 @@ def main():
                 ctx.load_eigs(fx.U, fx.lam, dtype=f)
             loaded[0] = f
 
+    if not args.no_graph:
+        use_form(form0)
+        result["diffusion_only"] = diffusion_only_leg(args, cfg, ctx, Qd, B, nbatch, K_RANK,
+                                                      chosen["hybrid_plan"][0], tgt["plain_cg"]["iters_max"],
+                                                      hd, torch)
+
     if not args.no_planner and not args.iters:
         use_form(form0)
         result["planner"] = planner_leg(args, cfg, fx, ctx, Qd, B, e0 if e0 is not None else eps_list[0],
@@ -428,6 +434,37 @@ def main():
 
     ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def diffusion_only_leg(args, cfg, ctx, Qd, B, nbatch, K, ih, ip, hd, torch):
+    """The path from a given y (spectral term, CG, combine, ranking: a2-a4),
+    without the similarity search and the top-k_y that form y (a1): the y of
+    each batch is formed once beforehand, then HIP-graph plans with y input
+    run the headline iteration counts."""
+    ys = []
+    for i in range(nbatch):
+        o = ctx.query_batch(Qd[i], alpha=cfg.alpha, max_iter=0, tol=0.0, rank_r=0, k_y=cfg.k_y,
+                            top_k=0, want_y=True)
+        ys.append((o["y_ids"], o["y_val"]))
+    torch.cuda.synchronize()
+    res = {"note": "y given (no similarity search), HIP-graph plans, headline iteration counts"}
+    for name, r_use, it in (("hybrid", -1, ih), ("plain_cg", 0, ip)):
+        pl = hd.Plan(ctx, B, "y", alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use, k_y=cfg.k_y, top_k=K)
+        out = {}
+        for w in range(max(1, args.warmup)):
+            pl.run(y_ids=ys[w % nbatch][0], y_val=ys[w % nbatch][1], out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            pl.run(y_ids=ys[k % nbatch][0], y_val=ys[k % nbatch][1], out=out)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        pl.close()
+        res[name] = {"iters": it, "ms_per_batch": round(1e3 * total / args.steps, 3),
+                     "queries_per_s": round(B * args.steps / total, 2)}
+        log(f"[diffusion only] {name} ({it} it): {1e3 * total / args.steps:.2f} ms per batch")
+    res["hybrid_over_plain"] = round(res["hybrid"]["queries_per_s"] / res["plain_cg"]["queries_per_s"], 3)
+    return res
 
 
 _TRUTH = {}
