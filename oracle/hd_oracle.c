@@ -255,28 +255,33 @@ int hdo_cg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *v
 }
 
 /* Section 3: items are ranked by decreasing x; equal values go to the lower
- * id. The comparison needs the score array, which qsort cannot pass, so it
- * is held in a file-scope pointer (the oracle is single-threaded). */
-static const double *g_rank_x;
+ * id. Each sort element carries its score and id, so the comparison needs no
+ * shared state and calls may run on several threads at once. */
+typedef struct {
+    double x;
+    int64_t id;
+} rank_item;
+
 static int rank_cmp(const void *a, const void *b)
 {
-    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
-    double xi = g_rank_x[i], xj = g_rank_x[j];
-    if (xi > xj) return -1;
-    if (xi < xj) return 1;
-    return (i > j) - (i < j);
+    const rank_item *u = (const rank_item *)a, *v = (const rank_item *)b;
+    if (u->x > v->x) return -1;
+    if (u->x < v->x) return 1;
+    return (u->id > v->id) - (u->id < v->id);
 }
 
 /* Top-K of the ranking: ids_out / score_out get the K best items in order. */
 int hdo_rank(int64_t n, const double *x, int32_t K, int32_t *ids_out, double *score_out)
 {
     if (K < 0 || K > n) return -1;
-    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    if (!idx) return -1;
-    for (int64_t i = 0; i < n; ++i) idx[i] = i;
-    g_rank_x = x;
-    qsort(idx, (size_t)n, sizeof(int64_t), rank_cmp);
-    for (int32_t t = 0; t < K; ++t) { ids_out[t] = (int32_t)idx[t]; score_out[t] = x[idx[t]]; }
-    free(idx);
+    rank_item *it = (rank_item *)malloc(sizeof(rank_item) * (size_t)(n > 0 ? n : 1));
+    if (!it) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        it[i].x = x[i];
+        it[i].id = i;
+    }
+    qsort(it, (size_t)n, sizeof(rank_item), rank_cmp);
+    for (int32_t t = 0; t < K; ++t) { ids_out[t] = (int32_t)it[t].id; score_out[t] = it[t].x; }
+    free(it);
     return 0;
 }

@@ -467,3 +467,17 @@ def test_general_filter_heat_kernel(r):
     ref = expm(t * (S - np.eye(g.n))) @ y
     x = O.filter_poly(g, Uf[:, :r] if r else None, w[:r], coeffs, ids, vals)
     assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_rank_concurrent_threads():
+    """The ranking is re-entrant: calls on several threads at once (as the
+    bench's CPU baseline makes them) give the sequential results."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(99)
+    xs = [np.round(rng.standard_normal(200003), 2) for _ in range(8)]  # many ties
+    want = [O.rank(x, 500) for x in xs]
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        got = list(ex.map(lambda x: O.rank(x, 500), xs * 3))
+    for t, (ids, sc) in enumerate(got):
+        wi, ws = want[t % 8]
+        assert np.array_equal(ids, wi) and np.array_equal(sc, ws)
