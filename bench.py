@@ -64,8 +64,8 @@ def parse():
     p.add_argument("--descriptors", choices=["f32", "bf16"], default=None,
                    help="descriptor storage (default: bf16 for n1m and n2m, f32 otherwise)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0,
-                   help="approximate CPU time budget of the oracle baseline sample")
+    p.add_argument("--cpu-threads", type=int, default=16,
+                   help="host threads of the oracle baseline (one query each)")
     p.add_argument("--eig-seconds", type=float, default=90.0)
     p.add_argument("--fixture-cache", default=None,
                    help="directory to keep the generated workload between runs")
@@ -700,46 +700,77 @@ def serving(args, cfg, fx, ctx, B, K, ih, ip, hd, np):
 
 
 def cpu_baseline(args, cfg, fx, ctx, Qd, B, iters, tol, torch, np):
-    """The FP64 oracle on a bounded sample of the same workload (whole query
-    path per query, single thread, at the GPU hybrid's iteration count), plus
-    the agreement of the GPU results with it on that sample: relative L2
-    error of x, identical y sets, top-100 overlap."""
+    """The FP64 oracle on a bounded sample of the same workload: the whole
+    query path per query (single-threaded C), one query per thread on up to 16
+    host threads at once (the C calls release the interpreter lock; inputs are
+    shared, converted to FP64 once), at the GPU hybrid's iteration count; plus
+    the agreement of the GPU results with it on that sample: relative L2 error
+    of x, identical y sets, top-100 overlap."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
-    U64 = fx.U.astype(np.float64)
+    U64 = np.ascontiguousarray(fx.U, np.float64)
+    V64 = np.ascontiguousarray(fx.V, np.float64)
     oh = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=iters, tol=tol, rank_r=-1,
                          k_y=cfg.k_y, top_k=100, want_x=True, want_y=True)
     torch.cuda.synchronize()
     yi = oh["y_ids"].cpu().numpy()
     ri = oh["rank_ids"].cpu().numpy()
-    Qh = Qd[0].cpu().numpy()
-    t_cpu = 0.0
-    done = 0
-    errs, yset_eq, overlaps = [], [], []
-    t_begin = time.time()
-    while done < B and (t_cpu < args.cpu_seconds or done == 0):
-        b = done
-        ts = time.process_time()
-        res = O.query(g, U64, fx.lam, cfg.alpha, fx.V, Qh[b], cfg.k_y, int(oh["iters"][b]), 0.0, 100)
-        t_cpu += time.process_time() - ts
-        same = set(res["y_ids"].tolist()) == set(yi[b].tolist())
-        yset_eq.append(same)
-        xb = oh["x"][b].double().cpu().numpy()
-        errs.append(float(np.linalg.norm(xb - res["x"]) / np.linalg.norm(res["x"])))
-        overlaps.append(len(set(ri[b].tolist()) & set(res["rank_ids"].tolist())) / 100.0)
-        done += 1
-        log(f"[cpu] oracle query {b}: {time.time() - t_begin:.1f}s")
+    Qh = np.ascontiguousarray(Qd[0].cpu().numpy(), np.float64)
+    nth = max(1, min(args.cpu_threads, B, os.cpu_count() or 1))
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+
+    def one(b):
+        ts = time.perf_counter()
+        res = O.query(g, U64, fx.lam, cfg.alpha, V64, Qh[b], cfg.k_y, int(oh["iters"][b]), 0.0, 100)
+        return b, res, time.perf_counter() - ts
+
+    t_begin = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=nth) as ex:
+        outs = list(ex.map(one, range(nth)))
+    wall = time.perf_counter() - t_begin
+    # agreement: x and the top-100 where the neighbour sets agree; where they
+    # differ (near-ties decided on the bf16-rounded descriptors), how far the
+    # GPU's weakest neighbour falls below the k_y-th best FP64 cosine
+    errs, overlaps, per = [], [], []
+    n_same, shortfall = 0, 0.0
+    for b, res, dt in outs:
+        per.append(dt)
+        if set(res["y_ids"].tolist()) == set(yi[b].tolist()):
+            n_same += 1
+            xb = oh["x"][b].double().cpu().numpy()
+            errs.append(float(np.linalg.norm(xb - res["x"]) / np.linalg.norm(res["x"])))
+            overlaps.append(len(set(ri[b].tolist()) & set(res["rank_ids"].tolist())) / 100.0)
+        else:
+            sims = O.similarities(V64, Qh[b])
+            kth = np.partition(sims, sims.size - cfg.k_y)[sims.size - cfg.k_y]
+            shortfall = max(shortfall, float(kth - sims[yi[b]].min()))
+    log(f"[cpu] {nth} oracle queries on {nth} threads in {wall:.1f}s wall "
+        f"({sum(per) / len(per):.1f}s per query); y sets identical {n_same}/{nth}")
     return {
-        "value": round(done / t_cpu, 4),
+        "value": round(nth / wall, 4),
         "unit": "queries/s",
-        "cores": 1,
+        "cores": nth,
         "kind": "oracle",
-        "sample": f"{done} queries of the first batch, whole path (y by brute force over all {fx.n} "
-                  f"items, spectral term, CG at the GPU's per-query iteration count, full sort), "
-                  f"single-threaded FP64, {t_cpu:.1f}s CPU",
-        "gpu_vs_oracle_max_rel_err": max(errs),
-        "y_sets_identical": f"{int(sum(yset_eq))}/{done}",
-        "top100_overlap_min": min(overlaps),
+        "sample": f"{nth} queries of the first batch, one per host thread ({cpu_model}), whole path "
+                  f"(y by brute force over all {fx.n} items, spectral term, CG at the GPU's per-query "
+                  f"iteration count, full sort), single-threaded FP64 each, {wall:.1f}s wall",
+        "per_core_queries_per_s": round(1.0 / (sum(per) / len(per)), 4),
+        "y_sets_identical": f"{n_same}/{nth}",
+        "y_max_cosine_shortfall": shortfall,
+        "gpu_vs_oracle_max_rel_err": max(errs) if errs else None,
+        "top100_overlap_min": min(overlaps) if overlaps else None,
+        "agreement_note": "x error and top-100 overlap over the queries whose y sets are identical; "
+                          "y_max_cosine_shortfall: over the others, the largest amount by which a GPU "
+                          "neighbour's FP64 cosine lies below the k_y-th best (near-ties decided on the "
+                          "bf16-rounded descriptors)",
     }
 
 
