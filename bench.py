@@ -82,6 +82,9 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=2000.0,
                    help="offered load (queries/s) of the open-loop serving run; 0 skips it")
     p.add_argument("--serve-requests", type=int, default=3000)
+    p.add_argument("--serve-sweep", default="200,500,1000,2000,5000",
+                   help="offered rates (q/s) of the serving sweep: hybrid server with 512 slots, "
+                        "per-request iteration caps drawn from 5..20 (empty: skip)")
     p.add_argument("--no-planner", action="store_true", help="skip the (r, i) planner leg")
     p.add_argument("--filter-steps", type=int, default=3,
                    help="batches timed in the general-filter leg (0 skips it)")
@@ -417,6 +420,10 @@ def main():
         ip_s = tgt["plain_cg"]["iters_max"]
         result["serving"] = serving(args, cfg, fx, ctx, B, K_RANK, ih_s, ip_s, hd, np)
 
+    if args.serve_sweep.strip():
+        use_form(form0)
+        result["serving_sweep"] = serving_sweep(args, cfg, fx, ctx, K_RANK, hd, np)
+
     if args.copy_calibration:
         nbytes = 1 << 30
         a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -696,6 +703,38 @@ def serving(args, cfg, fx, ctx, B, K, ih, ip, hd, np):
         out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
         log(f"[serve] {name}: {len(reqs)} requests at {args.serve_rate:g}/s: p50 {st['p50_ms']:.1f} ms, "
             f"p99 {st['p99_ms']:.1f} ms, {st['queries_per_s']:.0f} q/s")
+    return out
+
+
+def serving_sweep(args, cfg, fx, ctx, K, hd, np):
+    """Latency against offered load on the continuous-batching server (the
+    serving configuration's arrival rates and per-request iteration caps):
+    seeded Poisson arrivals of single queries (descriptors) at each rate, a
+    hybrid server with up to 512 solver columns, each request capped at an
+    iteration count drawn uniformly from 5..20 (seeded); latency from arrival
+    to result."""
+    from paper_1807_08692_amd import serve
+    rates = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
+    rng = np.random.default_rng(cfg.seed_base + 11)
+    srv = hd.Server(ctx, 512, alpha=cfg.alpha, max_iter=20, tol=0.0, rank_r=-1, k_y=cfg.k_y, top_k=K)
+    warm = [serve.Request(i, 0.0, "db", q_desc=fx.Q[i], max_iter=5) for i in range(8)]
+    serve.run({"db": srv}, warm)
+    out = {"slots": srv.slots, "iteration_caps": "uniform 5..20 per request (seeded)", "rates": []}
+    for i, rate in enumerate(rates):
+        n = int(min(3000, max(500, 2.5 * rate)))
+        arr = serve.poisson_arrivals(rate, n, seed=cfg.seed_base + 13 + i)
+        caps = rng.integers(5, 21, size=n)
+        reqs = [serve.Request(j, float(arr[j]), "db", q_desc=fx.Q[j % fx.Q.shape[0]], max_iter=int(caps[j]))
+                for j in range(n)]
+        reqs, wall = serve.run({"db": srv}, reqs)
+        st = serve.latency_stats(reqs)
+        rec = {"offered_per_s": rate, "requests": n, "queries_per_s": round(n / wall, 2),
+               "mean_cap": round(float(caps.mean()), 2)}
+        rec.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items() if k != "count"})
+        out["rates"].append(rec)
+        log(f"[serve sweep] {rate:g}/s: {n} requests, p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+            f"{rec['queries_per_s']:.0f} q/s")
+    srv.close()
     return out
 
 

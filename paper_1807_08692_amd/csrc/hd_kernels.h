@@ -57,9 +57,10 @@ hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart
 // writes the new per-tile active counts to nact_out
 hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
                             IterGuard g, int32_t *nact_out, hipStream_t s);
+// width (0 = ldb): only columns [0, width) are updated (row stride ldb)
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
-                            IterGuard g, hipStream_t s);
+                            IterGuard g, hipStream_t s, int width = 0);
 // update_xp that also writes the new P as its split transpose (bfloat16
 // forms; PT_hi / PT_lo ldb x ldpt, ldpt a multiple of 64 >= N)
 hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
@@ -95,10 +96,13 @@ hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *C
 
 // ---- sparse product (k_spmm.hip) ----
 // Q = (Zs - alpha * S P) / (1 - alpha); gpart[g][c] = sum over the rows of
-// block g of P[i][c] * Q[i][c] (double).
+// block g of P[i][c] * Q[i][c] (double). The launchers that take a width
+// (0 = ldb; a multiple of 64) compute only columns [0, width) of vectors of
+// row stride ldb.
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
-                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl = 0);
+                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl = 0,
+                       int width = 0);
 
 // ---- eigenvector products on MFMA (k_ugemm.hip) ----
 // Number of row chunks of the split-K product U^T P.
@@ -130,12 +134,13 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 // PT_hi / PT_lo (ldb x ldpt, bf16, item index contiguous, zero past N) =
 // hi / lo split of P^T (P: N x ldb fp32 node-major); ldpt a multiple of 64.
 hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
-                           unsigned short *PTl, IterGuard g, hipStream_t s);
+                           unsigned short *PTl, IterGuard g, hipStream_t s, int width = 0);
 // Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT, rp x ldut,
 // zero past N) and P as its split transpose (PT_hi / PT_lo, pitch ldut)
 hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned short *UT_lo,
                             int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
-                            int ldb, float *Cpart, IterGuard g, hipStream_t s, int nt = 0);
+                            int ldb, float *Cpart, IterGuard g, hipStream_t s, int nt = 0,
+                            int width = 0);
 // Z = P + alpha U Cl, U item-major (N x rp), Cl given as split transpose
 hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp, int rk,
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
@@ -149,7 +154,7 @@ int uc_update_r_blocks(int64_t N);
 hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp,
                                    int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
-                                   IterGuard g, hipStream_t s, int nt = 0);
+                                   IterGuard g, hipStream_t s, int nt = 0, int width = 0);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
 hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const unsigned short *U_lo,
                                int rp, int rk,

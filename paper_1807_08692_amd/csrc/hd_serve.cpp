@@ -311,24 +311,35 @@ int hd_serve_step(hd_server *v, int32_t iters) {
     const hd::IterGuard g{nullptr, 0};
     float *X = v->X.as<float>(), *R = v->R.as<float>(), *P = v->P.as<float>(), *Q = v->Q.as<float>();
     uint16_t *ClT_hi = v->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
-    for (int it = 0; it < iters && v->fused; ++it) {
+    // Free columns are never active and admission fills the lowest free ones,
+    // so the bfloat16 iteration runs its wide kernels over the occupied
+    // prefix only: columns [0, w), w the highest occupied column + 1 rounded
+    // up to 64 (row stride stays ldb). Each column's arithmetic does not
+    // depend on w; the scalar steps run over all columns (the free ones are
+    // inactive and keep their state).
+    int hi = -1;
+    for (int t = 0; t < ldb; ++t)
+        if (v->ticket[(size_t)t] >= 0) hi = t;
+    const int w = hi < 0 ? 0 : (hi + 64) / 64 * 64;
+    for (int it = 0; it < iters && v->fused && w > 0; ++it) {
         // L1 U1^T P for every column (a newly admitted column has P = y);
         // the correction goes into the residual update
         uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
-        HIP_TRY(hd::launch_split_pt(N, ldb, P, c->ldut, PTh, PTl, g, s));
+        HIP_TRY(hd::launch_split_pt(N, ldb, P, c->ldut, PTh, PTl, g, s, w));
         HIP_TRY(hd::launch_ut_p_bf16(N, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
-                                     v->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
+                                     v->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, w), w));
         HIP_TRY(hd::launch_reduce_c(v->nchunk, v->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), v->r_use,
                                     v->Cl.as<float>(), g, s, v->Dg.as<double>(), v->o.alpha));
         HIP_TRY(hd::launch_split_t(v->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
         HIP_TRY(hd::launch_spmm(N, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, P, Q,
-                                ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb)));
+                                ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, w),
+                                w));
         HIP_TRY(hd::launch_cg_step_a(ldb, v->part.as<double>(), v->rp.nblk, v->st, g, s, v->Dg.as<double>(), rk));
         HIP_TRY(hd::launch_uc_update_r_bf16(N, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q,
                                             v->o.alpha, R, v->st.a, v->part.as<double>(), g, s,
-                                            c->tv(HD_TUNE_UC_NT, ldb)));
+                                            c->tv(HD_TUNE_UC_NT, w), w));
         HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->nrb, v->o.tol, v->st, g, v->st.nact_part, s));
-        HIP_TRY(hd::launch_update_xp(N, ldb, X, P, R, v->st.a, v->st.beta, v->st.active, g, s));
+        HIP_TRY(hd::launch_update_xp(N, ldb, X, P, R, v->st.a, v->st.beta, v->st.active, g, s, w));
     }
     for (int it = 0; it < iters && !v->fused; ++it) {
         const float *Zs = P;

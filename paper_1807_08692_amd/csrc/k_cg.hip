@@ -322,12 +322,12 @@ hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, C
 
 // X += a P (the step of this iteration); P = R + beta P for columns still
 // active after the stopping test.
-__global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, float *X, float *P,
+__global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, int width, float *X, float *P,
                                                       const float *R, const double *a,
                                                       const double *beta, const int32_t *active,
                                                       IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
-    const int G = ldb / 4;
+    const int G = width / 4;  // columns [0, width) of rows of stride ldb
     const int rows = kBlock / G;
     int cg = threadIdx.x % G;
     int r0 = threadIdx.x / G;
@@ -356,12 +356,14 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, float 
 
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
-                            IterGuard g, hipStream_t s) {
-    int rows = kBlock / (ldb / 4);
+                            IterGuard g, hipStream_t s, int width) {
+    if (width == 0) width = ldb;
+    if (width % 64 != 0 || width > ldb || width > 4 * kBlock) return hipErrorInvalidValue;
+    int rows = kBlock / (width / 4);
     int64_t want = (N + rows - 1) / rows;
     int grid = (int)(want < 16384 ? want : 16384);
     if (grid < 1) grid = 1;
-    k_update_xp<<<grid, kBlock, 0, s>>>(N, ldb, X, P, R, a, beta, active, g);
+    k_update_xp<<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g);
     return hipGetLastError();
 }
 

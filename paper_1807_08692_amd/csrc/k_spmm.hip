@@ -151,15 +151,18 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__res
 bool tile_param_ok(int v, int ldb) { return (v == 1 || v == 2 || v == 4) && ldb % (64 * v) == 0; }
 
 // cpl: query columns per lane (a wave covers 64 cpl columns of a row); the
-// default is 2 when it divides ldb (measured fastest at 256 columns on a
-// million-row graph), else 1.
+// default is 2 when it divides the width (measured fastest at 256 columns on a
+// million-row graph), else 1. width (0 = ldb): only columns [0, width) are
+// computed (row stride stays ldb); a multiple of 64.
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
-                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl) {
+                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl, int width) {
     const float a = (float)alpha, oma = (float)(1.0 - alpha);
-    if (cpl == 0) cpl = ldb % 128 == 0 ? 2 : 1;
-    if (!tile_param_ok(cpl, ldb)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)rp.nblk, (unsigned)(ldb / (64 * cpl)));
+    if (width == 0) width = ldb;
+    if (width < 64 || width > ldb || width % 64 != 0) return hipErrorInvalidValue;
+    if (cpl == 0) cpl = width % 128 == 0 ? 2 : 1;
+    if (!tile_param_ok(cpl, width)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)rp.nblk, (unsigned)(width / (64 * cpl)));
     if (cpl == 1) {
         k_spmm<1><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g);
     } else if (cpl == 2) {

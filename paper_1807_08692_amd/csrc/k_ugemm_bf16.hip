@@ -232,9 +232,11 @@ __global__ __launch_bounds__(kBlock) void k_split_pt(int64_t N, int ldb, const f
 }
 
 hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
-                           unsigned short *PTl, IterGuard g, hipStream_t s) {
-    if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0) return hipErrorInvalidValue;
-    k_split_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(ldb / 64)), kBlock, 0, s>>>(N, ldb, P, ldpt, PTh,
+                           unsigned short *PTl, IterGuard g, hipStream_t s, int width) {
+    if (width == 0) width = ldb;
+    if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0 || width % 64 != 0 || width > ldb)
+        return hipErrorInvalidValue;
+    k_split_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(width / 64)), kBlock, 0, s>>>(N, ldb, P, ldpt, PTh,
                                                                                     PTl, g);
     return hipGetLastError();
 }
@@ -250,11 +252,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
                                                     int64_t ldut, int rk,
                                                     const unsigned short *__restrict__ PTh,
                                                     const unsigned short *__restrict__ PTl, int ldb,
-                                                    int64_t rc, int64_t kend_all,
+                                                    int wcols, int64_t rc, int64_t kend_all,
                                                     float *__restrict__ Cpart, IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     constexpr int MT = tn_mt(NT), RB = tn_rows(NT);
-    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT), nkg = (unsigned)(rk + RB - 1) / RB;
+    const unsigned L = xcd_tile(), ncg = (unsigned)wcols / (64 * NT), nkg = (unsigned)(rk + RB - 1) / RB;
     const unsigned chunk = L / (ncg * nkg);
     const int64_t m0 = (int64_t)((L / ncg) % nkg) * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -278,18 +280,20 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
 
 hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned short *UT_lo,
                             int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
-                            int ldb, float *Cpart, IterGuard g, hipStream_t s, int ntr) {
+                            int ldb, float *Cpart, IterGuard g, hipStream_t s, int ntr, int width) {
     int64_t rc;
     const int nchunk = ut_p_chunks(N, &rc);
     // rows run to N rounded up to 32 (UT and PT are zero past N)
     const int64_t kend = (N + 31) / 32 * 32;
-    if (kend > ldut || rc % 32 != 0) return hipErrorInvalidValue;
-    const int nt = tn_nt(ldb, ntr, 4);
+    if (width == 0) width = ldb;
+    if (kend > ldut || rc % 32 != 0 || width % 64 != 0 || width > ldb) return hipErrorInvalidValue;
+    const int nt = tn_nt(width, ntr, 4);
     if (nt == 0) return hipErrorInvalidValue;
-    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((rk + tn_rows_rt(nt) - 1) / tn_rows_rt(nt)) *
+    const unsigned nblk = (unsigned)(width / (64 * nt)) * (unsigned)((rk + tn_rows_rt(nt) - 1) / tn_rows_rt(nt)) *
                           (unsigned)nchunk;
-#define HD_UTP(LOV, NTV) \
-    k_ut_p_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(UT, UT_lo ? UT_lo : UT, ldut, rk, PTh, PTl, ldb, rc, kend, Cpart, g)
+#define HD_UTP(LOV, NTV)                                                                                       \
+    k_ut_p_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(UT, UT_lo ? UT_lo : UT, ldut, rk, PTh, PTl, ldb, width, rc, kend, \
+                                                Cpart, g)
     if (UT_lo) {
         if (nt == 4) HD_UTP(true, 4); else if (nt == 2) HD_UTP(true, 2); else HD_UTP(true, 1);
     } else {
@@ -373,13 +377,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
                                                            const unsigned short *__restrict__ CT_lo, int ldb,
                                                            const float *__restrict__ Qs, float cc,
                                                            float *__restrict__ R, const double *__restrict__ a,
-                                                           double *__restrict__ part, IterGuard ig) {
+                                                           double *__restrict__ part, int wcols, IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     // two m-tiles per wave (three waves per SIMD): with four, the main loop
     // is shorter but the epilogue's loads of Qs and r overlap less, and the
     // kernel measured no faster
     constexpr int RB = 64 * MT;
-    const unsigned L = xcd_tile(), ncg = (unsigned)ldb / (64 * NT);
+    const unsigned L = xcd_tile(), ncg = (unsigned)wcols / (64 * NT);
     const int64_t rb = (int64_t)(L / ncg);
     const int64_t i0 = rb * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -439,14 +443,16 @@ int uc_update_r_blocks(int64_t N) { return (int)((N + 127) / 128); }
 hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp,
                                    int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
-                                   IterGuard g, hipStream_t s, int ntr) {
-    const int nt = tn_nt(ldb, ntr, 2);
+                                   IterGuard g, hipStream_t s, int ntr, int width) {
+    if (width == 0) width = ldb;
+    if (width % 64 != 0 || width > ldb) return hipErrorInvalidValue;
+    const int nt = tn_nt(width, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
-    const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + 64 * kUcrMt - 1) / (64 * kUcrMt));
+    const unsigned nblk = (unsigned)(width / (64 * nt)) * (unsigned)((N + 64 * kUcrMt - 1) / (64 * kUcrMt));
     const float cc = (float)(alpha / (1.0 - alpha));
 #define HD_UR(LOV, NTV)                                                                                   \
     k_uc_update_r_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, Qs, \
-                                                       cc, R, a, part, g)
+                                                       cc, R, a, part, width, g)
     if (U_lo) {
         if (nt == 4) HD_UR(true, 4); else if (nt == 2) HD_UR(true, 2); else HD_UR(true, 1);
     } else {

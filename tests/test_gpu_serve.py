@@ -182,3 +182,81 @@ def test_request_loop_poisson(fx, ctx):
     assert all(r.result["status"] == O.CONVERGED for r in reqs)
     for s in servers.values():
         s.close()
+
+
+def _small_db(n, r, d, seed):
+    """A resident database for the multi-database test: a random symmetric
+    graph (about 10 entries per row), unit descriptors with normal entries and
+    an orthonormal U1 with disjoint column supports, eigenvalues in [0, 0.95)."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n, dtype=np.int64), 5)
+    cols = rng.integers(0, n, size=rows.size)
+    keep = rows != cols
+    a, b = np.minimum(rows[keep], cols[keep]), np.maximum(rows[keep], cols[keep])
+    key = np.unique(a * n + b)
+    a, b = key // n, key % n
+    w = rng.uniform(0.1, 1.0, size=a.size)
+    rr, cc, ww = np.concatenate([a, b]), np.concatenate([b, a]), np.concatenate([w, w])
+    o = np.lexsort((cc, rr))
+    rr, cc, ww = rr[o], cc[o], ww[o]
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, rr + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    comp = rng.permutation(n) % r
+    vals = rng.standard_normal(n)
+    norms = np.zeros(r)
+    np.add.at(norms, comp, vals ** 2)
+    vals /= np.sqrt(norms[comp])
+    U = np.zeros((n, r), np.float32)
+    U[np.arange(n), comp] = vals
+    lam = np.sort(rng.uniform(0.0, 0.95, size=r))[::-1].copy()
+    V = rng.standard_normal((n, d)).astype(np.float32)
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    return rowptr, cc.astype(np.int32), ww.astype(np.float32), U, lam, V
+
+
+def test_three_databases_poisson(torch_dev):
+    """The serving configuration at test scale: three resident databases of
+    different sizes and ranks on one device, seeded Poisson arrivals routed
+    uniformly to them, per-request iteration caps drawn from 5..20. Every
+    request finishes with its own cap and the ranking the batch path gives for
+    the same query and cap."""
+    import torch
+    from paper_1807_08692_amd import hd, serve
+    d, ky, K = 64, 10, 10
+    dbs = {"small": (2000, 16), "medium": (4000, 32), "large": (8000, 64)}
+    ctxs, servers, qs = {}, {}, {}
+    try:
+        for t, (name, (n, r)) in enumerate(dbs.items()):
+            rowptr, col, w, U, lam, V = _small_db(n, r, d, 100 + t)
+            c = hd.Context(0)
+            ctxs[name] = c
+            c.load_graph(n, rowptr, col, w, normalize=True)
+            c.load_eigs(U, lam, dtype="bf16x2")
+            c.load_descriptors(V)
+            servers[name] = hd.Server(c, 32, max_iter=20, tol=0.0, k_y=ky, top_k=K)
+            qs[name] = np.random.default_rng(200 + t).standard_normal((40, d)).astype(np.float32)
+        rng = np.random.default_rng(5)
+        names = list(dbs)
+        m = 90
+        arr = serve.poisson_arrivals(2000.0, m, seed=9)
+        route = rng.integers(0, 3, size=m)
+        caps = rng.integers(5, 21, size=m)
+        reqs = [serve.Request(i, float(arr[i]), names[route[i]], q_desc=qs[names[route[i]]][i % 40],
+                              max_iter=int(caps[i])) for i in range(m)]
+        reqs, wall = serve.run(servers, reqs)
+        st = serve.latency_stats(reqs)
+        assert st["count"] == m and all(r.finished >= r.arrival for r in reqs)
+        for rq in reqs:
+            res = rq.result
+            assert res["iters"] == rq.max_iter and res["status"] == O.MAXITER
+            q = torch.from_numpy(qs[rq.db][rq.rid % 40][None, :]).to(torch_dev)
+            out = ctxs[rq.db].query_batch(q, alpha=0.99, max_iter=rq.max_iter, tol=0.0, k_y=ky, top_k=K)
+            torch.cuda.synchronize()
+            assert np.array_equal(res["ids"], out["rank_ids"][0].cpu().numpy()), (rq.db, rq.rid)
+            assert np.allclose(res["scores"], out["rank_scores"][0].cpu().numpy(), rtol=1e-5, atol=1e-12)
+    finally:
+        for s in servers.values():
+            s.close()
+        for c in ctxs.values():
+            c.close()
