@@ -233,24 +233,27 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
         HIP_TRY(c->U.ensure(host.size() * sizeof(float)));
         HIP_TRY(hipMemcpy(c->U.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
     } else {
-        // hi terms first; the two-term form appends the lo terms (same layout)
-        const int64_t ldut = (n + 63) / 64 * 64;
+        // hi terms first; the two-term form appends the lo terms (same
+        // layout). Both copies are in fragment order: item-major over
+        // n16 x rp (rows padded to 16), component-major over rp x ldut.
+        const int64_t ldut = (n + 63) / 64 * 64, n16 = (n + 15) / 16 * 16;
         const int terms = dtype == HD_BF16X2 ? 2 : 1;
-        const size_t imn = (size_t)n * rp, cmn = (size_t)rp * ldut;
+        const size_t imn = (size_t)n16 * rp, cmn = (size_t)rp * ldut;
         std::vector<uint16_t> im(imn * terms, 0), cm(cmn * terms, 0);
         for (int64_t i = 0; i < n; ++i)
             for (int k = 0; k < r; ++k) {
                 const float u = U[(size_t)i * r + k];
                 const uint16_t h = bf16_rne_host(u);
-                im[(size_t)i * rp + k] = h;
-                cm[(size_t)k * ldut + i] = h;
+                const size_t oi = hd::frag_offset(i, k, rp / 32), oc = hd::frag_offset(k, i, ldut / 32);
+                im[oi] = h;
+                cm[oc] = h;
                 if (terms == 2) {
                     float hf;
                     const uint32_t hb = (uint32_t)h << 16;
                     std::memcpy(&hf, &hb, sizeof(hf));
                     const uint16_t l = bf16_rne_host(u - hf);
-                    im[imn + (size_t)i * rp + k] = l;
-                    cm[cmn + (size_t)k * ldut + i] = l;
+                    im[imn + oi] = l;
+                    cm[cmn + oc] = l;
                 }
             }
         HIP_TRY(c->Ub.ensure(im.size() * sizeof(uint16_t)));
@@ -359,9 +362,13 @@ int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
         HIP_TRY(c->V.ensure(host.size() * sizeof(float)));
         HIP_TRY(hipMemcpy(c->V.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
     } else {
-        std::vector<uint16_t> host((size_t)n * ldv, 0);
+        // fragment order over n16 x ldv (rows padded to 16), the operand
+        // order of the similarity kernel's matrix-core loads
+        const int64_t n16 = (n + 15) / 16 * 16;
+        std::vector<uint16_t> host((size_t)n16 * ldv, 0);
         for (int64_t i = 0; i < n; ++i)
-            for (int t = 0; t < d; ++t) host[(size_t)i * ldv + t] = bf16_rne_host(V[(size_t)i * d + t]);
+            for (int t = 0; t < d; ++t)
+                host[hd::frag_offset(i, t, ldv / 32)] = bf16_rne_host(V[(size_t)i * d + t]);
         HIP_TRY(c->Vb.ensure(host.size() * sizeof(uint16_t)));
         HIP_TRY(hipMemcpy(c->Vb.p, host.data(), host.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     }
@@ -516,7 +523,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     const float *Usv = c->Usv.as<float>(), *Ustv = c->Ustv.as<float>();
     const float *U = c->U.as<float>();
     const uint16_t *Ub = c->Ub.as<uint16_t>(), *UbT = c->UbT.as<uint16_t>();
-    const uint16_t *Ubl = two ? Ub + (size_t)n * c->rp : nullptr;
+    const uint16_t *Ubl = two ? c->ub_lo() : nullptr;
     const uint16_t *UbTl = two ? UbT + (size_t)c->rp * c->ldut : nullptr;
     uint16_t *ClT_hi = c->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
     uint16_t *CsT_hi = c->CsT.as<uint16_t>(), *CsT_lo = CsT_hi ? CsT_hi + (size_t)rk * ldb : nullptr;

@@ -155,8 +155,9 @@ struct hd_ctx {
     // graph
     int64_t n = 0, nnz = 0;
     DevBuf rowptr, col, val;
-    // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp) + UbT (bf16, rp x ldut);
-    // the two-term form stores the lo terms after the hi terms of each
+    // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp, rows padded to 16) +
+    // UbT (bf16, rp x ldut), both in fragment order (hd::frag_offset); the
+    // two-term form stores the lo terms after the hi terms of each
     int r = 0, rp = 0, u_dtype = HD_F32;
     int64_t ldut = 0;
     DevBuf U, Ub, UbT, lam;
@@ -166,7 +167,8 @@ struct hd_ctx {
     std::vector<double> lam_host;  // the loaded eigenvalues, padded with zeros to rp
     DevBuf gfil;                   // g(lambda) of a general filter
     int eig_outer = 0;             // Rayleigh-Ritz steps of the last hd_compute_eigs
-    // descriptors: V (fp32) or Vb (bf16), N x ldv
+    // descriptors: V (fp32, N x ldv) or Vb (bf16, N x ldv in fragment order,
+    // rows padded to 16)
     int d = 0, ldv = 0, v_dtype = HD_F32;
     DevBuf V, Vb;
     // solver workspace
@@ -182,7 +184,7 @@ struct hd_ctx {
     bool u_sparse() const { return u_dtype == HD_SPARSE_F32; }
     // second bfloat16 terms of the two-term U1 form (null otherwise)
     const uint16_t *ub_lo() const {
-        return u_dtype == HD_BF16X2 ? Ub.as<uint16_t>() + (size_t)n * rp : nullptr;
+        return u_dtype == HD_BF16X2 ? Ub.as<uint16_t>() + (size_t)((n + 15) / 16 * 16) * rp : nullptr;
     }
     const uint16_t *ubt_lo() const {
         return u_dtype == HD_BF16X2 ? UbT.as<uint16_t>() + (size_t)rp * ldut : nullptr;

@@ -7,6 +7,9 @@
 //     columns B..ldb-1 are padding that stays zero;
 //   - eigenvectors U: node-major N x rp (rp = r rounded up to 32, zero
 //     padded); coefficient matrices (C, Cl, Cs): rk x ldb;
+//   - bfloat16 operands that MFMA kernels stream from memory (the stored U1,
+//     item-major and component-major, and the bfloat16 descriptors) are kept
+//     in fragment order, see frag_offset;
 //   - scores for ranking and similarities: query-major B x ld rows.
 #pragma once
 
@@ -14,6 +17,19 @@
 #include <stdint.h>
 
 namespace hd {
+
+// Fragment order of an M x K bfloat16 matrix (K a multiple of 32, M padded
+// to a multiple of 16 with zero rows): the matrix is cut into 16 x 32 tiles,
+// tile (m / 16, k / 32) is stored at tile index (m / 16) kt + k / 32 (kt =
+// K / 32 tiles per tile row), and inside a tile as the 64 lanes' operands of
+// v_mfma_f32_16x16x32_bf16: lane l = m % 16 + 16 ((k % 32) / 8) holds the
+// eight consecutive k of its row at 8 l .. 8 l + 7. A wave then reads a whole
+// operand tile as one contiguous kilobyte.
+__host__ __device__ inline size_t frag_offset(int64_t m, int64_t k, int64_t kt) {
+    const size_t tile = (size_t)(m / 16) * (size_t)kt + (size_t)(k / 32);
+    const size_t lane = (size_t)(m % 16) + 16 * (size_t)((k % 32) / 8);
+    return (tile * 64 + lane) * 8 + (size_t)(k % 8);
+}
 
 // Per-column CG state on the device (all arrays hold ldb entries).
 struct CgState {
@@ -68,10 +84,10 @@ hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const flo
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
                                hipStream_t s);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
-// U is fp32 (u_bf16 = 0) or bf16 bit patterns (u_bf16 = 1), item-major N x rp.
 // colmap (nullptr = identity, B columns of ldb): y row t -> column colmap[t]
-// U: fp32 (u_bf16 = 0) or bfloat16 (u_bf16 = 1, value U + U_lo when U_lo is
-// not null: the two-term storage form)
+// U: fp32 item-major N x rp (u_bf16 = 0) or bfloat16 bit patterns in fragment
+// order over N x rp (u_bf16 = 1, value U + U_lo when U_lo is not null: the
+// two-term storage form)
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                               const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
@@ -126,7 +142,8 @@ hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, cons
 // ---- bfloat16 storage form of the eigenvector and descriptor products
 //      (k_ugemm_bf16.hip); bf16 values are passed as their 16-bit patterns.
 //      U_lo / UT_lo, when not null, hold the second bfloat16 term of the
-//      two-term form (U = U_hi + U_lo) in the same layout ----
+//      two-term form (U = U_hi + U_lo) in the same layout. The stored U1
+//      and the descriptors are in fragment order (frag_offset) ----
 // CT_hi / CT_lo (ldb x rk, bf16) = hi / lo split of C^T (C: rk x ldb fp32).
 // A null g.nact disables the iteration guard.
 hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi,
@@ -135,13 +152,15 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 // hi / lo split of P^T (P: N x ldb fp32 node-major); ldpt a multiple of 64.
 hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
                            unsigned short *PTl, IterGuard g, hipStream_t s, int width = 0);
-// Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT, rp x ldut,
-// zero past N) and P as its split transpose (PT_hi / PT_lo, pitch ldut)
+// Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT: the
+// rp x ldut matrix in fragment order, zero past N) and P as its split
+// transpose (PT_hi / PT_lo, pitch ldut)
 hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned short *UT_lo,
                             int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
                             int ldb, float *Cpart, IterGuard g, hipStream_t s, int nt = 0,
                             int width = 0);
-// Z = P + alpha U Cl, U item-major (N x rp), Cl given as split transpose
+// Z = P + alpha U Cl, U item-major (N x rp in fragment order, rows padded to
+// a multiple of 16), Cl given as split transpose
 hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp, int rk,
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                            const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
@@ -163,7 +182,7 @@ hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const 
 // Tile parameters: a requested value (0 = default) is valid for width ldb
 // when it is one of 1, 2, 4 and divides the width in 64-column units.
 bool tile_param_ok(int v, int ldb);
-// sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv); qsplit: scratch for
+// sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv, fragment order); qsplit: scratch for
 // 2 x B x ldv bf16 (the hi / lo parts of q)
 hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsigned short *V,
                            int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s);

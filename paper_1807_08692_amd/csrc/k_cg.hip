@@ -528,8 +528,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
     if (k < r_use && b < B) {
         for (int t = 0; t < ky; ++t) {
             int id = ids[b * ky + t];
-            if (id >= 0 && (int64_t)id < N)
-                acc += u_elem<UT>(U, U_lo, (size_t)id * rp + k) * (double)vals[b * ky + t];
+            if (id >= 0 && (int64_t)id < N) {
+                // fp32 U is row-major; the bfloat16 forms are in fragment order
+                const size_t o = sizeof(UT) == 4 ? (size_t)id * rp + k : frag_offset(id, k, rp / 32);
+                acc += u_elem<UT>(U, U_lo, o) * (double)vals[b * ky + t];
+            }
         }
     }
     double lk = k < r_use ? lam[k] : 0.0;

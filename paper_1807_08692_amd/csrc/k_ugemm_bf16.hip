@@ -2,8 +2,9 @@
 // low-rank parts of Section 4.2, eqs. (h-spectral) and (box)).
 //
 // U1 is stored in bfloat16 twice: item-major (N x rp, for U C) and
-// component-major (rp x N, for U^T P), so that every MFMA operand a lane
-// needs - eight consecutive K elements - is one 16-byte load. The other
+// component-major (rp x N, for U^T P), each in fragment order (16 x 32
+// tiles laid out as the 64 lanes' MFMA operands, frag_offset), so that a
+// wave reads every A operand tile as one contiguous kilobyte. The other
 // operand (P, or the small coefficient matrix C) stays fp32 in memory and is
 // split into hi + lo bfloat16 parts (hi = RNE(v), lo = RNE(v - hi)); each
 // product is done twice (hi and lo) into fp32 accumulators, so the only
@@ -75,7 +76,8 @@ static inline int tn_rows_rt(int nt) { return nt == 4 ? tn_rows(4) : tn_rows(1);
 // ---------------------------------------------------------------------------
 // Block GEMM shared by the three eigenvector products:
 //   acc[m][n] = sum_k A[m][k] B[n][k]
-// with both operands K-contiguous bfloat16: A (M x K, row stride lda, one or
+// with both operands K-contiguous bfloat16: A (M x K in fragment order, kt
+// tiles of 32 K per 16-row tile row, rows padded to a multiple of 16; one or
 // two terms A + Al) and B (N x K, row stride ldbk, split hi + lo). A block
 // covers 64 MT rows of M and 64*NT columns of N (from nb0); wave w owns rows
 // m0 + 16 MT w .. +16 MT - 1 (MT m-tiles) for all 64 NT columns (4 NT
@@ -84,7 +86,9 @@ static inline int tn_rows_rt(int nt) { return nt == 4 ? tn_rows(4) : tn_rows(1);
 // fragment read from LDS feeds 3 MT MFMAs. A is the large streamed operand (U1): each
 // wave loads its own A fragments straight from global memory into registers,
 // one 32-wide K step ahead, with no LDS staging and no barrier between the
-// load and its use. B (the coefficients, or the split P^T) is shared by the
+// load and its use; in fragment order each of those loads is one contiguous
+// kilobyte per wave (with rows of a plain row-major A it touched sixteen
+// rows and measured 1.2-2x slower). B (the coefficients, or the split P^T) is shared by the
 // four waves: per K step the block loads the 64 NT x 32 B tile (hi and lo; NT
 // 16-byte pieces per thread) once, stages it in LDS and every wave reads its
 // B fragments there; the next step's B pieces are fetched into registers while
@@ -98,7 +102,7 @@ static inline int tn_rows_rt(int nt) { return nt == 4 ? tn_rows(4) : tn_rows(1);
 // of 16 consecutive rows fall in distinct banks.
 template <bool LO, int NT, int MT = tn_mt(NT)>
 __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
-                                         const unsigned short *__restrict__ Al, int64_t lda,
+                                         const unsigned short *__restrict__ Al, int64_t kt,
                                          int64_t m0, int64_t mend,
                                          const unsigned short *__restrict__ Bh,
                                          const unsigned short *__restrict__ Bl, int64_t ldbk,
@@ -107,20 +111,23 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
     __shared__ __attribute__((aligned(16))) unsigned short Bsl[64 * NT][40];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
-    // this lane's A rows (one per m-tile) and k offset. Every load is
-    // unconditional and in bounds: a row past mend reads row m0 instead
-    // (its accumulator rows are never stored), and a K step past k1 reloads
-    // the last step (never used). Loads without branches keep the compiler's
-    // wait counts exact, so waiting for the staged B pieces does not also
-    // wait for the A prefetch issued after them.
+    // this lane's place in its A tiles (one tile row per m-tile); K step k
+    // is tile k / 32 of the row, 512 elements on. Every load is
+    // unconditional and in bounds: a tile past the last row tile reads tile
+    // m0 / 16 instead (its accumulator rows are never stored; rows past mend
+    // inside the last tile are the zero padding), and a K step past k1
+    // reloads the last step (never used). Loads without branches keep the
+    // compiler's wait counts exact, so waiting for the staged B pieces does
+    // not also wait for the A prefetch issued after them.
     const unsigned short *pa[MT];
     const unsigned short *pal[MT];
+    const int64_t mtiles = (mend + 15) / 16;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        const int64_t row = m0 + 16 * MT * w + 16 * mt + c16;
-        const int64_t rr = row < mend ? row : m0;
-        pa[mt] = A + (size_t)rr * lda + 8 * g;
-        pal[mt] = LO ? Al + (size_t)rr * lda + 8 * g : nullptr;
+        const int64_t tb = m0 / 16 + MT * w + mt;
+        const size_t o = ((size_t)(tb < mtiles ? tb : m0 / 16) * (size_t)kt * 64 + (size_t)lane) * 8;
+        pa[mt] = A + o;
+        pal[mt] = LO ? Al + o : nullptr;
     }
     const int64_t klast = k1 - 32;  // the last K step (K ranges are multiples of 32)
     // B staging: pieces p = NT t + j -> row p / 4, k 8 (p % 4)
@@ -132,8 +139,8 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
         const int64_t kc = k < k1 ? k : klast;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            af[slot][mt] = load8(pa[mt] + kc);
-            if (LO) afl[slot][mt] = load8(pal[mt] + kc);
+            af[slot][mt] = load8(pa[mt] + (size_t)kc * 16);  // tile kc / 32, 512 apart
+            if (LO) afl[slot][mt] = load8(pal[mt] + (size_t)kc * 16);
         }
     };
     auto fetch_b = [&](int64_t k) {
@@ -264,7 +271,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
     const int64_t ks = (int64_t)chunk * rc;
     const int64_t ke = ks + rc < kend_all ? ks + rc : kend_all;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(UT, UTl, ldut, m0, rk, PTh, PTl, ldut, nb0, ks, ke, acc);
+    tn_block<LO, NT>(UT, UTl, ldut / 32, m0, rk, PTh, PTl, ldut, nb0, ks, ke, acc);
     float *out = Cpart + (size_t)chunk * rk * ldb;
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
@@ -321,7 +328,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned 
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // branch-free loads (rows past N read row N - 1 and store nothing)
 #pragma unroll
@@ -345,6 +352,7 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                            const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
                            int ntr) {
+    if (rp % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
@@ -389,7 +397,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT, MT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    tn_block<LO, NT, MT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // r^2 of each 16-row m-tile and column (4 rows per lane, then across the
     // lane groups), summed below over the m-tiles of each 128-row group in
@@ -444,6 +452,7 @@ hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const uns
                                    int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
                                    IterGuard g, hipStream_t s, int ntr, int width) {
+    if (rp % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     if (width == 0) width = ldb;
     if (width % 64 != 0 || width > ldb) return hipErrorInvalidValue;
     const int nt = tn_nt(width, ntr, 2);
@@ -480,7 +489,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(U, Ul, rp, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // per m-tile (16 items) and group of four n-tiles (64 queries)
 #pragma unroll
@@ -515,6 +524,7 @@ hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const 
                                int rp, int rk, const unsigned short *CT_hi,
                                const unsigned short *CT_lo, int ldb, const float *X, float *x,
                                int64_t ldx, hipStream_t s, int ntr) {
+    if (rp % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
@@ -544,7 +554,8 @@ __global__ __launch_bounds__(kBlock) void k_split_q(int B, int d, int ldv, const
     Ql[idx] = bf16_rne(v - bf16_to_f(h));
 }
 
-// sim[b][j] = q[b] . V[j] with V stored bfloat16 (N x ldv) and q split hi/lo.
+// sim[b][j] = q[b] . V[j] with V stored bfloat16 (N x ldv in fragment order,
+// rows padded to a multiple of 16) and q split hi/lo.
 // M = b, N = j, K = t. A block covers 64 queries x 256 items; wave w owns
 // items [64w, 64w+64) (four n-tiles) for all 64 queries (four m-tiles, hi
 // and lo), so each V fragment feeds eight MFMAs. V rows are read by one wave
@@ -569,15 +580,18 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // this lane's V rows (one per n-tile) at k offset 8 (l / 16). Loads are
-    // unconditional and in bounds (rows past N read row jb, queries past B
-    // read row b0, a chunk past ldv reloads the last; none of those results
-    // is stored), so the compiler's wait counts stay exact.
+    // this lane's place in its V tiles (one 16-item tile row per n-tile;
+    // k chunk t is tile t / 32 of the row, 512 elements on). Loads are
+    // unconditional and in bounds (tiles past the last item tile read tile
+    // jb / 16, queries past B read row b0, a chunk past ldv reloads the last;
+    // none of those results is stored), so the compiler's wait counts stay
+    // exact.
     const unsigned short *pv[4];
+    const int64_t jtiles = (N + 15) / 16;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        const int64_t j = jb + 64 * w + 16 * n + c16;
-        pv[n] = V + (size_t)(j < N ? j : jb) * ldv + 8 * g;
+        const int64_t tb = jb / 16 + 4 * w + n;
+        pv[n] = V + ((size_t)(tb < jtiles ? tb : jb / 16) * (size_t)(ldv / 32) * 64 + (size_t)lane) * 8;
     }
     // Q staging: thread t -> array t/128, row (t%128)/2, k 16*(t%2) .. +15
     const int qa = threadIdx.x / 128, qr = (threadIdx.x % 128) / 2, qk = 16 * (threadIdx.x % 2);
@@ -586,7 +600,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
     auto fetch_v = [&](int slot, int t0) {
         const int tc = t0 < ldv ? t0 : ldv - 32;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) vf[slot][n] = load8(pv[n] + tc);
+        for (int n = 0; n < 4; ++n) vf[slot][n] = load8(pv[n] + (size_t)tc * 16);
     };
     auto fetch_q = [&](int t0) {
         const int tc = t0 < ldv ? t0 : ldv - 32;
