@@ -78,7 +78,8 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
                             const double *a, const double *beta, const int32_t *active,
                             IterGuard g, hipStream_t s, int width = 0);
 // update_xp that also writes the new P as its split transpose (bfloat16
-// forms; PT_hi / PT_lo ldb x ldpt, ldpt a multiple of 64 >= N)
+// forms; PT_hi / PT_lo ldb x ldpt in fragment order, ldpt a multiple of 64
+// >= N)
 hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
                                const double *a, const double *beta, const int32_t *active,
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
@@ -144,11 +145,12 @@ hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, cons
 //      U_lo / UT_lo, when not null, hold the second bfloat16 term of the
 //      two-term form (U = U_hi + U_lo) in the same layout. The stored U1
 //      and the descriptors are in fragment order (frag_offset) ----
-// CT_hi / CT_lo (ldb x rk, bf16) = hi / lo split of C^T (C: rk x ldb fp32).
+// CT_hi / CT_lo (ldb x rk, bf16, fragment order; rk a multiple of 32) = hi /
+// lo split of C^T (C: rk x ldb fp32).
 // A null g.nact disables the iteration guard.
 hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi,
                           unsigned short *CT_lo, IterGuard g, hipStream_t s);
-// PT_hi / PT_lo (ldb x ldpt, bf16, item index contiguous, zero past N) =
+// PT_hi / PT_lo (ldb x ldpt, bf16, fragment order over items, zero past N) =
 // hi / lo split of P^T (P: N x ldb fp32 node-major); ldpt a multiple of 64.
 hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
                            unsigned short *PTl, IterGuard g, hipStream_t s, int width = 0);

@@ -436,11 +436,12 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
             h[u][q] = hb;
             l[u][q] = (__bf16)(v - (float)hb);
         }
-    const size_t o = (size_t)(b0 + b) * ldpt + i0 + seg;
+    // PT in fragment order: each run of 8 items is one 16-byte lane piece
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        *reinterpret_cast<bf16x8_t *>(PTh + o + 8 * u) = h[u];
-        *reinterpret_cast<bf16x8_t *>(PTl + o + 8 * u) = l[u];
+        const size_t o = frag_offset(b0 + b, i0 + seg + 8 * u, ldpt / 32);
+        *reinterpret_cast<bf16x8_t *>(PTh + o) = h[u];
+        *reinterpret_cast<bf16x8_t *>(PTl + o) = l[u];
     }
 }
 

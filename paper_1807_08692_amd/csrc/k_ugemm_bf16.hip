@@ -52,7 +52,10 @@ __global__ __launch_bounds__(kBlock) void k_split_t(const float *__restrict__ C,
     if (ig.nact && all_stopped(ig.nact, ig.ntile)) return;
     const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (idx >= (size_t)rk * ldb) return;
-    const int b = (int)(idx / rk), k = (int)(idx % rk);
+    // idx runs over CT in fragment order (kt = rk / 32 tiles per tile row)
+    const int kt = rk / 32, e = (int)(idx % 8), l = (int)((idx / 8) % 64);
+    const size_t tile = idx / 512;
+    const int b = (int)(tile / kt) * 16 + l % 16, k = (int)(tile % kt) * 32 + 8 * (l / 16) + e;
     const float v = C[(size_t)k * ldb + b];
     const unsigned short h = bf16_rne(v);
     CT_hi[idx] = h;
@@ -63,6 +66,7 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
                           unsigned short *CT_lo, IterGuard g, hipStream_t s) {
     const size_t tot = (size_t)rk * ldb;
     if (tot == 0) return hipSuccess;
+    if (rk % 32 != 0 || ldb % 16 != 0) return hipErrorInvalidValue;  // whole fragment tiles
     k_split_t<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(C, rk, ldb, CT_hi, CT_lo, g);
     return hipGetLastError();
 }
@@ -78,7 +82,8 @@ static inline int tn_rows_rt(int nt) { return nt == 4 ? tn_rows(4) : tn_rows(1);
 //   acc[m][n] = sum_k A[m][k] B[n][k]
 // with both operands K-contiguous bfloat16: A (M x K in fragment order, kt
 // tiles of 32 K per 16-row tile row, rows padded to a multiple of 16; one or
-// two terms A + Al) and B (N x K, row stride ldbk, split hi + lo). A block
+// two terms A + Al) and B (N x K in fragment order, ktb tiles per tile row,
+// split hi + lo). A block
 // covers 64 MT rows of M and 64*NT columns of N (from nb0); wave w owns rows
 // m0 + 16 MT w .. +16 MT - 1 (MT m-tiles) for all 64 NT columns (4 NT
 // n-tiles), so it holds 4 MT NT accumulators per lane. MT = 4 (NT <= 2) or 2
@@ -89,26 +94,27 @@ static inline int tn_rows_rt(int nt) { return nt == 4 ? tn_rows(4) : tn_rows(1);
 // load and its use; in fragment order each of those loads is one contiguous
 // kilobyte per wave (with rows of a plain row-major A it touched sixteen
 // rows and measured 1.2-2x slower). B (the coefficients, or the split P^T) is shared by the
-// four waves: per K step the block loads the 64 NT x 32 B tile (hi and lo; NT
-// 16-byte pieces per thread) once, stages it in LDS and every wave reads its
-// B fragments there; the next step's B pieces are fetched into registers while
-// the current step's MFMAs run.
+// four waves: per K step the block loads the 64 NT x 32 B tile - 4 NT
+// fragment tiles of a kilobyte, hi and lo - once (NT 16-byte pieces per
+// thread, each wave copying whole tiles), stages it in LDS in the same order
+// and every wave reads its B fragments there; the next step's B pieces are
+// fetched into registers while the current step's MFMAs run.
 //   products per (A term, B term): A_hi B_hi + A_hi B_lo (+ A_lo B_hi)
 // The accumulation order over K (and of the terms) is fixed: results do not
 // depend on NT.
 // MFMA v_mfma_f32_16x16x32_bf16: A fragment = A[m0 + l%16][k + 8(l/16) ..+7],
 // B fragment = B[n + l%16][k + 8(l/16) ..+7], C[m = 4(l/16) + v][n = l%16].
-// LDS rows are padded to 40 halves (80 bytes) so the 16-byte fragment reads
-// of 16 consecutive rows fall in distinct banks.
+// In fragment order a wave's B fragment read from LDS is one contiguous
+// kilobyte, lane l at 16 l bytes, so it is free of bank conflicts.
 template <bool LO, int NT, int MT = tn_mt(NT)>
 __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
                                          const unsigned short *__restrict__ Al, int64_t kt,
                                          int64_t m0, int64_t mend,
                                          const unsigned short *__restrict__ Bh,
-                                         const unsigned short *__restrict__ Bl, int64_t ldbk,
+                                         const unsigned short *__restrict__ Bl, int64_t ktb,
                                          int64_t nb0, int64_t k0, int64_t k1, f32x4 (&acc)[MT][4 * NT]) {
-    __shared__ __attribute__((aligned(16))) unsigned short Bsh[64 * NT][40];
-    __shared__ __attribute__((aligned(16))) unsigned short Bsl[64 * NT][40];
+    __shared__ __attribute__((aligned(16))) unsigned short Bsh[4 * NT][512];
+    __shared__ __attribute__((aligned(16))) unsigned short Bsl[4 * NT][512];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
     // this lane's place in its A tiles (one tile row per m-tile); K step k
@@ -130,10 +136,12 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
         pal[mt] = LO ? Al + o : nullptr;
     }
     const int64_t klast = k1 - 32;  // the last K step (K ranges are multiples of 32)
-    // B staging: pieces p = NT t + j -> row p / 4, k 8 (p % 4)
-    const int brow0 = (NT * threadIdx.x) / 4, bk0 = 8 * ((NT * threadIdx.x) % 4);
-    const unsigned short *sbh = Bh + (size_t)(nb0 + brow0) * ldbk + bk0;
-    const unsigned short *sbl = Bl + (size_t)(nb0 + brow0) * ldbk + bk0;
+    // B staging: wave w copies lane `lane` of the block's n-tiles w, w + 4,
+    // ... (tile rows nb0 / 16 + w + 4 j, j < NT), four tile rows apart
+    const size_t boff = ((size_t)(nb0 / 16 + w) * (size_t)ktb * 64 + (size_t)lane) * 8;
+    const unsigned short *sbh = Bh + boff;
+    const unsigned short *sbl = Bl + boff;
+    const size_t bstep = (size_t)4 * (size_t)ktb * 512;
     bf16x8 af[2][MT], afl[2][MT], rbh[NT], rbl[NT];
     auto fetch_a = [&](int slot, int64_t k) {
         const int64_t kc = k < k1 ? k : klast;
@@ -145,11 +153,10 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
     };
     auto fetch_b = [&](int64_t k) {
         const int64_t kc = k < k1 ? k : klast;
-        // NT pieces run along one row (NT <= 4 pieces = the row's 32 k)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            rbh[j] = load8(sbh + kc + 8 * j);
-            rbl[j] = load8(sbl + kc + 8 * j);
+            rbh[j] = load8(sbh + j * bstep + (size_t)kc * 16);
+            rbl[j] = load8(sbl + j * bstep + (size_t)kc * 16);
         }
     };
 #pragma unroll
@@ -168,16 +175,16 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
                 __syncthreads();  // the previous step's LDS reads are done
 #pragma unroll
                 for (int j = 0; j < NT; ++j) {
-                    *reinterpret_cast<bf16x8 *>(&Bsh[brow0][bk0 + 8 * j]) = rbh[j];
-                    *reinterpret_cast<bf16x8 *>(&Bsl[brow0][bk0 + 8 * j]) = rbl[j];
+                    *reinterpret_cast<bf16x8 *>(&Bsh[w + 4 * j][8 * lane]) = rbh[j];
+                    *reinterpret_cast<bf16x8 *>(&Bsl[w + 4 * j][8 * lane]) = rbl[j];
                 }
                 __syncthreads();
                 fetch_b(kk + 32);
                 fetch_a(st ^ 1, kk + 32);
 #pragma unroll
                 for (int n = 0; n < 4 * NT; ++n) {
-                    const bf16x8 bh = load8(&Bsh[16 * n + c16][8 * g]);
-                    const bf16x8 bl = load8(&Bsl[16 * n + c16][8 * g]);
+                    const bf16x8 bh = load8(&Bsh[n][8 * lane]);
+                    const bf16x8 bl = load8(&Bsl[n][8 * lane]);
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) {
                         acc[mt][n] = mfma16bf(af[st][mt], bh, acc[mt][n]);
@@ -203,8 +210,8 @@ static inline int tn_nt(int ldb, int req, int cap) {
 
 // ---------------------------------------------------------------------------
 // P^T split: from P (N x ldb fp32, node-major) write PT_hi, PT_lo (ldb x ldpt
-// bfloat16, item index contiguous; items N .. ldpt-1 zero), the B operand of
-// U^T P. A block transposes a 64-item x 64-column tile through LDS.
+// bfloat16 in fragment order over items; items N .. ldpt-1 zero), the B
+// operand of U^T P. A block transposes a 64-item x 64-column tile through LDS.
 __global__ __launch_bounds__(kBlock) void k_split_pt(int64_t N, int ldb, const float *__restrict__ P,
                                                      int64_t ldpt, unsigned short *__restrict__ PTh,
                                                      unsigned short *__restrict__ PTl, IterGuard ig) {
@@ -230,11 +237,12 @@ __global__ __launch_bounds__(kBlock) void k_split_pt(int64_t N, int ldb, const f
             h[u][q] = hb;
             l[u][q] = (__bf16)(v - (float)hb);
         }
-    const size_t o = (size_t)(b0 + b) * ldpt + i0 + seg;
+    // PT in fragment order: each run of 8 items is one 16-byte lane piece
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        *reinterpret_cast<bf16x8 *>(PTh + o + 8 * u) = h[u];
-        *reinterpret_cast<bf16x8 *>(PTl + o + 8 * u) = l[u];
+        const size_t o = frag_offset(b0 + b, i0 + seg + 8 * u, ldpt / 32);
+        *reinterpret_cast<bf16x8 *>(PTh + o) = h[u];
+        *reinterpret_cast<bf16x8 *>(PTl + o) = l[u];
     }
 }
 
@@ -271,7 +279,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
     const int64_t ks = (int64_t)chunk * rc;
     const int64_t ke = ks + rc < kend_all ? ks + rc : kend_all;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(UT, UTl, ldut / 32, m0, rk, PTh, PTl, ldut, nb0, ks, ke, acc);
+    tn_block<LO, NT>(UT, UTl, ldut / 32, m0, rk, PTh, PTl, ldut / 32, nb0, ks, ke, acc);
     float *out = Cpart + (size_t)chunk * rk * ldb;
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
@@ -328,7 +336,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned 
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // branch-free loads (rows past N read row N - 1 and store nothing)
 #pragma unroll
@@ -352,7 +360,7 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                            const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
                            int ntr) {
-    if (rp % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
+    if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
@@ -397,7 +405,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT, MT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    tn_block<LO, NT, MT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // r^2 of each 16-row m-tile and column (4 rows per lane, then across the
     // lane groups), summed below over the m-tiles of each 128-row group in
@@ -452,7 +460,7 @@ hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const uns
                                    int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
                                    IterGuard g, hipStream_t s, int ntr, int width) {
-    if (rp % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
+    if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     if (width == 0) width = ldb;
     if (width % 64 != 0 || width > ldb) return hipErrorInvalidValue;
     const int nt = tn_nt(width, ntr, 2);
@@ -489,7 +497,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk, nb0, 0, rk, acc);
+    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // per m-tile (16 items) and group of four n-tiles (64 queries)
 #pragma unroll
@@ -524,7 +532,7 @@ hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const 
                                int rp, int rk, const unsigned short *CT_hi,
                                const unsigned short *CT_lo, int ldb, const float *X, float *x,
                                int64_t ldx, hipStream_t s, int ntr) {
-    if (rp % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
+    if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
