@@ -411,29 +411,37 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
     // lane groups), summed below over the m-tiles of each 128-row group in
     // order: the same sums whatever the block shape
     __shared__ double sh[4 * MT][64 * NT];
-    // Branch-free: rows past N load row N - 1 and store nothing, so the
-    // loads of a tile are issued together rather than one at a time.
+    // Per m-tile and group of up to eight n-tiles, every load of Qs and r is
+    // issued before the first store to r: a store could alias a later load,
+    // so loads placed after it would each wait a full memory latency.
+    // Branch-free: rows past N load row N - 1 and store nothing.
+    constexpr int NG = 4 * NT < 8 ? 4 * NT : 8;
 #pragma unroll
-    for (int n = 0; n < 4 * NT; ++n) {
-        const int col = (int)(nb0 + 16 * n + c16);
-        const double av = a[col];
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            float qv[4], rv[4];
+    for (int n0 = 0; n0 < 4 * NT; n0 += NG) {
+        float qv[NG][4], rv[NG][4];
+#pragma unroll
+        for (int n = 0; n < NG; ++n)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
-                const size_t o = vec_index(N, ldb, i < N ? i : N - 1, col);
-                qv[v] = Qs[o];
-                rv[v] = R[o];
+                const size_t o = vec_index(N, ldb, i < N ? i : N - 1, (int)(nb0 + 16 * (n0 + n) + c16));
+                qv[n][v] = Qs[o];
+                rv[n][v] = R[o];
             }
+#pragma unroll
+        for (int nn = 0; nn < NG; ++nn) {
+            const int n = n0 + nn;
+            const int col = (int)(nb0 + 16 * n + c16);
+            const double av = a[col];
             double ss = 0.0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
-                const float q = qv[v] + cc * acc[mt][n][v];
-                const float rn = (float)((double)rv[v] - av * (double)q);
-                const float r = av != 0.0 ? rn : rv[v];
+                const float q = qv[nn][v] + cc * acc[mt][n][v];
+                const float rn = (float)((double)rv[nn][v] - av * (double)q);
+                const float r = av != 0.0 ? rn : rv[nn][v];
                 if (i < N) R[vec_index(N, ldb, i, col)] = r;
                 ss += i < N ? (double)r * (double)r : 0.0;
             }
@@ -499,23 +507,31 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
     f32x4 acc[MT][4 * NT];
     tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
-    // per m-tile (16 items) and group of four n-tiles (64 queries)
+    // per m-tile (16 items) and group of four n-tiles (64 queries); the
+    // m-tile's loads of X are all issued first (branch-free: rows past N
+    // read row N - 1), not one group at a time between the barriers
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int64_t ib = i0 + 16 * MT * w + 16 * mt;
+        float xv[NT][4][4];
+#pragma unroll
+        for (int ng = 0; ng < NT; ++ng)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = ib + 4 * g + v;
+                const int64_t ic = i < N ? i : N - 1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    xv[ng][v][q] = X[vec_index(N, ldc, ic, (int)(nb0 + 64 * ng + 16 * q + c16))];
+            }
 #pragma unroll
         for (int ng = 0; ng < NT; ++ng) {
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rl = 4 * g + v;
-                const int64_t i = ib + rl;
-                const int64_t ic = i < N ? i : N - 1;  // branch-free loads
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int bl = 16 * q + c16;
-                    T[w][bl][rl] = acc[mt][4 * ng + q][v] + X[vec_index(N, ldc, ic, (int)(nb0 + 64 * ng + bl))];
-                }
+                for (int q = 0; q < 4; ++q) T[w][16 * q + c16][rl] = acc[mt][4 * ng + q][v] + xv[ng][v][q];
             }
             __syncthreads();
             // lane -> (query bl = f / 16, item f % 16)
