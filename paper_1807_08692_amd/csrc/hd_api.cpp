@@ -484,7 +484,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             ov = reinterpret_cast<float *>(oi + (size_t)B * ky);
         }
         if (c->v_dtype == HD_BF16) {
-            HIP_TRY(c->qsplit.ensure((size_t)2 * B * c->ldv * sizeof(uint16_t)));
+            HIP_TRY(c->qsplit.ensure((size_t)2 * hd::sim_qsplit_rows(B) * c->ldv * sizeof(uint16_t)));
             LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.as<uint16_t>(), c->ldv,
                                               c->qsplit.as<uint16_t>(), c->sim.as<float>(), lds, s));
         } else {

@@ -184,8 +184,9 @@ hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const 
 // Tile parameters: a requested value (0 = default) is valid for width ldb
 // when it is one of 1, 2, 4 and divides the width in 64-column units.
 bool tile_param_ok(int v, int ldb);
-// sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv, fragment order); qsplit: scratch for
-// 2 x B x ldv bf16 (the hi / lo parts of q)
+// sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv, fragment order); qsplit:
+// scratch for 2 x sim_qsplit_rows(B) x ldv bf16 (the hi / lo parts of q)
+inline int sim_qsplit_rows(int B) { return (B + 63) / 64 * 64; }
 hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsigned short *V,
                            int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s);
 

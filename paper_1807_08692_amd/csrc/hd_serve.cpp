@@ -254,7 +254,7 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
         HIP_TRY(v->topk.ensure(hd::topk_scratch_bytes(m > ldb ? m : ldb, N, ky > v->o.top_k ? ky : v->o.top_k)));
         HIP_TRY(hipMemcpyAsync(v->qbuf.p, q_desc, (size_t)m * c->d * sizeof(float), hipMemcpyHostToDevice, s));
         if (c->v_dtype == HD_BF16) {
-            HIP_TRY(v->qsplit.ensure((size_t)2 * m * c->ldv * sizeof(uint16_t)));
+            HIP_TRY(v->qsplit.ensure((size_t)2 * hd::sim_qsplit_rows(m) * c->ldv * sizeof(uint16_t)));
             HIP_TRY(hd::launch_sim_bf16(N, m, c->d, v->qbuf.as<float>(), c->Vb.as<uint16_t>(), c->ldv,
                                         v->qsplit.as<uint16_t>(), v->sim.as<float>(), lds, s));
         } else {

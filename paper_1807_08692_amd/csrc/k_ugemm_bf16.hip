@@ -564,15 +564,20 @@ hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const 
 }
 
 // ---------------------------------------------------------------------------
-// Query descriptors split once per batch: Qh / Ql (B x ldv bfloat16, zero
-// padded), the hi and lo parts of q.
-__global__ __launch_bounds__(kBlock) void k_split_q(int B, int d, int ldv, const float *__restrict__ q,
+// Query descriptors split once per batch: Qh / Ql (B64 x ldv bfloat16, B64 =
+// B rounded up to 64, in fragment order, zero padded), the hi and lo parts
+// of q.
+__global__ __launch_bounds__(kBlock) void k_split_q(int B, int B64, int d, int ldv,
+                                                    const float *__restrict__ q,
                                                     unsigned short *__restrict__ Qh,
                                                     unsigned short *__restrict__ Ql) {
     const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= (size_t)B * ldv) return;
-    const int b = (int)(idx / ldv), t = (int)(idx % ldv);
-    const float v = t < d ? q[(size_t)b * d + t] : 0.f;
+    if (idx >= (size_t)B64 * ldv) return;
+    // idx runs over the output in fragment order (kt = ldv / 32)
+    const int kt = ldv / 32, l = (int)((idx / 8) % 64);
+    const size_t tile = idx / 512;
+    const int b = (int)(tile / kt) * 16 + l % 16, t = (int)(tile % kt) * 32 + 8 * (l / 16) + (int)(idx % 8);
+    const float v = b < B && t < d ? q[(size_t)b * d + t] : 0.f;
     const unsigned short h = bf16_rne(v);
     Qh[idx] = h;
     Ql[idx] = bf16_rne(v - bf16_to_f(h));
@@ -584,8 +589,10 @@ __global__ __launch_bounds__(kBlock) void k_split_q(int B, int d, int ldv, const
 // items [64w, 64w+64) (four n-tiles) for all 64 queries (four m-tiles, hi
 // and lo), so each V fragment feeds eight MFMAs. V rows are read by one wave
 // only: each wave loads its V fragments straight from global memory into
-// registers, one 32-wide k chunk ahead. The Q tiles (64 x 32, hi and lo) are
-// shared by the four waves and staged in LDS per chunk. The logical tiles run
+// registers, one 32-wide k chunk ahead. The Q tiles (64 x 32, hi and lo:
+// eight fragment tiles) are shared by the four waves and staged in LDS per
+// chunk in fragment order, so the waves' fragment reads are conflict-free.
+// The logical tiles run
 // over the query tiles fastest, so the tiles of one item range run on one
 // XCD and share V through its L2.
 __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ldv,
@@ -593,7 +600,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
                                                      const unsigned short *__restrict__ Ql,
                                                      const unsigned short *__restrict__ V,
                                                      float *__restrict__ sim, int64_t lds) {
-    __shared__ __attribute__((aligned(16))) unsigned short Qs[2][64][40];
+    __shared__ __attribute__((aligned(16))) unsigned short Qs[2][4][512];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
     const unsigned L = xcd_tile(), nqt = (unsigned)(B + 63) / 64;
@@ -617,9 +624,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
         const int64_t tb = jb / 16 + 4 * w + n;
         pv[n] = V + ((size_t)(tb < jtiles ? tb : jb / 16) * (size_t)(ldv / 32) * 64 + (size_t)lane) * 8;
     }
-    // Q staging: thread t -> array t/128, row (t%128)/2, k 16*(t%2) .. +15
-    const int qa = threadIdx.x / 128, qr = (threadIdx.x % 128) / 2, qk = 16 * (threadIdx.x % 2);
-    const unsigned short *qsrc = (qa == 0 ? Qh : Ql) + (size_t)(b0 + qr < B ? b0 + qr : b0) * ldv;
+    // Q staging: threads t < 128 copy the hi tiles, the others the lo tiles;
+    // thread t copies lane `lane` of m-tiles qm and qm + 2 (qm = (t % 128) /
+    // 64). Rows past B are the zero padding of the split.
+    const int qa = threadIdx.x / 128, qm = (threadIdx.x % 128) / 64;
+    const unsigned short *qsrc =
+        (qa == 0 ? Qh : Ql) + ((size_t)(b0 / 16 + qm) * (size_t)(ldv / 32) * 64 + (size_t)lane) * 8;
+    const size_t qstep = (size_t)2 * (size_t)(ldv / 32) * 512;  // two tile rows on
     bf16x8 vf[2][4], qv[2];
     auto fetch_v = [&](int slot, int t0) {
         const int tc = t0 < ldv ? t0 : ldv - 32;
@@ -629,7 +640,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
     auto fetch_q = [&](int t0) {
         const int tc = t0 < ldv ? t0 : ldv - 32;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) qv[u] = load8(qsrc + tc + qk + 8 * u);
+        for (int u = 0; u < 2; ++u) qv[u] = load8(qsrc + u * qstep + (size_t)tc * 16);
     };
     fetch_v(0, 0);
     fetch_q(0);
@@ -641,14 +652,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
             if (tt < ldv) {
                 __syncthreads();
 #pragma unroll
-                for (int u = 0; u < 2; ++u) *reinterpret_cast<bf16x8 *>(&Qs[qa][qr][qk + 8 * u]) = qv[u];
+                for (int u = 0; u < 2; ++u) *reinterpret_cast<bf16x8 *>(&Qs[qa][qm + 2 * u][8 * lane]) = qv[u];
                 __syncthreads();
                 fetch_q(tt + 32);
                 fetch_v(st ^ 1, tt + 32);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const bf16x8 h = load8(&Qs[0][16 * m + c16][8 * g]);
-                    const bf16x8 l = load8(&Qs[1][16 * m + c16][8 * g]);
+                    const bf16x8 h = load8(&Qs[0][m][8 * lane]);
+                    const bf16x8 l = load8(&Qs[1][m][8 * lane]);
 #pragma unroll
                     for (int n = 0; n < 4; ++n) {
                         acc[m][n] = mfma16bf(h, vf[st][n], acc[m][n]);
@@ -674,9 +685,11 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
 
 hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsigned short *V,
                            int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s) {
-    unsigned short *Qh = qsplit, *Ql = qsplit + (size_t)B * ldv;
-    const size_t tot = (size_t)B * ldv;
-    k_split_q<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(B, d, ldv, q, Qh, Ql);
+    if (ldv % 32 != 0) return hipErrorInvalidValue;
+    const int B64 = sim_qsplit_rows(B);
+    unsigned short *Qh = qsplit, *Ql = qsplit + (size_t)B64 * ldv;
+    const size_t tot = (size_t)B64 * ldv;
+    k_split_q<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(B, B64, d, ldv, q, Qh, Ql);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nblk = (unsigned)((B + 63) / 64) * (unsigned)((N + 255) / 256);
