@@ -395,9 +395,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
                                                            float *__restrict__ R, const double *__restrict__ a,
                                                            double *__restrict__ part, int wcols, IterGuard ig) {
     if (all_stopped(ig.nact, ig.ntile)) return;
-    // two m-tiles per wave (three waves per SIMD): with four, the main loop
-    // is shorter but the epilogue's loads of Qs and r overlap less, and the
-    // kernel measured no faster
+    // two m-tiles per wave (three waves per SIMD): four measured no faster
+    // in the CG iteration (1.67 against 1.66 ms a launch at 1M rows, 256
+    // columns; 12% faster alone on inputs just copied in, where the
+    // epilogue's loads find fewer of Qs and r in the caches)
     constexpr int RB = 64 * MT;
     const unsigned L = xcd_tile(), ncg = (unsigned)wcols / (64 * NT);
     const int64_t rb = (int64_t)(L / ncg);
