@@ -641,8 +641,11 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                                                       c->tv(HD_TUNE_UC_NT, ldb)));
             LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), nrb, o->tol, st, g, nact_dev[it & 1],
                                                   s));
-            LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut, PTh,
-                                                        PTl, g, s));
+            if (it == o->max_iter)  // nothing reads the new P or its split transpose
+                LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s, 0, true));
+            else
+                LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut,
+                                                            PTh, PTl, g, s));
             if (!graph) {
                 HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),
                                        hipMemcpyDeviceToHost, s));
@@ -686,7 +689,9 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s));
         LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), g, s));
         LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, g, nact_dev[it & 1], s));
-        if (ubf && rk > 0) {
+        if (it == o->max_iter) {  // the last iteration: nothing reads the new P
+            LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s, 0, true));
+        } else if (ubf && rk > 0) {
             uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
             LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut,
                                                         PTh, PTl, g, s));

@@ -73,10 +73,12 @@ hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart
 // writes the new per-tile active counts to nact_out
 hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
                             IterGuard g, int32_t *nact_out, hipStream_t s);
-// width (0 = ldb): only columns [0, width) are updated (row stride ldb)
+// width (0 = ldb): only columns [0, width) are updated (row stride ldb);
+// x_only: X += a P alone, for the last iteration (P and R untouched)
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
-                            IterGuard g, hipStream_t s, int width = 0);
+                            IterGuard g, hipStream_t s, int width = 0,
+                            bool x_only = false);
 // update_xp that also writes the new P as its split transpose (bfloat16
 // forms; PT_hi / PT_lo ldb x ldpt in fragment order, ldpt a multiple of 64
 // >= N)

@@ -322,6 +322,9 @@ hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, C
 
 // X += a P (the step of this iteration); P = R + beta P for columns still
 // active after the stopping test.
+// XONLY: the last iteration's update, x += a p alone (no later iteration
+// reads the new p), with the same x arithmetic
+template <bool XONLY>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, int width, float *X, float *P,
                                                       const float *R, const double *a,
                                                       const double *beta, const int32_t *active,
@@ -339,12 +342,16 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, int wi
         const size_t o = vec_index(N, ldb, (int64_t)i, cg * 4);
         float4 *xp = reinterpret_cast<float4 *>(X + o);
         float4 *pp = reinterpret_cast<float4 *>(P + o);
-        float4 r = *reinterpret_cast<const float4 *>(R + o);
         float4 x = *xp, p = *pp;
         if (a0 != 0.0) x.x = (float)((double)x.x + a0 * (double)p.x);
         if (a1 != 0.0) x.y = (float)((double)x.y + a1 * (double)p.y);
         if (a2 != 0.0) x.z = (float)((double)x.z + a2 * (double)p.z);
         if (a3 != 0.0) x.w = (float)((double)x.w + a3 * (double)p.w);
+        if (XONLY) {
+            *xp = x;
+            continue;
+        }
+        const float4 r = *reinterpret_cast<const float4 *>(R + o);
         if (k0) p.x = (float)((double)r.x + b0 * (double)p.x);
         if (k1) p.y = (float)((double)r.y + b1 * (double)p.y);
         if (k2) p.z = (float)((double)r.z + b2 * (double)p.z);
@@ -356,14 +363,17 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, int wi
 
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
-                            IterGuard g, hipStream_t s, int width) {
+                            IterGuard g, hipStream_t s, int width, bool x_only) {
     if (width == 0) width = ldb;
     if (width % 64 != 0 || width > ldb || width > 4 * kBlock) return hipErrorInvalidValue;
     int rows = kBlock / (width / 4);
     int64_t want = (N + rows - 1) / rows;
     int grid = (int)(want < 16384 ? want : 16384);
     if (grid < 1) grid = 1;
-    k_update_xp<<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g);
+    if (x_only)
+        k_update_xp<true><<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g);
+    else
+        k_update_xp<false><<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g);
     return hipGetLastError();
 }
 
