@@ -627,7 +627,7 @@ def measured_traffic(workload, dom, rec):
     want = None
     if dom == "spmm":
         cpl = ((rec.get("autotune") or {}).get("spmm_cpl") or {}).get("chosen") or 2
-        want = f"hd::k_spmm<{cpl}>"
+        want = f"hd::k_spmm<{cpl}, false>"
     for name, k in data.get("kernels", {}).items():
         if k.get("kind") != dom or (want and name != want):
             continue

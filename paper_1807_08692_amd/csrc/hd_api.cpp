@@ -21,7 +21,7 @@ static int64_t ctx_bytes(const hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                            &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                           &c->topk, &c->err, &c->qsplit, &c->Dg};
+                           &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask};
     int64_t s = 0;
     for (const DevBuf *b : all) s += (int64_t)b->bytes;
     return s;
@@ -69,7 +69,7 @@ void hd_destroy(hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                      &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                     &c->topk, &c->err, &c->qsplit, &c->Dg};
+                     &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (hipEvent_t e : c->iter_ev)
@@ -505,7 +505,12 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     LAUNCH(K_FILL, hd::launch_fill_zero(R, nv, s));
     LAUNCH(K_FILL, hd::launch_fill_zero(P, nv, s));
     LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 1, s));
-    LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s));
+    // the rows of y: the first product gathers only these rows of P (= y)
+    const size_t nmask = (size_t)(n + 31) / 32;
+    HIP_TRY(c->ymask.ensure(nmask * sizeof(uint32_t)));
+    uint32_t *ymask = c->ymask.as<uint32_t>();
+    LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(ymask), nmask, s));
+    LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s, nullptr, ymask));
     LAUNCH(K_COLSQ, hd::launch_colsq_part(n, ldb, R, rp, c->part.as<double>(), s));
     LAUNCH(K_SCALAR, hd::launch_cg_init(B, ldb, c->part.as<double>(), rp.nblk, st, s));
     if (!graph) {
@@ -631,9 +636,10 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                                                        o->alpha));
                 LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
             }
-            LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P,
-                                           P, Q, ldb, o->alpha, rp, c->part.as<double>(), g, s,
-                                           c->tv(HD_TUNE_SPMM_CPL, ldb)));
+            LAUNCH(it == 1 ? K_SPMM_Y : K_SPMM,
+                   hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, P, Q,
+                                   ldb, o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb), 0,
+                                   it == 1 ? ymask : nullptr));
             LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, c->Dg.as<double>(),
                                                   rk));
             LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,
@@ -684,8 +690,10 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             }
             Zs = c->Z.as<float>();
         }
-        LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
-                                       ldb, o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb)));
+        LAUNCH(it == 1 ? K_SPMM_Y : K_SPMM,
+               hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q, ldb,
+                               o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb), 0,
+                               it == 1 ? ymask : nullptr));
         LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s));
         LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), g, s));
         LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, g, nact_dev[it & 1], s));

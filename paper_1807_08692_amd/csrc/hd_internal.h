@@ -78,11 +78,13 @@ inline int pow2_at_least(int v) {
 // Kernel kinds for the optional per-launch event timing.
 enum Kind {
     K_SIM, K_TOPK_Y, K_FILL, K_SCATTER, K_COLSQ, K_SCALAR, K_GATHER, K_UT_P, K_REDUCE_C,
-    K_U_C, K_SPMM, K_UPDATE_R, K_UPDATE_XP, K_COMBINE, K_TOPK_RANK, K_NKINDS
+    K_U_C, K_SPMM, K_UPDATE_R, K_UPDATE_XP, K_COMBINE, K_TOPK_RANK,
+    K_SPMM_Y,  // the first sparse product, gathering only the rows of y
+    K_NKINDS
 };
 inline const char *const kKindNames[K_NKINDS] = {
     "sim", "topk_y", "fill_zero", "scatter_y", "colsq", "cg_scalar", "gather_proj", "ut_p",
-    "reduce_c", "u_c", "spmm", "update_r", "update_xp", "combine", "topk_rank"};
+    "reduce_c", "u_c", "spmm", "update_r", "update_xp", "combine", "topk_rank", "spmm_y"};
 
 struct Timing {
     bool on = false;
@@ -176,6 +178,7 @@ struct hd_ctx {
     int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
     hipEvent_t iter_ev[2] = {nullptr, nullptr};
     DevBuf Dg;  // alpha / (1 - alpha) lambda (U1^T P)^2 per component and column
+    DevBuf ymask;  // one bit per item: the rows where y (the first P) is nonzero
     hd::CgState st{};
     Timing timing;
     int tune[HD_TUNE_NKEYS] = {0, 0, 0};  // launch parameters (0 = default)

@@ -57,10 +57,11 @@ RowPart make_row_part(int64_t N);
 
 // ---- CG vector kernels (k_cg.hip) ----
 hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s);
-// colmap (nullptr = identity): y row t goes to solver column colmap[t]
+// colmap (nullptr = identity): y row t goes to solver column colmap[t];
+// rowmask (nullptr = none): bit id of word id / 32 is set for every y id
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                             int ldb, float *R, float *P, int32_t *err, hipStream_t s,
-                            const int32_t *colmap = nullptr);
+                            const int32_t *colmap = nullptr, uint32_t *rowmask = nullptr);
 hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
                              hipStream_t s);
 hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s);
@@ -115,13 +116,14 @@ hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *C
 
 // ---- sparse product (k_spmm.hip) ----
 // Q = (Zs - alpha * S P) / (1 - alpha); gpart[g][c] = sum over the rows of
-// block g of P[i][c] * Q[i][c] (double). The launchers that take a width
+// block g of P[i][c] * Q[i][c] (double). With rowmask, neighbour rows whose
+// bit is clear (all zero in P) are not gathered; the result is the same. The launchers that take a width
 // (0 = ldb; a multiple of 64) compute only columns [0, width) of vectors of
 // row stride ldb.
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
                        RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl = 0,
-                       int width = 0);
+                       int width = 0, const uint32_t *rowmask = nullptr);
 
 // ---- eigenvector products on MFMA (k_ugemm.hip) ----
 // Number of row chunks of the split-K product U^T P.

@@ -54,7 +54,7 @@ hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s) {
 __global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32_t *ids,
                                                       const float *vals, int64_t N, int ldb,
                                                       float *R, float *P, int32_t *err,
-                                                      const int32_t *colmap) {
+                                                      const int32_t *colmap, uint32_t *rowmask) {
     int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= B * ky) return;
     int b = colmap ? colmap[idx / ky] : idx / ky;
@@ -67,15 +67,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32
     const size_t o = vec_index(N, ldb, id, b);
     atomicAdd(&R[o], v);
     atomicAdd(&P[o], v);
+    if (rowmask) atomicOr(&rowmask[id >> 5], 1u << (id & 31));
 }
 
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                             int ldb, float *R, float *P, int32_t *err, hipStream_t s,
-                            const int32_t *colmap) {
+                            const int32_t *colmap, uint32_t *rowmask) {
     int tot = B * ky;
     if (tot == 0) return hipSuccess;
     k_scatter_y<<<(tot + kBlock - 1) / kBlock, kBlock, 0, s>>>(B, ky, ids, vals, N, ldb, R, P, err,
-                                                                colmap);
+                                                                colmap, rowmask);
     return hipGetLastError();
 }
 

@@ -52,7 +52,12 @@ struct VecF<4> {
     }
 };
 
-template <int CPL>
+// MASKED: rowmask has bit j set for every row j of P that may be nonzero (the
+// support of y in the first CG iteration, where P = y); a neighbour whose bit
+// is clear is skipped instead of gathered. Its term would add v * 0 to the
+// accumulator, which leaves it unchanged, and the kept terms are added in the
+// same order, so the result is bit-identical to the full product.
+template <int CPL, bool MASKED>
 __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col,
                                                  const float *__restrict__ val,
@@ -60,7 +65,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__res
                                                  const float *__restrict__ Zs,
                                                  float *__restrict__ Q, int ldb, float alpha,
                                                  float one_minus_alpha, int64_t rb,
-                                                 double *__restrict__ gpart, IterGuard ig) {
+                                                 double *__restrict__ gpart, IterGuard ig,
+                                                 const uint32_t *__restrict__ rowmask) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     const int lane = threadIdx.x % kWave;
     const int w = threadIdx.x / kWave;
@@ -83,6 +89,22 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__res
             if (me < e1) {
                 cidx = col[me];
                 cv = val[me];
+            }
+            if (MASKED) {
+                // the lanes whose neighbour row is in the mask, in edge order
+                const bool nz = me < e1 && ((rowmask[cidx >> 5] >> (cidx & 31)) & 1u);
+                uint64_t bits = __ballot(nz);
+                while (bits) {
+                    const int t = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const int j = bcast_i(cidx, t);
+                    const float v = bcast_f(cv, t);
+                    VecF<CPL> pv;
+                    pv.load(P + (size_t)j * ldb + c0);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) acc[c] += v * pv.v[c];
+                }
+                continue;
             }
             const int cnt = (int)(e1 - eb < kWave ? e1 - eb : kWave);
             int t = 0;
@@ -153,23 +175,27 @@ bool tile_param_ok(int v, int ldb) { return (v == 1 || v == 2 || v == 4) && ldb 
 // cpl: query columns per lane (a wave covers 64 cpl columns of a row); the
 // default is 2 when it divides the width (measured fastest at 256 columns on a
 // million-row graph), else 1. width (0 = ldb): only columns [0, width) are
-// computed (row stride stays ldb); a multiple of 64.
+// computed (row stride stays ldb); a multiple of 64. rowmask (nullptr =
+// none): bit j of word j / 32 set for the rows of P that may be nonzero;
+// the others must be zero in every computed column.
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
-                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl, int width) {
+                       RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl, int width,
+                       const uint32_t *rowmask) {
     const float a = (float)alpha, oma = (float)(1.0 - alpha);
     if (width == 0) width = ldb;
     if (width < 64 || width > ldb || width % 64 != 0) return hipErrorInvalidValue;
     if (cpl == 0) cpl = width % 128 == 0 ? 2 : 1;
     if (!tile_param_ok(cpl, width)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)rp.nblk, (unsigned)(width / (64 * cpl)));
-    if (cpl == 1) {
-        k_spmm<1><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g);
-    } else if (cpl == 2) {
-        k_spmm<2><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g);
+#define HD_SPMM(C, M) \
+    k_spmm<C, M><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g, rowmask)
+    if (rowmask) {
+        if (cpl == 1) HD_SPMM(1, true); else if (cpl == 2) HD_SPMM(2, true); else HD_SPMM(4, true);
     } else {
-        k_spmm<4><<<grid, kBlock, 0, s>>>(N, rowptr, col, val, P, Zs, Q, ldb, a, oma, rp.rb, gpart, g);
+        if (cpl == 1) HD_SPMM(1, false); else if (cpl == 2) HD_SPMM(2, false); else HD_SPMM(4, false);
     }
+#undef HD_SPMM
     return hipGetLastError();
 }
 
