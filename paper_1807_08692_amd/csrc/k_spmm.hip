@@ -11,7 +11,10 @@
 // 64 (column id, value) pairs of its row at a time and broadcasts each pair
 // with readlane, keeping up to 16 gathers in flight. The kernel is bound by
 // HBM (or Infinity Cache) bandwidth: it reads the CSR once, gathers P, and
-// streams Zs in and Q out.
+// streams Zs in and Q out. In the first CG iteration P = y is nonzero on the
+// k_y rows of each query only: with the row mask the y scatter builds, that
+// product skips the gathers (and, when Zs = P, the own-row loads) of the
+// all-zero rows, with a bit-identical result.
 #include "hd_device.h"
 #include "hd_kernels.h"
 
@@ -146,7 +149,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t N, const int64_t *__res
             }
         }
         VecF<CPL> z, p, q;
-        z.load(Zs + (size_t)i * ldb + c0);
+        if (MASKED && Zs == P && !((rowmask[i >> 5] >> (i & 31)) & 1u)) {
+            // a row outside the mask is zero in P (= Zs here)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) z.v[c] = 0.f;
+        } else {
+            z.load(Zs + (size_t)i * ldb + c0);
+        }
         if (Zs == P) {
             p = z;
         } else {
