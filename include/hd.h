@@ -106,7 +106,8 @@ int hd_load_graph(hd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr,
  * U (host, fp32, n x r row-major: row i holds item i's r components),
  * lambda (host, double, r values, each in [-1, 1] up to 1e-6 of rounding). `dtype` selects the
  * storage precision on the device: HD_F32, or HD_BF16 (U rounded to
- * nearest-even bfloat16 and kept twice, item-major and component-major; the
+ * nearest-even bfloat16 and kept twice, item-major and component-major,
+ * each in the matrix cores' 16 x 32 operand-tile order; the
  * products multiply it with the fp32 operand split into two bfloat16 parts
  * and accumulate in fp32), or HD_BF16X2 (U kept as two bfloat16 terms in
  * both layouts, products over three bfloat16 terms, accuracy close to fp32
@@ -216,8 +217,10 @@ int hd_load_eigs_sparse(hd_ctx *ctx, int32_t r, int64_t nnz, const int64_t *rowp
  * (Section 3: nearest neighbours of the query in the dataset). V (host,
  * fp32, n x d row-major, unit-norm rows so that the dot product is the
  * cosine). `dtype` selects the device storage: HD_F32, or HD_BF16 (rounded to
- * nearest even; the query descriptors stay fp32 and are split into two
- * bfloat16 parts for the product). HD_BF16X2 is not accepted here.
+ * nearest even and kept in the matrix cores' 16 x 32 operand-tile order;
+ * the query descriptors stay fp32 and are split into two bfloat16 parts for
+ * the product). HD_BF16X2 is not accepted here. The host arrays are
+ * converted on the host and may be freed on return.
  * Errors: HD_ESTATE (no graph), HD_EINVAL (d <= 0, non-finite V, dtype).
  */
 int hd_load_descriptors(hd_ctx *ctx, int32_t d, const float *V, int32_t dtype);
