@@ -511,8 +511,8 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     uint32_t *ymask = c->ymask.as<uint32_t>();
     LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(ymask), nmask, s));
     LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s, nullptr, ymask));
-    LAUNCH(K_COLSQ, hd::launch_colsq_part(n, ldb, R, rp, c->part.as<double>(), s));
-    LAUNCH(K_SCALAR, hd::launch_cg_init(B, ldb, c->part.as<double>(), rp.nblk, st, s));
+    LAUNCH(K_COLSQ, hd::launch_ynorm_part(B, ky, yi, n, ldb, R, c->part.as<double>(), s));
+    LAUNCH(K_SCALAR, hd::launch_cg_init(B, ldb, c->part.as<double>(), 1, st, s));
     if (!graph) {
         HIP_TRY(hipMemcpyAsync(c->h_pinned + 200, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));

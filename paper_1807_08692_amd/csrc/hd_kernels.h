@@ -64,6 +64,11 @@ hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals
                             const int32_t *colmap = nullptr, uint32_t *rowmask = nullptr);
 hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
                              hipStream_t s);
+// part[c] (one row of ldb doubles) = the squared norm of column c of R right
+// after the y scatter, from the y ids alone (B y rows of ky ids; colmap as
+// in launch_scatter_y, without it columns >= B get 0)
+hipError_t launch_ynorm_part(int B, int ky, const int32_t *ids, int64_t N, int ldb, const float *R,
+                             double *part, hipStream_t s, const int32_t *colmap = nullptr);
 hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s);
 // gamma = the column sums of gpart (nblk rows), plus those of gpart2 (nblk2
 // rows) when given

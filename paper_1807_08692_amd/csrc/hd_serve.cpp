@@ -275,8 +275,8 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     HIP_TRY(hd::launch_zero_cols(N, ldb, v->X.as<float>(), v->R.as<float>(), v->P.as<float>(), cols, m, s));
     HIP_TRY(hd::launch_scatter_y(m, ky, yi, yv, N, ldb, v->R.as<float>(), v->P.as<float>(),
                                  v->err.as<int32_t>(), s, cols));
-    HIP_TRY(hd::launch_colsq_part(N, ldb, v->R.as<float>(), v->rp, v->part.as<double>(), s));
-    HIP_TRY(hd::launch_init_cols(ldb, v->part.as<double>(), v->rp.nblk, v->st, cols, v->maxit.as<int32_t>(), m, s));
+    HIP_TRY(hd::launch_ynorm_part(m, ky, yi, N, ldb, v->R.as<float>(), v->part.as<double>(), s, cols));
+    HIP_TRY(hd::launch_init_cols(ldb, v->part.as<double>(), 1, v->st, cols, v->maxit.as<int32_t>(), m, s));
     if (v->rk > 0) {
         const bool ubf = c->u_bf16();
         HIP_TRY(hd::launch_gather_proj(m, ky, yi, yv, N, ubf ? (const void *)c->Ub.p : (const void *)c->U.p,

@@ -128,6 +128,56 @@ __global__ __launch_bounds__(kBlock) void k_colsq_part(int64_t N, int ldb, const
     block_colsum4(s0, s1, s2, s3, G, part + (size_t)blockIdx.x * ldb);
 }
 
+// rho0 = y^T y per column straight from y: R holds y after the scatter and
+// is zero elsewhere, so the column sum of R^2 over all rows is the sum over
+// the distinct ids of the column's y (duplicate ids were added into one
+// entry). One wave per y row t (column colmap[t], or t): lane u squares the
+// entry of id u unless an earlier id repeats it, and the wave sums 64 ids at
+// a time in a fixed order (lane 0's butterfly), so the result depends on the
+// ids alone. Without colmap, columns B .. ldb-1 get 0.
+__global__ __launch_bounds__(kBlock) void k_ynorm_part(int B, int ky, const int32_t *__restrict__ ids,
+                                                       int64_t N, int ldb, const float *__restrict__ R,
+                                                       double *__restrict__ part,
+                                                       const int32_t *__restrict__ colmap) {
+    const int lane = threadIdx.x % kWave;
+    const int t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (t >= (colmap ? B : ldb)) return;  // whole waves
+    if (t >= B) {
+        if (lane == 0) part[t] = 0.0;
+        return;
+    }
+    const int col = colmap ? colmap[t] : t;
+    const int32_t *row = ids + (size_t)t * ky;
+    double sum = 0.0;
+    for (int u0 = 0; u0 < ky; u0 += kWave) {
+        const int u = u0 + lane;
+        double x2 = 0.0;
+        if (u < ky) {
+            const int32_t id = row[u];
+            if (id >= 0 && (int64_t)id < N) {
+                bool dup = false;
+                for (int v = 0; v < u && !dup; ++v) dup = row[v] == id;
+                if (!dup) {
+                    const double x = (double)R[vec_index(N, ldb, id, col)];
+                    x2 = x * x;
+                }
+            }
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) x2 += __shfl_xor(x2, off, kWave);
+        sum += x2;
+    }
+    if (lane == 0) part[col] = sum;
+}
+
+hipError_t launch_ynorm_part(int B, int ky, const int32_t *ids, int64_t N, int ldb, const float *R,
+                             double *part, hipStream_t s, const int32_t *colmap) {
+    const int waves = colmap ? B : ldb;
+    if (waves <= 0) return hipSuccess;
+    const int per = kBlock / kWave;
+    k_ynorm_part<<<(waves + per - 1) / per, kBlock, 0, s>>>(B, ky, ids, N, ldb, R, part, colmap);
+    return hipGetLastError();
+}
+
 hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
                              hipStream_t s) {
     k_colsq_part<<<rp.nblk, kBlock, 0, s>>>(N, ldb, R, rp.rb, part);
