@@ -62,8 +62,6 @@ hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s);
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                             int ldb, float *R, float *P, int32_t *err, hipStream_t s,
                             const int32_t *colmap = nullptr, uint32_t *rowmask = nullptr);
-hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
-                             hipStream_t s);
 // part[c] (one row of ldb doubles) = the squared norm of column c of R right
 // after the y scatter, from the y ids alone (B y rows of ky ids; colmap as
 // in launch_scatter_y, without it columns >= B get 0)

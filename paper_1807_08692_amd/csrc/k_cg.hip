@@ -109,25 +109,6 @@ __device__ __forceinline__ void block_colsum4(double s0, double s1, double s2, d
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_colsq_part(int64_t N, int ldb, const float *R,
-                                                       int64_t rb, double *part) {
-    const int G = ldb / 4;
-    const int rows = kBlock / G;
-    int cg = threadIdx.x % G;
-    int r0 = threadIdx.x / G;
-    int64_t rs = (int64_t)blockIdx.x * rb;
-    int64_t re = rs + rb < N ? rs + rb : N;
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    for (int64_t i = rs + r0; i < re; i += rows) {
-        float4 v = *reinterpret_cast<const float4 *>(R + vec_index(N, ldb, i, cg * 4));
-        s0 += (double)v.x * v.x;
-        s1 += (double)v.y * v.y;
-        s2 += (double)v.z * v.z;
-        s3 += (double)v.w * v.w;
-    }
-    block_colsum4(s0, s1, s2, s3, G, part + (size_t)blockIdx.x * ldb);
-}
-
 // rho0 = y^T y per column straight from y: R holds y after the scatter and
 // is zero elsewhere, so the column sum of R^2 over all rows is the sum over
 // the distinct ids of the column's y (duplicate ids were added into one
@@ -175,12 +156,6 @@ hipError_t launch_ynorm_part(int B, int ky, const int32_t *ids, int64_t N, int l
     if (waves <= 0) return hipSuccess;
     const int per = kBlock / kWave;
     k_ynorm_part<<<(waves + per - 1) / per, kBlock, 0, s>>>(B, ky, ids, N, ldb, R, part, colmap);
-    return hipGetLastError();
-}
-
-hipError_t launch_colsq_part(int64_t N, int ldb, const float *R, RowPart rp, double *part,
-                             hipStream_t s) {
-    k_colsq_part<<<rp.nblk, kBlock, 0, s>>>(N, ldb, R, rp.rb, part);
     return hipGetLastError();
 }
 
