@@ -607,22 +607,32 @@ hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *va
 // Each column is its own CG recurrence, so a request's arithmetic is the same
 // whatever else shares the batch.
 
+// Thread -> (row i, slot t) with t fastest, so the lanes of a wave cover
+// consecutive slots of a few rows: admission takes the lowest free columns,
+// so the slots are mostly runs of adjacent columns and the writes coalesce
+// (one thread per row looping over the columns touched 64 rows, 64 lines,
+// per instruction).
 __global__ __launch_bounds__(kBlock) void k_zero_cols(int64_t N, int ldb, float *X, float *R,
                                                       float *P, const int32_t *cols, int ncols) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= N) return;
-    for (int t = 0; t < ncols; ++t) {
-        const size_t o = (size_t)i * ldb + cols[t];
+    const size_t tot = (size_t)N * (size_t)ncols;
+    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < tot; k += (size_t)gridDim.x * kBlock) {
+        const size_t i = k / (size_t)ncols;
+        const size_t o = i * (size_t)ldb + (size_t)cols[k % (size_t)ncols];
         X[o] = 0.f;
         R[o] = 0.f;
         P[o] = 0.f;
     }
 }
 
+static unsigned grid_for(size_t tot) {
+    const size_t want = (tot + kBlock - 1) / kBlock;
+    return (unsigned)(want < 16384 ? (want > 0 ? want : 1) : 16384);
+}
+
 hipError_t launch_zero_cols(int64_t N, int ldb, float *X, float *R, float *P, const int32_t *cols,
                             int ncols, hipStream_t s) {
-    if (ncols == 0) return hipSuccess;
-    k_zero_cols<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, s>>>(N, ldb, X, R, P, cols, ncols);
+    if (ncols == 0 || N == 0) return hipSuccess;
+    k_zero_cols<<<grid_for((size_t)N * (size_t)ncols), kBlock, 0, s>>>(N, ldb, X, R, P, cols, ncols);
     return hipGetLastError();
 }
 
@@ -666,25 +676,34 @@ hipError_t launch_init_cols(int ldb, const double *part, int nblk, CgState st, c
     return hipGetLastError();
 }
 
+// Xc (N x ldc) and Csc (rk x ldc): slot t of each row takes column cols[t]
+// (zero for t >= ncols). Thread -> (row, slot) with the slot fastest, so a
+// wave reads runs of a few rows of X and writes whole rows of Xc.
 __global__ __launch_bounds__(kBlock) void k_gather_cols(int64_t N, int ldb, const float *X,
                                                         const float *Cs, int rk,
                                                         const int32_t *cols, int ncols, int ldc,
                                                         float *Xc, float *Csc) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < N)
-        for (int t = 0; t < ldc; ++t)
-            Xc[(size_t)i * ldc + t] = t < ncols ? X[(size_t)i * ldb + cols[t]] : 0.f;
-    if (i < rk)
-        for (int t = 0; t < ldc; ++t)
-            Csc[(size_t)i * ldc + t] = t < ncols ? Cs[(size_t)i * ldb + cols[t]] : 0.f;
+    const size_t totx = (size_t)N * (size_t)ldc, tot = totx + (size_t)rk * (size_t)ldc;
+    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < tot; k += (size_t)gridDim.x * kBlock) {
+        const bool x = k < totx;
+        const size_t kk = x ? k : k - totx;
+        const size_t i = kk / (size_t)ldc;
+        const int t = (int)(kk % (size_t)ldc);
+        const float *src = x ? X : Cs;
+        const float v = t < ncols ? src[i * (size_t)ldb + (size_t)cols[t]] : 0.f;
+        if (x)
+            Xc[kk] = v;
+        else
+            Csc[kk] = v;
+    }
 }
 
 hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *Cs, int rk,
                               const int32_t *cols, int ncols, int ldc, float *Xc, float *Csc,
                               hipStream_t s) {
-    const int64_t rows = N > rk ? N : rk;
-    k_gather_cols<<<(unsigned)((rows + kBlock - 1) / kBlock), kBlock, 0, s>>>(N, ldb, X, Cs, rk, cols,
-                                                                            ncols, ldc, Xc, Csc);
+    const size_t tot = ((size_t)N + (size_t)(rk > 0 ? rk : 0)) * (size_t)ldc;
+    if (tot == 0) return hipSuccess;
+    k_gather_cols<<<grid_for(tot), kBlock, 0, s>>>(N, ldb, X, Cs, rk, cols, ncols, ldc, Xc, Csc);
     return hipGetLastError();
 }
 
