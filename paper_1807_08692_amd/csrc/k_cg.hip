@@ -405,11 +405,11 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
 
 // update_xp for the bfloat16 forms of U1: the same X and P updates, and the
 // new P also written as its split transpose PT_hi / PT_lo (ldb x ldpt
-// bfloat16, item index contiguous, zero past N), the operand of the next
-// iteration's U1^T P. A block covers 64 items x 64 columns: thread t updates
-// the float4 at column 4(t%16) of rows t/16 + 16j, then the 64 x 64 tile of
-// new P is transposed through LDS and thread t writes column t/4, items
-// 16(t%4) .. +15 of PT as 16-byte stores.
+// bfloat16 in fragment order over items, zero past N), the operand of the
+// next iteration's U1^T P. A block covers 64 items x 64 columns: thread t
+// updates the float4 at column 4(t%16) of rows t/16 + 16j, then the 64 x 64
+// tile of new P is transposed through LDS and thread t writes column t/4,
+// items 16(t%4) .. +15 of PT as two 16-byte lane pieces.
 __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, float *X, float *P,
                                                          const float *R, const double *a,
                                                          const double *beta, const int32_t *active,
