@@ -57,7 +57,9 @@ typedef enum {
 typedef enum {
     HD_F32 = 0,
     HD_BF16 = 1,          /* bfloat16, rounded to nearest even from the fp32 input */
-    HD_FP8_E4M3 = 2,      /* OCP e4m3 with one fp32 scale per column (U1) or row (V) */
+    HD_FP8_E4M3 = 2,      /* OCP FP8 E4M3 codes (bias 7, max 448, no infinities)
+                             with one fp32 scale per column (U1) or per row (V):
+                             value = scale * code value */
     HD_BF16X2 = 3,        /* U1 only: two bfloat16 terms hi + lo, hi = RNE(u),
                              lo = RNE(u - hi) (about 16 significant bits) */
     HD_SPARSE_F32 = 4     /* U1 only, set by hd_load_eigs_sparse: sparsified
@@ -111,13 +113,45 @@ int hd_load_graph(hd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr,
  * products multiply it with the fp32 operand split into two bfloat16 parts
  * and accumulate in fp32), or HD_BF16X2 (U kept as two bfloat16 terms in
  * both layouts, products over three bfloat16 terms, accuracy close to fp32
- * at twice the bytes of HD_BF16). r = 0 unloads. Queries may use any prefix of the
+ * at twice the bytes of HD_BF16), or HD_FP8_E4M3 (each column k quantized
+ * as by hd_quantize_fp8_e4m3 with one scale per column and kept as one-byte
+ * codes in the same two layouts; the products convert the codes to bfloat16
+ * in registers, which is exact, and apply the scales to the small
+ * coefficient matrices). r = 0 unloads. Queries may use any prefix of the
  * loaded columns (hd_query_opts.rank_r).
+ * Every argument is checked before the context changes: a rejected call
+ * leaves the loaded eigenpairs as they were. A failure after the checks (an
+ * allocation or a copy) leaves no eigenpairs loaded.
  * Errors: HD_ESTATE (no graph), HD_EINVAL (r < 0, r > n, lambda outside
  * [-1, 1] or non-finite, non-finite U, unknown dtype).
  */
 int hd_load_eigs(hd_ctx *ctx, int32_t r, const float *U, const double *lambda,
                  int32_t dtype);
+
+/*
+ * Load r eigenpairs with U1 already in the FP8 form (the storage precision of
+ * the precision form; Section 4.1 defines U1): codes (host, n x r row-major
+ * OCP FP8 E4M3 bytes, so U1[i][k] = col_scale[k] * value(codes[i r + k])),
+ * col_scale (host, r fp32 values > 0), lambda (host, r doubles in [-1, 1]).
+ * Same device layout and queries as hd_load_eigs with HD_FP8_E4M3, and the
+ * same rule on rejected calls.
+ * Errors: HD_ESTATE (no graph), HD_EINVAL (r not in [1, n], NULL array, a NaN
+ * code 0x7F / 0xFF, a scale not positive and finite, lambda out of range).
+ */
+int hd_load_eigs_fp8(hd_ctx *ctx, int32_t r, const uint8_t *codes, const float *col_scale,
+                     const double *lambda);
+
+/*
+ * The FP8 quantizer of the precision form (host only, no device work): for a
+ * rows x cols row-major fp32 matrix A (host), one scale per column
+ * (per_column != 0, scales[cols]) or per row (per_column = 0, scales[rows]),
+ * scale = max |a| / 448 over the line (1 for an all-zero line, division in
+ * fp32), and codes[i cols + k] (host) = a / scale rounded to the nearest OCP
+ * FP8 E4M3 value, ties to even, magnitudes at or above 448 saturating to 448.
+ * Errors: HD_EINVAL (negative size, NULL array, non-finite input).
+ */
+int hd_quantize_fp8_e4m3(int64_t rows, int32_t cols, const float *A, int32_t per_column,
+                         uint8_t *codes, float *scales);
 
 /*
  * Launch parameters of the hot kernels: the search space of hd_autotune.
@@ -219,11 +253,26 @@ int hd_load_eigs_sparse(hd_ctx *ctx, int32_t r, int64_t nnz, const int64_t *rowp
  * cosine). `dtype` selects the device storage: HD_F32, or HD_BF16 (rounded to
  * nearest even and kept in the matrix cores' 16 x 32 operand-tile order;
  * the query descriptors stay fp32 and are split into two bfloat16 parts for
- * the product). HD_BF16X2 is not accepted here. The host arrays are
- * converted on the host and may be freed on return.
+ * the product), or HD_FP8_E4M3 (each row quantized as by
+ * hd_quantize_fp8_e4m3 with one scale per row, codes in the same operand
+ * order, converted to bfloat16 in registers; the scale multiplies the row's
+ * similarities). HD_BF16X2 is not accepted here. The host arrays are
+ * converted on the host and may be freed on return. A rejected call leaves
+ * the loaded descriptors as they were; a failure after the checks leaves
+ * none loaded.
  * Errors: HD_ESTATE (no graph), HD_EINVAL (d <= 0, non-finite V, dtype).
  */
 int hd_load_descriptors(hd_ctx *ctx, int32_t d, const float *V, int32_t dtype);
+
+/*
+ * Load descriptors already in the FP8 form: codes (host, n x d row-major OCP
+ * FP8 E4M3 bytes, V[i][t] = row_scale[i] * value(codes[i d + t])), row_scale
+ * (host, n fp32 values > 0). Same use as hd_load_descriptors with
+ * HD_FP8_E4M3 and the same rule on rejected calls.
+ * Errors: HD_ESTATE (no graph), HD_EINVAL (d <= 0, NULL array, a NaN code, a
+ * scale not positive and finite).
+ */
+int hd_load_descriptors_fp8(hd_ctx *ctx, int32_t d, const uint8_t *codes, const float *row_scale);
 
 /* Options of one query batch. */
 typedef struct {
@@ -417,6 +466,18 @@ int hd_serve_step(hd_server *srv, int32_t iters);
  */
 int hd_serve_poll(hd_server *srv, int32_t max_out, int64_t *tickets, int32_t *ids, float *scores,
                   int32_t *iters, double *relres, int32_t *status);
+
+/*
+ * Cancel requests: each of the n tickets (host) that names an admitted
+ * request not yet collected by hd_serve_poll has its column stopped after
+ * the iterations already queued and freed for the next admission; its
+ * results are discarded. The other columns' results do not change (each
+ * column is its own recurrence). Tickets that name no such request are
+ * ignored. Returns the number of requests cancelled, or a negative
+ * hd_status. Errors: HD_EINVAL (NULL server, n < 0, NULL tickets with n > 0),
+ * HD_EDEVICE.
+ */
+int hd_serve_cancel(hd_server *srv, int32_t n, const int64_t *tickets);
 
 /* Release the server's device memory and stream. NULL is accepted. */
 void hd_serve_close(hd_server *srv);

@@ -21,11 +21,13 @@ static int64_t ctx_bytes(const hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                            &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                           &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask};
+                           &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale};
     int64_t s = 0;
     for (const DevBuf *b : all) s += (int64_t)b->bytes;
     return s;
 }
+
+static void drop_eigs(hd_ctx *c);
 
 extern "C" {
 
@@ -69,7 +71,7 @@ void hd_destroy(hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                      &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                     &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask};
+                     &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (hipEvent_t e : c->iter_ev)
@@ -171,16 +173,12 @@ int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, cons
     }
     HIP_TRY(hipSetDevice(c->device));
     if (c->n != n) {
-        c->U.release();
-        c->Ub.release();
-        c->UbT.release();
-        for (DevBuf *b : {&c->Usr, &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv}) b->release();
-        c->u_dtype = HD_F32;
-        c->lam.release();
-        c->r = c->rp = 0;
+        drop_eigs(c);
         c->V.release();
         c->Vb.release();
+        c->vscale.release();
         c->d = c->ldv = 0;
+        c->v_dtype = HD_F32;
     }
     HIP_TRY(c->rowptr.ensure((size_t)(n + 1) * sizeof(int64_t)));
     HIP_TRY(c->col.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
@@ -195,37 +193,129 @@ int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, cons
     return HD_OK;
 }
 
+// Drop every form of the loaded eigenpairs: afterwards the context holds
+// none (r = 0), so no query can reach a released U1 buffer.
+static void drop_eigs(hd_ctx *c) {
+    for (DevBuf *b : {&c->U, &c->Ub, &c->UbT, &c->Usr, &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->lam,
+                      &c->uscale})
+        b->release();
+    c->u_dtype = HD_F32;
+    c->r = c->rp = 0;
+    c->ldut = 0;
+    c->us_nnz = 0;
+    c->lam_host.clear();
+}
+
+// Upload FP8 E4M3 codes of U1 (n x r row-major) and their per-component
+// scales: the codes in fragment order item-major (n16 x rp bytes) and
+// component-major (rp x ldut bytes), padding zero, padding scales 1.
+static int upload_eigs_fp8(hd_ctx *c, int r, int rp, const uint8_t *codes, const float *scales) {
+    const int64_t n = c->n, ldut = (n + 63) / 64 * 64, n16 = (n + 15) / 16 * 16;
+    std::vector<uint8_t> im((size_t)n16 * rp, 0), cm((size_t)rp * ldut, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < r; ++k) {
+            const uint8_t q = codes[(size_t)i * r + k];
+            im[hd::frag_offset(i, k, rp / 32)] = q;
+            cm[hd::frag_offset(k, i, ldut / 32)] = q;
+        }
+    std::vector<float> sc((size_t)rp, 1.0f);
+    for (int k = 0; k < r; ++k) sc[(size_t)k] = scales[k];
+    HIP_TRY(c->Ub.ensure(im.size()));
+    HIP_TRY(c->UbT.ensure(cm.size()));
+    HIP_TRY(c->uscale.ensure(sc.size() * sizeof(float)));
+    HIP_TRY(hipMemcpy(c->Ub.p, im.data(), im.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->UbT.p, cm.data(), cm.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->uscale.p, sc.data(), sc.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->ldut = ldut;
+    return HD_OK;
+}
+
+static int load_eigs_dense(hd_ctx *c, int r, int rp, const float *U, int dtype);
+static int upload_descriptors(hd_ctx *c, int d, int ldv, const float *V, int dtype);
+
+// The common tail of the eigenpair loaders: eigenvalues and the form.
+static int finish_eigs(hd_ctx *c, int r, int rp, const double *lambda, int dtype) {
+    std::vector<double> lam((size_t)rp, 0.0);
+    for (int k = 0; k < r; ++k) lam[(size_t)k] = lambda[k];
+    HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
+    HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->lam_host = lam;
+    c->r = r;
+    c->rp = rp;
+    c->u_dtype = dtype;
+    return HD_OK;
+}
+
+int hd_load_eigs_fp8(hd_ctx *c, int32_t r, const uint8_t *codes, const float *col_scale, const double *lambda) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_load_eigs_fp8: NULL context");
+    if (c->n == 0) return fail(HD_ESTATE, "hd_load_eigs_fp8: no graph loaded");
+    if (r < 1 || r > c->n) return fail(HD_EINVAL, "hd_load_eigs_fp8: r=%d not in [1, n]", r);
+    if (!codes || !col_scale || !lambda) return fail(HD_EINVAL, "hd_load_eigs_fp8: NULL array");
+    for (int k = 0; k < r; ++k) {
+        if (!(std::fabs(lambda[k]) <= 1.0 + 1e-6))
+            return fail(HD_EINVAL, "hd_load_eigs_fp8: lambda[%d]=%g outside [-1, 1]", k, lambda[k]);
+        if (!(col_scale[k] > 0.0f) || !std::isfinite(col_scale[k]))
+            return fail(HD_EINVAL, "hd_load_eigs_fp8: col_scale[%d] not positive and finite", k);
+    }
+    const int64_t n = c->n;
+    for (size_t t = 0; t < (size_t)n * r; ++t)
+        if (fp8_e4m3_is_nan(codes[t])) return fail(HD_EINVAL, "hd_load_eigs_fp8: NaN code at %zu", t);
+    HIP_TRY(hipSetDevice(c->device));
+    drop_eigs(c);
+    const int rp = (r + 31) / 32 * 32;
+    int e = upload_eigs_fp8(c, r, rp, codes, col_scale);
+    if (e == HD_OK) e = finish_eigs(c, r, rp, lambda, HD_FP8_E4M3);
+    if (e != HD_OK) drop_eigs(c);
+    return e;
+}
+
 int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int32_t dtype) {
     g_err.clear();
     if (!c) return fail(HD_EINVAL, "hd_load_eigs: NULL context");
     if (c->n == 0) return fail(HD_ESTATE, "hd_load_eigs: no graph loaded");
     if (r < 0 || r > c->n) return fail(HD_EINVAL, "hd_load_eigs: r=%d not in [0, n]", r);
-    if (dtype != HD_F32 && dtype != HD_BF16 && dtype != HD_BF16X2)
+    if (dtype != HD_F32 && dtype != HD_BF16 && dtype != HD_BF16X2 && dtype != HD_FP8_E4M3)
         return fail(HD_EINVAL, "hd_load_eigs: dtype %d not supported", dtype);
-    HIP_TRY(hipSetDevice(c->device));
-    c->U.release();
-    c->Ub.release();
-    c->UbT.release();
-    for (DevBuf *b : {&c->Usr, &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv}) b->release();
-    c->u_dtype = HD_F32;
-    if (r == 0) {
-        c->lam.release();
-        c->r = c->rp = 0;
-        return HD_OK;
-    }
-    if (!U || !lambda) return fail(HD_EINVAL, "hd_load_eigs: NULL array");
-    for (int k = 0; k < r; ++k)
-        // the spectrum of S lies in [-1, 1]; allow eigensolver rounding
-        if (!(std::fabs(lambda[k]) <= 1.0 + 1e-6))
-            return fail(HD_EINVAL, "hd_load_eigs: lambda[%d]=%g outside [-1, 1]", k, lambda[k]);
-    const int rp = (r + 31) / 32 * 32;
     const int64_t n = c->n;
-    for (int64_t i = 0; i < n; ++i)
+    // every check comes before the context is touched: a rejected call leaves
+    // the loaded eigenpairs as they were
+    if (r > 0) {
+        if (!U || !lambda) return fail(HD_EINVAL, "hd_load_eigs: NULL array");
         for (int k = 0; k < r; ++k)
-            if (!std::isfinite(U[(size_t)i * r + k]))
-                return fail(HD_EINVAL, "hd_load_eigs: non-finite U at row %lld", (long long)i);
-    std::vector<double> lam((size_t)rp, 0.0);
-    for (int k = 0; k < r; ++k) lam[(size_t)k] = lambda[k];
+            // the spectrum of S lies in [-1, 1]; allow eigensolver rounding
+            if (!(std::fabs(lambda[k]) <= 1.0 + 1e-6))
+                return fail(HD_EINVAL, "hd_load_eigs: lambda[%d]=%g outside [-1, 1]", k, lambda[k]);
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < r; ++k)
+                if (!std::isfinite(U[(size_t)i * r + k]))
+                    return fail(HD_EINVAL, "hd_load_eigs: non-finite U at row %lld", (long long)i);
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    // from here on a failure (allocation, copy) leaves no eigenpairs loaded
+    drop_eigs(c);
+    if (r == 0) return HD_OK;
+    const int rp = (r + 31) / 32 * 32;
+    const int e = load_eigs_dense(c, r, rp, U, dtype);
+    if (e != HD_OK) {
+        drop_eigs(c);
+        return e;
+    }
+    const int f = finish_eigs(c, r, rp, lambda, dtype);
+    if (f != HD_OK) drop_eigs(c);
+    return f;
+}
+
+// The device copies of a dense U1 (n x r fp32 host, validated) in the form
+// `dtype`; on failure the caller drops what was allocated.
+static int load_eigs_dense(hd_ctx *c, int r, int rp, const float *U, int dtype) {
+    const int64_t n = c->n;
+    if (dtype == HD_FP8_E4M3) {
+        std::vector<uint8_t> codes((size_t)n * r);
+        std::vector<float> sc((size_t)r);
+        fp8_quantize(n, r, U, true, codes.data(), sc.data());
+        return upload_eigs_fp8(c, r, rp, codes.data(), sc.data());
+    }
     if (dtype == HD_F32) {
         std::vector<float> host((size_t)n * rp, 0.f);
         for (int64_t i = 0; i < n; ++i)
@@ -262,14 +352,11 @@ int hd_load_eigs(hd_ctx *c, int32_t r, const float *U, const double *lambda, int
         HIP_TRY(hipMemcpy(c->UbT.p, cm.data(), cm.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
         c->ldut = ldut;
     }
-    HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
-    HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
-    c->lam_host = lam;
-    c->r = r;
-    c->rp = rp;
-    c->u_dtype = dtype;
     return HD_OK;
 }
+
+static int load_eigs_sparse(hd_ctx *c, int32_t r, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                            const float *val, const double *lambda);
 
 int hd_load_eigs_sparse(hd_ctx *c, int32_t r, int64_t nnz, const int64_t *rowptr, const int32_t *col,
                         const float *val, const double *lambda) {
@@ -293,9 +380,16 @@ int hd_load_eigs_sparse(hd_ctx *c, int32_t r, int64_t nnz, const int64_t *rowptr
         if (!(std::fabs(lambda[k]) <= 1.0 + 1e-6))
             return fail(HD_EINVAL, "hd_load_eigs_sparse: lambda[%d]=%g outside [-1, 1]", k, lambda[k]);
     HIP_TRY(hipSetDevice(c->device));
-    c->U.release();
-    c->Ub.release();
-    c->UbT.release();
+    drop_eigs(c);
+    const int e = load_eigs_sparse(c, r, nnz, rowptr, col, val, lambda);
+    if (e != HD_OK) drop_eigs(c);
+    return e;
+}
+
+// The device copies of a validated sparsified U1 (by item and by component).
+static int load_eigs_sparse(hd_ctx *c, int32_t r, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                            const float *val, const double *lambda) {
+    const int64_t n = c->n;
     const int rp = (r + 31) / 32 * 32;
     // by-component copy: counting sort of the entries by component
     std::vector<int64_t> cptr((size_t)rp + 1, 0);
@@ -327,15 +421,54 @@ int hd_load_eigs_sparse(hd_ctx *c, int32_t r, int64_t nnz, const int64_t *rowptr
         HIP_TRY(hipMemcpy(c->Ustr.p, crow.data(), (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c->Ustv.p, cval.data(), (size_t)nnz * sizeof(float), hipMemcpyHostToDevice));
     }
-    std::vector<double> lam((size_t)rp, 0.0);
-    for (int k = 0; k < r; ++k) lam[(size_t)k] = lambda[k];
-    HIP_TRY(c->lam.ensure(lam.size() * sizeof(double)));
-    HIP_TRY(hipMemcpy(c->lam.p, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
-    c->lam_host = lam;
-    c->r = r;
-    c->rp = rp;
     c->us_nnz = nnz;
-    c->u_dtype = HD_SPARSE_F32;
+    return finish_eigs(c, r, rp, lambda, HD_SPARSE_F32);
+}
+
+// Upload FP8 E4M3 descriptor codes (n x d row-major) in fragment order over
+// n16 x ldv bytes (zero padded) and one scale per row.
+static int upload_descriptors_fp8(hd_ctx *c, int d, int ldv, const uint8_t *codes, const float *row_scale) {
+    const int64_t n = c->n, n16 = (n + 15) / 16 * 16;
+    std::vector<uint8_t> host((size_t)n16 * ldv, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int t = 0; t < d; ++t) host[hd::frag_offset(i, t, ldv / 32)] = codes[(size_t)i * d + t];
+    HIP_TRY(c->Vb.ensure(host.size()));
+    HIP_TRY(c->vscale.ensure((size_t)n * sizeof(float)));
+    HIP_TRY(hipMemcpy(c->Vb.p, host.data(), host.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->vscale.p, row_scale, (size_t)n * sizeof(float), hipMemcpyHostToDevice));
+    return HD_OK;
+}
+
+static void drop_descriptors(hd_ctx *c) {
+    c->V.release();
+    c->Vb.release();
+    c->vscale.release();
+    c->d = c->ldv = 0;
+    c->v_dtype = HD_F32;
+}
+
+int hd_load_descriptors_fp8(hd_ctx *c, int32_t d, const uint8_t *codes, const float *row_scale) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_load_descriptors_fp8: NULL context");
+    if (c->n == 0) return fail(HD_ESTATE, "hd_load_descriptors_fp8: no graph loaded");
+    if (d <= 0 || !codes || !row_scale) return fail(HD_EINVAL, "hd_load_descriptors_fp8: bad d or NULL array");
+    const int64_t n = c->n;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(row_scale[i] > 0.0f) || !std::isfinite(row_scale[i]))
+            return fail(HD_EINVAL, "hd_load_descriptors_fp8: row_scale[%lld] not positive and finite", (long long)i);
+    for (size_t t = 0; t < (size_t)n * d; ++t)
+        if (fp8_e4m3_is_nan(codes[t])) return fail(HD_EINVAL, "hd_load_descriptors_fp8: NaN code at %zu", t);
+    HIP_TRY(hipSetDevice(c->device));
+    drop_descriptors(c);
+    const int ldv = (d + 31) / 32 * 32;
+    const int e = upload_descriptors_fp8(c, d, ldv, codes, row_scale);
+    if (e != HD_OK) {
+        drop_descriptors(c);
+        return e;
+    }
+    c->d = d;
+    c->ldv = ldv;
+    c->v_dtype = HD_FP8_E4M3;
     return HD_OK;
 }
 
@@ -344,7 +477,7 @@ int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
     if (!c) return fail(HD_EINVAL, "hd_load_descriptors: NULL context");
     if (c->n == 0) return fail(HD_ESTATE, "hd_load_descriptors: no graph loaded");
     if (d <= 0 || !V) return fail(HD_EINVAL, "hd_load_descriptors: bad d or NULL V");
-    if (dtype != HD_F32 && dtype != HD_BF16)
+    if (dtype != HD_F32 && dtype != HD_BF16 && dtype != HD_FP8_E4M3)
         return fail(HD_EINVAL, "hd_load_descriptors: dtype %d not supported", dtype);
     const int ldv = (d + 31) / 32 * 32;
     const int64_t n = c->n;
@@ -353,8 +486,30 @@ int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
             if (!std::isfinite(V[(size_t)i * d + t]))
                 return fail(HD_EINVAL, "hd_load_descriptors: non-finite V at row %lld", (long long)i);
     HIP_TRY(hipSetDevice(c->device));
-    c->V.release();
-    c->Vb.release();
+    drop_descriptors(c);
+    int e = HD_OK;
+    if (dtype == HD_FP8_E4M3) {
+        std::vector<uint8_t> codes((size_t)n * d);
+        std::vector<float> sc((size_t)n);
+        fp8_quantize(n, d, V, false, codes.data(), sc.data());
+        e = upload_descriptors_fp8(c, d, ldv, codes.data(), sc.data());
+    } else {
+        e = upload_descriptors(c, d, ldv, V, dtype);
+    }
+    if (e != HD_OK) {
+        drop_descriptors(c);
+        return e;
+    }
+    c->d = d;
+    c->ldv = ldv;
+    c->v_dtype = dtype;
+    return HD_OK;
+}
+
+// fp32 (n x ldv, zero padded) or bfloat16 (fragment order over n16 x ldv)
+// device copies of validated descriptors.
+static int upload_descriptors(hd_ctx *c, int d, int ldv, const float *V, int dtype) {
+    const int64_t n = c->n;
     if (dtype == HD_F32) {
         std::vector<float> host((size_t)n * ldv, 0.f);
         for (int64_t i = 0; i < n; ++i)
@@ -372,9 +527,6 @@ int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
         HIP_TRY(c->Vb.ensure(host.size() * sizeof(uint16_t)));
         HIP_TRY(hipMemcpy(c->Vb.p, host.data(), host.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     }
-    c->d = d;
-    c->ldv = ldv;
-    c->v_dtype = dtype;
     return HD_OK;
 }
 
@@ -432,7 +584,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     // product (Q = Qs + alpha / (1 - alpha) U1 L1 U1^T P, Qs = (P - alpha S P) /
     // (1 - alpha)) and U1 C is applied inside the residual update, so Q is
     // never stored; gamma = P^T Qs + alpha / (1 - alpha) (U1^T P)^T L1 (U1^T P).
-    const bool fused = rk > 0 && !sparse && c->u_bf16() && !flt;
+    const bool fused = rk > 0 && !sparse && c->u_mfma() && !flt;
     const int nrb = hd::uc_update_r_blocks(n);
     HIP_TRY(c->X.ensure(vec));
     HIP_TRY(c->R.ensure(vec));
@@ -444,7 +596,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         if (!sparse) HIP_TRY(c->Cpart.ensure((size_t)nchunk * rk * ldb * sizeof(float)));
         HIP_TRY(c->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         HIP_TRY(c->Cs.ensure((size_t)rk * ldb * sizeof(float)));
-        if (c->u_bf16()) {
+        if (c->u_mfma()) {
             HIP_TRY(c->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
             HIP_TRY(c->CsT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
             HIP_TRY(c->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
@@ -483,10 +635,10 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             oi = c->ybuf.as<int32_t>();
             ov = reinterpret_cast<float *>(oi + (size_t)B * ky);
         }
-        if (c->v_dtype == HD_BF16) {
+        if (c->v_dtype != HD_F32) {
             HIP_TRY(c->qsplit.ensure((size_t)2 * hd::sim_qsplit_rows(B) * c->ldv * sizeof(uint16_t)));
-            LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.as<uint16_t>(), c->ldv,
-                                              c->qsplit.as<uint16_t>(), c->sim.as<float>(), lds, s));
+            LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.p, c->ldv, c->qsplit.as<uint16_t>(),
+                                              c->sim.as<float>(), lds, s, c->v_scale()));
         } else {
             LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
         }
@@ -521,15 +673,11 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     }
 
     // ---- step 2: spectral coefficients (and L1 U1^T P for the first product) ----
-    const bool ubf = c->u_bf16();
-    const bool two = c->u_dtype == HD_BF16X2;
+    const bool ubf = c->u_mfma();
     const int64_t *Usr = c->Usr.as<int64_t>(), *Ustp = c->Ustp.as<int64_t>();
     const int32_t *Usc = c->Usc.as<int32_t>(), *Ustr = c->Ustr.as<int32_t>();
     const float *Usv = c->Usv.as<float>(), *Ustv = c->Ustv.as<float>();
     const float *U = c->U.as<float>();
-    const uint16_t *Ub = c->Ub.as<uint16_t>(), *UbT = c->UbT.as<uint16_t>();
-    const uint16_t *Ubl = two ? c->ub_lo() : nullptr;
-    const uint16_t *UbTl = two ? UbT + (size_t)c->rp * c->ldut : nullptr;
     uint16_t *ClT_hi = c->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
     uint16_t *CsT_hi = c->CsT.as<uint16_t>(), *CsT_lo = CsT_hi ? CsT_hi + (size_t)rk * ldb : nullptr;
     // a general filter's g(lambda_k) = h(lambda_k) - h(0) (Appendix A, eq. (2-aux))
@@ -553,10 +701,10 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                                                    o->alpha, ldb, c->Cs.as<float>(), c->Cl.as<float>(), s,
                                                    nullptr, gv));
     } else if (rk > 0) {
-        LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, ubf ? (const void *)Ub : (const void *)U,
-                                                Ubl, ubf ? 1 : 0, c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
+        LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, ubf ? c->Ub.p : (const void *)U, c->ub_lo(),
+                                                c->u_fmt(), c->rp, rk, r_use, c->lam.as<double>(), o->alpha,
                                                 ldb, c->Cs.as<float>(), c->Cl.as<float>(), s, nullptr, gv,
-                                                fused ? c->Dg.as<double>() : nullptr));
+                                                fused ? c->Dg.as<double>() : nullptr, c->u_scale()));
         if (ubf) {
             const hd::IterGuard none{nullptr, 0};
             LAUNCH(K_GATHER, hd::launch_split_t(c->Cs.as<float>(), rk, ldb, CsT_hi, CsT_lo, none, s));
@@ -585,16 +733,17 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                     if (ubf) {
                         uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
                         LAUNCH(K_UT_P, hd::launch_split_pt(n, ldb, P, c->ldut, PTh, PTl, none, s));
-                        LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb,
+                        LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, c->u_comp(), c->ldut, rk, PTh, PTl, ldb,
                                                             c->Cpart.as<float>(), none, s, c->tv(HD_TUNE_UTP_NT, ldb)));
                     } else {
                         LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), none, s));
                     }
                     LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(),
-                                                           r_use, c->Cl.as<float>(), none, s));
+                                                           r_use, c->Cl.as<float>(), none, s, nullptr, 0.0,
+                                                           c->u_scale()));
                     if (ubf) {
                         LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, none, s));
-                        LAUNCH(K_U_C, hd::launch_u_c_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, X, -1.0, Zb,
+                        LAUNCH(K_U_C, hd::launch_u_c_bf16(n, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, X, -1.0, Zb,
                                                           none, s, c->tv(HD_TUNE_UC_NT, ldb)));
                     } else {
                         LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, X, -1.0, Zb, none, s));
@@ -629,11 +778,11 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             if (it > 1) {
                 // L1 U1^T P (P^T split written by the previous iteration's
                 // update) and the eigenvector part of gamma
-                LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb, c->Cpart.as<float>(),
+                LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, c->u_comp(), c->ldut, rk, PTh, PTl, ldb, c->Cpart.as<float>(),
                                                     g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
                 LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(),
                                                        r_use, c->Cl.as<float>(), g, s, c->Dg.as<double>(),
-                                                       o->alpha));
+                                                       o->alpha, c->u_scale()));
                 LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
             }
             LAUNCH(it == 1 ? K_SPMM_Y : K_SPMM,
@@ -642,7 +791,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                                    it == 1 ? ymask : nullptr));
             LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, c->Dg.as<double>(),
                                                   rk));
-            LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,
+            LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,
                                                       st.a, c->part.as<double>(), g, s,
                                                       c->tv(HD_TUNE_UC_NT, ldb)));
             LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), nrb, o->tol, st, g, nact_dev[it & 1],
@@ -673,17 +822,17 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                 if (ubf) {
                     // PT was written by the previous iteration's update_xp
                     uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
-                    LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, UbT, UbTl, c->ldut, rk, PTh, PTl, ldb,
+                    LAUNCH(K_UT_P, hd::launch_ut_p_bf16(n, c->u_comp(), c->ldut, rk, PTh, PTl, ldb,
                                                         c->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
                 } else {
                     LAUNCH(K_UT_P, hd::launch_ut_p(n, U, c->rp, rk, P, ldb, c->Cpart.as<float>(), g, s));
                 }
                 LAUNCH(K_REDUCE_C, hd::launch_reduce_c(nchunk, c->Cpart.as<float>(), rk, ldb, c->lam.as<double>(),
-                                                       r_use, c->Cl.as<float>(), g, s));
+                                                       r_use, c->Cl.as<float>(), g, s, nullptr, 0.0, c->u_scale()));
                 if (ubf) LAUNCH(K_REDUCE_C, hd::launch_split_t(c->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
             }
             if (ubf) {
-                LAUNCH(K_U_C, hd::launch_u_c_bf16(n, Ub, Ubl, c->rp, rk, ClT_hi, ClT_lo, ldb, P, o->alpha,
+                LAUNCH(K_U_C, hd::launch_u_c_bf16(n, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, P, o->alpha,
                                                   c->Z.as<float>(), g, s, c->tv(HD_TUNE_UC_NT, ldb)));
             } else {
                 LAUNCH(K_U_C, hd::launch_u_c(n, U, c->rp, rk, c->Cl.as<float>(), ldb, P, o->alpha, c->Z.as<float>(), g, s));
@@ -750,7 +899,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         if (sparse && rk > 0) {
             LAUNCH(K_COMBINE, hd::launch_sp_combine(n, B, Usr, Usc, Usv, c->Cs.as<float>(), ldb, temporal, xq, n, s));
         } else if (ubf && rk > 0) {
-            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, Ub, Ubl, c->rp, rk, CsT_hi, CsT_lo, ldb, temporal, xq, n,
+            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal, xq, n,
                                                         s, c->tv(HD_TUNE_UC_NT, ldb)));
         } else {
             LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, temporal, xq, n, s));

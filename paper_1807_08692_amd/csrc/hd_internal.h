@@ -69,6 +69,15 @@ inline uint16_t bf16_rne_host(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// OCP FP8 E4M3 (hd_fp8.cpp): round to nearest even with saturation at 448,
+// the value of a code, the NaN codes (0x7F, 0xFF), and the quantizer of a
+// rows x cols row-major matrix with one scale per column or per row (scale =
+// max |a| / 448, 1 for an all-zero line; code = RNE(a / scale)).
+uint8_t fp8_e4m3_rne(float x);
+float fp8_e4m3_value(uint8_t b);
+bool fp8_e4m3_is_nan(uint8_t b);
+void fp8_quantize(int64_t rows, int32_t cols, const float *A, bool per_column, uint8_t *codes, float *scales);
+
 inline int pow2_at_least(int v) {
     int p = 64;
     while (p < v) p <<= 1;
@@ -159,10 +168,12 @@ struct hd_ctx {
     DevBuf rowptr, col, val;
     // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp, rows padded to 16) +
     // UbT (bf16, rp x ldut), both in fragment order (hd::frag_offset); the
-    // two-term form stores the lo terms after the hi terms of each
+    // two-term form stores the lo terms after the hi terms of each; the fp8
+    // form keeps E4M3 codes (one byte per element) in the same two layouts
+    // and one fp32 scale per component in uscale (rp values)
     int r = 0, rp = 0, u_dtype = HD_F32;
     int64_t ldut = 0;
-    DevBuf U, Ub, UbT, lam;
+    DevBuf U, Ub, UbT, lam, uscale;
     // sparsified U1 (SHybrid): by item (CSR) and by component (CSC, rp + 1 pointers)
     DevBuf Usr, Usc, Usv, Ustp, Ustr, Ustv;
     int64_t us_nnz = 0;
@@ -172,7 +183,7 @@ struct hd_ctx {
     // descriptors: V (fp32, N x ldv) or Vb (bf16, N x ldv in fragment order,
     // rows padded to 16)
     int d = 0, ldv = 0, v_dtype = HD_F32;
-    DevBuf V, Vb;
+    DevBuf V, Vb, vscale;  // vscale: one fp32 scale per row of fp8 descriptors
     // solver workspace
     DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, PT, part, scal, xbuf, sim, ybuf, topk, err, qsplit;
     int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
@@ -183,7 +194,11 @@ struct hd_ctx {
     Timing timing;
     int tune[HD_TUNE_NKEYS] = {0, 0, 0};  // launch parameters (0 = default)
 
-    bool u_bf16() const { return u_dtype == HD_BF16 || u_dtype == HD_BF16X2; }
+    // the matrix-core storage forms of U1 (fragment order): bf16, two-term bf16, fp8
+    bool u_mfma() const { return u_dtype == HD_BF16 || u_dtype == HD_BF16X2 || u_dtype == HD_FP8_E4M3; }
+    bool u_fp8() const { return u_dtype == HD_FP8_E4M3; }
+    // per-component scales of the fp8 form (null otherwise)
+    const float *u_scale() const { return u_fp8() ? uscale.as<float>() : nullptr; }
     bool u_sparse() const { return u_dtype == HD_SPARSE_F32; }
     // second bfloat16 terms of the two-term U1 form (null otherwise)
     const uint16_t *ub_lo() const {
@@ -192,6 +207,14 @@ struct hd_ctx {
     const uint16_t *ubt_lo() const {
         return u_dtype == HD_BF16X2 ? UbT.as<uint16_t>() + (size_t)rp * ldut : nullptr;
     }
+    // the stored U1 as the matrix-core kernels' operand: item-major / component-major
+    hd::UOperand u_item() const { return hd::UOperand{Ub.p, ub_lo(), u_fp8()}; }
+    hd::UOperand u_comp() const { return hd::UOperand{UbT.p, ubt_lo(), u_fp8()}; }
+    // storage kind for launch_gather_proj: 0 fp32, 1 bf16 terms, 2 fp8 codes
+    int u_fmt() const { return u_fp8() ? 2 : (u_mfma() ? 1 : 0); }
+    // descriptors: the stored matrix of the similarity kernels (fp32 V, or the
+    // fragment-order bf16 / fp8 Vb) and the fp8 row scales (null otherwise)
+    const float *v_scale() const { return v_dtype == HD_FP8_E4M3 ? vscale.as<float>() : nullptr; }
     // launch parameter `key` for solver width ldb (0 = default when unset or
     // not fitting the width)
     int tv(int key, int ldb) const { return hd::tile_param_ok(tune[key], ldb) ? tune[key] : 0; }

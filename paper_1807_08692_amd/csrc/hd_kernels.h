@@ -31,6 +31,19 @@ __host__ __device__ inline size_t frag_offset(int64_t m, int64_t k, int64_t kt) 
     return (tile * 64 + lane) * 8 + (size_t)(k % 8);
 }
 
+// The stored U1 of the matrix-core forms, in fragment order (frag_offset):
+// bfloat16 bit patterns (lo = null), two bfloat16 terms hi + lo (lo in the
+// same layout), or OCP FP8 E4M3 codes, one byte per element at the same
+// element offsets (fp8 = true). The fp8 form carries one fp32 scale per
+// component (column of U1); the kernels multiply the codes' values, and the
+// scales are applied to the small coefficient matrices (launch_gather_proj,
+// launch_reduce_c), never per element.
+struct UOperand {
+    const void *hi;
+    const void *lo;
+    bool fp8;
+};
+
 // Per-column CG state on the device (all arrays hold ldb entries).
 struct CgState {
     double *rho0, *rho, *a, *beta, *relres;
@@ -92,14 +105,18 @@ hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const flo
                                hipStream_t s);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 // colmap (nullptr = identity, B columns of ldb): y row t -> column colmap[t]
-// U: fp32 item-major N x rp (u_bf16 = 0) or bfloat16 bit patterns in fragment
-// order over N x rp (u_bf16 = 1, value U + U_lo when U_lo is not null: the
-// two-term storage form)
+// U: fp32 item-major N x rp (fmt = 0), bfloat16 bit patterns in fragment
+// order over N x rp (fmt = 1, value U + U_lo when U_lo is not null: the
+// two-term storage form) or FP8 E4M3 codes in fragment order (fmt = 2) with
+// uscale[k] the scale of component k. c = U1^T y is exact for the stored
+// U1 (codes times scales); with uscale, Cs and Cl are written pre-multiplied
+// by uscale (the coefficients of the codes in U1 Cs and U1 Cl) while Dg uses
+// c itself.
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                              const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
+                              const void *U, const void *U_lo, int fmt, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
                               hipStream_t s, const int32_t *colmap = nullptr, const double *gv = nullptr,
-                              double *Dg = nullptr);
+                              double *Dg = nullptr, const float *uscale = nullptr);
 // P = c R + qs Q over n floats (polynomial filter step); qs = 0 does not read Q
 hipError_t launch_filter_axpy(float *P, const float *R, const float *Q, size_t n, double c, double qs,
                               hipStream_t s);
@@ -112,6 +129,8 @@ hipError_t launch_zero_cols(int64_t N, int ldb, float *X, float *R, float *P, co
 // rho0 = rho = y^T y, iteration 0, cap maxit[t] (written to st.maxit)
 hipError_t launch_init_cols(int ldb, const double *part, int nblk, CgState st, const int32_t *cols,
                             const int32_t *maxit, int ncols, hipStream_t s);
+// columns cols[0..ncols) stop: inactive from now on (their vectors untouched)
+hipError_t launch_cancel_cols(CgState st, const int32_t *cols, int ncols, hipStream_t s);
 // Xc (N x ldc node-major) and Csc (rk x ldc) = the columns cols[0..ncols) of X and Cs
 hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *Cs, int rk,
                               const int32_t *cols, int ncols, int ldc, float *Xc, float *Csc,
@@ -137,9 +156,13 @@ hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P
 // Cl = lambda .* sum_c Cpart[c]   (rows k >= r_use zeroed); with Dg also
 // Dg = alpha / (1 - alpha) lambda .* (sum_c Cpart[c])^2 (double, rk x ldb):
 // the eigenvector part of P^T Q when the correction follows the sparse product
+// With uscale (the fp8 form: Cpart holds the products of the codes), the
+// sum of component k is first multiplied by uscale[k] (giving U1^T P), and Cl
+// is written pre-multiplied by uscale[k] once more (the coefficient of the
+// codes in U1 Cl).
 hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
                            int r_use, float *Cl, IterGuard g, hipStream_t s, double *Dg = nullptr,
-                           double alpha = 0.0);
+                           double alpha = 0.0, const float *uscale = nullptr);
 // Z = P + alpha * U Cl
 hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl, int ldb,
                       const float *P, double alpha, float *Z, IterGuard g, hipStream_t s);
@@ -149,9 +172,8 @@ hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, cons
 
 // ---- bfloat16 storage form of the eigenvector and descriptor products
 //      (k_ugemm_bf16.hip); bf16 values are passed as their 16-bit patterns.
-//      U_lo / UT_lo, when not null, hold the second bfloat16 term of the
-//      two-term form (U = U_hi + U_lo) in the same layout. The stored U1
-//      and the descriptors are in fragment order (frag_offset) ----
+//      The stored U1 (UOperand: one or two bfloat16 terms, or FP8 codes) and
+//      the descriptors are in fragment order (frag_offset) ----
 // CT_hi / CT_lo (ldb x rk, bf16, fragment order; rk a multiple of 32) = hi /
 // lo split of C^T (C: rk x ldb fp32).
 // A null g.nact disables the iteration guard.
@@ -164,13 +186,12 @@ hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, uns
 // Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT: the
 // rp x ldut matrix in fragment order, zero past N) and P as its split
 // transpose (PT_hi / PT_lo, pitch ldut)
-hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned short *UT_lo,
-                            int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
+hipError_t launch_ut_p_bf16(int64_t N, UOperand UT, int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
                             int ldb, float *Cpart, IterGuard g, hipStream_t s, int nt = 0,
                             int width = 0);
 // Z = P + alpha U Cl, U item-major (N x rp in fragment order, rows padded to
 // a multiple of 16), Cl given as split transpose
-hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp, int rk,
+hipError_t launch_u_c_bf16(int64_t N, UOperand U, int rp, int rk,
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                            const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
                            int nt = 0);
@@ -179,23 +200,24 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
 // transpose), and part[g][c] = sum over the rows of 128-row block g of the
 // new r^2 (uc_update_r_blocks(N) rows of ldb doubles)
 int uc_update_r_blocks(int64_t N);
-hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp,
-                                   int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
+hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
                                    IterGuard g, hipStream_t s, int nt = 0, int width = 0);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
-hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const unsigned short *U_lo,
-                               int rp, int rk,
+hipError_t launch_combine_bf16(int64_t N, int B, UOperand U, int rp, int rk,
                                const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                const float *X, float *x, int64_t ldx, hipStream_t s, int nt = 0);
 // Tile parameters: a requested value (0 = default) is valid for width ldb
 // when it is one of 1, 2, 4 and divides the width in 64-column units.
 bool tile_param_ok(int v, int ldb);
-// sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv, fragment order); qsplit:
-// scratch for 2 x sim_qsplit_rows(B) x ldv bf16 (the hi / lo parts of q)
+// sim[b][j] = q[b] . V[j], V stored bf16 (N x ldv, fragment order), or as
+// FP8 E4M3 codes in the same order (vscale != null: row j's value is
+// vscale[j] times its codes); qsplit: scratch for 2 x sim_qsplit_rows(B) x
+// ldv bf16 (the hi / lo parts of q)
 inline int sim_qsplit_rows(int B) { return (B + 63) / 64 * 64; }
-hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsigned short *V,
-                           int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s);
+hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const void *V,
+                           int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s,
+                           const float *vscale = nullptr);
 
 // ---- similarity product for the observation vector (k_sim.hip) ----
 // sim[b][j] = sum_t q[b][t] V[j][t]  (q: B x d, row stride d; V: N x ldv)

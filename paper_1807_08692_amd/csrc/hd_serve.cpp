@@ -55,11 +55,18 @@ int64_t bytes_per_column(const hd_ctx *c, int rk, int nchunk, int nblk, int top_
     // the vectors, the partial and full coefficient columns, reduction
     // partials (and the eigenvector part of gamma), the gathered x columns,
     // the split P^T of the bfloat16 forms
-    const bool fused = c->u_bf16() && rk > 0;
+    const bool fused = c->u_mfma() && rk > 0;
     const int64_t nrb = hd::uc_update_r_blocks(c->n);
     const int64_t prow = fused && nrb > nblk ? nrb : nblk;
+    const int64_t kmax = ky > top_k ? ky : top_k;
+    // the top-k scratch of one row (y selection or ranking), and, when the
+    // requests come as descriptors, the row of similarities, the query and
+    // its bfloat16 split
+    const int64_t topk_row = (int64_t)hd::topk_scratch_bytes(1, c->n, (int)kmax);
+    const int64_t desc = c->d > 0 ? 4 * ((c->n + 63) / 64 * 64) + 4 * (int64_t)c->d + 4 * (int64_t)c->ldv : 0;
     return (fused ? 4 : 5) * 4 * c->n + (int64_t)4 * rk * (nchunk + 4) + 8 * prow + (fused ? 8 * rk : 0) +
-           4 * c->n * 2 + (fused ? 4 * c->ldut : 0) + (int64_t)top_k * 8 + (int64_t)ky * 8 + 64;
+           4 * c->n * 2 + (fused ? 4 * c->ldut : 0) + (int64_t)top_k * 8 + (int64_t)ky * 8 + topk_row + desc +
+           64;
 }
 
 // The context's loaded data and layouts; a server refuses to run once they
@@ -68,7 +75,8 @@ std::vector<intptr_t> data_of(const hd_ctx *c) {
     return {(intptr_t)c->n, (intptr_t)c->nnz, (intptr_t)c->r, (intptr_t)c->rp, (intptr_t)c->u_dtype,
             (intptr_t)c->ldut, (intptr_t)c->d, (intptr_t)c->ldv, (intptr_t)c->v_dtype,
             (intptr_t)c->rowptr.p, (intptr_t)c->U.p, (intptr_t)c->Ub.p, (intptr_t)c->UbT.p,
-            (intptr_t)c->lam.p, (intptr_t)c->V.p, (intptr_t)c->Vb.p};
+            (intptr_t)c->lam.p, (intptr_t)c->V.p, (intptr_t)c->Vb.p, (intptr_t)c->uscale.p,
+            (intptr_t)c->vscale.p};
 }
 
 }  // namespace
@@ -135,7 +143,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
                              hipGetErrorString(e_)));                                          \
     } while (0)
     SRV_TRY(hipStreamCreate(&v->s));
-    v->fused = c->u_bf16() && rk > 0;
+    v->fused = c->u_mfma() && rk > 0;
     v->nrb = hd::uc_update_r_blocks(c->n);
     if (v->fused) SRV_TRY(v->Dg.ensure((size_t)rk * ldb * sizeof(double)));
     const size_t vec = (size_t)c->n * ldb * sizeof(float);
@@ -149,7 +157,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
         SRV_TRY(v->Cl.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->Cs.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->ClT.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
-        if (c->u_bf16()) SRV_TRY(v->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
+        if (c->u_mfma()) SRV_TRY(v->PT.ensure((size_t)ldb * c->ldut * 2 * sizeof(uint16_t)));
         SRV_TRY(v->csc.ensure((size_t)rk * ldb * sizeof(float)));
         SRV_TRY(v->cst.ensure((size_t)rk * ldb * 2 * sizeof(uint16_t)));
     }
@@ -213,6 +221,33 @@ int hd_serve_in_use(const hd_server *v) {
     return k;
 }
 
+int hd_serve_cancel(hd_server *v, int32_t n, const int64_t *tickets) {
+    g_err.clear();
+    if (!v) return fail(HD_EINVAL, "hd_serve_cancel: NULL server");
+    if (n < 0 || (n > 0 && !tickets)) return fail(HD_EINVAL, "hd_serve_cancel: bad n or NULL tickets");
+    hd_ctx *c = v->c;
+    std::vector<int32_t> cols;
+    for (int q = 0; q < n; ++q) {
+        if (tickets[q] < 0) continue;
+        for (int t = 0; t < v->ldb; ++t)
+            if (v->ticket[(size_t)t] == tickets[q]) {
+                bool seen = false;
+                for (int32_t k : cols) seen = seen || k == t;
+                if (!seen) cols.push_back(t);
+            }
+    }
+    if (cols.empty()) return 0;
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = v->s;
+    // after the queued steps on the server's stream: the columns stop and
+    // leave; the other columns' arithmetic does not involve them
+    HIP_TRY(hipMemcpyAsync(v->cols.p, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hd::launch_cancel_cols(v->st, v->cols.as<int32_t>(), (int)cols.size(), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int32_t t : cols) v->ticket[(size_t)t] = -1;
+    return (int)cols.size();
+}
+
 void hd_serve_close(hd_server *v) {
     if (!v) return;
     if (v->s) (void)hipStreamSynchronize(v->s);
@@ -241,6 +276,10 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     if (m == 0) return 0;
     for (int t = 0; t < m && max_iter; ++t)
         if (max_iter[t] < 0) return fail(HD_EINVAL, "hd_serve_submit: max_iter[%d] < 0", t);
+    // y ids are checked here, before any column changes
+    for (size_t t = 0; !q_desc && t < (size_t)m * ky; ++t)
+        if (y_ids[t] < 0 || (int64_t)y_ids[t] >= c->n)
+            return fail(HD_EINVAL, "hd_serve_submit: y id %d of request %zu is outside [0, n)", y_ids[t], t / ky);
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = v->s;
     const int64_t N = c->n;
@@ -253,10 +292,10 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
         HIP_TRY(v->sim.ensure((size_t)m * lds * sizeof(float)));
         HIP_TRY(v->topk.ensure(hd::topk_scratch_bytes(m > ldb ? m : ldb, N, ky > v->o.top_k ? ky : v->o.top_k)));
         HIP_TRY(hipMemcpyAsync(v->qbuf.p, q_desc, (size_t)m * c->d * sizeof(float), hipMemcpyHostToDevice, s));
-        if (c->v_dtype == HD_BF16) {
+        if (c->v_dtype != HD_F32) {
             HIP_TRY(v->qsplit.ensure((size_t)2 * hd::sim_qsplit_rows(m) * c->ldv * sizeof(uint16_t)));
-            HIP_TRY(hd::launch_sim_bf16(N, m, c->d, v->qbuf.as<float>(), c->Vb.as<uint16_t>(), c->ldv,
-                                        v->qsplit.as<uint16_t>(), v->sim.as<float>(), lds, s));
+            HIP_TRY(hd::launch_sim_bf16(N, m, c->d, v->qbuf.as<float>(), c->Vb.p, c->ldv, v->qsplit.as<uint16_t>(),
+                                        v->sim.as<float>(), lds, s, c->v_scale()));
         } else {
             HIP_TRY(hd::launch_sim(N, m, c->d, v->qbuf.as<float>(), c->V.as<float>(), c->ldv,
                                    v->sim.as<float>(), lds, s));
@@ -278,15 +317,18 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     HIP_TRY(hd::launch_ynorm_part(m, ky, yi, N, ldb, v->R.as<float>(), v->part.as<double>(), s, cols));
     HIP_TRY(hd::launch_init_cols(ldb, v->part.as<double>(), 1, v->st, cols, v->maxit.as<int32_t>(), m, s));
     if (v->rk > 0) {
-        const bool ubf = c->u_bf16();
-        HIP_TRY(hd::launch_gather_proj(m, ky, yi, yv, N, ubf ? (const void *)c->Ub.p : (const void *)c->U.p,
-                                       c->ub_lo(), ubf ? 1 : 0, c->rp, v->rk, v->r_use, c->lam.as<double>(), v->o.alpha,
-                                       ldb, v->Cs.as<float>(), nullptr, s, cols));
+        const bool ubf = c->u_mfma();
+        HIP_TRY(hd::launch_gather_proj(m, ky, yi, yv, N, ubf ? c->Ub.p : c->U.p, c->ub_lo(), c->u_fmt(), c->rp,
+                                       v->rk, v->r_use, c->lam.as<double>(), v->o.alpha, ldb, v->Cs.as<float>(),
+                                       nullptr, s, cols, nullptr, nullptr, c->u_scale()));
     }
     HIP_TRY(hipMemcpyAsync(v->h + 3 * ldb, v->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (v->h[3 * ldb] != 0) {
-        // undo: the admitted columns stay free (their state is reset on the next admission)
+        // undo: stop the columns just started; they stay free (their state is
+        // reset on the next admission)
+        HIP_TRY(hd::launch_cancel_cols(v->st, cols, m, s));
+        HIP_TRY(hipStreamSynchronize(s));
         return fail(HD_EINVAL, "hd_serve_submit: a y id is outside [0, n)");
     }
     for (int t = 0; t < m; ++t) {
@@ -307,7 +349,7 @@ int hd_serve_step(hd_server *v, int32_t iters) {
     hipStream_t s = v->s;
     const int64_t N = c->n;
     const int ldb = v->ldb, rk = v->rk;
-    const bool ubf = c->u_bf16();
+    const bool ubf = c->u_mfma();
     const hd::IterGuard g{nullptr, 0};
     float *X = v->X.as<float>(), *R = v->R.as<float>(), *P = v->P.as<float>(), *Q = v->Q.as<float>();
     uint16_t *ClT_hi = v->ClT.as<uint16_t>(), *ClT_lo = ClT_hi ? ClT_hi + (size_t)rk * ldb : nullptr;
@@ -326,16 +368,16 @@ int hd_serve_step(hd_server *v, int32_t iters) {
         // the correction goes into the residual update
         uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
         HIP_TRY(hd::launch_split_pt(N, ldb, P, c->ldut, PTh, PTl, g, s, w));
-        HIP_TRY(hd::launch_ut_p_bf16(N, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
+        HIP_TRY(hd::launch_ut_p_bf16(N, c->u_comp(), c->ldut, rk, PTh, PTl, ldb,
                                      v->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, w), w));
         HIP_TRY(hd::launch_reduce_c(v->nchunk, v->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), v->r_use,
-                                    v->Cl.as<float>(), g, s, v->Dg.as<double>(), v->o.alpha));
+                                    v->Cl.as<float>(), g, s, v->Dg.as<double>(), v->o.alpha, c->u_scale()));
         HIP_TRY(hd::launch_split_t(v->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
         HIP_TRY(hd::launch_spmm(N, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, P, Q,
                                 ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, w),
                                 w));
         HIP_TRY(hd::launch_cg_step_a(ldb, v->part.as<double>(), v->rp.nblk, v->st, g, s, v->Dg.as<double>(), rk));
-        HIP_TRY(hd::launch_uc_update_r_bf16(N, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q,
+        HIP_TRY(hd::launch_uc_update_r_bf16(N, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q,
                                             v->o.alpha, R, v->st.a, v->part.as<double>(), g, s,
                                             c->tv(HD_TUNE_UC_NT, w), w));
         HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->nrb, v->o.tol, v->st, g, v->st.nact_part, s));
@@ -348,16 +390,16 @@ int hd_serve_step(hd_server *v, int32_t iters) {
             if (ubf) {
                 uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
                 HIP_TRY(hd::launch_split_pt(N, ldb, P, c->ldut, PTh, PTl, g, s));
-                HIP_TRY(hd::launch_ut_p_bf16(N, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
+                HIP_TRY(hd::launch_ut_p_bf16(N, c->u_comp(), c->ldut, rk, PTh, PTl, ldb,
                                              v->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, ldb)));
             } else {
                 HIP_TRY(hd::launch_ut_p(N, c->U.as<float>(), c->rp, rk, P, ldb, v->Cpart.as<float>(), g, s));
             }
             HIP_TRY(hd::launch_reduce_c(v->nchunk, v->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), v->r_use,
-                                        v->Cl.as<float>(), g, s));
+                                        v->Cl.as<float>(), g, s, nullptr, 0.0, c->u_scale()));
             if (ubf) {
                 HIP_TRY(hd::launch_split_t(v->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
-                HIP_TRY(hd::launch_u_c_bf16(N, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, ClT_hi, ClT_lo, ldb, P, v->o.alpha,
+                HIP_TRY(hd::launch_u_c_bf16(N, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, P, v->o.alpha,
                                             v->Z.as<float>(), g, s, c->tv(HD_TUNE_UC_NT, ldb)));
             } else {
                 HIP_TRY(hd::launch_u_c(N, c->U.as<float>(), c->rp, rk, v->Cl.as<float>(), ldb, P, v->o.alpha,
@@ -404,10 +446,10 @@ int hd_serve_poll(hd_server *v, int32_t max_out, int64_t *tickets, int32_t *ids,
     HIP_TRY(hd::launch_gather_cols(N, ldb, v->X.as<float>(), v->Cs.as<float>(), rk, v->cols.as<int32_t>(), m,
                                    ldc, v->xc.as<float>(), v->csc.as<float>(), s));
     float *xq = v->xq.as<float>();
-    if (rk > 0 && c->u_bf16()) {
+    if (rk > 0 && c->u_mfma()) {
         uint16_t *hi = v->cst.as<uint16_t>(), *lo = hi + (size_t)rk * ldc;
         HIP_TRY(hd::launch_split_t(v->csc.as<float>(), rk, ldc, hi, lo, hd::IterGuard{nullptr, 0}, s));
-        HIP_TRY(hd::launch_combine_bf16(N, m, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, hi, lo, ldc, v->xc.as<float>(), xq,
+        HIP_TRY(hd::launch_combine_bf16(N, m, c->u_item(), c->rp, rk, hi, lo, ldc, v->xc.as<float>(), xq,
                                         N, s, c->tv(HD_TUNE_UC_NT, ldc)));
     } else {
         HIP_TRY(hd::launch_combine(N, m, c->U.as<float>(), c->rp, rk, v->csc.as<float>(), ldc, v->xc.as<float>(),

@@ -55,7 +55,7 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
     const int64_t n = c->n;
     const int ldb = pow2_at_least(batch);
     const int rk = c->rp;
-    const bool ubf = c->u_bf16() && rk > 0;
+    const bool ubf = c->u_mfma() && rk > 0;
     const size_t vec = (size_t)n * ldb * sizeof(float);
     const hd::RowPart rp = hd::make_row_part(n);
     int64_t rc;
@@ -92,11 +92,11 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
                                    c->P.as<float>(), c->Z.as<float>(), c->Q.as<float>(), ldb, 0.99, rp,
                                    c->part.as<double>(), none, s, v);
         case HD_TUNE_UTP_NT:
-            return hd::launch_ut_p_bf16(n, c->UbT.as<uint16_t>(), c->ubt_lo(), c->ldut, rk, PTh, PTl, ldb,
+            return hd::launch_ut_p_bf16(n, c->u_comp(), c->ldut, rk, PTh, PTl, ldb,
                                         c->Cpart.as<float>(), none, s, v);
         default:
             // U C as it runs in CG: fused with the residual update
-            return hd::launch_uc_update_r_bf16(n, c->Ub.as<uint16_t>(), c->ub_lo(), c->rp, rk, CTh, CTl, ldb,
+            return hd::launch_uc_update_r_bf16(n, c->u_item(), c->rp, rk, CTh, CTl, ldb,
                                                c->Q.as<float>(), 0.99, c->Z.as<float>(), c->Dg.as<double>(),
                                                c->part.as<double>(), none, s, v);
         }

@@ -49,34 +49,48 @@ hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-// R, P = y (dense, node-major) from the sparse y of each column. Ids outside
-// [0, N) are skipped and flagged in *err.
-__global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32_t *ids,
-                                                      const float *vals, int64_t N, int ldb,
-                                                      float *R, float *P, int32_t *err,
-                                                      const int32_t *colmap, uint32_t *rowmask) {
-    int idx = blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= B * ky) return;
-    int b = colmap ? colmap[idx / ky] : idx / ky;
-    int id = ids[idx];
-    if (id < 0 || (int64_t)id >= N) {
-        atomicOr(err, 1);
-        return;
+// R, P = y (dense, node-major) from the sparse y of each column; R and P are
+// zero in the columns written. One wave per y row: the lane holding the
+// first occurrence of an id sums the values of all its occurrences in index
+// order and writes the entry (no atomics), so a column's R and P do not
+// depend on timing even when an id repeats. Ids outside [0, N) are skipped
+// and flagged in *err.
+__global__ __launch_bounds__(kBlock) void k_scatter_y(int B, int ky, const int32_t *__restrict__ ids,
+                                                      const float *__restrict__ vals, int64_t N, int ldb,
+                                                      float *__restrict__ R, float *__restrict__ P,
+                                                      int32_t *err, const int32_t *__restrict__ colmap,
+                                                      uint32_t *rowmask) {
+    const int lane = threadIdx.x % kWave;
+    const int t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (t >= B) return;  // whole waves
+    const int b = colmap ? colmap[t] : t;
+    const int32_t *row = ids + (size_t)t * ky;
+    const float *rv = vals + (size_t)t * ky;
+    for (int u = lane; u < ky; u += kWave) {
+        const int32_t id = row[u];
+        if (id < 0 || (int64_t)id >= N) {
+            atomicOr(err, 1);
+            continue;
+        }
+        bool first = true;
+        for (int v = 0; v < u && first; ++v) first = row[v] != id;
+        if (!first) continue;
+        float acc = rv[u];
+        for (int v = u + 1; v < ky; ++v)
+            if (row[v] == id) acc += rv[v];
+        const size_t o = vec_index(N, ldb, id, b);
+        R[o] = acc;
+        P[o] = acc;
+        if (rowmask) atomicOr(&rowmask[id >> 5], 1u << (id & 31));
     }
-    float v = vals[idx];
-    const size_t o = vec_index(N, ldb, id, b);
-    atomicAdd(&R[o], v);
-    atomicAdd(&P[o], v);
-    if (rowmask) atomicOr(&rowmask[id >> 5], 1u << (id & 31));
 }
 
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
                             int ldb, float *R, float *P, int32_t *err, hipStream_t s,
                             const int32_t *colmap, uint32_t *rowmask) {
-    int tot = B * ky;
-    if (tot == 0) return hipSuccess;
-    k_scatter_y<<<(tot + kBlock - 1) / kBlock, kBlock, 0, s>>>(B, ky, ids, vals, N, ldb, R, P, err,
-                                                                colmap, rowmask);
+    if (B <= 0 || ky <= 0) return hipSuccess;
+    const int per = kBlock / kWave;
+    k_scatter_y<<<(B + per - 1) / per, kBlock, 0, s>>>(B, ky, ids, vals, N, ldb, R, P, err, colmap, rowmask);
     return hipGetLastError();
 }
 
@@ -533,29 +547,31 @@ hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s) {
 // Section 4.2, eq. (h-spectral): c = U1^T y is a gather of the k_y rows of U1
 // that y touches. Writes Cs = g(lambda) .* c (the spectral coefficients,
 // g(x) = h(x) - h(0), eq. (aux)) and Cl = lambda .* c, which is L1 U1^T P for
-// the first CG product since P0 = y.
-template <typename UT>
-__device__ __forceinline__ double u_elem(const UT *U, const UT *U_lo, size_t o);
-template <>
-__device__ __forceinline__ double u_elem<float>(const float *U, const float *, size_t o) {
-    return (double)U[o];
-}
-template <>
-__device__ __forceinline__ double u_elem<unsigned short>(const unsigned short *U,
-                                                         const unsigned short *U_lo, size_t o) {
-    double v = (double)__uint_as_float((uint32_t)U[o] << 16);
-    if (U_lo) v += (double)__uint_as_float((uint32_t)U_lo[o] << 16);
+// the first CG product since P0 = y. Storage kinds: fp32 row-major, one or
+// two bfloat16 terms in fragment order, FP8 E4M3 codes in fragment order
+// with one scale per component (applied here: c is the product with the
+// stored U1 itself, and Cs, Cl are written as the coefficients of the codes).
+enum { UF_F32 = 0, UF_BF16 = 1, UF_FP8 = 2 };
+template <int UF>
+__device__ __forceinline__ double u_elem(const void *U, const void *U_lo, size_t o) {
+    if (UF == UF_F32) return (double)reinterpret_cast<const float *>(U)[o];
+    if (UF == UF_FP8)
+        // OCP E4M3 code to fp32 by the gfx950 scaled conversion (scale 1)
+        return (double)__builtin_amdgcn_cvt_scalef32_f32_fp8(
+            (unsigned)reinterpret_cast<const uint8_t *>(U)[o], 1.0f, 0);
+    double v = (double)__uint_as_float((uint32_t)reinterpret_cast<const unsigned short *>(U)[o] << 16);
+    if (U_lo) v += (double)__uint_as_float((uint32_t)reinterpret_cast<const unsigned short *>(U_lo)[o] << 16);
     return v;
 }
 
-template <typename UT>
+template <int UF>
 __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int32_t *ids,
                                                         const float *vals, int64_t N,
-                                                        const UT *U, const UT *U_lo, int rp, int rk,
+                                                        const void *U, const void *U_lo, int rp, int rk,
                                                         int r_use, const double *lam, double alpha,
                                                         int ldb, float *Cs, float *Cl,
                                                         const int32_t *colmap, const double *gv,
-                                                        double *Dg) {
+                                                        double *Dg, const float *uscale) {
     int k = blockIdx.x * kBlock + threadIdx.x;
     int b = blockIdx.y;  // y row; its solver column is colmap[b] (or b)
     if (k >= rk) return;
@@ -566,38 +582,39 @@ __global__ __launch_bounds__(kBlock) void k_gather_proj(int B, int ky, const int
         for (int t = 0; t < ky; ++t) {
             int id = ids[b * ky + t];
             if (id >= 0 && (int64_t)id < N) {
-                // fp32 U is row-major; the bfloat16 forms are in fragment order
-                const size_t o = sizeof(UT) == 4 ? (size_t)id * rp + k : frag_offset(id, k, rp / 32);
-                acc += u_elem<UT>(U, U_lo, o) * (double)vals[b * ky + t];
+                // fp32 U is row-major; the matrix-core forms are in fragment order
+                const size_t o = UF == UF_F32 ? (size_t)id * rp + k : frag_offset(id, k, rp / 32);
+                acc += u_elem<UF>(U, U_lo, o) * (double)vals[b * ky + t];
             }
         }
     }
+    // the fp8 codes' scale: acc becomes the product with the stored U1, and
+    // the coefficients below are those of the codes
+    const double sk = UF == UF_FP8 && k < r_use ? (double)uscale[k] : 1.0;
+    acc *= sk;
     double lk = k < r_use ? lam[k] : 0.0;
     double h = (1.0 - alpha) / (1.0 - alpha * lk);
     // g of a general filter (Appendix A, eq. (2-aux)) when given, else g_alpha
     double g = gv ? (k < r_use ? gv[k] : 0.0) : h - (1.0 - alpha);
-    Cs[(size_t)k * ldb + col] = (float)(g * acc);
-    if (Cl) Cl[(size_t)k * ldb + col] = (float)(lk * acc);
+    Cs[(size_t)k * ldb + col] = (float)(g * acc * sk);
+    if (Cl) Cl[(size_t)k * ldb + col] = (float)(lk * acc * sk);
     // eigenvector part of y^T Q when the correction follows the sparse product
     if (Dg) Dg[(size_t)k * ldb + col] = alpha / (1.0 - alpha) * lk * acc * acc;
 }
 
 hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
-                              const void *U, const void *U_lo, int u_bf16, int rp, int rk, int r_use,
+                              const void *U, const void *U_lo, int fmt, int rp, int rk, int r_use,
                               const double *lam, double alpha, int ldb, float *Cs, float *Cl,
-                              hipStream_t s, const int32_t *colmap, const double *gv, double *Dg) {
+                              hipStream_t s, const int32_t *colmap, const double *gv, double *Dg,
+                              const float *uscale) {
     if (rk == 0) return hipSuccess;
+    if (fmt == UF_FP8 && !uscale) return hipErrorInvalidValue;
     dim3 grid((rk + kBlock - 1) / kBlock, colmap ? B : ldb);
-    if (u_bf16) {
-        k_gather_proj<unsigned short><<<grid, kBlock, 0, s>>>(
-            B, ky, ids, vals, N, reinterpret_cast<const unsigned short *>(U),
-            reinterpret_cast<const unsigned short *>(U_lo), rp, rk, r_use, lam, alpha, ldb, Cs, Cl,
-            colmap, gv, Dg);
-    } else {
-        k_gather_proj<float><<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N,
-                                                     reinterpret_cast<const float *>(U), nullptr, rp,
-                                                     rk, r_use, lam, alpha, ldb, Cs, Cl, colmap, gv, Dg);
-    }
+#define HD_GP(UFV)                                                                                               \
+    k_gather_proj<UFV><<<grid, kBlock, 0, s>>>(B, ky, ids, vals, N, U, U_lo, rp, rk, r_use, lam, alpha, ldb, Cs, \
+                                               Cl, colmap, gv, Dg, uscale)
+    if (fmt == UF_FP8) HD_GP(UF_FP8); else if (fmt == UF_BF16) HD_GP(UF_BF16); else HD_GP(UF_F32);
+#undef HD_GP
     return hipGetLastError();
 }
 
@@ -673,6 +690,23 @@ hipError_t launch_init_cols(int ldb, const double *part, int nblk, CgState st, c
                             const int32_t *maxit, int ncols, hipStream_t s) {
     if (ncols == 0) return hipSuccess;
     k_init_cols<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, part, nblk, st, cols, maxit, ncols);
+    return hipGetLastError();
+}
+
+// Stop columns cols[0..ncols) at once (cancelled requests, or an admission
+// that failed): they take no further part in any iteration. Their vectors
+// are left as they are; the next admission into a column zeroes it.
+__global__ void k_cancel_cols(CgState st, const int32_t *cols, int ncols) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncols) return;
+    const int c = cols[t];
+    st.active[c] = 0;
+    st.a[c] = 0.0;
+}
+
+hipError_t launch_cancel_cols(CgState st, const int32_t *cols, int ncols, hipStream_t s) {
+    if (ncols == 0) return hipSuccess;
+    k_cancel_cols<<<(ncols + 63) / 64, 64, 0, s>>>(st, cols, ncols);
     return hipGetLastError();
 }
 

@@ -142,7 +142,8 @@ hipError_t launch_ut_p(int64_t N, const float *U, int rp, int rk, const float *P
 __global__ __launch_bounds__(kBlock) void k_reduce_c(int nchunk, const float *__restrict__ Cpart,
                                                      int rk, int ldb, const double *lam, int r_use,
                                                      float *__restrict__ Cl, IterGuard ig,
-                                                     double *__restrict__ Dg, double cc) {
+                                                     double *__restrict__ Dg, double cc,
+                                                     const float *__restrict__ uscale) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     __shared__ double sh[4][kWave];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -158,18 +159,23 @@ __global__ __launch_bounds__(kBlock) void k_reduce_c(int nchunk, const float *__
     sh[w][lane] = s0 + s1;
     __syncthreads();
     if (w == 0) {
-        const double sum = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
         const int k = (int)(idx / ldb);
-        Cl[idx] = k < r_use ? (float)(lam[k] * sum) : 0.f;
+        // fp8 codes: the scale of component k turns the codes' product into
+        // U1^T P, and once more makes Cl the coefficient of the codes
+        const double sk = uscale && k < r_use ? (double)uscale[k] : 1.0;
+        const double sum = (((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane]) * sk;
+        Cl[idx] = k < r_use ? (float)(lam[k] * sum * sk) : 0.f;
         if (Dg) Dg[idx] = k < r_use ? cc * lam[k] * sum * sum : 0.0;
     }
 }
 
 hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, const double *lam,
-                           int r_use, float *Cl, IterGuard g, hipStream_t s, double *Dg, double alpha) {
+                           int r_use, float *Cl, IterGuard g, hipStream_t s, double *Dg, double alpha,
+                           const float *uscale) {
     size_t tot = (size_t)rk * ldb;
     const double cc = Dg ? alpha / (1.0 - alpha) : 0.0;
-    k_reduce_c<<<(unsigned)(tot / kWave), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb, lam, r_use, Cl, g, Dg, cc);
+    k_reduce_c<<<(unsigned)(tot / kWave), kBlock, 0, s>>>(nchunk, Cpart, rk, ldb, lam, r_use, Cl, g, Dg, cc,
+                                                          uscale);
     return hipGetLastError();
 }
 

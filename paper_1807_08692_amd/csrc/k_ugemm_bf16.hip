@@ -10,10 +10,17 @@
 // product is done twice (hi and lo) into fp32 accumulators, so the only
 // approximation beyond fp32 is the bfloat16 storage of U1 itself.
 //
-// Two-term form (LO = true): U1 is also stored as U_hi + U_lo, two bfloat16
+// Two-term form (AK_BF16X2): U1 is also stored as U_hi + U_lo, two bfloat16
 // arrays of the same layout (about 16 significant bits), and each product
 // takes the three terms U_hi P_hi + U_hi P_lo + U_lo P_hi (the U_lo P_lo term
 // is below fp32 rounding of the sum and is dropped).
+//
+// FP8 form: U1 is stored as OCP FP8 E4M3 codes in the same fragment order
+// (one byte per element, so a wave's operand tile is half a kilobyte) with
+// one fp32 scale per component. Each lane converts its eight codes to
+// bfloat16 in registers (exact: every E4M3 value is a bfloat16 value) and
+// the products run as in the one-term form; the scales are applied to the
+// small coefficient matrices by the callers.
 //
 // MFMA v_mfma_f32_16x16x32_bf16 operand layout (lane l of 64):
 //   A (16 x 32): row l % 16, k = 8*(l/16) .. +7;  B (32 x 16): col l % 16,
@@ -41,6 +48,30 @@ __device__ __forceinline__ float bf16_to_f(unsigned short h) {
 __device__ __forceinline__ bf16x8 load8(const unsigned short *p) {
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(p));
 }
+
+// Eight OCP FP8 E4M3 codes (consecutive bytes, element 0 in the lowest
+// byte) to eight bfloat16 values by the gfx950 scaled conversion with scale
+// 1, two codes per instruction.
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 w) {
+    const bf16x2v a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.x, 1.0f, false);
+    const bf16x2v b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.x, 1.0f, true);
+    const bf16x2v c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.y, 1.0f, false);
+    const bf16x2v d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w.y, 1.0f, true);
+    return bf16x8{a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
+}
+
+// Storage kinds of the streamed operand: one bfloat16 term, two terms
+// (hi + lo), FP8 E4M3 codes.
+enum { AK_BF16 = 0, AK_BF16X2 = 1, AK_FP8 = 2 };
+// The eight consecutive elements of a lane's operand piece at element offset
+// o (a multiple of 8) of a stored operand of kind AK.
+template <int AK>
+__device__ __forceinline__ bf16x8 load_a8(const void *A, size_t o) {
+    if (AK == AK_FP8) return fp8x8_to_bf16(*reinterpret_cast<const uint2 *>(reinterpret_cast<const uint8_t *>(A) + o));
+    return load8(reinterpret_cast<const unsigned short *>(A) + o);
+}
+static inline int akind(const UOperand &u) { return u.fp8 ? AK_FP8 : (u.lo ? AK_BF16X2 : AK_BF16); }
 
 // ---------------------------------------------------------------------------
 // C^T split: from an fp32 rk x ldb matrix C write CT_hi, CT_lo (ldb x rk
@@ -106,9 +137,9 @@ static inline int tn_rows_rt(int nt) { return nt == 4 ? tn_rows(4) : tn_rows(1);
 // B fragment = B[n + l%16][k + 8(l/16) ..+7], C[m = 4(l/16) + v][n = l%16].
 // In fragment order a wave's B fragment read from LDS is one contiguous
 // kilobyte, lane l at 16 l bytes, so it is free of bank conflicts.
-template <bool LO, int NT, int MT = tn_mt(NT)>
-__device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
-                                         const unsigned short *__restrict__ Al, int64_t kt,
+template <int AK, int NT, int MT = tn_mt(NT)>
+__device__ __forceinline__ void tn_block(const void *__restrict__ A,
+                                         const void *__restrict__ Al, int64_t kt,
                                          int64_t m0, int64_t mend,
                                          const unsigned short *__restrict__ Bh,
                                          const unsigned short *__restrict__ Bl, int64_t ktb,
@@ -125,15 +156,13 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
     // reloads the last step (never used). Loads without branches keep the
     // compiler's wait counts exact, so waiting for the staged B pieces does
     // not also wait for the A prefetch issued after them.
-    const unsigned short *pa[MT];
-    const unsigned short *pal[MT];
+    constexpr bool LO = AK == AK_BF16X2;
+    size_t pa[MT];  // element offsets of this lane's pieces (bytes for fp8 codes)
     const int64_t mtiles = (mend + 15) / 16;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int64_t tb = m0 / 16 + MT * w + mt;
-        const size_t o = ((size_t)(tb < mtiles ? tb : m0 / 16) * (size_t)kt * 64 + (size_t)lane) * 8;
-        pa[mt] = A + o;
-        pal[mt] = LO ? Al + o : nullptr;
+        pa[mt] = ((size_t)(tb < mtiles ? tb : m0 / 16) * (size_t)kt * 64 + (size_t)lane) * 8;
     }
     const int64_t klast = k1 - 32;  // the last K step (K ranges are multiples of 32)
     // B staging: wave w copies lane `lane` of the block's n-tiles w, w + 4,
@@ -147,8 +176,8 @@ __device__ __forceinline__ void tn_block(const unsigned short *__restrict__ A,
         const int64_t kc = k < k1 ? k : klast;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            af[slot][mt] = load8(pa[mt] + (size_t)kc * 16);  // tile kc / 32, 512 apart
-            if (LO) afl[slot][mt] = load8(pal[mt] + (size_t)kc * 16);
+            af[slot][mt] = load_a8<AK>(A, pa[mt] + (size_t)kc * 16);  // tile kc / 32, 512 apart
+            if (LO) afl[slot][mt] = load_a8<AK_BF16>(Al, pa[mt] + (size_t)kc * 16);
         }
     };
     auto fetch_b = [&](int64_t k) {
@@ -261,9 +290,9 @@ hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, uns
 // row stride ldut, items past N zero), N = b (PT rows), K = the chunk's
 // items. Logical tiles: column group fastest, then k group, then row chunk,
 // so the tiles of one chunk run on one XCD and share PT and UT in its L2.
-template <bool LO, int NT>
-__global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__restrict__ UT,
-                                                    const unsigned short *__restrict__ UTl,
+template <int AK, int NT>
+__global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const void *__restrict__ UT,
+                                                    const void *__restrict__ UTl,
                                                     int64_t ldut, int rk,
                                                     const unsigned short *__restrict__ PTh,
                                                     const unsigned short *__restrict__ PTl, int ldb,
@@ -279,7 +308,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
     const int64_t ks = (int64_t)chunk * rc;
     const int64_t ke = ks + rc < kend_all ? ks + rc : kend_all;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(UT, UTl, ldut / 32, m0, rk, PTh, PTl, ldut / 32, nb0, ks, ke, acc);
+    tn_block<AK, NT>(UT, UTl, ldut / 32, m0, rk, PTh, PTl, ldut / 32, nb0, ks, ke, acc);
     float *out = Cpart + (size_t)chunk * rk * ldb;
     const int g = lane / 16, c16 = lane % 16;
 #pragma unroll
@@ -293,8 +322,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_ut_p_tn(const unsigned short *__r
         }
 }
 
-hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned short *UT_lo,
-                            int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
+hipError_t launch_ut_p_bf16(int64_t N, UOperand UT, int64_t ldut, int rk, const unsigned short *PTh, const unsigned short *PTl,
                             int ldb, float *Cpart, IterGuard g, hipStream_t s, int ntr, int width) {
     int64_t rc;
     const int nchunk = ut_p_chunks(N, &rc);
@@ -306,14 +334,17 @@ hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned 
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(width / (64 * nt)) * (unsigned)((rk + tn_rows_rt(nt) - 1) / tn_rows_rt(nt)) *
                           (unsigned)nchunk;
-#define HD_UTP(LOV, NTV)                                                                                       \
-    k_ut_p_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(UT, UT_lo ? UT_lo : UT, ldut, rk, PTh, PTl, ldb, width, rc, kend, \
-                                                Cpart, g)
-    if (UT_lo) {
-        if (nt == 4) HD_UTP(true, 4); else if (nt == 2) HD_UTP(true, 2); else HD_UTP(true, 1);
-    } else {
-        if (nt == 4) HD_UTP(false, 4); else if (nt == 2) HD_UTP(false, 2); else HD_UTP(false, 1);
+#define HD_UTP(AKV, NTV)                                                                                     \
+    k_ut_p_tn<AKV, NTV><<<nblk, kBlock, 0, s>>>(UT.hi, UT.lo ? UT.lo : UT.hi, ldut, rk, PTh, PTl, ldb, width, rc, \
+                                                kend, Cpart, g)
+#define HD_UTP_NT(AKV) \
+    if (nt == 4) HD_UTP(AKV, 4); else if (nt == 2) HD_UTP(AKV, 2); else HD_UTP(AKV, 1)
+    switch (akind(UT)) {
+        case AK_FP8: HD_UTP_NT(AK_FP8); break;
+        case AK_BF16X2: HD_UTP_NT(AK_BF16X2); break;
+        default: HD_UTP_NT(AK_BF16); break;
     }
+#undef HD_UTP_NT
 #undef HD_UTP
     return hipGetLastError();
 }
@@ -322,9 +353,9 @@ hipError_t launch_ut_p_bf16(int64_t N, const unsigned short *UT, const unsigned 
 // Z = P + alpha U Cl: M = items (128 per block), N = solver columns, K = rk;
 // A = U item-major (row stride rp), B = ClT split (ldb x rk). Logical tiles:
 // column group fastest, then 128-row block.
-template <bool LO, int NT>
-__global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned short *__restrict__ U,
-                                                   const unsigned short *__restrict__ Ul, int rp, int rk,
+template <int AK, int NT>
+__global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const void *__restrict__ U,
+                                                   const void *__restrict__ Ul, int rp, int rk,
                                                    const unsigned short *__restrict__ CT_hi,
                                                    const unsigned short *__restrict__ CT_lo, int ldb,
                                                    const float *__restrict__ P, float alpha,
@@ -336,7 +367,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned 
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
+    tn_block<AK, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // branch-free loads (rows past N read row N - 1 and store nothing)
 #pragma unroll
@@ -356,7 +387,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_u_c_tn(int64_t N, const unsigned 
         }
 }
 
-hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp, int rk,
+hipError_t launch_u_c_bf16(int64_t N, UOperand U, int rp, int rk,
                            const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                            const float *P, double alpha, float *Z, IterGuard g, hipStream_t s,
                            int ntr) {
@@ -365,13 +396,16 @@ hipError_t launch_u_c_bf16(int64_t N, const unsigned short *U, const unsigned sh
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
     const float a = (float)alpha;
-#define HD_UC(LOV, NTV) \
-    k_u_c_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, P, a, Z, g)
-    if (U_lo) {
-        if (nt == 4) HD_UC(true, 4); else if (nt == 2) HD_UC(true, 2); else HD_UC(true, 1);
-    } else {
-        if (nt == 4) HD_UC(false, 4); else if (nt == 2) HD_UC(false, 2); else HD_UC(false, 1);
+#define HD_UC(AKV, NTV) \
+    k_u_c_tn<AKV, NTV><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, CT_lo, ldb, P, a, Z, g)
+#define HD_UC_NT(AKV) \
+    if (nt == 4) HD_UC(AKV, 4); else if (nt == 2) HD_UC(AKV, 2); else HD_UC(AKV, 1)
+    switch (akind(U)) {
+        case AK_FP8: HD_UC_NT(AK_FP8); break;
+        case AK_BF16X2: HD_UC_NT(AK_BF16X2); break;
+        default: HD_UC_NT(AK_BF16); break;
     }
+#undef HD_UC_NT
 #undef HD_UC
     return hipGetLastError();
 }
@@ -386,9 +420,9 @@ constexpr int kUcrMt = 2;  // m-tiles per wave of the fused residual update
 // which follows update_r (double arithmetic, a = 0 leaves a stopped column
 // untouched), and the column sums of r^2 go to part, one row of ldb doubles
 // per 128-row group (a block covers one or two groups).
-template <bool LO, int NT, int MT = kUcrMt>
-__global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const unsigned short *__restrict__ U,
-                                                           const unsigned short *__restrict__ Ul, int rp, int rk,
+template <int AK, int NT, int MT = kUcrMt>
+__global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const void *__restrict__ U,
+                                                           const void *__restrict__ Ul, int rp, int rk,
                                                            const unsigned short *__restrict__ CT_hi,
                                                            const unsigned short *__restrict__ CT_lo, int ldb,
                                                            const float *__restrict__ Qs, float cc,
@@ -406,7 +440,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT, MT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
+    tn_block<AK, NT, MT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // r^2 of each 16-row m-tile and column (4 rows per lane, then across the
     // lane groups), summed below over the m-tiles of each 128-row group in
@@ -465,8 +499,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const u
 
 int uc_update_r_blocks(int64_t N) { return (int)((N + 127) / 128); }
 
-hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const unsigned short *U_lo, int rp,
-                                   int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
+hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
                                    IterGuard g, hipStream_t s, int ntr, int width) {
     if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
@@ -476,14 +509,17 @@ hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const uns
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(width / (64 * nt)) * (unsigned)((N + 64 * kUcrMt - 1) / (64 * kUcrMt));
     const float cc = (float)(alpha / (1.0 - alpha));
-#define HD_UR(LOV, NTV)                                                                                   \
-    k_uc_update_r_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, Qs, \
+#define HD_UR(AKV, NTV)                                                                                       \
+    k_uc_update_r_tn<AKV, NTV><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, CT_lo, ldb, Qs, \
                                                        cc, R, a, part, width, g)
-    if (U_lo) {
-        if (nt == 4) HD_UR(true, 4); else if (nt == 2) HD_UR(true, 2); else HD_UR(true, 1);
-    } else {
-        if (nt == 4) HD_UR(false, 4); else if (nt == 2) HD_UR(false, 2); else HD_UR(false, 1);
+#define HD_UR_NT(AKV) \
+    if (nt == 4) HD_UR(AKV, 4); else if (nt == 2) HD_UR(AKV, 2); else HD_UR(AKV, 1)
+    switch (akind(U)) {
+        case AK_FP8: HD_UR_NT(AK_FP8); break;
+        case AK_BF16X2: HD_UR_NT(AK_BF16X2); break;
+        default: HD_UR_NT(AK_BF16); break;
     }
+#undef HD_UR_NT
 #undef HD_UR
     return hipGetLastError();
 }
@@ -492,9 +528,9 @@ hipError_t launch_uc_update_r_bf16(int64_t N, const unsigned short *U, const uns
 // ldc >= B columns of CsT; each wave then writes its tile query-major, one
 // 16-item m-tile at a time through LDS, so that every query's 16 items go
 // out as one 64-byte run.
-template <bool LO, int NT>
-__global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, const unsigned short *__restrict__ U,
-                                                       const unsigned short *__restrict__ Ul, int rp,
+template <int AK, int NT>
+__global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, const void *__restrict__ U,
+                                                       const void *__restrict__ Ul, int rp,
                                                        int rk, const unsigned short *__restrict__ CT_hi,
                                                        const unsigned short *__restrict__ CT_lo, int ldc,
                                                        const float *__restrict__ X, float *__restrict__ x,
@@ -506,7 +542,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
     f32x4 acc[MT][4 * NT];
-    tn_block<LO, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
+    tn_block<AK, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // per m-tile (16 items) and group of four n-tiles (64 queries); the
     // m-tile's loads of X are all issued first (branch-free: rows past N
@@ -545,21 +581,24 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
     }
 }
 
-hipError_t launch_combine_bf16(int64_t N, int B, const unsigned short *U, const unsigned short *U_lo,
-                               int rp, int rk, const unsigned short *CT_hi,
+hipError_t launch_combine_bf16(int64_t N, int B, UOperand U, int rp, int rk, const unsigned short *CT_hi,
                                const unsigned short *CT_lo, int ldb, const float *X, float *x,
                                int64_t ldx, hipStream_t s, int ntr) {
     if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
-#define HD_CB(LOV, NTV) \
-    k_combine_tn<LOV, NTV><<<nblk, kBlock, 0, s>>>(N, B, U, U_lo ? U_lo : U, rp, rk, CT_hi, CT_lo, ldb, X, x, ldx)
-    if (U_lo) {
-        if (nt == 4) HD_CB(true, 4); else if (nt == 2) HD_CB(true, 2); else HD_CB(true, 1);
-    } else {
-        if (nt == 4) HD_CB(false, 4); else if (nt == 2) HD_CB(false, 2); else HD_CB(false, 1);
+#define HD_CB(AKV, NTV) \
+    k_combine_tn<AKV, NTV><<<nblk, kBlock, 0, s>>>(N, B, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, CT_lo, ldb, X, x, \
+                                                   ldx)
+#define HD_CB_NT(AKV) \
+    if (nt == 4) HD_CB(AKV, 4); else if (nt == 2) HD_CB(AKV, 2); else HD_CB(AKV, 1)
+    switch (akind(U)) {
+        case AK_FP8: HD_CB_NT(AK_FP8); break;
+        case AK_BF16X2: HD_CB_NT(AK_BF16X2); break;
+        default: HD_CB_NT(AK_BF16); break;
     }
+#undef HD_CB_NT
 #undef HD_CB
     return hipGetLastError();
 }
@@ -596,10 +635,12 @@ __global__ __launch_bounds__(kBlock) void k_split_q(int B, int B64, int d, int l
 // The logical tiles run
 // over the query tiles fastest, so the tiles of one item range run on one
 // XCD and share V through its L2.
+template <int VK>
 __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ldv,
                                                      const unsigned short *__restrict__ Qh,
                                                      const unsigned short *__restrict__ Ql,
-                                                     const unsigned short *__restrict__ V,
+                                                     const void *__restrict__ V,
+                                                     const float *__restrict__ vscale,
                                                      float *__restrict__ sim, int64_t lds) {
     __shared__ __attribute__((aligned(16))) unsigned short Qs[2][4][512];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -618,12 +659,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
     // jb / 16, queries past B read row b0, a chunk past ldv reloads the last;
     // none of those results is stored), so the compiler's wait counts stay
     // exact.
-    const unsigned short *pv[4];
+    size_t pv[4];  // element offsets (bytes for fp8 codes)
     const int64_t jtiles = (N + 15) / 16;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int64_t tb = jb / 16 + 4 * w + n;
-        pv[n] = V + ((size_t)(tb < jtiles ? tb : jb / 16) * (size_t)(ldv / 32) * 64 + (size_t)lane) * 8;
+        pv[n] = ((size_t)(tb < jtiles ? tb : jb / 16) * (size_t)(ldv / 32) * 64 + (size_t)lane) * 8;
     }
     // Q staging: threads t < 128 copy the hi tiles, the others the lo tiles;
     // thread t copies lane `lane` of m-tiles qm and qm + 2 (qm = (t % 128) /
@@ -636,7 +677,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
     auto fetch_v = [&](int slot, int t0) {
         const int tc = t0 < ldv ? t0 : ldv - 32;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) vf[slot][n] = load8(pv[n] + (size_t)tc * 16);
+        for (int n = 0; n < 4; ++n) vf[slot][n] = load_a8<VK>(V, pv[n] + (size_t)tc * 16);
     };
     auto fetch_q = [&](int t0) {
         const int tc = t0 < ldv ? t0 : ldv - 32;
@@ -674,18 +715,21 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
     for (int n = 0; n < 4; ++n) {
         const int64_t j = jb + 64 * w + 16 * n + c16;
         if (j >= N) continue;
+        // fp8 descriptors: row j's scale (its codes' products are acc)
+        const float sc = VK == AK_FP8 ? vscale[j] : 1.0f;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int b = b0 + 16 * m + 4 * g + v;
-                if (b < B) sim[(size_t)b * lds + j] = acc[m][n][v];
+                if (b < B) sim[(size_t)b * lds + j] = VK == AK_FP8 ? acc[m][n][v] * sc : acc[m][n][v];
             }
     }
 }
 
-hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsigned short *V,
-                           int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s) {
+hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const void *V,
+                           int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s,
+                           const float *vscale) {
     if (ldv % 32 != 0) return hipErrorInvalidValue;
     const int B64 = sim_qsplit_rows(B);
     unsigned short *Qh = qsplit, *Ql = qsplit + (size_t)B64 * ldv;
@@ -694,7 +738,10 @@ hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const unsign
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nblk = (unsigned)((B + 63) / 64) * (unsigned)((N + 255) / 256);
-    k_sim_bf16<<<nblk, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, sim, lds);
+    if (vscale)
+        k_sim_bf16<AK_FP8><<<nblk, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, vscale, sim, lds);
+    else
+        k_sim_bf16<AK_BF16><<<nblk, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, vscale, sim, lds);
     return hipGetLastError();
 }
 

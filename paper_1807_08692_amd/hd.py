@@ -31,6 +31,9 @@ _SIGS = {
     "hd_load_graph": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P, ctypes.c_uint32]),
     "hd_load_eigs": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "hd_load_descriptors": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32]),
+    "hd_load_eigs_fp8": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "hd_load_descriptors_fp8": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "hd_quantize_fp8_e4m3": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "hd_load_eigs_sparse": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
     "hd_compute_eigs": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "hd_query_filter": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32,
@@ -53,6 +56,7 @@ _SIGS = {
     "hd_serve_step": (ctypes.c_int, [_P, ctypes.c_int32]),
     "hd_serve_poll": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
     "hd_serve_close": (None, [_P]),
+    "hd_serve_cancel": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "hd_set_tuning": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "hd_get_tuning": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "hd_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
@@ -80,6 +84,18 @@ def rank_plan(lam, cand_r, *, alpha=0.99, eps=1e-3, lambda_min=-1.0, fixed_ms=No
                               None if im is None else im.ctypes.data_as(_P),
                               it.ctypes.data_as(_P), pm.ctypes.data_as(_P), ctypes.byref(best)))
     return {"iters": it, "pred_ms": pm if fx is not None else None, "best": best.value}
+
+def quantize_fp8(A, per_column: bool):
+    """FP8 E4M3 quantizer of the precision form (hd_quantize_fp8_e4m3, host
+    only): returns (codes uint8 rows x cols, scales fp32 per column or row)."""
+    A = np.ascontiguousarray(A, np.float32)
+    rows, cols = A.shape
+    codes = np.zeros((rows, cols), np.uint8)
+    sc = np.zeros(cols if per_column else rows, np.float32)
+    _check(lib().hd_quantize_fp8_e4m3(int(rows), int(cols), A.ctypes.data_as(_P), 1 if per_column else 0,
+                                      codes.ctypes.data_as(_P), sc.ctypes.data_as(_P)))
+    return codes, sc
+
 
 # Launch parameters (hd_tune_key)
 TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2}
@@ -192,6 +208,14 @@ class Context:
         _check(lib().hd_load_eigs(self._h, r, Up, lp, _DTYPES[dtype]))
         self.r = r
 
+    def load_eigs_fp8(self, codes, col_scale, lam):
+        """U1 given as FP8 E4M3 codes (n x r uint8) and per-column scales."""
+        cd, cdp = _host(codes, np.uint8)
+        sc, scp = _host(col_scale, np.float32)
+        la, lp = _host(lam, np.float64)
+        _check(lib().hd_load_eigs_fp8(self._h, int(cd.shape[1]), cdp, scp, lp))
+        self.r = int(cd.shape[1])
+
     def compute_eigs(self, r, dtype="f32", *, guard=None, degree=12, max_outer=60, tol=1e-9,
                      time_budget_s=0.0, seed=1, lambda_min=-1.0, want_U=False):
         """Top-r eigenpairs of the loaded S on the device (hd_compute_eigs),
@@ -218,6 +242,13 @@ class Context:
         Va, Vp = _host(V, np.float32)
         _check(lib().hd_load_descriptors(self._h, int(Va.shape[1]), Vp, _DTYPES[dtype]))
         self.d = int(Va.shape[1])
+
+    def load_descriptors_fp8(self, codes, row_scale):
+        """Descriptors given as FP8 E4M3 codes (n x d uint8) and per-row scales."""
+        cd, cdp = _host(codes, np.uint8)
+        sc, scp = _host(row_scale, np.float32)
+        _check(lib().hd_load_descriptors_fp8(self._h, int(cd.shape[1]), cdp, scp))
+        self.d = int(cd.shape[1])
 
     def device_bytes(self) -> int:
         return int(lib().hd_device_bytes(self._h))
@@ -430,6 +461,14 @@ class Server:
 
     def step(self, iters: int = 1):
         _check(lib().hd_serve_step(self._h, int(iters)))
+
+    def cancel(self, tickets) -> int:
+        """Cancel admitted, uncollected requests; returns how many were."""
+        t, tp = _host(np.atleast_1d(np.asarray(tickets, np.int64)), np.int64)
+        got = lib().hd_serve_cancel(self._h, int(t.size), tp)
+        if got < 0:
+            _check(got)
+        return got
 
     def poll(self, max_out: int = 1024):
         """Finished requests: dict of arrays keyed tickets, ids, scores,

@@ -4,13 +4,17 @@ eigenvector columns, a batch of 256 queries (solver width 256), autotuned
 launch parameters, four hybrid iterations and seven plain ones. Sampled
 columns are checked against the oracle run on the same y for the same
 number of products, the neighbour selection against FP64 cosines of the
-rounded descriptors, and the ranking against the oracle's sort of the GPU's
-x. The inputs are synthetic and cheap to build: a random symmetric graph
-with about 46 entries per row (the bench graph's density), unit descriptors
-with independent normal entries, and an orthonormal U1 whose columns have
-disjoint supports (the oracle follows the same formulas for any orthonormal
-U1 and eigenvalues in [0, 1), for which the deflated system stays positive
-definite)."""
+rounded descriptors (every sampled column), and the ranking against the
+oracle's sort of the GPU's x. The inputs are synthetic and cheap to build:
+a random symmetric graph with about 46 entries per row (the bench graph's
+density) and unit descriptors with independent normal entries. U1 comes in
+two kinds: orthonormal with disjoint column supports (one entry per row),
+and dense (Gaussian columns scaled by 1 / sqrt(N), every row holding all
+1000 components, so the K = 1024 reductions of U1^T P, U1 C and the combine
+run over dense rows). The oracle follows the same formulas for any U1 with
+eigenvalues in [0, 0.95), for which the deflated system stays positive
+definite; it is given the two-term U1 as stored (hi + lo)."""
+import concurrent.futures as cf
 import numpy as np
 import pytest
 
@@ -73,6 +77,21 @@ def setup():
     return dict(rowptr=rowptr, col=col, s32=s32, g=g, U=U, lam=lam, V=V, Q=Q, comp=comp, vals=vals)
 
 
+def check_y(st, yi, cols):
+    """Neighbour sets of the sampled columns against FP64 cosines of the
+    bfloat16-rounded descriptors (computed in row blocks)."""
+    Qs = st["Q"][list(cols)].astype(np.float64)
+    S = np.empty((N, len(cols)))
+    for a in range(0, N, 100_000):
+        S[a:a + 100_000] = bf16_round(st["V"][a:a + 100_000]).astype(np.float64) @ Qs.T
+    for t, b in enumerate(cols):
+        s = S[:, t]
+        kth = np.sort(s)[::-1][KY - 1]
+        assert np.all(s[yi[b]] >= kth - 1e-5), b
+        assert set(np.nonzero(s > kth + 1e-5)[0].tolist()) <= set(yi[b].tolist()), b
+
+
+@pytest.mark.timeout(600)
 def test_full_size_parity(setup):
     import torch
     from paper_1807_08692_amd import hd
@@ -95,15 +114,10 @@ def test_full_size_parity(setup):
         lo = bf16_round((u32 - hi).astype(np.float32))
         U2 = np.zeros((N, R))
         U2[np.arange(N), st["comp"]] = hi.astype(np.float64) + lo.astype(np.float64)
+        check_y(st, hyb["y_ids"].cpu().numpy(), (0, 131, B - 1))
         for b in (0, 131, B - 1):
             yi = hyb["y_ids"][b].cpu().numpy()
             yv = hyb["y_val"][b].cpu().numpy()
-            # neighbour selection against FP64 cosines of the rounded descriptors
-            if b == 0:
-                s = bf16_round(st["V"]).astype(np.float64) @ st["Q"][b].astype(np.float64)
-                kth = np.sort(s)[::-1][KY - 1]
-                assert np.all(s[yi] >= kth - 1e-5)
-                assert set(np.nonzero(s > kth + 1e-5)[0].tolist()) <= set(yi.tolist())
             assert np.array_equal(pl["y_ids"][b].cpu().numpy(), yi)
             for out, U_, lam_, it in ((hyb, U2, st["lam"], 4), (pl, None, None, 7)):
                 xo, *_ = O.iterate(st["g"], U_, lam_, 0.99, yi, yv, it, 0.0)
@@ -112,5 +126,57 @@ def test_full_size_parity(setup):
                 assert err <= 1e-4, (b, it, err, tune)
                 oid, _ = O.rank(x, 100)
                 assert np.array_equal(out["rank_ids"][b].cpu().numpy(), oid)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_dense_u1(setup):
+    """The metric's configuration with a dense U1 (see the module text)."""
+    import torch
+    from paper_1807_08692_amd import hd
+    dev = torch.device("cuda:0")
+    st = setup
+    rng = np.random.default_rng(77)
+    U = np.empty((N, R), np.float32)
+    for a in range(0, N, 100_000):
+        U[a:a + 100_000] = rng.standard_normal((min(100_000, N - a), R), dtype=np.float32)
+    U *= np.float32(1.0 / np.sqrt(N))
+    lam = np.sort(rng.uniform(0.0, 0.95, size=R))[::-1].copy()
+    ctx = hd.Context(0)
+    try:
+        ctx.load_graph(N, st["rowptr"], st["col"], st["s32"])
+        ctx.load_eigs(U, lam, dtype="bf16x2")
+        ctx.load_descriptors(st["V"], dtype="bf16")
+        tune = ctx.autotune(B, 2)
+        q = torch.from_numpy(st["Q"]).to(dev)
+        out = ctx.query_batch(q, alpha=0.99, tol=0.0, max_iter=4, rank_r=-1, k_y=KY, top_k=100, want_x=True,
+                              want_y=True)
+        torch.cuda.synchronize()
+        cols = (0, 37, 131, 200, B - 1)
+        yi = out["y_ids"].cpu().numpy()
+        yv = out["y_val"].cpu().numpy()
+        x = out["x"].cpu().numpy()
+        rid = out["rank_ids"].cpu().numpy()
+        check_y(st, yi, cols)
+        # the two-term U1 as stored, in double
+        U2 = np.empty((N, R))
+        for a in range(0, N, 100_000):
+            blk = U[a:a + 100_000]
+            hi = bf16_round(blk)
+            U2[a:a + 100_000] = hi.astype(np.float64) + bf16_round((blk - hi).astype(np.float32)).astype(np.float64)
+        del U
+
+        def one(b):
+            xo, *_ = O.iterate(st["g"], U2, lam, 0.99, yi[b], yv[b], 4, 0.0)
+            return xo
+
+        with cf.ThreadPoolExecutor(len(cols)) as ex:
+            xos = list(ex.map(one, cols))
+        for b, xo in zip(cols, xos):
+            err = np.linalg.norm(x[b].astype(np.float64) - xo) / np.linalg.norm(xo)
+            assert err <= 1e-4, (b, err, tune)
+            oid, _ = O.rank(x[b], 100)
+            assert np.array_equal(rid[b], oid), b
     finally:
         ctx.close()

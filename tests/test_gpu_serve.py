@@ -107,7 +107,7 @@ def test_server_matches_batch_and_oracle(fx, ctx, torch_dev):
         assert np.allclose(r["scores"], out["rank_scores"].cpu().numpy()[b], rtol=1e-5, atol=1e-12)
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "bf16x2"])
+@pytest.mark.parametrize("dtype", ["bf16", "bf16x2", "fp8"])
 def test_server_bf16_forms_match_batch(fx, torch_dev, dtype):
     """The server with bfloat16 (one- and two-term) U1: same ranking as the
     batch path with the same storage, scores within fp32 rounding."""
@@ -260,3 +260,98 @@ def test_three_databases_poisson(torch_dev):
             s.close()
         for c in ctxs.values():
             c.close()
+
+
+def test_cancel_leaves_other_columns_bitwise(fx, ctx):
+    """Requests cancelled in the middle of their solves never come back, free
+    their columns at once, and every other request's result is bit for bit
+    what it is in the same run without the cancellations; a request admitted
+    into a freed column gets its result alone."""
+    from paper_1807_08692_amd import hd
+    ids, vals = ys(fx, np.arange(31))
+    kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+
+    def run(cancel):
+        srv = hd.Server(ctx, 32, **kw)
+        res = {}
+        tk = srv.submit(ids[:30], vals[:30])
+        srv.step(2)
+        late = None
+        if cancel:
+            gone = [int(tk[q]) for q in (3, 4, 17, 29)]
+            assert srv.cancel(gone + [10 ** 9]) == 4  # an unknown ticket is ignored
+            assert srv.in_use == 26
+            assert srv.cancel(gone) == 0
+            late = srv.submit(ids[30:31], vals[30:31])
+            assert srv.in_use == 27
+        drain(srv, 27 if cancel else 30, res)
+        assert srv.in_use == 0
+        srv.close()
+        return tk, res, late
+
+    tk0, full, _ = run(False)
+    tk1, part, late = run(True)
+    cancelled = {int(tk1[q]) for q in (3, 4, 17, 29)}
+    assert not cancelled & set(part)
+    for q in range(30):
+        if int(tk1[q]) in cancelled:
+            continue
+        a, b = full[int(tk0[q])], part[int(tk1[q])]
+        assert np.array_equal(a["ids"], b["ids"]) and np.array_equal(a["scores"], b["scores"]), q
+        assert a["iters"] == b["iters"] and a["relres"] == b["relres"], q
+    alone = {}
+    srv = hd.Server(ctx, 32, **kw)
+    t = srv.submit(ids[30:31], vals[30:31])
+    drain(srv, 1, alone)
+    srv.close()
+    assert np.array_equal(alone[int(t[0])]["scores"], part[int(late[0])]["scores"])
+
+
+def test_repeated_y_ids_alone_equals_mix(fx, ctx):
+    """A y whose ids repeat (three and four times: their values add) gives
+    bit for bit the same result alone and in a busy server, and the oracle's
+    result for the summed y."""
+    from paper_1807_08692_amd import hd
+    ids, vals = ys(fx, np.arange(20))
+    ids[5, 1:4] = ids[5, 0]          # one id four times
+    ids[5, 6:9] = ids[5, 5]          # another three times
+    kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+    alone = {}
+    srv = hd.Server(ctx, 32, **kw)
+    t = srv.submit(ids[5:6], vals[5:6])
+    drain(srv, 1, alone)
+    srv.close()
+    a = alone[int(t[0])]
+    for rep in range(2):
+        srv = hd.Server(ctx, 32, **kw)
+        res = {}
+        tk = srv.submit(ids[:5], vals[:5])
+        srv.step(1 + rep)
+        tj = srv.submit(ids[5:20], vals[5:20])
+        drain(srv, 20, res)
+        srv.close()
+        m = res[int(tj[0])]
+        assert np.array_equal(m["ids"], a["ids"]) and np.array_equal(m["scores"], a["scores"])
+        assert m["iters"] == a["iters"]
+    g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
+    xo, *_ = O.iterate(g, fx.U, fx.lam, 0.99, ids[5], vals[5], int(a["iters"]), 0.0)
+    assert np.allclose(a["scores"], xo[a["ids"]], rtol=2e-4, atol=1e-9 * np.abs(xo).max())
+
+
+def test_bad_y_id_admits_nothing(fx, ctx):
+    """A submission with an id outside [0, n) is rejected before any column
+    changes: nothing is admitted and the server keeps working."""
+    from paper_1807_08692_amd import hd
+    ids, vals = ys(fx, np.arange(4))
+    kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+    srv = hd.Server(ctx, 8, **kw)
+    bad = ids.copy()
+    bad[2, 3] = fx.n
+    with pytest.raises(hd.HDError):
+        srv.submit(bad, vals)
+    assert srv.in_use == 0
+    tk = srv.submit(ids, vals)
+    res = {}
+    drain(srv, 4, res)
+    assert set(res) == {int(t) for t in tk}
+    srv.close()
