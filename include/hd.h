@@ -29,6 +29,7 @@
 #ifndef HD_H
 #define HD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -382,6 +383,44 @@ void hd_plan_destroy(hd_plan *plan);
  */
 int hd_rank(hd_ctx *ctx, int32_t B, int64_t n, const float *x, int64_t ldx,
             int32_t K, int32_t *ids_out, float *scores_out, void *stream);
+
+/*
+ * hd_rank without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, result and ordering as hd_rank; its scratch is
+ * a fixed array of the library on each device (64 MiB, held for the life of
+ * the process), so B rows of n items must fit:
+ * hd_rank_noalloc_scratch_bytes(B, n, K) <= 64 MiB (about 260 rows of a
+ * million items). The array is shared by every call on a device and keeps
+ * the last call's contents: calls that overlap on one device (on different
+ * streams, or from different threads) race and must not be issued.
+ * Errors: HD_EINVAL (as hd_rank, or a size above the fixed scratch),
+ * HD_ESTATE (scratch of the context's device not set up), HD_EDEVICE.
+ */
+int hd_rank_noalloc(hd_ctx *ctx, int32_t B, int64_t n, const float *x, int64_t ldx,
+                    int32_t K, int32_t *ids_out, float *scores_out, void *stream);
+/* Scratch bytes hd_rank_noalloc needs for B rows of n items (0 for sizes < 1). */
+size_t hd_rank_noalloc_scratch_bytes(int32_t B, int64_t n, int32_t K);
+
+/*
+ * Memory probes (a measuring aid): the rate the device attains for the
+ * access patterns of the query path's memory-bound kernels, by the library's
+ * own kernels. mode: 0 = read a buffer of `bytes` once (16-byte loads),
+ * 1 = copy it (read + write), 2 = gather whole rows of row_bytes at
+ * pseudo-random row ids over the buffer (as many rows as it holds; the
+ * sparse product's access to P), 3 = the sparse product's own gathers on
+ * the loaded graph without its arithmetic (for every edge, the neighbour's
+ * row of an N x row_bytes matrix; `bytes` ignored). row_bytes: 256, 512 or
+ * 1024 (modes 2, 3). bytes: a multiple of 4096 in [1 MiB, 64 GiB] (modes
+ * 0-2). One warm-up and `reps` timed launches on the null stream; buffers
+ * are allocated for the call and freed. Outputs (host): *ms_out, the mean
+ * milliseconds per launch; *bytes_out, the bytes one launch reads and
+ * writes (mode 3: rows gathered plus the CSR).
+ * Errors: HD_EINVAL (arguments), HD_ESTATE (mode 3 with no graph),
+ * HD_ENOMEM, HD_EDEVICE.
+ */
+int hd_probe_memory(hd_ctx *ctx, int32_t mode, int64_t bytes, int32_t row_bytes, int32_t reps,
+                    double *ms_out, double *bytes_out);
 
 /* Device bytes currently held by the context (graph, eigenpairs,
  * descriptors, solver workspace). Returns 0 for NULL. */

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhd.so")
 SOURCES = ["k_cg.hip", "k_spmm.hip", "k_ugemm.hip", "k_ugemm_bf16.hip", "k_sparse_u.hip", "k_sim.hip", "k_topk.hip",
-           "k_eig.hip", "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp", "hd_eig.cpp", "hd_fp8.cpp"]
+           "k_eig.hip", "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp", "hd_eig.cpp", "hd_fp8.cpp", "hd_noalloc.hip"]
 # ROCm libraries for the eigensolver's dense steps (rocBLAS: Gram matrix,
 # rotations, triangular solve; rocSOLVER: Cholesky, small eigenproblem)
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]

@@ -42,6 +42,10 @@ int hd_create(int device, hd_ctx **out) {
     if (device < 0 || device >= count)
         return fail(HD_EINVAL, "hd_create: device %d not in [0, %d)", device, count);
     HIP_TRY(hipSetDevice(device));
+    {
+        const int e = noalloc_init(device);
+        if (e != HD_OK) return e;
+    }
     hd_ctx *c = new (std::nothrow) hd_ctx();
     if (!c) return fail(HD_ENOMEM, "hd_create: out of host memory");
     c->device = device;

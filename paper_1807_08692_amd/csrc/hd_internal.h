@@ -78,6 +78,10 @@ float fp8_e4m3_value(uint8_t b);
 bool fp8_e4m3_is_nan(uint8_t b);
 void fp8_quantize(int64_t rows, int32_t cols, const float *A, bool per_column, uint8_t *codes, float *scales);
 
+// Device address of the fixed scratch array of hd_rank_noalloc on `device`,
+// taken once per device (hd_noalloc.hip); called by hd_create.
+int noalloc_init(int device);
+
 inline int pow2_at_least(int v) {
     int p = 64;
     while (p < v) p <<= 1;

@@ -42,6 +42,9 @@ _SIGS = {
                                       _P, _P, _P, _P]),
     "hd_rank": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
                                ctypes.c_int32, _P, _P, _P]),
+    "hd_rank_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
+                                       ctypes.c_int32, _P, _P, _P]),
+    "hd_rank_noalloc_scratch_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]),
     "hd_device_bytes": (ctypes.c_int64, [_P]),
     "hd_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "hd_timing_enable_kinds": (ctypes.c_int, [_P, ctypes.c_uint32]),
@@ -365,6 +368,20 @@ class Context:
             scores = torch.empty((B, K), dtype=torch.float32, device=x.device)
         _check(lib().hd_rank(self._h, B, n, _dptr(x), ldx, int(K), _dptr(ids), _dptr(scores),
                              _stream_ptr(stream)))
+        return ids, scores
+
+
+    def rank_noalloc(self, x, K, stream=None, ids=None, scores=None):
+        """hd_rank_noalloc: the top-K of each row of x with the library's fixed
+        scratch (no device allocation in the call)."""
+        import torch
+        B, n = int(x.shape[0]), int(x.shape[1])
+        if ids is None:
+            ids = torch.empty((B, K), dtype=torch.int32, device=x.device)
+        if scores is None:
+            scores = torch.empty((B, K), dtype=torch.float32, device=x.device)
+        _check(lib().hd_rank_noalloc(self._h, B, n, _dptr(x), int(x.stride(0)), int(K), _dptr(ids), _dptr(scores),
+                                     _stream_ptr(stream)))
         return ids, scores
 
 
