@@ -58,8 +58,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="n1m")
     p.add_argument("--forms", default=None,
-                   help="comma list of U1 storage forms to measure, from f32, bf16, bf16x2 and "
-                        "sparseXX (SHybrid, XX%% of U1 zeroed) (default: bf16x2,bf16,sparse99 for "
+                   help="comma list of U1 storage forms to measure, from f32, bf16, bf16x2, fp8 and "
+                        "sparseXX (SHybrid, XX%% of U1 zeroed) (default: bf16x2,bf16,fp8 for "
                         "n1m and n2m, f32 otherwise)")
     p.add_argument("--descriptors", choices=["f32", "bf16"], default=None,
                    help="descriptor storage (default: bf16 for n1m and n2m, f32 otherwise)")
@@ -73,8 +73,10 @@ def parse():
                    help="also run a plain device copy of known size (for counter scaling)")
     p.add_argument("--eps", default="1e-3,1e-2",
                    help="relative-error targets against the exact solution, primary first")
-    p.add_argument("--calib-queries", type=int, default=4,
+    p.add_argument("--calib-queries", type=int, default=256,
                    help="queries of the first batch whose exact solution fixes the iteration counts")
+    p.add_argument("--parity-queries", type=int, default=16,
+                   help="queries of the headline diffusion parity against the oracle (0 skips it)")
     p.add_argument("--calib-max-iter", type=int, default=40)
     p.add_argument("--no-graph", action="store_true",
                    help="time only eager launches (no HIP-graph query plans)")
@@ -95,6 +97,26 @@ def parse():
     p.add_argument("--iters", default=None,
                    help="H,P: fixed CG iteration counts for hybrid and plain CG instead of the "
                         "calibration (for profiling runs)")
+    p.add_argument("--c2-eig-seconds", type=float, default=60.0)
+    p.add_argument("--narrow", type=int, default=1,
+                   help="1: time narrow batches (1..64 queries) through the multi-kernel path and the "
+                        "persistent CG kernel, on the 5,000-item workload and on this one")
+    p.add_argument("--probes", type=int, default=1,
+                   help="1: measure the memory probes (stream, copy, row gathers, the graph's own "
+                        "gathers) beside the roofline")
+    p.add_argument("--c2", type=int, default=None,
+                   help="1: also run the fp32 100,000-item configuration (r = 400, 64 queries, CG to "
+                        "relative residual 1e-5) as a leg of the line (default 1 for n1m)")
+    p.add_argument("--mode", choices=["line", "r-sweep", "serve-dbs"], default="line",
+                   help="line: the benchmark line (default); r-sweep: the space-time sweep on the "
+                        "workload (--workload n2m), iterations per rank for rel-err 1e-3 and the batch "
+                        "time; serve-dbs: three resident databases (n50k, n300k, n1m) under Poisson "
+                        "load")
+    p.add_argument("--r-sweep", default="0,100,400,1000",
+                   help="ranks of the r-sweep mode (prefixes of the largest, which is computed)")
+    p.add_argument("--sweep-steps", type=int, default=5)
+    p.add_argument("--serve-budget-gb", type=float, default=40.0,
+                   help="HBM budget of each server in the serve-dbs mode")
     p.add_argument("--tol-mode", action="store_true",
                    help="time both methods with the workload's residual tolerance instead")
     return p.parse_args()
@@ -102,7 +124,7 @@ def parse():
 
 # U1 storage forms whose CG iteration applies the eigenvector correction after
 # the sparse product, inside the residual update
-FUSED_FORMS = ("bf16", "bf16x2")
+FUSED_FORMS = ("bf16", "bf16x2", "fp8")
 
 
 def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False):
@@ -145,9 +167,17 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.mode == "r-sweep":
+        print(json.dumps(r_sweep_mode(args, hd, W, torch, np)), flush=True)
+        return
+    if args.mode == "serve-dbs":
+        print(json.dumps(serve_dbs_mode(args, hd, W, torch, np)), flush=True)
+        return
     cfg = W.CONFIGS[args.workload]
     big = args.workload in ("n1m", "n2m")
-    forms = [f for f in (args.forms or ("bf16x2,bf16,sparse99" if big else "f32")).split(",") if f]
+    if args.c2 is None:
+        args.c2 = 1 if args.workload == "n1m" else 0
+    forms = [f for f in (args.forms or ("bf16x2,bf16,fp8" if big else "f32")).split(",") if f]
     vprec = args.descriptors or ("bf16" if big else "f32")
     B = cfg.batch
     nbatch = 4
@@ -250,7 +280,7 @@ def main():
             # the hybrid never reaches any target (its error floor lies above):
             # time it at the iteration of its smallest error, plain CG at the
             # loosest target
-            curve = cal["rel_err_by_iter"]["hybrid"]
+            curve = cal["rel_err_by_iter_worst"]["hybrid"]
             i_floor = int(np.argmin(curve))
             ip_ = cal["iters"][str(max(eps_list))]["plain"] or args.calib_max_iter
             plans.append((f"hybrid at its error floor {min(curve):.3g}", None, (i_floor, 0.0), (ip_, 0.0)))
@@ -262,7 +292,7 @@ def main():
         _, _, _, tm_all = timed(-1, ih0, th0, max(3, args.steps // 4), True)
         costed = [k for k, (ms, cnt) in tm_all.items() if cnt and algorithmic_cost(k, 1, 1, 64, 32, 1, 1, 1)]
         dom = max(costed, key=lambda k: tm_all[k][0])
-        su = {"f32": 4, "bf16": 2, "bf16x2": 4}.get(form, 4)
+        su = {"f32": 4, "bf16": 2, "bf16x2": 4, "fp8": 1}.get(form, 4)
         sv = 4 if vprec == "f32" else 2
         kernels = {}
         for kind, (ms, cnt) in tm_all.items():
@@ -351,7 +381,8 @@ def main():
               f"{tgt['hybrid']['iters_max']} CG iterations, plain CG {tgt['plain_cg']['iters_max']})"
               if e0 is not None else (f"fixed iteration counts {args.iters} (hybrid, plain CG)" if args.iters
                                       else f"CG to relative residual {cfg.tol:g}"))
-    form_txt = {"f32": "FP32", "bf16": "BF16", "bf16x2": "two-term BF16 (hi+lo)"}.get(
+    form_txt = {"f32": "FP32", "bf16": "BF16", "bf16x2": "two-term BF16 (hi+lo)",
+                "fp8": "FP8 E4M3 with per-column scales"}.get(
         form0, f"sparsified FP32 (SHybrid, {form0[6:]}% zeros)")
     result = {
         "metric": METRIC,
@@ -380,13 +411,23 @@ def main():
         "plain_cg": tgt["plain_cg"],
         "hybrid_over_plain": tgt["hybrid_over_plain"],
         "forms": {rec["form"]: {"targets": rec["targets"], "calibration": rec["calibration"],
-                                "autotune": rec["autotune"]} for rec in recs},
+                                "autotune": rec["autotune"],
+                                "u1_products": {k: v for k, v in rec["kernels"].items()
+                                                if k in ("ut_p", "u_c", "combine", "gather_proj")}}
+                  for rec in recs},
         "roofline": roof,
         "kernels": chosen["kernels"],
         "fixture": {"eig_max_residual": fx.info["eig_max_residual"], "mean_degree": fx.info["mean_degree"],
                     "isolated": fx.info["isolated"], "lambda_1": float(fx.lam[0]) if fx.lam.size else None,
                     "lambda_r": float(fx.lam[-1]) if fx.lam.size else None},
     }
+
+    if chosen["calibration"] is not None and e0 is not None:
+        acc = chosen["calibration"]["per_query"].get(str(e0), {})
+        result["accuracy"] = {
+            "against": "x* = (1 - alpha)(I - alpha S)^-1 y, FP64 oracle, y formed by the GPU path",
+            "queries": chosen["calibration"]["sample_queries"], "eps": e0,
+            "hybrid": acc.get("hybrid"), "plain_cg": acc.get("plain")}
 
     loaded = [recs[-1]["form"]]
 
@@ -439,6 +480,20 @@ def main():
         ih0, th0 = chosen["hybrid_plan"]
         result["cpu_baseline"] = cpu_baseline(args, cfg, fx, ctx, Qd, B, ih0, th0, torch, np)
 
+    if args.parity_queries > 0 and not form0.startswith("sparse"):
+        use_form(form0)
+        result["diffusion_parity"] = diffusion_parity(args, cfg, fx, ctx, Qd, form0, chosen["hybrid_plan"][0],
+                                                      torch, np)
+
+    if args.probes:
+        result["memory_probes"] = probes_leg(ctx, ldb, roof, np)
+
+    if args.narrow:
+        result["narrow_batches"] = narrow_leg(args, cfg, ctx, Qd, tgt["plain_cg"]["iters_max"], hd, W, torch, np)
+
+    if args.c2:
+        result["plain_fp32_n100k"] = c2_leg(args, hd, torch, np)
+
     ctx.close()
     print(json.dumps(result), flush=True)
 
@@ -477,71 +532,120 @@ def diffusion_only_leg(args, cfg, ctx, Qd, B, nbatch, K, ih, ip, hd, torch):
 _TRUTH = {}
 
 
-def exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np):
-    """x* for the sampled queries of the first batch: the FP64 oracle's tight
-    CG solve of (I - alpha S) x = (1 - alpha) y, with the y the GPU path itself
-    formed (so every method is measured on the diffusion alone). Cached: the
+def host_threads_avail():
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def host_threads(args):
+    """Threads for the host-side oracle work: the requested count, at most
+    the CPUs this process may run on."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return max(1, min(args.cpu_threads, avail))
+
+
+def exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np, ns=None):
+    """x* for the first ns queries of the first batch: the FP64 oracle's tight
+    CG solve of (I - alpha S) x = (1 - alpha) y (relative residual 1e-11), with
+    the y the GPU path itself formed (so every method is measured on the
+    diffusion alone), one query per host thread. Cached per workload: the
     descriptors, hence y, are the same for every U1 form."""
-    if "truths" in _TRUTH:
-        return _TRUTH["truths"], _TRUTH["iters"]
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
-    ns = max(1, min(args.calib_queries, B))
+    ns = max(1, min(ns or args.calib_queries, B))
+    key = cfg.name
+    have = _TRUTH.get(key)
+    if have and len(have["truths"]) >= ns:
+        return have["truths"][:ns], have["iters"][:ns]
     g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
     o = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=0, tol=0.0, rank_r=0, k_y=cfg.k_y,
                         top_k=0, want_y=True)
     torch.cuda.synchronize()
     yi = o["y_ids"][:ns].cpu().numpy()
     yv = o["y_val"][:ns].cpu().numpy().astype(np.float64)
-    truths, exact_iters = [], []
+
+    def solve(b):
+        t, it_t, _, _ = O.cg(g, None, None, cfg.alpha, O.dense_y(fx.n, yi[b], yv[b]), 2000, 1e-11)
+        return t, int(it_t)
+
     t0 = time.time()
-    for b in range(ns):
-        y = O.dense_y(fx.n, yi[b], yv[b])
-        t, it_t, _, _ = O.cg(g, None, None, cfg.alpha, y, 2000, 1e-11)
-        truths.append(t)
-        exact_iters.append(int(it_t))
-    log(f"[calib] exact solutions of {ns} queries in {time.time() - t0:.1f}s (iters {exact_iters})")
-    _TRUTH.update(truths=truths, iters=exact_iters)
+    with ThreadPoolExecutor(max_workers=host_threads(args)) as ex:
+        res = list(ex.map(solve, range(ns)))
+    truths = [t for t, _ in res]
+    exact_iters = [it for _, it in res]
+    log(f"[calib] exact solutions of {ns} queries in {time.time() - t0:.1f}s on {host_threads(args)} "
+        f"threads (iters {min(exact_iters)}..{max(exact_iters)})")
+    _TRUTH[key] = dict(truths=truths, iters=exact_iters)
     return truths, exact_iters
 
 
-def error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np):
+def error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np, keep=False):
     """Relative L2 error against x* of the GPU path at 0, 1, 2, ...
-    iterations (no tolerance), until eps_min is reached or the error stops
-    falling (no 2% gain over four iterations)."""
+    iterations (no tolerance), until eps_min is reached on every query or
+    the worst error stops falling (no 2% gain over four iterations).
+    Returns the worst error per iteration, and with keep=True also every
+    query's error per iteration."""
     ns = len(truths)
-    norms = [np.linalg.norm(t) for t in truths]
-    errs = []
+    norms = np.array([np.linalg.norm(t) for t in truths])
+    worst, per = [], []
     for it in range(0, args.calib_max_iter + 1):
         ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use, k_y=cfg.k_y,
                         top_k=0, want_x=True, out=buf)
-        X = buf["x"][:ns].double().cpu().numpy()
-        err = max(float(np.linalg.norm(X[b] - truths[b]) / norms[b]) for b in range(ns))
-        errs.append(err)
-        if err <= eps_min:
+        X = buf["x"][:ns].cpu().numpy()
+        e = np.array([np.linalg.norm(X[b].astype(np.float64) - truths[b]) for b in range(ns)]) / norms
+        worst.append(float(e.max()))
+        if keep:
+            per.append(e)
+        if worst[-1] <= eps_min:
             break
-        if it >= 6 and err > 0.98 * min(errs[:-4]):
+        if it >= 6 and worst[-1] > 0.98 * min(worst[:-4]):
             break
-    return errs
+    return (worst, per) if keep else worst
+
+
+def top_overlap(ids, truth, K=100):
+    """|top-K of the GPU ∩ top-K of x*| / K, where an item of the GPU's list
+    also counts when its exact score is within 1e-6 max|x*| of the K-th best
+    (near-ties of x* may go either way)."""
+    import numpy as np
+    kth = np.partition(truth, truth.size - K)[truth.size - K]
+    tol = 1e-6 * float(np.abs(truth).max())
+    return float(np.sum(truth[ids[:K]] >= kth - tol)) / K
+
+
+def stats(v, np):
+    v = np.asarray(v, np.float64)
+    return {"max": float(f"{v.max():.4g}"), "p99": float(f"{np.percentile(v, 99):.4g}"),
+            "p50": float(f"{np.percentile(v, 50):.4g}"), "min": float(f"{v.min():.4g}")}
 
 
 def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
     """Fewest CG iterations at which each method is within relative error eps
-    of the exact solution on every sampled query; the GPU results come from
-    runs with a fixed iteration count and no tolerance."""
+    of the exact solution on every sampled query (the first batch's first
+    calib_queries queries); the GPU results come from runs with a fixed
+    iteration count and no tolerance. At those counts: every query's
+    relative error (max, p99, median) and its top-100 overlap with x*."""
     truths, exact_iters = exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np)
     ns = len(truths)
     buf = {"x": torch.empty((B, fx.n), dtype=torch.float32, device=Qd.device)}
     eps_min = min(eps_list)
-    curves, iters, floors, overlap = {}, {}, {}, {}
+    curves, iters, floors, acc = {}, {}, {}, {}
+    per_q = {}
     for name, r_use in (("hybrid", -1), ("plain", 0)):
-        errs = error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np)
+        errs, per = error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np, keep=True)
         curves[name] = [float(f"{e:.4g}") for e in errs]
         floors[name] = min(errs)
+        per_q[name] = per
         for e in eps_list:
             hit = [i for i, v in enumerate(errs) if v <= e]
             iters.setdefault(str(e), {})[name] = hit[0] if hit else None
-        log(f"[calib] {name}: rel-err by iteration {curves[name]}")
-    # top-100 overlap with the exact ranking at the primary counts
+        log(f"[calib] {name}: worst rel-err over {ns} queries by iteration {curves[name]}")
+    # per-query accuracy at each target's counts (and at the hybrid's floor)
     for e in eps_list:
         for name, r_use in (("hybrid", -1), ("plain", 0)):
             it = iters[str(e)][name]
@@ -550,14 +654,442 @@ def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
             oo = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use,
                                  k_y=cfg.k_y, top_k=100)
             ids = oo["rank_ids"][:ns].cpu().numpy()
-            ov = [len(set(ids[b].tolist()) & set(np.argsort(-truths[b], kind="stable")[:100].tolist())) / 100.0
-                  for b in range(ns)]
-            overlap.setdefault(str(e), {})[name] = float(min(ov))
+            ov = [top_overlap(ids[b], truths[b]) for b in range(ns)]
+            acc.setdefault(str(e), {})[name] = {
+                "iters": it, "rel_err": stats(per_q[name][it], np),
+                "top100_overlap": {"min": min(ov), "p1": float(np.percentile(ov, 1)),
+                                   "mean": round(float(np.mean(ov)), 4)}}
     del buf
-    return {"sample_queries": ns, "exact_solve": "FP64 oracle CG on (I - alpha S), relative residual 1e-11",
-            "exact_solve_iters": exact_iters, "rel_err_by_iter": curves,
+    return {"sample_queries": ns, "exact_solve": "FP64 oracle CG on (I - alpha S), relative residual 1e-11, "
+                                                 "one query per host thread",
+            "exact_solve_iters": {"min": min(exact_iters), "max": max(exact_iters)},
+            "rel_err_by_iter_worst": curves,
             "error_floor": {k: float(f"{v:.4g}") for k, v in floors.items()},
-            "iters": iters, "top100_overlap_min": overlap}
+            "iters": iters, "per_query": acc}
+
+
+def represented_u(fx, form, np):
+    """U1 as the GPU stores it, in double: fp32, bfloat16 (RNE), the two-term
+    hi + lo form, or the FP8 codes' values times their column scales (the
+    library's own host quantizer, hd_quantize_fp8_e4m3, gives the codes)."""
+    U = fx.U
+    if form == "f32":
+        return np.ascontiguousarray(U, np.float64)
+
+    def bf16(a):
+        u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+        return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32) << 16).view(np.float32)
+
+    out = np.empty(U.shape, np.float64)
+    if form == "fp8":
+        from paper_1807_08692_amd import hd
+        codes, sc = hd.quantize_fp8(U, True)
+        c = codes.astype(np.int64)
+        e = (c >> 3) & 15
+        m = c & 7
+        val = np.where(e == 0, m * 2.0 ** -9, 2.0 ** (e - 7.0) * (1.0 + m / 8.0))
+        return np.where(c & 0x80, -val, val) * sc.astype(np.float64)[None, :]
+    for a in range(0, U.shape[0], 65536):
+        blk = U[a:a + 65536]
+        hi = bf16(blk)
+        out[a:a + 65536] = hi
+        if form == "bf16x2":
+            out[a:a + 65536] += bf16((blk - hi).astype(np.float32))
+    return out
+
+
+def diffusion_parity(args, cfg, fx, ctx, Qd, form, iters, torch, np):
+    """Parity of the diffusion at the headline configuration: the GPU's x for
+    the first queries of the first batch (hybrid, the headline iteration
+    count) against the FP64 oracle's iterate fed the GPU's own y and U1 as
+    the GPU stores it (represented_u), one query per host thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    nq = max(1, min(args.parity_queries, cfg.batch))
+    o = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=iters, tol=0.0, rank_r=-1, k_y=cfg.k_y,
+                        top_k=100, want_x=True, want_y=True)
+    torch.cuda.synchronize()
+    yi = o["y_ids"][:nq].cpu().numpy()
+    yv = o["y_val"][:nq].cpu().numpy()
+    X = o["x"][:nq].cpu().numpy()
+    ri = o["rank_ids"][:nq].cpu().numpy()
+    t0 = time.time()
+    Ur = represented_u(fx, form, np)
+    g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
+
+    def one(b):
+        xo, *_ = O.iterate(g, Ur, fx.lam, cfg.alpha, yi[b], yv[b], iters, 0.0)
+        oid, _ = O.rank(X[b], 100)
+        return (float(np.linalg.norm(X[b].astype(np.float64) - xo) / np.linalg.norm(xo)),
+                bool(np.array_equal(ri[b], oid)))
+
+    with ThreadPoolExecutor(max_workers=host_threads(args)) as ex:
+        res = list(ex.map(one, range(nq)))
+    errs = [e for e, _ in res]
+    log(f"[parity] {nq} queries, U1 {form}, {iters} iterations: max rel err {max(errs):.3e} "
+        f"({time.time() - t0:.1f}s)")
+    return {"queries": nq, "form": form, "iters": iters,
+            "oracle": "FP64 iterate (spectral term + CG, same iteration count) on the GPU's y and the "
+                      "stored U1 in double",
+            "rel_err": [float(f"{e:.3e}") for e in errs], "max_rel_err": float(f"{max(errs):.3e}"),
+            "bar": 1e-4, "within_bar": bool(max(errs) <= 1e-4),
+            "top100_equals_oracle_sort_of_gpu_x": all(k for _, k in res)}
+
+
+def c2_leg(args, hd, torch, np):
+    """The plain fp32 configuration: 100,000 items, d = 2048, r = 400 fp32
+    eigenvectors and fp32 descriptors, batches of 64 queries, CG to relative
+    residual 1e-5, for the hybrid (r = 400) and plain CG; eager launches and
+    HIP-graph plans; every query's relative error against x* on the first
+    batch (64 exact solutions); the rates of the fp32 matrix-core products
+    from per-kernel events."""
+    from paper_1807_08692_amd import workload as W
+    cfg = W.CONFIGS["n100k"]
+    B, nb = cfg.batch, 2
+    t0 = time.time()
+    fx = W.build_fixture(cfg, n_queries=B * nb, prefer_gpu=True, eig_time_budget=args.c2_eig_seconds,
+                         log=lambda m: log("[n100k fixture]", m))
+    ctx = hd.Context(0)
+    ctx.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    ctx.load_eigs(fx.U, fx.lam, dtype="f32")
+    ctx.load_descriptors(fx.V, dtype="f32")
+    Qd = torch.from_numpy(fx.Q.reshape(nb, B, cfg.d)).to(torch.device("cuda:0"))
+    torch.cuda.synchronize()
+    log(f"[n100k] fixture and load {time.time() - t0:.1f}s, nnz {fx.nnz}, eig max residual "
+        f"{fx.info['eig_max_residual']:.2e}")
+    kw = dict(alpha=cfg.alpha, max_iter=cfg.max_iter, tol=cfg.tol, k_y=cfg.k_y, top_k=100)
+    steps = max(args.steps, 10)
+    out = {"workload": f"vMF mixture N={cfg.n} d={cfg.d} clusters={cfg.clusters} kappa={cfg.kappa:g}, reciprocal "
+                       f"kNN k={cfg.k} (nnz={fx.nnz}), alpha={cfg.alpha}, U1 FP32 r={cfg.r}, descriptors FP32, "
+                       f"batch {B}, k_y={cfg.k_y}, CG to relative residual {cfg.tol:g}",
+           "eig_max_residual": fx.info["eig_max_residual"]}
+    truths, _ = exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np, ns=B)
+    for name, r_use in (("hybrid", -1), ("plain_cg", 0)):
+        for w in range(max(1, args.warmup)):
+            ctx.query_batch(Qd[w % nb], rank_r=r_use, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its = []
+        for k in range(steps):
+            o = ctx.query_batch(Qd[k % nb], rank_r=r_use, **kw)
+            its.append(o["iters"].copy())
+        torch.cuda.synchronize()
+        eager = time.perf_counter() - t1
+        pl = hd.Plan(ctx, B, "descriptors", rank_r=r_use, **kw)
+        for w in range(max(1, args.warmup)):
+            pl.run(Qd[w % nb])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(steps):
+            pl.run(Qd[k % nb])
+        torch.cuda.synchronize()
+        graph = time.perf_counter() - t1
+        pl.close()
+        o = ctx.query_batch(Qd[0], rank_r=r_use, want_x=True, **kw)
+        torch.cuda.synchronize()
+        X = o["x"].cpu().numpy()
+        errs = [float(np.linalg.norm(X[b].astype(np.float64) - truths[b]) / np.linalg.norm(truths[b]))
+                for b in range(B)]
+        ids = o["rank_ids"].cpu().numpy()
+        ov = [top_overlap(ids[b], truths[b]) for b in range(B)]
+        best = min(eager, graph)
+        its = np.concatenate(its)
+        out[name] = {"queries_per_s": round(B * steps / best, 2), "ms_per_batch": round(1e3 * best / steps, 3),
+                     "launch": "graph" if graph < eager else "eager",
+                     "eager_ms_per_batch": round(1e3 * eager / steps, 3),
+                     "graph_ms_per_batch": round(1e3 * graph / steps, 3),
+                     "iters_mean": float(its.mean()), "iters_max": int(its.max()),
+                     "rel_err_vs_exact": stats(errs, np),
+                     "top100_overlap": {"min": min(ov), "mean": round(float(np.mean(ov)), 4)}}
+        log(f"[n100k] {name}: {out[name]['ms_per_batch']:.2f} ms per batch, {its.mean():.1f} it, "
+            f"max rel err {max(errs):.2e}")
+    out["hybrid_over_plain"] = round(out["hybrid"]["queries_per_s"] / out["plain_cg"]["queries_per_s"], 3)
+    # the fp32 matrix-core products of the hybrid, from per-kernel events
+    ldb = 64
+    rk = (cfg.r + 31) // 32 * 32
+    nchunk = -(-fx.n // max(256, ((-(-fx.n // 256)) + 63) // 64 * 64))
+    ctx.timing_enable(True)
+    for k in range(5):
+        ctx.query_batch(Qd[k % nb], rank_r=-1, **kw)
+    torch.cuda.synchronize()
+    tm = ctx.timing()
+    ctx.timing_enable(False)
+    kern = {}
+    for kind in ("ut_p", "u_c", "spmm", "combine", "sim"):
+        ms, cnt = tm.get(kind, (0.0, 0))
+        if not cnt:
+            continue
+        by, fl = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, 4, False)
+        avg = ms / cnt * 1e-3
+        kern[kind] = {"avg_us": round(avg * 1e6, 2), "GB_s": round(by / avg / 1e9, 1),
+                      "TFLOP_s": round(fl / avg / 1e12, 2)}
+        if kind in ("ut_p", "u_c", "combine", "sim"):
+            kern[kind]["frac_of_fp32_mfma_peak"] = round(fl / avg / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4)
+    out["kernels"] = kern
+    # the on-device eigensolver on this graph (the off-line input of the
+    # hybrid): r = 400 leading eigenpairs, its time and residuals; the
+    # library's pairs are then loaded in place of the workload's
+    t1 = time.perf_counter()
+    ev = ctx.compute_eigs(cfg.r, "f32", tol=1e-9, max_outer=60, seed=11, lambda_min=-1.0, want_U=False)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t1
+    out["eigensolver"] = {"r": cfg.r, "seconds": round(secs, 2), "max_residual": float(f"{ev['resid'].max():.3e}"),
+                          "max_abs_eigenvalue_diff_vs_workload": float(f"{np.abs(ev['lam'] - fx.lam).max():.3e}"),
+                          "note": "Chebyshev-filtered subspace iteration in FP64: sparse products, recurrence and "
+                                  "the N x m Gram and rotation products in the library's kernels (FP64 matrix "
+                                  "cores); Cholesky, its inverse and the m x m eigenproblem in rocSOLVER"}
+    log(f"[n100k] eigensolver r={cfg.r}: {secs:.1f}s, max residual {ev['resid'].max():.2e}")
+    ctx.close()
+    return out
+
+
+def r_sweep_mode(args, hd, W, torch, np):
+    """Space-time sweep (the batched configuration: 2,000,000 items, d = 512,
+    k = 30, batches of 1,024 queries, U1 in bfloat16): for each rank r (a
+    prefix of the computed eigenpairs), the fewest CG iterations whose result
+    is within relative error 1e-3 of x* on every sampled query, and the batch
+    time there (eager launches and HIP-graph plans), beside plain CG (r = 0)."""
+    ranks = sorted({int(x) for x in args.r_sweep.split(",") if x.strip()})
+    cfg = W.CONFIGS[args.workload]
+    rmax = max(ranks)
+    B = cfg.batch
+    t0 = time.time()
+    fx = W.build_fixture(cfg, n_queries=B, r=rmax, prefer_gpu=True, eig_time_budget=args.eig_seconds,
+                         log=lambda m: log("[fixture]", m), cache_dir=args.fixture_cache)
+    dev = torch.device("cuda:0")
+    ctx = hd.Context(0)
+    ctx.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    ctx.load_descriptors(fx.V, dtype="bf16")
+    if rmax > 0:
+        ctx.load_eigs(fx.U, fx.lam, dtype=args.forms or "bf16")
+    Qd = torch.from_numpy(fx.Q.reshape(1, B, cfg.d)).to(dev)
+    torch.cuda.synchronize()
+    log(f"[sweep] fixture and load {time.time() - t0:.1f}s, nnz {fx.nnz}, eig max residual "
+        f"{fx.info['eig_max_residual']:.2e}")
+    if not args.no_autotune:
+        ctx.autotune(B, 2)
+    truths, _ = exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np, ns=min(args.calib_queries, 64))
+    buf = {"x": torch.empty((B, fx.n), dtype=torch.float32, device=dev)}
+    eps = 1e-3
+    rows = []
+    for r in ranks:
+        errs = error_curve(args, cfg, ctx, Qd, truths, r, eps, buf, np)
+        hit = [i for i, v in enumerate(errs) if v <= eps]
+        it = hit[0] if hit else int(np.argmin(errs))
+        kw = dict(alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r, k_y=cfg.k_y, top_k=100)
+        for w in range(max(1, args.warmup)):
+            ctx.query_batch(Qd[0], **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(args.sweep_steps):
+            ctx.query_batch(Qd[0], **kw)
+        torch.cuda.synchronize()
+        eager = (time.perf_counter() - t1) / args.sweep_steps
+        pl = hd.Plan(ctx, B, "descriptors", **kw)
+        pl.run(Qd[0])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(args.sweep_steps):
+            pl.run(Qd[0])
+        torch.cuda.synchronize()
+        graph = (time.perf_counter() - t1) / args.sweep_steps
+        pl.close()
+        best = min(eager, graph)
+        rows.append({"r": r, "iters": it, "reached": bool(hit), "error_floor": float(f"{min(errs):.4g}"),
+                     "ms_per_batch": round(1e3 * best, 3), "queries_per_s": round(B / best, 2),
+                     "eager_ms": round(1e3 * eager, 3), "graph_ms": round(1e3 * graph, 3),
+                     "u1_bytes": 2 * 2 * fx.n * ((r + 31) // 32 * 32)})
+        log(f"[sweep] r={r}: {it} it ({'reached' if hit else 'floor'} {min(errs):.2e}), "
+            f"{1e3 * best:.1f} ms per batch")
+    ctx.close()
+    return {"mode": "r-sweep", "workload": f"vMF mixture N={cfg.n} d={cfg.d} clusters={cfg.clusters} "
+                                           f"kappa={cfg.kappa:g}, reciprocal kNN k={cfg.k} (nnz={fx.nnz}), "
+                                           f"alpha={cfg.alpha}, batch {B}, k_y={cfg.k_y}, U1 "
+                                           f"{args.forms or 'bf16'}, descriptors BF16",
+            "eps": eps, "sample_queries": len(truths), "eig_max_residual": fx.info["eig_max_residual"],
+            "rows": rows}
+
+
+def serve_dbs_mode(args, hd, W, torch, np):
+    """The serving configuration: three resident databases (50,000 items with
+    r = 200, 300,000 with r = 400, 1,000,000 with r = 1000; d = 2048, k = 50,
+    two-term bfloat16 U1, bfloat16 descriptors) on one device, each behind a
+    continuous-batching server whose column count the HBM budget sets (at
+    most 512). Seeded Poisson arrivals at each offered rate, routed uniformly
+    to the databases, per-request iteration caps drawn from 5..20; latency
+    from arrival to result, per rate and per database."""
+    from paper_1807_08692_amd import serve
+    names = ("n50k", "n300k", "n1m")
+    ctxs, servers, fxs = {}, {}, {}
+    t0 = time.time()
+    budget = int(args.serve_budget_gb * (1 << 30))
+    for name in names:
+        cfg = W.CONFIGS[name]
+        fx = W.build_fixture(cfg, n_queries=256, prefer_gpu=True, eig_time_budget=args.eig_seconds,
+                             log=lambda m, n_=name: log(f"[{n_} fixture]", m))
+        c = hd.Context(0)
+        c.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+        c.load_eigs(fx.U, fx.lam, dtype="bf16x2")
+        c.load_descriptors(fx.V, dtype="bf16")
+        if not args.no_autotune:
+            c.autotune(256, 2)
+        ctxs[name] = c
+        servers[name] = hd.Server(c, 512, hbm_budget_bytes=budget, alpha=cfg.alpha, max_iter=20, tol=0.0,
+                                  rank_r=-1, k_y=cfg.k_y, top_k=100)
+        fxs[name] = fx
+        log(f"[serve-dbs] {name}: N={fx.n} r={cfg.r} nnz={fx.nnz}, {servers[name].slots} columns, "
+            f"{time.time() - t0:.1f}s")
+    rates = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
+    rng = np.random.default_rng(77)
+    warm = {n: [serve.Request(i, 0.0, n, q_desc=fxs[n].Q[i], max_iter=5) for i in range(4)] for n in names}
+    serve.run(servers, [r for v in warm.values() for r in v])
+    out = {"mode": "serve-dbs", "databases": {n: {"N": fxs[n].n, "r": W.CONFIGS[n].r, "nnz": fxs[n].nnz,
+                                                  "columns": servers[n].slots,
+                                                  "column_bytes": hd.Server.column_bytes(
+                                                      ctxs[n], k_y=W.CONFIGS[n].k_y, top_k=100),
+                                                  "eig_max_residual": fxs[n].info["eig_max_residual"]}
+                                              for n in names},
+           "hbm_budget_per_server_bytes": budget, "iteration_caps": "uniform 5..20 per request (seeded)",
+           "routing": "uniform over the three databases (seeded)", "rates": []}
+    for i, rate in enumerate(rates):
+        n = int(min(args.serve_requests, max(600, 3 * rate)))
+        arr = serve.poisson_arrivals(rate, n, seed=101 + i)
+        route = rng.integers(0, 3, size=n)
+        caps = rng.integers(5, 21, size=n)
+        reqs = [serve.Request(j, float(arr[j]), names[route[j]], q_desc=fxs[names[route[j]]].Q[j % 256],
+                              max_iter=int(caps[j])) for j in range(n)]
+        reqs, wall = serve.run(servers, reqs)
+        st = serve.latency_stats(reqs)
+        rec = {"offered_per_s": rate, "requests": n, "queries_per_s": round(n / wall, 2),
+               "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "per_db": {}}
+        for name in names:
+            sub = [r for r in reqs if r.db == name]
+            if sub:
+                ss = serve.latency_stats(sub)
+                rec["per_db"][name] = {"requests": len(sub), "p50_ms": round(ss["p50_ms"], 3),
+                                       "p99_ms": round(ss["p99_ms"], 3)}
+        out["rates"].append(rec)
+        log(f"[serve-dbs] {rate:g}/s: {n} requests, {rec['queries_per_s']:.0f} q/s served, "
+            f"p50 {rec['p50_ms']:.1f} ms, p99 {rec['p99_ms']:.1f} ms")
+    for name in names:
+        servers[name].close()
+        ctxs[name].close()
+    return out
+
+
+def probes_leg(ctx, ldb, roof, np):
+    """The device's attainable rates for the memory-bound kernels' access
+    patterns (hd_probe_memory, the library's own probe kernels): streaming
+    read and copy of 1 GiB, gathers of whole 256 B and 1 KiB rows at random
+    row ids over 1 GiB, and the sparse product's own gathers on the loaded
+    graph (rows of ldb floats, CSR order). The sparse product is then placed
+    against the last: the fraction of the graph-gather floor it attains."""
+    out = {}
+    for name, mode, rb in (("stream_read_1GiB", "stream", 1024), ("copy_1GiB", "copy", 1024),
+                           ("gather_256B_rows_1GiB", "gather", 256), ("gather_1KiB_rows_1GiB", "gather", 1024),
+                           ("graph_gather", "graph", 4 * ldb)):
+        r = ctx.probe_memory(mode, 1 << 30, rb, 5)
+        out[name] = {"ms": round(r["ms"], 4), "bytes": r["bytes"], "GB_s": round(r["GB_s"], 1)}
+        log(f"[probe] {name}: {r['ms']:.3f} ms, {r['GB_s']:.0f} GB/s")
+    if roof.get("kernel") in ("spmm",):
+        floor_ms = out["graph_gather"]["ms"]
+        out["spmm_vs_graph_gather"] = {
+            "spmm_ms": round(roof["avg_us"] / 1e3, 4), "graph_gather_ms": floor_ms,
+            "frac_of_gather_floor": round(floor_ms / (roof["avg_us"] / 1e3), 4),
+            "note": "graph_gather reads the same CSR and gathers the same neighbour rows of a matrix of the "
+                    "same shape as P, without the multiply-adds and without writing Q"}
+    return out
+
+
+def narrow_leg(args, cfg, ctx, Qd, ip, hd, W, torch, np):
+    """Narrow batches, multi-kernel path against the persistent CG kernel
+    (hd_set_persistent): (1) the plain configuration at 5,000 items (d = 128,
+    k = 10, one query, CG to relative residual 1e-6, at most 20 iterations,
+    r = 0 and r = 50 fp32): latency per query, eager launches and HIP-graph
+    plans, and the relative error against the FP64 oracle's dense solve;
+    (2) plain CG on this workload at its equal-error iteration count for 1,
+    16 and 64 queries per batch (the persistent kernel needs no 64-column
+    padding)."""
+    from oracle import oracle as O
+    out = {}
+    c5 = W.CONFIGS["n5k"]
+    fx = W.build_fixture(c5, n_queries=64, prefer_gpu=True)
+    c = hd.Context(0)
+    c.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    c.load_eigs(fx.U, fx.lam, dtype="f32")
+    c.load_descriptors(fx.V)
+    dev = Qd.device
+    S = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s).dense()
+    reps = 50
+    rows = []
+    for r in (0, c5.r):
+        kw = dict(alpha=c5.alpha, max_iter=c5.max_iter, tol=c5.tol, rank_r=r, k_y=c5.k_y, top_k=100)
+        rec = {"r": r}
+        for name, mode in (("eager", 0), ("persistent", 1)):
+            c.set_persistent(mode)
+            lat, errs = [], []
+            for k in range(reps + 3):
+                q = torch.from_numpy(fx.Q[k % 64][None, :]).to(dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                o = c.query_batch(q, want_x=(k < 8), want_y=(k < 8), **kw)
+                torch.cuda.synchronize()
+                if k >= 3:
+                    lat.append(time.perf_counter() - t0)
+                if k < 8:
+                    y = O.dense_y(fx.n, o["y_ids"][0].cpu().numpy(), o["y_val"][0].cpu().numpy())
+                    xt = O.truth_dense(S, c5.alpha, y)
+                    errs.append(float(np.linalg.norm(o["x"][0].double().cpu().numpy() - xt) / np.linalg.norm(xt)))
+            pl = hd.Plan(c, 1, "descriptors", **kw)
+            q0 = torch.from_numpy(fx.Q[:1]).to(dev)
+            for _ in range(3):
+                pl.run(q0)
+            torch.cuda.synchronize()
+            glat = []
+            for k in range(reps):
+                q = torch.from_numpy(fx.Q[k % 64][None, :]).to(dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pr = pl.run(q)
+                torch.cuda.synchronize()
+                glat.append(time.perf_counter() - t0)
+            pl.close()
+            rec[name] = {"p50_ms": round(1e3 * float(np.median(lat)), 4),
+                         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 4),
+                         "graph_p50_ms": round(1e3 * float(np.median(glat)), 4),
+                         "iters": int(pr["iters"][0]), "max_rel_err_vs_dense_solve": float(f"{max(errs):.3e}")}
+            log(f"[narrow] n5k r={r} {name}: p50 {rec[name]['p50_ms']:.3f} ms, graph "
+                f"{rec[name]['graph_p50_ms']:.3f} ms, {rec[name]['iters']} it, err {max(errs):.2e}")
+        rows.append(rec)
+    c.close()
+    out["n5k_one_query"] = {"workload": f"vMF mixture N={c5.n} d={c5.d} clusters={c5.clusters} "
+                                        f"kappa={c5.kappa:g}, reciprocal kNN k={c5.k}, alpha={c5.alpha}, "
+                                        f"one query, k_y={c5.k_y}, CG to relative residual {c5.tol:g}, at most "
+                                        f"{c5.max_iter} iterations, U1 FP32, whole path (y, CG, ranking)",
+                            "rows": rows}
+    # plain CG on the main workload at narrow widths
+    big = []
+    kw = dict(alpha=cfg.alpha, max_iter=ip, tol=0.0, rank_r=0, k_y=cfg.k_y, top_k=100)
+    for B in (1, 16, 64):
+        rec = {"batch": B}
+        for name, mode in (("eager", 0), ("persistent", 2)):
+            ctx.set_persistent(mode)
+            q = Qd[0][:B]
+            for _ in range(2):
+                ctx.query_batch(q, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                ctx.query_batch(q, **kw)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / 5
+            rec[name] = {"ms_per_batch": round(ms, 3), "queries_per_s": round(B / ms * 1e3, 2)}
+        ctx.set_persistent(0)
+        log(f"[narrow] N={cfg.n} plain CG {ip} it, B={B}: eager {rec['eager']['ms_per_batch']:.2f} ms, "
+            f"persistent {rec['persistent']['ms_per_batch']:.2f} ms")
+        big.append(rec)
+    out["plain_cg_main_workload"] = {"iters": ip, "rows": big}
+    return out
 
 
 def planner_leg(args, cfg, fx, ctx, Qd, B, eps, hd, torch, np):
@@ -593,7 +1125,9 @@ def planner_leg(args, cfg, fx, ctx, Qd, B, eps, hd, torch, np):
         fixed.append(max(0.0, t2 - 2 * per_it[-1]))
     plan = hd.rank_plan(fx.lam, cands, alpha=cfg.alpha, eps=eps, lambda_min=-1.0,
                         fixed_ms=fixed, iter_ms=per_it)
-    truths, _ = exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np)
+    # 16 of the calibration's exact solutions: the planner compares ranks,
+    # not the per-query spread
+    truths, _ = exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np, ns=16)
     buf = {"x": torch.empty((B, fx.n), dtype=torch.float32, device=Qd.device)}
     rows = []
     for c, r in enumerate(cands):
@@ -756,7 +1290,7 @@ def cpu_baseline(args, cfg, fx, ctx, Qd, B, iters, tol, torch, np):
     yi = oh["y_ids"].cpu().numpy()
     ri = oh["rank_ids"].cpu().numpy()
     Qh = np.ascontiguousarray(Qd[0].cpu().numpy(), np.float64)
-    nth = max(1, min(args.cpu_threads, B, os.cpu_count() or 1))
+    nth = max(1, min(host_threads(args), B))
     cpu_model = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -802,6 +1336,9 @@ def cpu_baseline(args, cfg, fx, ctx, Qd, B, iters, tol, torch, np):
                   f"(y by brute force over all {fx.n} items, spectral term, CG at the GPU's per-query "
                   f"iteration count, full sort), single-threaded FP64 each, {wall:.1f}s wall",
         "per_core_queries_per_s": round(1.0 / (sum(per) / len(per)), 4),
+        "host_cpus": {"os_cpu_count": os.cpu_count(), "usable_by_process": host_threads_avail(),
+                      "threads_used": nth,
+                      "note": "16 threads: the host CPU share of a one-GPU box; one oracle query per thread"},
         "y_sets_identical": f"{n_same}/{nth}",
         "y_max_cosine_shortfall": shortfall,
         "gpu_vs_oracle_max_rel_err": max(errs) if errs else None,

@@ -187,6 +187,25 @@ int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
 int hd_autotune(hd_ctx *ctx, int32_t batch, int32_t reps, double *times_ms);
 
 /*
+ * Persistent CG (batching form): with mode 1 (batches of at most 16 queries)
+ * or 2 (at most 64), hd_query_batch, hd_plan_create and hd_plan_run run
+ * every CG iteration of an eligible batch in one kernel (Section 5: CG; the
+ * operator of Section 4.2, eq. (box)): solver vectors W columns wide (the
+ * batch size rounded up to a power of two, instead of at least 64), blocks
+ * co-resident and separated by grid barriers, scalars reduced in a fixed
+ * order by the last block to reach each barrier. Eligible: plain CG (rank 0)
+ * or fp32 U1 with at most 1024 components in use and at most 16 queries, no
+ * polynomial filter. Other batches take the multi-kernel path. Mode 0 (the
+ * default) turns it off. Results agree with the multi-kernel path to fp32
+ * rounding (its partial sums are grouped differently); each column is
+ * still independent of the others. spin_limit (> 0; 0 = the default, 2^24):
+ * the bound on each barrier wait, in polling rounds; a wait past it ends
+ * the kernel early and the call returns HD_EDEVICE.
+ * Errors: HD_EINVAL (NULL context, mode not in {0, 1, 2}, spin_limit < 0).
+ */
+int hd_set_persistent(hd_ctx *ctx, int32_t mode, int64_t spin_limit);
+
+/*
  * (r, i) planner (Section 5, eqs. (bound) and (cond-r)): for each candidate
  * number of deflated eigenpairs cand_r[c] (0 <= r <= nlam), the number of CG
  * iterations that the error bound guarantees to bring the relative A-norm

@@ -17,9 +17,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhd.so")
 SOURCES = ["k_cg.hip", "k_spmm.hip", "k_ugemm.hip", "k_ugemm_bf16.hip", "k_sparse_u.hip", "k_sim.hip", "k_topk.hip",
-           "k_eig.hip", "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp", "hd_eig.cpp", "hd_fp8.cpp", "hd_noalloc.hip"]
-# ROCm libraries for the eigensolver's dense steps (rocBLAS: Gram matrix,
-# rotations, triangular solve; rocSOLVER: Cholesky, small eigenproblem)
+           "k_eig.hip", "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp", "hd_eig.cpp", "hd_fp8.cpp", "k_probe.hip", "k_persist.hip", "k_eig_gemm.hip", "hd_noalloc.hip"]
+# ROCm libraries for the eigensolver's m x m steps (rocSOLVER: Cholesky and
+# its inverse, the small symmetric eigenproblem; rocBLAS: its handle)
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = "gfx950"
 

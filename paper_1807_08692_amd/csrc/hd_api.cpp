@@ -21,7 +21,7 @@ static int64_t ctx_bytes(const hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                            &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                           &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale};
+                           &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale, &c->pbar};
     int64_t s = 0;
     for (const DevBuf *b : all) s += (int64_t)b->bytes;
     return s;
@@ -75,7 +75,7 @@ void hd_destroy(hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                      &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                     &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale};
+                     &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale, &c->pbar};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (hipEvent_t e : c->iter_ev)
@@ -85,6 +85,16 @@ void hd_destroy(hd_ctx *c) {
 }
 
 int64_t hd_device_bytes(const hd_ctx *c) { return c ? ctx_bytes(c) : 0; }
+
+int hd_set_persistent(hd_ctx *c, int32_t mode, int64_t spin_limit) {
+    g_err.clear();
+    if (!c) return fail(HD_EINVAL, "hd_set_persistent: NULL context");
+    if (mode < 0 || mode > 2) return fail(HD_EINVAL, "hd_set_persistent: mode %d not in {0, 1, 2}", mode);
+    if (spin_limit < 0) return fail(HD_EINVAL, "hd_set_persistent: spin_limit < 0");
+    c->persist_mode = mode;
+    c->persist_spin = spin_limit > 0 ? (long long)spin_limit : (1LL << 24);
+    return HD_OK;
+}
 
 int hd_timing_enable(hd_ctx *c, int enable) {
     g_err.clear();
@@ -550,6 +560,139 @@ int hd_rank(hd_ctx *c, int32_t B, int64_t n, const float *x, int64_t ldx, int32_
 
 }  // extern "C"
 
+// Step 1 (Section 3; Section 6.1): the observation vectors y of B queries from
+// their descriptors (similarities to every item, the k_y largest, cubed), or
+// the given sparse y copied to the optional outputs. *yi / *yv receive the
+// device arrays of y the later steps read.
+static int queue_y(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids, const float *y_val, int ky,
+                   int32_t *y_ids_out, float *y_val_out, hipStream_t s, const int32_t **yi, const float **yv) {
+    const int64_t n = c->n;
+    if (q_desc) {
+        const int64_t lds = (n + 63) / 64 * 64;
+        HIP_TRY(c->sim.ensure((size_t)B * lds * sizeof(float)));
+        HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, ky)));
+        int32_t *oi = y_ids_out;
+        float *ov = y_val_out;
+        if (!oi || !ov) {
+            HIP_TRY(c->ybuf.ensure((size_t)B * ky * (sizeof(int32_t) + sizeof(float))));
+            oi = c->ybuf.as<int32_t>();
+            ov = reinterpret_cast<float *>(oi + (size_t)B * ky);
+        }
+        if (c->v_dtype != HD_F32) {
+            HIP_TRY(c->qsplit.ensure((size_t)2 * hd::sim_qsplit_rows(B) * c->ldv * sizeof(uint16_t)));
+            LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.p, c->ldv, c->qsplit.as<uint16_t>(),
+                                              c->sim.as<float>(), lds, s, c->v_scale()));
+        } else {
+            LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
+        }
+        LAUNCH(K_TOPK_Y, hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
+        *yi = oi;
+        *yv = ov;
+    } else {
+        if (y_ids_out) HIP_TRY(hipMemcpyAsync(y_ids_out, y_ids, (size_t)B * ky * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        if (y_val_out) HIP_TRY(hipMemcpyAsync(y_val_out, y_val, (size_t)B * ky * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    return HD_OK;
+}
+
+// The persistent form of steps 2-4 for a narrow batch (queue_query checked
+// the arguments and the eligibility): W = the batch width rounded up to a
+// power of two; plain CG (rk = 0) or fp32 U1. Set-up kernels (y scatter, y^T
+// y, spectral coefficients), one persistent kernel for every CG iteration,
+// the narrow combine and the ranking.
+static int queue_persist(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids, const float *y_val,
+                         const hd_query_opts *o, int r_use, int rk, int W, int32_t *rank_ids, float *rank_scores,
+                         float *x_out, int32_t *y_ids_out, float *y_val_out, hipStream_t s, bool graph,
+                         int *last_iter_out) {
+    const int64_t n = c->n;
+    const int ky = o->k_y;
+    const int G = hd::persist_grid(W, rk, n);
+    if (G < 1) return fail(HD_EDEVICE, "hd_query_batch: no co-resident grid for the persistent CG (width %d)", W);
+    const size_t vec = (size_t)n * W * sizeof(float);
+    HIP_TRY(c->X.ensure(vec));
+    HIP_TRY(c->R.ensure(vec));
+    HIP_TRY(c->P.ensure(vec));
+    HIP_TRY(c->Q.ensure(vec));
+    if (rk > 0) {
+        HIP_TRY(c->Cl.ensure((size_t)rk * W * sizeof(float)));
+        HIP_TRY(c->Cs.ensure((size_t)rk * W * sizeof(float)));
+        HIP_TRY(c->Cpart.ensure((size_t)G * rk * W * sizeof(float)));
+    }
+    HIP_TRY(c->part.ensure((size_t)(2 * G + 1) * W * sizeof(double)));
+    HIP_TRY(c->scal.ensure((size_t)W * (5 * sizeof(double) + 3 * sizeof(int32_t)) + 128 * sizeof(int32_t)));
+    HIP_TRY(c->err.ensure(sizeof(int32_t) * 4));
+    HIP_TRY(c->pbar.ensure(sizeof(uint32_t) * 4));
+    {
+        char *b = c->scal.as<char>();
+        hd::CgState &st = c->st;
+        st.rho0 = reinterpret_cast<double *>(b); b += W * sizeof(double);
+        st.rho = reinterpret_cast<double *>(b); b += W * sizeof(double);
+        st.a = reinterpret_cast<double *>(b); b += W * sizeof(double);
+        st.beta = reinterpret_cast<double *>(b); b += W * sizeof(double);
+        st.relres = reinterpret_cast<double *>(b); b += W * sizeof(double);
+        st.active = reinterpret_cast<int32_t *>(b); b += W * sizeof(int32_t);
+        st.iters = reinterpret_cast<int32_t *>(b); b += W * sizeof(int32_t);
+        st.status = reinterpret_cast<int32_t *>(b); b += W * sizeof(int32_t);
+        st.nact_part = reinterpret_cast<int32_t *>(b);
+        st.maxit = nullptr;
+    }
+    const hd::CgState st = c->st;
+    const int32_t *yi = y_ids;
+    const float *yv = y_val;
+    {
+        const int e = queue_y(c, B, q_desc, y_ids, y_val, ky, y_ids_out, y_val_out, s, &yi, &yv);
+        if (e != HD_OK) return e;
+    }
+    float *X = c->X.as<float>(), *R = c->R.as<float>(), *P = c->P.as<float>(), *Q = c->Q.as<float>();
+    double *gpart = c->part.as<double>(), *rpart = gpart + (size_t)G * W, *yn = rpart + (size_t)G * W;
+    const size_t nv = (size_t)n * W;
+    LAUNCH(K_FILL, hd::launch_fill_zero(X, nv, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(R, nv, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(P, nv, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 2, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(c->pbar.p), 4, s));
+    LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, W, R, P, c->err.as<int32_t>(), s));
+    LAUNCH(K_COLSQ, hd::launch_ynorm_part(B, ky, yi, n, W, R, yn, s));
+    if (!graph) {
+        HIP_TRY(hipMemcpyAsync(c->h_pinned + 200, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c->timing.on) HIP_TRY(c->timing.harvest(0));
+        if (c->h_pinned[200] != 0) return fail(HD_EINVAL, "hd_query_batch: a y id is outside [0, n)");
+    }
+    const float *U = c->U.as<float>();
+    if (rk > 0)
+        LAUNCH(K_GATHER, hd::launch_gather_proj(B, ky, yi, yv, n, U, nullptr, 0, c->rp, rk, r_use, c->lam.as<double>(),
+                                                o->alpha, W, c->Cs.as<float>(), c->Cl.as<float>(), s));
+    c->timing.tag = 1;
+    LAUNCH(K_PERSIST, hd::launch_cg_persist(W, G, n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(),
+                                            c->val.as<float>(), rk > 0 ? U : nullptr, c->rp, rk, r_use,
+                                            c->lam.as<double>(), o->alpha, X, R, P, Q, c->Cl.as<float>(),
+                                            c->Cpart.as<float>(), gpart, rpart, yn, st, B, o->max_iter, o->tol,
+                                            c->pbar.as<uint32_t>(), c->persist_spin, c->err.as<int32_t>(), s));
+    c->timing.tag = 0;
+    LAUNCH(K_SCALAR, hd::launch_cg_final(W, st, s));
+    if (!graph) {
+        HIP_TRY(hipMemcpyAsync(c->h_pinned + 201, c->err.as<int32_t>() + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c->h_pinned[201] != 0)
+            return fail(HD_EDEVICE, "hd_query_batch: a grid barrier wait of the persistent CG ran past its limit");
+    }
+    float *xq = x_out;
+    if (!xq) {
+        HIP_TRY(c->xbuf.ensure((size_t)B * n * sizeof(float)));
+        xq = c->xbuf.as<float>();
+    }
+    if (x_out || o->top_k > 0)
+        LAUNCH(K_COMBINE, hd::launch_combine_narrow(W, n, B, rk > 0 ? U : nullptr, c->rp, rk, c->Cs.as<float>(), X, xq,
+                                                    n, s));
+    if (o->top_k > 0 && (rank_ids || rank_scores)) {
+        HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, o->top_k)));
+        LAUNCH(K_TOPK_RANK, hd::launch_topk(B, n, xq, n, o->top_k, c->topk.p, rank_ids, rank_scores, 0, s));
+    }
+    if (last_iter_out) *last_iter_out = o->max_iter;
+    return HD_OK;
+}
+
 int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_ids,
                      const float *y_val, const hd_query_opts *o, int32_t *rank_ids,
                      float *rank_scores, float *x_out, int32_t *y_ids_out, float *y_val_out,
@@ -574,6 +717,15 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         return fail(HD_EINVAL, "hd_query_batch: give q_desc or both y_ids and y_val");
     }
     HIP_TRY(hipSetDevice(c->device));
+
+    if (c->persist_mode != 0 && !flt && !c->u_sparse() && (r_use == 0 || c->u_dtype == HD_F32)) {
+        int W = 1;
+        while (W < B) W <<= 1;
+        const int rkp = (r_use + 31) / 32 * 32;
+        if (B <= (c->persist_mode == 2 ? 64 : 16) && hd::persist_width_ok(W, rkp))
+            return queue_persist(c, B, q_desc, y_ids, y_val, o, r_use, rkp, W, rank_ids, rank_scores, x_out,
+                                 y_ids_out, y_val_out, s, graph, last_iter_out);
+    }
 
     const int ldb = pow2_at_least(B);
     const size_t vec = (size_t)n * ldb * sizeof(float);
@@ -628,30 +780,9 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     // ---- step 1: observation vectors ----
     const int32_t *yi = y_ids;
     const float *yv = y_val;
-    if (q_desc) {
-        const int64_t lds = (n + 63) / 64 * 64;
-        HIP_TRY(c->sim.ensure((size_t)B * lds * sizeof(float)));
-        HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, ky)));
-        int32_t *oi = y_ids_out;
-        float *ov = y_val_out;
-        if (!oi || !ov) {
-            HIP_TRY(c->ybuf.ensure((size_t)B * ky * (sizeof(int32_t) + sizeof(float))));
-            oi = c->ybuf.as<int32_t>();
-            ov = reinterpret_cast<float *>(oi + (size_t)B * ky);
-        }
-        if (c->v_dtype != HD_F32) {
-            HIP_TRY(c->qsplit.ensure((size_t)2 * hd::sim_qsplit_rows(B) * c->ldv * sizeof(uint16_t)));
-            LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.p, c->ldv, c->qsplit.as<uint16_t>(),
-                                              c->sim.as<float>(), lds, s, c->v_scale()));
-        } else {
-            LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
-        }
-        LAUNCH(K_TOPK_Y, hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
-        yi = oi;
-        yv = ov;
-    } else {
-        if (y_ids_out) HIP_TRY(hipMemcpyAsync(y_ids_out, y_ids, (size_t)B * ky * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        if (y_val_out) HIP_TRY(hipMemcpyAsync(y_val_out, y_val, (size_t)B * ky * sizeof(float), hipMemcpyDeviceToDevice, s));
+    {
+        const int e = queue_y(c, B, q_desc, y_ids, y_val, ky, y_ids_out, y_val_out, s, &yi, &yv);
+        if (e != HD_OK) return e;
     }
 
     // ---- CG set-up: X = 0, R = P = y, rho0 = y^T y ----
@@ -660,7 +791,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     LAUNCH(K_FILL, hd::launch_fill_zero(X, nv, s));
     LAUNCH(K_FILL, hd::launch_fill_zero(R, nv, s));
     LAUNCH(K_FILL, hd::launch_fill_zero(P, nv, s));
-    LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 1, s));
+    LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 2, s));
     // the rows of y: the first product gathers only these rows of P (= y)
     const size_t nmask = (size_t)(n + 31) / 32;
     HIP_TRY(c->ymask.ensure(nmask * sizeof(uint32_t)));

@@ -10,11 +10,12 @@
 //      three-term recurrence;
 //   4. orthonormalise X by shifted CholeskyQR (one shifted pass, then two
 //      plain passes; Fukaya et al. 2020), and go to 1.
-// The sparse products and the recurrence run in this library's kernels; the
-// dense m-column steps use rocBLAS (Gram matrix, rotations, triangular solve)
-// and rocSOLVER (Cholesky, the m x m symmetric eigenproblem). Blocks are
-// item-major N x m, which is column-major m x N with leading dimension m for
-// the BLAS calls.
+// The sparse products, the recurrence and every product over the N rows of a
+// block (Gram matrices, X^T S X, the rotations X Z and X R^-1) run in this
+// library's kernels (k_eig.hip, k_eig_gemm.hip: FP64 matrix cores). Only the
+// m x m steps use rocSOLVER: the Cholesky factor and its inverse, and the
+// m x m symmetric eigenproblem. Blocks are item-major N x m; the m x m
+// matrices handed to rocSOLVER are column-major.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -63,7 +64,7 @@ int hd_compute_eigs(hd_ctx *c, int32_t r, int32_t dtype, const hd_eig_opts *opts
     HIP_TRY(hipSetDevice(c->device));
     const auto t0 = std::chrono::steady_clock::now();
     const size_t blk = (size_t)N * m * sizeof(double);
-    DevBuf X, SX, T1, T2, G, W, Wk, info, part;
+    DevBuf X, SX, T1, T2, G, W, Wk, info, part, Gpart;
     HIP_TRY(X.ensure(blk));
     HIP_TRY(SX.ensure(blk));
     HIP_TRY(T1.ensure(blk));
@@ -72,6 +73,7 @@ int hd_compute_eigs(hd_ctx *c, int32_t r, int32_t dtype, const hd_eig_opts *opts
     HIP_TRY(W.ensure((size_t)m * sizeof(double)));
     HIP_TRY(Wk.ensure((size_t)m * sizeof(double)));
     HIP_TRY(info.ensure(sizeof(rocblas_int)));
+    HIP_TRY(Gpart.ensure((size_t)hd::gram_chunks(N) * m * m * sizeof(double)));
     const int64_t rb = std::max<int64_t>(1024, (N + 1023) / 1024);
     const int nblk = (int)((N + rb - 1) / rb);
     HIP_TRY(part.ensure((size_t)nblk * m * sizeof(double)));
@@ -79,20 +81,20 @@ int hd_compute_eigs(hd_ctx *c, int32_t r, int32_t dtype, const hd_eig_opts *opts
     Blas bl;
     RB_TRY(rocblas_create_handle(&bl.h));
     RB_TRY(rocblas_set_stream(bl.h, s));
-    const double one = 1.0, zero = 0.0;
     const int64_t *rowptr = c->rowptr.as<int64_t>();
     const int32_t *col = c->col.as<int32_t>();
     const float *val = c->val.as<float>();
     double *x = X.as<double>(), *sx = SX.as<double>(), *t1 = T1.as<double>(), *t2 = T2.as<double>();
     std::vector<double> hG((size_t)m * m), w(m), res(m);
 
-    // orthonormalise the block held in *px (shifted CholeskyQR3)
-    auto orth = [&](double *px) -> int {
+    // orthonormalise the block held in px (shifted CholeskyQR3): G = X^T X,
+    // G + shift = R^T R (Cholesky), X <- X R^-1 out of place into ptmp, then
+    // the two pointers swap
+    auto orth = [&](double *&px, double *&ptmp) -> int {
         double shift = 0.0;
         for (int pass = 0; pass < 3; ++pass) {
             for (int attempt = 0;; ++attempt) {
-                RB_TRY(rocblas_dsyrk(bl.h, rocblas_fill_upper, rocblas_operation_none, m, (rocblas_int)N, &one, px, m,
-                                     &zero, G.as<double>(), m));
+                HIP_TRY(hd::launch_gram(N, m, px, px, Gpart.as<double>(), G.as<double>(), s));
                 HIP_TRY(hipMemcpy(hG.data(), G.p, hG.size() * sizeof(double), hipMemcpyDeviceToHost));
                 if (pass == 0 || attempt > 0) {
                     double tr = 0.0;
@@ -108,23 +110,32 @@ int hd_compute_eigs(hd_ctx *c, int32_t r, int32_t dtype, const hd_eig_opts *opts
                 if (inf == 0) break;
                 if (attempt >= 6) return fail(HD_EDEVICE, "hd_compute_eigs: Cholesky of the Gram matrix failed");
             }
-            // X (item-major) = Q R  ->  column-major X <- R^-T X
-            RB_TRY(rocblas_dtrsm(bl.h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                                 rocblas_diagonal_non_unit, m, (rocblas_int)N, &one, G.as<double>(), m, px, m));
+            // R^-1 (upper, column-major), its strict lower part zeroed, then
+            // X <- X R^-1 (item-major: row i of X times R^-1)
+            RB_TRY(rocsolver_dtrtri(bl.h, rocblas_fill_upper, rocblas_diagonal_non_unit, m, G.as<double>(), m,
+                                    info.as<rocblas_int>()));
+            rocblas_int inf = 0;
+            HIP_TRY(hipMemcpy(&inf, info.p, sizeof(inf), hipMemcpyDeviceToHost));
+            if (inf != 0) return fail(HD_EDEVICE, "hd_compute_eigs: inverse of the Cholesky factor failed");
+            HIP_TRY(hipMemcpy(hG.data(), G.p, hG.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (int q = 0; q < m; ++q)
+                for (int p = q + 1; p < m; ++p) hG[(size_t)q * m + p] = 0.0;
+            HIP_TRY(hipMemcpy(G.p, hG.data(), hG.size() * sizeof(double), hipMemcpyHostToDevice));
+            HIP_TRY(hd::launch_rotate(N, m, px, G.as<double>(), m, ptmp, s));
+            std::swap(px, ptmp);
         }
         return HD_OK;
     };
 
     HIP_TRY(hd::launch_eig_rand(N, m, opts->seed, x, s));
-    int e = orth(x);
+    int e = orth(x, t1);
     if (e != HD_OK) return e;
     int outer = 0;
     double maxres = 0.0;
     for (;; ++outer) {
         // Rayleigh-Ritz
         HIP_TRY(hd::launch_eig_cheb(N, rowptr, col, val, m, x, nullptr, sx, 1.0, 0.0, 0.0, s));
-        RB_TRY(rocblas_dgemm(bl.h, rocblas_operation_none, rocblas_operation_transpose, m, m, (rocblas_int)N, &one, x,
-                             m, sx, m, &zero, G.as<double>(), m));
+        HIP_TRY(hd::launch_gram(N, m, x, sx, Gpart.as<double>(), G.as<double>(), s));
         HIP_TRY(hipMemcpy(hG.data(), G.p, hG.size() * sizeof(double), hipMemcpyDeviceToHost));
         for (int a = 0; a < m; ++a)
             for (int b = a + 1; b < m; ++b) {
@@ -149,10 +160,8 @@ int hd_compute_eigs(hd_ctx *c, int32_t r, int32_t dtype, const hd_eig_opts *opts
         HIP_TRY(hipMemcpy(G.p, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(W.p, w.data(), m * sizeof(double), hipMemcpyHostToDevice));
         // X <- X Z, SX <- SX Z (column-major: Z^T X)
-        RB_TRY(rocblas_dgemm(bl.h, rocblas_operation_transpose, rocblas_operation_none, m, (rocblas_int)N, m, &one,
-                             G.as<double>(), m, x, m, &zero, t1, m));
-        RB_TRY(rocblas_dgemm(bl.h, rocblas_operation_transpose, rocblas_operation_none, m, (rocblas_int)N, m, &one,
-                             G.as<double>(), m, sx, m, &zero, t2, m));
+        HIP_TRY(hd::launch_rotate(N, m, x, G.as<double>(), m, t1, s));
+        HIP_TRY(hd::launch_rotate(N, m, sx, G.as<double>(), m, t2, s));
         std::swap(x, t1);
         std::swap(sx, t2);
         // residuals
@@ -188,7 +197,9 @@ int hd_compute_eigs(hd_ctx *c, int32_t r, int32_t dtype, const hd_eig_opts *opts
             else if (y1 == t1) std::swap(x, t1);
             else std::swap(x, t2);
         }
-        e = orth(x);
+        // x holds the filtered block; t1 is free for the out-of-place
+        // rotations (orth exchanges the two pointers)
+        e = orth(x, t1);
         if (e != HD_OK) return e;
     }
     if (lambda_out) std::copy(w.begin(), w.begin() + r, lambda_out);

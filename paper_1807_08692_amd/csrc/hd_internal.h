@@ -93,11 +93,12 @@ enum Kind {
     K_SIM, K_TOPK_Y, K_FILL, K_SCATTER, K_COLSQ, K_SCALAR, K_GATHER, K_UT_P, K_REDUCE_C,
     K_U_C, K_SPMM, K_UPDATE_R, K_UPDATE_XP, K_COMBINE, K_TOPK_RANK,
     K_SPMM_Y,  // the first sparse product, gathering only the rows of y
+    K_PERSIST, // the persistent CG kernel (every iteration of a narrow batch)
     K_NKINDS
 };
 inline const char *const kKindNames[K_NKINDS] = {
     "sim", "topk_y", "fill_zero", "scatter_y", "colsq", "cg_scalar", "gather_proj", "ut_p",
-    "reduce_c", "u_c", "spmm", "update_r", "update_xp", "combine", "topk_rank", "spmm_y"};
+    "reduce_c", "u_c", "spmm", "update_r", "update_xp", "combine", "topk_rank", "spmm_y", "cg_persist"};
 
 struct Timing {
     bool on = false;
@@ -197,6 +198,11 @@ struct hd_ctx {
     hd::CgState st{};
     Timing timing;
     int tune[HD_TUNE_NKEYS] = {0, 0, 0};  // launch parameters (0 = default)
+    // persistent CG for narrow batches: 0 off, 1 up to 16 queries, 2 up to 64;
+    // the bound on each grid-barrier wait (spins); its barrier words
+    int persist_mode = 0;
+    long long persist_spin = 1LL << 24;
+    DevBuf pbar;
 
     // the matrix-core storage forms of U1 (fragment order): bf16, two-term bf16, fp8
     bool u_mfma() const { return u_dtype == HD_BF16 || u_dtype == HD_BF16X2 || u_dtype == HD_FP8_E4M3; }

@@ -136,6 +136,28 @@ hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *C
                               const int32_t *cols, int ncols, int ldc, float *Xc, float *Csc,
                               hipStream_t s);
 
+// ---- persistent CG for narrow batches (k_persist.hip): node-major N x W
+//      vectors, W a power of two in 1..64; plain CG, or with fp32 U1
+//      (rp = row stride, rk components, W <= 16, rk <= 1024) ----
+bool persist_width_ok(int W, int rk);
+size_t persist_lds_bytes(int W, int rk);
+// co-resident grid for width W and rk components on N rows (0: not possible)
+int persist_grid(int W, int rk, int64_t N);
+// Runs every CG iteration (up to max_iter, stopping test tol per column):
+// on entry X = 0, R = P = y, Cl = L1 U1^T y (hybrid), yn[c] = y^T y; on exit
+// X = the temporal term and st the per-column results (relres by
+// launch_cg_final). sync_words: 4 zeroed words; err[1] is set if a grid
+// barrier wait ran past spin_limit (the kernel then ends early).
+hipError_t launch_cg_persist(int W, int grid, int64_t N, const int64_t *rowptr, const int32_t *col,
+                             const float *val, const float *U, int rp, int rk, int r_use, const double *lam,
+                             double alpha, float *X, float *R, float *P, float *Q, float *Cl, float *Cpart,
+                             double *gpart, double *rpart, const double *yn, CgState st, int B, int max_iter,
+                             double tol, unsigned *sync_words, long long spin_limit, int32_t *err,
+                             hipStream_t s);
+// x[b][i] = (U1 Cs)[i][b] + X[i][b], b < B, X narrow (N x W), Cs rk x W
+hipError_t launch_combine_narrow(int W, int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
+                                 const float *X, float *x, int64_t ldx, hipStream_t s);
+
 // ---- sparse product (k_spmm.hip) ----
 // Q = (Zs - alpha * S P) / (1 - alpha); gpart[g][c] = sum over the rows of
 // block g of P[i][c] * Q[i][c] (double). With rowmask, neighbour rows whose
@@ -256,5 +278,14 @@ hipError_t launch_eig_cheb(int64_t N, const int64_t *rowptr, const int32_t *col,
 hipError_t launch_eig_resid(int64_t N, int m, const double *SX, const double *X, const double *w, int64_t rb,
                             int nblk, double *part, hipStream_t s);
 hipError_t launch_eig_extract(int64_t N, int m, int r, const double *X, float *U, hipStream_t s);
+// ---- FP64 matrix-core products of the eigensolver blocks (k_eig_gemm.hip);
+//      m a multiple of 64 ----
+// row chunks of the split Gram product (Gpart holds gram_chunks(N) m x m)
+int64_t gram_chunks(int64_t N);
+// G (m x m, row-major) = A^T B, A and B item-major N x m
+hipError_t launch_gram(int64_t N, int m, const double *A, const double *B, double *Gpart, double *G,
+                       hipStream_t s);
+// Y = X Z (item-major N x m), Z column-major m x m with leading dimension ldz; Y != X
+hipError_t launch_rotate(int64_t N, int m, const double *X, const double *Z, int ldz, double *Y, hipStream_t s);
 
 }  // namespace hd

@@ -38,12 +38,14 @@ std::vector<intptr_t> snapshot(const hd_ctx *c) {
                             &c->Cpart,  &c->Cl,  &c->Cs,  &c->ClT,  &c->CsT,  &c->PT,   &c->part,
                             &c->scal,   &c->xbuf, &c->sim, &c->ybuf, &c->topk, &c->err, &c->qsplit,
                             &c->Usr,    &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->Dg,
-                            &c->ymask,  &c->uscale, &c->vscale};
+                            &c->ymask,  &c->uscale, &c->vscale, &c->pbar};
     std::vector<intptr_t> v;
     for (const DevBuf *b : bufs) v.push_back((intptr_t)b->p);
     const int64_t meta[] = {c->n, c->nnz, c->r, c->rp, c->u_dtype, c->ldut, c->d, c->ldv, c->v_dtype};
     for (int64_t m : meta) v.push_back((intptr_t)m);
     for (int t : c->tune) v.push_back(t);
+    v.push_back(c->persist_mode);
+    v.push_back((intptr_t)c->persist_spin);
     return v;
 }
 
@@ -174,9 +176,11 @@ int hd_plan_run(hd_plan *p, const float *q_desc, const int32_t *y_ids, const flo
     if (iters) HIP_TRY(hipMemcpyAsync(iters, st.iters, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (status) HIP_TRY(hipMemcpyAsync(status, st.status, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (relres) HIP_TRY(hipMemcpyAsync(relres, st.relres, B * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(c->h_pinned + 200, c->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c->h_pinned + 200, c->err.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (c->h_pinned[200] != 0) return fail(HD_EINVAL, "hd_plan_run: a y id is outside [0, n)");
+    if (c->h_pinned[201] != 0)
+        return fail(HD_EDEVICE, "hd_plan_run: a grid barrier wait of the persistent CG ran past its limit");
     return HD_OK;
 }
 

@@ -45,6 +45,8 @@ _SIGS = {
     "hd_rank_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64,
                                        ctypes.c_int32, _P, _P, _P]),
     "hd_rank_noalloc_scratch_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]),
+    "hd_probe_memory": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "hd_set_persistent": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
     "hd_device_bytes": (ctypes.c_int64, [_P]),
     "hd_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "hd_timing_enable_kinds": (ctypes.c_int, [_P, ctypes.c_uint32]),
@@ -252,6 +254,21 @@ class Context:
         sc, scp = _host(row_scale, np.float32)
         _check(lib().hd_load_descriptors_fp8(self._h, int(cd.shape[1]), cdp, scp))
         self.d = int(cd.shape[1])
+
+    def probe_memory(self, mode: str, bytes_: int = 1 << 30, row_bytes: int = 1024, reps: int = 5) -> dict:
+        """hd_probe_memory: mode "stream", "copy", "gather" or "graph"; returns
+        ms per launch, bytes per launch and GB/s."""
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        m = {"stream": 0, "copy": 1, "gather": 2, "graph": 3}[mode]
+        _check(lib().hd_probe_memory(self._h, m, int(bytes_), int(row_bytes), int(reps), ctypes.byref(ms),
+                                     ctypes.byref(by)))
+        return {"ms": ms.value, "bytes": by.value, "GB_s": by.value / (ms.value * 1e-3) / 1e9}
+
+    def set_persistent(self, mode: int, spin_limit: int = 0):
+        """Persistent CG for narrow batches (hd_set_persistent): 0 off, 1 up to
+        16 queries, 2 up to 64."""
+        _check(lib().hd_set_persistent(self._h, int(mode), int(spin_limit)))
 
     def device_bytes(self) -> int:
         return int(lib().hd_device_bytes(self._h))

@@ -3,6 +3,7 @@
     python -m paper_1807_08692_amd.profsum trace TRACE_CSV > summary.md
     python -m paper_1807_08692_amd.profsum traffic FETCH_CSV WRITE_CSV OUT_JSON > table.md
     python -m paper_1807_08692_amd.profsum mfma COUNTER_CSV > mfma.md
+    python -m paper_1807_08692_amd.profsum counters COUNTER_CSV > counters.md
 
 `trace` reads a --kernel-trace CSV (one row per dispatch) and prints, per
 kernel, the dispatch count and mean duration over all dispatches and over the
@@ -11,8 +12,10 @@ test, and an iteration queued after every column stopped returns at once
 (a few microseconds), which would otherwise pull the mean down.
 
 `traffic` reads the FETCH_SIZE and WRITE_SIZE counter CSVs of two --pmc runs
-that include a 1 GiB device copy (grid 131072 of __amd_rocclr_copyBuffer),
-scales each counter by what it reads for that copy (1 GiB read and written),
+that include a 1 GiB device copy (the library's own probe copy kernel,
+hd::k_probe_copy of hd_probe_memory mode 1, or grid 131072 of
+__amd_rocclr_copyBuffer), scales each counter by what it reads for that copy
+(1 GiB read and written),
 and writes per-kernel HBM-side bytes per dispatch to OUT_JSON together with a
 SHA-256 of each kernel's source file, so that a later run can tell whether the
 kernel has changed since the counters were taken.
@@ -42,6 +45,14 @@ KINDS = {
     "hd::k_combine": ("combine", "k_ugemm.hip"),
     "hd::k_sim_bf16": ("sim", "k_ugemm_bf16.hip"),
     "hd::k_sim": ("sim", "k_sim.hip"),
+    "hd::k_cg_persist": ("cg_persist", "k_persist.hip"),
+    "hd::k_combine_narrow": ("combine", "k_persist.hip"),
+    "hd::k_probe_read": ("probe", "k_probe.hip"),
+    "hd::k_probe_copy": ("probe", "k_probe.hip"),
+    "hd::k_probe_gather": ("probe", "k_probe.hip"),
+    "hd::k_probe_graph": ("probe", "k_probe.hip"),
+    "hd::k_gram_tn": ("eig", "k_eig_gemm.hip"),
+    "hd::k_rotate_nn": ("eig", "k_eig_gemm.hip"),
 }
 
 
@@ -86,14 +97,15 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str) -> str:
         copy = []
         for r in csv.DictReader(open(fn)):
             v = float(r["Counter_Value"])
-            if "copyBuffer" in r["Kernel_Name"] and r["Grid_Size"] == "131072":
+            if ("copyBuffer" in r["Kernel_Name"] and r["Grid_Size"] == "131072") or \
+                    short(r["Kernel_Name"]) == "hd::k_probe_copy":
                 copy.append(v)
             a[short(r["Kernel_Name"])].append(v)
         return a, copy
     fs, cf = agg(fetch_csv)
     ws, cw = agg(write_csv)
     if not cf or not cw:
-        raise SystemExit("no 1 GiB copy dispatch in the counter runs (bench.py --copy-calibration)")
+        raise SystemExit("no 1 GiB copy dispatch in the counter runs (bench.py --probes 1 or --copy-calibration)")
     kf = 1048576.0 / (sum(cf) / len(cf))
     kw = 1048576.0 / (sum(cw) / len(cw))
     rows = ["| kernel | dispatches | FETCH_SIZE KiB (mean) | fetched GB | WRITE_SIZE KiB (mean) | written GB |",
@@ -150,6 +162,33 @@ def mfma(path: str) -> str:
     return "\n".join(out)
 
 
+def counters(path: str) -> str:
+    """Per kernel, the mean of each counter per working dispatch (each counter
+    summed over its instances; working = its first counter >= 5% of the
+    kernel's largest), from one --pmc pass (e.g. TCC_HIT_sum TCC_MISS_sum, or
+    TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_DRAM_sum)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(float)))
+    names = []
+    for r in csv.DictReader(open(path)):
+        per[short(r["Kernel_Name"])][r["Dispatch_Id"]][r["Counter_Name"]] += float(r["Counter_Value"])
+        if r["Counter_Name"] not in names:
+            names.append(r["Counter_Name"])
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    rows = []
+    for k, disp in per.items():
+        if not k.startswith("hd::"):
+            continue
+        first = [d.get(names[0], 0.0) for d in disp.values()]
+        mx = max(first) if first else 0.0
+        work = [d for d in disp.values() if mx > 0 and d.get(names[0], 0.0) >= 0.05 * mx]
+        if not work:
+            continue
+        mean = [sum(d.get(c, 0.0) for d in work) / len(work) for c in names]
+        rows.append((mean[0] * len(work), f"| {k} | {len(work)} | " + " | ".join(f"{v:.4g}" for v in mean) + " |"))
+    out += [r for _, r in sorted(rows, reverse=True)]
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         print(trace(sys.argv[2]))
@@ -157,5 +196,7 @@ if __name__ == "__main__":
         print(traffic(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "mfma":
         print(mfma(sys.argv[2]))
+    elif sys.argv[1] == "counters":
+        print(counters(sys.argv[2]))
     else:
         raise SystemExit(__doc__)

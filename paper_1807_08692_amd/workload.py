@@ -71,6 +71,10 @@ CONFIGS = {
     "n100k": WorkloadConfig("n100k", 100_000, 2048, 1000, 60.0, 50, 0.99, 400, 64, 50, 1e-5, 100, 1000),
     # 1,000,000 items, d=2048, 10,000 clusters (kappa 60), k=50, r=1000, 256 queries.
     "n1m": WorkloadConfig("n1m", 1_000_000, 2048, 10_000, 60.0, 50, 0.99, 1000, 256, 50, 1e-5, 100, 2000),
+    # the serving configuration's two smaller resident databases (d=2048, k=50,
+    # N/100 clusters): 50,000 items with r=200, 300,000 items with r=400
+    "n50k": WorkloadConfig("n50k", 50_000, 2048, 500, 60.0, 50, 0.99, 200, 64, 50, 1e-5, 100, 5000),
+    "n300k": WorkloadConfig("n300k", 300_000, 2048, 3000, 60.0, 50, 0.99, 400, 64, 50, 1e-5, 100, 6000),
     # 2,000,000 items, d=512, 20,000 clusters (kappa 60), k=30, r up to 4000, 1024 queries.
     "n2m": WorkloadConfig("n2m", 2_000_000, 512, 20_000, 60.0, 30, 0.99, 400, 1024, 50, 1e-3, 100, 4000),
 }
