@@ -74,7 +74,8 @@ def parse():
     p.add_argument("--eps", default="1e-3,1e-2",
                    help="relative-error targets against the exact solution, primary first")
     p.add_argument("--calib-queries", type=int, default=256,
-                   help="queries of the first batch whose exact solution fixes the iteration counts")
+                   help="queries (the first ones, over up to 4 batches) whose exact solutions fix the "
+                        "iteration counts; 1024 covers the precision configuration's 1,000-query subsample")
     p.add_argument("--parity-queries", type=int, default=16,
                    help="queries of the headline diffusion parity against the oracle (0 skips it)")
     p.add_argument("--calib-max-iter", type=int, default=40)
@@ -98,6 +99,8 @@ def parse():
                    help="H,P: fixed CG iteration counts for hybrid and plain CG instead of the "
                         "calibration (for profiling runs)")
     p.add_argument("--c2-eig-seconds", type=float, default=60.0)
+    p.add_argument("--knn-check-rows", type=int, default=1000,
+                   help="rows of the workload's reciprocal k-NN graph checked against FP64 cosines (0 skips)")
     p.add_argument("--narrow", type=int, default=1,
                    help="1: time narrow batches (1..64 queries) through the multi-kernel path and the "
                         "persistent CG kernel, on the 5,000-item workload and on this one")
@@ -419,7 +422,9 @@ def main():
         "kernels": chosen["kernels"],
         "fixture": {"eig_max_residual": fx.info["eig_max_residual"], "mean_degree": fx.info["mean_degree"],
                     "isolated": fx.info["isolated"], "lambda_1": float(fx.lam[0]) if fx.lam.size else None,
-                    "lambda_r": float(fx.lam[-1]) if fx.lam.size else None},
+                    "lambda_r": float(fx.lam[-1]) if fx.lam.size else None,
+                    "knn_check": knn_check(fx, cfg, args.knn_check_rows, torch, np) if args.knn_check_rows > 0
+                    else None},
     }
 
     if chosen["calibration"] is not None and e0 is not None:
@@ -557,17 +562,21 @@ def exact_solutions(args, cfg, fx, ctx, Qd, B, torch, np, ns=None):
     descriptors, hence y, are the same for every U1 form."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
-    ns = max(1, min(ns or args.calib_queries, B))
+    ns = max(1, min(ns or args.calib_queries, B * Qd.shape[0]))
     key = cfg.name
     have = _TRUTH.get(key)
     if have and len(have["truths"]) >= ns:
         return have["truths"][:ns], have["iters"][:ns]
     g = O.Graph64.from_csr(fx.n, fx.rowptr, fx.col, fx.s)
-    o = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=0, tol=0.0, rank_r=0, k_y=cfg.k_y,
-                        top_k=0, want_y=True)
-    torch.cuda.synchronize()
-    yi = o["y_ids"][:ns].cpu().numpy()
-    yv = o["y_val"][:ns].cpu().numpy().astype(np.float64)
+    yis, yvs = [], []
+    for b in range((ns + B - 1) // B):  # the first ns queries, batch by batch
+        o = ctx.query_batch(Qd[b], alpha=cfg.alpha, max_iter=0, tol=0.0, rank_r=0, k_y=cfg.k_y,
+                            top_k=0, want_y=True)
+        torch.cuda.synchronize()
+        yis.append(o["y_ids"].cpu().numpy())
+        yvs.append(o["y_val"].cpu().numpy().astype(np.float64))
+    yi = np.concatenate(yis)[:ns]
+    yv = np.concatenate(yvs)[:ns]
 
     def solve(b):
         t, it_t, _, _ = O.cg(g, None, None, cfg.alpha, O.dense_y(fx.n, yi[b], yv[b]), 2000, 1e-11)
@@ -591,13 +600,18 @@ def error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np, keep=False)
     Returns the worst error per iteration, and with keep=True also every
     query's error per iteration."""
     ns = len(truths)
+    B = buf["x"].shape[0]
     norms = np.array([np.linalg.norm(t) for t in truths])
     worst, per = [], []
     for it in range(0, args.calib_max_iter + 1):
-        ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use, k_y=cfg.k_y,
-                        top_k=0, want_x=True, out=buf)
-        X = buf["x"][:ns].cpu().numpy()
-        e = np.array([np.linalg.norm(X[b].astype(np.float64) - truths[b]) for b in range(ns)]) / norms
+        e = np.empty(ns)
+        for bt in range((ns + B - 1) // B):  # the first ns queries, batch by batch
+            ctx.query_batch(Qd[bt], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use, k_y=cfg.k_y,
+                            top_k=0, want_x=True, out=buf)
+            q0, q1 = bt * B, min(ns, (bt + 1) * B)
+            X = buf["x"][:q1 - q0].cpu().numpy()
+            e[q0:q1] = [np.linalg.norm(X[b].astype(np.float64) - truths[q0 + b]) for b in range(q1 - q0)]
+        e /= norms
         worst.append(float(e.max()))
         if keep:
             per.append(e)
@@ -651,17 +665,20 @@ def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
             it = iters[str(e)][name]
             if it is None:
                 continue
-            oo = ctx.query_batch(Qd[0], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use,
-                                 k_y=cfg.k_y, top_k=100)
-            ids = oo["rank_ids"][:ns].cpu().numpy()
+            ids = []
+            for bt in range((ns + B - 1) // B):
+                oo = ctx.query_batch(Qd[bt], alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use,
+                                     k_y=cfg.k_y, top_k=100)
+                ids.append(oo["rank_ids"].cpu().numpy())
+            ids = np.concatenate(ids)[:ns]
             ov = [top_overlap(ids[b], truths[b]) for b in range(ns)]
             acc.setdefault(str(e), {})[name] = {
                 "iters": it, "rel_err": stats(per_q[name][it], np),
                 "top100_overlap": {"min": min(ov), "p1": float(np.percentile(ov, 1)),
                                    "mean": round(float(np.mean(ov)), 4)}}
     del buf
-    return {"sample_queries": ns, "exact_solve": "FP64 oracle CG on (I - alpha S), relative residual 1e-11, "
-                                                 "one query per host thread",
+    return {"sample_queries": ns, "batches": (ns + B - 1) // B,
+            "exact_solve": "FP64 oracle CG on (I - alpha S), relative residual 1e-11, one query per host thread",
             "exact_solve_iters": {"min": min(exact_iters), "max": max(exact_iters)},
             "rel_err_by_iter_worst": curves,
             "error_floor": {k: float(f"{v:.4g}") for k, v in floors.items()},
@@ -1090,6 +1107,61 @@ def narrow_leg(args, cfg, ctx, Qd, ip, hd, W, torch, np):
         big.append(rec)
     out["plain_cg_main_workload"] = {"iters": ip, "rows": big}
     return out
+
+
+def knn_check(fx, cfg, rows, torch, np):
+    """Spot check of the workload's reciprocal k-NN graph, which the fixture
+    builds from float32 (bfloat16 at this size) similarity products: for
+    `rows` seeded items i, exact FP64 cosines give i's k nearest items (self
+    excluded, ties to the lower id) and each of those items' own k nearest;
+    i's exact reciprocal set (positive cosines only) is compared with row i
+    of the graph, and the graph's weights with max(0, cos)^3 in FP64. Input
+    preparation only: torch on the GPU."""
+    dev = torch.device("cuda:0")
+    k = cfg.k
+    rng = np.random.default_rng(cfg.seed_base + 31)
+    sample = np.sort(rng.choice(fx.n, size=min(rows, fx.n), replace=False))
+    Vd = torch.from_numpy(fx.V).to(dev).double()
+
+    def nearest(ids):
+        out = np.empty((len(ids), k), np.int64)
+        for a in range(0, len(ids), 256):
+            idt = torch.from_numpy(np.ascontiguousarray(ids[a:a + 256])).to(dev)
+            sim = Vd[idt] @ Vd.T
+            sim[torch.arange(len(idt), device=dev), idt] = -3.0
+            v, idx = torch.topk(sim, k + 8, dim=1)
+            v, idx = v.cpu().numpy(), idx.cpu().numpy()
+            for r in range(len(idt)):
+                out[a + r] = idx[r][np.lexsort((idx[r], -v[r]))[:k]]
+            del sim
+        return out
+
+    t0 = time.time()
+    nn_i = nearest(sample)
+    cand = np.unique(nn_i.ravel())
+    nn_c = nearest(cand)
+    pos = {int(c): j for j, c in enumerate(cand)}
+    same, worst, wmax = 0, 0, 0.0
+    for r, i in enumerate(sample):
+        i = int(i)
+        cos_i = fx.V[nn_i[r]].astype(np.float64) @ fx.V[i].astype(np.float64)
+        exact = {int(j) for j, c in zip(nn_i[r], cos_i) if c > 0 and i in set(nn_c[pos[int(j)]].tolist())}
+        lo, hi = int(fx.rowptr[i]), int(fx.rowptr[i + 1])
+        row = fx.col[lo:hi].astype(np.int64)
+        d = len(exact ^ set(row.tolist()))
+        same += d == 0
+        worst = max(worst, d)
+        if hi > lo:
+            w64 = np.maximum(fx.V[row].astype(np.float64) @ fx.V[i].astype(np.float64), 0.0) ** 3
+            wmax = max(wmax, float(np.max(np.abs(fx.w[lo:hi] - w64) / np.maximum(w64, 1e-300))))
+    del Vd
+    torch.cuda.empty_cache()
+    log(f"[knn check] {len(sample)} rows: {same} identical reciprocal sets, worst symmetric difference "
+        f"{worst}, max relative weight error {wmax:.2e} ({time.time() - t0:.1f}s)")
+    return {"rows": int(len(sample)), "identical_reciprocal_sets": int(same), "max_symmetric_difference": int(worst),
+            "max_rel_weight_error": float(f"{wmax:.3e}"),
+            "note": "exact FP64 k nearest of each sampled item and of its candidates, ties to the lower id; "
+                    "a difference is a near-tie at the k-th neighbour decided by the build's rounded products"}
 
 
 def planner_leg(args, cfg, fx, ctx, Qd, B, eps, hd, torch, np):

@@ -11,7 +11,9 @@
 //
 // v_mfma_f64_16x16x4f64 operand layout (lane l of 64):
 //   A (16 x 4): A[l % 16][l / 16];  B (4 x 16): B[l / 16][l % 16];
-//   D (16 x 16, 4 doubles): D[4 (l / 16) + v][l % 16].
+//   D (16 x 16, 4 doubles): D[l / 16 + 4 v][l % 16] (the double-precision
+//   accumulator interleaves its rows: one row per register per lane group,
+//   unlike the four consecutive rows of the fp32 16 x 16 forms).
 #include "hd_device.h"
 #include "hd_kernels.h"
 
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_tn(int64_t N, int m, const doub
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int p = p0 + wp + 16 * a + 4 * (lane / 16) + v;
+                const int p = p0 + wp + 16 * a + lane / 16 + 4 * v;
                 const int q = q0 + wq + 16 * b + lane % 16;
                 out[(size_t)p * m + q] = acc[a][b][v];
             }
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_rotate_nn(int64_t N, int m, const do
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t i = i0 + wi + 16 * a + 4 * (lane / 16) + v;
+                const int64_t i = i0 + wi + 16 * a + lane / 16 + 4 * v;
                 const int q = q0 + wq + 16 * b + lane % 16;
                 if (i < N) Y[(size_t)i * m + q] = acc[a][b][v];
             }
