@@ -118,6 +118,9 @@ def parse():
     p.add_argument("--r-sweep", default="0,100,400,1000",
                    help="ranks of the r-sweep mode (prefixes of the largest, which is computed)")
     p.add_argument("--sweep-steps", type=int, default=5)
+    p.add_argument("--r-cost", default="4000",
+                   help="ranks of the r-sweep mode timed for cost only: the computed eigenvectors plus "
+                        "columns with eigenvalue 0, which leave x unchanged (empty: none)")
     p.add_argument("--serve-budget-gb", type=float, default=40.0,
                    help="HBM budget of each server in the serve-dbs mode")
     p.add_argument("--tol-mode", action="store_true",
@@ -918,13 +921,71 @@ def r_sweep_mode(args, hd, W, torch, np):
                      "u1_bytes": 2 * 2 * fx.n * ((r + 31) // 32 * 32)})
         log(f"[sweep] r={r}: {it} it ({'reached' if hit else 'floor'} {min(errs):.2e}), "
             f"{1e3 * best:.1f} ms per batch")
+    # cost-only ranks: eigenvalue-0 columns add nothing to either term (g(0) = 0
+    # and lambda = 0 in the deflation), so x stays that of r = rmax while every
+    # U1 product does the work of the larger rank
+    cost_ranks = sorted({int(x) for x in (args.r_cost or "").split(",") if x.strip()} - set(ranks))
+    cost_rows = []
+    if rmax > 0 and cost_ranks and rows:
+        it = rows[-1]["iters"]
+        kw = dict(alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=-1, k_y=cfg.k_y, top_k=100)
+        ref = ctx.query_batch(Qd[0], want_x=True, **dict(kw, rank_r=rmax))["x"].clone()
+        gen = torch.Generator(device=dev).manual_seed(cfg.seed_base + 97)
+        for rc in cost_ranks:
+            extra = rc - rmax
+            if extra <= 0:
+                continue
+            Ux = np.empty((fx.n, rc), np.float32)
+            Ux[:, :rmax] = fx.U[:, :rmax]
+            for a in range(0, fx.n, 1 << 18):
+                b = min(fx.n, a + (1 << 18))
+                Ux[a:b, rmax:] = (torch.randn((b - a, extra), generator=gen, device=dev)
+                                  / float(np.sqrt(fx.n))).cpu().numpy()
+            lx = np.concatenate([fx.lam[:rmax], np.zeros(extra)])
+            t1 = time.time()
+            ctx.load_eigs(Ux, lx, dtype=args.forms or "bf16")
+            del Ux
+            tl = time.time() - t1
+            o = ctx.query_batch(Qd[0], want_x=True, **kw)
+            torch.cuda.synchronize()
+            dx = float(((o["x"] - ref).norm(dim=1) / ref.norm(dim=1)).max())
+            del o
+            for w in range(max(1, args.warmup)):
+                ctx.query_batch(Qd[0], **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for k in range(args.sweep_steps):
+                ctx.query_batch(Qd[0], **kw)
+            torch.cuda.synchronize()
+            eager = (time.perf_counter() - t1) / args.sweep_steps
+            pl = hd.Plan(ctx, B, "descriptors", **kw)
+            pl.run(Qd[0])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for k in range(args.sweep_steps):
+                pl.run(Qd[0])
+            torch.cuda.synchronize()
+            graph = (time.perf_counter() - t1) / args.sweep_steps
+            pl.close()
+            best = min(eager, graph)
+            cost_rows.append({"r": rc, "computed_eigenpairs": rmax, "iters": it,
+                              "max_rel_diff_x_vs_r_computed": float(f"{dx:.3e}"),
+                              "ms_per_batch": round(1e3 * best, 3), "queries_per_s": round(B / best, 2),
+                              "eager_ms": round(1e3 * eager, 3), "graph_ms": round(1e3 * graph, 3),
+                              "load_s": round(tl, 1), "u1_bytes": 2 * 2 * fx.n * ((rc + 31) // 32 * 32)})
+            log(f"[sweep] r={rc} (cost only, {rmax} computed + {extra} zero-eigenvalue columns): {it} it, "
+                f"{1e3 * best:.1f} ms per batch, x differs from r={rmax} by {dx:.1e}")
     ctx.close()
     return {"mode": "r-sweep", "workload": f"vMF mixture N={cfg.n} d={cfg.d} clusters={cfg.clusters} "
                                            f"kappa={cfg.kappa:g}, reciprocal kNN k={cfg.k} (nnz={fx.nnz}), "
                                            f"alpha={cfg.alpha}, batch {B}, k_y={cfg.k_y}, U1 "
                                            f"{args.forms or 'bf16'}, descriptors BF16",
             "eps": eps, "sample_queries": len(truths), "eig_max_residual": fx.info["eig_max_residual"],
-            "rows": rows}
+            "rows": rows, "cost_only_rows": cost_rows,
+            "cost_only_note": "U1 = the computed eigenvectors and Gaussian columns with eigenvalue 0: "
+                              "g(0) = 0 and a zero eigenvalue leave the spectral term and the deflated "
+                              "operator unchanged, so x is that of the computed rank (difference reported) "
+                              "and the iterations are the computed rank's; the time is the larger rank's"}
 
 
 def serve_dbs_mode(args, hd, W, torch, np):

@@ -20,7 +20,7 @@ SOURCES = ["k_cg.hip", "k_spmm.hip", "k_ugemm.hip", "k_ugemm_bf16.hip", "k_spars
            "k_eig.hip", "hd_api.cpp", "hd_serve.cpp", "hd_tune.cpp", "hd_plan.cpp", "hd_planner.cpp", "hd_eig.cpp", "hd_fp8.cpp", "k_probe.hip", "k_persist.hip", "k_eig_gemm.hip", "hd_noalloc.hip"]
 # ROCm libraries for the eigensolver's m x m steps (rocSOLVER: Cholesky and
 # its inverse, the small symmetric eigenproblem; rocBLAS: its handle)
-LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-pthread", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = "gfx950"
 
 

@@ -11,6 +11,9 @@
 //                  stopping test read back once per iteration
 //   4. x = U1 Cs + X, transposed to query-major; top-K     (k_combine, k_topk)
 #include "hd_internal.h"
+#include <algorithm>
+#include <atomic>
+#include <thread>
 
 namespace hdi {
 thread_local std::string g_err;
@@ -28,6 +31,27 @@ static int64_t ctx_bytes(const hd_ctx *c) {
 }
 
 static void drop_eigs(hd_ctx *c);
+
+// f(a, b) over [0, n) in blocks of `grain` rows on up to 16 host threads
+// (each row handled by exactly one thread).
+template <class F>
+static void host_parallel_rows(int64_t n, int64_t grain, F f) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t blocks = (n + grain - 1) / grain;
+    const int nt = (int)std::min<int64_t>(blocks, std::min<unsigned>(hw ? hw : 1, 16u));
+    if (nt <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto work = [&] {
+        for (int64_t b; (b = next.fetch_add(1)) < blocks;) f(b * grain, std::min(n, (b + 1) * grain));
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+}
 
 extern "C" {
 
@@ -332,8 +356,10 @@ static int load_eigs_dense(hd_ctx *c, int r, int rp, const float *U, int dtype) 
     }
     if (dtype == HD_F32) {
         std::vector<float> host((size_t)n * rp, 0.f);
-        for (int64_t i = 0; i < n; ++i)
-            std::memcpy(host.data() + (size_t)i * rp, U + (size_t)i * r, (size_t)r * sizeof(float));
+        host_parallel_rows(n, 4096, [&](int64_t a, int64_t b) {
+            for (int64_t i = a; i < b; ++i)
+                std::memcpy(host.data() + (size_t)i * rp, U + (size_t)i * r, (size_t)r * sizeof(float));
+        });
         HIP_TRY(c->U.ensure(host.size() * sizeof(float)));
         HIP_TRY(hipMemcpy(c->U.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
     } else {
@@ -344,22 +370,25 @@ static int load_eigs_dense(hd_ctx *c, int r, int rp, const float *U, int dtype) 
         const int terms = dtype == HD_BF16X2 ? 2 : 1;
         const size_t imn = (size_t)n16 * rp, cmn = (size_t)rp * ldut;
         std::vector<uint16_t> im(imn * terms, 0), cm(cmn * terms, 0);
-        for (int64_t i = 0; i < n; ++i)
-            for (int k = 0; k < r; ++k) {
-                const float u = U[(size_t)i * r + k];
-                const uint16_t h = bf16_rne_host(u);
-                const size_t oi = hd::frag_offset(i, k, rp / 32), oc = hd::frag_offset(k, i, ldut / 32);
-                im[oi] = h;
-                cm[oc] = h;
-                if (terms == 2) {
-                    float hf;
-                    const uint32_t hb = (uint32_t)h << 16;
-                    std::memcpy(&hf, &hb, sizeof(hf));
-                    const uint16_t l = bf16_rne_host(u - hf);
-                    im[imn + oi] = l;
-                    cm[cmn + oc] = l;
+        // blocks of 64 items: whole 16-row tiles of both layouts per thread
+        host_parallel_rows(n, 64, [&](int64_t a, int64_t b) {
+            for (int64_t i = a; i < b; ++i)
+                for (int k = 0; k < r; ++k) {
+                    const float u = U[(size_t)i * r + k];
+                    const uint16_t h = bf16_rne_host(u);
+                    const size_t oi = hd::frag_offset(i, k, rp / 32), oc = hd::frag_offset(k, i, ldut / 32);
+                    im[oi] = h;
+                    cm[oc] = h;
+                    if (terms == 2) {
+                        float hf;
+                        const uint32_t hb = (uint32_t)h << 16;
+                        std::memcpy(&hf, &hb, sizeof(hf));
+                        const uint16_t l = bf16_rne_host(u - hf);
+                        im[imn + oi] = l;
+                        cm[cmn + oc] = l;
+                    }
                 }
-            }
+        });
         HIP_TRY(c->Ub.ensure(im.size() * sizeof(uint16_t)));
         HIP_TRY(c->UbT.ensure(cm.size() * sizeof(uint16_t)));
         HIP_TRY(hipMemcpy(c->Ub.p, im.data(), im.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
@@ -722,7 +751,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         int W = 1;
         while (W < B) W <<= 1;
         const int rkp = (r_use + 31) / 32 * 32;
-        if (B <= (c->persist_mode == 2 ? 64 : 16) && hd::persist_width_ok(W, rkp))
+        if (B <= (c->persist_mode == 2 ? 64 : 16) && hd::persist_width_ok(W, rkp) && hd::persist_grid(W, rkp, n) > 0)
             return queue_persist(c, B, q_desc, y_ids, y_val, o, r_use, rkp, W, rank_ids, rank_scores, x_out,
                                  y_ids_out, y_val_out, s, graph, last_iter_out);
     }
