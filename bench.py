@@ -76,6 +76,9 @@ def parse():
     p.add_argument("--calib-queries", type=int, default=256,
                    help="queries (the first ones, over up to 4 batches) whose exact solutions fix the "
                         "iteration counts; 1024 covers the precision configuration's 1,000-query subsample")
+    p.add_argument("--floor-eps", type=float, default=1e-5,
+                   help="continue the hybrid's calibration curve down to this error (or until it stops "
+                        "falling): its floor shows what the eigenpairs' residual and U1's storage allow")
     p.add_argument("--parity-queries", type=int, default=16,
                    help="queries of the headline diffusion parity against the oracle (0 skips it)")
     p.add_argument("--calib-max-iter", type=int, default=40)
@@ -110,11 +113,12 @@ def parse():
     p.add_argument("--c2", type=int, default=None,
                    help="1: also run the fp32 100,000-item configuration (r = 400, 64 queries, CG to "
                         "relative residual 1e-5) as a leg of the line (default 1 for n1m)")
-    p.add_argument("--mode", choices=["line", "r-sweep", "serve-dbs"], default="line",
+    p.add_argument("--mode", choices=["line", "r-sweep", "serve-dbs", "narrow"], default="line",
                    help="line: the benchmark line (default); r-sweep: the space-time sweep on the "
                         "workload (--workload n2m), iterations per rank for rel-err 1e-3 and the batch "
                         "time; serve-dbs: three resident databases (n50k, n300k, n1m) under Poisson "
-                        "load")
+                        "load; narrow: the narrow-batch leg alone (plain CG on the workload's graph, "
+                        "no eigenpairs needed, --iters sets its iteration count, default 7)")
     p.add_argument("--r-sweep", default="0,100,400,1000",
                    help="ranks of the r-sweep mode (prefixes of the largest, which is computed)")
     p.add_argument("--sweep-steps", type=int, default=5)
@@ -178,6 +182,9 @@ def main():
         return
     if args.mode == "serve-dbs":
         print(json.dumps(serve_dbs_mode(args, hd, W, torch, np)), flush=True)
+        return
+    if args.mode == "narrow":
+        print(json.dumps(narrow_mode(args, hd, W, torch, np)), flush=True)
         return
     cfg = W.CONFIGS[args.workload]
     big = args.workload in ("n1m", "n2m")
@@ -654,7 +661,8 @@ def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
     curves, iters, floors, acc = {}, {}, {}, {}
     per_q = {}
     for name, r_use in (("hybrid", -1), ("plain", 0)):
-        errs, per = error_curve(args, cfg, ctx, Qd, truths, r_use, eps_min, buf, np, keep=True)
+        stop = min(eps_min, args.floor_eps) if (name == "hybrid" and args.floor_eps > 0) else eps_min
+        errs, per = error_curve(args, cfg, ctx, Qd, truths, r_use, stop, buf, np, keep=True)
         curves[name] = [float(f"{e:.4g}") for e in errs]
         floors[name] = min(errs)
         per_q[name] = per
@@ -684,6 +692,7 @@ def calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np):
             "exact_solve": "FP64 oracle CG on (I - alpha S), relative residual 1e-11, one query per host thread",
             "exact_solve_iters": {"min": min(exact_iters), "max": max(exact_iters)},
             "rel_err_by_iter_worst": curves,
+            "hybrid_curve_continued_to": args.floor_eps if args.floor_eps > 0 else eps_min,
             "error_floor": {k: float(f"{v:.4g}") for k, v in floors.items()},
             "iters": iters, "per_query": acc}
 
@@ -1168,6 +1177,27 @@ def narrow_leg(args, cfg, ctx, Qd, ip, hd, W, torch, np):
         big.append(rec)
     out["plain_cg_main_workload"] = {"iters": ip, "rows": big}
     return out
+
+
+def narrow_mode(args, hd, W, torch, np):
+    """The narrow-batch leg on its own: the workload's graph and descriptors
+    (no eigenpairs: the large-graph rows are plain CG), then narrow_leg."""
+    cfg = W.CONFIGS[args.workload]
+    t0 = time.time()
+    fx = W.build_fixture(cfg, n_queries=64, r=0, prefer_gpu=True, log=lambda m: log("[fixture]", m),
+                         cache_dir=args.fixture_cache)
+    ctx = hd.Context(0)
+    ctx.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    ctx.load_descriptors(fx.V, dtype=args.descriptors or "bf16")
+    Qd = torch.from_numpy(fx.Q.reshape(1, 64, cfg.d)).to(torch.device("cuda:0"))
+    log(f"[narrow] fixture and load {time.time() - t0:.1f}s")
+    ip = int(args.iters.split(",")[-1]) if args.iters else 7
+    out = narrow_leg(args, cfg, ctx, Qd, ip, hd, W, torch, np)
+    ctx.close()
+    return {"mode": "narrow", "workload": f"vMF mixture N={cfg.n} d={cfg.d} clusters={cfg.clusters} "
+                                          f"kappa={cfg.kappa:g}, reciprocal kNN k={cfg.k} (nnz={fx.nnz}), "
+                                          f"alpha={cfg.alpha}, k_y={cfg.k_y}, top-100, plain CG",
+            **out}
 
 
 def knn_check(fx, cfg, rows, torch, np):

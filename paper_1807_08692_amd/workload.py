@@ -303,12 +303,85 @@ def top_eigs_arpack(n, rowptr, col, sval, r, seed):
     return Uf, w, res
 
 
+# Dense operands handed to the vendor routines below (sparse x dense
+# products, QR, GEMM) stay under 2^31 elements: those routines index with
+# 32-bit integers, and a 2M x 1250 double block (2.5e9 elements) is past it.
+_LIB_ELEMS = (1 << 31) - 1
+
+
+def _col_chunks(n, m, limit):
+    w = max(1, min(m, limit // max(n, 1)))
+    return [(a, min(m, a + w)) for a in range(0, m, w)]
+
+
+def _row_chunks(n, m, limit):
+    h = max(1, min(n, limit // max(m, 1)))
+    return [(a, min(n, a + h)) for a in range(0, n, h)]
+
+
+def _spmm_chunked(S, X, limit):
+    """S @ X column block by column block (each block n x w, w n < limit)."""
+    import torch
+    n, m = X.shape
+    out = torch.empty_like(X)
+    for a, b in _col_chunks(n, m, limit):
+        out[:, a:b] = S @ X[:, a:b].contiguous()
+    return out
+
+
+def _gram_chunked(A, B, limit):
+    """A^T B summed over row blocks in order."""
+    n, m = A.shape
+    G = None
+    for a, b in _row_chunks(n, max(m, B.shape[1]), limit):
+        g = A[a:b].T @ B[a:b]
+        G = g if G is None else G + g
+    return G
+
+
+def _rotate_chunked(X, Z, limit):
+    """X @ Z row block by row block."""
+    import torch
+    n, m = X.shape
+    out = torch.empty((n, Z.shape[1]), dtype=X.dtype, device=X.device)
+    for a, b in _row_chunks(n, max(m, Z.shape[1]), limit):
+        out[a:b] = X[a:b] @ Z
+    return out
+
+
+def _qr_chunked(X, limit):
+    """Orthonormal basis of X's columns: one Householder QR when X is small
+    enough, else TSQR (QR of each row block, QR of the stacked R factors,
+    and the block Q factors times the matching slices of the second Q)."""
+    import torch
+    n, m = X.shape
+    if n * m <= limit:
+        return torch.linalg.qr(X)[0]
+    blocks = _row_chunks(n, m, limit)
+    Qs, Rs = [], []
+    for a, b in blocks:
+        q, r_ = torch.linalg.qr(X[a:b])
+        Qs.append(q)
+        Rs.append(r_)
+    Q2, _ = torch.linalg.qr(torch.cat(Rs, dim=0))
+    out = torch.empty_like(X)
+    k = 0
+    for (a, b), q in zip(blocks, Qs):
+        w = q.shape[1]
+        out[a:b] = q @ Q2[k:k + w]
+        k += w
+    return out
+
+
 def top_eigs_chebyshev(n, rowptr, col, sval, r, seed, guard=None, degree=12,
-                       max_outer=60, tol=1e-9, time_budget=120.0, prefer_gpu=True):
+                       max_outer=60, tol=1e-9, time_budget=120.0, prefer_gpu=True,
+                       lib_elems=_LIB_ELEMS):
     """r algebraically largest eigenpairs by Chebyshev-filtered subspace
     iteration with Rayleigh-Ritz, in float64 (torch; GPU if present).
     The filter damps the interval [-1, b] with b the smallest Ritz value of
-    the block. Returns (U n x r, lambda r, residual norms r)."""
+    the block. Every sparse product, QR, Gram matrix and rotation works on
+    blocks of fewer than lib_elems elements. Returns (U n x r, lambda r,
+    residual norms r)."""
     import torch
     dev = _torch_device(prefer_gpu)
     if r == 0:
@@ -321,30 +394,36 @@ def top_eigs_chebyshev(n, rowptr, col, sval, r, seed, guard=None, degree=12,
                                 size=(n, n)).to(dev)
     g = torch.Generator(device="cpu").manual_seed(int(seed))
     X = torch.randn(n, m, generator=g, dtype=torch.float64).to(dev)
-    X, _ = torch.linalg.qr(X)
+    X = _qr_chunked(X, lib_elems)
     t0 = time.time()
     lam = None
     res = None
     for outer in range(max_outer):
-        SX = S @ X
-        H = X.T @ SX
+        SX = _spmm_chunked(S, X, lib_elems)
+        H = _gram_chunked(X, SX, lib_elems)
         H = 0.5 * (H + H.T)
         w, Z = torch.linalg.eigh(H)
         w, Z = w.flip(0), Z.flip(1)
-        X = X @ Z
-        SX = SX @ Z
+        X = _rotate_chunked(X, Z, lib_elems)
+        SX = _rotate_chunked(SX, Z, lib_elems)
         lam = w
-        res = torch.linalg.vector_norm(SX - X * w, dim=0)
+        res = torch.zeros(m, dtype=torch.float64, device=X.device)
+        for a, b in _row_chunks(n, m, lib_elems):
+            res += ((SX[a:b] - X[a:b] * w) ** 2).sum(0)
+        res = torch.sqrt(res)
+        del SX
         if float(res[:r].max()) < tol or time.time() - t0 > time_budget:
             break
         a, b = -1.0, float(w[-1])
         c, e = 0.5 * (a + b), 0.5 * (b - a)
         Y0 = X
-        Y1 = (S @ X - c * X) / e
+        Y1 = (_spmm_chunked(S, X, lib_elems) - c * X) / e
         for _ in range(2, degree + 1):
-            Y2 = 2.0 * (S @ Y1 - c * Y1) / e - Y0
+            Y2 = 2.0 * (_spmm_chunked(S, Y1, lib_elems) - c * Y1) / e - Y0
             Y0, Y1 = Y1, Y2
-        X, _ = torch.linalg.qr(Y1)
+        del Y0
+        X = _qr_chunked(Y1, lib_elems)
+        del Y1
     return (X[:, :r].cpu().numpy(), lam[:r].cpu().numpy(), res[:r].cpu().numpy())
 
 
@@ -486,6 +565,9 @@ def _build_fixture(cfg, n_queries, r, prefer_gpu, eig_time_budget, log) -> Fixtu
                                             time_budget=eig_time_budget, prefer_gpu=prefer_gpu)
         U = U64.astype(np.float32)
     say(f"eigs r={rr} max_res={float(res.max()) if res.size else 0:.2e} {time.time() - t0:.1f}s")
+    if dev.type == "cuda":  # hand the blocks' device memory back before the library allocates
+        import torch
+        torch.cuda.empty_cache()
     deg = np.diff(rowptr)
     info = dict(nnz=int(col.size), mean_degree=float(deg.mean()), isolated=int((deg == 0).sum()),
                 eig_max_residual=float(res.max()) if res.size else 0.0,
