@@ -375,7 +375,7 @@ def _qr_chunked(X, limit):
 
 def top_eigs_chebyshev(n, rowptr, col, sval, r, seed, guard=None, degree=12,
                        max_outer=60, tol=1e-9, time_budget=120.0, prefer_gpu=True,
-                       lib_elems=_LIB_ELEMS):
+                       lib_elems=_LIB_ELEMS, log=None):
     """r algebraically largest eigenpairs by Chebyshev-filtered subspace
     iteration with Rayleigh-Ritz, in float64 (torch; GPU if present).
     The filter damps the interval [-1, b] with b the smallest Ritz value of
@@ -412,7 +412,10 @@ def top_eigs_chebyshev(n, rowptr, col, sval, r, seed, guard=None, degree=12,
             res += ((SX[a:b] - X[a:b] * w) ** 2).sum(0)
         res = torch.sqrt(res)
         del SX
-        if float(res[:r].max()) < tol or time.time() - t0 > time_budget:
+        worst = float(res[:r].max())
+        if log:
+            log(f"eigs outer {outer}: max residual {worst:.2e} ({time.time() - t0:.1f}s)")
+        if worst < tol or time.time() - t0 > time_budget:
             break
         a, b = -1.0, float(w[-1])
         c, e = 0.5 * (a + b), 0.5 * (b - a)
@@ -562,7 +565,7 @@ def _build_fixture(cfg, n_queries, r, prefer_gpu, eig_time_budget, log) -> Fixtu
         U = U64.astype(np.float32)
     else:
         U64, lam, res = top_eigs_chebyshev(cfg.n, rowptr, col, s32.astype(np.float64), rr, se,
-                                            time_budget=eig_time_budget, prefer_gpu=prefer_gpu)
+                                            time_budget=eig_time_budget, prefer_gpu=prefer_gpu, log=log)
         U = U64.astype(np.float32)
     say(f"eigs r={rr} max_res={float(res.max()) if res.size else 0:.2e} {time.time() - t0:.1f}s")
     if dev.type == "cuda":  # hand the blocks' device memory back before the library allocates
