@@ -269,7 +269,7 @@ def main():
             for kv in args.tune.split(","):
                 k, v = kv.split("=")
                 ctx.set_tuning(k.strip(), int(v))
-            tune = {k: {"chosen": ctx.get_tuning(k), "times_ms": {}} for k in ("spmm_cpl", "utp_nt", "uc_nt")}
+            tune = {k: {"chosen": ctx.get_tuning(k), "times_ms": {}} for k in ("spmm_cpl", "utp_nt", "uc_nt", "spmm_bands")}
         elif not args.no_autotune:
             tune = ctx.autotune(B, 3)
         if tune:

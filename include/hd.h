@@ -164,11 +164,16 @@ typedef enum {
     HD_TUNE_SPMM_CPL = 0,  /* sparse product: query columns per lane (1, 2, 4) */
     HD_TUNE_UTP_NT = 1,    /* U1^T P, bfloat16 forms: 16-column tiles per wave */
     HD_TUNE_UC_NT = 2,     /* U1 C and the final combine, bfloat16 forms: same */
-    HD_TUNE_NKEYS = 3
+    HD_TUNE_SPMM_BANDS = 3, /* sparse product: source bands (1, 2, 4, 8): each
+                              row's neighbours split by neighbour id into that
+                              many runs, one launch per run, so that the rows
+                              of P gathered at one time fit the device's
+                              memory-side cache; bit-identical results */
+    HD_TUNE_NKEYS = 4
 } hd_tune_key;
 
 /* Set / read one launch parameter. Errors: HD_EINVAL (key, value not in
- * {0, 1, 2, 4}, NULL). */
+ * {0, 1, 2, 4}, or {0, 1, 2, 4, 8} for HD_TUNE_SPMM_BANDS; NULL). */
 int hd_set_tuning(hd_ctx *ctx, int32_t key, int32_t value);
 int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
 
@@ -178,9 +183,12 @@ int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
  * (one warm-up and `reps` timed launches each, on device scratch vectors of
  * the solver width, on the null stream) and keep the fastest in the
  * context; the built-in default is kept unless a candidate beats it by more
- * than 2%. times_ms (host, may be NULL) receives HD_TUNE_NKEYS x 3 mean
- * launch times in ms for the values 1, 2, 4 (-1 where a value does not fit
- * or the kernel is not used: no eigenvectors, or fp32 storage).
+ * than 2%. The sparse product's two parameters (columns per lane, source
+ * bands) are tuned together over every pair. times_ms (host, may be NULL)
+ * receives HD_TUNE_NKEYS x 4 mean launch times in ms for the values 1, 2,
+ * 4, 8 (-1 where a value does not fit or the kernel is not used: no
+ * eigenvectors, or fp32 storage); for the two sparse-product keys, the time
+ * of that value with the other key at its chosen value.
  * Synchronous. Errors: HD_ESTATE (no graph), HD_EINVAL (batch not in
  * [1, 1024], reps not in [1, 1000]).
  */
@@ -426,8 +434,11 @@ size_t hd_rank_noalloc_scratch_bytes(int32_t B, int64_t n, int32_t K);
  * access patterns of the query path's memory-bound kernels, by the library's
  * own kernels. mode: 0 = read a buffer of `bytes` once (16-byte loads),
  * 1 = copy it (read + write), 2 = gather whole rows of row_bytes at
- * pseudo-random row ids over the buffer (as many rows as it holds; the
- * sparse product's access to P), 3 = the sparse product's own gathers on
+ * pseudo-random row ids over the buffer (as many rows as it holds, at
+ * least 1 GiB of rows; the sparse product's access to P; a buffer that fits
+ * a cache gives that cache's gather rate; the ids are read from an int32
+ * array written before the timed launches, 64 per coalesced load, and
+ * counted in *bytes_out), 3 = the sparse product's own gathers on
  * the loaded graph without its arithmetic (for every edge, the neighbour's
  * row of an N x row_bytes matrix; `bytes` ignored). row_bytes: 256, 512 or
  * 1024 (modes 2, 3). bytes: a multiple of 4096 in [1 MiB, 64 GiB] (modes

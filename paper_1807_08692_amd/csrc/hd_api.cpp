@@ -218,10 +218,15 @@ int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, cons
         c->d = c->ldv = 0;
         c->v_dtype = HD_F32;
     }
+    std::vector<int32_t> cuts((size_t)n * 8);
+    hd::build_band_cuts(n, rowptr, col, cuts.data());
+    c->n = c->nnz = 0;  // nothing loaded until every copy has succeeded
     HIP_TRY(c->rowptr.ensure((size_t)(n + 1) * sizeof(int64_t)));
     HIP_TRY(c->col.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
     HIP_TRY(c->val.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(float)));
+    HIP_TRY(c->cut.ensure(cuts.size() * sizeof(int32_t)));
     HIP_TRY(hipMemcpy(c->rowptr.p, rowptr, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->cut.p, cuts.data(), cuts.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (nnz > 0) {
         HIP_TRY(hipMemcpy(c->col.p, col, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c->val.p, vals, (size_t)nnz * sizeof(float), hipMemcpyHostToDevice));
@@ -917,7 +922,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             }
             LAUNCH(K_SPMM, hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs,
                                            Q, ldb, -1.0, rp, c->part.as<double>(), none, s,
-                                           c->tv(HD_TUNE_SPMM_CPL, ldb)));
+                                           c->tv(HD_TUNE_SPMM_CPL, ldb), 0, nullptr, c->bands(), c->cuts()));
             LAUNCH(K_UPDATE_XP, hd::launch_filter_axpy(P, R, Q, nv2, flt->coeffs[i], 2.0, s));
         }
         temporal = P;
@@ -952,7 +957,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             LAUNCH(it == 1 ? K_SPMM_Y : K_SPMM,
                    hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, P, Q,
                                    ldb, o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb), 0,
-                                   it == 1 ? ymask : nullptr));
+                                   it == 1 ? ymask : nullptr, c->bands(), c->cuts()));
             LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, c->Dg.as<double>(),
                                                   rk));
             LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,
@@ -1006,7 +1011,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         LAUNCH(it == 1 ? K_SPMM_Y : K_SPMM,
                hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q, ldb,
                                o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb), 0,
-                               it == 1 ? ymask : nullptr));
+                               it == 1 ? ymask : nullptr, c->bands(), c->cuts()));
         LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s));
         LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), g, s));
         LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, g, nact_dev[it & 1], s));

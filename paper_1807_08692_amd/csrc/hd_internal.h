@@ -171,6 +171,7 @@ struct hd_ctx {
     // graph
     int64_t n = 0, nnz = 0;
     DevBuf rowptr, col, val;
+    DevBuf cut;  // source-band cut offsets of the sparse product (8 per row)
     // eigenpairs: U (fp32, N x rp) or Ub (bf16, N x rp, rows padded to 16) +
     // UbT (bf16, rp x ldut), both in fragment order (hd::frag_offset); the
     // two-term form stores the lo terms after the hi terms of each; the fp8
@@ -197,7 +198,7 @@ struct hd_ctx {
     DevBuf ymask;  // one bit per item: the rows where y (the first P) is nonzero
     hd::CgState st{};
     Timing timing;
-    int tune[HD_TUNE_NKEYS] = {0, 0, 0};  // launch parameters (0 = default)
+    int tune[HD_TUNE_NKEYS] = {0, 0, 0, 0};  // launch parameters (0 = default)
     // persistent CG for narrow batches: 0 off, 1 up to 16 queries, 2 up to 64;
     // the bound on each grid-barrier wait (spins); its barrier words
     int persist_mode = 0;
@@ -227,7 +228,13 @@ struct hd_ctx {
     const float *v_scale() const { return v_dtype == HD_FP8_E4M3 ? vscale.as<float>() : nullptr; }
     // launch parameter `key` for solver width ldb (0 = default when unset or
     // not fitting the width)
-    int tv(int key, int ldb) const { return hd::tile_param_ok(tune[key], ldb) ? tune[key] : 0; }
+    int tv(int key, int ldb) const {
+        if (key == HD_TUNE_SPMM_BANDS) return hd::band_param_ok(tune[key]) ? tune[key] : 1;
+        return hd::tile_param_ok(tune[key], ldb) ? tune[key] : 0;
+    }
+    // the sparse product's source-band count and cut offsets
+    int bands() const { return hd::band_param_ok(tune[HD_TUNE_SPMM_BANDS]) ? tune[HD_TUNE_SPMM_BANDS] : 1; }
+    const int32_t *cuts() const { return cut.as<int32_t>(); }
 };
 
 namespace hdi {

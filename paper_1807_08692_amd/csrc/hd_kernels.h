@@ -167,7 +167,13 @@ hipError_t launch_combine_narrow(int W, int64_t N, int B, const float *U, int rp
 hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, const float *val,
                        const float *P, const float *Zs, float *Q, int ldb, double alpha,
                        RowPart rp, double *gpart, IterGuard g, hipStream_t s, int cpl = 0,
-                       int width = 0, const uint32_t *rowmask = nullptr);
+                       int width = 0, const uint32_t *rowmask = nullptr, int bands = 1,
+                       const int32_t *cut = nullptr);
+// valid source-band counts of launch_spmm (1, 2, 4, 8)
+bool band_param_ok(int v);
+// cut[8 i + b - 1], b = 1..8: the number of row i's edges whose neighbour id
+// is below b N / 8 (host; rows with strictly increasing columns)
+void build_band_cuts(int64_t N, const int64_t *rowptr, const int32_t *col, int32_t *cut);
 
 // ---- eigenvector products on MFMA (k_ugemm.hip) ----
 // Number of row chunks of the split-K product U^T P.

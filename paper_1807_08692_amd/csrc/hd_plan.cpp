@@ -33,7 +33,7 @@ struct hd_plan {
 namespace {
 
 std::vector<intptr_t> snapshot(const hd_ctx *c) {
-    const DevBuf *bufs[] = {&c->rowptr, &c->col, &c->val, &c->U,    &c->Ub,   &c->UbT,  &c->lam,
+    const DevBuf *bufs[] = {&c->rowptr, &c->col, &c->val, &c->cut, &c->U,    &c->Ub,   &c->UbT,  &c->lam,
                             &c->V,      &c->Vb,  &c->X,   &c->R,    &c->P,    &c->Q,    &c->Z,
                             &c->Cpart,  &c->Cl,  &c->Cs,  &c->ClT,  &c->CsT,  &c->PT,   &c->part,
                             &c->scal,   &c->xbuf, &c->sim, &c->ybuf, &c->topk, &c->err, &c->qsplit,

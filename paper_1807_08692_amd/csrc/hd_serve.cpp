@@ -375,7 +375,7 @@ int hd_serve_step(hd_server *v, int32_t iters) {
         HIP_TRY(hd::launch_split_t(v->Cl.as<float>(), rk, ldb, ClT_hi, ClT_lo, g, s));
         HIP_TRY(hd::launch_spmm(N, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, P, Q,
                                 ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, w),
-                                w));
+                                w, nullptr, c->bands(), c->cuts()));
         HIP_TRY(hd::launch_cg_step_a(ldb, v->part.as<double>(), v->rp.nblk, v->st, g, s, v->Dg.as<double>(), rk));
         HIP_TRY(hd::launch_uc_update_r_bf16(N, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q,
                                             v->o.alpha, R, v->st.a, v->part.as<double>(), g, s,
@@ -408,7 +408,8 @@ int hd_serve_step(hd_server *v, int32_t iters) {
             Zs = v->Z.as<float>();
         }
         HIP_TRY(hd::launch_spmm(N, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q,
-                                ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb)));
+                                ldb, v->o.alpha, v->rp, v->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb),
+                                0, nullptr, c->bands(), c->cuts()));
         HIP_TRY(hd::launch_cg_step_a(ldb, v->part.as<double>(), v->rp.nblk, v->st, g, s));
         HIP_TRY(hd::launch_update_r(N, ldb, Q, R, v->rp, v->st.a, v->part.as<double>(), g, s));
         HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->rp.nblk, v->o.tol, v->st, g,

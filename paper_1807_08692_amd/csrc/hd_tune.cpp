@@ -31,8 +31,12 @@ int hd_set_tuning(hd_ctx *c, int32_t key, int32_t value) {
     g_err.clear();
     if (!c) return fail(HD_EINVAL, "hd_set_tuning: NULL context");
     if (key < 0 || key >= HD_TUNE_NKEYS) return fail(HD_EINVAL, "hd_set_tuning: key %d unknown", key);
-    if (value != 0 && value != 1 && value != 2 && value != 4)
+    if (key == HD_TUNE_SPMM_BANDS) {
+        if (value != 0 && !hd::band_param_ok(value))
+            return fail(HD_EINVAL, "hd_set_tuning: value %d not in {0, 1, 2, 4, 8}", value);
+    } else if (value != 0 && value != 1 && value != 2 && value != 4) {
         return fail(HD_EINVAL, "hd_set_tuning: value %d not in {0, 1, 2, 4}", value);
+    }
     c->tune[key] = value;
     return HD_OK;
 }
@@ -85,12 +89,13 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
         HIP_TRY(hd::launch_split_pt(n, ldb, c->P.as<float>(), c->ldut, PTh, PTl, hd::IterGuard{nullptr, 0}, s));
     }
     const hd::IterGuard none{nullptr, 0};
-    auto launch = [&](int key, int v) -> hipError_t {
+    // v: the key's value; bands: the sparse product's source bands
+    auto launch = [&](int key, int v, int bands) -> hipError_t {
         switch (key) {
         case HD_TUNE_SPMM_CPL:
             return hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(),
                                    c->P.as<float>(), c->Z.as<float>(), c->Q.as<float>(), ldb, 0.99, rp,
-                                   c->part.as<double>(), none, s, v);
+                                   c->part.as<double>(), none, s, v, 0, nullptr, bands, c->cuts());
         case HD_TUNE_UTP_NT:
             return hd::launch_ut_p_bf16(n, c->u_comp(), c->ldut, rk, PTh, PTl, ldb,
                                         c->Cpart.as<float>(), none, s, v);
@@ -104,37 +109,75 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int cand[3] = {1, 2, 4};
+    const int cand[4] = {1, 2, 4, 8};
     int err = HD_OK;
-    for (int key = 0; key < HD_TUNE_NKEYS && err == HD_OK; ++key) {
-        const bool used = key == HD_TUNE_SPMM_CPL || ubf;
+    // mean ms of one launch (one warm-up first); < 0 on error
+    auto time_one = [&](int key, int v, int bands) -> double {
+        hipError_t e = launch(key, v, bands);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int t = 0; t < reps && e == hipSuccess; ++t) e = launch(key, v, bands);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float el = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+        if (e != hipSuccess) {
+            err = fail(HD_EDEVICE, "hd_autotune: %s", hipGetErrorString(e));
+            return -1.0;
+        }
+        return (double)el / reps;
+    };
+    if (times_ms)
+        for (int j = 0; j < 4 * HD_TUNE_NKEYS; ++j) times_ms[j] = -1.0;
+    // the sparse product: every (columns per lane, bands) pair
+    {
+        double t[3][4];
+        double best = -1.0;
+        int bc = 0, bb = 0;
+        const int def_c = default_value(HD_TUNE_SPMM_CPL, ldb), def_b = 1;
+        double def_ms = -1.0;
+        for (int i = 0; i < 3 && err == HD_OK; ++i)
+            for (int j = 0; j < 4 && err == HD_OK; ++j) {
+                t[i][j] = -1.0;
+                if (!hd::tile_param_ok(cand[i], ldb)) continue;
+                const double ms = time_one(HD_TUNE_SPMM_CPL, cand[i], cand[j]);
+                if (ms < 0.0) break;
+                t[i][j] = ms;
+                if (cand[i] == def_c && cand[j] == def_b) def_ms = ms;
+                if (best < 0.0 || ms < best) {
+                    best = ms;
+                    bc = i;
+                    bb = j;
+                }
+            }
+        if (err == HD_OK && best >= 0.0) {
+            const bool keep = def_ms >= 0.0 && best >= kKeepDefault * def_ms;
+            c->tune[HD_TUNE_SPMM_CPL] = keep ? def_c : cand[bc];
+            c->tune[HD_TUNE_SPMM_BANDS] = keep ? def_b : cand[bb];
+            const int ci = keep ? (def_c == 1 ? 0 : def_c == 2 ? 1 : 2) : bc, bi = keep ? 0 : bb;
+            if (times_ms) {
+                for (int i = 0; i < 3; ++i) times_ms[HD_TUNE_SPMM_CPL * 4 + i] = t[i][bi];
+                for (int j = 0; j < 4; ++j) times_ms[HD_TUNE_SPMM_BANDS * 4 + j] = t[ci][j];
+            }
+        }
+    }
+    for (int key : {HD_TUNE_UTP_NT, HD_TUNE_UC_NT}) {
+        if (err != HD_OK || !ubf) break;
         double best = -1.0, def_ms = -1.0;
         int best_v = 0;
         const int def_v = default_value(key, ldb);
         for (int j = 0; j < 3; ++j) {
-            double ms = -1.0;
-            if (used && hd::tile_param_ok(cand[j], ldb)) {
-                hipError_t e = launch(key, cand[j]);
-                if (e == hipSuccess) e = hipEventRecord(e0, s);
-                for (int t = 0; t < reps && e == hipSuccess; ++t) e = launch(key, cand[j]);
-                if (e == hipSuccess) e = hipEventRecord(e1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float el = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
-                if (e != hipSuccess) {
-                    err = fail(HD_EDEVICE, "hd_autotune: %s", hipGetErrorString(e));
-                    break;
-                }
-                ms = (double)el / reps;
-                if (cand[j] == def_v) def_ms = ms;
-                if (best < 0.0 || ms < best) {
-                    best = ms;
-                    best_v = cand[j];
-                }
+            if (!hd::tile_param_ok(cand[j], ldb)) continue;
+            const double ms = time_one(key, cand[j], 1);
+            if (ms < 0.0) break;
+            if (cand[j] == def_v) def_ms = ms;
+            if (best < 0.0 || ms < best) {
+                best = ms;
+                best_v = cand[j];
             }
-            if (times_ms) times_ms[key * 3 + j] = ms;
+            if (times_ms) times_ms[key * 4 + j] = ms;
         }
-        if (used && best_v != 0) c->tune[key] = (def_ms >= 0.0 && best >= kKeepDefault * def_ms) ? def_v : best_v;
+        if (err == HD_OK && best_v != 0)
+            c->tune[key] = (def_ms >= 0.0 && best >= kKeepDefault * def_ms) ? def_v : best_v;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

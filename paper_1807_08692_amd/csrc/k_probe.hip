@@ -3,8 +3,9 @@
 // (the ceilings the sparse product and the vector updates are compared with).
 //   stream : every 16-byte word of a buffer read once (grid stride)
 //   copy   : a buffer read and written once
-//   gather : whole rows (row_bytes each, one wave per row) at pseudo-random
-//            row ids over the buffer, as the sparse product gathers rows of P
+//   gather : whole rows (row_bytes each) at pseudo-random row ids over the
+//            buffer, read from an id array as the sparse product reads its
+//            column ids, 16 gathers in flight per wave
 //   graph  : the sparse product's own gathers without its arithmetic: for
 //            every edge of the loaded graph the neighbour's row of an
 //            N x (row_bytes / 4) matrix, rows in CSR order, one wave per row
@@ -37,20 +38,47 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// One wave per gathered row; V floats per lane (row = 64 V floats).
+// The row ids of the gather probe, pseudo-random over [0, rows), written
+// once before the timed launches so that the timed kernel does no hashing.
+__global__ __launch_bounds__(kBlock) void k_probe_ids(int32_t *__restrict__ ids, int64_t n, int64_t rows,
+                                                      uint64_t seed) {
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += (int64_t)gridDim.x * kBlock)
+        ids[g] = (int32_t)(mix64(seed + (uint64_t)g) % (uint64_t)rows);
+}
+
+// One wave per run of 64 ids (read with one coalesced load, as the sparse
+// product reads a row's column ids), each id's row (64 V floats) gathered
+// whole, 16 gathers in flight.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_probe_gather(const float *__restrict__ a, int64_t rows,
-                                                         int64_t ngather, uint64_t seed,
+__global__ __launch_bounds__(kBlock) void k_probe_gather(const float *__restrict__ a,
+                                                         const int32_t *__restrict__ ids, int64_t ngather,
                                                          float *__restrict__ out) {
     const int lane = threadIdx.x % kWave;
     const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
     float s = 0.f;
-    for (int64_t g = w0; g < ngather; g += nw) {
-        const int64_t row = (int64_t)(mix64(seed + (uint64_t)g) % (uint64_t)rows);
-        const float *p = a + (size_t)row * (64 * V) + (size_t)lane * V;
+    for (int64_t g0 = w0 * kWave; g0 < ngather; g0 += nw * kWave) {
+        const int id = g0 + lane < ngather ? ids[g0 + lane] : 0;
+        const int cnt = (int)(ngather - g0 < kWave ? ngather - g0 : kWave);
+        int t = 0;
+        for (; t + 16 <= cnt; t += 16) {
+            float pv[16][V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) s += p[v];
+            for (int u = 0; u < 16; ++u) {
+                const float *p = a + (size_t)bcast_i(id, t + u) * (64 * V) + (size_t)lane * V;
+#pragma unroll
+                for (int v = 0; v < V; ++v) pv[u][v] = p[v];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) s += pv[u][v];
+        }
+        for (; t < cnt; ++t) {
+            const float *p = a + (size_t)bcast_i(id, t) * (64 * V) + (size_t)lane * V;
+#pragma unroll
+            for (int v = 0; v < V; ++v) s += p[v];
+        }
     }
     out[(size_t)blockIdx.x * kBlock + threadIdx.x] = s;
 }
@@ -112,11 +140,12 @@ extern "C" int hd_probe_memory(hd_ctx *c, int32_t mode, int64_t bytes, int32_t r
     HIP_TRY(hipSetDevice(c->device));
     const int64_t buf_bytes = mode == 3 ? c->n * (int64_t)row_bytes : bytes;
     const int grid = 2048;
-    DevBuf a, b, out;
+    DevBuf a, b, out, ids;
     auto cleanup = [&]() {
         a.release();
         b.release();
         out.release();
+        ids.release();
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = HD_OK;
@@ -135,7 +164,22 @@ extern "C" int hd_probe_memory(hd_ctx *c, int32_t mode, int64_t bytes, int32_t r
         }
         const int V = row_bytes / 256;
         const int64_t rows = buf_bytes / row_bytes;
-        const int64_t ngather = rows;  // as many rows gathered as the buffer holds
+        // as many rows gathered as the buffer holds, and at least 1 GiB of
+        // them, so that a buffer small enough to stay in a cache still gives
+        // a launch long enough to time
+        const int64_t min_rows = ((int64_t)1 << 30) / row_bytes;
+        const int64_t ngather = rows > min_rows ? rows : min_rows;
+        if (mode == 2) {
+            if ((e = ids.ensure((size_t)ngather * sizeof(int32_t))) != hipSuccess) {
+                rc = fail(e == hipErrorOutOfMemory ? HD_ENOMEM : HD_EDEVICE, "hd_probe_memory: %s", hipGetErrorString(e));
+                break;
+            }
+            hd::k_probe_ids<<<grid, hd::kBlock>>>(ids.as<int32_t>(), ngather, rows, 12345u);
+            if ((e = hipGetLastError()) != hipSuccess) {
+                rc = fail(HD_EDEVICE, "hd_probe_memory: %s", hipGetErrorString(e));
+                break;
+            }
+        }
         double moved = 0.0;
         auto launch = [&]() -> hipError_t {
             switch (mode) {
@@ -146,9 +190,9 @@ extern "C" int hd_probe_memory(hd_ctx *c, int32_t mode, int64_t bytes, int32_t r
                     hd::k_probe_copy<<<grid, hd::kBlock>>>(a.as<float4>(), b.as<float4>(), (size_t)buf_bytes / 16);
                     break;
                 case 2:
-                    if (V == 1) hd::k_probe_gather<1><<<grid, hd::kBlock>>>(a.as<float>(), rows, ngather, 12345u, out.as<float>());
-                    else if (V == 2) hd::k_probe_gather<2><<<grid, hd::kBlock>>>(a.as<float>(), rows, ngather, 12345u, out.as<float>());
-                    else hd::k_probe_gather<4><<<grid, hd::kBlock>>>(a.as<float>(), rows, ngather, 12345u, out.as<float>());
+                    if (V == 1) hd::k_probe_gather<1><<<grid, hd::kBlock>>>(a.as<float>(), ids.as<int32_t>(), ngather, out.as<float>());
+                    else if (V == 2) hd::k_probe_gather<2><<<grid, hd::kBlock>>>(a.as<float>(), ids.as<int32_t>(), ngather, out.as<float>());
+                    else hd::k_probe_gather<4><<<grid, hd::kBlock>>>(a.as<float>(), ids.as<int32_t>(), ngather, out.as<float>());
                     break;
                 default:
                     if (V == 1) hd::k_probe_graph<1><<<grid, hd::kBlock>>>(c->n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), a.as<float>(), out.as<float>());
@@ -161,7 +205,7 @@ extern "C" int hd_probe_memory(hd_ctx *c, int32_t mode, int64_t bytes, int32_t r
         switch (mode) {
             case 0: moved = (double)buf_bytes; break;
             case 1: moved = 2.0 * (double)buf_bytes; break;
-            case 2: moved = (double)ngather * row_bytes; break;
+            case 2: moved = (double)ngather * (row_bytes + 4); break;
             default: moved = (double)c->nnz * row_bytes + 12.0 * (double)c->n + 4.0 * (double)c->nnz; break;
         }
         if ((e = launch()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {

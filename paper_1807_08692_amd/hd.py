@@ -103,7 +103,7 @@ def quantize_fp8(A, per_column: bool):
 
 
 # Launch parameters (hd_tune_key)
-TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2}
+TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2, "spmm_bands": 3}
 
 
 class hd_eig_opts(ctypes.Structure):
@@ -284,11 +284,11 @@ class Context:
     def autotune(self, batch: int, reps: int = 5) -> dict:
         """Time every candidate launch parameter at this batch size and keep
         the fastest; returns {key: {value: mean ms}} and the chosen values."""
-        t = (ctypes.c_double * (3 * len(TUNE_KEYS)))()
+        t = (ctypes.c_double * (4 * len(TUNE_KEYS)))()
         _check(lib().hd_autotune(self._h, int(batch), int(reps), t))
         out = {}
         for name, k in TUNE_KEYS.items():
-            out[name] = {"times_ms": {v: t[3 * k + j] for j, v in enumerate((1, 2, 4)) if t[3 * k + j] >= 0},
+            out[name] = {"times_ms": {v: t[4 * k + j] for j, v in enumerate((1, 2, 4, 8)) if t[4 * k + j] >= 0},
                          "chosen": self.get_tuning(name)}
         return out
 

@@ -108,6 +108,15 @@ def test_full_size_parity(setup):
         hyb = ctx.query_batch(q, max_iter=4, rank_r=-1, **kw)
         pl = ctx.query_batch(q, max_iter=7, rank_r=0, **kw)
         torch.cuda.synchronize()
+        # every source-band count of the sparse product gives the same bits
+        chosen = ctx.get_tuning("spmm_bands")
+        for bands in (1, 2, 4, 8):
+            ctx.set_tuning("spmm_bands", bands)
+            xb = ctx.query_batch(q, max_iter=4, rank_r=-1, **kw)["x"]
+            torch.cuda.synchronize()
+            assert torch.equal(xb, hyb["x"]), (bands, chosen)
+            del xb
+        ctx.set_tuning("spmm_bands", chosen)
         # the two-term form as the oracle sees it (hi + lo on the support)
         u32 = st["vals"].astype(np.float32)
         hi = bf16_round(u32)

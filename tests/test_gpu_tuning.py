@@ -43,31 +43,46 @@ def run(ctx, fx, torch_dev, B):
     return out["x"].cpu().numpy(), out["rank_ids"].cpu().numpy(), out["iters"].copy()
 
 
+KEYS = ("spmm_cpl", "utp_nt", "uc_nt", "spmm_bands")
+VALUES = {"spmm_cpl": (1, 2, 4), "utp_nt": (1, 2, 4), "uc_nt": (1, 2, 4), "spmm_bands": (1, 2, 4, 8)}
+
+
 @pytest.mark.parametrize("B", [40, 130, 300])
 def test_every_setting_same_result(ctx, fx, torch_dev, B):
-    for k in ("spmm_cpl", "utp_nt", "uc_nt"):
+    for k in KEYS:
         ctx.set_tuning(k, 0)
     x0, r0, it0 = run(ctx, fx, torch_dev, B)
-    for key in ("spmm_cpl", "utp_nt", "uc_nt"):
-        for v in (1, 2, 4):
+    for key in KEYS:
+        for v in VALUES[key]:
             ctx.set_tuning(key, v)
             x, r, it = run(ctx, fx, torch_dev, B)
             ctx.set_tuning(key, 0)
             assert np.array_equal(it, it0), (key, v)
             assert np.array_equal(r, r0), (key, v)
             assert np.array_equal(x, x0), (key, v, float(np.abs(x - x0).max()))
+    # source bands together with every column tiling of the sparse product
+    for cpl in (1, 2, 4):
+        for bands in (2, 8):
+            ctx.set_tuning("spmm_cpl", cpl)
+            ctx.set_tuning("spmm_bands", bands)
+            x, r, it = run(ctx, fx, torch_dev, B)
+            ctx.set_tuning("spmm_cpl", 0)
+            ctx.set_tuning("spmm_bands", 0)
+            assert np.array_equal(x, x0) and np.array_equal(r, r0) and np.array_equal(it, it0), (cpl, bands)
 
 
 def test_autotune_keeps_valid_values(ctx, fx, torch_dev):
-    for k in ("spmm_cpl", "utp_nt", "uc_nt"):
+    for k in KEYS:
         ctx.set_tuning(k, 0)
     x0, r0, _ = run(ctx, fx, torch_dev, 200)
     res = ctx.autotune(256, reps=2)
     for key, rec in res.items():
-        assert rec["chosen"] in (0, 1, 2, 4)
+        assert rec["chosen"] in (0,) + VALUES[key]
         for v, ms in rec["times_ms"].items():
             assert ms > 0.0
     assert res["spmm_cpl"]["chosen"] in (1, 2, 4)
+    assert res["spmm_bands"]["chosen"] in (1, 2, 4, 8)
+    assert len(res["spmm_bands"]["times_ms"]) == 4
     x, r, _ = run(ctx, fx, torch_dev, 200)
     assert np.array_equal(r, r0) and np.array_equal(x, x0)
 
@@ -76,4 +91,11 @@ def test_set_tuning_rejects_bad_values(ctx):
     from paper_1807_08692_amd import hd
     with pytest.raises(hd.HDError):
         ctx.set_tuning("spmm_cpl", 3)
+    with pytest.raises(hd.HDError):
+        ctx.set_tuning("spmm_cpl", 8)
+    with pytest.raises(hd.HDError):
+        ctx.set_tuning("spmm_bands", 3)
+    with pytest.raises(hd.HDError):
+        ctx.set_tuning("spmm_bands", 16)
     assert ctx.get_tuning("spmm_cpl") in (0, 1, 2, 4)
+    assert ctx.get_tuning("spmm_bands") in (0, 1, 2, 4, 8)
