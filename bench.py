@@ -113,18 +113,26 @@ def parse():
     p.add_argument("--c2", type=int, default=None,
                    help="1: also run the fp32 100,000-item configuration (r = 400, 64 queries, CG to "
                         "relative residual 1e-5) as a leg of the line (default 1 for n1m)")
-    p.add_argument("--mode", choices=["line", "r-sweep", "serve-dbs", "narrow"], default="line",
+    p.add_argument("--eig-budget", type=float, default=150.0,
+                   help="eigs mode: time budget of the on-device eigensolver (seconds)")
+    p.add_argument("--mode", choices=["line", "r-sweep", "serve-dbs", "narrow", "eigs", "locality"],
+                   default="line",
                    help="line: the benchmark line (default); r-sweep: the space-time sweep on the "
                         "workload (--workload n2m), iterations per rank for rel-err 1e-3 and the batch "
                         "time; serve-dbs: three resident databases (n50k, n300k, n1m) under Poisson "
                         "load; narrow: the narrow-batch leg alone (plain CG on the workload's graph, "
-                        "no eigenpairs needed, --iters sets its iteration count, default 7)")
+                        "no eigenpairs needed, --iters sets its iteration count, default 7); eigs: "
+                        "the on-device eigensolver on the workload's graph (r of the workload, "
+                        "--eig-budget); locality: the sparse product on the workload's graph in its "
+                        "own id order and after a reverse Cuthill-McKee relabelling")
     p.add_argument("--r-sweep", default="0,100,400,1000",
                    help="ranks of the r-sweep mode (prefixes of the largest, which is computed)")
     p.add_argument("--sweep-steps", type=int, default=5)
     p.add_argument("--r-cost", default="4000",
                    help="ranks of the r-sweep mode timed for cost only: the computed eigenvectors plus "
                         "columns with eigenvalue 0, which leave x unchanged (empty: none)")
+    p.add_argument("--serve-dbs-requests", type=int, default=10000,
+                   help="serve-dbs mode: requests per offered rate")
     p.add_argument("--serve-budget-gb", type=float, default=40.0,
                    help="HBM budget of each server in the serve-dbs mode")
     p.add_argument("--tol-mode", action="store_true",
@@ -185,6 +193,12 @@ def main():
         return
     if args.mode == "narrow":
         print(json.dumps(narrow_mode(args, hd, W, torch, np)), flush=True)
+        return
+    if args.mode == "eigs":
+        print(json.dumps(eigs_mode(args, hd, W, torch, np)), flush=True)
+        return
+    if args.mode == "locality":
+        print(json.dumps(locality_mode(args, hd, W, torch, np)), flush=True)
         return
     cfg = W.CONFIGS[args.workload]
     big = args.workload in ("n1m", "n2m")
@@ -1039,7 +1053,7 @@ def serve_dbs_mode(args, hd, W, torch, np):
            "hbm_budget_per_server_bytes": budget, "iteration_caps": "uniform 5..20 per request (seeded)",
            "routing": "uniform over the three databases (seeded)", "rates": []}
     for i, rate in enumerate(rates):
-        n = int(min(args.serve_requests, max(600, 3 * rate)))
+        n = int(args.serve_dbs_requests)
         arr = serve.poisson_arrivals(rate, n, seed=101 + i)
         route = rng.integers(0, 3, size=n)
         caps = rng.integers(5, 21, size=n)
@@ -1078,6 +1092,14 @@ def probes_leg(ctx, ldb, roof, np):
         r = ctx.probe_memory(mode, 1 << 30, rb, 5)
         out[name] = {"ms": round(r["ms"], 4), "bytes": r["bytes"], "GB_s": round(r["GB_s"], 1)}
         log(f"[probe] {name}: {r['ms']:.3f} ms, {r['GB_s']:.0f} GB/s")
+    # random 1 KiB row gathers over buffers from L2-sized to far past the
+    # Infinity Cache (at least 1 GiB of rows gathered each time)
+    sweep = {}
+    for mib in (16, 64, 128, 256, 512, 1024, 4096):
+        r = ctx.probe_memory("gather", mib << 20, 1024, 5)
+        sweep[str(mib)] = round(r["GB_s"], 1)
+    out["gather_1KiB_rows_by_buffer_MiB"] = sweep
+    log("[probe] 1 KiB row gathers by buffer size (MiB: GB/s): " + ", ".join(f"{k}: {v:.0f}" for k, v in sweep.items()))
     if roof.get("kernel") in ("spmm",):
         floor_ms = out["graph_gather"]["ms"]
         out["spmm_vs_graph_gather"] = {
@@ -1198,6 +1220,99 @@ def narrow_mode(args, hd, W, torch, np):
                                           f"kappa={cfg.kappa:g}, reciprocal kNN k={cfg.k} (nnz={fx.nnz}), "
                                           f"alpha={cfg.alpha}, k_y={cfg.k_y}, top-100, plain CG",
             **out}
+
+
+def eigs_mode(args, hd, W, torch, np):
+    """The on-device eigensolver (hd_compute_eigs: Chebyshev-filtered
+    subspace iteration in FP64 on the library's kernels) at the workload's
+    rank on its graph, within --eig-budget seconds: time, outer steps and
+    the largest residual norm ||S u - lambda u|| reached."""
+    cfg = W.CONFIGS[args.workload]
+    t0 = time.time()
+    fx = W.build_fixture(cfg, n_queries=cfg.batch, r=0, prefer_gpu=True, log=lambda m: log("[fixture]", m),
+                         cache_dir=args.fixture_cache)
+    ctx = hd.Context(0)
+    ctx.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    log(f"[eigs] graph {time.time() - t0:.1f}s, nnz {fx.nnz}")
+    t1 = time.perf_counter()
+    ev = ctx.compute_eigs(cfg.r, "bf16x2", tol=1e-9, max_outer=400, seed=11, lambda_min=-1.0,
+                          time_budget_s=args.eig_budget, want_U=False)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t1
+    outer = ctx.eig_outer()
+    log(f"[eigs] r={cfg.r}: {secs:.1f}s, {outer} outer steps, max residual {ev['resid'].max():.2e}, "
+        f"lambda in [{ev['lam'].min():.4f}, {ev['lam'].max():.4f}]")
+    ctx.close()
+    return {"mode": "eigs", "workload": f"vMF mixture N={cfg.n} d={cfg.d} clusters={cfg.clusters} "
+                                        f"kappa={cfg.kappa:g}, reciprocal kNN k={cfg.k} (nnz={fx.nnz})",
+            "r": cfg.r, "block": cfg.r + max(20, cfg.r // 4), "filter_degree": 12, "seconds": round(secs, 2),
+            "time_budget_s": args.eig_budget, "outer_steps": outer,
+            "max_residual": float(f"{ev['resid'].max():.3e}"),
+            "median_residual": float(f"{np.median(ev['resid']):.3e}"),
+            "lambda_max": float(ev["lam"].max()), "lambda_r": float(ev["lam"].min()),
+            "note": "FP64 throughout; the sparse products, Chebyshev recurrence, N x m Gram matrices and "
+                    "rotations in the library's kernels (FP64 matrix cores); Cholesky, its inverse and the "
+                    "m x m eigenproblem in rocSOLVER; the result is loaded as two-term bfloat16 U1"}
+
+
+def locality_mode(args, hd, W, torch, np):
+    """The sparse product's sensitivity to the graph's id order: the
+    workload's graph as generated (ids in random order with respect to the
+    clusters, as in a real database) and relabelled by reverse Cuthill-McKee
+    (scipy, on the host), each loaded into its own context. Per order: how
+    far apart the two ends of an edge lie (median |i - j| / N, the share of
+    edges within 4,096 rows: 4 MiB of 256 fp32 columns, one XCD's L2), the
+    graph-gather probe and the autotuned sparse product at the headline
+    width."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    cfg = W.CONFIGS[args.workload]
+    t0 = time.time()
+    fx = W.build_fixture(cfg, n_queries=cfg.batch, r=0, prefer_gpu=True, log=lambda m: log("[fixture]", m),
+                         cache_dir=args.fixture_cache)
+    n = fx.n
+    A = sp.csr_matrix((fx.s, fx.col, fx.rowptr), shape=(n, n))
+    t1 = time.time()
+    perm = np.asarray(reverse_cuthill_mckee(A, symmetric_mode=True), np.int64)
+    t_rcm = time.time() - t1
+    log(f"[locality] graph {t1 - t0:.1f}s, nnz {fx.nnz}; reverse Cuthill-McKee {t_rcm:.1f}s")
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    B = cfg.batch
+    ldb = 1 << max(6, (B - 1).bit_length())
+    orders = {"generated": None, "reverse_cuthill_mckee": perm}
+    out = {"mode": "locality", "workload": f"vMF mixture N={n} d={cfg.d} clusters={cfg.clusters} "
+                                           f"kappa={cfg.kappa:g}, reciprocal kNN k={cfg.k} (nnz={fx.nnz})",
+           "solver_width": ldb, "rcm_seconds": round(t_rcm, 1), "orders": {}}
+    for name, pm in orders.items():
+        if pm is None:
+            rowptr, col, val = fx.rowptr, fx.col, fx.s
+        else:
+            Ap = A[pm][:, pm].tocsr()
+            Ap.sort_indices()
+            rowptr, col, val = Ap.indptr.astype(np.int64), Ap.indices.astype(np.int32), Ap.data.astype(np.float32)
+        rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+        dist = np.abs(rows - col.astype(np.int64))
+        rec = {"median_edge_span_over_n": float(f"{np.median(dist) / n:.4g}"),
+               "edges_within_4096_rows": float(f"{np.mean(dist < 4096):.4g}"),
+               "bandwidth": int(dist.max())}
+        del rows, dist
+        ctx = hd.Context(0)
+        ctx.load_graph(n, rowptr, col, val)
+        pr = ctx.probe_memory("graph", 0, 4 * ldb, 5)
+        tune = ctx.autotune(B, 5)
+        cpl = tune["spmm_cpl"]["chosen"]
+        bands = tune["spmm_bands"]["chosen"]
+        rec["graph_gather"] = {"ms": round(pr["ms"], 4), "GB_s": round(pr["GB_s"], 1)}
+        rec["spmm_ms"] = round(min(tune["spmm_cpl"]["times_ms"].values()), 4)
+        rec["spmm_tuning"] = {"cpl": cpl, "bands": bands, "times_ms_by_cpl": tune["spmm_cpl"]["times_ms"],
+                              "times_ms_by_bands": tune["spmm_bands"]["times_ms"]}
+        ctx.close()
+        out["orders"][name] = rec
+        log(f"[locality] {name}: median span {rec['median_edge_span_over_n']:.3g} N, "
+            f"{100 * rec['edges_within_4096_rows']:.2f}% of edges within 4096 rows; graph gather "
+            f"{pr['ms']:.3f} ms ({pr['GB_s']:.0f} GB/s); sparse product {rec['spmm_ms']:.3f} ms")
+    return out
 
 
 def knn_check(fx, cfg, rows, torch, np):

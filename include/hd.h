@@ -257,6 +257,9 @@ typedef struct {
 } hd_eig_opts;
 int hd_compute_eigs(hd_ctx *ctx, int32_t r, int32_t dtype, const hd_eig_opts *opts, double *lambda_out,
                     double *resid_out, float *U_out);
+/* Rayleigh-Ritz steps taken by the last successful hd_compute_eigs on ctx
+ * (0 before any, and for NULL). */
+int32_t hd_eig_steps(const hd_ctx *ctx);
 
 /*
  * SHybrid (Section 6.2): load a sparsified U1 (most entries set to zero,

@@ -820,17 +820,26 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     }
 
     // ---- CG set-up: X = 0, R = P = y, rho0 = y^T y ----
+    // With the dense bfloat16 forms and plain CG, the first iteration reads
+    // R and P only on the rows of y (row mask) and X nowhere, and writes all
+    // three everywhere: only the rows of y are zeroed before the scatter.
+    // The other paths (fp32 or sparse U1, filters, no iteration) fill X, R
+    // and P.
     float *X = c->X.as<float>(), *R = c->R.as<float>(), *P = c->P.as<float>(), *Q = c->Q.as<float>();
     const size_t nv = (size_t)n * ldb;
-    LAUNCH(K_FILL, hd::launch_fill_zero(X, nv, s));
-    LAUNCH(K_FILL, hd::launch_fill_zero(R, nv, s));
-    LAUNCH(K_FILL, hd::launch_fill_zero(P, nv, s));
+    const bool nofill = !flt && o->max_iter >= 1 && (fused || rk == 0);
+    if (!nofill) {
+        LAUNCH(K_FILL, hd::launch_fill_zero(X, nv, s));
+        LAUNCH(K_FILL, hd::launch_fill_zero(R, nv, s));
+        LAUNCH(K_FILL, hd::launch_fill_zero(P, nv, s));
+    }
     LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(c->err.p), 2, s));
     // the rows of y: the first product gathers only these rows of P (= y)
     const size_t nmask = (size_t)(n + 31) / 32;
     HIP_TRY(c->ymask.ensure(nmask * sizeof(uint32_t)));
     uint32_t *ymask = c->ymask.as<uint32_t>();
     LAUNCH(K_FILL, hd::launch_fill_zero(reinterpret_cast<float *>(ymask), nmask, s));
+    if (nofill) LAUNCH(K_FILL, hd::launch_zero_yrows(B, ky, yi, n, ldb, R, P, s));
     LAUNCH(K_SCATTER, hd::launch_scatter_y(B, ky, yi, yv, n, ldb, R, P, c->err.as<int32_t>(), s, nullptr, ymask));
     LAUNCH(K_COLSQ, hd::launch_ynorm_part(B, ky, yi, n, ldb, R, c->part.as<double>(), s));
     LAUNCH(K_SCALAR, hd::launch_cg_init(B, ldb, c->part.as<double>(), 1, st, s));
@@ -942,6 +951,12 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     auto enqueue_iter = [&](int it) -> int {
         c->timing.tag = it;
         const hd::IterGuard g{nact_dev[(it - 1) & 1], ntile};
+        // first iteration without fills: the updates read R and P on the
+        // rows of y only, and always run (they write X, R and P everywhere;
+        // a = 0 leaves a stopped column's values as they are)
+        const bool m1 = nofill && it == 1;
+        const uint32_t *rm = m1 ? ymask : nullptr;
+        const hd::IterGuard gu = m1 ? hd::IterGuard{nullptr, 0} : g;
         if (fused) {
             uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
             if (it > 1) {
@@ -961,15 +976,16 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
             LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, c->Dg.as<double>(),
                                                   rk));
             LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,
-                                                      st.a, c->part.as<double>(), g, s,
-                                                      c->tv(HD_TUNE_UC_NT, ldb)));
+                                                      st.a, c->part.as<double>(), gu, s,
+                                                      c->tv(HD_TUNE_UC_NT, ldb), 0, rm));
             LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), nrb, o->tol, st, g, nact_dev[it & 1],
                                                   s));
             if (it == o->max_iter)  // nothing reads the new P or its split transpose
-                LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s, 0, true));
+                LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, true,
+                                                         rm));
             else
                 LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut,
-                                                            PTh, PTl, g, s));
+                                                            PTh, PTl, gu, s, rm));
             if (!graph) {
                 HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),
                                        hipMemcpyDeviceToHost, s));
@@ -1013,16 +1029,16 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                                o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb), 0,
                                it == 1 ? ymask : nullptr, c->bands(), c->cuts()));
         LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s));
-        LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), g, s));
+        LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), gu, s, rm));
         LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, g, nact_dev[it & 1], s));
         if (it == o->max_iter) {  // the last iteration: nothing reads the new P
-            LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s, 0, true));
+            LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, true, rm));
         } else if (ubf && rk > 0) {
             uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
             LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut,
-                                                        PTh, PTl, g, s));
+                                                        PTh, PTl, gu, s, rm));
         } else {
-            LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, g, s));
+            LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, false, rm));
         }
         if (!graph) {
             HIP_TRY(hipMemcpyAsync(c->h_pinned + 64 * (it & 1), nact_dev[it & 1], ntile * sizeof(int32_t),

@@ -75,6 +75,11 @@ __device__ __forceinline__ bool all_stopped(const int32_t *nact, int ntile) {
     return s == 0;
 }
 
+// Row i is in a row mask (bit i of word i / 32; nullptr: every row is).
+__device__ __forceinline__ bool row_live(const uint32_t *m, int64_t i) {
+    return !m || ((m[i >> 5] >> (i & 31)) & 1u);
+}
+
 // Sum of a double over the 64 lanes of a wavefront (fixed butterfly order).
 __device__ __forceinline__ double wave_sum_f64(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

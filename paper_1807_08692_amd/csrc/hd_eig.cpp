@@ -220,3 +220,5 @@ int hd_compute_eigs(hd_ctx *c, int32_t r, int32_t dtype, const hd_eig_opts *opts
 }
 
 }  // extern "C"
+
+extern "C" int32_t hd_eig_steps(const hd_ctx *c) { return c ? c->eig_outer : 0; }

@@ -70,6 +70,11 @@ RowPart make_row_part(int64_t N);
 
 // ---- CG vector kernels (k_cg.hip) ----
 hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s);
+// zero rows ids[t][u] (t < B, u < ky; ids outside [0, N) skipped) of R and P,
+// all ldb columns: before the y scatter when the first CG iteration runs
+// with the y row mask instead of full fills of X, R and P
+hipError_t launch_zero_yrows(int B, int ky, const int32_t *ids, int64_t N, int ldb, float *R, float *P,
+                             hipStream_t s);
 // colmap (nullptr = identity): y row t goes to solver column colmap[t];
 // rowmask (nullptr = none): bit id of word id / 32 is set for every y id
 hipError_t launch_scatter_y(int B, int ky, const int32_t *ids, const float *vals, int64_t N,
@@ -85,8 +90,12 @@ hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState 
 // rows) when given
 hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, IterGuard g,
                             hipStream_t s, const double *gpart2 = nullptr, int nblk2 = 0);
+// rowmask (the updates below too; nullptr = none): the first CG iteration
+// after launch_zero_yrows, rows outside the mask taken as zero in R and P
+// (and X as zero) without reading them; every row is written
 hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
-                           const double *a, double *part, IterGuard g, hipStream_t s);
+                           const double *a, double *part, IterGuard g, hipStream_t s,
+                           const uint32_t *rowmask = nullptr);
 // writes the new per-tile active counts to nact_out
 hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
                             IterGuard g, int32_t *nact_out, hipStream_t s);
@@ -95,14 +104,14 @@ hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, C
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
                             IterGuard g, hipStream_t s, int width = 0,
-                            bool x_only = false);
+                            bool x_only = false, const uint32_t *rowmask = nullptr);
 // update_xp that also writes the new P as its split transpose (bfloat16
 // forms; PT_hi / PT_lo ldb x ldpt in fragment order, ldpt a multiple of 64
 // >= N)
 hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
                                const double *a, const double *beta, const int32_t *active,
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
-                               hipStream_t s);
+                               hipStream_t s, const uint32_t *rowmask = nullptr);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 // colmap (nullptr = identity, B columns of ldb): y row t -> column colmap[t]
 // U: fp32 item-major N x rp (fmt = 0), bfloat16 bit patterns in fragment
@@ -230,7 +239,8 @@ hipError_t launch_u_c_bf16(int64_t N, UOperand U, int rp, int rk,
 int uc_update_r_blocks(int64_t N);
 hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
-                                   IterGuard g, hipStream_t s, int nt = 0, int width = 0);
+                                   IterGuard g, hipStream_t s, int nt = 0, int width = 0,
+                                   const uint32_t *rowmask = nullptr);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
 hipError_t launch_combine_bf16(int64_t N, int B, UOperand U, int rp, int rk,
                                const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,

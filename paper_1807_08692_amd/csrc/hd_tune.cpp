@@ -150,10 +150,23 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
                 }
             }
         if (err == HD_OK && best >= 0.0) {
-            const bool keep = def_ms >= 0.0 && best >= kKeepDefault * def_ms;
-            c->tune[HD_TUNE_SPMM_CPL] = keep ? def_c : cand[bc];
-            c->tune[HD_TUNE_SPMM_BANDS] = keep ? def_b : cand[bb];
-            const int ci = keep ? (def_c == 1 ? 0 : def_c == 2 ? 1 : 2) : bc, bi = keep ? 0 : bb;
+            // one pass first: the fastest column tiling unless the default is
+            // within 2%; more bands only when they beat that by more than 2%
+            double b1 = -1.0;
+            int c1 = 0;
+            for (int i = 0; i < 3; ++i)
+                if (t[i][0] >= 0.0 && (b1 < 0.0 || t[i][0] < b1)) {
+                    b1 = t[i][0];
+                    c1 = i;
+                }
+            if (def_ms >= 0.0 && b1 >= kKeepDefault * def_ms) {
+                b1 = def_ms;
+                c1 = def_c == 1 ? 0 : def_c == 2 ? 1 : 2;
+            }
+            const bool banded = bb > 0 && b1 >= 0.0 && best < kKeepDefault * b1;
+            const int ci = banded ? bc : c1, bi = banded ? bb : 0;
+            c->tune[HD_TUNE_SPMM_CPL] = cand[ci];
+            c->tune[HD_TUNE_SPMM_BANDS] = cand[bi];
             if (times_ms) {
                 for (int i = 0; i < 3; ++i) times_ms[HD_TUNE_SPMM_CPL * 4 + i] = t[i][bi];
                 for (int j = 0; j < 4; ++j) times_ms[HD_TUNE_SPMM_BANDS * 4 + j] = t[ci][j];

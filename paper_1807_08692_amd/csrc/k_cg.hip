@@ -49,6 +49,39 @@ hipError_t launch_fill_zero(float *p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Zero every row of R and P that some y of the batch touches (all ldb
+// columns): with the first CG iteration reading R and P only on those rows
+// (row mask) and writing every row, the scatter of y then needs no full
+// fill of R and P. One wave per y row; ids outside [0, N) are skipped (the
+// scatter flags them). Rows repeated across y rows are zeroed more than
+// once, with the same value.
+__global__ __launch_bounds__(kBlock) void k_zero_yrows(int B, int ky, const int32_t *__restrict__ ids, int64_t N,
+                                                       int ldb, float *__restrict__ R, float *__restrict__ P) {
+    const int lane = threadIdx.x % kWave;
+    const int t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (t >= B) return;  // whole waves
+    const int32_t *row = ids + (size_t)t * ky;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int u = 0; u < ky; ++u) {
+        const int32_t id = row[u];
+        if (id < 0 || (int64_t)id >= N) continue;
+        for (int c = 4 * lane; c < ldb; c += 4 * kWave) {
+            const size_t o = vec_index(N, ldb, id, c);
+            *reinterpret_cast<float4 *>(R + o) = z;
+            *reinterpret_cast<float4 *>(P + o) = z;
+        }
+    }
+}
+
+hipError_t launch_zero_yrows(int B, int ky, const int32_t *ids, int64_t N, int ldb, float *R, float *P,
+                             hipStream_t s) {
+    if (B <= 0 || ky <= 0) return hipSuccess;
+    if (ldb % 4 != 0) return hipErrorInvalidValue;
+    const int per = kBlock / kWave;
+    k_zero_yrows<<<(B + per - 1) / per, kBlock, 0, s>>>(B, ky, ids, N, ldb, R, P);
+    return hipGetLastError();
+}
+
 // R, P = y (dense, node-major) from the sparse y of each column; R and P are
 // zero in the columns written. One wave per y row: the lane holding the
 // first occurrence of an id sums the values of all its occurrences in index
@@ -273,10 +306,12 @@ hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, 
     return hipGetLastError();
 }
 
-// R -= a Q, and per-block partials of the new R^T R.
+// R -= a Q, and per-block partials of the new R^T R. rowmask (the first CG
+// iteration, when R was zeroed only on the rows of y): rows outside it are
+// taken as zero in R and not read.
 __global__ __launch_bounds__(kBlock) void k_update_r(int64_t N, int ldb, const float *Q, float *R,
                                                      int64_t rb, const double *a, double *part,
-                                                     IterGuard ig) {
+                                                     IterGuard ig, const uint32_t *rowmask) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     const int G = ldb / 4;
     const int rows = kBlock / G;
@@ -290,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t N, int ldb, const f
         const size_t o = vec_index(N, ldb, i, cg * 4);
         float4 *rp = reinterpret_cast<float4 *>(R + o);
         float4 q = *reinterpret_cast<const float4 *>(Q + o);
-        float4 r = *rp;
+        float4 r = row_live(rowmask, (int64_t)i) ? *rp : make_float4(0.f, 0.f, 0.f, 0.f);
         // a = 0 leaves a stopped column untouched even if its Q is not finite
         if (a0 != 0.0) r.x = (float)((double)r.x - a0 * (double)q.x);
         if (a1 != 0.0) r.y = (float)((double)r.y - a1 * (double)q.y);
@@ -306,8 +341,9 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t N, int ldb, const f
 }
 
 hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart rp,
-                           const double *a, double *part, IterGuard g, hipStream_t s) {
-    k_update_r<<<rp.nblk, kBlock, 0, s>>>(N, ldb, Q, R, rp.rb, a, part, g);
+                           const double *a, double *part, IterGuard g, hipStream_t s,
+                           const uint32_t *rowmask) {
+    k_update_r<<<rp.nblk, kBlock, 0, s>>>(N, ldb, Q, R, rp.rb, a, part, g, rowmask);
     return hipGetLastError();
 }
 
@@ -363,12 +399,14 @@ hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, C
 // X += a P (the step of this iteration); P = R + beta P for columns still
 // active after the stopping test.
 // XONLY: the last iteration's update, x += a p alone (no later iteration
-// reads the new p), with the same x arithmetic
+// reads the new p), with the same x arithmetic. rowmask (the first CG
+// iteration, when only the rows of y were zeroed): X is taken as zero and
+// not read, P as zero outside the mask; every row is written.
 template <bool XONLY>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, int width, float *X, float *P,
                                                       const float *R, const double *a,
                                                       const double *beta, const int32_t *active,
-                                                      IterGuard ig) {
+                                                      IterGuard ig, const uint32_t *rowmask) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     const int G = width / 4;  // columns [0, width) of rows of stride ldb
     const int rows = kBlock / G;
@@ -382,7 +420,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, int wi
         const size_t o = vec_index(N, ldb, (int64_t)i, cg * 4);
         float4 *xp = reinterpret_cast<float4 *>(X + o);
         float4 *pp = reinterpret_cast<float4 *>(P + o);
-        float4 x = *xp, p = *pp;
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 x = rowmask ? z4 : *xp, p = row_live(rowmask, (int64_t)i) ? *pp : z4;
         if (a0 != 0.0) x.x = (float)((double)x.x + a0 * (double)p.x);
         if (a1 != 0.0) x.y = (float)((double)x.y + a1 * (double)p.y);
         if (a2 != 0.0) x.z = (float)((double)x.z + a2 * (double)p.z);
@@ -403,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t N, int ldb, int wi
 
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,
                             const double *a, const double *beta, const int32_t *active,
-                            IterGuard g, hipStream_t s, int width, bool x_only) {
+                            IterGuard g, hipStream_t s, int width, bool x_only, const uint32_t *rowmask) {
     if (width == 0) width = ldb;
     if (width % 64 != 0 || width > ldb || width > 4 * kBlock) return hipErrorInvalidValue;
     int rows = kBlock / (width / 4);
@@ -411,9 +450,9 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
     int grid = (int)(want < 16384 ? want : 16384);
     if (grid < 1) grid = 1;
     if (x_only)
-        k_update_xp<true><<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g);
+        k_update_xp<true><<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g, rowmask);
     else
-        k_update_xp<false><<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g);
+        k_update_xp<false><<<grid, kBlock, 0, s>>>(N, ldb, width, X, P, R, a, beta, active, g, rowmask);
     return hipGetLastError();
 }
 
@@ -428,7 +467,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
                                                          const float *R, const double *a,
                                                          const double *beta, const int32_t *active,
                                                          int64_t ldpt, unsigned short *PTh,
-                                                         unsigned short *PTl, IterGuard ig) {
+                                                         unsigned short *PTl, IterGuard ig,
+                                                         const uint32_t *rowmask) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     __shared__ float T[64][65];
     const int64_t i0 = (int64_t)blockIdx.x * 64;
@@ -443,14 +483,17 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
         kv[q] = active[b0 + c4 + q];
     }
     // the four rows' loads first, unconditionally (a row past N reads row
-    // N - 1 and stores nothing), so all twelve are in flight together
+    // N - 1 and stores nothing), so all twelve are in flight together; with
+    // rowmask (first iteration) X is zero and P zero outside the mask
     float4 xv[4], pv[4], rv[4];
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t i = i0 + threadIdx.x / 16 + 16 * j;
-        const size_t o = vec_index(N, ldb, i < N ? i : N - 1, b0 + c4);
-        xv[j] = *reinterpret_cast<const float4 *>(X + o);
-        pv[j] = *reinterpret_cast<const float4 *>(P + o);
+        const int64_t ic = i < N ? i : N - 1;
+        const size_t o = vec_index(N, ldb, ic, b0 + c4);
+        xv[j] = rowmask ? z4 : *reinterpret_cast<const float4 *>(X + o);
+        pv[j] = row_live(rowmask, ic) ? *reinterpret_cast<const float4 *>(P + o) : z4;
         rv[j] = *reinterpret_cast<const float4 *>(R + o);
     }
 #pragma unroll
@@ -498,10 +541,10 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
 hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
                                const double *a, const double *beta, const int32_t *active,
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
-                               hipStream_t s) {
+                               hipStream_t s, const uint32_t *rowmask) {
     if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0) return hipErrorInvalidValue;
     k_update_xp_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(ldb / 64)), kBlock, 0, s>>>(
-        N, ldb, X, P, R, a, beta, active, ldpt, PTh, PTl, g);
+        N, ldb, X, P, R, a, beta, active, ldpt, PTh, PTl, g, rowmask);
     return hipGetLastError();
 }
 

@@ -419,7 +419,9 @@ constexpr int kUcrMt = 2;  // m-tiles per wave of the fused residual update
 // stored: each element of the U Cl tile goes straight into the update of r,
 // which follows update_r (double arithmetic, a = 0 leaves a stopped column
 // untouched), and the column sums of r^2 go to part, one row of ldb doubles
-// per 128-row group (a block covers one or two groups).
+// per 128-row group (a block covers one or two groups). rowmask (the first
+// CG iteration, R zeroed only on the rows of y): r is taken as zero outside
+// it and not read; every row is written.
 template <int AK, int NT, int MT = kUcrMt>
 __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const void *__restrict__ U,
                                                            const void *__restrict__ Ul, int rp, int rk,
@@ -427,7 +429,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
                                                            const unsigned short *__restrict__ CT_lo, int ldb,
                                                            const float *__restrict__ Qs, float cc,
                                                            float *__restrict__ R, const double *__restrict__ a,
-                                                           double *__restrict__ part, int wcols, IterGuard ig) {
+                                                           double *__restrict__ part, int wcols, IterGuard ig,
+                                                           const uint32_t *__restrict__ rowmask) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     // two m-tiles per wave (three waves per SIMD): four measured no faster
     // in the CG iteration (1.67 against 1.66 ms a launch at 1M rows, 256
@@ -461,9 +464,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + 16 * MT * w + 16 * mt + 4 * g + v;
-                const size_t o = vec_index(N, ldb, i < N ? i : N - 1, (int)(nb0 + 16 * (n0 + n) + c16));
+                const int64_t ic = i < N ? i : N - 1;
+                const size_t o = vec_index(N, ldb, ic, (int)(nb0 + 16 * (n0 + n) + c16));
                 qv[n][v] = Qs[o];
-                rv[n][v] = R[o];
+                rv[n][v] = row_live(rowmask, ic) ? R[o] : 0.f;
             }
 #pragma unroll
         for (int nn = 0; nn < NG; ++nn) {
@@ -501,7 +505,7 @@ int uc_update_r_blocks(int64_t N) { return (int)((N + 127) / 128); }
 
 hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
-                                   IterGuard g, hipStream_t s, int ntr, int width) {
+                                   IterGuard g, hipStream_t s, int ntr, int width, const uint32_t *rowmask) {
     if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     if (width == 0) width = ldb;
     if (width % 64 != 0 || width > ldb) return hipErrorInvalidValue;
@@ -511,7 +515,7 @@ hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const 
     const float cc = (float)(alpha / (1.0 - alpha));
 #define HD_UR(AKV, NTV)                                                                                       \
     k_uc_update_r_tn<AKV, NTV><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, CT_lo, ldb, Qs, \
-                                                       cc, R, a, part, width, g)
+                                                       cc, R, a, part, width, g, rowmask)
 #define HD_UR_NT(AKV) \
     if (nt == 4) HD_UR(AKV, 4); else if (nt == 2) HD_UR(AKV, 2); else HD_UR(AKV, 1)
     switch (akind(U)) {

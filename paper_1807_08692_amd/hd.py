@@ -36,6 +36,7 @@ _SIGS = {
     "hd_quantize_fp8_e4m3": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
     "hd_load_eigs_sparse": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P]),
     "hd_compute_eigs": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
+    "hd_eig_steps": (ctypes.c_int32, [_P]),
     "hd_query_filter": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "hd_query_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -233,6 +234,10 @@ class Context:
         _check(lib().hd_compute_eigs(self._h, int(r), _DTYPES[dtype], ctypes.byref(o), lam.ctypes.data_as(_P),
                                      res.ctypes.data_as(_P), None if U is None else U.ctypes.data_as(_P)))
         return {"lam": lam, "resid": res, "U": U}
+
+    def eig_outer(self) -> int:
+        """Rayleigh-Ritz steps of the last compute_eigs (hd_eig_steps)."""
+        return int(lib().hd_eig_steps(self._h))
 
     def load_eigs_sparse(self, r, rowptr, col, val, lam):
         """Sparsified U1 (SHybrid) by item in CSR form: rowptr (n+1), col
