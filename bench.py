@@ -144,6 +144,12 @@ def parse():
 # the sparse product, inside the residual update
 FUSED_FORMS = ("bf16", "bf16x2", "fp8")
 
+# The tolerance of the timed fixed-iteration runs: tol < 0 runs max_iter
+# products like tol = 0, but the last product updates x alone and forms no
+# residual (no output reads it; x and the ranking are bitwise those of
+# tol = 0, relres is that of the residual before the last product)
+FIXED_TOL = -1.0
+
 
 def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False):
     """(bytes, flops) one launch of kernel `kind` must move / compute;
@@ -296,13 +302,13 @@ def main():
         plans = []   # (label, eps, hybrid (iters, tol), plain (iters, tol))
         if args.iters:
             ih_, ip_ = (int(v) for v in args.iters.split(","))
-            plans.append((f"fixed {ih_}/{ip_} iterations", None, (ih_, 0.0), (ip_, 0.0)))
+            plans.append((f"fixed {ih_}/{ip_} iterations", None, (ih_, FIXED_TOL), (ip_, FIXED_TOL)))
         elif not args.tol_mode:
             cal = calibrate(args, cfg, fx, ctx, Qd, B, eps_list, torch, np)
             for e in eps_list:
                 ih, ip = cal["iters"][str(e)]["hybrid"], cal["iters"][str(e)]["plain"]
                 if ih is not None and ip is not None:
-                    plans.append((f"rel-err {e:g}", e, (ih, 0.0), (ip, 0.0)))
+                    plans.append((f"rel-err {e:g}", e, (ih, FIXED_TOL), (ip, FIXED_TOL)))
         if not plans and cal is not None:
             # the hybrid never reaches any target (its error floor lies above):
             # time it at the iteration of its smallest error, plain CG at the
@@ -310,7 +316,8 @@ def main():
             curve = cal["rel_err_by_iter_worst"]["hybrid"]
             i_floor = int(np.argmin(curve))
             ip_ = cal["iters"][str(max(eps_list))]["plain"] or args.calib_max_iter
-            plans.append((f"hybrid at its error floor {min(curve):.3g}", None, (i_floor, 0.0), (ip_, 0.0)))
+            plans.append((f"hybrid at its error floor {min(curve):.3g}", None, (i_floor, FIXED_TOL),
+                          (ip_, FIXED_TOL)))
         if not plans:
             plans.append((f"rel-res {cfg.tol:g}", None, (cfg.max_iter, cfg.tol), (cfg.max_iter, cfg.tol)))
         # breakdown pass at the first target: every kernel bracketed by events
@@ -540,7 +547,8 @@ def diffusion_only_leg(args, cfg, ctx, Qd, B, nbatch, K, ih, ip, hd, torch):
     torch.cuda.synchronize()
     res = {"note": "y given (no similarity search), HIP-graph plans, headline iteration counts"}
     for name, r_use, it in (("hybrid", -1, ih), ("plain_cg", 0, ip)):
-        pl = hd.Plan(ctx, B, "y", alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r_use, k_y=cfg.k_y, top_k=K)
+        pl = hd.Plan(ctx, B, "y", alpha=cfg.alpha, max_iter=it, tol=FIXED_TOL, rank_r=r_use, k_y=cfg.k_y,
+                     top_k=K)
         out = {}
         for w in range(max(1, args.warmup)):
             pl.run(y_ids=ys[w % nbatch][0], y_val=ys[w % nbatch][1], out=out)
@@ -919,7 +927,7 @@ def r_sweep_mode(args, hd, W, torch, np):
         errs = error_curve(args, cfg, ctx, Qd, truths, r, eps, buf, np)
         hit = [i for i, v in enumerate(errs) if v <= eps]
         it = hit[0] if hit else int(np.argmin(errs))
-        kw = dict(alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=r, k_y=cfg.k_y, top_k=100)
+        kw = dict(alpha=cfg.alpha, max_iter=it, tol=FIXED_TOL, rank_r=r, k_y=cfg.k_y, top_k=100)
         for w in range(max(1, args.warmup)):
             ctx.query_batch(Qd[0], **kw)
         torch.cuda.synchronize()
@@ -951,7 +959,7 @@ def r_sweep_mode(args, hd, W, torch, np):
     cost_rows = []
     if rmax > 0 and cost_ranks and rows:
         it = rows[-1]["iters"]
-        kw = dict(alpha=cfg.alpha, max_iter=it, tol=0.0, rank_r=-1, k_y=cfg.k_y, top_k=100)
+        kw = dict(alpha=cfg.alpha, max_iter=it, tol=FIXED_TOL, rank_r=-1, k_y=cfg.k_y, top_k=100)
         ref = ctx.query_batch(Qd[0], want_x=True, **dict(kw, rank_r=rmax))["x"].clone()
         gen = torch.Generator(device=dev).manual_seed(cfg.seed_base + 97)
         for rc in cost_ranks:
@@ -1437,17 +1445,22 @@ def measured_traffic(workload, dom, rec):
         return None
     data = json.load(open(path))
     want = None
+    per_launch = 1  # dispatches per launch of the kind (source bands: one each)
     if dom == "spmm":
-        cpl = ((rec.get("autotune") or {}).get("spmm_cpl") or {}).get("chosen") or 2
-        want = f"hd::k_spmm<{cpl}, false>"
+        tune = rec.get("autotune") or {}
+        cpl = (tune.get("spmm_cpl") or {}).get("chosen") or 2
+        bands = (tune.get("spmm_bands") or {}).get("chosen") or 1
+        want = f"hd::k_spmm<{cpl}, false, {'true' if bands > 1 else 'false'}>"
+        per_launch = bands
     for name, k in data.get("kernels", {}).items():
         if k.get("kind") != dom or (want and name != want):
             continue
         src = os.path.join(ROOT, "paper_1807_08692_amd", "csrc", k["source"])
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != k["sha256"]:
             return None
-        return {"bytes": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
-                "write_bytes": k["write_bytes"], "kernel": name,
+        return {"bytes": per_launch * (k["fetch_bytes"] + k["write_bytes"]),
+                "fetch_bytes": per_launch * k["fetch_bytes"],
+                "write_bytes": per_launch * k["write_bytes"], "kernel": name, "dispatches_per_launch": per_launch,
                 "scale": {"fetch": data["scale_fetch"], "write": data["scale_write"]},
                 "source": f"profiles/traffic_{workload}.json"}
     return None

@@ -184,7 +184,8 @@ int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
  * the solver width, on the null stream) and keep the fastest in the
  * context; the built-in default is kept unless a candidate beats it by more
  * than 2%. The sparse product's two parameters (columns per lane, source
- * bands) are tuned together over every pair. times_ms (host, may be NULL)
+ * bands) are tuned together over every pair; more than one band is kept
+ * only when 5% faster than the best single pass. times_ms (host, may be NULL)
  * receives HD_TUNE_NKEYS x 4 mean launch times in ms for the values 1, 2,
  * 4, 8 (-1 where a value does not fit or the kernel is not used: no
  * eigenvectors, or fp32 storage); for the two sparse-product keys, the time
@@ -310,7 +311,11 @@ typedef struct {
     double alpha;      /* Section 3: alpha in [0, 1); the paper uses 0.99      */
     int32_t max_iter;  /* CG iteration cap (number of operator products), >= 0 */
     double tol;        /* stop a column when sqrt(r^T r / y^T y) <= tol (after
-                          the x and r updates); tol <= 0 runs max_iter products */
+                          the x and r updates); tol <= 0 runs max_iter products.
+                          tol < 0 (hd_query_batch and plans, multi-kernel
+                          path): as 0, except that the last product updates
+                          x alone and forms no residual (nothing else reads
+                          it), so relres reports the residual before it */
     int32_t rank_r;    /* use the first rank_r loaded eigenpairs (0 = plain CG,
                           the temporal filtering of eq. (temporal)); -1 = all  */
     int32_t k_y;       /* non-zeros of y per query, 1..min(n, 1024)             */

@@ -793,6 +793,8 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         }
     }
     HIP_TRY(c->part.ensure((size_t)(fused && nrb > rp.nblk ? nrb : rp.nblk) * ldb * sizeof(double)));
+    HIP_TRY(c->pre.ensure((size_t)2 * hd::kPreSplitRows * ldb * sizeof(double)));
+    double *pre = c->pre.as<double>();
     HIP_TRY(c->scal.ensure((size_t)ldb * (5 * sizeof(double) + 3 * sizeof(int32_t)) + 128 * sizeof(int32_t)));
     HIP_TRY(c->err.ensure(sizeof(int32_t) * 4));
     {
@@ -957,6 +959,8 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         const bool m1 = nofill && it == 1;
         const uint32_t *rm = m1 ? ymask : nullptr;
         const hd::IterGuard gu = m1 ? hd::IterGuard{nullptr, 0} : g;
+        // tol < 0: the last product forms no residual (x alone is updated)
+        const bool nores = o->tol < 0.0 && it == o->max_iter;
         if (fused) {
             uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
             if (it > 1) {
@@ -974,12 +978,13 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                                    ldb, o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb), 0,
                                    it == 1 ? ymask : nullptr, c->bands(), c->cuts()));
             LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, c->Dg.as<double>(),
-                                                  rk));
-            LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha, R,
-                                                      st.a, c->part.as<double>(), gu, s,
-                                                      c->tv(HD_TUNE_UC_NT, ldb), 0, rm));
-            LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), nrb, o->tol, st, g, nact_dev[it & 1],
-                                                  s));
+                                                  rk, pre));
+            if (!nores)
+                LAUNCH(K_U_C, hd::launch_uc_update_r_bf16(n, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q, o->alpha,
+                                                          R, st.a, c->part.as<double>(), gu, s,
+                                                          c->tv(HD_TUNE_UC_NT, ldb), 0, rm));
+            LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, nores ? nullptr : c->part.as<double>(), nrb, o->tol, st, g,
+                                                  nact_dev[it & 1], s, pre));
             if (it == o->max_iter)  // nothing reads the new P or its split transpose
                 LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, true,
                                                          rm));
@@ -1028,9 +1033,10 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                hd::launch_spmm(n, c->rowptr.as<int64_t>(), c->col.as<int32_t>(), c->val.as<float>(), P, Zs, Q, ldb,
                                o->alpha, rp, c->part.as<double>(), g, s, c->tv(HD_TUNE_SPMM_CPL, ldb), 0,
                                it == 1 ? ymask : nullptr, c->bands(), c->cuts()));
-        LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s));
-        LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), gu, s, rm));
-        LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, c->part.as<double>(), rp.nblk, o->tol, st, g, nact_dev[it & 1], s));
+        LAUNCH(K_SCALAR, hd::launch_cg_step_a(ldb, c->part.as<double>(), rp.nblk, st, g, s, nullptr, 0, pre));
+        if (!nores) LAUNCH(K_UPDATE_R, hd::launch_update_r(n, ldb, Q, R, rp, st.a, c->part.as<double>(), gu, s, rm));
+        LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, nores ? nullptr : c->part.as<double>(), rp.nblk, o->tol, st, g,
+                                              nact_dev[it & 1], s, pre));
         if (it == o->max_iter) {  // the last iteration: nothing reads the new P
             LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, true, rm));
         } else if (ubf && rk > 0) {

@@ -195,6 +195,7 @@ struct hd_ctx {
     int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
     hipEvent_t iter_ev[2] = {nullptr, nullptr};
     DevBuf Dg;  // alpha / (1 - alpha) lambda (U1^T P)^2 per component and column
+    DevBuf pre;  // pre-reduced partial sums of the scalar kernels (2 x 64 rows of ldb)
     DevBuf ymask;  // one bit per item: the rows where y (the first P) is nonzero
     hd::CgState st{};
     Timing timing;

@@ -87,9 +87,13 @@ hipError_t launch_ynorm_part(int B, int ky, const int32_t *ids, int64_t N, int l
                              double *part, hipStream_t s, const int32_t *colmap = nullptr);
 hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState st, hipStream_t s);
 // gamma = the column sums of gpart (nblk rows), plus those of gpart2 (nblk2
-// rows) when given
+// rows) when given. scratch (this and step_b; nullptr = none): 2 x
+// kPreSplitRows rows of ldb doubles, where long lists of partial rows are
+// first reduced in parallel
+constexpr int kPreSplitRows = 64;
 hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, IterGuard g,
-                            hipStream_t s, const double *gpart2 = nullptr, int nblk2 = 0);
+                            hipStream_t s, const double *gpart2 = nullptr, int nblk2 = 0,
+                            double *scratch = nullptr);
 // rowmask (the updates below too; nullptr = none): the first CG iteration
 // after launch_zero_yrows, rows outside the mask taken as zero in R and P
 // (and X as zero) without reading them; every row is written
@@ -97,8 +101,10 @@ hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart
                            const double *a, double *part, IterGuard g, hipStream_t s,
                            const uint32_t *rowmask = nullptr);
 // writes the new per-tile active counts to nact_out
+// part == nullptr: the last of a fixed number of products with no residual
+// formed (each active column counts it and stops, status MAXITER)
 hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
-                            IterGuard g, int32_t *nact_out, hipStream_t s);
+                            IterGuard g, int32_t *nact_out, hipStream_t s, double *scratch = nullptr);
 // width (0 = ldb): only columns [0, width) are updated (row stride ldb);
 // x_only: X += a P alone, for the last iteration (P and R untouched)
 hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float *R,

@@ -22,6 +22,10 @@ int default_value(int key, int ldb) {
 }
 
 constexpr double kKeepDefault = 0.98;
+// more than one source band of the sparse product: only when 5% faster than
+// one pass (on graphs without locality the bands add work and no cache hits;
+// a 2% margin let timing noise pick them)
+constexpr double kKeepBands = 0.95;
 
 }  // namespace
 
@@ -151,7 +155,7 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
             }
         if (err == HD_OK && best >= 0.0) {
             // one pass first: the fastest column tiling unless the default is
-            // within 2%; more bands only when they beat that by more than 2%
+            // within 2%; more bands only when they beat that by more than 5%
             double b1 = -1.0;
             int c1 = 0;
             for (int i = 0; i < 3; ++i)
@@ -163,7 +167,7 @@ int hd_autotune(hd_ctx *c, int32_t batch, int32_t reps, double *times_ms) {
                 b1 = def_ms;
                 c1 = def_c == 1 ? 0 : def_c == 2 ? 1 : 2;
             }
-            const bool banded = bb > 0 && b1 >= 0.0 && best < kKeepDefault * b1;
+            const bool banded = bb > 0 && b1 >= 0.0 && best < kKeepBands * b1;
             const int ci = banded ? bc : c1, bi = banded ? bb : 0;
             c->tune[HD_TUNE_SPMM_CPL] = cand[ci];
             c->tune[HD_TUNE_SPMM_BANDS] = cand[bi];

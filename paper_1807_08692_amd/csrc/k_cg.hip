@@ -273,6 +273,39 @@ hipError_t launch_cg_init(int B, int ldb, const double *part, int nblk, CgState 
     return hipGetLastError();
 }
 
+// Partial-sum rows pre-reduced in parallel for the scalar kernels below: a
+// tile's 1024 threads reading thousands of rows alone are latency-bound
+// (about 50 us for 7,800 rows of 256 columns). Block (tile, s) sums rows
+// [s per, (s + 1) per) of its 64 columns, per = ceil(nblk / kPreSplit), in
+// tile_reduce's order and writes row s of out; the scalar kernel then sums
+// the kPreSplit rows. The order depends on nblk only.
+constexpr int kPreSplit = kPreSplitRows;
+__global__ __launch_bounds__(kScalarThreads) void k_part_prereduce(const double *part, int nblk, int ldb,
+                                                                   double *out, IterGuard ig) {
+    if (all_stopped(ig.nact, ig.ntile)) return;
+    const int lane = threadIdx.x % kWave;
+    const int c = blockIdx.x * kWave + lane;
+    const int per = (nblk + kPreSplit - 1) / kPreSplit;
+    const int lo = blockIdx.y * per;
+    const int hi = lo + per < nblk ? lo + per : nblk;
+    const double t = tile_reduce(part + (size_t)(lo < nblk ? lo : 0) * ldb, hi > lo ? hi - lo : 0, ldb, c);
+    if (threadIdx.x < kWave) out[(size_t)blockIdx.y * ldb + c] = t;
+}
+
+// With scratch (kPreSplit rows of ldb doubles) and more than 2 kPreSplit
+// rows, pre-reduce part into scratch; returns the rows the scalar kernel
+// then reads (and how many) through *rows / *n.
+static hipError_t prereduce(const double *part, int nblk, int ldb, double *scratch, IterGuard g, hipStream_t s,
+                            const double **rows, int *n) {
+    *rows = part;
+    *n = nblk;
+    if (!scratch || nblk <= 2 * kPreSplit) return hipSuccess;
+    k_part_prereduce<<<dim3((unsigned)(ldb / kWave), kPreSplit), kScalarThreads, 0, s>>>(part, nblk, ldb, scratch, g);
+    *rows = scratch;
+    *n = kPreSplit;
+    return hipGetLastError();
+}
+
 // gamma = P^T Q per column; a = rho / gamma, or stop the column (breakdown)
 // when gamma is not positive and finite.
 __global__ __launch_bounds__(kScalarThreads) void k_cg_step_a(int ldb, const double *gpart, int nblk,
@@ -301,7 +334,12 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_a(int ldb, const dou
 }
 
 hipError_t launch_cg_step_a(int ldb, const double *gpart, int nblk, CgState st, IterGuard g,
-                            hipStream_t s, const double *gpart2, int nblk2) {
+                            hipStream_t s, const double *gpart2, int nblk2, double *scratch) {
+    hipError_t e = prereduce(gpart, nblk, ldb, scratch, g, s, &gpart, &nblk);
+    if (e == hipSuccess && gpart2)
+        e = prereduce(gpart2, nblk2, ldb, scratch ? scratch + (size_t)kPreSplit * ldb : nullptr, g, s, &gpart2,
+                      &nblk2);
+    if (e != hipSuccess) return e;
     k_cg_step_a<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, gpart, nblk, st, g, gpart2, nblk2);
     return hipGetLastError();
 }
@@ -349,6 +387,9 @@ hipError_t launch_update_r(int64_t N, int ldb, const float *Q, float *R, RowPart
 
 // rho' = R^T R per column; stopping test sqrt(rho'/rho0) <= tol after the
 // update; beta = rho'/rho for the columns that go on.
+// part == nullptr: the last of a fixed number of products, whose residual
+// is not formed: each active column counts the product and stops (status
+// stays MAXITER, rho that of the residual before the product).
 __global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const double *part, int nblk,
                                                       double tol, CgState st, IterGuard ig,
                                                       int32_t *nact_out) {
@@ -359,6 +400,14 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const dou
     }
     int lane = threadIdx.x % kWave;
     int c = blockIdx.x * kWave + lane;
+    if (!part) {
+        if (threadIdx.x < kWave && st.active[c]) {
+            st.iters[c] += 1;
+            st.active[c] = 0;
+        }
+        if (threadIdx.x == 0) nact_out[blockIdx.x] = 0;
+        return;
+    }
     double rho_new = tile_reduce(part, nblk, ldb, c);
     __shared__ int cnt[kWave];
     if (threadIdx.x < kWave) {
@@ -391,7 +440,9 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_step_b(int ldb, const dou
 }
 
 hipError_t launch_cg_step_b(int ldb, const double *part, int nblk, double tol, CgState st,
-                            IterGuard g, int32_t *nact_out, hipStream_t s) {
+                            IterGuard g, int32_t *nact_out, hipStream_t s, double *scratch) {
+    const hipError_t e = part ? prereduce(part, nblk, ldb, scratch, g, s, &part, &nblk) : hipSuccess;
+    if (e != hipSuccess) return e;
     k_cg_step_b<<<ldb / kWave, kScalarThreads, 0, s>>>(ldb, part, nblk, tol, st, g, nact_out);
     return hipGetLastError();
 }

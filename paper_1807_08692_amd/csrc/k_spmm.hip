@@ -236,7 +236,8 @@ void build_band_cuts(int64_t N, const int64_t *rowptr, const int32_t *col, int32
 
 // cpl: query columns per lane (a wave covers 64 cpl columns of a row); the
 // default is 2 when it divides the width (measured fastest at 256 columns on a
-// million-row graph), else 1. width (0 = ldb): only columns [0, width) are
+// million-row graph), else 1; the masked product takes the widest that
+// divides the width. width (0 = ldb): only columns [0, width) are
 // computed (row stride stays ldb); a multiple of 64. rowmask (nullptr =
 // none): bit j of word j / 32 set for the rows of P that may be nonzero;
 // the others must be zero in every computed column. bands (0 or 1 = one
@@ -251,6 +252,10 @@ hipError_t launch_spmm(int64_t N, const int64_t *rowptr, const int32_t *col, con
     if (width < 64 || width > ldb || width % 64 != 0) return hipErrorInvalidValue;
     if (cpl == 0) cpl = width % 128 == 0 ? 2 : 1;
     if (!tile_param_ok(cpl, width)) return hipErrorInvalidValue;
+    // the masked product is bound by each row's chain of dependent loads
+    // (row pointers, column ids, mask words, the few gathers), which every
+    // column slice repeats: one wave covers as many columns as it can
+    if (rowmask) cpl = width % 256 == 0 ? 4 : width % 128 == 0 ? 2 : 1;
     if (bands == 0 || rowmask) bands = 1;
     if (!band_param_ok(bands) || (bands > 1 && !cut)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)rp.nblk, (unsigned)(width / (64 * cpl)));

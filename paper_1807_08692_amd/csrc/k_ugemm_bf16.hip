@@ -421,7 +421,7 @@ constexpr int kUcrMt = 2;  // m-tiles per wave of the fused residual update
 // untouched), and the column sums of r^2 go to part, one row of ldb doubles
 // per 128-row group (a block covers one or two groups). rowmask (the first
 // CG iteration, R zeroed only on the rows of y): r is taken as zero outside
-// it and not read; every row is written.
+// it (whatever the memory holds); every row is written.
 template <int AK, int NT, int MT = kUcrMt>
 __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const void *__restrict__ U,
                                                            const void *__restrict__ Ul, int rp, int rk,
@@ -467,7 +467,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
                 const int64_t ic = i < N ? i : N - 1;
                 const size_t o = vec_index(N, ldb, ic, (int)(nb0 + 16 * (n0 + n) + c16));
                 qv[n][v] = Qs[o];
-                rv[n][v] = row_live(rowmask, ic) ? R[o] : 0.f;
+                // unconditional load, then the mask (a conditional load made
+                // the compiler's wait counts conservative: 10% slower)
+                const float rr = R[o];
+                rv[n][v] = row_live(rowmask, ic) ? rr : 0.f;
             }
 #pragma unroll
         for (int nn = 0; nn < NG; ++nn) {
