@@ -422,7 +422,7 @@ constexpr int kUcrMt = 2;  // m-tiles per wave of the fused residual update
 // per 128-row group (a block covers one or two groups). rowmask (the first
 // CG iteration, R zeroed only on the rows of y): r is taken as zero outside
 // it (whatever the memory holds); every row is written.
-template <int AK, int NT, int MT = kUcrMt>
+template <int AK, int NT, bool MASKR, int MT = kUcrMt>
 __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const void *__restrict__ U,
                                                            const void *__restrict__ Ul, int rp, int rk,
                                                            const unsigned short *__restrict__ CT_hi,
@@ -455,7 +455,20 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
     // Branch-free: rows past N load row N - 1 and store nothing.
     constexpr int NG = 4 * NT < 8 ? 4 * NT : 8;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt) {
+    // the first iteration's row mask: this lane's four rows (4g .. 4g + 3
+    // of a 16-row m-tile, so within one 32-row mask word) read once per
+    // m-tile; the mask is a separate instantiation, since a test inside the
+    // load loop below, even an always-true one, split its group of loads
+    // (9% slower)
+    bool live[4] = {true, true, true, true};
+    if (MASKR) {
+        const int64_t ib = i0 + 16 * MT * w + 16 * mt + 4 * g;
+        const int64_t ibc = ib < N ? ib : N - 1;
+        const uint32_t word = rowmask[ibc >> 5];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) live[v] = (word >> ((ibc + v) & 31)) & 1u;
+    }
 #pragma unroll
     for (int n0 = 0; n0 < 4 * NT; n0 += NG) {
         float qv[NG][4], rv[NG][4];
@@ -467,10 +480,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
                 const int64_t ic = i < N ? i : N - 1;
                 const size_t o = vec_index(N, ldb, ic, (int)(nb0 + 16 * (n0 + n) + c16));
                 qv[n][v] = Qs[o];
-                // unconditional load, then the mask (a conditional load made
-                // the compiler's wait counts conservative: 10% slower)
                 const float rr = R[o];
-                rv[n][v] = row_live(rowmask, ic) ? rr : 0.f;
+                rv[n][v] = live[v] ? rr : 0.f;
             }
 #pragma unroll
         for (int nn = 0; nn < NG; ++nn) {
@@ -491,6 +502,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
             ss += __shfl_xor(ss, 32, kWave);
             if (g == 0) sh[MT * w + mt][16 * n + c16] = ss;
         }
+    }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < (MT / 2) * 64 * NT; t += kBlock) {
@@ -516,11 +528,17 @@ hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const 
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(width / (64 * nt)) * (unsigned)((N + 64 * kUcrMt - 1) / (64 * kUcrMt));
     const float cc = (float)(alpha / (1.0 - alpha));
-#define HD_UR(AKV, NTV)                                                                                       \
-    k_uc_update_r_tn<AKV, NTV><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, CT_lo, ldb, Qs, \
-                                                       cc, R, a, part, width, g, rowmask)
+#define HD_UR(AKV, NTV)                                                                                     \
+    if (rowmask)                                                                                            \
+        k_uc_update_r_tn<AKV, NTV, true><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, \
+                                                                 CT_lo, ldb, Qs, cc, R, a, part, width, g,   \
+                                                                 rowmask);                                   \
+    else                                                                                                    \
+        k_uc_update_r_tn<AKV, NTV, false><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, \
+                                                                  CT_lo, ldb, Qs, cc, R, a, part, width, g,   \
+                                                                  nullptr)
 #define HD_UR_NT(AKV) \
-    if (nt == 4) HD_UR(AKV, 4); else if (nt == 2) HD_UR(AKV, 2); else HD_UR(AKV, 1)
+    if (nt == 4) { HD_UR(AKV, 4); } else if (nt == 2) { HD_UR(AKV, 2); } else { HD_UR(AKV, 1); }
     switch (akind(U)) {
         case AK_FP8: HD_UR_NT(AK_FP8); break;
         case AK_BF16X2: HD_UR_NT(AK_BF16X2); break;

@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the query path (a developer utility).
 
     python -m paper_1807_08692_amd.profsum trace TRACE_CSV > summary.md
-    python -m paper_1807_08692_amd.profsum traffic FETCH_CSV WRITE_CSV OUT_JSON > table.md
+    python -m paper_1807_08692_amd.profsum traffic FETCH_CSV WRITE_CSV OUT_JSON [--merge] > table.md
     python -m paper_1807_08692_amd.profsum mfma COUNTER_CSV > mfma.md
     python -m paper_1807_08692_amd.profsum counters COUNTER_CSV > counters.md
 
@@ -91,7 +91,7 @@ def trace(path: str, work_frac: float = 0.05) -> str:
     return "\n".join(out)
 
 
-def traffic(fetch_csv: str, write_csv: str, out_json: str) -> str:
+def traffic(fetch_csv: str, write_csv: str, out_json: str, merge: bool = False) -> str:
     def agg(fn):
         a = collections.defaultdict(list)
         copy = []
@@ -124,6 +124,12 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str) -> str:
         if kd:
             res["kernels"][k] = {"kind": kd[0], "fetch_bytes": fb, "write_bytes": wb,
                                  "source": kd[1], "sha256": sha(kd[1])}
+    if merge and os.path.exists(out_json):
+        # add this run's kernels (for instance another launch variant) to an
+        # existing summary; entries of kernels measured again are replaced
+        old = json.load(open(out_json))
+        old["kernels"].update(res["kernels"])
+        res["kernels"] = old["kernels"]
     with open(out_json, "w") as fh:
         json.dump(res, fh, indent=1)
     head = (f"Counter scaling from the 1 GiB copy: FETCH_SIZE x {kf:.3f}, WRITE_SIZE x {kw:.3f}.\n\n")
@@ -193,7 +199,7 @@ if __name__ == "__main__":
     if sys.argv[1] == "trace":
         print(trace(sys.argv[2]))
     elif sys.argv[1] == "traffic":
-        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4]))
+        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], merge="--merge" in sys.argv[5:]))
     elif sys.argv[1] == "mfma":
         print(mfma(sys.argv[2]))
     elif sys.argv[1] == "counters":

@@ -5,7 +5,8 @@ routed to one database. The loop admits waiting requests into free solver
 columns as soon as columns free up (hd_serve_submit), queues one CG
 iteration on every server that has work (hd_serve_step, asynchronous, so the
 servers' GPU work overlaps), and collects finished requests
-(hd_serve_poll). Latency is measured from arrival to collection.
+(hd_serve_poll) when it knows some have finished. Latency is measured from
+arrival to collection.
 """
 from __future__ import annotations
 
@@ -36,15 +37,27 @@ def poisson_arrivals(rate_per_s: float, count: int, seed: int) -> np.ndarray:
     return np.cumsum(gaps)
 
 
-def run(servers: dict, requests: list, iters_per_step: int = 1, max_admit: int = 1024):
+def run(servers: dict, requests: list, iters_per_step: int = 1, max_admit: int = 1024,
+        poll_every: int = 8):
     """Serve `requests` (sorted by arrival) on `servers` ({db: hd.Server}).
-    Returns (requests with timings and results, wall seconds)."""
+    Returns (requests with timings and results, wall seconds).
+
+    A server is polled (a stream synchronisation, and for the finished
+    columns one pass over U1 to combine and one top-K) only when a request
+    on it has certainly finished - the loop counts each request's iterations
+    against its cap - or every `poll_every` turns (columns that converge
+    before their cap, with tol > 0, or stop at once with y = 0). Between
+    polls the loop queues the next iterations without waiting for the
+    device."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = {db: deque() for db in servers}
     by_ticket = {db: {} for db in servers}
+    iters_done = {db: {} for db in servers}    # ticket -> iterations queued since admission
     t0 = time.perf_counter()
     done = 0
+    turn = 0
     while done < len(requests):
+        turn += 1
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
             r = pending.popleft()
@@ -64,17 +77,26 @@ def run(servers: dict, requests: list, iters_per_step: int = 1, max_admit: int =
                 for t, r in zip(tk, batch):
                     r.admitted = t_adm
                     by_ticket[db][int(t)] = r
+                    iters_done[db][int(t)] = 0
                     q.popleft()
             if srv.in_use:
                 srv.step(iters_per_step)
+                for t in iters_done[db]:
+                    iters_done[db][t] += iters_per_step
                 busy = True
         for db, srv in servers.items():
             if not by_ticket[db]:
+                continue
+            # each request's own cap is passed at submission (it overrides
+            # the server's default)
+            known = any(iters_done[db][t] >= r.max_iter for t, r in by_ticket[db].items())
+            if not known and turn % poll_every != 0:
                 continue
             res = srv.poll()
             t_fin = time.perf_counter() - t0
             for k, t in enumerate(res["tickets"]):
                 r = by_ticket[db].pop(int(t))
+                iters_done[db].pop(int(t))
                 r.finished = t_fin
                 r.result = {key: res[key][k] for key in ("ids", "scores", "iters", "relres", "status")}
                 done += 1
