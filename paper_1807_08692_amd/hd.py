@@ -463,6 +463,7 @@ class Server:
         self.ctx = ctx  # keeps the context alive
         self.k_y = int(k_y)
         self.top_k = int(top_k)
+        self.tol = float(tol)
 
     @staticmethod
     def column_bytes(ctx: Context, *, alpha=0.99, max_iter=20, tol=1e-6, rank_r=-1, k_y=10, top_k=100) -> int:

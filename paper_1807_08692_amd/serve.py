@@ -42,13 +42,14 @@ def run(servers: dict, requests: list, iters_per_step: int = 1, max_admit: int =
     """Serve `requests` (sorted by arrival) on `servers` ({db: hd.Server}).
     Returns (requests with timings and results, wall seconds).
 
-    A server is polled (a stream synchronisation, and for the finished
-    columns one pass over U1 to combine and one top-K) only when a request
-    on it has certainly finished - the loop counts each request's iterations
-    against its cap - or every `poll_every` turns (columns that converge
-    before their cap, with tol > 0, or stop at once with y = 0). Between
-    polls the loop queues the next iterations without waiting for the
-    device."""
+    A server without a tolerance (tol <= 0: every request runs to its cap)
+    is polled (a stream synchronisation, and for the finished columns one
+    pass over U1 to combine and one top-K) only when a request on it has
+    certainly finished - the loop counts each request's iterations against
+    its cap - or every `poll_every` turns (columns that stop at once, with
+    y = 0 or a breakdown); between polls the loop queues the next iterations
+    without waiting for the device. A server with tol > 0, whose columns may
+    converge at any iteration, is polled every turn."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = {db: deque() for db in servers}
     by_ticket = {db: {} for db in servers}
@@ -89,8 +90,9 @@ def run(servers: dict, requests: list, iters_per_step: int = 1, max_admit: int =
                 continue
             # each request's own cap is passed at submission (it overrides
             # the server's default)
+            capped = getattr(srv, "tol", 1.0) <= 0.0
             known = any(iters_done[db][t] >= r.max_iter for t, r in by_ticket[db].items())
-            if not known and turn % poll_every != 0:
+            if capped and not known and turn % poll_every != 0:
                 continue
             res = srv.poll()
             t_fin = time.perf_counter() - t0
