@@ -108,6 +108,12 @@ def test_full_size_parity(setup):
         hyb = ctx.query_batch(q, max_iter=4, rank_r=-1, **kw)
         pl = ctx.query_batch(q, max_iter=7, rank_r=0, **kw)
         torch.cuda.synchronize()
+        # the timed form of a fixed iteration count (tol < 0: the last product
+        # forms no residual) gives the same bits
+        xf = ctx.query_batch(q, max_iter=4, rank_r=-1, **dict(kw, tol=-1.0))["x"]
+        torch.cuda.synchronize()
+        assert torch.equal(xf, hyb["x"])
+        del xf
         # every source-band count of the sparse product gives the same bits
         chosen = ctx.get_tuning("spmm_bands")
         for bands in (1, 2, 4, 8):
