@@ -439,6 +439,11 @@ def main():
             "global_batch": B,
             "parallelism": "single GPU",
         },
+        "timed_runs": ({"tol": cfg.tol, "note": "CG to the workload's relative residual"} if args.tol_mode else
+                       {"tol": FIXED_TOL,
+                        "note": "fixed iteration counts for both methods, run with tol < 0: the last CG "
+                                "product updates x and forms no residual (no output reads it); x, the "
+                                "ranking and the iteration counts are bitwise those of tol = 0 (tested)"}),
         "latency_ms": {"p50": tgt["hybrid"]["p50_ms"], "p99": tgt["hybrid"]["p99_ms"],
                        "note": "per query = its batch's wall time (closed loop)"},
         "hybrid": tgt["hybrid"],
