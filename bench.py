@@ -149,14 +149,17 @@ FUSED_FORMS = ("bf16", "bf16x2", "fp8")
 # residual (no output reads it; x and the ranking are bitwise those of
 # tol = 0, relres is that of the residual before the last product)
 FIXED_TOL = -1.0
+# rows of at least this many items take the one-pass top-k (HD_TUNE_TOPK_ONEPASS)
+ONEPASS_MIN_N = 65536
 
 
-def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False):
+def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False, onepass=False):
     """(bytes, flops) one launch of kernel `kind` must move / compute;
     su = bytes per stored U1 / descriptor element (4 fp32, 2 bf16).
     fused: the dense bfloat16 forms, where the sparse product reads P only
     (Zs = P) and u_c is fused with the residual update (reads Qs and r,
-    writes r)."""
+    writes r). onepass: the similarity / combine kernel hands its scores to
+    the top-k candidate lists and writes no B x n score matrix."""
     v = 4.0 * n * ldb
     if kind == "spmm":
         return 8.0 * (n + 1) + 8.0 * nnz + v * (3 if rk > 0 and not fused else 2), 2.0 * nnz * ldb
@@ -168,10 +171,11 @@ def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False):
         return 3 * v, 2.0 * n * ldb
     if kind == "update_xp":
         return 5 * v, 4.0 * n * ldb
+    out = 0.0 if onepass else 4.0 * B * n
     if kind == "sim":
-        return su * n * d + 4.0 * B * d + 4.0 * B * n, 2.0 * B * n * d
+        return su * n * d + 4.0 * B * d + out, 2.0 * B * n * d
     if kind == "combine":
-        return su * n * rk + v + 4.0 * B * n, 2.0 * n * rk * B
+        return su * n * rk + v + out, 2.0 * n * rk * B
     return None
 
 
@@ -289,7 +293,8 @@ def main():
             for kv in args.tune.split(","):
                 k, v = kv.split("=")
                 ctx.set_tuning(k.strip(), int(v))
-            tune = {k: {"chosen": ctx.get_tuning(k), "times_ms": {}} for k in ("spmm_cpl", "utp_nt", "uc_nt", "spmm_bands")}
+            tune = {k: {"chosen": ctx.get_tuning(k), "times_ms": {}}
+                    for k in ("spmm_cpl", "utp_nt", "uc_nt", "spmm_bands", "topk_onepass")}
         elif not args.no_autotune:
             tune = ctx.autotune(B, 3)
         if tune:
@@ -332,8 +337,10 @@ def main():
         for kind, (ms, cnt) in tm_all.items():
             if cnt == 0:
                 continue
+            onepass = (fx.n >= ONEPASS_MIN_N and ctx.get_tuning("topk_onepass") != 1
+                       and ((kind == "sim" and vprec != "f32") or (kind == "combine" and (form in FUSED_FORMS or rk == 0))))
             cost = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, sv if kind == "sim" else su,
-                                    form in FUSED_FORMS)
+                                    form in FUSED_FORMS, onepass)
             kernels[kind] = {"ms_total": round(ms, 4), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 3)}
             if cost:
                 by, fl = cost

@@ -169,11 +169,21 @@ typedef enum {
                               many runs, one launch per run, so that the rows
                               of P gathered at one time fit the device's
                               memory-side cache; bit-identical results */
-    HD_TUNE_NKEYS = 4
+    HD_TUNE_TOPK_ONEPASS = 4, /* top-k of the similarities (bfloat16 or fp8
+                              descriptors) and the final top-K (plain CG or
+                              the matrix-core U1 forms, no x output) for
+                              n >= 65536 items: 0 or 2 one pass (a sampled
+                              threshold per row, candidates taken from the
+                              scores as they are produced, no score matrix
+                              written unless a row needs the exact
+                              fallback), 1 two passes (the score matrix,
+                              then the selection); identical results */
+    HD_TUNE_NKEYS = 5
 } hd_tune_key;
 
 /* Set / read one launch parameter. Errors: HD_EINVAL (key, value not in
- * {0, 1, 2, 4}, or {0, 1, 2, 4, 8} for HD_TUNE_SPMM_BANDS; NULL). */
+ * {0, 1, 2, 4}, {0, 1, 2, 4, 8} for HD_TUNE_SPMM_BANDS, {0, 1, 2} for
+ * HD_TUNE_TOPK_ONEPASS; NULL). */
 int hd_set_tuning(hd_ctx *ctx, int32_t key, int32_t value);
 int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
 
@@ -189,7 +199,8 @@ int hd_get_tuning(const hd_ctx *ctx, int32_t key, int32_t *value);
  * receives HD_TUNE_NKEYS x 4 mean launch times in ms for the values 1, 2,
  * 4, 8 (-1 where a value does not fit or the kernel is not used: no
  * eigenvectors, or fp32 storage); for the two sparse-product keys, the time
- * of that value with the other key at its chosen value.
+ * of that value with the other key at its chosen value. HD_TUNE_TOPK_ONEPASS
+ * is not searched (its times are -1, its value unchanged).
  * Synchronous. Errors: HD_ESTATE (no graph), HD_EINVAL (batch not in
  * [1, 1024], reps not in [1, 1000]).
  */

@@ -24,7 +24,8 @@ static int64_t ctx_bytes(const hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                            &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                            &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                           &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale, &c->pbar};
+                           &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale, &c->pbar,
+                     &c->cut, &c->pre, &c->Vsm, &c->Usm, &c->tsx};
     int64_t s = 0;
     for (const DevBuf *b : all) s += (int64_t)b->bytes;
     return s;
@@ -99,7 +100,8 @@ void hd_destroy(hd_ctx *c) {
                            &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->gfil, &c->V,
                      &c->Vb, &c->X, &c->R, &c->P, &c->Q, &c->Z, &c->Cpart, &c->Cl, &c->Cs,
                      &c->ClT, &c->CsT, &c->PT, &c->part, &c->scal, &c->xbuf, &c->sim, &c->ybuf,
-                     &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale, &c->pbar};
+                     &c->topk, &c->err, &c->qsplit, &c->Dg, &c->ymask, &c->uscale, &c->vscale, &c->pbar,
+                     &c->cut, &c->pre, &c->Vsm, &c->Usm, &c->tsx};
     for (DevBuf *b : all) b->release();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (hipEvent_t e : c->iter_ev)
@@ -240,8 +242,9 @@ int hd_load_graph(hd_ctx *c, int64_t n, int64_t nnz, const int64_t *rowptr, cons
 // none (r = 0), so no query can reach a released U1 buffer.
 static void drop_eigs(hd_ctx *c) {
     for (DevBuf *b : {&c->U, &c->Ub, &c->UbT, &c->Usr, &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->lam,
-                      &c->uscale})
+                      &c->uscale, &c->Usm})
         b->release();
+    c->usm_lo_off = 0;
     c->u_dtype = HD_F32;
     c->r = c->rp = 0;
     c->ldut = 0;
@@ -276,6 +279,46 @@ static int upload_eigs_fp8(hd_ctx *c, int r, int rp, const uint8_t *codes, const
 static int load_eigs_dense(hd_ctx *c, int r, int rp, const float *U, int dtype);
 static int upload_descriptors(hd_ctx *c, int d, int ldv, const float *V, int dtype);
 
+// The one-pass top-K's row samples (hd::topk_sample) of the stored matrix-core
+// forms, built on the device from the stored copies: the sampled item-major
+// U1 rows (each term) and the sampled descriptors (with their fp8 row
+// scales). None for fp32 storage or n < hd::kTopkFuseMin.
+static int build_usample(hd_ctx *c) {
+    c->Usm.release();
+    c->usm_lo_off = 0;
+    if (c->n < hd::kTopkFuseMin || !c->u_mfma() || c->rp == 0) return HD_OK;
+    int64_t st, m;
+    hd::topk_sample(c->n, &st, &m);
+    const int eb = c->u_fp8() ? 1 : 2, terms = c->u_dtype == HD_BF16X2 ? 2 : 1;
+    const size_t per = (size_t)((m + 15) / 16 * 16) * c->rp * eb, per_src = (size_t)((c->n + 15) / 16 * 16) * c->rp * eb;
+    HIP_TRY(c->Usm.ensure(per * terms));
+    for (int t = 0; t < terms; ++t)
+        HIP_TRY(hd::launch_sample_frag(m, st, c->rp, c->Ub.as<char>() + t * per_src, c->Usm.as<char>() + t * per, eb,
+                                       nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    c->usm_lo_off = per;
+    return HD_OK;
+}
+
+static int build_vsample(hd_ctx *c) {
+    c->Vsm.release();
+    c->vsm_scale_off = 0;
+    if (c->n < hd::kTopkFuseMin || c->v_dtype == HD_F32) return HD_OK;
+    int64_t st, m;
+    hd::topk_sample(c->n, &st, &m);
+    const bool fp8 = c->v_dtype == HD_FP8_E4M3;
+    const int eb = fp8 ? 1 : 2;
+    const size_t codes = ((size_t)((m + 15) / 16 * 16) * c->ldv * eb + 255) / 256 * 256;
+    HIP_TRY(c->Vsm.ensure(codes + (fp8 ? (size_t)m * sizeof(float) : 0)));
+    HIP_TRY(hd::launch_sample_frag(m, st, c->ldv, c->Vb.p, c->Vsm.p, eb, nullptr));
+    if (fp8)
+        HIP_TRY(hd::launch_sample_rows(m, st, 1, c->vscale.as<float>(),
+                                       reinterpret_cast<float *>(c->Vsm.as<char>() + codes), nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    c->vsm_scale_off = codes;
+    return HD_OK;
+}
+
 // The common tail of the eigenpair loaders: eigenvalues and the form.
 static int finish_eigs(hd_ctx *c, int r, int rp, const double *lambda, int dtype) {
     std::vector<double> lam((size_t)rp, 0.0);
@@ -286,7 +329,7 @@ static int finish_eigs(hd_ctx *c, int r, int rp, const double *lambda, int dtype
     c->r = r;
     c->rp = rp;
     c->u_dtype = dtype;
-    return HD_OK;
+    return build_usample(c);
 }
 
 int hd_load_eigs_fp8(hd_ctx *c, int32_t r, const uint8_t *codes, const float *col_scale, const double *lambda) {
@@ -491,6 +534,8 @@ static void drop_descriptors(hd_ctx *c) {
     c->V.release();
     c->Vb.release();
     c->vscale.release();
+    c->Vsm.release();
+    c->vsm_scale_off = 0;
     c->d = c->ldv = 0;
     c->v_dtype = HD_F32;
 }
@@ -517,7 +562,9 @@ int hd_load_descriptors_fp8(hd_ctx *c, int32_t d, const uint8_t *codes, const fl
     c->d = d;
     c->ldv = ldv;
     c->v_dtype = HD_FP8_E4M3;
-    return HD_OK;
+    const int f = build_vsample(c);
+    if (f != HD_OK) drop_descriptors(c);
+    return f;
 }
 
 int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
@@ -551,7 +598,9 @@ int hd_load_descriptors(hd_ctx *c, int32_t d, const float *V, int32_t dtype) {
     c->d = d;
     c->ldv = ldv;
     c->v_dtype = dtype;
-    return HD_OK;
+    const int f = build_vsample(c);
+    if (f != HD_OK) drop_descriptors(c);
+    return f;
 }
 
 // fp32 (n x ldv, zero padded) or bfloat16 (fragment order over n16 x ldv)
@@ -614,12 +663,37 @@ static int queue_y(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
         }
         if (c->v_dtype != HD_F32) {
             HIP_TRY(c->qsplit.ensure((size_t)2 * hd::sim_qsplit_rows(B) * c->ldv * sizeof(uint16_t)));
-            LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.p, c->ldv, c->qsplit.as<uint16_t>(),
-                                              c->sim.as<float>(), lds, s, c->v_scale()));
-        } else {
-            LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
         }
-        LAUNCH(K_TOPK_Y, hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
+        uint16_t *qs = c->qsplit.as<uint16_t>();
+        if (c->v_dtype != HD_F32 && c->onepass_y()) {
+            // one-pass top-k_y: thresholds from the sampled items'
+            // similarities, then the similarity kernel offers every value to
+            // the lists without writing sim; sim is written only if some row
+            // needs the exact fallback
+            int64_t st, m;
+            hd::topk_sample(n, &st, &m);
+            const int64_t lss = (m + 63) / 64 * 64;
+            HIP_TRY(c->tsx.ensure((size_t)B * lss * sizeof(float)));
+            const hd::TopkLists tl = hd::topk_lists(c->topk.p, B, n);
+            const int32_t *gate = hd::topk_fallback_gate(c->topk.p, B, n);
+            LAUNCH(K_TOPK_Y, hd::launch_sim_bf16(m, B, c->d, q_desc, c->Vsm.p, c->ldv, qs, c->tsx.as<float>(), lss, s,
+                                                 c->vsm_scale()));
+            LAUNCH(K_TOPK_Y, hd::launch_topk_prepare(B, n, c->tsx.as<float>(), lss, 1, ky, c->topk.p, s));
+            LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.p, c->ldv, qs, nullptr, lds, s, c->v_scale(),
+                                              &tl, nullptr, false));
+            LAUNCH(K_TOPK_Y, hd::launch_topk_select_lists(B, n, ky, c->topk.p, oi, ov, 1, s));
+            LAUNCH(K_TOPK_Y, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.p, c->ldv, qs, c->sim.as<float>(), lds, s,
+                                                 c->v_scale(), nullptr, gate, false));
+            LAUNCH(K_TOPK_Y, hd::launch_topk_fallback(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
+        } else {
+            if (c->v_dtype != HD_F32) {
+                LAUNCH(K_SIM, hd::launch_sim_bf16(n, B, c->d, q_desc, c->Vb.p, c->ldv, qs, c->sim.as<float>(), lds, s,
+                                                  c->v_scale()));
+            } else {
+                LAUNCH(K_SIM, hd::launch_sim(n, B, c->d, q_desc, c->V.as<float>(), c->ldv, c->sim.as<float>(), lds, s));
+            }
+            LAUNCH(K_TOPK_Y, hd::launch_topk(B, n, c->sim.as<float>(), lds, ky, c->topk.p, oi, ov, 1, s));
+        }
         *yi = oi;
         *yv = ov;
     } else {
@@ -1086,19 +1160,55 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         HIP_TRY(c->xbuf.ensure((size_t)B * n * sizeof(float)));
         xq = c->xbuf.as<float>();
     }
-    if (x_out || o->top_k > 0) {
-        if (sparse && rk > 0) {
-            LAUNCH(K_COMBINE, hd::launch_sp_combine(n, B, Usr, Usc, Usv, c->Cs.as<float>(), ldb, temporal, xq, n, s));
-        } else if (ubf && rk > 0) {
-            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal, xq, n,
-                                                        s, c->tv(HD_TUNE_UC_NT, ldb)));
+    const bool rank = o->top_k > 0 && (rank_ids || rank_scores);
+    const int K = o->top_k;
+    if (rank && !x_out && (rk == 0 || (ubf && !sparse)) && c->onepass_rank(rk)) {
+        // one-pass ranking: thresholds from the sampled items' x, then the
+        // combine offers every x to the lists without writing x; xq is
+        // written only if some row needs the exact fallback
+        int64_t st, m;
+        hd::topk_sample(n, &st, &m);
+        const int64_t lss = (m + 63) / 64 * 64;
+        HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, K)));
+        HIP_TRY(c->tsx.ensure(((size_t)B * lss + (size_t)m * ldb) * sizeof(float)));
+        float *ss = c->tsx.as<float>(), *xs = ss + (size_t)B * lss;
+        const hd::TopkLists tl = hd::topk_lists(c->topk.p, B, n);
+        const int32_t *gate = hd::topk_fallback_gate(c->topk.p, B, n);
+        const int nt = c->tv(HD_TUNE_UC_NT, ldb);
+        LAUNCH(K_TOPK_RANK, hd::launch_sample_rows(m, st, ldb, temporal, xs, s));
+        if (rk > 0) {
+            LAUNCH(K_TOPK_RANK, hd::launch_combine_bf16(m, B, c->u_item_sample(), c->rp, rk, CsT_hi, CsT_lo, ldb, xs,
+                                                          ss, lss, s, nt));
+            LAUNCH(K_TOPK_RANK, hd::launch_topk_prepare(B, n, ss, lss, 1, K, c->topk.p, s));
+            LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal,
+                                                        nullptr, n, s, nt, &tl));
         } else {
-            LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, temporal, xq, n, s));
+            LAUNCH(K_TOPK_RANK, hd::launch_topk_prepare(B, n, xs, 1, ldb, K, c->topk.p, s));
+            LAUNCH(K_COMBINE, hd::launch_topk_emit_nm(n, B, ldb, temporal, tl, s));
         }
-    }
-    if (o->top_k > 0 && (rank_ids || rank_scores)) {
-        HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, o->top_k)));
-        LAUNCH(K_TOPK_RANK, hd::launch_topk(B, n, xq, n, o->top_k, c->topk.p, rank_ids, rank_scores, 0, s));
+        LAUNCH(K_TOPK_RANK, hd::launch_topk_select_lists(B, n, K, c->topk.p, rank_ids, rank_scores, 0, s));
+        if (rk > 0) {
+            LAUNCH(K_TOPK_RANK, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal, xq,
+                                                          n, s, nt, nullptr, gate));
+        } else {
+            LAUNCH(K_TOPK_RANK, hd::launch_combine(n, B, nullptr, c->rp, 0, nullptr, ldb, temporal, xq, n, s, gate));
+        }
+        LAUNCH(K_TOPK_RANK, hd::launch_topk_fallback(B, n, xq, n, K, c->topk.p, rank_ids, rank_scores, 0, s));
+    } else {
+        if (x_out || o->top_k > 0) {
+            if (sparse && rk > 0) {
+                LAUNCH(K_COMBINE, hd::launch_sp_combine(n, B, Usr, Usc, Usv, c->Cs.as<float>(), ldb, temporal, xq, n, s));
+            } else if (ubf && rk > 0) {
+                LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal,
+                                                            xq, n, s, c->tv(HD_TUNE_UC_NT, ldb)));
+            } else {
+                LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, temporal, xq, n, s));
+            }
+        }
+        if (rank) {
+            HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, K)));
+            LAUNCH(K_TOPK_RANK, hd::launch_topk(B, n, xq, n, K, c->topk.p, rank_ids, rank_scores, 0, s));
+        }
     }
     if (last_iter_out) *last_iter_out = last_iter;
     return HD_OK;

@@ -190,6 +190,14 @@ struct hd_ctx {
     // rows padded to 16)
     int d = 0, ldv = 0, v_dtype = HD_F32;
     DevBuf V, Vb, vscale;  // vscale: one fp32 scale per row of fp8 descriptors
+    // the one-pass top-K's row sample (items t * stride, hd::topk_sample) of
+    // the matrix-core storage forms, in the same layouts: Vsm the sampled
+    // descriptors (then, for fp8, their row scales), Usm the sampled
+    // item-major U1 rows (hi, then lo for the two-term form); empty when
+    // n < hd::kTopkFuseMin or the form is fp32. tsx: per-batch sample scores
+    // and sampled rows of x^t
+    DevBuf Vsm, Usm, tsx;
+    size_t vsm_scale_off = 0, usm_lo_off = 0;  // bytes: fp8 row scales in Vsm, lo terms in Usm
     // solver workspace
     DevBuf X, R, P, Q, Z, Cpart, Cl, Cs, ClT, CsT, PT, part, scal, xbuf, sim, ybuf, topk, err, qsplit;
     int32_t *h_pinned = nullptr;  // [0..128): nact counts by parity, [200]: error flag
@@ -199,7 +207,7 @@ struct hd_ctx {
     DevBuf ymask;  // one bit per item: the rows where y (the first P) is nonzero
     hd::CgState st{};
     Timing timing;
-    int tune[HD_TUNE_NKEYS] = {0, 0, 0, 0};  // launch parameters (0 = default)
+    int tune[HD_TUNE_NKEYS] = {0, 0, 0, 0, 0};  // launch parameters (0 = default)
     // persistent CG for narrow batches: 0 off, 1 up to 16 queries, 2 up to 64;
     // the bound on each grid-barrier wait (spins); its barrier words
     int persist_mode = 0;
@@ -231,11 +239,24 @@ struct hd_ctx {
     // not fitting the width)
     int tv(int key, int ldb) const {
         if (key == HD_TUNE_SPMM_BANDS) return hd::band_param_ok(tune[key]) ? tune[key] : 1;
+        if (key == HD_TUNE_TOPK_ONEPASS) return tune[key];
         return hd::tile_param_ok(tune[key], ldb) ? tune[key] : 0;
     }
     // the sparse product's source-band count and cut offsets
     int bands() const { return hd::band_param_ok(tune[HD_TUNE_SPMM_BANDS]) ? tune[HD_TUNE_SPMM_BANDS] : 1; }
     const int32_t *cuts() const { return cut.as<int32_t>(); }
+    // the one-pass top-K applies to the y step / the ranking (setting 1
+    // keeps the two-pass form everywhere)
+    const float *vsm_scale() const {
+        return v_dtype == HD_FP8_E4M3 ? reinterpret_cast<const float *>(Vsm.as<char>() + vsm_scale_off) : nullptr;
+    }
+    hd::UOperand u_item_sample() const {
+        return hd::UOperand{Usm.p, u_dtype == HD_BF16X2 ? Usm.as<char>() + usm_lo_off : nullptr, u_fp8()};
+    }
+    bool onepass_y() const { return tune[HD_TUNE_TOPK_ONEPASS] != 1 && Vsm.p != nullptr; }
+    bool onepass_rank(int rk) const {
+        return tune[HD_TUNE_TOPK_ONEPASS] != 1 && n >= hd::kTopkFuseMin && (rk == 0 || (u_mfma() && Usm.p));
+    }
 };
 
 namespace hdi {

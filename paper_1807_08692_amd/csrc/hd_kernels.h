@@ -18,6 +18,18 @@
 
 namespace hd {
 
+// Candidate lists of the one-pass top-K (launch_topk_prepare and the
+// kernels that take a TopkLists): rows of at least kTopkFuseMin items.
+constexpr int64_t kTopkFuseMin = 65536;
+constexpr int kTopkChunk = 8192;    // items per candidate list of a row
+constexpr int kTopkChunkCap = 256;  // candidates kept per list
+struct TopkLists {
+    uint64_t *cand;        // [rows][nchunk][kTopkChunkCap] ranking keys
+    int32_t *cnt;          // [rows][nchunk] candidates offered to each list
+    const uint32_t *thr;   // [rows] order key of the row's threshold
+    int nchunk;
+};
+
 // Fragment order of an M x K bfloat16 matrix (K a multiple of 32, M padded
 // to a multiple of 16 with zero rows): the matrix is cut into 16 x 32 tiles,
 // tile (m / 16, k / 32) is stored at tile index (m / 16) kt + k / 32 (kt =
@@ -210,8 +222,10 @@ hipError_t launch_reduce_c(int nchunk, const float *Cpart, int rk, int ldb, cons
 hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl, int ldb,
                       const float *P, double alpha, float *Z, IterGuard g, hipStream_t s);
 // x[b][i] = (U Cs)[i][b] + X[i][b] for b < B, i < N   (x row stride ldx)
+// gate (nullptr = none): every block returns at once while *gate == 0
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
-                          int ldb, const float *X, float *x, int64_t ldx, hipStream_t s);
+                          int ldb, const float *X, float *x, int64_t ldx, hipStream_t s,
+                          const int32_t *gate = nullptr);
 
 // ---- bfloat16 storage form of the eigenvector and descriptor products
 //      (k_ugemm_bf16.hip); bf16 values are passed as their 16-bit patterns.
@@ -248,9 +262,12 @@ hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const 
                                    IterGuard g, hipStream_t s, int nt = 0, int width = 0,
                                    const uint32_t *rowmask = nullptr);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
+// tl (one-pass top-K): candidates to the lists, x not written; gate as in
+// launch_combine
 hipError_t launch_combine_bf16(int64_t N, int B, UOperand U, int rp, int rk,
                                const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
-                               const float *X, float *x, int64_t ldx, hipStream_t s, int nt = 0);
+                               const float *X, float *x, int64_t ldx, hipStream_t s, int nt = 0,
+                               const TopkLists *tl = nullptr, const int32_t *gate = nullptr);
 // Tile parameters: a requested value (0 = default) is valid for width ldb
 // when it is one of 1, 2, 4 and divides the width in 64-column units.
 bool tile_param_ok(int v, int ldb);
@@ -259,9 +276,13 @@ bool tile_param_ok(int v, int ldb);
 // vscale[j] times its codes); qsplit: scratch for 2 x sim_qsplit_rows(B) x
 // ldv bf16 (the hi / lo parts of q)
 inline int sim_qsplit_rows(int B) { return (B + 63) / 64 * 64; }
+// tl (one-pass top-K): candidates to the lists, sim not written; gate: every
+// block returns at once while *gate == 0; split_q = false reuses the split
+// of q already in qsplit (the same q, B and d)
 hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const void *V,
                            int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s,
-                           const float *vscale = nullptr);
+                           const float *vscale = nullptr, const TopkLists *tl = nullptr,
+                           const int32_t *gate = nullptr, bool split_q = true);
 
 // ---- similarity product for the observation vector (k_sim.hip) ----
 // sim[b][j] = sum_t q[b][t] V[j][t]  (q: B x d, row stride d; V: N x ldv)
@@ -276,6 +297,36 @@ size_t topk_scratch_bytes(int B, int64_t n, int K);
 // the lower id. transform = 1 writes max(0, s)^3 in place of the score.
 hipError_t launch_topk(int B, int64_t n, const float *x, int64_t ldx, int K, void *scratch,
                        int32_t *ids, float *scores, int transform, hipStream_t s);
+
+// ---- one-pass top-K: the filter fused into the kernel that produces the
+//      scores (rows of n >= kTopkFuseMin items; same scratch as launch_topk).
+// The scores of a fixed sample of each row (items t * stride, t < m, see
+// topk_sample) set the row's threshold (launch_topk_prepare); the score
+// kernel, given the TopkLists, appends every score at or above it to the
+// row's candidate lists and writes no score matrix; launch_topk_select_lists
+// sorts the lists. A row whose lists overflow or hold fewer than K is
+// flagged and left unwritten: a second launch of the score kernel gated on
+// topk_fallback_gate (its blocks return at once when no row is flagged)
+// writes the score matrix, and launch_topk_fallback selects the flagged rows
+// exactly from it. The result is the one launch_topk gives on the same scores.
+void topk_sample(int64_t n, int64_t *stride, int64_t *m);
+TopkLists topk_lists(void *scratch, int B, int64_t n);
+const int32_t *topk_fallback_gate(void *scratch, int B, int64_t n);
+// thresholds from the sample scores: value t of row b at S[b * ld_row + t * ld_item];
+// also empties the lists and clears the flags
+hipError_t launch_topk_prepare(int B, int64_t n, const float *S, int64_t ld_row, int64_t ld_item, int K,
+                               void *scratch, hipStream_t s);
+hipError_t launch_topk_select_lists(int B, int64_t n, int K, void *scratch, int32_t *ids, float *scores,
+                                    int transform, hipStream_t s);
+hipError_t launch_topk_fallback(int B, int64_t n, const float *x, int64_t ldx, int K, void *scratch,
+                                int32_t *ids, float *scores, int transform, hipStream_t s);
+// candidates of the scores x[b][i] = X[i][b] (node-major X, b < B <= ldb)
+hipError_t launch_topk_emit_nm(int64_t n, int B, int ldb, const float *X, TopkLists tl, hipStream_t s);
+// the sample's rows: fragment-order matrices (ld a multiple of 32, elem_bytes
+// 2 or 1; dst is m rounded up to 16 rows, zero past m) and row-major rows
+hipError_t launch_sample_frag(int64_t m, int64_t stride, int64_t ld, const void *src, void *dst, int elem_bytes,
+                              hipStream_t s);
+hipError_t launch_sample_rows(int64_t m, int64_t stride, int ld, const float *src, float *dst, hipStream_t s);
 
 // ---- SHybrid: sparsified U1 (k_sparse_u.hip). U~ by item (CSR rptr / rcol /
 //      rval, N rows) and by component (CSC cptr / crow / cval, rk columns) ----

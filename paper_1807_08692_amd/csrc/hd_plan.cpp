@@ -38,7 +38,8 @@ std::vector<intptr_t> snapshot(const hd_ctx *c) {
                             &c->Cpart,  &c->Cl,  &c->Cs,  &c->ClT,  &c->CsT,  &c->PT,   &c->part,
                             &c->scal,   &c->xbuf, &c->sim, &c->ybuf, &c->topk, &c->err, &c->qsplit,
                             &c->Usr,    &c->Usc, &c->Usv, &c->Ustp, &c->Ustr, &c->Ustv, &c->Dg,
-                            &c->ymask,  &c->uscale, &c->vscale, &c->pbar, &c->pre};
+                            &c->ymask,  &c->uscale, &c->vscale, &c->pbar, &c->pre, &c->Vsm, &c->Usm,
+                            &c->tsx};
     std::vector<intptr_t> v;
     for (const DevBuf *b : bufs) v.push_back((intptr_t)b->p);
     const int64_t meta[] = {c->n, c->nnz, c->r, c->rp, c->u_dtype, c->ldut, c->d, c->ldv, c->v_dtype};

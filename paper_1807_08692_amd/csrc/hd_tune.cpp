@@ -38,6 +38,8 @@ int hd_set_tuning(hd_ctx *c, int32_t key, int32_t value) {
     if (key == HD_TUNE_SPMM_BANDS) {
         if (value != 0 && !hd::band_param_ok(value))
             return fail(HD_EINVAL, "hd_set_tuning: value %d not in {0, 1, 2, 4, 8}", value);
+    } else if (key == HD_TUNE_TOPK_ONEPASS) {
+        if (value < 0 || value > 2) return fail(HD_EINVAL, "hd_set_tuning: value %d not in {0, 1, 2}", value);
     } else if (value != 0 && value != 1 && value != 2 && value != 4) {
         return fail(HD_EINVAL, "hd_set_tuning: value %d not in {0, 1, 2, 4}", value);
     }

@@ -28,16 +28,26 @@
 // full-row selection; at 8192 it is about one in 10^7. The kernel time of a
 // batch is that of its slowest row, so the cap matters more than the mean.
 // Candidate order within a list depends on timing; the result does not.
+//
+// One-pass form (rows of n >= kTopkFuseMin items): the threshold comes from
+// the scores of a fixed sample of the row's items, computed before the full
+// scores (launch_topk_prepare); the kernel that produces the scores appends
+// the candidates to the lists itself (hd_emit.h) and never writes the score
+// matrix; the select step then runs on the lists alone
+// (launch_topk_select_lists). A row it cannot finish from its lists is
+// flagged instead, and launch_topk_fallback selects the flagged rows exactly
+// once a gated second launch of the score kernel has written their scores.
 #include "hd_device.h"
 #include "hd_kernels.h"
+#include "hd_emit.h"
 
 namespace hd {
 
 constexpr int kCap = 8192;        // candidates per row for the final sort (64 KB of LDS)
 constexpr int kMaxChunk = 4096;   // filter blocks per row the fast path accepts (n <= 32M)
 constexpr int kSample = 4096;     // sampled elements per row
-constexpr int kChunk = 8192;      // row elements per filter block
-constexpr int kChunkCap = 256;    // candidates kept per filter block
+constexpr int kChunk = kTopkChunk;        // row elements per filter block
+constexpr int kChunkCap = kTopkChunkCap;  // candidates kept per filter block
 constexpr int kWide = 1024;       // threads of the thresh / select blocks
 
 struct TopkScratch {
@@ -45,6 +55,7 @@ struct TopkScratch {
     int32_t *cnt;     // [B][nchunk]
     uint32_t *thr;    // [B]
     int32_t *all;     // [B] 1 = threshold admits every element
+    int32_t *fb;      // [1 + B] one-pass form: any row flagged, then the row flags
     int nchunk;
 };
 
@@ -61,6 +72,8 @@ static TopkScratch carve(void *scratch, int B, int64_t n) {
     t.thr = reinterpret_cast<uint32_t *>(p);
     p += (size_t)B * sizeof(uint32_t);
     t.all = reinterpret_cast<int32_t *>(p);
+    p += (size_t)B * sizeof(int32_t);
+    t.fb = reinterpret_cast<int32_t *>(p);
     return t;
 }
 
@@ -68,8 +81,21 @@ size_t topk_scratch_bytes(int B, int64_t n, int K) {
     (void)K;
     const int64_t nchunk = ceil_div(n, kChunk);
     return (size_t)B * (nchunk * (kChunkCap * sizeof(uint64_t) + sizeof(int32_t)) +
-                        sizeof(uint32_t) + sizeof(int32_t)) + 256;
+                        sizeof(uint32_t) + 2 * sizeof(int32_t)) + sizeof(int32_t) + 256;
 }
+
+void topk_sample(int64_t n, int64_t *stride, int64_t *m) {
+    const int64_t st = ceil_div(n, kSample);
+    *stride = st;
+    *m = ceil_div(n, st);
+}
+
+TopkLists topk_lists(void *scratch, int B, int64_t n) {
+    const TopkScratch t = carve(scratch, B, n);
+    return TopkLists{t.cand, t.cnt, t.thr, t.nchunk};
+}
+
+const int32_t *topk_fallback_gate(void *scratch, int B, int64_t n) { return carve(scratch, B, n).fb; }
 
 template <typename T, int NT>
 __device__ __forceinline__ void bitonic_desc(T *s, int size) {
@@ -147,11 +173,13 @@ __device__ __forceinline__ uint32_t block_select_key(const uint32_t *key, int nk
     return prefix;
 }
 
-__global__ __launch_bounds__(kWide) void k_topk_thresh(int64_t n, const float *__restrict__ x,
-                                                       int64_t ldx, int K, int64_t stride,
-                                                       TopkScratch ts) {
+// Row b's sample: m values at x[b * ldx + t * sstride], t < m, drawn from a
+// row of n elements. lists = true (one-pass form) also empties the row's
+// candidate lists and clears its fallback flag (block 0 the shared one).
+__global__ __launch_bounds__(kWide) void k_topk_thresh(int64_t n, int64_t m, const float *__restrict__ x,
+                                                       int64_t ldx, int64_t sstride, int K,
+                                                       TopkScratch ts, bool lists) {
     const int b = blockIdx.x;
-    const int64_t m = (n + stride - 1) / stride;  // sample size, <= kSample = 4 * kWide
     uint32_t key[4];
     int nkey = 0;
 #pragma unroll
@@ -159,7 +187,7 @@ __global__ __launch_bounds__(kWide) void k_topk_thresh(int64_t n, const float *_
         const int64_t t = threadIdx.x + (int64_t)u * kWide;
         key[u] = 0u;
         if (t < m) {
-            key[u] = float_order_key(x[(size_t)b * ldx + (size_t)t * stride]);
+            key[u] = float_order_key(x[(size_t)b * ldx + (size_t)t * sstride]);
             nkey = u + 1;
         }
     }
@@ -173,6 +201,13 @@ __global__ __launch_bounds__(kWide) void k_topk_thresh(int64_t n, const float *_
     if (threadIdx.x == 0) {
         ts.thr[b] = thr;
         ts.all[b] = all ? 1 : 0;
+    }
+    if (lists) {
+        for (int c = threadIdx.x; c < ts.nchunk; c += kWide) ts.cnt[(size_t)b * ts.nchunk + c] = 0;
+        if (threadIdx.x == 0) {
+            ts.fb[1 + b] = 0;
+            if (b == 0) ts.fb[0] = 0;
+        }
     }
 }
 
@@ -270,10 +305,15 @@ __device__ __forceinline__ void write_out(const uint64_t *s, int K, int b, int32
     }
 }
 
+// mode 0: the two-pass form (fast path from the lists, else exact from x);
+// mode 1: the one-pass form, lists only (x is not read: a row the lists
+// cannot finish is flagged and left unwritten); mode 2: the flagged rows
+// only, exactly from x (every other block returns at once).
 __global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *__restrict__ x,
                                                        int64_t ldx, int K, TopkScratch ts,
                                                        int32_t *__restrict__ ids,
-                                                       float *__restrict__ scores, int transform) {
+                                                       float *__restrict__ scores, int transform,
+                                                       int mode) {
     __shared__ uint64_t s[kCap];
     __shared__ int offs[kMaxChunk + 1];
     __shared__ int hist[256];
@@ -283,10 +323,13 @@ __global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *_
     const float *row = x + (size_t)b * ldx;
     const int nchunk = ts.nchunk;
 
+    if (mode == 2 && ts.fb[1 + b] == 0) return;
     // ---- fast paths ----
     int total = -1;
-    if (ts.all[b]) {
-        if (n <= kCap) total = (int)n;
+    if (mode == 2) {
+        // flagged: straight to the exact selection
+    } else if (ts.all[b]) {
+        if (n <= kCap && mode == 0) total = (int)n;
     } else if (nchunk <= kMaxChunk) {
         // offsets of the per-chunk lists: 4 consecutive chunks per thread
         constexpr int kPer = kMaxChunk / kWide;
@@ -340,6 +383,14 @@ __global__ __launch_bounds__(kWide) void k_topk_select(int64_t n, const float *_
         return;
     }
 
+    if (mode == 1) {
+        // the lists cannot give this row's top K: flag it for the fallback
+        if (threadIdx.x == 0) {
+            ts.fb[1 + b] = 1;
+            atomicOr(&ts.fb[0], 1);
+        }
+        return;
+    }
     // ---- exact selection within the block ----
     uint32_t prefix = 0, pmask = 0;
     int need = K;  // rank (1-based) of the wanted key among those matching the prefix
@@ -420,7 +471,7 @@ hipError_t launch_topk(int B, int64_t n, const float *x, int64_t ldx, int K, voi
     if (K < 1 || K > kTopkMax || K > n || B < 1) return hipErrorInvalidValue;
     TopkScratch ts = carve(scratch, B, n);
     const int64_t stride = ceil_div(n, kSample);
-    k_topk_thresh<<<B, kWide, 0, s>>>(n, x, ldx, K, stride, ts);
+    k_topk_thresh<<<B, kWide, 0, s>>>(n, ceil_div(n, stride), x, ldx, stride, K, ts, false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 fg((unsigned)ts.nchunk, B);
@@ -431,7 +482,120 @@ hipError_t launch_topk(int B, int64_t n, const float *x, int64_t ldx, int K, voi
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_topk_select<<<B, kWide, 0, s>>>(n, x, ldx, K, ts, ids, scores, transform);
+    k_topk_select<<<B, kWide, 0, s>>>(n, x, ldx, K, ts, ids, scores, transform, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk_prepare(int B, int64_t n, const float *S, int64_t ld_row, int64_t ld_item, int K,
+                               void *scratch, hipStream_t s) {
+    if (K < 1 || K > kTopkMax || K > n || B < 1 || n < kTopkFuseMin) return hipErrorInvalidValue;
+    int64_t stride, m;
+    topk_sample(n, &stride, &m);
+    k_topk_thresh<<<B, kWide, 0, s>>>(n, m, S, ld_row, ld_item, K, carve(scratch, B, n), true);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk_select_lists(int B, int64_t n, int K, void *scratch, int32_t *ids, float *scores,
+                                    int transform, hipStream_t s) {
+    if (K < 1 || K > kTopkMax || K > n || B < 1 || n < kTopkFuseMin) return hipErrorInvalidValue;
+    k_topk_select<<<B, kWide, 0, s>>>(n, nullptr, 0, K, carve(scratch, B, n), ids, scores, transform, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk_fallback(int B, int64_t n, const float *x, int64_t ldx, int K, void *scratch,
+                                int32_t *ids, float *scores, int transform, hipStream_t s) {
+    if (K < 1 || K > kTopkMax || K > n || B < 1 || n < kTopkFuseMin) return hipErrorInvalidValue;
+    k_topk_select<<<B, kWide, 0, s>>>(n, x, ldx, K, carve(scratch, B, n), ids, scores, transform, 2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// One-pass candidates straight from node-major X (plain CG ranks x = X^T):
+// a block covers 256 items (64 per wave, so one list chunk) and 64 query
+// columns, lane = column; every wave loads its 64 items' column runs before
+// testing them.
+__global__ __launch_bounds__(kBlock) void k_topk_emit_nm(int64_t n, int B, int ldb, const float *__restrict__ X,
+                                                         TopkLists tl) {
+    __shared__ EmitStage es;
+    __shared__ uint32_t thr[64];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int b0 = blockIdx.y * 64;
+    const int64_t i0 = (int64_t)blockIdx.x * 256;
+    if (threadIdx.x < 64) thr[threadIdx.x] = b0 + threadIdx.x < B ? tl.thr[b0 + threadIdx.x] : 0u;
+    if (threadIdx.x == 0) es.n = 0;
+    __syncthreads();
+    const int b = b0 + lane;
+    const int64_t ib = i0 + 64 * w;
+    float v[16];
+    for (int u = 0; u < 64; u += 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t i = ib + u + q;
+            v[q] = i < n && b < B ? X[vec_index(n, ldb, i, b)] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t i = ib + u + q;
+            if (i < n && b < B) emit_one(es, thr[lane], b, i, v[q]);
+        }
+    }
+    __syncthreads();
+    emit_flush(es, tl, (int)(i0 / kTopkChunk), b0, b0 + 64 < B ? b0 + 64 : B);
+}
+
+hipError_t launch_topk_emit_nm(int64_t n, int B, int ldb, const float *X, TopkLists tl, hipStream_t s) {
+    if (n < 1 || B < 1 || B > ldb) return hipErrorInvalidValue;
+    const dim3 g((unsigned)ceil_div(n, 256), (unsigned)ceil_div(B, 64));
+    k_topk_emit_nm<<<g, kBlock, 0, s>>>(n, B, ldb, X, tl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Row samples. Fragment-order matrices (rows padded to 16, ld a multiple of
+// 32; elem_bytes 2 for bfloat16, 1 for fp8 codes): dst row t = src row
+// t * stride for t < m, zero rows from m to m rounded up to 16. A thread
+// copies one 8-element lane piece, contiguous in both layouts.
+__global__ __launch_bounds__(kBlock) void k_sample_frag(int64_t m, int64_t m16, int64_t stride, int64_t ld,
+                                                        const uint8_t *__restrict__ src,
+                                                        uint8_t *__restrict__ dst, int eb) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t pieces = ld / 8;
+    if (idx >= m16 * pieces) return;
+    const int64_t t = idx / pieces, k = 8 * (idx % pieces);
+    const size_t od = frag_offset(t, k, ld / 32) * (size_t)eb;
+    if (eb == 2) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (t < m) v = *reinterpret_cast<const uint4 *>(src + frag_offset(t * stride, k, ld / 32) * 2);
+        *reinterpret_cast<uint4 *>(dst + od) = v;
+    } else {
+        uint2 v = make_uint2(0u, 0u);
+        if (t < m) v = *reinterpret_cast<const uint2 *>(src + frag_offset(t * stride, k, ld / 32));
+        *reinterpret_cast<uint2 *>(dst + od) = v;
+    }
+}
+
+hipError_t launch_sample_frag(int64_t m, int64_t stride, int64_t ld, const void *src, void *dst, int elem_bytes,
+                              hipStream_t s) {
+    if (m < 1 || stride < 1 || ld % 32 != 0 || (elem_bytes != 1 && elem_bytes != 2)) return hipErrorInvalidValue;
+    const int64_t m16 = (m + 15) / 16 * 16, tot = m16 * (ld / 8);
+    k_sample_frag<<<(unsigned)ceil_div(tot, kBlock), kBlock, 0, s>>>(m, m16, stride, ld,
+                                                                     reinterpret_cast<const uint8_t *>(src),
+                                                                     reinterpret_cast<uint8_t *>(dst), elem_bytes);
+    return hipGetLastError();
+}
+
+// Row-major rows: dst[t * ld + c] = src[t * stride * ld + c], t < m, c < ld.
+__global__ __launch_bounds__(kBlock) void k_sample_rows(int64_t m, int64_t stride, int ld,
+                                                        const float *__restrict__ src, float *__restrict__ dst) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= m * ld) return;
+    const int64_t t = idx / ld, c = idx % ld;
+    dst[idx] = src[(size_t)t * (size_t)stride * (size_t)ld + (size_t)c];
+}
+
+hipError_t launch_sample_rows(int64_t m, int64_t stride, int ld, const float *src, float *dst, hipStream_t s) {
+    if (m < 1 || stride < 1 || ld < 1) return hipErrorInvalidValue;
+    k_sample_rows<<<(unsigned)ceil_div(m * ld, kBlock), kBlock, 0, s>>>(m, stride, ld, src, dst);
     return hipGetLastError();
 }
 

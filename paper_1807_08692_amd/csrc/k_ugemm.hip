@@ -307,7 +307,9 @@ hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl
 __global__ __launch_bounds__(kBlock) void k_combine(int64_t N, int B, const float *__restrict__ U,
                                                     int rp, int rk, const float *__restrict__ Csp,
                                                     int ldb, const float *__restrict__ X,
-                                                    float *__restrict__ x, int64_t ldx) {
+                                                    float *__restrict__ x, int64_t ldx,
+                                                    const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     __shared__ float Us[128][33];
     __shared__ __attribute__((aligned(16))) float Cs[32][64 + 4];
     __shared__ float T[64][129];
@@ -351,10 +353,44 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t N, int B, const floa
     }
 }
 
+// x[b][i] = X[i][b] (the combine with no eigenvector term): a block
+// transposes a 64-item x 64-query tile through LDS, reading 256-byte runs of
+// X's rows and writing 256-byte runs of x's rows.
+__global__ __launch_bounds__(kBlock) void k_xt(int64_t N, int B, int ldb, const float *__restrict__ X,
+                                               float *__restrict__ x, int64_t ldx,
+                                               const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
+    __shared__ float T[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int b0 = blockIdx.y * 64;
+    const int c = threadIdx.x % 64, r0 = threadIdx.x / 64;
+    float v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t i = i0 + r0 + 4 * r;
+        v[r] = i < N && b0 + c < B ? X[vec_index(N, ldb, i, b0 + c)] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) T[r0 + 4 * r][c] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int bl = r0 + 4 * r;
+        const int64_t i = i0 + c;
+        if (b0 + bl < B && i < N) x[(size_t)(b0 + bl) * ldx + i] = T[c][bl];
+    }
+}
+
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
-                          int ldb, const float *X, float *x, int64_t ldx, hipStream_t s) {
+                          int ldb, const float *X, float *x, int64_t ldx, hipStream_t s,
+                          const int32_t *gate) {
+    if (rk == 0) {
+        const dim3 g((unsigned)((N + 63) / 64), (unsigned)((B + 63) / 64));
+        k_xt<<<g, kBlock, 0, s>>>(N, B, ldb, X, x, ldx, gate);
+        return hipGetLastError();
+    }
     const unsigned nblk = (unsigned)((N + 127) / 128) * (unsigned)((B + 63) / 64);
-    k_combine<<<nblk, kBlock, 0, s>>>(N, B, U, rp, rk, Cs, ldb, X, x, ldx);
+    k_combine<<<nblk, kBlock, 0, s>>>(N, B, U, rp, rk, Cs, ldb, X, x, ldx, gate);
     return hipGetLastError();
 }
 

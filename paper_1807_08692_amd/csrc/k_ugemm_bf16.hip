@@ -27,6 +27,7 @@
 //   k = 8*(l/16) .. +7;  C (16 x 16, 4 values): row 4*(l/16) + v, col l % 16.
 #include "hd_device.h"
 #include "hd_kernels.h"
+#include "hd_emit.h"
 
 namespace hd {
 
@@ -552,20 +553,32 @@ hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const 
 // x[b][i] = (U Cs)[i][b] + X[i][b] (b < B): the product as in u_c over the
 // ldc >= B columns of CsT; each wave then writes its tile query-major, one
 // 16-item m-tile at a time through LDS, so that every query's 16 items go
-// out as one 64-byte run.
-template <int AK, int NT>
+// out as one 64-byte run. EMIT (one-pass top-K): each x is offered to its
+// query's candidate lists instead (a block's RB items lie in one list
+// chunk) and x is not written. gate: the launch returns while *gate == 0.
+template <int AK, int NT, bool EMIT>
 __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, const void *__restrict__ U,
                                                        const void *__restrict__ Ul, int rp,
                                                        int rk, const unsigned short *__restrict__ CT_hi,
                                                        const unsigned short *__restrict__ CT_lo, int ldc,
                                                        const float *__restrict__ X, float *__restrict__ x,
-                                                       int64_t ldx) {
+                                                       int64_t ldx, TopkLists tl,
+                                                       const int32_t *__restrict__ gate) {
+    if (!EMIT && gate && *gate == 0) return;
     __shared__ float T[4][64][17];
     constexpr int MT = tn_mt(NT), RB = tn_rows(NT);
     const unsigned L = xcd_tile(), ncg = (unsigned)ldc / (64 * NT);
     const int64_t i0 = (int64_t)(L / ncg) * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
+    __shared__ EmitStage es;
+    __shared__ uint32_t thr[64 * NT];
+    if (EMIT) {
+        // published by the first barrier of the block GEMM
+        for (int t = threadIdx.x; t < 64 * NT; t += kBlock)
+            thr[t] = nb0 + t < B ? tl.thr[nb0 + t] : 0u;
+        if (threadIdx.x == 0) es.n = 0;
+    }
     f32x4 acc[MT][4 * NT];
     tn_block<AK, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
@@ -600,22 +613,42 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
             for (int f = lane; f < 64 * 16; f += kWave) {
                 const int bl = f / 16, rl = f % 16;
                 const int64_t b = nb0 + 64 * ng + bl, i = ib + rl;
-                if (b < B && i < N) x[(size_t)b * ldx + i] = T[w][bl][rl];
+                if (b < B && i < N) {
+                    if (EMIT)
+                        emit_one(es, thr[64 * ng + bl], (int)b, i, T[w][bl][rl]);
+                    else
+                        x[(size_t)b * ldx + i] = T[w][bl][rl];
+                }
             }
         }
+    }
+    if (EMIT) {
+        __syncthreads();
+        const int64_t bh = nb0 + 64 * NT < B ? nb0 + 64 * NT : B;
+        emit_flush(es, tl, (int)(i0 / kTopkChunk), (int)nb0, (int)bh);
     }
 }
 
 hipError_t launch_combine_bf16(int64_t N, int B, UOperand U, int rp, int rk, const unsigned short *CT_hi,
                                const unsigned short *CT_lo, int ldb, const float *X, float *x,
-                               int64_t ldx, hipStream_t s, int ntr) {
+                               int64_t ldx, hipStream_t s, int ntr, const TopkLists *tl,
+                               const int32_t *gate) {
     if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
+    if (tl && (gate || kTopkChunk % tn_rows(1) != 0 || kTopkChunk % tn_rows(4) != 0)) return hipErrorInvalidValue;
     const int nt = tn_nt(ldb, ntr, 2);
     if (nt == 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
-#define HD_CB(AKV, NTV) \
-    k_combine_tn<AKV, NTV><<<nblk, kBlock, 0, s>>>(N, B, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, CT_lo, ldb, X, x, \
-                                                   ldx)
+    const TopkLists none{nullptr, nullptr, nullptr, 0};
+    const TopkLists &l = tl ? *tl : none;
+#define HD_CB(AKV, NTV)                                                                                         \
+    do {                                                                                                        \
+        if (tl)                                                                                                 \
+            k_combine_tn<AKV, NTV, true><<<nblk, kBlock, 0, s>>>(N, B, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, \
+                                                                 CT_lo, ldb, X, x, ldx, l, gate);               \
+        else                                                                                                    \
+            k_combine_tn<AKV, NTV, false><<<nblk, kBlock, 0, s>>>(N, B, U.hi, U.lo ? U.lo : U.hi, rp, rk,       \
+                                                                  CT_hi, CT_lo, ldb, X, x, ldx, l, gate);       \
+    } while (0)
 #define HD_CB_NT(AKV) \
     if (nt == 4) HD_CB(AKV, 4); else if (nt == 2) HD_CB(AKV, 2); else HD_CB(AKV, 1)
     switch (akind(U)) {
@@ -660,19 +693,31 @@ __global__ __launch_bounds__(kBlock) void k_split_q(int B, int B64, int d, int l
 // The logical tiles run
 // over the query tiles fastest, so the tiles of one item range run on one
 // XCD and share V through its L2.
-template <int VK>
+// EMIT (one-pass top-k): every similarity is offered to its query's
+// candidate lists (tl) and sim is not written; a block's 256 items lie in
+// one list chunk. gate: the whole launch returns while *gate == 0.
+template <int VK, bool EMIT>
 __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ldv,
                                                      const unsigned short *__restrict__ Qh,
                                                      const unsigned short *__restrict__ Ql,
                                                      const void *__restrict__ V,
                                                      const float *__restrict__ vscale,
-                                                     float *__restrict__ sim, int64_t lds) {
+                                                     float *__restrict__ sim, int64_t lds, TopkLists tl,
+                                                     const int32_t *__restrict__ gate) {
+    if (!EMIT && gate && *gate == 0) return;
     __shared__ __attribute__((aligned(16))) unsigned short Qs[2][4][512];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int g = lane / 16, c16 = lane % 16;
     const unsigned L = xcd_tile(), nqt = (unsigned)(B + 63) / 64;
     const int b0 = (int)(L % nqt) * 64;
     const int64_t jb = (int64_t)(L / nqt) * 256;
+    __shared__ EmitStage es;
+    __shared__ uint32_t thr[64];
+    if (EMIT) {
+        // published by the first barrier of the k loop
+        if (threadIdx.x < 64) thr[threadIdx.x] = b0 + (int)threadIdx.x < B ? tl.thr[b0 + threadIdx.x] : 0u;
+        if (threadIdx.x == 0) es.n = 0;
+    }
     f32x4 acc[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -746,27 +791,44 @@ __global__ __launch_bounds__(kBlock, 3) void k_sim_bf16(int64_t N, int B, int ld
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int b = b0 + 16 * m + 4 * g + v;
-                if (b < B) sim[(size_t)b * lds + j] = VK == AK_FP8 ? acc[m][n][v] * sc : acc[m][n][v];
+                const int bl = 16 * m + 4 * g + v, b = b0 + bl;
+                if (b >= B) continue;
+                const float val = VK == AK_FP8 ? acc[m][n][v] * sc : acc[m][n][v];
+                if (EMIT)
+                    emit_one(es, thr[bl], b, j, val);
+                else
+                    sim[(size_t)b * lds + j] = val;
             }
+    }
+    if (EMIT) {
+        __syncthreads();
+        emit_flush(es, tl, (int)(jb / kTopkChunk), b0, b0 + 64 < B ? b0 + 64 : B);
     }
 }
 
 hipError_t launch_sim_bf16(int64_t N, int B, int d, const float *q, const void *V,
                            int ldv, unsigned short *qsplit, float *sim, int64_t lds, hipStream_t s,
-                           const float *vscale) {
+                           const float *vscale, const TopkLists *tl, const int32_t *gate, bool split_q) {
     if (ldv % 32 != 0) return hipErrorInvalidValue;
+    if (tl && (gate || kTopkChunk % 256 != 0)) return hipErrorInvalidValue;
     const int B64 = sim_qsplit_rows(B);
     unsigned short *Qh = qsplit, *Ql = qsplit + (size_t)B64 * ldv;
     const size_t tot = (size_t)B64 * ldv;
-    k_split_q<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(B, B64, d, ldv, q, Qh, Ql);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (split_q) {
+        k_split_q<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(B, B64, d, ldv, q, Qh, Ql);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const unsigned nblk = (unsigned)((B + 63) / 64) * (unsigned)((N + 255) / 256);
-    if (vscale)
-        k_sim_bf16<AK_FP8><<<nblk, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, vscale, sim, lds);
-    else
-        k_sim_bf16<AK_BF16><<<nblk, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, vscale, sim, lds);
+    const TopkLists none{nullptr, nullptr, nullptr, 0};
+    const TopkLists &l = tl ? *tl : none;
+#define HD_SIM(VKV, EM) k_sim_bf16<VKV, EM><<<nblk, kBlock, 0, s>>>(N, B, ldv, Qh, Ql, V, vscale, sim, lds, l, gate)
+    if (vscale) {
+        if (tl) HD_SIM(AK_FP8, true); else HD_SIM(AK_FP8, false);
+    } else {
+        if (tl) HD_SIM(AK_BF16, true); else HD_SIM(AK_BF16, false);
+    }
+#undef HD_SIM
     return hipGetLastError();
 }
 

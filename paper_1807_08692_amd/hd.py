@@ -104,7 +104,7 @@ def quantize_fp8(A, per_column: bool):
 
 
 # Launch parameters (hd_tune_key)
-TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2, "spmm_bands": 3}
+TUNE_KEYS = {"spmm_cpl": 0, "utp_nt": 1, "uc_nt": 2, "spmm_bands": 3, "topk_onepass": 4}
 
 
 class hd_eig_opts(ctypes.Structure):

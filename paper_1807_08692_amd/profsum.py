@@ -43,6 +43,7 @@ KINDS = {
     "hd::k_update_r": ("update_r", "k_cg.hip"),
     "hd::k_combine_tn": ("combine", "k_ugemm_bf16.hip"),
     "hd::k_combine": ("combine", "k_ugemm.hip"),
+    "hd::k_xt": ("combine", "k_ugemm.hip"),
     "hd::k_sim_bf16": ("sim", "k_ugemm_bf16.hip"),
     "hd::k_sim": ("sim", "k_sim.hip"),
     "hd::k_cg_persist": ("cg_persist", "k_persist.hip"),

@@ -43,8 +43,9 @@ def run(ctx, fx, torch_dev, B):
     return out["x"].cpu().numpy(), out["rank_ids"].cpu().numpy(), out["iters"].copy()
 
 
-KEYS = ("spmm_cpl", "utp_nt", "uc_nt", "spmm_bands")
-VALUES = {"spmm_cpl": (1, 2, 4), "utp_nt": (1, 2, 4), "uc_nt": (1, 2, 4), "spmm_bands": (1, 2, 4, 8)}
+KEYS = ("spmm_cpl", "utp_nt", "uc_nt", "spmm_bands", "topk_onepass")
+VALUES = {"spmm_cpl": (1, 2, 4), "utp_nt": (1, 2, 4), "uc_nt": (1, 2, 4), "spmm_bands": (1, 2, 4, 8),
+          "topk_onepass": (1, 2)}
 
 
 @pytest.mark.parametrize("B", [40, 130, 300])
@@ -83,6 +84,7 @@ def test_autotune_keeps_valid_values(ctx, fx, torch_dev):
     assert res["spmm_cpl"]["chosen"] in (1, 2, 4)
     assert res["spmm_bands"]["chosen"] in (1, 2, 4, 8)
     assert len(res["spmm_bands"]["times_ms"]) == 4
+    assert res["topk_onepass"]["times_ms"] == {} and res["topk_onepass"]["chosen"] == 0
     x, r, _ = run(ctx, fx, torch_dev, 200)
     assert np.array_equal(r, r0) and np.array_equal(x, x0)
 
@@ -97,5 +99,9 @@ def test_set_tuning_rejects_bad_values(ctx):
         ctx.set_tuning("spmm_bands", 3)
     with pytest.raises(hd.HDError):
         ctx.set_tuning("spmm_bands", 16)
+    with pytest.raises(hd.HDError):
+        ctx.set_tuning("topk_onepass", 3)
+    with pytest.raises(hd.HDError):
+        ctx.set_tuning("topk_onepass", 4)
     assert ctx.get_tuning("spmm_cpl") in (0, 1, 2, 4)
     assert ctx.get_tuning("spmm_bands") in (0, 1, 2, 4, 8)
