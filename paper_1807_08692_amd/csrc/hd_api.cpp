@@ -643,6 +643,14 @@ int hd_rank(hd_ctx *c, int32_t B, int64_t n, const float *x, int64_t ldx, int32_
 
 }  // extern "C"
 
+// Bytes of the one-pass top-K's per-batch sample buffer (c->tsx): the B x m
+// sample scores (rows padded to 64) and m sampled rows of x^t at the widest
+// solver width; one size for both selections of a query, so the second
+// never reallocates the buffer under the first.
+static size_t onepass_sample_bytes(int B, int64_t m) {
+    return ((size_t)B * (size_t)((m + 63) / 64 * 64) + (size_t)m * 1024) * sizeof(float);
+}
+
 // Step 1 (Section 3; Section 6.1): the observation vectors y of B queries from
 // their descriptors (similarities to every item, the k_y largest, cubed), or
 // the given sparse y copied to the optional outputs. *yi / *yv receive the
@@ -673,7 +681,7 @@ static int queue_y(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y_i
             int64_t st, m;
             hd::topk_sample(n, &st, &m);
             const int64_t lss = (m + 63) / 64 * 64;
-            HIP_TRY(c->tsx.ensure((size_t)B * lss * sizeof(float)));
+            HIP_TRY(c->tsx.ensure(onepass_sample_bytes(B, m)));
             const hd::TopkLists tl = hd::topk_lists(c->topk.p, B, n);
             const int32_t *gate = hd::topk_fallback_gate(c->topk.p, B, n);
             LAUNCH(K_TOPK_Y, hd::launch_sim_bf16(m, B, c->d, q_desc, c->Vsm.p, c->ldv, qs, c->tsx.as<float>(), lss, s,
@@ -1170,7 +1178,7 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         hd::topk_sample(n, &st, &m);
         const int64_t lss = (m + 63) / 64 * 64;
         HIP_TRY(c->topk.ensure(hd::topk_scratch_bytes(B, n, K)));
-        HIP_TRY(c->tsx.ensure(((size_t)B * lss + (size_t)m * ldb) * sizeof(float)));
+        HIP_TRY(c->tsx.ensure(onepass_sample_bytes(B, m)));
         float *ss = c->tsx.as<float>(), *xs = ss + (size_t)B * lss;
         const hd::TopkLists tl = hd::topk_lists(c->topk.p, B, n);
         const int32_t *gate = hd::topk_fallback_gate(c->topk.p, B, n);

@@ -125,11 +125,11 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
                             bool x_only = false, const uint32_t *rowmask = nullptr);
 // update_xp that also writes the new P as its split transpose (bfloat16
 // forms; PT_hi / PT_lo ldb x ldpt in fragment order, ldpt a multiple of 64
-// >= N)
+// >= N); width as in launch_update_xp
 hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
                                const double *a, const double *beta, const int32_t *active,
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
-                               hipStream_t s, const uint32_t *rowmask = nullptr);
+                               hipStream_t s, const uint32_t *rowmask = nullptr, int width = 0);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 // colmap (nullptr = identity, B columns of ldb): y row t -> column colmap[t]
 // U: fp32 item-major N x rp (fmt = 0), bfloat16 bit patterns in fragment
@@ -240,6 +240,12 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 // hi / lo split of P^T (P: N x ldb fp32 node-major); ldpt a multiple of 64.
 hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
                            unsigned short *PTl, IterGuard g, hipStream_t s, int width = 0);
+// Columns cols[0..m) admitted into a running solve, their P set to y (the
+// k_y rows ids[t * ky ..] of column cols[t], zero elsewhere): their part of
+// PT_hi / PT_lo is zeroed, then written from P at the y rows, as
+// launch_split_pt would write it.
+hipError_t launch_pt_admit(int m, int ky, const int32_t *ids, const int32_t *cols, int64_t N, int ldb,
+                           const float *P, int64_t ldpt, unsigned short *PTh, unsigned short *PTl, hipStream_t s);
 // Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT: the
 // rp x ldut matrix in fragment order, zero past N) and P as its split
 // transpose (PT_hi / PT_lo, pitch ldut)

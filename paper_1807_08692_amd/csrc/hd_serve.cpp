@@ -197,6 +197,10 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
     SRV_TRY(hd::launch_fill_zero(v->P.as<float>(), (size_t)c->n * ldb, v->s));
     SRV_TRY(hd::launch_fill_zero(v->scal.as<float>(), v->scal.bytes / sizeof(float), v->s));
     if (rk > 0) SRV_TRY(hd::launch_fill_zero(v->Cs.as<float>(), (size_t)rk * ldb, v->s));
+    // the split P^T of the bfloat16 forms is kept equal to the split of P
+    // from here on (admission writes the new columns' part, every iteration
+    // the whole of it with the new P)
+    if (v->fused) SRV_TRY(hd::launch_fill_zero(v->PT.as<float>(), (size_t)ldb * c->ldut, v->s));
     SRV_TRY(hipStreamSynchronize(v->s));
 #undef SRV_TRY
     *out = sv;
@@ -314,6 +318,10 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     HIP_TRY(hd::launch_zero_cols(N, ldb, v->X.as<float>(), v->R.as<float>(), v->P.as<float>(), cols, m, s));
     HIP_TRY(hd::launch_scatter_y(m, ky, yi, yv, N, ldb, v->R.as<float>(), v->P.as<float>(),
                                  v->err.as<int32_t>(), s, cols));
+    if (v->fused) {
+        uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
+        HIP_TRY(hd::launch_pt_admit(m, ky, yi, cols, N, ldb, v->P.as<float>(), c->ldut, PTh, PTl, s));
+    }
     HIP_TRY(hd::launch_ynorm_part(m, ky, yi, N, ldb, v->R.as<float>(), v->part.as<double>(), s, cols));
     HIP_TRY(hd::launch_init_cols(ldb, v->part.as<double>(), 1, v->st, cols, v->maxit.as<int32_t>(), m, s));
     if (v->rk > 0) {
@@ -364,10 +372,10 @@ int hd_serve_step(hd_server *v, int32_t iters) {
         if (v->ticket[(size_t)t] >= 0) hi = t;
     const int w = hi < 0 ? 0 : (hi + 64) / 64 * 64;
     for (int it = 0; it < iters && v->fused && w > 0; ++it) {
-        // L1 U1^T P for every column (a newly admitted column has P = y);
-        // the correction goes into the residual update
+        // L1 U1^T P for every column (a newly admitted column has P = y),
+        // from the split P^T that admission and the previous x/p update
+        // wrote; the correction goes into the residual update
         uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
-        HIP_TRY(hd::launch_split_pt(N, ldb, P, c->ldut, PTh, PTl, g, s, w));
         HIP_TRY(hd::launch_ut_p_bf16(N, c->u_comp(), c->ldut, rk, PTh, PTl, ldb,
                                      v->Cpart.as<float>(), g, s, c->tv(HD_TUNE_UTP_NT, w), w));
         HIP_TRY(hd::launch_reduce_c(v->nchunk, v->Cpart.as<float>(), rk, ldb, c->lam.as<double>(), v->r_use,
@@ -381,7 +389,8 @@ int hd_serve_step(hd_server *v, int32_t iters) {
                                             v->o.alpha, R, v->st.a, v->part.as<double>(), g, s,
                                             c->tv(HD_TUNE_UC_NT, w), w));
         HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->nrb, v->o.tol, v->st, g, v->st.nact_part, s));
-        HIP_TRY(hd::launch_update_xp(N, ldb, X, P, R, v->st.a, v->st.beta, v->st.active, g, s, w));
+        HIP_TRY(hd::launch_update_xp_pt(N, ldb, X, P, R, v->st.a, v->st.beta, v->st.active, c->ldut, PTh, PTl, g, s,
+                                        nullptr, w));
     }
     for (int it = 0; it < iters && !v->fused; ++it) {
         const float *Zs = P;

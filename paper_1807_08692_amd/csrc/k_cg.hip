@@ -592,9 +592,11 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
 hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
                                const double *a, const double *beta, const int32_t *active,
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
-                               hipStream_t s, const uint32_t *rowmask) {
-    if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0) return hipErrorInvalidValue;
-    k_update_xp_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(ldb / 64)), kBlock, 0, s>>>(
+                               hipStream_t s, const uint32_t *rowmask, int width) {
+    if (width == 0) width = ldb;
+    if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0 || width % 64 != 0 || width > ldb)
+        return hipErrorInvalidValue;
+    k_update_xp_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(width / 64)), kBlock, 0, s>>>(
         N, ldb, X, P, R, a, beta, active, ldpt, PTh, PTl, g, rowmask);
     return hipGetLastError();
 }

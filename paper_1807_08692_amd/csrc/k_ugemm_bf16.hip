@@ -286,6 +286,50 @@ hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, uns
     return hipGetLastError();
 }
 
+// Admitted columns: zero their lane pieces (one 8-item piece of one column
+// per thread, hi and lo), then write the split of P at their y rows.
+__global__ __launch_bounds__(kBlock) void k_pt_zero_cols(const int32_t *__restrict__ cols, int64_t ldpt,
+                                                         unsigned short *__restrict__ PTh,
+                                                         unsigned short *__restrict__ PTl) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= ldpt / 8) return;
+    const size_t o = frag_offset(cols[blockIdx.y], 8 * p, ldpt / 32);
+    *reinterpret_cast<uint4 *>(PTh + o) = make_uint4(0u, 0u, 0u, 0u);
+    *reinterpret_cast<uint4 *>(PTl + o) = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pt_scatter_y(int m, int ky, const int32_t *__restrict__ ids,
+                                                         const int32_t *__restrict__ cols, int64_t N, int ldb,
+                                                         const float *__restrict__ P, int64_t ldpt,
+                                                         unsigned short *__restrict__ PTh,
+                                                         unsigned short *__restrict__ PTl) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= m * ky) return;
+    const int64_t i = ids[t];
+    if (i < 0 || i >= N) return;  // the admission's id check rejects the batch
+    const int col = cols[t / ky];
+    // repeated ids write the same value (P holds their sum)
+    const float v = P[vec_index(N, ldb, i, col)];
+    const __bf16 hb = (__bf16)v;
+    const size_t o = frag_offset(col, i, ldpt / 32);
+    PTh[o] = __builtin_bit_cast(unsigned short, hb);
+    PTl[o] = __builtin_bit_cast(unsigned short, (__bf16)(v - (float)hb));
+}
+
+hipError_t launch_pt_admit(int m, int ky, const int32_t *ids, const int32_t *cols, int64_t N, int ldb,
+                           const float *P, int64_t ldpt, unsigned short *PTh, unsigned short *PTl, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    if (ldpt % 64 != 0 || ldpt < N || ky < 1) return hipErrorInvalidValue;
+    k_pt_zero_cols<<<dim3((unsigned)((ldpt / 8 + kBlock - 1) / kBlock), (unsigned)m), kBlock, 0, s>>>(cols, ldpt, PTh,
+                                                                                                    PTl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int tot = m * ky;
+    k_pt_scatter_y<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(m, ky, ids, cols, N, ldb, P, ldpt, PTh,
+                                                                           PTl);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Cpart[c] = U[chunk c]^T P[chunk c]: M = k (UT rows, component-major U,
 // row stride ldut, items past N zero), N = b (PT rows), K = the chunk's
