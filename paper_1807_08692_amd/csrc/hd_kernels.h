@@ -125,11 +125,14 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
                             bool x_only = false, const uint32_t *rowmask = nullptr);
 // update_xp that also writes the new P as its split transpose (bfloat16
 // forms; PT_hi / PT_lo ldb x ldpt in fragment order, ldpt a multiple of 64
-// >= N); width as in launch_update_xp
-hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
+// >= N); width as in launch_update_xp. iters (a server's running solve; no
+// rowmask): a column's first update (iters 1) overwrites X with a p, and a
+// stopped column's P and R are set to zero (its PT with them)
+hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, float *R,
                                const double *a, const double *beta, const int32_t *active,
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
-                               hipStream_t s, const uint32_t *rowmask = nullptr, int width = 0);
+                               hipStream_t s, const uint32_t *rowmask = nullptr, int width = 0,
+                               const int32_t *iters = nullptr);
 hipError_t launch_cg_final(int ldb, CgState st, hipStream_t s);
 // colmap (nullptr = identity, B columns of ldb): y row t -> column colmap[t]
 // U: fp32 item-major N x rp (fmt = 0), bfloat16 bit patterns in fragment
@@ -158,10 +161,11 @@ hipError_t launch_init_cols(int ldb, const double *part, int nblk, CgState st, c
                             const int32_t *maxit, int ncols, hipStream_t s);
 // columns cols[0..ncols) stop: inactive from now on (their vectors untouched)
 hipError_t launch_cancel_cols(CgState st, const int32_t *cols, int ncols, hipStream_t s);
-// Xc (N x ldc node-major) and Csc (rk x ldc) = the columns cols[0..ncols) of X and Cs
+// Xc (N x ldc node-major) and Csc (rk x ldc) = the columns cols[0..ncols) of X and Cs;
+// iters (nullptr = none): columns with no iteration done give x = 0
 hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *Cs, int rk,
                               const int32_t *cols, int ncols, int ldc, float *Xc, float *Csc,
-                              hipStream_t s);
+                              hipStream_t s, const int32_t *iters = nullptr);
 
 // ---- persistent CG for narrow batches (k_persist.hip): node-major N x W
 //      vectors, W a power of two in 1..64; plain CG, or with fp32 U1
@@ -241,11 +245,13 @@ hipError_t launch_split_t(const float *C, int rk, int ldb, unsigned short *CT_hi
 hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
                            unsigned short *PTl, IterGuard g, hipStream_t s, int width = 0);
 // Columns cols[0..m) admitted into a running solve, their P set to y (the
-// k_y rows ids[t * ky ..] of column cols[t], zero elsewhere): their part of
-// PT_hi / PT_lo is zeroed, then written from P at the y rows, as
-// launch_split_pt would write it.
-hipError_t launch_pt_admit(int m, int ky, const int32_t *ids, const int32_t *cols, int64_t N, int ldb,
-                           const float *P, int64_t ldpt, unsigned short *PTh, unsigned short *PTl, hipStream_t s);
+// k_y rows ids[t * ky ..] of column cols[t], zero elsewhere): the part of
+// PT_hi / PT_lo of the columns zcols[0..nz) (those whose PT may not be zero)
+// is zeroed, then every admitted column's is written from P at its y rows,
+// as launch_split_pt would write it.
+hipError_t launch_pt_admit(int m, int ky, const int32_t *ids, const int32_t *cols, const int32_t *zcols, int nz,
+                           int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
+                           unsigned short *PTl, hipStream_t s);
 // Cpart[c] = U[chunk c]^T P[chunk c], U given component-major (UT: the
 // rp x ldut matrix in fragment order, zero past N) and P as its split
 // transpose (PT_hi / PT_lo, pitch ldut)

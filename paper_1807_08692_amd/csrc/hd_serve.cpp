@@ -32,6 +32,12 @@ struct Srv {
     int32_t *h = nullptr;  // pinned: [0,ldb) active, [ldb,2ldb) iters, [2ldb,3ldb) status, err
     double *hr = nullptr;  // pinned: relres
     std::vector<int64_t> ticket;  // per column, -1 = free
+    // per column (bfloat16 forms): 1 = its X, R, P may hold values that no
+    // step has cleared since a request was admitted into it or stopped
+    // outside a step (cancelled); admission clears such a column first. A
+    // column whose request stops inside a step is cleared by that step's
+    // x/p update (launch_update_xp_pt with the iteration counts).
+    std::vector<uint8_t> dirty;
     int64_t next_ticket = 1;
 
     void release() {
@@ -164,7 +170,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
     SRV_TRY(v->part.ensure((size_t)(v->fused && v->nrb > rp.nblk ? v->nrb : rp.nblk) * ldb * sizeof(double)));
     SRV_TRY(v->scal.ensure((size_t)ldb * (5 * sizeof(double) + 4 * sizeof(int32_t)) + 128 * sizeof(int32_t)));
     SRV_TRY(v->err.ensure(16));
-    SRV_TRY(v->cols.ensure((size_t)ldb * sizeof(int32_t)));
+    SRV_TRY(v->cols.ensure((size_t)2 * ldb * sizeof(int32_t)));  // admitted columns, then the ones to clear
     SRV_TRY(v->maxit.ensure((size_t)ldb * sizeof(int32_t)));
     SRV_TRY(v->xc.ensure(vec));
     SRV_TRY(v->xq.ensure((size_t)c->n * ldb * sizeof(float)));
@@ -201,6 +207,7 @@ int hd_serve_open(hd_ctx *c, int32_t slots, int64_t hbm_budget_bytes, const hd_q
     // from here on (admission writes the new columns' part, every iteration
     // the whole of it with the new P)
     if (v->fused) SRV_TRY(hd::launch_fill_zero(v->PT.as<float>(), (size_t)ldb * c->ldut, v->s));
+    v->dirty.assign((size_t)ldb, 0);
     SRV_TRY(hipStreamSynchronize(v->s));
 #undef SRV_TRY
     *out = sv;
@@ -248,7 +255,10 @@ int hd_serve_cancel(hd_server *v, int32_t n, const int64_t *tickets) {
     HIP_TRY(hipMemcpyAsync(v->cols.p, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hd::launch_cancel_cols(v->st, v->cols.as<int32_t>(), (int)cols.size(), s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (int32_t t : cols) v->ticket[(size_t)t] = -1;
+    for (int32_t t : cols) {
+        v->ticket[(size_t)t] = -1;
+        v->dirty[(size_t)t] = 1;
+    }
     return (int)cols.size();
 }
 
@@ -311,17 +321,24 @@ int hd_serve_submit(hd_server *v, int32_t n, const float *q_desc, const int32_t 
     }
     std::vector<int32_t> caps((size_t)m);
     for (int t = 0; t < m; ++t) caps[(size_t)t] = max_iter ? max_iter[t] : v->o.max_iter;
-    HIP_TRY(hipMemcpyAsync(v->cols.p, freec.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // the admitted columns, then those of them to clear first: all of them
+    // without the bfloat16 forms, else the dirty ones
+    std::vector<int32_t> lists(freec.begin(), freec.begin() + m);
+    for (int t = 0; t < m; ++t)
+        if (!v->fused || v->dirty[(size_t)freec[(size_t)t]]) lists.push_back(freec[(size_t)t]);
+    const int nz = (int)lists.size() - m;
+    HIP_TRY(hipMemcpyAsync(v->cols.p, lists.data(), lists.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(v->maxit.p, caps.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    const int32_t *cols = v->cols.as<int32_t>();
+    const int32_t *cols = v->cols.as<int32_t>(), *zcols = cols + m;
     HIP_TRY(hd::launch_fill_zero(v->err.as<float>(), 1, s));
-    HIP_TRY(hd::launch_zero_cols(N, ldb, v->X.as<float>(), v->R.as<float>(), v->P.as<float>(), cols, m, s));
+    HIP_TRY(hd::launch_zero_cols(N, ldb, v->X.as<float>(), v->R.as<float>(), v->P.as<float>(), zcols, nz, s));
     HIP_TRY(hd::launch_scatter_y(m, ky, yi, yv, N, ldb, v->R.as<float>(), v->P.as<float>(),
                                  v->err.as<int32_t>(), s, cols));
     if (v->fused) {
         uint16_t *PTh = v->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
-        HIP_TRY(hd::launch_pt_admit(m, ky, yi, cols, N, ldb, v->P.as<float>(), c->ldut, PTh, PTl, s));
+        HIP_TRY(hd::launch_pt_admit(m, ky, yi, cols, zcols, nz, N, ldb, v->P.as<float>(), c->ldut, PTh, PTl, s));
     }
+    for (int t = 0; t < m; ++t) v->dirty[(size_t)freec[(size_t)t]] = 1;
     HIP_TRY(hd::launch_ynorm_part(m, ky, yi, N, ldb, v->R.as<float>(), v->part.as<double>(), s, cols));
     HIP_TRY(hd::launch_init_cols(ldb, v->part.as<double>(), 1, v->st, cols, v->maxit.as<int32_t>(), m, s));
     if (v->rk > 0) {
@@ -390,8 +407,11 @@ int hd_serve_step(hd_server *v, int32_t iters) {
                                             c->tv(HD_TUNE_UC_NT, w), w));
         HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->nrb, v->o.tol, v->st, g, v->st.nact_part, s));
         HIP_TRY(hd::launch_update_xp_pt(N, ldb, X, P, R, v->st.a, v->st.beta, v->st.active, c->ldut, PTh, PTl, g, s,
-                                        nullptr, w));
+                                        nullptr, w, v->st.iters));
     }
+    // every column below w went through the x/p update: a stopped one is clear
+    if (v->fused && iters > 0)
+        for (int t = 0; t < w; ++t) v->dirty[(size_t)t] = 0;
     for (int it = 0; it < iters && !v->fused; ++it) {
         const float *Zs = P;
         if (rk > 0) {
@@ -454,7 +474,7 @@ int hd_serve_poll(hd_server *v, int32_t max_out, int64_t *tickets, int32_t *ids,
     const int ldc = pow2_at_least(m);
     HIP_TRY(hipMemcpyAsync(v->cols.p, done.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hd::launch_gather_cols(N, ldb, v->X.as<float>(), v->Cs.as<float>(), rk, v->cols.as<int32_t>(), m,
-                                   ldc, v->xc.as<float>(), v->csc.as<float>(), s));
+                                   ldc, v->xc.as<float>(), v->csc.as<float>(), s, v->st.iters));
     float *xq = v->xq.as<float>();
     if (rk > 0 && c->u_mfma()) {
         uint16_t *hi = v->cst.as<uint16_t>(), *lo = hi + (size_t)rk * ldc;

@@ -514,12 +514,20 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
 // updates the float4 at column 4(t%16) of rows t/16 + 16j, then the 64 x 64
 // tile of new P is transposed through LDS and thread t writes column t/4,
 // items 16(t%4) .. +15 of PT as two 16-byte lane pieces.
+//
+// SERVE (a server's running solve, iters = the columns' iteration counts):
+// a column's first update (iters 1) overwrites X with a p instead of adding
+// to the previous occupant's x, and a stopped column's P is set to zero and
+// its nonzero R entries are written back as zero, so a column freed by a
+// finished request is clean for its next admission without a pass of its
+// own (the rows of X, P and PT are written here anyway, those of R read).
+template <bool SERVE>
 __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, float *X, float *P,
-                                                         const float *R, const double *a,
+                                                         float *R, const double *a,
                                                          const double *beta, const int32_t *active,
                                                          int64_t ldpt, unsigned short *PTh,
                                                          unsigned short *PTl, IterGuard ig,
-                                                         const uint32_t *rowmask) {
+                                                         const uint32_t *rowmask, const int32_t *iters) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     __shared__ float T[64][65];
     const int64_t i0 = (int64_t)blockIdx.x * 64;
@@ -527,11 +535,13 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
     const int c4 = 4 * (threadIdx.x % 16);
     double av[4], bv[4];
     int kv[4];
+    bool fresh[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         av[q] = a[b0 + c4 + q];
         bv[q] = beta[b0 + c4 + q];
         kv[q] = active[b0 + c4 + q];
+        fresh[q] = SERVE && iters[b0 + c4 + q] == 1;
     }
     // the four rows' loads first, unconditionally (a row past N reads row
     // N - 1 and stores nothing), so all twelve are in flight together; with
@@ -552,16 +562,25 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
         const int r = threadIdx.x / 16 + 16 * j;
         const int64_t i = i0 + r;
         float xs[4] = {xv[j].x, xv[j].y, xv[j].z, xv[j].w}, ps[4] = {pv[j].x, pv[j].y, pv[j].z, pv[j].w};
-        const float rs[4] = {rv[j].x, rv[j].y, rv[j].z, rv[j].w};
+        float rs[4] = {rv[j].x, rv[j].y, rv[j].z, rv[j].w};
+        bool rclear = false;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (av[q] != 0.0) xs[q] = (float)((double)xs[q] + av[q] * (double)ps[q]);
-            if (kv[q]) ps[q] = (float)((double)rs[q] + bv[q] * (double)ps[q]);
+            if (av[q] != 0.0) xs[q] = (float)((double)(fresh[q] ? 0.f : xs[q]) + av[q] * (double)ps[q]);
+            if (kv[q]) {
+                ps[q] = (float)((double)rs[q] + bv[q] * (double)ps[q]);
+            } else if (SERVE) {
+                ps[q] = 0.f;
+                rclear |= rs[q] != 0.f;
+                rs[q] = 0.f;
+            }
         }
         if (i < N) {
             const size_t o = vec_index(N, ldb, i, b0 + c4);
             *reinterpret_cast<float4 *>(X + o) = make_float4(xs[0], xs[1], xs[2], xs[3]);
             *reinterpret_cast<float4 *>(P + o) = make_float4(ps[0], ps[1], ps[2], ps[3]);
+            // an active column's r is written back as it was read
+            if (SERVE && rclear) *reinterpret_cast<float4 *>(R + o) = make_float4(rs[0], rs[1], rs[2], rs[3]);
         }
         // items past N stay zero in the transpose
 #pragma unroll
@@ -589,15 +608,21 @@ __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, flo
     }
 }
 
-hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, const float *R,
+hipError_t launch_update_xp_pt(int64_t N, int ldb, float *X, float *P, float *R,
                                const double *a, const double *beta, const int32_t *active,
                                int64_t ldpt, unsigned short *PTh, unsigned short *PTl, IterGuard g,
-                               hipStream_t s, const uint32_t *rowmask, int width) {
+                               hipStream_t s, const uint32_t *rowmask, int width, const int32_t *iters) {
     if (width == 0) width = ldb;
     if (ldpt % 64 != 0 || ldpt < N || ldb % 64 != 0 || width % 64 != 0 || width > ldb)
         return hipErrorInvalidValue;
-    k_update_xp_pt<<<dim3((unsigned)(ldpt / 64), (unsigned)(width / 64)), kBlock, 0, s>>>(
-        N, ldb, X, P, R, a, beta, active, ldpt, PTh, PTl, g, rowmask);
+    if (iters && rowmask) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(ldpt / 64), (unsigned)(width / 64));
+    if (iters)
+        k_update_xp_pt<true><<<grid, kBlock, 0, s>>>(N, ldb, X, P, R, a, beta, active, ldpt, PTh, PTl, g, rowmask,
+                                                     iters);
+    else
+        k_update_xp_pt<false><<<grid, kBlock, 0, s>>>(N, ldb, X, P, R, a, beta, active, ldpt, PTh, PTl, g, rowmask,
+                                                      nullptr);
     return hipGetLastError();
 }
 
@@ -720,32 +745,36 @@ hipError_t launch_gather_proj(int B, int ky, const int32_t *ids, const float *va
 // Each column is its own CG recurrence, so a request's arithmetic is the same
 // whatever else shares the batch.
 
-// Thread -> (row i, slot t) with t fastest, so the lanes of a wave cover
-// consecutive slots of a few rows: admission takes the lowest free columns,
-// so the slots are mostly runs of adjacent columns and the writes coalesce
-// (one thread per row looping over the columns touched 64 rows, 64 lines,
-// per instruction).
+// A wave per row, lane -> slot t (t fastest, 64 slots per instruction):
+// admission takes the lowest free columns, so the slots are mostly runs of
+// adjacent columns and a wave's writes to a row coalesce. The slot list is
+// staged in LDS once per block (ncols <= 1024) and every index is 32-bit
+// within a row (a 64-bit divide per element had made this ALU-bound).
 __global__ __launch_bounds__(kBlock) void k_zero_cols(int64_t N, int ldb, float *X, float *R,
                                                       float *P, const int32_t *cols, int ncols) {
-    const size_t tot = (size_t)N * (size_t)ncols;
-    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < tot; k += (size_t)gridDim.x * kBlock) {
-        const size_t i = k / (size_t)ncols;
-        const size_t o = i * (size_t)ldb + (size_t)cols[k % (size_t)ncols];
-        X[o] = 0.f;
-        R[o] = 0.f;
-        P[o] = 0.f;
+    __shared__ int32_t sc[1024];
+    for (int t = threadIdx.x; t < ncols; t += kBlock) sc[t] = cols[t];
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, wr = threadIdx.x / kWave;
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + wr; i < N;
+         i += (int64_t)gridDim.x * (kBlock / kWave)) {
+        const size_t row = vec_index(N, ldb, i, 0);
+        for (int t = lane; t < ncols; t += kWave) {
+            const size_t o = row + (size_t)sc[t];
+            X[o] = 0.f;
+            R[o] = 0.f;
+            P[o] = 0.f;
+        }
     }
 }
 
-static unsigned grid_for(size_t tot) {
-    const size_t want = (tot + kBlock - 1) / kBlock;
-    return (unsigned)(want < 16384 ? (want > 0 ? want : 1) : 16384);
-}
 
 hipError_t launch_zero_cols(int64_t N, int ldb, float *X, float *R, float *P, const int32_t *cols,
                             int ncols, hipStream_t s) {
     if (ncols == 0 || N == 0) return hipSuccess;
-    k_zero_cols<<<grid_for((size_t)N * (size_t)ncols), kBlock, 0, s>>>(N, ldb, X, R, P, cols, ncols);
+    if (ncols > 1024 || ncols > ldb) return hipErrorInvalidValue;
+    const int64_t want = (N + kBlock / kWave - 1) / (kBlock / kWave);
+    k_zero_cols<<<(unsigned)(want < 16384 ? want : 16384), kBlock, 0, s>>>(N, ldb, X, R, P, cols, ncols);
     return hipGetLastError();
 }
 
@@ -807,33 +836,44 @@ hipError_t launch_cancel_cols(CgState st, const int32_t *cols, int ncols, hipStr
 }
 
 // Xc (N x ldc) and Csc (rk x ldc): slot t of each row takes column cols[t]
-// (zero for t >= ncols). Thread -> (row, slot) with the slot fastest, so a
-// wave reads runs of a few rows of X and writes whole rows of Xc.
+// (zero for t >= ncols). A wave per row (the N rows of X, then the rk rows
+// of Cs), lane -> slot (64 per instruction): it reads runs of one row of X
+// and writes whole rows of Xc; the slot list is staged in LDS.
+// iters (nullptr = none): a column with no iteration done takes x = 0 (its
+// X may still hold a previous occupant's values, overwritten at its first
+// update).
 __global__ __launch_bounds__(kBlock) void k_gather_cols(int64_t N, int ldb, const float *X,
                                                         const float *Cs, int rk,
                                                         const int32_t *cols, int ncols, int ldc,
-                                                        float *Xc, float *Csc) {
-    const size_t totx = (size_t)N * (size_t)ldc, tot = totx + (size_t)rk * (size_t)ldc;
-    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < tot; k += (size_t)gridDim.x * kBlock) {
-        const bool x = k < totx;
-        const size_t kk = x ? k : k - totx;
-        const size_t i = kk / (size_t)ldc;
-        const int t = (int)(kk % (size_t)ldc);
-        const float *src = x ? X : Cs;
-        const float v = t < ncols ? src[i * (size_t)ldb + (size_t)cols[t]] : 0.f;
-        if (x)
-            Xc[kk] = v;
-        else
-            Csc[kk] = v;
+                                                        float *Xc, float *Csc, const int32_t *iters) {
+    __shared__ int32_t sc[1024];
+    __shared__ bool xz[1024];
+    for (int t = threadIdx.x; t < ncols; t += kBlock) {
+        sc[t] = cols[t];
+        xz[t] = iters && iters[cols[t]] == 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, wr = threadIdx.x / kWave;
+    const int64_t rows = N + (rk > 0 ? rk : 0);
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + wr; i < rows;
+         i += (int64_t)gridDim.x * (kBlock / kWave)) {
+        const bool x = i < N;
+        const int64_t r = x ? i : i - N;
+        const float *src = (x ? X : Cs) + (size_t)r * (size_t)ldb;
+        float *dst = (x ? Xc : Csc) + (size_t)r * (size_t)ldc;
+        for (int t = lane; t < ldc; t += kWave) dst[t] = t < ncols && !(x && xz[t]) ? src[sc[t]] : 0.f;
     }
 }
 
 hipError_t launch_gather_cols(int64_t N, int ldb, const float *X, const float *Cs, int rk,
                               const int32_t *cols, int ncols, int ldc, float *Xc, float *Csc,
-                              hipStream_t s) {
-    const size_t tot = ((size_t)N + (size_t)(rk > 0 ? rk : 0)) * (size_t)ldc;
-    if (tot == 0) return hipSuccess;
-    k_gather_cols<<<grid_for(tot), kBlock, 0, s>>>(N, ldb, X, Cs, rk, cols, ncols, ldc, Xc, Csc);
+                              hipStream_t s, const int32_t *iters) {
+    const int64_t rows = N + (rk > 0 ? rk : 0);
+    if (rows == 0 || ldc == 0) return hipSuccess;
+    if (ncols > ldc || ldc > 1024) return hipErrorInvalidValue;
+    const int64_t want = (rows + kBlock / kWave - 1) / (kBlock / kWave);
+    k_gather_cols<<<(unsigned)(want < 16384 ? want : 16384), kBlock, 0, s>>>(N, ldb, X, Cs, rk, cols, ncols, ldc,
+                                                                            Xc, Csc, iters);
     return hipGetLastError();
 }
 

@@ -286,14 +286,17 @@ hipError_t launch_split_pt(int64_t N, int ldb, const float *P, int64_t ldpt, uns
     return hipGetLastError();
 }
 
-// Admitted columns: zero their lane pieces (one 8-item piece of one column
-// per thread, hi and lo), then write the split of P at their y rows.
-__global__ __launch_bounds__(kBlock) void k_pt_zero_cols(const int32_t *__restrict__ cols, int64_t ldpt,
-                                                         unsigned short *__restrict__ PTh,
+// Admitted columns: zero their lane pieces, then write the split of P at
+// their y rows. Zeroing: thread -> (slot t = 32 y + tid % 32, piece
+// 8 x + tid / 32) with the slot fastest, so adjacent admitted columns (the
+// usual case) write adjacent 16-byte pieces of one fragment tile.
+__global__ __launch_bounds__(kBlock) void k_pt_zero_cols(const int32_t *__restrict__ cols, int ncols,
+                                                         int64_t ldpt, unsigned short *__restrict__ PTh,
                                                          unsigned short *__restrict__ PTl) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= ldpt / 8) return;
-    const size_t o = frag_offset(cols[blockIdx.y], 8 * p, ldpt / 32);
+    const int t = (int)blockIdx.y * 32 + (int)threadIdx.x % 32;
+    const int64_t p = (int64_t)blockIdx.x * (kBlock / 32) + threadIdx.x / 32;
+    if (t >= ncols || p >= ldpt / 8) return;
+    const size_t o = frag_offset(cols[t], 8 * p, ldpt / 32);
     *reinterpret_cast<uint4 *>(PTh + o) = make_uint4(0u, 0u, 0u, 0u);
     *reinterpret_cast<uint4 *>(PTl + o) = make_uint4(0u, 0u, 0u, 0u);
 }
@@ -316,14 +319,18 @@ __global__ __launch_bounds__(kBlock) void k_pt_scatter_y(int m, int ky, const in
     PTl[o] = __builtin_bit_cast(unsigned short, (__bf16)(v - (float)hb));
 }
 
-hipError_t launch_pt_admit(int m, int ky, const int32_t *ids, const int32_t *cols, int64_t N, int ldb,
-                           const float *P, int64_t ldpt, unsigned short *PTh, unsigned short *PTl, hipStream_t s) {
+hipError_t launch_pt_admit(int m, int ky, const int32_t *ids, const int32_t *cols, const int32_t *zcols, int nz,
+                           int64_t N, int ldb, const float *P, int64_t ldpt, unsigned short *PTh,
+                           unsigned short *PTl, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    if (ldpt % 64 != 0 || ldpt < N || ky < 1) return hipErrorInvalidValue;
-    k_pt_zero_cols<<<dim3((unsigned)((ldpt / 8 + kBlock - 1) / kBlock), (unsigned)m), kBlock, 0, s>>>(cols, ldpt, PTh,
-                                                                                                    PTl);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (ldpt % 64 != 0 || ldpt < N || ky < 1 || nz < 0) return hipErrorInvalidValue;
+    if (nz > 0) {
+        const int64_t pieces = ldpt / 8, per = kBlock / 32;
+        k_pt_zero_cols<<<dim3((unsigned)((pieces + per - 1) / per), (unsigned)((nz + 31) / 32)), kBlock, 0, s>>>(
+            zcols, nz, ldpt, PTh, PTl);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int tot = m * ky;
     k_pt_scatter_y<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(m, ky, ids, cols, N, ldb, P, ldpt, PTh,
                                                                            PTl);
