@@ -355,3 +355,93 @@ def test_bad_y_id_admits_nothing(fx, ctx):
     drain(srv, 4, res)
     assert set(res) == {int(t) for t in tk}
     srv.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_bf16x2(fx, torch_dev):
+    from paper_1807_08692_amd import hd
+    c = hd.Context(0)
+    c.load_graph(fx.n, fx.rowptr, fx.col, fx.s)
+    c.load_eigs(fx.U, fx.lam, dtype="bf16x2")
+    yield c
+    c.close()
+
+
+def alone_results(ctx, ids, vals, caps, kw):
+    from paper_1807_08692_amd import hd
+    out = []
+    for q in range(len(ids)):
+        srv = hd.Server(ctx, 8, **kw)
+        t = srv.submit(ids[q:q + 1], vals[q:q + 1], max_iter=[int(caps[q])])
+        res = {}
+        drain(srv, 1, res)
+        srv.close()
+        out.append(res[int(t[0])])
+    return out
+
+
+def same(a, b):
+    return (np.array_equal(a["ids"], b["ids"]) and np.array_equal(a["scores"], b["scores"])
+            and a["iters"] == b["iters"] and a["relres"] == b["relres"] and a["status"] == b["status"])
+
+
+def test_bf16_column_reuse_alone_equals_mix(fx, ctx_bf16x2):
+    """Two-term bf16 U1 (the server whose x/p update clears the columns of
+    finished requests): 24 requests with caps 2..9 through 8 columns, so
+    every column is reused several times, each admitted right after a poll
+    freed it; one request has y = 0 (zero right-hand side, stopped at
+    admission). Every result equals the request's result alone, bit for bit."""
+    from paper_1807_08692_amd import hd
+    ids, vals = ys(fx, np.arange(24))
+    vals[5] = 0.0
+    caps = 2 + (np.arange(24) * 7) % 8
+    kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+    ref = alone_results(ctx_bf16x2, ids, vals, caps, kw)
+    srv = hd.Server(ctx_bf16x2, 8, **kw)
+    res, tick, nxt = {}, {}, 0
+    for _ in range(400):
+        if nxt < 24 and srv.in_use < 8:
+            k = min(8 - srv.in_use, 24 - nxt, 3)
+            tk = srv.submit(ids[nxt:nxt + k], vals[nxt:nxt + k], max_iter=[int(c) for c in caps[nxt:nxt + k]])
+            for j, t in enumerate(tk):
+                tick[int(t)] = nxt + j
+            nxt += len(tk)
+        srv.step(1)
+        r = srv.poll()
+        for k, t in enumerate(r["tickets"]):
+            res[int(t)] = {key: r[key][k] for key in ("ids", "scores", "iters", "relres", "status")}
+        if len(res) == 24:
+            break
+    srv.close()
+    assert len(res) == 24
+    for t, q in tick.items():
+        assert same(res[t], ref[q]), q
+    assert res[[t for t, q in tick.items() if q == 5][0]]["status"] == 2  # zero right-hand side
+
+
+def test_bf16_cancel_then_readmit(fx, ctx_bf16x2):
+    """A request admitted into the column of one cancelled a moment before
+    (no step in between: the column still holds the cancelled request's
+    vectors) gets its result alone, bit for bit, and so do the others."""
+    from paper_1807_08692_amd import hd
+    ids, vals = ys(fx, np.arange(12))
+    caps = [20] * 12
+    kw = dict(alpha=0.99, max_iter=20, tol=1e-6, rank_r=50, k_y=fx.cfg.k_y, top_k=50)
+    ref = alone_results(ctx_bf16x2, ids, vals, caps, kw)
+    srv = hd.Server(ctx_bf16x2, 9, **kw)
+    assert srv.slots == 9
+    tk = srv.submit(ids[:8], vals[:8])
+    srv.step(3)
+    assert srv.cancel([int(tk[2]), int(tk[5])]) == 2
+    late = srv.submit(ids[8:10], vals[8:10])  # into the two cancelled columns
+    assert len(late) == 2
+    srv.step(2)
+    assert srv.cancel([int(tk[0])]) == 1
+    late2 = srv.submit(ids[10:12], vals[10:12])  # one into the cancelled column, one into the unused ninth
+    assert len(late2) == 2
+    res = {}
+    drain(srv, 9, res)
+    srv.close()
+    for q, t in [(1, tk[1]), (3, tk[3]), (4, tk[4]), (6, tk[6]), (7, tk[7]),
+                 (8, late[0]), (9, late[1]), (10, late2[0]), (11, late2[1])]:
+        assert same(res[int(t)], ref[q]), q
