@@ -1032,6 +1032,13 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     // active one into empty kernels.
     const int ntile = ldb / 64;
     int32_t *nact_dev[2] = {st.nact_part, st.nact_part + 64};
+    // the last iteration's x update (x += a p; nothing reads the new P) is
+    // left to the combine when its kernel can apply it (the two-term, bf16
+    // and fp8 U1 forms, and r = 0) and x is read at all; it is not for one
+    // iteration, whose update runs with the row mask of y
+    const bool xfold = !flt && o->max_iter >= 2 &&
+                       (rk == 0 || (ubf && !sparse && hd::combine_nt(ldb, c->tv(HD_TUNE_UC_NT, ldb)) != 4)) &&
+                       (x_out || (o->top_k > 0 && (rank_ids || rank_scores)));
     auto enqueue_iter = [&](int it) -> int {
         c->timing.tag = it;
         const hd::IterGuard g{nact_dev[(it - 1) & 1], ntile};
@@ -1067,10 +1074,11 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                                                           c->tv(HD_TUNE_UC_NT, ldb), 0, rm));
             LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, nores ? nullptr : c->part.as<double>(), nrb, o->tol, st, g,
                                                   nact_dev[it & 1], s, pre));
-            if (it == o->max_iter)  // nothing reads the new P or its split transpose
-                LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, true,
-                                                         rm));
-            else
+            if (it == o->max_iter) {  // nothing reads the new P or its split transpose
+                if (!xfold)
+                    LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0,
+                                                             true, rm));
+            } else
                 LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut,
                                                             PTh, PTl, gu, s, rm));
             if (!graph) {
@@ -1120,7 +1128,9 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         LAUNCH(K_SCALAR, hd::launch_cg_step_b(ldb, nores ? nullptr : c->part.as<double>(), rp.nblk, o->tol, st, g,
                                               nact_dev[it & 1], s, pre));
         if (it == o->max_iter) {  // the last iteration: nothing reads the new P
-            LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, true, rm));
+            if (!xfold)
+                LAUNCH(K_UPDATE_XP, hd::launch_update_xp(n, ldb, X, P, R, st.a, st.beta, st.active, gu, s, 0, true,
+                                                         rm));
         } else if (ubf && rk > 0) {
             uint16_t *PTh = c->PT.as<uint16_t>(), *PTl = PTh + (size_t)ldb * c->ldut;
             LAUNCH(K_UPDATE_XP, hd::launch_update_xp_pt(n, ldb, X, P, R, st.a, st.beta, st.active, c->ldut,
@@ -1170,6 +1180,9 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
     }
     const bool rank = o->top_k > 0 && (rank_ids || rank_scores);
     const int K = o->top_k;
+    // the last iteration's x update, when it was left to the combine
+    const hd::XFold xf{st.a, P, hd::IterGuard{nact_dev[(o->max_iter - 1) & 1], ntile}};
+    const hd::XFold *fold = xfold ? &xf : nullptr;
     if (rank && !x_out && (rk == 0 || (ubf && !sparse)) && c->onepass_rank(rk)) {
         // one-pass ranking: thresholds from the sampled items' x, then the
         // combine offers every x to the lists without writing x; xq is
@@ -1183,23 +1196,24 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
         const hd::TopkLists tl = hd::topk_lists(c->topk.p, B, n);
         const int32_t *gate = hd::topk_fallback_gate(c->topk.p, B, n);
         const int nt = c->tv(HD_TUNE_UC_NT, ldb);
-        LAUNCH(K_TOPK_RANK, hd::launch_sample_rows(m, st, ldb, temporal, xs, s));
+        LAUNCH(K_TOPK_RANK, hd::launch_sample_rows(m, st, ldb, temporal, xs, s, fold));
         if (rk > 0) {
             LAUNCH(K_TOPK_RANK, hd::launch_combine_bf16(m, B, c->u_item_sample(), c->rp, rk, CsT_hi, CsT_lo, ldb, xs,
                                                           ss, lss, s, nt));
             LAUNCH(K_TOPK_RANK, hd::launch_topk_prepare(B, n, ss, lss, 1, K, c->topk.p, s));
             LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal,
-                                                        nullptr, n, s, nt, &tl));
+                                                        nullptr, n, s, nt, &tl, nullptr, fold));
         } else {
             LAUNCH(K_TOPK_RANK, hd::launch_topk_prepare(B, n, xs, 1, ldb, K, c->topk.p, s));
-            LAUNCH(K_COMBINE, hd::launch_topk_emit_nm(n, B, ldb, temporal, tl, s));
+            LAUNCH(K_COMBINE, hd::launch_topk_emit_nm(n, B, ldb, temporal, tl, s, fold));
         }
         LAUNCH(K_TOPK_RANK, hd::launch_topk_select_lists(B, n, K, c->topk.p, rank_ids, rank_scores, 0, s));
         if (rk > 0) {
             LAUNCH(K_TOPK_RANK, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal, xq,
-                                                          n, s, nt, nullptr, gate));
+                                                          n, s, nt, nullptr, gate, fold));
         } else {
-            LAUNCH(K_TOPK_RANK, hd::launch_combine(n, B, nullptr, c->rp, 0, nullptr, ldb, temporal, xq, n, s, gate));
+            LAUNCH(K_TOPK_RANK, hd::launch_combine(n, B, nullptr, c->rp, 0, nullptr, ldb, temporal, xq, n, s, gate,
+                                                   fold));
         }
         LAUNCH(K_TOPK_RANK, hd::launch_topk_fallback(B, n, xq, n, K, c->topk.p, rank_ids, rank_scores, 0, s));
     } else {
@@ -1208,9 +1222,11 @@ int hdi::queue_query(hd_ctx *c, int32_t B, const float *q_desc, const int32_t *y
                 LAUNCH(K_COMBINE, hd::launch_sp_combine(n, B, Usr, Usc, Usv, c->Cs.as<float>(), ldb, temporal, xq, n, s));
             } else if (ubf && rk > 0) {
                 LAUNCH(K_COMBINE, hd::launch_combine_bf16(n, B, c->u_item(), c->rp, rk, CsT_hi, CsT_lo, ldb, temporal,
-                                                            xq, n, s, c->tv(HD_TUNE_UC_NT, ldb)));
+                                                            xq, n, s, c->tv(HD_TUNE_UC_NT, ldb), nullptr, nullptr,
+                                                            fold));
             } else {
-                LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, temporal, xq, n, s));
+                LAUNCH(K_COMBINE, hd::launch_combine(n, B, U, c->rp, rk, c->Cs.as<float>(), ldb, temporal, xq, n, s,
+                                                     nullptr, rk == 0 ? fold : nullptr));
             }
         }
         if (rank) {

@@ -75,6 +75,11 @@ __device__ __forceinline__ bool all_stopped(const int32_t *nact, int ntile) {
     return s == 0;
 }
 
+// x + a p as the x-only update writes it (a = 0: x unchanged)
+__device__ __forceinline__ float fold_x(float x, float p, double a) {
+    return a != 0.0 ? (float)((double)x + a * (double)p) : x;
+}
+
 // Row i is in a row mask (bit i of word i / 32; nullptr: every row is).
 __device__ __forceinline__ bool row_live(const uint32_t *m, int64_t i) {
     return !m || ((m[i >> 5] >> (i & 31)) & 1u);

@@ -72,6 +72,17 @@ struct IterGuard {
     int ntile;
 };
 
+// The last CG iteration's x update (x += a p, the update launch_update_xp
+// makes with x_only) carried out by the kernel that reads x next (the
+// combine) instead of a pass of its own: element (i, b) of x is taken as
+// x + a[b] p(i, b) where a[b] != 0, unless the guard shows every column
+// stopped before that iteration. a == nullptr: no fold.
+struct XFold {
+    const double *a;
+    const float *P;  // the search directions, laid out as x (node-major)
+    IterGuard g;
+};
+
 // Row partition shared by every kernel that writes per-block partial sums:
 // block g covers rows [g*rb, min(N, (g+1)*rb)).
 struct RowPart {
@@ -229,7 +240,7 @@ hipError_t launch_u_c(int64_t N, const float *U, int rp, int rk, const float *Cl
 // gate (nullptr = none): every block returns at once while *gate == 0
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
                           int ldb, const float *X, float *x, int64_t ldx, hipStream_t s,
-                          const int32_t *gate = nullptr);
+                          const int32_t *gate = nullptr, const XFold *fold = nullptr);  // fold: rk = 0 only
 
 // ---- bfloat16 storage form of the eigenvector and descriptor products
 //      (k_ugemm_bf16.hip); bf16 values are passed as their 16-bit patterns.
@@ -274,12 +285,16 @@ hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const 
                                    IterGuard g, hipStream_t s, int nt = 0, int width = 0,
                                    const uint32_t *rowmask = nullptr);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
+// n-tiles per wave launch_combine_bf16 uses for width ldb and requested
+// value req (0 = default); the fold is not available with 4
+int combine_nt(int ldb, int req);
 // tl (one-pass top-K): candidates to the lists, x not written; gate as in
 // launch_combine
 hipError_t launch_combine_bf16(int64_t N, int B, UOperand U, int rp, int rk,
                                const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                const float *X, float *x, int64_t ldx, hipStream_t s, int nt = 0,
-                               const TopkLists *tl = nullptr, const int32_t *gate = nullptr);
+                               const TopkLists *tl = nullptr, const int32_t *gate = nullptr,
+                               const XFold *fold = nullptr);
 // Tile parameters: a requested value (0 = default) is valid for width ldb
 // when it is one of 1, 2, 4 and divides the width in 64-column units.
 bool tile_param_ok(int v, int ldb);
@@ -333,12 +348,15 @@ hipError_t launch_topk_select_lists(int B, int64_t n, int K, void *scratch, int3
 hipError_t launch_topk_fallback(int B, int64_t n, const float *x, int64_t ldx, int K, void *scratch,
                                 int32_t *ids, float *scores, int transform, hipStream_t s);
 // candidates of the scores x[b][i] = X[i][b] (node-major X, b < B <= ldb)
-hipError_t launch_topk_emit_nm(int64_t n, int B, int ldb, const float *X, TopkLists tl, hipStream_t s);
+hipError_t launch_topk_emit_nm(int64_t n, int B, int ldb, const float *X, TopkLists tl, hipStream_t s,
+                               const XFold *fold = nullptr);
 // the sample's rows: fragment-order matrices (ld a multiple of 32, elem_bytes
 // 2 or 1; dst is m rounded up to 16 rows, zero past m) and row-major rows
 hipError_t launch_sample_frag(int64_t m, int64_t stride, int64_t ld, const void *src, void *dst, int elem_bytes,
                               hipStream_t s);
-hipError_t launch_sample_rows(int64_t m, int64_t stride, int ld, const float *src, float *dst, hipStream_t s);
+// fold (ld = the solver width): the sampled rows of x with the fold applied
+hipError_t launch_sample_rows(int64_t m, int64_t stride, int ld, const float *src, float *dst, hipStream_t s,
+                              const XFold *fold = nullptr);
 
 // ---- SHybrid: sparsified U1 (k_sparse_u.hip). U~ by item (CSR rptr / rcol /
 //      rval, N rows) and by component (CSC cptr / crow / cval, rk columns) ----

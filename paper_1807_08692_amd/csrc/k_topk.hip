@@ -514,8 +514,9 @@ hipError_t launch_topk_fallback(int B, int64_t n, const float *x, int64_t ldx, i
 // a block covers 256 items (64 per wave, so one list chunk) and 64 query
 // columns, lane = column; every wave loads its 64 items' column runs before
 // testing them.
+template <bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_topk_emit_nm(int64_t n, int B, int ldb, const float *__restrict__ X,
-                                                         TopkLists tl) {
+                                                         TopkLists tl, XFold fold) {
     __shared__ EmitStage es;
     __shared__ uint32_t thr[64];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -526,12 +527,19 @@ __global__ __launch_bounds__(kBlock) void k_topk_emit_nm(int64_t n, int B, int l
     __syncthreads();
     const int b = b0 + lane;
     const int64_t ib = i0 + 64 * w;
-    float v[16];
+    const double fa = FOLD && b < B && !all_stopped(fold.g.nact, fold.g.ntile) ? fold.a[b] : 0.0;
+    float v[16], pv[16];
     for (int u = 0; u < 64; u += 16) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int64_t i = ib + u + q;
-            v[q] = i < n && b < B ? X[vec_index(n, ldb, i, b)] : 0.f;
+            const size_t o = vec_index(n, ldb, i < n ? i : n - 1, b < B ? b : 0);
+            v[q] = X[o];
+            if (FOLD) pv[q] = fold.P[o];
+        }
+        if (FOLD) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = fold_x(v[q], pv[q], fa);
         }
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -543,10 +551,14 @@ __global__ __launch_bounds__(kBlock) void k_topk_emit_nm(int64_t n, int B, int l
     emit_flush(es, tl, (int)(i0 / kTopkChunk), b0, b0 + 64 < B ? b0 + 64 : B);
 }
 
-hipError_t launch_topk_emit_nm(int64_t n, int B, int ldb, const float *X, TopkLists tl, hipStream_t s) {
+hipError_t launch_topk_emit_nm(int64_t n, int B, int ldb, const float *X, TopkLists tl, hipStream_t s,
+                               const XFold *fold) {
     if (n < 1 || B < 1 || B > ldb) return hipErrorInvalidValue;
     const dim3 g((unsigned)ceil_div(n, 256), (unsigned)ceil_div(B, 64));
-    k_topk_emit_nm<<<g, kBlock, 0, s>>>(n, B, ldb, X, tl);
+    if (fold)
+        k_topk_emit_nm<true><<<g, kBlock, 0, s>>>(n, B, ldb, X, tl, *fold);
+    else
+        k_topk_emit_nm<false><<<g, kBlock, 0, s>>>(n, B, ldb, X, tl, XFold{nullptr, nullptr, IterGuard{nullptr, 0}});
     return hipGetLastError();
 }
 
@@ -584,18 +596,24 @@ hipError_t launch_sample_frag(int64_t m, int64_t stride, int64_t ld, const void 
     return hipGetLastError();
 }
 
-// Row-major rows: dst[t * ld + c] = src[t * stride * ld + c], t < m, c < ld.
+// Row-major rows: dst[t * ld + c] = src[t * stride * ld + c], t < m, c < ld
+// (with the fold: x + a p as the combine will read it).
 __global__ __launch_bounds__(kBlock) void k_sample_rows(int64_t m, int64_t stride, int ld,
-                                                        const float *__restrict__ src, float *__restrict__ dst) {
+                                                        const float *__restrict__ src, float *__restrict__ dst,
+                                                        XFold fold) {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (idx >= m * ld) return;
     const int64_t t = idx / ld, c = idx % ld;
-    dst[idx] = src[(size_t)t * (size_t)stride * (size_t)ld + (size_t)c];
+    const size_t o = (size_t)t * (size_t)stride * (size_t)ld + (size_t)c;
+    const bool fo = fold.a && !all_stopped(fold.g.nact, fold.g.ntile);
+    dst[idx] = fo ? fold_x(src[o], fold.P[o], fold.a[c]) : src[o];
 }
 
-hipError_t launch_sample_rows(int64_t m, int64_t stride, int ld, const float *src, float *dst, hipStream_t s) {
+hipError_t launch_sample_rows(int64_t m, int64_t stride, int ld, const float *src, float *dst, hipStream_t s,
+                              const XFold *fold) {
     if (m < 1 || stride < 1 || ld < 1) return hipErrorInvalidValue;
-    k_sample_rows<<<(unsigned)ceil_div(m * ld, kBlock), kBlock, 0, s>>>(m, stride, ld, src, dst);
+    k_sample_rows<<<(unsigned)ceil_div(m * ld, kBlock), kBlock, 0, s>>>(
+        m, stride, ld, src, dst, fold ? *fold : XFold{nullptr, nullptr, IterGuard{nullptr, 0}});
     return hipGetLastError();
 }
 

@@ -356,19 +356,29 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t N, int B, const floa
 // x[b][i] = X[i][b] (the combine with no eigenvector term): a block
 // transposes a 64-item x 64-query tile through LDS, reading 256-byte runs of
 // X's rows and writing 256-byte runs of x's rows.
+// FOLD: x + a p (XFold), loads of X and P issued together.
+template <bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_xt(int64_t N, int B, int ldb, const float *__restrict__ X,
                                                float *__restrict__ x, int64_t ldx,
-                                               const int32_t *__restrict__ gate) {
+                                               const int32_t *__restrict__ gate, XFold fold) {
     if (gate && *gate == 0) return;
     __shared__ float T[64][65];
     const int64_t i0 = (int64_t)blockIdx.x * 64;
     const int b0 = blockIdx.y * 64;
     const int c = threadIdx.x % 64, r0 = threadIdx.x / 64;
-    float v[16];
+    const double fa = FOLD && !all_stopped(fold.g.nact, fold.g.ntile) ? fold.a[b0 + c] : 0.0;
+    float v[16], pv[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t i = i0 + r0 + 4 * r;
-        v[r] = i < N && b0 + c < B ? X[vec_index(N, ldb, i, b0 + c)] : 0.f;
+        const size_t o = vec_index(N, ldb, i < N ? i : N - 1, b0 + c);
+        v[r] = X[o];
+        if (FOLD) pv[r] = fold.P[o];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        if (FOLD) v[r] = fold_x(v[r], pv[r], fa);
+        if (i0 + r0 + 4 * r >= N || b0 + c >= B) v[r] = 0.f;
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) T[r0 + 4 * r][c] = v[r];
@@ -383,12 +393,16 @@ __global__ __launch_bounds__(kBlock) void k_xt(int64_t N, int B, int ldb, const 
 
 hipError_t launch_combine(int64_t N, int B, const float *U, int rp, int rk, const float *Cs,
                           int ldb, const float *X, float *x, int64_t ldx, hipStream_t s,
-                          const int32_t *gate) {
+                          const int32_t *gate, const XFold *fold) {
     if (rk == 0) {
         const dim3 g((unsigned)((N + 63) / 64), (unsigned)((B + 63) / 64));
-        k_xt<<<g, kBlock, 0, s>>>(N, B, ldb, X, x, ldx, gate);
+        if (fold)
+            k_xt<true><<<g, kBlock, 0, s>>>(N, B, ldb, X, x, ldx, gate, *fold);
+        else
+            k_xt<false><<<g, kBlock, 0, s>>>(N, B, ldb, X, x, ldx, gate, XFold{nullptr, nullptr, IterGuard{nullptr, 0}});
         return hipGetLastError();
     }
+    if (fold) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)((N + 127) / 128) * (unsigned)((B + 63) / 64);
     k_combine<<<nblk, kBlock, 0, s>>>(N, B, U, rp, rk, Cs, ldb, X, x, ldx, gate);
     return hipGetLastError();

@@ -607,15 +607,17 @@ hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const 
 // out as one 64-byte run. EMIT (one-pass top-K): each x is offered to its
 // query's candidate lists instead (a block's RB items lie in one list
 // chunk) and x is not written. gate: the launch returns while *gate == 0.
-template <int AK, int NT, bool EMIT>
+template <int AK, int NT, bool EMIT, bool FOLD>
 __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, const void *__restrict__ U,
                                                        const void *__restrict__ Ul, int rp,
                                                        int rk, const unsigned short *__restrict__ CT_hi,
                                                        const unsigned short *__restrict__ CT_lo, int ldc,
                                                        const float *__restrict__ X, float *__restrict__ x,
                                                        int64_t ldx, TopkLists tl,
-                                                       const int32_t *__restrict__ gate) {
+                                                       const int32_t *__restrict__ gate, XFold fold) {
     if (!EMIT && gate && *gate == 0) return;
+    // FOLD: the guard decides whether the last update applies (a = 0: not)
+    const bool fo = FOLD && !all_stopped(fold.g.nact, fold.g.ntile);
     __shared__ float T[4][64][17];
     constexpr int MT = tn_mt(NT), RB = tn_rows(NT);
     const unsigned L = xcd_tile(), ncg = (unsigned)ldc / (64 * NT);
@@ -634,22 +636,43 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
     tn_block<AK, NT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
     // per m-tile (16 items) and group of four n-tiles (64 queries); the
-    // m-tile's loads of X are all issued first (branch-free: rows past N
-    // read row N - 1), not one group at a time between the barriers
+    // m-tile's loads of X (and with FOLD of P) are all issued first
+    // (branch-free: rows past N read row N - 1), not one group at a time
+    // between the barriers
+    // groups of n-tile groups whose P loads are in flight together (with
+    // four n-tile groups one at a time, to stay within the registers)
+    constexpr int GB = FOLD && NT == 4 ? 1 : NT;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int64_t ib = i0 + 16 * MT * w + 16 * mt;
         float xv[NT][4][4];
 #pragma unroll
-        for (int ng = 0; ng < NT; ++ng)
+        for (int n0 = 0; n0 < NT; n0 += GB) {
+            float pv[GB][4][4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t i = ib + 4 * g + v;
-                const int64_t ic = i < N ? i : N - 1;
+            for (int ng = n0; ng < n0 + GB; ++ng)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    xv[ng][v][q] = X[vec_index(N, ldc, ic, (int)(nb0 + 64 * ng + 16 * q + c16))];
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t i = ib + 4 * g + v;
+                    const int64_t ic = i < N ? i : N - 1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const size_t o = vec_index(N, ldc, ic, (int)(nb0 + 64 * ng + 16 * q + c16));
+                        xv[ng][v][q] = X[o];
+                        if (FOLD) pv[ng - n0][v][q] = fold.P[o];
+                    }
+                }
+            if (FOLD) {
+#pragma unroll
+                for (int ng = n0; ng < n0 + GB; ++ng)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double a = fo ? fold.a[nb0 + 64 * ng + 16 * q + c16] : 0.0;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) xv[ng][v][q] = fold_x(xv[ng][v][q], pv[ng - n0][v][q], a);
+                    }
             }
+        }
 #pragma unroll
         for (int ng = 0; ng < NT; ++ng) {
             __syncthreads();
@@ -680,35 +703,52 @@ __global__ __launch_bounds__(kBlock, 2) void k_combine_tn(int64_t N, int B, cons
     }
 }
 
+int combine_nt(int ldb, int req) { return tn_nt(ldb, req, 2); }
+
 hipError_t launch_combine_bf16(int64_t N, int B, UOperand U, int rp, int rk, const unsigned short *CT_hi,
                                const unsigned short *CT_lo, int ldb, const float *X, float *x,
                                int64_t ldx, hipStream_t s, int ntr, const TopkLists *tl,
-                               const int32_t *gate) {
+                               const int32_t *gate, const XFold *fold) {
     if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
     if (tl && (gate || kTopkChunk % tn_rows(1) != 0 || kTopkChunk % tn_rows(4) != 0)) return hipErrorInvalidValue;
     const int nt = tn_nt(ldb, ntr, 2);
-    if (nt == 0) return hipErrorInvalidValue;
+    if (nt == 0 || (fold && nt == 4)) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)(ldb / (64 * nt)) * (unsigned)((N + tn_rows_rt(nt) - 1) / tn_rows_rt(nt));
     const TopkLists none{nullptr, nullptr, nullptr, 0};
     const TopkLists &l = tl ? *tl : none;
-#define HD_CB(AKV, NTV)                                                                                         \
-    do {                                                                                                        \
-        if (tl)                                                                                                 \
-            k_combine_tn<AKV, NTV, true><<<nblk, kBlock, 0, s>>>(N, B, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, \
-                                                                 CT_lo, ldb, X, x, ldx, l, gate);               \
-        else                                                                                                    \
-            k_combine_tn<AKV, NTV, false><<<nblk, kBlock, 0, s>>>(N, B, U.hi, U.lo ? U.lo : U.hi, rp, rk,       \
-                                                                  CT_hi, CT_lo, ldb, X, x, ldx, l, gate);       \
+    const XFold nofold{nullptr, nullptr, IterGuard{nullptr, 0}};
+    const XFold &f = fold ? *fold : nofold;
+#define HD_CB2(AKV, NTV, EM, FO)                                                                                \
+    k_combine_tn<AKV, NTV, EM, FO><<<nblk, kBlock, 0, s>>>(N, B, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, CT_lo, ldb, \
+                                                           X, x, ldx, l, gate, f)
+#define HD_CB(AKV, NTV)                                     \
+    do {                                                    \
+        if (tl) {                                           \
+            if (fold) HD_CB2(AKV, NTV, true, true);         \
+            else HD_CB2(AKV, NTV, true, false);             \
+        } else {                                            \
+            if (fold) HD_CB2(AKV, NTV, false, true);        \
+            else HD_CB2(AKV, NTV, false, false);            \
+        }                                                   \
+    } while (0)
+// four n-tiles per wave have no registers left for the fold's P (see
+// combine_nt); their callers keep the separate last update
+#define HD_CB4(AKV)                                 \
+    do {                                            \
+        if (tl) HD_CB2(AKV, 4, true, false);        \
+        else HD_CB2(AKV, 4, false, false);          \
     } while (0)
 #define HD_CB_NT(AKV) \
-    if (nt == 4) HD_CB(AKV, 4); else if (nt == 2) HD_CB(AKV, 2); else HD_CB(AKV, 1)
+    if (nt == 4) HD_CB4(AKV); else if (nt == 2) HD_CB(AKV, 2); else HD_CB(AKV, 1)
     switch (akind(U)) {
         case AK_FP8: HD_CB_NT(AK_FP8); break;
         case AK_BF16X2: HD_CB_NT(AK_BF16X2); break;
         default: HD_CB_NT(AK_BF16); break;
     }
 #undef HD_CB_NT
+#undef HD_CB4
 #undef HD_CB
+#undef HD_CB2
     return hipGetLastError();
 }
 
