@@ -278,12 +278,16 @@ hipError_t launch_u_c_bf16(int64_t N, UOperand U, int rp, int rk,
 // With Qs = (P - alpha S P) / (1 - alpha) (launch_spmm with Zs = P): the
 // residual update r -= a (Qs + alpha / (1 - alpha) U Cl) (Cl as split
 // transpose), and part[g][c] = sum over the rows of 128-row block g of the
-// new r^2 (uc_update_r_blocks(N) rows of ldb doubles)
+// new r^2 (uc_update_r_blocks(N) rows of ldb doubles). iters / maxit (a
+// server's running solve; no rowmask): a column whose cap ends it in this
+// iteration (iters + 1 >= maxit) has its new r counted in r^2 but stored as
+// zero
 int uc_update_r_blocks(int64_t N);
 hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
                                    IterGuard g, hipStream_t s, int nt = 0, int width = 0,
-                                   const uint32_t *rowmask = nullptr);
+                                   const uint32_t *rowmask = nullptr, const int32_t *iters = nullptr,
+                                   const int32_t *maxit = nullptr);
 // x[b][i] = (U Cs)[i][b] + X[i][b], Cs given as split transpose
 // n-tiles per wave launch_combine_bf16 uses for width ldb and requested
 // value req (0 = default); the fold is not available with 4

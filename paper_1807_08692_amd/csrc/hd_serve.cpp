@@ -404,7 +404,7 @@ int hd_serve_step(hd_server *v, int32_t iters) {
         HIP_TRY(hd::launch_cg_step_a(ldb, v->part.as<double>(), v->rp.nblk, v->st, g, s, v->Dg.as<double>(), rk));
         HIP_TRY(hd::launch_uc_update_r_bf16(N, c->u_item(), c->rp, rk, ClT_hi, ClT_lo, ldb, Q,
                                             v->o.alpha, R, v->st.a, v->part.as<double>(), g, s,
-                                            c->tv(HD_TUNE_UC_NT, w), w));
+                                            c->tv(HD_TUNE_UC_NT, w), w, nullptr, v->st.iters, v->st.maxit));
         HIP_TRY(hd::launch_cg_step_b(ldb, v->part.as<double>(), v->nrb, v->o.tol, v->st, g, v->st.nact_part, s));
         HIP_TRY(hd::launch_update_xp_pt(N, ldb, X, P, R, v->st.a, v->st.beta, v->st.active, c->ldut, PTh, PTl, g, s,
                                         nullptr, w, v->st.iters));

@@ -520,7 +520,9 @@ hipError_t launch_update_xp(int64_t N, int ldb, float *X, float *P, const float 
 // to the previous occupant's x, and a stopped column's P is set to zero and
 // its nonzero R entries are written back as zero, so a column freed by a
 // finished request is clean for its next admission without a pass of its
-// own (the rows of X, P and PT are written here anyway, those of R read).
+// own (the rows of X, P and PT are written here anyway, those of R read;
+// a column ended by its cap already had its last r stored as zero by the
+// residual update, so only those stopped by the tolerance write R here).
 template <bool SERVE>
 __global__ __launch_bounds__(kBlock) void k_update_xp_pt(int64_t N, int ldb, float *X, float *P,
                                                          float *R, const double *a,

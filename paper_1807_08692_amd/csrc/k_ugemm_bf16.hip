@@ -482,7 +482,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
                                                            const float *__restrict__ Qs, float cc,
                                                            float *__restrict__ R, const double *__restrict__ a,
                                                            double *__restrict__ part, int wcols, IterGuard ig,
-                                                           const uint32_t *__restrict__ rowmask) {
+                                                           const uint32_t *__restrict__ rowmask,
+                                                           const int32_t *__restrict__ iters,
+                                                           const int32_t *__restrict__ maxit) {
     if (all_stopped(ig.nact, ig.ntile)) return;
     // two m-tiles per wave (three waves per SIMD): four measured no faster
     // in the CG iteration (1.67 against 1.66 ms a launch at 1M rows, 256
@@ -494,6 +496,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
     const int64_t i0 = rb * RB;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nb0 = (int64_t)(L % ncg) * 64 * NT;
+    // iters / maxit (a server's running solve): bit n set when this lane's
+    // column of n-tile n ends by its cap in this iteration; its new residual
+    // still enters r^2 (the stopping test and relres) but is stored as zero,
+    // as nothing reads it again, so the column's r is clear for the next
+    // request admitted into it
+    uint32_t zmask = 0u;
+    if (iters) {
+#pragma unroll
+        for (int n = 0; n < 4 * NT; ++n) {
+            const int col = (int)(nb0 + 16 * n + lane % 16);
+            zmask |= (iters[col] + 1 >= maxit[col] ? 1u : 0u) << n;
+        }
+    }
     f32x4 acc[MT][4 * NT];
     tn_block<AK, NT, MT>(U, Ul, rp / 32, i0, N, CT_hi, CT_lo, rk / 32, nb0, 0, rk, acc);
     const int g = lane / 16, c16 = lane % 16;
@@ -547,7 +562,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_uc_update_r_tn(int64_t N, const v
                 const float q = qv[nn][v] + cc * acc[mt][n][v];
                 const float rn = (float)((double)rv[nn][v] - av * (double)q);
                 const float r = av != 0.0 ? rn : rv[nn][v];
-                if (i < N) R[vec_index(N, ldb, i, col)] = r;
+                if (i < N) R[vec_index(N, ldb, i, col)] = (zmask >> n) & 1u ? 0.f : r;
                 ss += i < N ? (double)r * (double)r : 0.0;
             }
             ss += __shfl_xor(ss, 16, kWave);
@@ -572,8 +587,10 @@ int uc_update_r_blocks(int64_t N) { return (int)((N + 127) / 128); }
 
 hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const unsigned short *CT_hi, const unsigned short *CT_lo, int ldb,
                                    const float *Qs, double alpha, float *R, const double *a, double *part,
-                                   IterGuard g, hipStream_t s, int ntr, int width, const uint32_t *rowmask) {
+                                   IterGuard g, hipStream_t s, int ntr, int width, const uint32_t *rowmask,
+                                   const int32_t *iters, const int32_t *maxit) {
     if (rp % 32 != 0 || rk % 32 != 0) return hipErrorInvalidValue;  // whole 32-wide K tiles
+    if (iters && (!maxit || rowmask)) return hipErrorInvalidValue;
     if (width == 0) width = ldb;
     if (width % 64 != 0 || width > ldb) return hipErrorInvalidValue;
     const int nt = tn_nt(width, ntr, 2);
@@ -584,11 +601,11 @@ hipError_t launch_uc_update_r_bf16(int64_t N, UOperand U, int rp, int rk, const 
     if (rowmask)                                                                                            \
         k_uc_update_r_tn<AKV, NTV, true><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, \
                                                                  CT_lo, ldb, Qs, cc, R, a, part, width, g,   \
-                                                                 rowmask);                                   \
+                                                                 rowmask, nullptr, nullptr);                 \
     else                                                                                                    \
         k_uc_update_r_tn<AKV, NTV, false><<<nblk, kBlock, 0, s>>>(N, U.hi, U.lo ? U.lo : U.hi, rp, rk, CT_hi, \
                                                                   CT_lo, ldb, Qs, cc, R, a, part, width, g,   \
-                                                                  nullptr)
+                                                                  nullptr, iters, maxit)
 #define HD_UR_NT(AKV) \
     if (nt == 4) { HD_UR(AKV, 4); } else if (nt == 2) { HD_UR(AKV, 2); } else { HD_UR(AKV, 1); }
     switch (akind(U)) {
