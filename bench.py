@@ -153,13 +153,14 @@ FIXED_TOL = -1.0
 ONEPASS_MIN_N = 65536
 
 
-def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False, onepass=False):
+def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False, onepass=False, xfold=False):
     """(bytes, flops) one launch of kernel `kind` must move / compute;
     su = bytes per stored U1 / descriptor element (4 fp32, 2 bf16).
     fused: the dense bfloat16 forms, where the sparse product reads P only
     (Zs = P) and u_c is fused with the residual update (reads Qs and r,
     writes r). onepass: the similarity / combine kernel hands its scores to
-    the top-k candidate lists and writes no B x n score matrix."""
+    the top-k candidate lists and writes no B x n score matrix. xfold: the
+    combine also applies the last iteration's x update (reads P beside x)."""
     v = 4.0 * n * ldb
     if kind == "spmm":
         return 8.0 * (n + 1) + 8.0 * nnz + v * (3 if rk > 0 and not fused else 2), 2.0 * nnz * ldb
@@ -175,7 +176,7 @@ def algorithmic_cost(kind, n, nnz, ldb, rk, B, d, nchunk, su=4, fused=False, one
     if kind == "sim":
         return su * n * d + 4.0 * B * d + out, 2.0 * B * n * d
     if kind == "combine":
-        return su * n * rk + v + out, 2.0 * n * rk * B
+        return su * n * rk + v * (2 if xfold else 1) + out, 2.0 * n * rk * B
     return None
 
 
@@ -339,8 +340,10 @@ def main():
                 continue
             onepass = (fx.n >= ONEPASS_MIN_N and ctx.get_tuning("topk_onepass") != 1
                        and ((kind == "sim" and vprec != "f32") or (kind == "combine" and (form in FUSED_FORMS or rk == 0))))
+            # the last x update rides on the combine when a batch runs 2 or more iterations
+            xfold = kind == "combine" and ih0 >= 2 and (form in FUSED_FORMS or rk == 0)
             cost = algorithmic_cost(kind, fx.n, fx.nnz, ldb, rk, B, cfg.d, nchunk, sv if kind == "sim" else su,
-                                    form in FUSED_FORMS, onepass)
+                                    form in FUSED_FORMS, onepass, xfold)
             kernels[kind] = {"ms_total": round(ms, 4), "launches": cnt, "avg_us": round(1e3 * ms / cnt, 3)}
             if cost:
                 by, fl = cost
