@@ -47,3 +47,26 @@ def test_null_context_errors_without_device():
 def test_binding_raises_on_error():
     with pytest.raises(hd.HDError):
         hd._check(hd.lib().hd_load_graph(None, 1, 0, None, None, None, 0))
+
+
+def header_enum(name):
+    """{enumerator: value} of a typedef enum in include/hd.h."""
+    text = open(os.path.join(ROOT, "include", "hd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    m = re.search(r"typedef enum\s*\{([^}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    return {k: int(v) for k, v in re.findall(r"(\w+)\s*=\s*(-?\d+)", m.group(1))}
+
+
+def test_tuning_keys_match_header():
+    """The binding's launch-parameter keys are the header's, one for one
+    (hd_autotune fills HD_TUNE_NKEYS x 4 times, which the binding sizes from
+    its own table)."""
+    e = header_enum("hd_tune_key")
+    nkeys = e.pop("HD_TUNE_NKEYS")
+    assert len(hd.TUNE_KEYS) == nkeys
+    assert sorted(hd.TUNE_KEYS.values()) == list(range(nkeys))
+    assert sorted(e.values()) == list(range(nkeys))
+    for name, k in hd.TUNE_KEYS.items():
+        assert e["HD_TUNE_" + name.upper()] == k, name
+
