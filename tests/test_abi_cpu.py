@@ -70,3 +70,18 @@ def test_tuning_keys_match_header():
     for name, k in hd.TUNE_KEYS.items():
         assert e["HD_TUNE_" + name.upper()] == k, name
 
+
+
+def test_status_and_dtype_codes_match_header():
+    """The binding's column-status and storage-type codes are the header's."""
+    st = header_enum("hd_col_status")
+    assert (hd.COL_CONVERGED, hd.COL_MAXITER, hd.COL_ZERO_RHS, hd.COL_BREAKDOWN) == (
+        st["HD_COL_CONVERGED"], st["HD_COL_MAXITER"], st["HD_COL_ZERO_RHS"], st["HD_COL_BREAKDOWN"])
+    dt = header_enum("hd_dtype")
+    for name, code in hd._DTYPES.items():
+        want = {"f32": "HD_F32", "bf16": "HD_BF16", "fp8": "HD_FP8_E4M3", "bf16x2": "HD_BF16X2"}[name]
+        assert dt[want] == code, name
+    assert dt["HD_SPARSE_F32"] == hd.HD_SPARSE_F32
+    rc = header_enum("hd_status")
+    assert (hd.HD_OK, hd.HD_EINVAL, hd.HD_ENOMEM, hd.HD_EDEVICE, hd.HD_ESTATE) == (
+        rc["HD_OK"], rc["HD_EINVAL"], rc["HD_ENOMEM"], rc["HD_EDEVICE"], rc["HD_ESTATE"])
