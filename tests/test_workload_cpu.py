@@ -33,3 +33,25 @@ def test_chunked_eigensolver_matches_arpack(limit):
     assert res.max() <= 1e-9
     # the same invariant subspace: every principal angle's cosine is 1
     assert np.linalg.svd(U0.T @ U, compute_uv=False).min() >= 1 - 1e-10
+
+
+@pytest.mark.parametrize("limit", [W._LIB_ELEMS, 2000])
+def test_cholqr3_orthonormal_basis_of_the_same_span(limit):
+    """The eigensolver's orthogonalisation (shifted CholeskyQR3, row-chunked):
+    orthonormal columns spanning the input's columns, for a well-conditioned
+    block, one with condition number 1e10, and a rank-deficient one (a
+    repeated column: the factorisation may fail and fall back to QR)."""
+    import torch
+    rng = np.random.default_rng(11)
+    n, m = 3000, 40
+    A = rng.standard_normal((n, m))
+    Uq, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    ill = (Uq * np.logspace(0, -10, m)) @ Vq.T
+    dup = A.copy()
+    dup[:, 7] = dup[:, 3]
+    for X, orth_tol in ((A, 1e-13), (ill, 1e-11), (dup, 1e-11)):
+        Q = W._orth_cholqr3(torch.from_numpy(X), limit).numpy()
+        assert np.abs(Q.T @ Q - np.eye(m)).max() <= orth_tol
+        # every column of X lies in span(Q)
+        assert np.linalg.norm(X - Q @ (Q.T @ X)) <= 1e-9 * np.linalg.norm(X)
