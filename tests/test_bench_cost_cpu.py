@@ -43,3 +43,17 @@ def test_cg_update_bytes():
     by, fl = bench.algorithmic_cost("u_c", N, NNZ, LDB, RK, B, D, 1, 4, True)
     assert by == 4.0 * N * RK + 4.0 * RK * LDB + 3 * V
     assert fl == 2.0 * N * RK * LDB
+
+
+def test_more_than_one_gpu_is_refused():
+    """The benchmark measures one GPU: --gpus N > 1 prints a JSON error line
+    and exits 2 before touching a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", "--steps", "1",
+                        "--warmup", "0"], capture_output=True, text=True, timeout=120, cwd=root)
+    assert p.returncode == 2
+    assert "one GPU" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
